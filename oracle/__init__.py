@@ -1,0 +1,132 @@
+"""ctypes front end of the plain C oracle (dibella_oracle.c).
+
+Test infrastructure: only the tests, the smoke check and the benchmark's
+CPU-baseline leg import this package.  It shares nothing with the HIP
+library.  Inputs are anything with nrows/ncols/rowptr/col/val attributes
+(numpy arrays); outputs are plain numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from types import SimpleNamespace
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dibella_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+VARIANT_B = 0x1
+RULE_EDGE = 0x2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain gcc -O2 (single thread)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64, i32, u32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+        lib.oracle_overlap_rows.argtypes = [i64, i64, P, P, P, i32, P, i64, P,
+                                            P, P, P, P]
+        lib.oracle_transitive_reduce.argtypes = [i64, P, P, P, i32, u32, P, P, P, P, P, P, i32]
+        lib.oracle_tr_pass_marks.argtypes = [i64, P, P, P, i32, u32, P, i64, P]
+        lib.oracle_free.argtypes = [P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _take(lib, p, count, dtype, width=1):
+    """Copy a malloc'd C array into numpy and free it."""
+    n = int(count) * width
+    if n:
+        arr = np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(np.ctypeslib.as_ctypes_type(dtype))),
+                                    shape=(n,)).copy()
+    else:
+        arr = np.zeros(0, dtype=dtype)
+    lib.oracle_free(p)
+    return arr
+
+
+def _csr_arrays(M):
+    return (np.ascontiguousarray(M.rowptr, dtype=np.int64),
+            np.ascontiguousarray(M.col, dtype=np.int32),
+            np.ascontiguousarray(M.val, dtype=np.int32))
+
+
+def overlap(A, min_shared: int = 1, rows=None):
+    """C = A A^T over the overlap semiring.  rows: optional row subset
+    (the result then has len(rows) rows, in that order)."""
+    lib = _load()
+    rp, ci, va = _csr_arrays(A)
+    if rows is None:
+        sel, nsel, nout = None, -1, A.nrows
+    else:
+        sel = np.ascontiguousarray(rows, dtype=np.int64)
+        nsel = nout = sel.size
+    out_rp = np.zeros(nout + 1, np.int64)
+    pc, pn, ps = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    nnz = ctypes.c_int64()
+    lib.oracle_overlap_rows(A.nrows, A.ncols, _ptr(rp), _ptr(ci), _ptr(va), int(min_shared),
+                            _ptr(sel) if sel is not None else None, nsel, _ptr(out_rp),
+                            ctypes.byref(pc), ctypes.byref(pn), ctypes.byref(ps),
+                            ctypes.byref(nnz))
+    return SimpleNamespace(nrows=nout, ncols=A.nrows, rowptr=out_rp,
+                           col=_take(lib, pc, nnz.value, np.int32),
+                           count=_take(lib, pn, nnz.value, np.int32),
+                           seed=_take(lib, ps, nnz.value, np.int32, 4).reshape(-1, 4))
+
+
+def transitive_reduce(R, fuzz: int, variant: str = "A", rule: str = "row"):
+    """S = TR(R).  Returns (S, iterations, nnz_trace)."""
+    lib = _load()
+    rp, ci, va = _csr_arrays(R)
+    flags = (VARIANT_B if variant == "B" else 0) | (RULE_EDGE if rule == "edge" else 0)
+    out_rp = np.zeros(R.nrows + 1, np.int64)
+    pc, pv = ctypes.c_void_p(), ctypes.c_void_p()
+    nnz, iters = ctypes.c_int64(), ctypes.c_int32()
+    trace = np.zeros(4096, np.int64)
+    lib.oracle_transitive_reduce(R.nrows, _ptr(rp), _ptr(ci), _ptr(va), int(fuzz), flags,
+                                 _ptr(out_rp), ctypes.byref(pc), ctypes.byref(pv),
+                                 ctypes.byref(nnz), ctypes.byref(iters), _ptr(trace), trace.size)
+    S = SimpleNamespace(nrows=R.nrows, ncols=R.nrows, rowptr=out_rp,
+                        col=_take(lib, pc, nnz.value, np.int32),
+                        val=_take(lib, pv, nnz.value, np.int32))
+    ntr = min(iters.value + 1, trace.size)
+    return S, iters.value, trace[:ntr].copy()
+
+
+def tr_pass_marks(R, fuzz: int, variant: str = "A", rule: str = "row", rows=None):
+    """One reduction pass on R as given: uint8 mark per entry (1 = transitive).
+    Only rows in `rows` are examined (others stay 0)."""
+    lib = _load()
+    rp, ci, va = _csr_arrays(R)
+    flags = (VARIANT_B if variant == "B" else 0) | (RULE_EDGE if rule == "edge" else 0)
+    mark = np.zeros(ci.size, np.uint8)
+    if rows is None:
+        sel, nsel = None, -1
+    else:
+        sel = np.ascontiguousarray(rows, dtype=np.int64)
+        nsel = sel.size
+    lib.oracle_tr_pass_marks(R.nrows, _ptr(rp), _ptr(ci), _ptr(va), int(fuzz), flags,
+                             _ptr(sel) if sel is not None else None, nsel, _ptr(mark))
+    return mark

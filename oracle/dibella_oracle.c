@@ -1,0 +1,324 @@
+/*
+ * Plain CPU oracle for the two semiring sparse products of diBELLA 2D.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark compare against.  It shares no code, header or table with the
+ * HIP library, and the library never calls it.
+ *
+ * Everything is integer arithmetic.  Matrices are CSR with int64 row
+ * pointers and int32 column indices and values (the layouts the generator
+ * documents).  Output arrays are malloc'd here and released with
+ * oracle_free().
+ *
+ * Overlap (Sec. IV-D): C = A * A^T where A_ik is the position of k-mer k in
+ * read i.  The semiring's multiply pairs up the two positions of a shared
+ * k-mer; its add counts shared k-mers and appends another position pair while
+ * fewer than two are stored.  Appending is done in increasing k-mer order, so
+ * the kept pairs are those of the two smallest shared k-mer columns (the
+ * order the paper leaves to the library is fixed this way).
+ *
+ * Transitive reduction (Sec. IV-E, Algorithm "TransitiveReduction" and the
+ * MinPlus semiring): repeat { N = R^2 over MinPlus with the walk check;
+ * v = row max of R; v += x; M = R with row i's entries replaced by v_i;
+ * I = (M >= N) with the end-orientation check; R = R minus I } until nnz(R)
+ * stops changing.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_VARIANT_B 0x1u  /* N only over paths whose end code matches R_ij */
+#define ORACLE_RULE_EDGE 0x2u  /* M_ij = overhang(R_ij) + x instead of row max + x */
+
+void oracle_free(void* p) { free(p); }
+
+static void* xmalloc(size_t bytes) { return malloc(bytes ? bytes : 1); }
+
+/* ------------------------------------------------------------------------ */
+/* A^T by a stable bucket pass over the rows of A (Algorithm diBELLA 2D,     */
+/* Transpose): row k of A^T lists (read j, position) in increasing j.        */
+/* ------------------------------------------------------------------------ */
+static void transpose(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                      const int32_t* val, int64_t* t_rowptr, int32_t* t_read, int32_t* t_pos) {
+    int64_t* fill = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(m + 1));
+    memset(t_rowptr, 0, sizeof(int64_t) * (size_t)(m + 1));
+    for (int64_t e = 0; e < rowptr[n]; ++e) t_rowptr[col[e] + 1]++;
+    for (int64_t k = 0; k < m; ++k) t_rowptr[k + 1] += t_rowptr[k];
+    memcpy(fill, t_rowptr, sizeof(int64_t) * (size_t)(m + 1));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            int64_t d = fill[col[e]]++;
+            t_read[d] = (int32_t)i;
+            t_pos[d] = val[e];
+        }
+    free(fill);
+}
+
+static int cmp_i32(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Rows `sel[0..nsel)` of C = A A^T (nsel < 0: all rows, in order).
+ * Per row: walk k in A_i in increasing order, and for every (j, p_j) in row k
+ * of A^T, add 1 to the count of C_ij and append (A_ik, p_j) while fewer than
+ * two pairs are stored.  Keep entries with count >= min_shared, sorted by j.
+ * Outputs: out_rowptr[nrows_out+1], *out_col, *out_count, *out_seed (4 per
+ * entry: p_i0, p_j0, p_i1, p_j1, -1 where absent). */
+int oracle_overlap_rows(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                        const int32_t* val, int32_t min_shared, const int64_t* sel, int64_t nsel,
+                        int64_t* out_rowptr, int32_t** out_col, int32_t** out_count,
+                        int32_t** out_seed, int64_t* out_nnz) {
+    int64_t nnz_a = rowptr[n];
+    int64_t* t_rowptr = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(m + 1));
+    int32_t* t_read = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)nnz_a);
+    int32_t* t_pos = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)nnz_a);
+    transpose(n, m, rowptr, col, val, t_rowptr, t_read, t_pos);
+
+    int32_t* count = (int32_t*)calloc((size_t)(n ? n : 1), sizeof(int32_t));
+    int32_t* seeds = (int32_t*)xmalloc(sizeof(int32_t) * 4 * (size_t)(n ? n : 1));
+    int32_t* touched = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int64_t nrows_out = nsel < 0 ? n : nsel;
+    int64_t cap = 1024, nnz = 0;
+    int32_t* oc = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
+    int32_t* on = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
+    int32_t* os = (int32_t*)xmalloc(sizeof(int32_t) * 4 * (size_t)cap);
+    out_rowptr[0] = 0;
+    for (int64_t r = 0; r < nrows_out; ++r) {
+        int64_t i = nsel < 0 ? r : sel[r];
+        int64_t nt = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            int32_t k = col[e];
+            for (int64_t f = t_rowptr[k]; f < t_rowptr[k + 1]; ++f) {
+                int32_t j = t_read[f];
+                if (count[j] == 0) {
+                    touched[nt++] = j;
+                    seeds[4 * j + 0] = seeds[4 * j + 1] = seeds[4 * j + 2] = seeds[4 * j + 3] = -1;
+                }
+                int32_t c = count[j]++;
+                if (c < 2) {                  /* concatenate while fewer than two */
+                    seeds[4 * j + 2 * c + 0] = val[e];
+                    seeds[4 * j + 2 * c + 1] = t_pos[f];
+                }
+            }
+        }
+        qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+        for (int64_t q = 0; q < nt; ++q) {
+            int32_t j = touched[q];
+            if (count[j] >= min_shared) {
+                if (nnz == cap) {
+                    cap *= 2;
+                    oc = (int32_t*)realloc(oc, sizeof(int32_t) * (size_t)cap);
+                    on = (int32_t*)realloc(on, sizeof(int32_t) * (size_t)cap);
+                    os = (int32_t*)realloc(os, sizeof(int32_t) * 4 * (size_t)cap);
+                }
+                oc[nnz] = j;
+                on[nnz] = count[j];
+                memcpy(os + 4 * nnz, seeds + 4 * j, 4 * sizeof(int32_t));
+                nnz++;
+            }
+            count[j] = 0;
+        }
+        out_rowptr[r + 1] = nnz;
+    }
+    free(t_rowptr); free(t_read); free(t_pos); free(count); free(seeds); free(touched);
+    *out_col = oc; *out_count = on; *out_seed = os; *out_nnz = nnz;
+    return 0;
+}
+
+int oracle_overlap(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                   const int32_t* val, int32_t min_shared, int64_t* out_rowptr,
+                   int32_t** out_col, int32_t** out_count, int32_t** out_seed, int64_t* out_nnz) {
+    return oracle_overlap_rows(n, m, rowptr, col, val, min_shared, NULL, -1, out_rowptr,
+                               out_col, out_count, out_seed, out_nnz);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transitive reduction                                                      */
+/* ------------------------------------------------------------------------ */
+/* R value: (overhang << 2) | (o_src << 1) | o_dst.                          */
+static int32_t oh_of(int32_t v) { return v >> 2; }
+static int32_t src_of(int32_t v) { return (v >> 1) & 1; }
+static int32_t dst_of(int32_t v) { return v & 1; }
+static int32_t code_of(int32_t v) { return v & 3; }
+
+#define INF_KEY 0xFFFFFFFFu
+
+/* MinPlus semiring of the reduction.  An N value is the pair (sum of
+ * overhangs, end code) packed as (sum << 2) | code, so that Add = min picks
+ * the shortest suffix (ties broken by the code).  Multiply returns a+b only
+ * if the walk i -> k -> j is valid, i.e. both heads at k point opposite ways:
+ * k is left by the orientation it was entered with (dst(R_ik) == src(R_kj)).
+ * The end code of the walk is (src(R_ik), dst(R_kj)). */
+static uint32_t minplus_multiply(int32_t r_ik, int32_t r_kj) {
+    if (dst_of(r_ik) != src_of(r_kj)) return INF_KEY;          /* Id() */
+    uint32_t sum = (uint32_t)(oh_of(r_ik) + oh_of(r_kj));
+    return (sum << 2) | (uint32_t)(src_of(r_ik) << 1) | (uint32_t)dst_of(r_kj);
+}
+static uint32_t minplus_add(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+/* N = R^2 (one CSR, rows sorted).  Under variant B only entries on the
+ * pattern of R whose end code equals that of R_ij are accumulated. */
+static void square(int64_t n, const int64_t* rp, const int32_t* ci, const int32_t* va,
+                   uint32_t flags, int64_t** n_rp, int32_t** n_ci, uint32_t** n_va) {
+    uint32_t* acc = (uint32_t*)xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    int32_t* rcode = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int32_t* touched = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    for (int64_t j = 0; j < n; ++j) { acc[j] = INF_KEY; rcode[j] = -1; }
+    int64_t cap = 1024, nnz = 0;
+    int64_t* orp = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t* oci = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
+    uint32_t* ova = (uint32_t*)xmalloc(sizeof(uint32_t) * (size_t)cap);
+    orp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) rcode[ci[e]] = code_of(va[e]);
+        int64_t nt = 0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            int32_t k = ci[e];
+            for (int64_t f = rp[k]; f < rp[k + 1]; ++f) {
+                int32_t j = ci[f];
+                uint32_t key = minplus_multiply(va[e], va[f]);
+                if (key == INF_KEY) continue;
+                if ((flags & ORACLE_VARIANT_B) && (rcode[j] < 0 || (int32_t)(key & 3u) != rcode[j]))
+                    continue;
+                if (acc[j] == INF_KEY) touched[nt++] = j;
+                acc[j] = minplus_add(acc[j], key);
+            }
+        }
+        qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+        for (int64_t q = 0; q < nt; ++q) {
+            if (nnz == cap) {
+                cap *= 2;
+                oci = (int32_t*)realloc(oci, sizeof(int32_t) * (size_t)cap);
+                ova = (uint32_t*)realloc(ova, sizeof(uint32_t) * (size_t)cap);
+            }
+            oci[nnz] = touched[q];
+            ova[nnz] = acc[touched[q]];
+            nnz++;
+            acc[touched[q]] = INF_KEY;
+        }
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) rcode[ci[e]] = -1;
+        orp[i + 1] = nnz;
+    }
+    free(acc); free(rcode); free(touched);
+    *n_rp = orp; *n_ci = oci; *n_va = ova;
+}
+
+/* Value of sparse N at (i, j) or INF_KEY (binary search in the sorted row). */
+static uint32_t lookup(const int64_t* rp, const int32_t* ci, const uint32_t* va, int64_t i, int32_t j) {
+    int64_t lo = rp[i], hi = rp[i + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (ci[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return (lo < rp[i + 1] && ci[lo] == j) ? va[lo] : INF_KEY;
+}
+
+/* S = TransitiveReduction(R, x).  Entries with overhang <= 0 are contained
+ * overlaps and are dropped first.  `iterations` counts executed passes,
+ * including the final pass that deletes nothing.  nnz_trace (if non-NULL,
+ * room for max_trace values) receives nnz(R) after the drop and after every
+ * pass. */
+int oracle_transitive_reduce(int64_t n, const int64_t* rowptr, const int32_t* col,
+                             const int32_t* val, int32_t fuzz, uint32_t flags,
+                             int64_t* out_rowptr, int32_t** out_col, int32_t** out_val,
+                             int64_t* out_nnz, int32_t* iterations, int64_t* nnz_trace,
+                             int32_t max_trace) {
+    int64_t nnz = 0;
+    int64_t* rp = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t* ci = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(rowptr[n] ? rowptr[n] : 1));
+    int32_t* va = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(rowptr[n] ? rowptr[n] : 1));
+    rp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {           /* contained overlaps are discarded */
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (oh_of(val[e]) > 0) { ci[nnz] = col[e]; va[nnz] = val[e]; nnz++; }
+        rp[i + 1] = nnz;
+    }
+    int32_t ntrace = 0;
+    if (nnz_trace && ntrace < max_trace) nnz_trace[ntrace++] = nnz;
+    int32_t* v = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int32_t iter = 0;
+    int64_t prev;
+    do {
+        prev = nnz;
+        iter++;
+        int64_t* n_rp; int32_t* n_ci; uint32_t* n_va;
+        square(n, rp, ci, va, flags, &n_rp, &n_ci, &n_va);        /* N = R^2 */
+        for (int64_t i = 0; i < n; ++i) {                         /* v = Reduce(Row, 0, max) */
+            v[i] = 0;
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (oh_of(va[e]) > v[i]) v[i] = oh_of(va[e]);
+        }
+        for (int64_t i = 0; i < n; ++i)                           /* v = Apply(v, +x) on nonzeros */
+            if (v[i] != 0) v[i] += fuzz;
+        int64_t w = 0;
+        int64_t row_start = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t e = row_start; e < rp[i + 1]; ++e) {
+                /* M = DimApply(R, v): row i of R takes v_i (or R_ij + x under the edge rule) */
+                int64_t mij = (flags & ORACLE_RULE_EDGE) ? (int64_t)oh_of(va[e]) + fuzz : (int64_t)v[i];
+                uint32_t nij = lookup(n_rp, n_ci, n_va, i, ci[e]);
+                /* I = M >= N, on entries present in both, with matching end heads */
+                int transitive = nij != INF_KEY && (int32_t)(nij & 3u) == code_of(va[e]) &&
+                                 (int64_t)(nij >> 2) <= mij;
+                if (!transitive) { ci[w] = ci[e]; va[w] = va[e]; w++; }   /* R = R .* !I */
+            }
+            row_start = rp[i + 1];
+            rp[i + 1] = w;
+        }
+        nnz = w;
+        free(n_rp); free(n_ci); free(n_va);
+        if (nnz_trace && ntrace < max_trace) nnz_trace[ntrace++] = nnz;
+    } while (nnz != prev);
+    free(v);
+    memcpy(out_rowptr, rp, sizeof(int64_t) * (size_t)(n + 1));
+    free(rp);
+    *out_col = ci; *out_val = va; *out_nnz = nnz; *iterations = iter;
+    return 0;
+}
+
+/* One pass of the reduction on R as given (no contained-overlap drop):
+ * writes mark[e] = 1 for every entry found transitive.  Rows other than
+ * those in sel[0..nsel) are not examined (nsel < 0: all rows).  Used to
+ * check sampled rows of large inputs. */
+int oracle_tr_pass_marks(int64_t n, const int64_t* rowptr, const int32_t* col,
+                         const int32_t* val, int32_t fuzz, uint32_t flags,
+                         const int64_t* sel, int64_t nsel, uint8_t* mark) {
+    uint32_t* acc = (uint32_t*)xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    int32_t* rcode = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    for (int64_t j = 0; j < n; ++j) { acc[j] = INF_KEY; rcode[j] = -1; }
+    int64_t rows = nsel < 0 ? n : nsel;
+    for (int64_t r = 0; r < rows; ++r) {
+        int64_t i = nsel < 0 ? r : sel[r];
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) rcode[col[e]] = code_of(val[e]);
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {   /* row i of N = R^2 */
+            int32_t k = col[e];
+            for (int64_t f = rowptr[k]; f < rowptr[k + 1]; ++f) {
+                int32_t j = col[f];
+                uint32_t key = minplus_multiply(val[e], val[f]);
+                if (key == INF_KEY) continue;
+                if ((flags & ORACLE_VARIANT_B) && (rcode[j] < 0 || (int32_t)(key & 3u) != rcode[j]))
+                    continue;
+                acc[j] = minplus_add(acc[j], key);
+            }
+        }
+        int32_t vi = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (oh_of(val[e]) > vi) vi = oh_of(val[e]);
+        if (vi != 0) vi += fuzz;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            int64_t mij = (flags & ORACLE_RULE_EDGE) ? (int64_t)oh_of(val[e]) + fuzz : (int64_t)vi;
+            uint32_t nij = acc[col[e]];
+            mark[e] = (uint8_t)(nij != INF_KEY && (int32_t)(nij & 3u) == code_of(val[e]) &&
+                                (int64_t)(nij >> 2) <= mij);
+        }
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            int32_t k = col[e];
+            for (int64_t f = rowptr[k]; f < rowptr[k + 1]; ++f) acc[col[f]] = INF_KEY;
+            rcode[col[e]] = -1;
+        }
+    }
+    free(acc); free(rcode);
+    return 0;
+}

@@ -1,0 +1,353 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against things it does not contain itself:
+brute force from the raw read strings, scipy's sparse product, closed forms
+for the diagonal and the total count, the paper's worked example, networkx's
+transitive reduction of DAGs, and the exact string graph of error-free reads.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from paper_2010_10055_amd import synth
+from tests import bruteforce
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _small_reads_workload(seed, G=30_000, n_reads=40, err=0.15, fams=(), lo=2, hi=8):
+    rng = np.random.default_rng(seed)
+    g = synth.insert_repeats(rng, synth.random_genome(rng, G), list(fams))
+    reads = synth.sample_reads(rng, g, n_reads=n_reads, length_uniform=(1000, 4000),
+                               error_rate=err)
+    A, _ = synth.kmer_matrix(reads, 17, lo, hi)
+    return reads, A
+
+
+def _c_as_dict(C):
+    out = {}
+    for i in range(C.nrows):
+        for e in range(int(C.rowptr[i]), int(C.rowptr[i + 1])):
+            out[(i, int(C.col[e]))] = (int(C.count[e]), tuple(int(x) for x in C.seed[e]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Overlap  C = A A^T
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,min_shared,fams,lo,hi", [
+    (11, 1, (), 2, 8),
+    (12, 2, ((500, 6, 0.01),), 2, 8),
+    (13, 3, ((300, 12, 0.02),), 2, 20),
+])
+def test_overlap_equals_bruteforce_from_reads(seed, min_shared, fams, lo, hi):
+    reads, A = _small_reads_workload(seed, fams=fams, lo=lo, hi=hi)
+    expect, n_reliable = bruteforce.overlap_from_reads(reads, 17, lo, hi, min_shared)
+    assert A.ncols == n_reliable
+    C = oracle.overlap(A, min_shared)
+    assert _c_as_dict(C) == expect
+
+
+def test_overlap_tiny_workload_bruteforce():
+    w = synth.make_workload("tiny")
+    expect, _ = bruteforce.overlap_from_reads(w.reads, 17, w.lo, w.hi, w.min_shared)
+    C = oracle.overlap(w.A, w.min_shared)
+    got = _c_as_dict(C)
+    assert len(got) == len(expect)
+    assert got == expect
+
+
+def _pattern(A):
+    return sp.csr_matrix((np.ones(A.nnz, np.int64), A.col, A.rowptr), shape=(A.nrows, A.ncols))
+
+
+@pytest.mark.parametrize("seed,n,m,density,min_shared", [
+    (1, 60, 300, 0.05, 1), (2, 80, 200, 0.1, 2), (3, 50, 1000, 0.01, 1), (4, 1, 10, 0.5, 1),
+])
+def test_overlap_counts_equal_scipy_product(seed, n, m, density, min_shared):
+    rng = np.random.default_rng(seed)
+    A = synth.random_a(rng, n, m, density)
+    C = oracle.overlap(A, min_shared)
+    P = _pattern(A)
+    ref = (P @ P.T).tocsr()
+    ref.data[ref.data < min_shared] = 0
+    ref.eliminate_zeros()
+    ref.sort_indices()
+    assert np.array_equal(C.rowptr, ref.indptr.astype(np.int64))
+    assert np.array_equal(C.col, ref.indices.astype(np.int32))
+    assert np.array_equal(C.count, ref.data.astype(np.int32))
+
+
+def test_overlap_invariants_on_tiny_workload():
+    w = synth.make_workload("tiny")
+    A = w.A
+    C = oracle.overlap(A, 1)
+    d = _c_as_dict(C)
+    # symmetry with each seed pair swapped
+    for (i, j), (c, s) in d.items():
+        assert d[(j, i)] == (c, (s[1], s[0], s[3], s[2]))
+    # diagonal closed form: count = nnz(A_i); seeds = first two positions twice
+    for i in range(A.nrows):
+        cols, vals = A.row(i)
+        if cols.size == 0:
+            assert (i, i) not in d
+            continue
+        s1 = (int(vals[1]), int(vals[1])) if cols.size > 1 else (-1, -1)
+        assert d[(i, i)] == (cols.size, (int(vals[0]), int(vals[0])) + s1)
+    # total count = sum over k-mers of (column count)^2
+    assert int(C.count.astype(np.int64).sum()) == synth.overlap_products(A)
+
+
+def test_overlap_seeds_smallest_two_kmers_adversarial():
+    # one column shared by every row plus a dense row
+    rng = np.random.default_rng(7)
+    A = synth.random_a(rng, 40, 120, 0.05, dense_rows=[3], dense_cols=[0, 57])
+    C = oracle.overlap(A, 1)
+    d = _c_as_dict(C)
+    for (i, j), (c, s) in d.items():
+        ci, vi = A.row(i)
+        cj, vj = A.row(j)
+        shared = sorted(set(ci.tolist()) & set(cj.tolist()))
+        assert c == len(shared)
+        k0 = shared[0]
+        exp = [int(vi[ci == k0][0]), int(vj[cj == k0][0]), -1, -1]
+        if len(shared) > 1:
+            k1 = shared[1]
+            exp[2:] = [int(vi[ci == k1][0]), int(vj[cj == k1][0])]
+        assert s == tuple(exp)
+
+
+def test_overlap_row_subset_matches_full():
+    w = synth.make_workload("tiny")
+    full = oracle.overlap(w.A, 1)
+    rows = np.array([5, 0, 199, 77, 77])
+    sub = oracle.overlap(w.A, 1, rows=rows)
+    for r, i in enumerate(rows):
+        a, b = full.rowptr[i], full.rowptr[i + 1]
+        c, d = sub.rowptr[r], sub.rowptr[r + 1]
+        assert np.array_equal(full.col[a:b], sub.col[c:d])
+        assert np.array_equal(full.count[a:b], sub.count[c:d])
+        assert np.array_equal(full.seed[a:b], sub.seed[c:d])
+
+
+def test_overlap_empty_inputs():
+    A = synth.CSR(3, 5, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    C = oracle.overlap(A, 1)
+    assert C.col.size == 0 and np.all(C.rowptr == 0)
+    A0 = synth.CSR(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    C0 = oracle.overlap(A0, 1)
+    assert C0.rowptr.size == 1
+
+
+# ---------------------------------------------------------------------------
+# Transitive reduction
+# ---------------------------------------------------------------------------
+
+def _dense_to_r(values, codes=None):
+    n = len(values)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j in range(n):
+            if values[i][j]:
+                c = 0 if codes is None else codes[i][j]
+                rows.append(i)
+                cols.append(j)
+                vals.append((values[i][j] << 2) | c)
+    return synth.coo_to_csr(n, n, rows, cols, vals)
+
+
+def _s_dense(S):
+    D = np.zeros((S.nrows, S.nrows), np.int64)
+    for i in range(S.nrows):
+        for e in range(int(S.rowptr[i]), int(S.rowptr[i + 1])):
+            D[i, int(S.col[e])] = int(S.val[e]) >> 2
+    return D
+
+
+def test_worked_example_from_paper():
+    g = json.load(open(os.path.join(GOLDEN, "tr_worked_example.json")))
+    R = _dense_to_r(g["R"])
+    for rule in ("row", "edge"):
+        for variant in ("A", "B"):
+            S, iters, trace = oracle.transitive_reduce(R, g["x"], variant, rule)
+            assert _s_dense(S).tolist() == g["S"]
+            assert iters == g["productive_passes"] + 1
+    marks = oracle.tr_pass_marks(R, g["x"])
+    got_I = np.zeros((4, 4), np.int64)
+    for i in range(4):
+        for e in range(int(R.rowptr[i]), int(R.rowptr[i + 1])):
+            got_I[i, R.col[e]] = marks[e]
+    assert got_I.tolist() == g["I"]
+    # N, v and M of the example follow from R directly
+    Rm = np.array(g["R"])
+    for i in range(4):
+        row = Rm[i][Rm[i] > 0]
+        assert (row.max() if row.size else 0) == g["v"][i]
+        for j in range(4):
+            paths = [Rm[i][k] + Rm[k][j] for k in range(4) if Rm[i][k] and Rm[k][j]]
+            assert (min(paths) if paths else 0) == g["N"][i][j]
+
+
+@pytest.mark.parametrize("code", [(0, 0), (1, 1)])
+def test_worked_example_uniform_orientation(code):
+    g = json.load(open(os.path.join(GOLDEN, "tr_worked_example.json")))
+    c = (code[0] << 1) | code[1]
+    R = _dense_to_r(g["R"], [[c] * 4 for _ in range(4)])
+    S, _, _ = oracle.transitive_reduce(R, g["x"])
+    assert _s_dense(S).tolist() == g["S"]
+
+
+def test_worked_example_invalid_walk_keeps_edge():
+    # R_32 enters read 2 by one head and R_21 leaves by the same head:
+    # 3 -> 2 -> 1 is not a valid walk, so 3 -> 1 stays (condition (a)).
+    # 4 -> 3 -> 2 is still a valid walk but now ends with code (0, 1) while
+    # R_42 has (0, 0): condition (c) fails and 4 -> 2 stays as well.
+    g = json.load(open(os.path.join(GOLDEN, "tr_worked_example.json")))
+    codes = [[0] * 4 for _ in range(4)]
+    codes[2][1] = 0b01          # (o_src, o_dst) = (0, 1)
+    R = _dense_to_r(g["R"], codes)
+    S, _, _ = oracle.transitive_reduce(R, g["x"])
+    D = _s_dense(S)
+    assert D[2, 0] == 80 and D[3, 1] == 80
+
+
+def test_worked_example_end_heads_must_match():
+    # 3 -> 2 -> 1 is a valid walk with end code (0, 0), but R_31 has code
+    # (0, 1): condition (c) fails, the edge stays.
+    g = json.load(open(os.path.join(GOLDEN, "tr_worked_example.json")))
+    codes = [[0] * 4 for _ in range(4)]
+    codes[2][0] = 0b01
+    R = _dense_to_r(g["R"], codes)
+    S, _, _ = oracle.transitive_reduce(R, g["x"])
+    assert _s_dense(S)[2, 0] == 80
+
+
+def _dense_from_bf(D, n):
+    out = np.zeros((n, n), np.int64) - 1
+    for i in range(n):
+        for j in range(n):
+            if D[i][j] is not None:
+                out[i, j] = D[i][j]
+    return out
+
+
+def _s_packed(S):
+    out = np.zeros((S.nrows, S.nrows), np.int64) - 1
+    for i in range(S.nrows):
+        for e in range(int(S.rowptr[i]), int(S.rowptr[i + 1])):
+            out[i, int(S.col[e])] = int(S.val[e])
+    return out
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("variant,rule", [("A", "row"), ("B", "row"), ("A", "edge"), ("B", "edge")])
+def test_tr_equals_dense_bruteforce_random(seed, variant, rule):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 16))
+    R = synth.random_r(rng, n, float(rng.uniform(0.15, 0.6)), max_overhang=60,
+                       allow_nonpositive=(seed % 3 == 0))
+    fuzz = int(rng.integers(0, 40))
+    D, iters, _ = bruteforce.tr_dense(R, fuzz, variant, rule)
+    S, it2, trace = oracle.transitive_reduce(R, fuzz, variant, rule)
+    assert np.array_equal(_s_packed(S), _dense_from_bf(D, n))
+    assert it2 == iters
+    assert np.all(np.diff(trace) <= 0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tr_first_pass_marks_equal_bruteforce(seed):
+    rng = np.random.default_rng(300 + seed)
+    n = 14
+    R = synth.random_r(rng, n, 0.4, max_overhang=50)
+    _, _, first = bruteforce.tr_dense(R, 15, "A", "row")
+    marks = oracle.tr_pass_marks(R, 15)
+    got = set()
+    for i in range(n):
+        for e in range(int(R.rowptr[i]), int(R.rowptr[i + 1])):
+            if marks[e]:
+                got.add((i, int(R.col[e])))
+    assert got == first
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_tr_closed_dag_reduces_to_networkx_transitive_reduction(seed):
+    nx = pytest.importorskip("networkx")
+    rng = np.random.default_rng(500 + seed)
+    n = 12
+    G = nx.DiGraph()
+    G.add_nodes_from(range(n))
+    for i in range(n):
+        for j in range(i + 1, n):
+            if rng.random() < 0.25:
+                G.add_edge(i, j)
+    Cl = nx.transitive_closure_dag(G)
+    Tr = nx.transitive_reduction(Cl)
+    oh = {e: int(rng.integers(1, 50)) for e in Cl.edges}
+    rows = [u for u, v in Cl.edges]
+    cols = [v for u, v in Cl.edges]
+    vals = [oh[e] << 2 for e in Cl.edges]
+    R = synth.coo_to_csr(n, n, rows, cols, vals)
+    S, iters, _ = oracle.transitive_reduce(R, 2 * 50)
+    got = set()
+    for i in range(n):
+        for e in range(int(S.rowptr[i]), int(S.rowptr[i + 1])):
+            got.add((i, int(S.col[e])))
+    assert got == set(Tr.edges)
+    assert iters == (2 if got != set(Cl.edges) else 1)
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_tr_error_free_reads_give_the_chain(seed):
+    rng = np.random.default_rng(seed)
+    g = synth.random_genome(rng, 60_000)
+    reads = synth.sample_reads(rng, g, n_reads=120, length_uniform=(2000, 6000), error_rate=0.0)
+    R = synth.overlap_graph(reads.start, reads.end, reads.strand, policy="reads")
+    S, iters, _ = oracle.transitive_reduce(R, 1000)
+    alive = ~synth.contained_reads(reads.start, reads.end)
+    idx = np.nonzero(alive)[0]
+    idx = idx[np.argsort(reads.start[idx], kind="stable")]
+    expect = set()
+    for a, b in zip(idx[:-1], idx[1:]):
+        if reads.start[b] < reads.end[a]:
+            expect.add((int(a), int(b)))
+            expect.add((int(b), int(a)))
+    got = set()
+    for i in range(S.nrows):
+        for e in range(int(S.rowptr[i]), int(S.rowptr[i + 1])):
+            got.add((i, int(S.col[e])))
+    assert got == expect
+    assert iters == 2
+
+
+def test_tr_invariants_on_noisy_tiny_workload():
+    w = synth.make_workload("tiny")
+    rng = np.random.default_rng(9)
+    Rn = synth.perturb_graph(rng, w.R, jitter=40, false_edges=300, flip_codes=0.05)
+    for variant in ("A", "B"):
+        S, iters, trace = oracle.transitive_reduce(Rn, w.fuzz, variant)
+        # S is a subset of R (values unchanged)
+        Rp = {(i, int(Rn.col[e])): int(Rn.val[e]) for i in range(Rn.nrows)
+              for e in range(int(Rn.rowptr[i]), int(Rn.rowptr[i + 1]))}
+        for i in range(S.nrows):
+            for e in range(int(S.rowptr[i]), int(S.rowptr[i + 1])):
+                assert Rp[(i, int(S.col[e]))] == int(S.val[e])
+        # idempotent: reducing S again deletes nothing
+        S2, it2, _ = oracle.transitive_reduce(S, w.fuzz, variant)
+        assert it2 == 1 and np.array_equal(S2.col, S.col) and np.array_equal(S2.rowptr, S.rowptr)
+        assert np.all(np.diff(trace) <= 0)
+        if variant == "B":
+            assert iters <= 2
+
+
+def test_tr_contained_entries_dropped():
+    R = synth.coo_to_csr(3, 3, [0, 1, 1, 2], [1, 0, 2, 1],
+                         synth.encode_r([0, 5, -3, 7], [0, 0, 0, 0], [0, 0, 0, 0]))
+    S, iters, trace = oracle.transitive_reduce(R, 10)
+    assert trace[0] == 2
+    assert {(0, 1), (1, 2)}.isdisjoint({(i, int(S.col[e])) for i in range(3)
+                                        for e in range(int(S.rowptr[i]), int(S.rowptr[i + 1]))})
