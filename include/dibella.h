@@ -1,0 +1,210 @@
+/*
+ * dibella.h -- C ABI of the MI355X (gfx950) library for the two semiring
+ * sparse products of diBELLA 2D (Guidi et al., "Parallel String Graph
+ * Construction and Transitive Reduction for De Novo Genome Assembly",
+ * arXiv 2010.10055).
+ *
+ *   dibella_overlap            C = A * A^T over the overlap semiring
+ *                              (Sec. IV-D, Algorithm "diBELLA 2D": Transpose
+ *                              and the candidate overlap matrix).
+ *   dibella_transitive_reduce  S = transitive reduction of the overlap graph R
+ *                              (Sec. IV-E, Algorithm "TransitiveReduction" and
+ *                              the MinPlus semiring algorithm).
+ *   *_batched                  the same for many independent sets in one
+ *                              set of launches.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrix pointers are DEVICE pointers on the current HIP device.
+ *   Inputs are borrowed and never written.
+ * - CSR: rowptr int64[nrows+1] with rowptr[0] = 0 and rowptr[nrows] = nnz,
+ *   col int32 strictly increasing inside a row, val int32.
+ * - Every kernel and copy is enqueued on `hip_stream` (NULL = the null
+ *   stream).  On return the outputs are fully described (sizes and pointers)
+ *   but their contents are ready only once the stream reaches that point.
+ * - Outputs and workspace are obtained through `alloc(bytes, ctx)` and
+ *   released through `free(p, ctx)`.  Workspace is released before the call
+ *   returns while work may still be queued, so the allocator must be stream
+ *   ordered on `hip_stream` (PyTorch's caching allocator on the current
+ *   stream is; so is the built-in hipMallocAsync/hipFreeAsync used when
+ *   alloc == NULL).  Output buffers belong to the caller.  A zero-byte
+ *   request is never made: empty outputs come back as NULL.
+ * - Return value: DIBELLA_OK or a negative status.  On error no output is
+ *   returned (everything allocated by the call has been released) and
+ *   dibella_last_error() describes the problem.
+ * - Calls on different streams from different host threads are independent.
+ */
+#ifndef DIBELLA_H
+#define DIBELLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIBELLA_OK          0
+#define DIBELLA_EINVAL     (-1)  /* malformed matrix or argument */
+#define DIBELLA_ENOMEM     (-2)  /* the allocator returned NULL */
+#define DIBELLA_EDEVICE    (-3)  /* a HIP call failed (message in last_error) */
+#define DIBELLA_EOVERFLOW  (-4)  /* sizes beyond the index widths */
+
+/* Flags of the transitive reduction. */
+#define DIBELLA_TR_VARIANT_B   0x1u  /* N_ij only over walks whose end heads match R_ij */
+#define DIBELLA_TR_RULE_EDGE   0x2u  /* M_ij = overhang(R_ij) + fuzz (default: row max + fuzz) */
+#define DIBELLA_NO_VALIDATE    0x4u  /* skip the structural checks of the input */
+#define DIBELLA_TR_USE_GRAPH   0x8u  /* run the passes as captured HIP graphs */
+/* Bits 16..31: stop after this many passes (0 = run to the fixed point). */
+#define DIBELLA_TR_MAX_PASSES(n) (((uint32_t)(n) & 0xFFFFu) << 16)
+
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    const int64_t* rowptr;
+    const int32_t* col;
+    const int32_t* val;
+} dibella_csr;
+
+/* C = A A^T: per entry the number of shared k-mers and two seed pairs
+ * seed[4e..4e+3] = (pos in read i, pos in read j) for the smallest shared
+ * k-mer column, then for the second smallest; -1 where absent. */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    int64_t* rowptr;
+    int32_t* col;
+    int32_t* count;
+    int32_t* seed;
+} dibella_overlap_out;
+
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    int64_t* rowptr;
+    int32_t* col;
+    int32_t* val;
+} dibella_csr_out;
+
+typedef void* (*dibella_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*dibella_free_fn)(void* p, void* ctx);
+
+/*
+ * dibella_overlap -- candidate overlap matrix C = A * A^T (Sec. IV-D).
+ *
+ * A: reads x reliable k-mers; A_ik = start of k-mer k in read i (>= 0).
+ * The multiply of the semiring pairs the two positions of a shared k-mer;
+ * the add counts shared k-mers and keeps the position pairs of the two
+ * smallest shared k-mer columns (the paper keeps "two positions" and leaves
+ * their order to the library; this fixes it so C_ji is C_ij with each pair
+ * swapped).  Entries with count < min_shared are not stored; the diagonal
+ * is kept.  C rows are sorted by column.  Output arrays: rowptr[n+1],
+ * col/count[nnz], seed[4*nnz].
+ * Errors: EINVAL for a malformed A (rowptr, column order or range, negative
+ * value) or min_shared < 1; EOVERFLOW if nrows >= 2^24 or nnz >= 2^40.
+ * Host synchronisation: two stream syncs (three if some row needs more
+ * distinct columns than one LDS table holds).
+ */
+int dibella_overlap(const dibella_csr* A, int32_t min_shared, dibella_overlap_out* C,
+                    dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx,
+                    void* hip_stream);
+
+/*
+ * dibella_transitive_reduce -- string graph S from the overlap graph R
+ * (Sec. IV-E).
+ *
+ * R: square; R_ij = the overlap of read i followed by read j, packed as
+ * (overhang << 2) | (o_i << 1) | o_j where overhang is the suffix of j past
+ * the overlap and o = 0/1 says the read is walked as sequenced / reverse
+ * complemented.  Entries with overhang <= 0 are contained overlaps and are
+ * discarded first.  Then passes repeat until a pass deletes nothing:
+ *   N_ij = min over k of (overhang_ik + overhang_kj, end code) taken only over
+ *          valid walks (the heads at k are opposite: o_k of R_ik equals o_k of
+ *          R_kj), computed on the pattern of R;
+ *   v_i  = max overhang in row i;  M_ij = v_i + fuzz (RULE_EDGE: overhang_ij + fuzz);
+ *   delete R_ij where N_ij exists, its end code equals that of R_ij and
+ *   its overhang sum <= M_ij; all deletions of a pass at once.
+ * *iterations = passes executed, counting the final pass that deletes
+ * nothing.  S has R's layout.
+ * Errors: EINVAL for a malformed or non-square R, a diagonal entry, an
+ * overhang >= 2^28, or fuzz outside [0, 2^30).
+ * Host synchronisation: one stream sync per pass (per captured graph of
+ * passes with DIBELLA_TR_USE_GRAPH).
+ */
+int dibella_transitive_reduce(const dibella_csr* R, int32_t fuzz, uint32_t flags,
+                              dibella_csr_out* S, int32_t* iterations,
+                              dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx,
+                              void* hip_stream);
+
+/*
+ * Batched forms: nsets independent problems (arrays of nsets descriptors,
+ * per-set min_shared / fuzz / iterations) processed by the same kernels in
+ * one set of launches; every set's result is bit-identical to its own
+ * single call.  Work items are the rows of all sets, ordered by estimated
+ * cost and drained from a device queue.
+ */
+int dibella_overlap_batched(const dibella_csr* A, int32_t nsets, const int32_t* min_shared,
+                            dibella_overlap_out* C, dibella_alloc_fn alloc,
+                            dibella_free_fn free_fn, void* ctx, void* hip_stream);
+
+int dibella_transitive_reduce_batched(const dibella_csr* R, int32_t nsets, const int32_t* fuzz,
+                                      uint32_t flags, dibella_csr_out* S, int32_t* iterations,
+                                      dibella_alloc_fn alloc, dibella_free_fn free_fn,
+                                      void* ctx, void* hip_stream);
+
+/* Message of the last nonzero status returned on this host thread. */
+const char* dibella_last_error(void);
+
+/* Launch shapes and table sizes.  Values outside the supported sets are
+ * rejected with EINVAL.  The setting is process wide; change it only while
+ * no call is running. */
+typedef struct {
+    int32_t sym_block;        /* threads per workgroup, symbolic phase: 64,128,256,512 */
+    int32_t num_block;        /* numeric phase: 64,128,256,512 */
+    int32_t tr_block;         /* reduction pass: 64,128,256,512 */
+    int32_t sym_max_log2;     /* largest symbolic LDS hash table, log2 slots: 10..14 */
+    int32_t num_max_log2;     /* largest numeric LDS hash table, log2 slots: 8..12 */
+    int32_t min_table_log2;   /* smallest hash table, log2 slots: 5..8 */
+    int32_t load_log2;        /* table >= 2^load_log2 * (expected distinct keys): 1..2 */
+    int32_t tr_lds_cap;       /* longest row kept in LDS by a pass: 256..8192 */
+    int32_t tr_graph_passes;  /* passes per captured graph: 1..16 */
+} dibella_tuning;
+
+int dibella_get_tuning(dibella_tuning* out);
+int dibella_set_tuning(const dibella_tuning* t);
+
+/* Counters of the last call on this host thread (for measurement). */
+typedef struct {
+    int64_t products;         /* overlap: semiring multiplies = sum_k (col count)^2 */
+    int64_t esc_rows;         /* overlap: rows handled by expand-sort-compress */
+    int64_t host_syncs;       /* stream synchronisations made by the call */
+    int64_t triples;          /* reduction: walks i->k->j examined, all passes */
+    int32_t passes;           /* reduction: passes run (max over sets) */
+    int32_t trace_len;        /* entries used in nnz_trace / triples_trace */
+    int64_t nnz_trace[64];    /* reduction: total nnz after the contained drop, then after each pass */
+    int64_t triples_trace[64];/* reduction: triples examined in each pass */
+} dibella_stats;
+
+int dibella_last_stats(dibella_stats* out);
+
+/* Kernel timing with HIP events recorded on the caller's stream around each
+ * launch of the main kernels (per host thread).  Phases:
+ *   0 transpose  (column histogram, scan, scatter of A^T)
+ *   1 symbolic   (LDS-hash symbolic kernels, one record per table-size bin)
+ *   2 numeric    (LDS-hash numeric kernels, one record per table-size bin)
+ *   3 esc        (expand-sort-compress kernels of dense rows)
+ *   4 tr_mark    (reduction pass kernels: N, row max, compare, flags)
+ *   5 tr_compact (row-pointer scan and compaction of a pass)
+ * Passes run as captured graphs are not timed.  Enabling clears the
+ * accumulators; collect waits for the recorded events, returns the summed
+ * milliseconds and number of records per phase, and clears them. */
+#define DIBELLA_NUM_PHASES 8
+typedef struct {
+    double ms[DIBELLA_NUM_PHASES];
+    int64_t records[DIBELLA_NUM_PHASES];
+} dibella_timing;
+
+int dibella_timing_enable(int on);
+int dibella_timing_collect(dibella_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIBELLA_H */

@@ -44,7 +44,7 @@ def _load():
         i64, i32, u32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
         lib.oracle_overlap_rows.argtypes = [i64, i64, P, P, P, i32, P, i64, P,
                                             P, P, P, P]
-        lib.oracle_transitive_reduce.argtypes = [i64, P, P, P, i32, u32, P, P, P, P, P, P, i32]
+        lib.oracle_transitive_reduce.argtypes = [i64, P, P, P, i32, u32, P, P, P, P, P, P, i32, P]
         lib.oracle_tr_pass_marks.argtypes = [i64, P, P, P, i32, u32, P, i64, P]
         lib.oracle_free.argtypes = [P]
         _lib = lib
@@ -96,22 +96,26 @@ def overlap(A, min_shared: int = 1, rows=None):
                            seed=_take(lib, ps, nnz.value, np.int32, 4).reshape(-1, 4))
 
 
-def transitive_reduce(R, fuzz: int, variant: str = "A", rule: str = "row"):
-    """S = TR(R).  Returns (S, iterations, nnz_trace)."""
+def transitive_reduce(R, fuzz: int, variant: str = "A", rule: str = "row", with_walks=False):
+    """S = TR(R).  Returns (S, iterations, nnz_trace) (plus the number of
+    walks i -> k -> j enumerated over all passes if with_walks)."""
     lib = _load()
     rp, ci, va = _csr_arrays(R)
     flags = (VARIANT_B if variant == "B" else 0) | (RULE_EDGE if rule == "edge" else 0)
     out_rp = np.zeros(R.nrows + 1, np.int64)
     pc, pv = ctypes.c_void_p(), ctypes.c_void_p()
-    nnz, iters = ctypes.c_int64(), ctypes.c_int32()
+    nnz, iters, walks = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
     trace = np.zeros(4096, np.int64)
     lib.oracle_transitive_reduce(R.nrows, _ptr(rp), _ptr(ci), _ptr(va), int(fuzz), flags,
                                  _ptr(out_rp), ctypes.byref(pc), ctypes.byref(pv),
-                                 ctypes.byref(nnz), ctypes.byref(iters), _ptr(trace), trace.size)
+                                 ctypes.byref(nnz), ctypes.byref(iters), _ptr(trace), trace.size,
+                                 ctypes.byref(walks))
     S = SimpleNamespace(nrows=R.nrows, ncols=R.nrows, rowptr=out_rp,
                         col=_take(lib, pc, nnz.value, np.int32),
                         val=_take(lib, pv, nnz.value, np.int32))
     ntr = min(iters.value + 1, trace.size)
+    if with_walks:
+        return S, iters.value, trace[:ntr].copy(), walks.value
     return S, iters.value, trace[:ntr].copy()
 
 

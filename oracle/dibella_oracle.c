@@ -161,7 +161,8 @@ static uint32_t minplus_add(uint32_t a, uint32_t b) { return a < b ? a : b; }
 /* N = R^2 (one CSR, rows sorted).  Under variant B only entries on the
  * pattern of R whose end code equals that of R_ij are accumulated. */
 static void square(int64_t n, const int64_t* rp, const int32_t* ci, const int32_t* va,
-                   uint32_t flags, int64_t** n_rp, int32_t** n_ci, uint32_t** n_va) {
+                   uint32_t flags, int64_t** n_rp, int32_t** n_ci, uint32_t** n_va,
+                   int64_t* walks) {
     uint32_t* acc = (uint32_t*)xmalloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
     int32_t* rcode = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
     int32_t* touched = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
@@ -176,6 +177,7 @@ static void square(int64_t n, const int64_t* rp, const int32_t* ci, const int32_
         int64_t nt = 0;
         for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
             int32_t k = ci[e];
+            *walks += rp[k + 1] - rp[k];
             for (int64_t f = rp[k]; f < rp[k + 1]; ++f) {
                 int32_t j = ci[f];
                 uint32_t key = minplus_multiply(va[e], va[f]);
@@ -219,13 +221,14 @@ static uint32_t lookup(const int64_t* rp, const int32_t* ci, const uint32_t* va,
  * overlaps and are dropped first.  `iterations` counts executed passes,
  * including the final pass that deletes nothing.  nnz_trace (if non-NULL,
  * room for max_trace values) receives nnz(R) after the drop and after every
- * pass. */
+ * pass; *walks counts the walks i -> k -> j enumerated by all squarings. */
 int oracle_transitive_reduce(int64_t n, const int64_t* rowptr, const int32_t* col,
                              const int32_t* val, int32_t fuzz, uint32_t flags,
                              int64_t* out_rowptr, int32_t** out_col, int32_t** out_val,
                              int64_t* out_nnz, int32_t* iterations, int64_t* nnz_trace,
-                             int32_t max_trace) {
+                             int32_t max_trace, int64_t* walks) {
     int64_t nnz = 0;
+    *walks = 0;
     int64_t* rp = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(n + 1));
     int32_t* ci = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(rowptr[n] ? rowptr[n] : 1));
     int32_t* va = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(rowptr[n] ? rowptr[n] : 1));
@@ -244,7 +247,7 @@ int oracle_transitive_reduce(int64_t n, const int64_t* rowptr, const int32_t* co
         prev = nnz;
         iter++;
         int64_t* n_rp; int32_t* n_ci; uint32_t* n_va;
-        square(n, rp, ci, va, flags, &n_rp, &n_ci, &n_va);        /* N = R^2 */
+        square(n, rp, ci, va, flags, &n_rp, &n_ci, &n_va, walks);  /* N = R^2 */
         for (int64_t i = 0; i < n; ++i) {                         /* v = Reduce(Row, 0, max) */
             v[i] = 0;
             for (int64_t e = rp[i]; e < rp[i + 1]; ++e)

@@ -1,0 +1,339 @@
+"""ctypes binding of libdibella.so (include/dibella.h).
+
+Argument marshalling only: torch tensors supply device memory (through the
+library's allocator callbacks, which draw from PyTorch's caching allocator on
+the current stream) and the HIP stream; every step of the computation runs
+in the library's HIP kernels.  If the library is missing the import fails:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch  # must be imported before the library so that both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdibella.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW = 0, -1, -2, -3, -4
+TR_VARIANT_B = 0x1
+TR_RULE_EDGE = 0x2
+NO_VALIDATE = 0x4
+TR_USE_GRAPH = 0x8
+
+EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batched",
+           "dibella_transitive_reduce_batched", "dibella_last_error", "dibella_get_tuning",
+           "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
+           "dibella_timing_collect"]
+PHASES = ["transpose", "symbolic", "numeric", "esc", "tr_mark", "tr_compact"]
+
+
+class DibellaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"dibella status {status}: {msg}")
+        self.status = status
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _OverlapOut(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("seed", ctypes.c_void_p)]
+
+
+class _CSROut(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "sym_block", "num_block", "tr_block", "sym_max_log2", "num_max_log2", "min_table_log2",
+        "load_log2", "tr_lds_cap", "tr_graph_passes")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("products", ctypes.c_int64), ("esc_rows", ctypes.c_int64),
+                ("host_syncs", ctypes.c_int64), ("triples", ctypes.c_int64),
+                ("passes", ctypes.c_int32), ("trace_len", ctypes.c_int32),
+                ("nnz_trace", ctypes.c_int64 * 64), ("triples_trace", ctypes.c_int64 * 64)]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("records", ctypes.c_int64 * 8)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+    lib.dibella_overlap.argtypes = [P, i32, P, ALLOC_FN, FREE_FN, P, P]
+    lib.dibella_overlap_batched.argtypes = [P, i32, P, P, ALLOC_FN, FREE_FN, P, P]
+    lib.dibella_transitive_reduce.argtypes = [P, i32, u32, P, P, ALLOC_FN, FREE_FN, P, P]
+    lib.dibella_transitive_reduce_batched.argtypes = [P, i32, P, u32, P, P, ALLOC_FN, FREE_FN, P, P]
+    for f in EXPORTS:
+        getattr(lib, f).restype = ctypes.c_int
+    lib.dibella_last_error.restype = ctypes.c_char_p
+    lib.dibella_last_error.argtypes = []
+    lib.dibella_get_tuning.argtypes = [P]
+    lib.dibella_set_tuning.argtypes = [P]
+    lib.dibella_last_stats.argtypes = [P]
+    lib.dibella_timing_enable.argtypes = [ctypes.c_int]
+    lib.dibella_timing_collect.argtypes = [P]
+    return lib
+
+
+_lib: Optional[ctypes.CDLL] = None
+_lock = threading.Lock()
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                _lib = load_library()
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# Allocator: every byte the library asks for is a torch uint8 tensor on the
+# current device and stream.  Live blocks are kept per call in a registry so
+# that outputs can be handed back as tensors.
+# ---------------------------------------------------------------------------
+class _Allocations:
+    def __init__(self, device: torch.device):
+        self.device = device
+        self.live = {}
+
+    def alloc(self, nbytes: int, _ctx) -> int:
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:  # out of memory: the library reports DIBELLA_ENOMEM
+            return 0
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def free(self, p: int, _ctx) -> None:
+        self.live.pop(p, None)
+
+    def take(self, p: Optional[int], dtype: torch.dtype, count: int) -> torch.Tensor:
+        if not p or count == 0:
+            return torch.empty(0, dtype=dtype, device=self.device)
+        t = self.live.pop(p)
+        return t.view(dtype)[:count]
+
+
+class _Call:
+    """Callbacks bound to one call (ctypes keeps no reference itself)."""
+
+    def __init__(self, device: torch.device):
+        self.mem = _Allocations(device)
+        self.alloc_cb = ALLOC_FN(self.mem.alloc)
+        self.free_cb = FREE_FN(self.mem.free)
+
+
+def _stream_handle(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        raise DibellaError(status, lib().dibella_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+# Public data holders
+# ---------------------------------------------------------------------------
+@dataclass
+class CSRTensors:
+    """CSR on the device: rowptr int64[n+1], col int32, val int32."""
+    nrows: int
+    ncols: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def from_numpy(cls, M, device="cuda"):
+        return cls(int(M.nrows), int(M.ncols),
+                   torch.as_tensor(M.rowptr, dtype=torch.int64).to(device),
+                   torch.as_tensor(M.col, dtype=torch.int32).to(device),
+                   torch.as_tensor(M.val, dtype=torch.int32).to(device))
+
+
+@dataclass
+class OverlapCSR:
+    nrows: int
+    ncols: int
+    rowptr: torch.Tensor   # int64[n+1]
+    col: torch.Tensor      # int32[nnz]
+    count: torch.Tensor    # int32[nnz]
+    seed: torch.Tensor     # int32[nnz, 4]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+
+def _csr_struct(M: CSRTensors) -> _CSR:
+    for name, t, dt in (("rowptr", M.rowptr, torch.int64), ("col", M.col, torch.int32),
+                        ("val", M.val, torch.int32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {dt} device tensor")
+    return _CSR(M.nrows, M.ncols, M.nnz, M.rowptr.data_ptr(),
+                M.col.data_ptr() if M.nnz else None, M.val.data_ptr() if M.nnz else None)
+
+
+def _device_of(mats: Sequence[CSRTensors]) -> torch.device:
+    return mats[0].rowptr.device if mats else torch.device("cuda", torch.cuda.current_device())
+
+
+def overlap_batched(As: Sequence[CSRTensors], min_shared) -> List[OverlapCSR]:
+    """C_s = A_s A_s^T for every set, in one set of launches."""
+    n = len(As)
+    if isinstance(min_shared, int):
+        min_shared = [min_shared] * n
+    dev = _device_of(As)
+    call = _Call(dev)
+    ins = (_CSR * max(n, 1))(*[_csr_struct(a) for a in As])
+    outs = (_OverlapOut * max(n, 1))()
+    ms = (ctypes.c_int32 * max(n, 1))(*min_shared)
+    with torch.cuda.device(dev):
+        st = lib().dibella_overlap_batched(ins, n, ms, outs, call.alloc_cb, call.free_cb, None,
+                                           _stream_handle(dev))
+    _check(st)
+    res = []
+    for s in range(n):
+        o = outs[s]
+        res.append(OverlapCSR(o.nrows, o.ncols,
+                              call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                              call.mem.take(o.col, torch.int32, o.nnz),
+                              call.mem.take(o.count, torch.int32, o.nnz),
+                              call.mem.take(o.seed, torch.int32, 4 * o.nnz).view(-1, 4)))
+    return res
+
+
+def overlap(A: CSRTensors, min_shared: int = 1) -> OverlapCSR:
+    """C = A A^T over the overlap semiring (count + two seeds)."""
+    dev = _device_of([A])
+    call = _Call(dev)
+    a = _csr_struct(A)
+    o = _OverlapOut()
+    with torch.cuda.device(dev):
+        st = lib().dibella_overlap(ctypes.byref(a), int(min_shared), ctypes.byref(o), call.alloc_cb,
+                                   call.free_cb, None, _stream_handle(dev))
+    _check(st)
+    return OverlapCSR(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                      call.mem.take(o.col, torch.int32, o.nnz),
+                      call.mem.take(o.count, torch.int32, o.nnz),
+                      call.mem.take(o.seed, torch.int32, 4 * o.nnz).view(-1, 4))
+
+
+def tr_flags(variant: str = "A", rule: str = "row", graph: bool = False, max_passes: int = 0,
+             validate: bool = True) -> int:
+    f = (TR_VARIANT_B if variant == "B" else 0) | (TR_RULE_EDGE if rule == "edge" else 0)
+    f |= (TR_USE_GRAPH if graph else 0) | (0 if validate else NO_VALIDATE)
+    return f | ((int(max_passes) & 0xFFFF) << 16)
+
+
+def transitive_reduce_batched(Rs: Sequence[CSRTensors], fuzz, variant="A", rule="row", graph=False,
+                              max_passes=0):
+    """S_s = TR(R_s) for every set in one set of launches.  Returns (list of
+    S, list of pass counts)."""
+    n = len(Rs)
+    if isinstance(fuzz, int):
+        fuzz = [fuzz] * n
+    dev = _device_of(Rs)
+    call = _Call(dev)
+    ins = (_CSR * max(n, 1))(*[_csr_struct(r) for r in Rs])
+    outs = (_CSROut * max(n, 1))()
+    fz = (ctypes.c_int32 * max(n, 1))(*fuzz)
+    its = (ctypes.c_int32 * max(n, 1))()
+    with torch.cuda.device(dev):
+        st = lib().dibella_transitive_reduce_batched(
+            ins, n, fz, tr_flags(variant, rule, graph, max_passes), outs, its, call.alloc_cb,
+            call.free_cb, None, _stream_handle(dev))
+    _check(st)
+    res = []
+    for s in range(n):
+        o = outs[s]
+        res.append(CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                              call.mem.take(o.col, torch.int32, o.nnz),
+                              call.mem.take(o.val, torch.int32, o.nnz)))
+    return res, [int(its[s]) for s in range(n)]
+
+
+def transitive_reduce(R: CSRTensors, fuzz: int, variant="A", rule="row", graph=False, max_passes=0,
+                      validate=True):
+    """S = TR(R).  Returns (S, passes executed)."""
+    dev = _device_of([R])
+    call = _Call(dev)
+    r = _csr_struct(R)
+    o = _CSROut()
+    it = ctypes.c_int32()
+    with torch.cuda.device(dev):
+        st = lib().dibella_transitive_reduce(
+            ctypes.byref(r), int(fuzz), tr_flags(variant, rule, graph, max_passes, validate),
+            ctypes.byref(o), ctypes.byref(it), call.alloc_cb, call.free_cb, None, _stream_handle(dev))
+    _check(st)
+    S = CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                   call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
+    return S, int(it.value)
+
+
+def last_stats() -> dict:
+    s = _Stats()
+    _check(lib().dibella_last_stats(ctypes.byref(s)))
+    n = s.trace_len
+    return {"products": s.products, "esc_rows": s.esc_rows, "host_syncs": s.host_syncs,
+            "triples": s.triples, "passes": s.passes,
+            "nnz_trace": [s.nnz_trace[i] for i in range(n)],
+            "triples_trace": [s.triples_trace[i] for i in range(max(0, min(s.passes, 64)))]}
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(lib().dibella_get_tuning(ctypes.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(**kw) -> dict:
+    cur = get_tuning()
+    cur.update(kw)
+    t = Tuning(**cur)
+    _check(lib().dibella_set_tuning(ctypes.byref(t)))
+    return cur
+
+
+def timing_enable(on: bool = True) -> None:
+    """Record HIP events around the main kernels of later calls on this thread."""
+    _check(lib().dibella_timing_enable(1 if on else 0))
+
+
+def timing_collect() -> dict:
+    """{phase: (milliseconds summed, records)} since enabling / the last collect."""
+    t = _Timing()
+    _check(lib().dibella_timing_collect(ctypes.byref(t)))
+    return {name: (t.ms[i], int(t.records[i])) for i, name in enumerate(PHASES)}

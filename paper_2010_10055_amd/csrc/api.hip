@@ -1,0 +1,125 @@
+// extern "C" entry points of include/dibella.h: argument checks, statistics
+// reset, and the stream / allocator plumbing around the two drivers.
+#include "common.hpp"
+
+#include <cstring>
+
+namespace dibella {
+int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibella_overlap_out* C,
+                uint32_t flags, Arena& ar);
+int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags, dibella_csr_out* S,
+           int32_t* iterations, Arena& ar);
+}  // namespace dibella
+
+using namespace dibella;
+
+namespace {
+
+void reset_stats() { std::memset(&stats(), 0, sizeof(dibella_stats)); }
+
+// On failure: wait for everything already enqueued (it may still reference
+// workspace and staging), then let the arena release outputs too.
+template <class Fn>
+int guarded(Arena& ar, Fn&& fn) {
+    int s = fn();
+    if (s != DIBELLA_OK) {
+        (void)hipStreamSynchronize(ar.stream());
+        ar.fail();
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dibella_overlap(const dibella_csr* A, int32_t min_shared, dibella_overlap_out* C, dibella_alloc_fn alloc,
+                    dibella_free_fn free_fn, void* ctx, void* hip_stream) {
+    return dibella_overlap_batched(A, 1, &min_shared, C, alloc, free_fn, ctx, hip_stream);
+}
+
+int dibella_overlap_batched(const dibella_csr* A, int32_t nsets, const int32_t* min_shared,
+                            dibella_overlap_out* C, dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx,
+                            void* hip_stream) {
+    reset_stats();
+    if (!A || !C || !min_shared || nsets < 0 || (alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("dibella_overlap: bad arguments");
+        return DIBELLA_EINVAL;
+    }
+    if (nsets == 0) return DIBELLA_OK;
+    int status;
+    {
+        Arena ar(alloc, free_fn, ctx, static_cast<hipStream_t>(hip_stream));
+        status = guarded(ar, [&] { return overlap_run(A, nsets, min_shared, C, 0u, ar); });
+    }
+    if (status != DIBELLA_OK)
+        for (int s = 0; s < nsets; ++s) std::memset(&C[s], 0, sizeof(C[s]));
+    return status;
+}
+
+int dibella_transitive_reduce(const dibella_csr* R, int32_t fuzz, uint32_t flags, dibella_csr_out* S,
+                              int32_t* iterations, dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx,
+                              void* hip_stream) {
+    return dibella_transitive_reduce_batched(R, 1, &fuzz, flags, S, iterations, alloc, free_fn, ctx, hip_stream);
+}
+
+int dibella_transitive_reduce_batched(const dibella_csr* R, int32_t nsets, const int32_t* fuzz, uint32_t flags,
+                                      dibella_csr_out* S, int32_t* iterations, dibella_alloc_fn alloc,
+                                      dibella_free_fn free_fn, void* ctx, void* hip_stream) {
+    reset_stats();
+    if (!R || !S || !fuzz || !iterations || nsets < 0 || (alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("dibella_transitive_reduce: bad arguments");
+        return DIBELLA_EINVAL;
+    }
+    if (nsets == 0) return DIBELLA_OK;
+    int status;
+    {
+        Arena ar(alloc, free_fn, ctx, static_cast<hipStream_t>(hip_stream));
+        status = guarded(ar, [&] { return tr_run(R, nsets, fuzz, flags, S, iterations, ar); });
+    }
+    if (status != DIBELLA_OK)
+        for (int s = 0; s < nsets; ++s) {
+            std::memset(&S[s], 0, sizeof(S[s]));
+            iterations[s] = 0;
+        }
+    return status;
+}
+
+const char* dibella_last_error(void) { return error_slot().c_str(); }
+
+int dibella_get_tuning(dibella_tuning* out) {
+    if (!out) return DIBELLA_EINVAL;
+    *out = tuning();
+    return DIBELLA_OK;
+}
+
+int dibella_set_tuning(const dibella_tuning* t) {
+    auto block_ok = [](int b) { return b == 64 || b == 128 || b == 256 || b == 512; };
+    if (!t || !block_ok(t->sym_block) || !block_ok(t->num_block) || !block_ok(t->tr_block) ||
+        t->sym_max_log2 < 10 || t->sym_max_log2 > 14 || t->num_max_log2 < 8 || t->num_max_log2 > 12 ||
+        t->min_table_log2 < 5 || t->min_table_log2 > 8 || t->load_log2 < 1 || t->load_log2 > 2 ||
+        t->tr_lds_cap < 256 || t->tr_lds_cap > 8192 || t->tr_graph_passes < 1 || t->tr_graph_passes > 16) {
+        set_error("dibella_set_tuning: value outside the supported range");
+        return DIBELLA_EINVAL;
+    }
+    tuning() = *t;
+    return DIBELLA_OK;
+}
+
+int dibella_timing_enable(int on) {
+    timing_set_enabled(on != 0);
+    return DIBELLA_OK;
+}
+
+int dibella_timing_collect(dibella_timing* out) {
+    if (!out) return DIBELLA_EINVAL;
+    return timing_collect(out);
+}
+
+int dibella_last_stats(dibella_stats* out) {
+    if (!out) return DIBELLA_EINVAL;
+    *out = stats();
+    return DIBELLA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// Shared host and device helpers of the HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "dibella.h"
+
+namespace dibella {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+std::string& error_slot();
+
+#define DB_HIP(expr)                                                                  \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess) {                                                       \
+            ::dibella::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));  \
+            return DIBELLA_EDEVICE;                                                   \
+        }                                                                             \
+    } while (0)
+
+#define DB_TRY(expr)                        \
+    do {                                    \
+        int _s = (expr);                    \
+        if (_s != DIBELLA_OK) return _s;    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Tuning (process wide) and per-thread statistics
+// ---------------------------------------------------------------------------
+dibella_tuning& tuning();
+dibella_stats& stats();
+
+// ---------------------------------------------------------------------------
+// Allocation through the caller's callbacks (or hipMallocAsync), released
+// in reverse order when the call ends.  Outputs are kept unless the call
+// fails.
+// ---------------------------------------------------------------------------
+class Arena {
+  public:
+    Arena(dibella_alloc_fn a, dibella_free_fn f, void* ctx, hipStream_t s)
+        : alloc_(a), free_(f), ctx_(ctx), stream_(s) {}
+    ~Arena();
+    Arena(const Arena&) = delete;
+    Arena& operator=(const Arena&) = delete;
+
+    // Workspace: freed when the Arena dies.  bytes == 0 gives nullptr.
+    int work(size_t bytes, void** out);
+    // Caller-owned output: freed only if fail() was called.
+    int output(size_t bytes, void** out);
+    void fail() { failed_ = true; }
+    hipStream_t stream() const { return stream_; }
+
+    template <class T>
+    int work_n(size_t n, T** out) {
+        void* p = nullptr;
+        int s = work(n * sizeof(T), &p);
+        *out = static_cast<T*>(p);
+        return s;
+    }
+    template <class T>
+    int output_n(size_t n, T** out) {
+        void* p = nullptr;
+        int s = output(n * sizeof(T), &p);
+        *out = static_cast<T*>(p);
+        return s;
+    }
+
+  private:
+    void release(void* p);
+    dibella_alloc_fn alloc_;
+    dibella_free_fn free_;
+    void* ctx_;
+    hipStream_t stream_;
+    bool failed_ = false;
+    std::vector<void*> work_;
+    std::vector<void*> outputs_;
+};
+
+// Pinned host staging per host thread.  begin() waits until the previous
+// call's uploads from it have executed.
+struct HostStage {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t last_use = nullptr;
+    int reserve(size_t need);
+};
+HostStage& host_stage();
+int stage_done(hipStream_t s);       // record that the stage has been consumed
+
+int sync_stream(hipStream_t s);       // hipStreamSynchronize + counter
+
+// Event timing of phases (no-ops unless enabled on this host thread).
+enum Phase { kPhTranspose = 0, kPhSymbolic, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact };
+bool timing_on();
+int timing_begin(int phase, hipStream_t s, int* token);
+int timing_end(int token, hipStream_t s);
+void timing_set_enabled(bool on);
+int timing_collect(dibella_timing* out);
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan: out[0] = 0, out[i+1] = sum_{q<=i} in[q].
+// `enable` (device int, may be null): when it reads 0 the scan does nothing.
+// ---------------------------------------------------------------------------
+int scan_exclusive(const int32_t* in, int64_t* out, int64_t n, const int32_t* enable, Arena& ar);
+int scan_exclusive(const int64_t* in, int64_t* out, int64_t n, const int32_t* enable, Arena& ar);
+// Same with caller-provided workspace of scan_workspace_elems(n) int64s.
+int64_t scan_workspace_elems(int64_t n);
+int scan_exclusive_ws(const int32_t* in, int64_t* out, int64_t n, const int32_t* enable,
+                      int64_t* tiles, hipStream_t s);
+int scan_exclusive_ws(const int64_t* in, int64_t* out, int64_t n, const int32_t* enable,
+                      int64_t* tiles, hipStream_t s);
+
+// Fill kernels (used instead of memset nodes so that graph capture is safe).
+int fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+int fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int grid_for(int64_t items, int block, int64_t cap = 1 << 20) {
+    int64_t g = ceil_div(items, block);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<int>(g);
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ int32_t atomic_add(int32_t* p, int32_t v) { return atomicAdd(p, v); }
+__device__ __forceinline__ uint32_t atomic_add(uint32_t* p, uint32_t v) { return atomicAdd(p, v); }
+__device__ __forceinline__ int64_t atomic_add(int64_t* p, int64_t v) {
+    return (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+__device__ __forceinline__ int32_t atomic_max(int32_t* p, int32_t v) { return atomicMax(p, v); }
+__device__ __forceinline__ int64_t atomic_max(int64_t* p, int64_t v) {
+    return (int64_t)atomicMax(reinterpret_cast<long long*>(p), (long long)v);
+}
+
+// Largest s in [0, nsets) with base[s] <= g (base ascending, base[0] = 0).
+__device__ __forceinline__ int find_set(const int64_t* base, int nsets, int64_t g) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        T o = __shfl_xor(v, d, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+template <class T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+    const int lane = lane_id();
+    for (int d = 1; d < kWave; d <<= 1) {
+        T y = __shfl_up(v, d, kWave);
+        if (lane >= d) v += y;
+    }
+    return v;
+}
+
+// Exclusive block scan of one value per thread; `tmp` holds BLOCK/64 + 1
+// values of T in LDS.  Returns the exclusive prefix; *total = block sum.
+// Contains barriers: every thread of the block must call it.
+template <int BLOCK, class T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T* tmp, T* total) {
+    constexpr int W = BLOCK / kWave;
+    const int w = wave_id();
+    T inc = wave_inclusive_sum(v);
+    if (lane_id() == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = 0;
+        for (int q = 0; q < W; ++q) {
+            T x = tmp[q];
+            tmp[q] = acc;
+            acc += x;
+        }
+        tmp[W] = acc;
+    }
+    __syncthreads();
+    T excl = inc - v + tmp[w];
+    *total = tmp[W];
+    __syncthreads();
+    return excl;
+}
+
+// Block-wide reductions through one LDS word (all threads must call).
+template <class T>
+__device__ __forceinline__ T block_sum_lds(T v, T* slot) {
+    if (threadIdx.x == 0) *slot = 0;
+    __syncthreads();
+    v = wave_sum(v);
+    if (lane_id() == 0) atomic_add(slot, v);
+    __syncthreads();
+    T r = *slot;
+    __syncthreads();
+    return r;
+}
+template <class T>
+__device__ __forceinline__ T block_max_lds(T v, T* slot) {
+    if (threadIdx.x == 0) *slot = 0;
+    __syncthreads();
+    v = wave_max(v);
+    if (lane_id() == 0) atomic_max(slot, v);
+    __syncthreads();
+    T r = *slot;
+    __syncthreads();
+    return r;
+}
+
+// Index of the last element <= q in the ascending array off[0..len) with
+// off[0] = 0 <= q (LDS binary search).
+__device__ __forceinline__ int upper_index(const int32_t* off, int len, int32_t q) {
+    int lo = 0, hi = len - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__host__ __device__ __forceinline__ int ceil_log2_i64(int64_t x) {
+    int r = 0;
+    while ((int64_t(1) << r) < x) ++r;
+    return r;
+}
+
+}  // namespace dibella

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle,
+bit for bit (all of the arithmetic is integer)."""
+import contextlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_10055_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    _dev()
+    import paper_2010_10055_amd as pkg
+    return pkg
+
+
+@contextlib.contextmanager
+def tuned(pkg, **kw):
+    old = pkg.get_tuning()
+    pkg.set_tuning(**kw)
+    try:
+        yield
+    finally:
+        pkg.set_tuning(**old)
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def assert_overlap_equal(C, ref, tag=""):
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(C.rowptr), ref.rowptr), f"{tag} rowptr"
+    assert np.array_equal(_np(C.col), ref.col), f"{tag} col"
+    assert np.array_equal(_np(C.count), ref.count), f"{tag} count"
+    assert np.array_equal(_np(C.seed), ref.seed), f"{tag} seed"
+
+
+def assert_csr_equal(S, ref, tag=""):
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(S.rowptr), ref.rowptr), f"{tag} rowptr"
+    assert np.array_equal(_np(S.col), ref.col), f"{tag} col"
+    assert np.array_equal(_np(S.val), ref.val), f"{tag} val"
+
+
+def _run_overlap(pkg, A, ms):
+    print(f"overlap n={A.nrows} m={A.ncols} nnz={A.nnz} min_shared={ms}", flush=True)
+    C = pkg.overlap(pkg.CSRTensors.from_numpy(A, _dev()), ms)
+    return C
+
+
+# ---------------------------------------------------------------------------
+# Overlap
+# ---------------------------------------------------------------------------
+
+def test_overlap_tiny_workload(lib):
+    w = synth.make_workload("tiny")
+    C = _run_overlap(lib, w.A, w.min_shared)
+    assert_overlap_equal(C, oracle.overlap(w.A, w.min_shared), "tiny")
+    st = lib.last_stats()
+    assert st["products"] == synth.overlap_products(w.A)
+
+
+@pytest.mark.parametrize("seed,n,m,density,ms", [
+    (1, 300, 2000, 0.01, 1), (2, 500, 800, 0.02, 2), (3, 64, 64, 0.3, 1), (4, 1, 5, 0.6, 1),
+    (5, 257, 4097, 0.004, 3), (6, 1000, 30000, 0.001, 1),
+])
+def test_overlap_random(lib, seed, n, m, density, ms):
+    rng = np.random.default_rng(seed)
+    A = synth.random_a(rng, n, m, density)
+    C = _run_overlap(lib, A, ms)
+    assert_overlap_equal(C, oracle.overlap(A, ms), f"random{seed}")
+
+
+def test_overlap_empty_rows_and_matrix(lib):
+    A = synth.CSR(4, 7, np.zeros(5, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    C = _run_overlap(lib, A, 1)
+    assert C.nnz == 0 and np.all(_np(C.rowptr) == 0)
+    rng = np.random.default_rng(8)
+    A2 = synth.random_a(rng, 50, 100, 0.05)
+    keep = np.ones(50, bool)
+    keep[::3] = False   # blank every third row
+    rows = np.repeat(np.arange(50), np.diff(A2.rowptr))
+    sel = keep[rows]
+    A3 = synth.coo_to_csr(50, 100, rows[sel], A2.col[sel], A2.val[sel])
+    assert_overlap_equal(_run_overlap(lib, A3, 1), oracle.overlap(A3, 1), "blank rows")
+
+
+def test_overlap_adversarial_dense(lib):
+    rng = np.random.default_rng(9)
+    # one k-mer in every read, one read with every k-mer
+    A = synth.random_a(rng, 700, 900, 0.01, dense_rows=[17], dense_cols=[3, 500])
+    for ms in (1, 2):
+        assert_overlap_equal(_run_overlap(lib, A, ms), oracle.overlap(A, ms), f"dense ms={ms}")
+
+
+def test_overlap_esc_and_overflow_paths(lib):
+    rng = np.random.default_rng(10)
+    A = synth.random_a(rng, 3000, 400, 0.02, dense_cols=[7, 8])
+    ref = oracle.overlap(A, 1)
+    # numeric tables of at most 256 slots: rows with > 128 distinct go to ESC;
+    # symbolic tables of at most 1024 slots: rows with > ~700 distinct overflow
+    with tuned(lib, sym_max_log2=10, num_max_log2=8):
+        C = _run_overlap(lib, A, 1)
+        st = lib.last_stats()
+    assert st["esc_rows"] > 0
+    assert st["host_syncs"] == 3
+    assert_overlap_equal(C, ref, "esc")
+
+
+@pytest.mark.parametrize("block", [64, 128, 512])
+def test_overlap_launch_shapes_give_same_bits(lib, block):
+    w = synth.make_workload("tiny")
+    ref = oracle.overlap(w.A, 1)
+    with tuned(lib, sym_block=block, num_block=block, min_table_log2=5, load_log2=2):
+        assert_overlap_equal(_run_overlap(lib, w.A, 1), ref, f"block {block}")
+
+
+def test_overlap_batched_equals_solo(lib):
+    sets = [synth.make_workload("tiny", seed=1000 + s).A for s in range(3)]
+    rng = np.random.default_rng(11)
+    sets.append(synth.CSR(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32)))
+    sets.append(synth.random_a(rng, 40, 30, 0.2))
+    ms = [1, 2, 1, 1, 3]
+    Cs = lib.overlap_batched([lib.CSRTensors.from_numpy(a, _dev()) for a in sets], ms)
+    for s, (a, m) in enumerate(zip(sets, ms)):
+        assert_overlap_equal(Cs[s], oracle.overlap(a, m), f"set {s}")
+
+
+def test_overlap_deterministic(lib):
+    w = synth.make_workload("tiny", seed=77)
+    A = lib.CSRTensors.from_numpy(w.A, _dev())
+    C1 = lib.overlap(A, 1)
+    C2 = lib.overlap(A, 1)
+    torch.cuda.synchronize()
+    for f in ("rowptr", "col", "count", "seed"):
+        assert torch.equal(getattr(C1, f), getattr(C2, f))
+
+
+@pytest.mark.parametrize("case", ["unsorted", "colrange", "negative", "rowptr", "min_shared"])
+def test_overlap_rejects_malformed(lib, case):
+    rng = np.random.default_rng(12)
+    A = synth.random_a(rng, 20, 50, 0.2)
+    rowptr, col, val, ms = A.rowptr.copy(), A.col.copy(), A.val.copy(), 1
+    if case == "unsorted":
+        r = int(np.argmax(np.diff(rowptr)))
+        a = rowptr[r]
+        col[a], col[a + 1] = col[a + 1], col[a]
+    elif case == "colrange":
+        col[3] = 50
+    elif case == "negative":
+        val[5] = -1
+    elif case == "rowptr":
+        rowptr[-2] = rowptr[-1] + 5     # row ranges past nnz and decreasing
+    else:
+        ms = 0
+    bad = synth.CSR(20, 50, rowptr, col, val)
+    with pytest.raises(lib.DibellaError) as ei:
+        _run_overlap(lib, bad, ms)
+    assert ei.value.status == -1
+
+
+# ---------------------------------------------------------------------------
+# Transitive reduction
+# ---------------------------------------------------------------------------
+
+def _run_tr(pkg, R, fuzz, **kw):
+    print(f"tr n={R.nrows} nnz={R.nnz} fuzz={fuzz} {kw}", flush=True)
+    return pkg.transitive_reduce(pkg.CSRTensors.from_numpy(R, _dev()), fuzz, **kw)
+
+
+@pytest.mark.parametrize("policy", ["edges", "reads"])
+@pytest.mark.parametrize("variant,rule", [("A", "row"), ("B", "row"), ("A", "edge"), ("B", "edge")])
+def test_tr_tiny_workload(lib, policy, variant, rule):
+    w = synth.make_workload("tiny", policy=policy)
+    S, it = _run_tr(lib, w.R, w.fuzz, variant=variant, rule=rule)
+    ref, it_ref, trace = oracle.transitive_reduce(w.R, w.fuzz, variant, rule)
+    assert_csr_equal(S, ref, f"{policy} {variant} {rule}")
+    assert it == it_ref
+    st = lib.last_stats()
+    assert st["nnz_trace"] == list(trace)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_tr_noisy_tiny(lib, graph):
+    w = synth.make_workload("tiny")
+    rng = np.random.default_rng(13)
+    Rn = synth.perturb_graph(rng, w.R, jitter=60, false_edges=500, flip_codes=0.05)
+    for variant in ("A", "B"):
+        S, it = _run_tr(lib, Rn, w.fuzz, variant=variant, graph=graph)
+        ref, it_ref, _ = oracle.transitive_reduce(Rn, w.fuzz, variant)
+        assert_csr_equal(S, ref, f"noisy {variant}")
+        assert it == it_ref
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tr_random(lib, seed):
+    rng = np.random.default_rng(200 + seed)
+    n = int(rng.integers(5, 300))
+    R = synth.random_r(rng, n, float(rng.uniform(0.01, 0.2)), max_overhang=200,
+                       allow_nonpositive=True)
+    fuzz = int(rng.integers(0, 100))
+    S, it = _run_tr(lib, R, fuzz)
+    ref, it_ref, _ = oracle.transitive_reduce(R, fuzz)
+    assert_csr_equal(S, ref, f"random {seed}")
+    assert it == it_ref
+
+
+def test_tr_long_rows_global_path(lib):
+    rng = np.random.default_rng(14)
+    n = 1500
+    R = synth.random_r(rng, n, 0.01, max_overhang=300)
+    # two hub rows longer than the LDS cap
+    rows, cols, vals = [], [], []
+    for hub in (5, 900):
+        cs = np.setdiff1d(rng.choice(n, 800, replace=False), [hub])
+        rows += [hub] * cs.size
+        cols += cs.tolist()
+        vals += synth.encode_r(rng.integers(1, 300, cs.size), rng.integers(0, 2, cs.size),
+                               rng.integers(0, 2, cs.size)).tolist()
+    base_rows = np.repeat(np.arange(n), np.diff(R.rowptr))
+    keep = ~np.isin(base_rows, [5, 900])
+    Rb = synth.coo_to_csr(n, n, np.concatenate([base_rows[keep], rows]),
+                          np.concatenate([R.col[keep], cols]), np.concatenate([R.val[keep], vals]))
+    ref, it_ref, _ = oracle.transitive_reduce(Rb, 50)
+    with tuned(lib, tr_lds_cap=512):
+        S, it = _run_tr(lib, Rb, 50)
+    assert_csr_equal(S, ref, "hubs")
+    assert it == it_ref
+
+
+@pytest.mark.parametrize("block", [64, 128, 512])
+def test_tr_launch_shapes_give_same_bits(lib, block):
+    w = synth.make_workload("tiny")
+    ref, _, _ = oracle.transitive_reduce(w.R, w.fuzz)
+    with tuned(lib, tr_block=block, tr_graph_passes=2):
+        S, _ = _run_tr(lib, w.R, w.fuzz, graph=True)
+    assert_csr_equal(S, ref, f"block {block}")
+
+
+def test_tr_one_pass(lib):
+    w = synth.make_workload("tiny")
+    rng = np.random.default_rng(15)
+    Rn = synth.perturb_graph(rng, w.R, jitter=30, false_edges=200)
+    S, it = _run_tr(lib, Rn, w.fuzz, max_passes=1)
+    assert it == 1
+    # expected: R without contained entries, minus the marks of one pass
+    oh = Rn.val >> 2
+    rows = np.repeat(np.arange(Rn.nrows), np.diff(Rn.rowptr))
+    pos = oh > 0
+    R0 = synth.coo_to_csr(Rn.nrows, Rn.nrows, rows[pos], Rn.col[pos], Rn.val[pos])
+    mark = oracle.tr_pass_marks(R0, w.fuzz)
+    rows0 = np.repeat(np.arange(R0.nrows), np.diff(R0.rowptr))
+    k = mark == 0
+    exp = synth.coo_to_csr(R0.nrows, R0.nrows, rows0[k], R0.col[k], R0.val[k])
+    assert_csr_equal(S, exp, "one pass")
+
+
+def test_tr_batched_equals_solo(lib):
+    Rs = [synth.make_workload("tiny", seed=1000 + s).R for s in range(3)]
+    rng = np.random.default_rng(16)
+    Rs.append(synth.random_r(rng, 60, 0.1, allow_nonpositive=True))
+    Rs.append(synth.CSR(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32)))
+    fz = [1000, 500, 0, 20, 7]
+    for graph in (False, True):
+        Ss, its = lib.transitive_reduce_batched([lib.CSRTensors.from_numpy(r, _dev()) for r in Rs], fz,
+                                                graph=graph)
+        for s, (r, f) in enumerate(zip(Rs, fz)):
+            ref, it_ref, _ = oracle.transitive_reduce(r, f)
+            assert_csr_equal(Ss[s], ref, f"set {s}")
+            assert its[s] == it_ref
+
+
+@pytest.mark.parametrize("case", ["diagonal", "unsorted", "colrange", "bigoverhang", "fuzz"])
+def test_tr_rejects_malformed(lib, case):
+    rng = np.random.default_rng(17)
+    R = synth.random_r(rng, 30, 0.2)
+    col, val, fuzz = R.col.copy(), R.val.copy(), 10
+    r = int(np.argmax(np.diff(R.rowptr)))
+    a = int(R.rowptr[r])
+    if case == "diagonal":
+        col[a] = r
+        col[a:R.rowptr[r + 1]] = np.sort(col[a:R.rowptr[r + 1]])
+    elif case == "unsorted":
+        col[a], col[a + 1] = col[a + 1], col[a]
+    elif case == "colrange":
+        col[a] = 30
+    elif case == "bigoverhang":
+        val[a] = (1 << 28) << 2          # overhang 2^28 does not fit the packed key
+    else:
+        fuzz = -1
+    bad = synth.CSR(30, 30, R.rowptr, col, val)
+    with pytest.raises(lib.DibellaError) as ei:
+        _run_tr(lib, bad, fuzz)
+    assert ei.value.status == -1

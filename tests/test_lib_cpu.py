@@ -1,0 +1,69 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every symbol the header declares, and its argument checks and tuning
+interface behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dibella.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(dibella_[a-z_]+)\s*\(", text)) - {"dibella_alloc_fn", "dibella_free_fn"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2010_10055_amd import _lib
+    return _lib.lib()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "dibella_overlap" in names and "dibella_transitive_reduce" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_2010_10055_amd import _lib
+    assert sorted(_lib.EXPORTS) == _declared()
+
+
+def test_null_arguments_rejected_without_gpu(lib):
+    from paper_2010_10055_amd import _lib
+    st = lib.dibella_overlap(None, 1, None, _lib.ALLOC_FN(0), _lib.FREE_FN(0), None, None)
+    assert st == _lib.EINVAL
+    assert b"bad arguments" in lib.dibella_last_error()
+    it = ctypes.c_int32()
+    st = lib.dibella_transitive_reduce(None, 0, 0, None, ctypes.byref(it), _lib.ALLOC_FN(0),
+                                       _lib.FREE_FN(0), None, None)
+    assert st == _lib.EINVAL
+
+
+def test_zero_sets_is_a_no_op(lib):
+    from paper_2010_10055_amd import _lib
+    dummy = (_lib._CSR * 1)()
+    out = (_lib._OverlapOut * 1)()
+    ms = (ctypes.c_int32 * 1)(1)
+    assert lib.dibella_overlap_batched(dummy, 0, ms, out, _lib.ALLOC_FN(0), _lib.FREE_FN(0), None,
+                                       None) == _lib.OK
+
+
+def test_tuning_roundtrip_and_range_checks():
+    import paper_2010_10055_amd as pkg
+    old = pkg.get_tuning()
+    try:
+        new = pkg.set_tuning(num_block=128, tr_lds_cap=2048)
+        assert pkg.get_tuning() == new
+        for bad in ({"sym_block": 96}, {"num_max_log2": 13}, {"tr_graph_passes": 0},
+                    {"sym_max_log2": 15}, {"load_log2": 3}):
+            with pytest.raises(pkg.DibellaError):
+                pkg.set_tuning(**bad)
+        assert pkg.get_tuning() == new
+    finally:
+        pkg.set_tuning(**old)
