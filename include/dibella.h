@@ -159,12 +159,17 @@ typedef struct {
     int32_t sym_block;        /* threads per workgroup, symbolic phase: 64,128,256,512 */
     int32_t num_block;        /* numeric phase: 64,128,256,512 */
     int32_t tr_block;         /* reduction pass: 64,128,256,512 */
-    int32_t sym_max_log2;     /* largest symbolic LDS hash table, log2 slots: 10..14 */
-    int32_t num_max_log2;     /* largest numeric LDS hash table, log2 slots: 8..12 */
-    int32_t min_table_log2;   /* smallest hash table, log2 slots: 5..8 */
-    int32_t load_log2;        /* table >= 2^load_log2 * (expected distinct keys): 1..2 */
-    int32_t tr_lds_cap;       /* longest row kept in LDS by a pass: 256..8192 */
+    int32_t sym_first_log2;   /* first symbolic LDS hash table, log2 slots: 8..13; rows
+                                 that overflow it are retried with the retry table */
+    int32_t sym_max_log2;     /* retry table, log2 slots: sym_first_log2..14; rows that
+                                 overflow it go to expand-sort-compress */
+    int32_t num_max_entries;  /* most output entries a row may have in the numeric LDS path:
+                                 256..8192 (capped by the LDS); larger rows go to ESC */
+    int32_t load_pct;         /* hash-table load limit in percent: 40..85 */
+    int32_t tr_lds_cap;       /* longest row kept in LDS by a pass: 512..8192 */
     int32_t tr_graph_passes;  /* passes per captured graph: 1..16 */
+    int32_t bits_max_words;   /* bitmap path for sets with at most 32 * this many reads
+                                 (and min_shared <= 4): 0..8192; 0 = hash path only */
 } dibella_tuning;
 
 int dibella_get_tuning(dibella_tuning* out);

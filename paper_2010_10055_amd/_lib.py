@@ -56,8 +56,8 @@ class _CSROut(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
-        "sym_block", "num_block", "tr_block", "sym_max_log2", "num_max_log2", "min_table_log2",
-        "load_log2", "tr_lds_cap", "tr_graph_passes")]
+        "sym_block", "num_block", "tr_block", "sym_first_log2", "sym_max_log2", "num_max_entries",
+        "load_pct", "tr_lds_cap", "tr_graph_passes", "bits_max_words")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

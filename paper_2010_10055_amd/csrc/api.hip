@@ -96,9 +96,11 @@ int dibella_get_tuning(dibella_tuning* out) {
 int dibella_set_tuning(const dibella_tuning* t) {
     auto block_ok = [](int b) { return b == 64 || b == 128 || b == 256 || b == 512; };
     if (!t || !block_ok(t->sym_block) || !block_ok(t->num_block) || !block_ok(t->tr_block) ||
-        t->sym_max_log2 < 10 || t->sym_max_log2 > 14 || t->num_max_log2 < 8 || t->num_max_log2 > 12 ||
-        t->min_table_log2 < 5 || t->min_table_log2 > 8 || t->load_log2 < 1 || t->load_log2 > 2 ||
-        t->tr_lds_cap < 256 || t->tr_lds_cap > 8192 || t->tr_graph_passes < 1 || t->tr_graph_passes > 16) {
+        t->sym_first_log2 < 8 || t->sym_first_log2 > 13 || t->sym_max_log2 < t->sym_first_log2 ||
+        t->sym_max_log2 > 14 || t->num_max_entries < 256 || t->num_max_entries > 8192 ||
+        t->load_pct < 40 || t->load_pct > 85 || t->tr_lds_cap < 512 || t->tr_lds_cap > 8192 ||
+        t->tr_graph_passes < 1 || t->tr_graph_passes > 16 || t->bits_max_words < 0 ||
+        t->bits_max_words > 8192) {
         set_error("dibella_set_tuning: value outside the supported range");
         return DIBELLA_EINVAL;
     }

@@ -3,14 +3,23 @@
 // two smallest shared k-mer columns.
 //
 // Pipeline (one launch per step for all sets of a batch):
-//   validate + column histogram  ->  scan  ->  scatter A^T (read, pos) pairs,
-//   per-entry A^T segment (start, length) and per-row products  ->  bins by
-//   products  ->  symbolic (LDS hash of distinct j, counts)  ->  bins by
-//   distinct count  ->  scan to row pointers  ->  numeric (LDS hash with
-//   count and min-2 seeds, bitonic sort by j, coalesced write).
-//   Rows whose distinct columns do not fit an LDS table go through
-//   expand-sort-compress (ESC): products are expanded in k-mer order, stably
-//   radix sorted by j and compressed by runs.
+//   validate + column histogram (the returned count is each entry's slot in
+//   its A^T row)  ->  scan  ->  scatter A^T (read, pos) pairs, per-entry A^T
+//   segment (start, length), products per row, row bins  ->  symbolic  ->
+//   bins by output size  ->  scan to row pointers  ->  numeric.
+// Symbolic and numeric walk the products of one row per workgroup:
+//   * bitmap path (sets whose read count fits an LDS bitmap): the symbolic
+//     phase marks every column j in 1..4 bit planes ("seen >= p times"); the
+//     plane of min_shared lists the output columns already in order.  The
+//     numeric phase maps a column to its output rank with a per-word
+//     popcount prefix.
+//   * hash path (larger sets): LDS hash tables of (j, count) in the symbolic
+//     phase (compacted and bitonic-sorted to give the output columns), a
+//     small LDS hash from j to output rank in the numeric phase.
+//   The symbolic phase stores each row's output columns in a scratch range;
+//   the numeric phase counts and keeps the two smallest-k seeds per column.
+// Rows too dense for LDS go through expand-sort-compress (ESC): products are
+// expanded in k-mer order, stably radix sorted by j and compressed by runs.
 #include "common.hpp"
 
 #include <algorithm>
@@ -25,23 +34,36 @@ struct OvSet {
     int64_t n, m, nnz;
     int64_t row_base, col_base, nnz_base;
     int32_t min_shared;
-    int32_t id_bits;  // bits needed for a read id of this set (ESC radix passes)
+    int32_t id_bits;   // bits needed for a read id of this set (ESC radix passes)
+    int32_t words;     // 32-bit words of a bitmap over the set's reads
+    int32_t use_bits;  // 1: bitmap path, 0: hash path
     int64_t* c_rowptr;
     int32_t* c_col;
     int32_t* c_count;
     int32_t* c_seed;
 };
 
-constexpr int kMaxLog2 = 16;
+constexpr int kMaxLog2 = 16;   // first-level symbolic classes (log2 table size)
+constexpr int kMaxBins = 32;   // numeric bins: hash bins then bitmap bins
+constexpr int kBitsClass = 0;  // symbolic class index used for bitmap rows
 
 struct OvCounters {
     int64_t products;
     int64_t max_flops;
     int64_t esc_flops;
-    int32_t sym_count[kMaxLog2];
-    int32_t num_count[kMaxLog2];
+    int32_t sym_count[kMaxLog2];   // rows per symbolic class
+    int32_t num_count[kMaxBins];   // rows per numeric bin
+    int32_t retry_rows;            // hash rows that overflowed the first table
     int32_t esc_rows;
-    int32_t overflow_rows;
+    int32_t overflow_rows;         // hash rows that overflowed the retry table too
+    int32_t pad;
+};
+
+// Numeric bins: bin b holds rows with output size in (d[b-1], d[b]];
+// bins [0, nh) serve the hash path, bins [nh, nh + nb) the bitmap path.
+struct NumBins {
+    int32_t nh, nb;
+    int32_t d[kMaxBins];
 };
 
 enum : int32_t {
@@ -53,47 +75,100 @@ enum : int32_t {
 };
 
 constexpr uint64_t kEmpty64 = ~0ull;
-
-__device__ __forceinline__ uint32_t hash_slot(int32_t j, int logT) {
-    return ((uint32_t)j * 0x9E3779B1u) >> (32 - logT);
-}
+constexpr int kMaxPlanes = 4;
 
 __device__ __forceinline__ int32_t wave_or(int32_t v) {
     for (int d = kWave / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, kWave);
     return v;
 }
 
-// Insert key j into an open-addressing table (linear probing).  Returns the
-// slot, or -1 if no slot was found within T probes.  *fresh = 1 if this
-// call created the entry.
-__device__ __forceinline__ int table_insert(int32_t* keys, int logT, int32_t j, int* fresh) {
-    const uint32_t mask = (1u << logT) - 1u;
-    uint32_t h = hash_slot(j, logT);
-    *fresh = 0;
-    for (uint32_t p = 0; p <= mask; ++p) {
-        int32_t k = keys[h];
+// Open addressing with linear probing over T slots (any T): the start slot
+// is the high part of (j * golden) * T.
+__device__ __forceinline__ uint32_t hash_slot(int32_t j, uint32_t T) {
+    return (uint32_t)(((uint64_t)((uint32_t)j * 0x9E3779B1u) * (uint64_t)T) >> 32);
+}
+
+// Insert key j; returns its slot, or -1 if all T slots were probed.
+__device__ __forceinline__ int table_insert(int32_t* keys, uint32_t T, int32_t j) {
+    uint32_t h = hash_slot(j, T);
+    for (uint32_t p = 0; p < T; ++p) {
+        const int32_t k = keys[h];
         if (k == j) return (int)h;
         if (k == -1) {
-            int32_t old = atomicCAS(&keys[h], -1, j);
-            if (old == -1) {
-                *fresh = 1;
-                return (int)h;
-            }
-            if (old == j) return (int)h;
+            const int32_t old = atomicCAS(&keys[h], -1, j);
+            if (old == -1 || old == j) return (int)h;
         }
-        h = (h + 1u) & mask;
+        if (++h == T) h = 0;
     }
     return -1;
 }
 
+// Slot of key j, or -1 if absent.
+__device__ __forceinline__ int table_find(const int32_t* keys, uint32_t T, int32_t j) {
+    uint32_t h = hash_slot(j, T);
+    for (uint32_t p = 0; p < T; ++p) {
+        const int32_t k = keys[h];
+        if (k == j) return (int)h;
+        if (k == -1) return -1;
+        if (++h == T) h = 0;
+    }
+    return -1;
+}
+
+// Count one more occurrence of j in a table of u64 slots (j << 32) | count:
+// insertion is a 64-bit CAS, the count a 64-bit add.  Returns the slot or -1
+// (table full); *fresh = 1 if this call created the entry.
+__device__ __forceinline__ int table64_add(uint64_t* tab, uint32_t T, int32_t j, int* fresh) {
+    uint32_t h = hash_slot(j, T);
+    const uint64_t mine = ((uint64_t)(uint32_t)j << 32) | 1ull;
+    *fresh = 0;
+    for (uint32_t p = 0; p < T; ++p) {
+        uint64_t v = tab[h];
+        if (v == kEmpty64) {
+            v = atomicCAS(&tab[h], kEmpty64, mine);
+            if (v == kEmpty64) {
+                *fresh = 1;
+                return (int)h;
+            }
+        }
+        if ((int32_t)(v >> 32) == j) {
+            atomicAdd(&tab[h], 1ull);
+            return (int)h;
+        }
+        if (++h == T) h = 0;
+    }
+    return -1;
+}
+
+// Slots for `keys` distinct keys at a load of at most load_pct percent,
+// rounded up to a multiple of 64.
+__host__ __device__ __forceinline__ int64_t table_slots(int64_t keys, int load_pct) {
+    const int64_t need = (keys * 100 + load_pct - 1) / load_pct;
+    return ((need + 63) / 64) * 64;
+}
+
+// Bit planes of the bitmap path: plane p has bit j set once j was seen
+// more than p times.  With min_shared <= kMaxPlanes planes the last plane
+// is the output set.
+__device__ __forceinline__ void planes_mark(uint32_t* B, int words, int planes, int32_t j) {
+    const int w = j >> 5;
+    const uint32_t bit = 1u << (j & 31);
+    for (int p = 0; p < planes; ++p) {
+        const uint32_t old = atomicOr(&B[p * words + w], bit);
+        if (!(old & bit)) break;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Step 1: validate A, histogram of columns (one wave per row).
+// Step 1: validate A, histogram of columns (one wave per row); the returned
+// count is the entry's slot inside its A^T row.
 // ---------------------------------------------------------------------------
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_hist(const OvSet* __restrict__ sets, int nsets,
                                                         const int64_t* __restrict__ set_base,
                                                         int64_t total_rows, int32_t* __restrict__ cnt,
-                                                        int32_t* __restrict__ flags, int checks) {
+                                                        int32_t* __restrict__ slot, int32_t* __restrict__ flags,
+                                                        int checks) {
     const int lane = lane_id();
     for (int64_t g = (int64_t)blockIdx.x * WPB + wave_id(); g < total_rows;
          g += (int64_t)gridDim.x * WPB) {
@@ -114,7 +189,7 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_hist(const OvSet* __restrict_
                 if (k < 0 || k >= S.m) {
                     bad |= kBadCol;
                 } else {
-                    atomicAdd(&cnt[S.col_base + k], 1);
+                    slot[S.nnz_base + e] = atomicAdd(&cnt[S.col_base + k], 1);
                 }
                 if (checks) {
                     if (e > lo && S.a_col[e - 1] >= k) bad |= kUnsorted;
@@ -129,17 +204,38 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_hist(const OvSet* __restrict_
 
 // ---------------------------------------------------------------------------
 // Step 3: scatter A^T, record each A entry's A^T segment, products per row,
-// and bin rows for the symbolic phase by table size.
+// and bin rows for the symbolic phase: bitmap-path rows in one class,
+// hash-path rows by first-level table size.  A workgroup owns
+// kRowsPerBlock consecutive rows (one wave per row at a time); bin counts
+// and totals are gathered in LDS and published with one global atomic per
+// workgroup and counter.
 // ---------------------------------------------------------------------------
+constexpr int kRowsPerBlock = 64;
+
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
-    const int64_t* __restrict__ t_rowptr, int32_t* __restrict__ cnt, int2* __restrict__ at,
+    const int64_t* __restrict__ t_rowptr, const int32_t* __restrict__ slot_of, int2* __restrict__ at,
     uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row, int32_t* __restrict__ sym_list,
-    OvCounters* __restrict__ ctr, int min_log2, int max_log2, int load_log2) {
+    OvCounters* __restrict__ ctr, int first_log2, int load_pct) {
+    __shared__ int32_t s_cnt[kMaxLog2], s_base[kMaxLog2];
+    __shared__ int32_t s_bin[kRowsPerBlock], s_pos[kRowsPerBlock];
+    __shared__ unsigned long long s_prod;
+    __shared__ int64_t s_max;
     const int lane = lane_id();
-    for (int64_t g = (int64_t)blockIdx.x * WPB + wave_id(); g < total_rows;
-         g += (int64_t)gridDim.x * WPB) {
+    if (threadIdx.x < kMaxLog2) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        s_prod = 0;
+        s_max = 0;
+    }
+    __syncthreads();
+    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock;
+    for (int r = wave_id(); r < kRowsPerBlock; r += WPB) {
+        const int64_t g = row0 + r;
+        if (g >= total_rows) {
+            if (lane == 0) s_bin[r] = -1;
+            continue;
+        }
         const int s = find_set(set_base, nsets, g);
         const OvSet& S = sets[s];
         const int64_t i = g - S.row_base;
@@ -153,8 +249,7 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
                     const int64_t gk = S.col_base + k;
                     const int64_t t0 = t_rowptr[gk];
                     const int64_t len = t_rowptr[gk + 1] - t0;
-                    const int32_t slot = atomicSub(&cnt[gk], 1) - 1;
-                    at[t0 + slot] = make_int2((int32_t)i, S.a_val[e]);
+                    at[t0 + slot_of[S.nnz_base + e]] = make_int2((int32_t)i, S.a_val[e]);
                     sg = ((uint64_t)t0 << 24) | (uint64_t)len;
                     fl += len;
                 }
@@ -164,29 +259,51 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
         fl = wave_sum(fl);
         if (lane == 0) {
             flops_row[g] = fl;
+            s_bin[r] = -1;
             if (fl > 0) {
-                atomic_add(&ctr->products, fl);
-                atomic_max(&ctr->max_flops, fl);
-                const int64_t keys = fl < S.n ? fl : S.n;
-                int lg = ceil_log2_i64(keys) + load_log2;
-                lg = lg < min_log2 ? min_log2 : (lg > max_log2 ? max_log2 : lg);
-                const int32_t pos = atomicAdd(&ctr->sym_count[lg], 1);
-                sym_list[(int64_t)lg * total_rows + pos] = (int32_t)g;
+                atomicAdd(&s_prod, (unsigned long long)fl);
+                atomic_max(&s_max, fl);
+                int lg = kBitsClass;
+                if (!S.use_bits) {
+                    const int64_t keys = fl < S.n ? fl : S.n;
+                    lg = ceil_log2_i64((keys * 100 + load_pct - 1) / load_pct);
+                    lg = lg < 6 ? 6 : (lg > first_log2 ? first_log2 : lg);
+                }
+                s_bin[r] = lg;
+                s_pos[r] = atomicAdd(&s_cnt[lg], 1);
             }
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxLog2 && s_cnt[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&ctr->sym_count[threadIdx.x], s_cnt[threadIdx.x]);
+    if (threadIdx.x == kWave && s_prod > 0) {
+        atomic_add(&ctr->products, (int64_t)s_prod);
+        atomic_max(&ctr->max_flops, s_max);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < kRowsPerBlock; r += WPB * kWave) {
+        const int b = s_bin[r];
+        if (b >= 0) sym_list[(int64_t)b * total_rows + s_base[b] + s_pos[r]] = (int32_t)(row0 + r);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Shared product walk: for each A entry t of row i (in chunks of BLOCK) the
-// A^T segment seg[t]; products are numbered t-major, and f(t, e) is called
-// for product e of A^T belonging to entry t.  The block must call it
-// uniformly.  `stop` (LDS flag) lets the callee abandon the walk.
+// Shared product walk: the A entries t of row i are taken in chunks of
+// BLOCK; seg[t] gives the A^T segment (start, length) of entry t, and the
+// products of the chunk are numbered t-major.  Each thread takes PER
+// products per step, resolves their t by binary search over the chunk's
+// prefix sums and issues all PER gathers of A^T pairs before handing them
+// to f(t, (j, p_j), q), so that PER independent loads are in flight.
+// The block must call it uniformly.  `stop` (LDS flag) abandons the walk.
 // ---------------------------------------------------------------------------
+constexpr int kPer = 4;
+
 template <int BLOCK, class F>
-__device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L, int64_t* c_start,
-                                              int64_t* c_off, int64_t* s_tmp, const int32_t* stop,
-                                              F&& f) {
+__device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
+                                              const int2* __restrict__ at, int64_t* c_start, int64_t* c_off,
+                                              int64_t* s_tmp, const int32_t* stop, F&& f) {
+    int64_t done = 0;   // products of earlier chunks
     for (int cbase = 0; cbase < L; cbase += BLOCK) {
         const int cl = min(BLOCK, L - cbase);
         int64_t len = 0, st = 0;
@@ -200,37 +317,52 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
         c_start[threadIdx.x] = st;
         c_off[threadIdx.x] = ex;
         __syncthreads();
-        for (int64_t q = threadIdx.x; q < tot; q += BLOCK) {
+        for (int64_t q0 = threadIdx.x; q0 < tot; q0 += (int64_t)BLOCK * kPer) {
             if (stop && *(volatile const int32_t*)stop) break;
-            int lo = 0, hi = cl - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (c_off[mid] <= q) lo = mid; else hi = mid - 1;
+            int tt[kPer];
+            int2 jp[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int64_t q = q0 + (int64_t)u * BLOCK;
+                tt[u] = -1;
+                if (q < tot) {
+                    int lo = 0, hi = cl - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (c_off[mid] <= q) lo = mid; else hi = mid - 1;
+                    }
+                    tt[u] = lo;
+                    jp[u] = at[c_start[lo] + (q - c_off[lo])];
+                }
             }
-            f(cbase + lo, c_start[lo] + (q - c_off[lo]), q);
+#pragma unroll
+            for (int u = 0; u < kPer; ++u)
+                if (tt[u] >= 0) f(cbase + tt[u], jp[u], done + q0 + (int64_t)u * BLOCK);
         }
+        done += tot;
         __syncthreads();
         if (stop && *(volatile const int32_t*)stop) break;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Symbolic phase: distinct j per row and how many reach min_shared.
+// Symbolic phase, bitmap path.  Per row: mark every product's j in the bit
+// planes; the output columns are the set bits of plane min_shared - 1,
+// written to the row's scratch range in increasing order.
+// LDS: chunk arrays | planes x words u32.
 // ---------------------------------------------------------------------------
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_ov_symbolic(
+__global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
-    const int32_t* __restrict__ list, int logT, int limit, const uint64_t* __restrict__ seg,
-    const int2* __restrict__ at, int64_t* __restrict__ nnzrow, int32_t* __restrict__ distinct,
-    OvCounters* __restrict__ ctr) {
+    const int32_t* __restrict__ list, const uint64_t* __restrict__ seg, const int2* __restrict__ at,
+    const int64_t* __restrict__ soff, int32_t* __restrict__ scratch, int64_t* __restrict__ nnzrow,
+    int32_t* __restrict__ distinct) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int T = 1 << logT;
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + BLOCK;
-    int32_t* keys = reinterpret_cast<int32_t*>(c_off + BLOCK);
-    int32_t* cnt = keys + T;
+    uint32_t* B = reinterpret_cast<uint32_t*>(c_off + BLOCK);
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
-    __shared__ int32_t s_nd, s_ovf, s_red;
+    __shared__ int32_t s_red;
 
     const int64_t g = list[blockIdx.x];
     const int s = find_set(set_base, nsets, g);
@@ -238,68 +370,310 @@ __global__ __launch_bounds__(BLOCK) void k_ov_symbolic(
     const int64_t i = g - S.row_base;
     const int64_t lo = S.a_rowptr[i];
     const int L = (int)(S.a_rowptr[i + 1] - lo);
-    for (int q = threadIdx.x; q < T; q += BLOCK) {
-        keys[q] = -1;
-        cnt[q] = 0;
-    }
-    if (threadIdx.x == 0) {
-        s_nd = 0;
-        s_ovf = 0;
-    }
+    const int words = S.words;
+    const int planes = S.min_shared;
+    for (int q = threadIdx.x; q < planes * words; q += BLOCK) B[q] = 0u;
     __syncthreads();
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, c_start, c_off, s_tmp, &s_ovf,
-                         [&](int, int64_t e, int64_t) {
-                             const int32_t j = at[e].x;
-                             int fresh;
-                             const int slot = table_insert(keys, logT, j, &fresh);
-                             if (slot < 0) {
-                                 s_ovf = 1;
-                                 return;
-                             }
-                             atomicAdd(&cnt[slot], 1);
-                             if (fresh && atomicAdd(&s_nd, 1) + 1 >= limit) s_ovf = 1;
-                         });
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, nullptr,
+                         [&](int, int2 jp, int64_t) { planes_mark(B, words, planes, jp.x); });
     __syncthreads();
-    if (s_ovf) {
-        if (threadIdx.x == 0) {
-            nnzrow[g] = 0;
-            distinct[g] = -1;
-            atomicAdd(&ctr->overflow_rows, 1);
+    const uint32_t* out_plane = B + (planes - 1) * words;
+    int32_t d = 0;
+    for (int w = threadIdx.x; w < words; w += BLOCK) d += __popc(B[w]);
+    d = block_sum_lds(d, &s_red);
+    int32_t* out = scratch + soff[g];
+    int64_t base = 0;
+    for (int c = 0; c < words; c += BLOCK) {
+        const int w = c + threadIdx.x;
+        uint32_t bits = w < words ? out_plane[w] : 0u;
+        int64_t tot;
+        int64_t pos = base + block_exclusive_sum<BLOCK>((int64_t)__popc(bits), s_tmp, &tot);
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            out[pos++] = (w << 5) | b;
+            bits &= bits - 1;
         }
-        return;
+        base += tot;
     }
-    int32_t mine = 0;
-    for (int q = threadIdx.x; q < T; q += BLOCK)
-        if (keys[q] != -1 && cnt[q] >= S.min_shared) ++mine;
-    const int32_t tot = block_sum_lds(mine, &s_red);
     if (threadIdx.x == 0) {
-        nnzrow[g] = tot;
-        distinct[g] = s_nd;
+        nnzrow[g] = base;
+        distinct[g] = d;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Bins for the numeric phase, ESC routing.
+// Symbolic phase, hash path.  Per row: count every j in an LDS hash table
+// whose slot is one u64 = (j << 32) | count, then compact the entries with
+// count >= min_shared to the front of the table, bitonic-sort them by j (the
+// high word) and store the sorted columns in the row's scratch range.
+// Work items come from `list` (count = *dcount if given, else hcount).  The
+// first level uses a table sized for min(products, n) keys capped at a
+// modest size; a row that exceeds the load limit is queued for the retry
+// level (one large table per workgroup); at the retry level an overflowing
+// row is marked for expand-sort-compress (distinct = -1).
+// LDS: chunk arrays | T u64.
 // ---------------------------------------------------------------------------
-__global__ void k_ov_bin_numeric(int64_t total_rows, const int64_t* __restrict__ flops_row,
-                                 const int32_t* __restrict__ distinct, int32_t* __restrict__ num_list,
-                                 int32_t* __restrict__ esc_list, int64_t* __restrict__ esc_off,
-                                 OvCounters* __restrict__ ctr, int min_log2, int max_log2, int load_log2) {
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
+    const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ dcount, int hcount, int T, int limit,
+    int retry_level, int32_t* __restrict__ retry_list, const uint64_t* __restrict__ seg,
+    const int2* __restrict__ at, const int64_t* __restrict__ soff, int32_t* __restrict__ scratch,
+    int64_t* __restrict__ nnzrow, int32_t* __restrict__ distinct, OvCounters* __restrict__ ctr) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t* c_start = reinterpret_cast<int64_t*>(smem);
+    int64_t* c_off = c_start + BLOCK;
+    uint64_t* tab = reinterpret_cast<uint64_t*>(c_off + BLOCK);
+    __shared__ int64_t s_tmp[BLOCK / kWave + 1];
+    __shared__ int32_t s_nd, s_ovf;
+    const int items = dcount ? *dcount : hcount;
+    for (int w = blockIdx.x; w < items; w += gridDim.x) {
+        const int64_t g = list[w];
+        const int s = find_set(set_base, nsets, g);
+        const OvSet& S = sets[s];
+        const int64_t i = g - S.row_base;
+        const int64_t lo = S.a_rowptr[i];
+        const int L = (int)(S.a_rowptr[i + 1] - lo);
+        for (int q = threadIdx.x; q < T; q += BLOCK) tab[q] = kEmpty64;
+        if (threadIdx.x == 0) {
+            s_nd = 0;
+            s_ovf = 0;
+        }
+        __syncthreads();
+        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, &s_ovf,
+                             [&](int, int2 jp, int64_t) {
+                                 int fresh;
+                                 const int slot = table64_add(tab, (uint32_t)T, jp.x, &fresh);
+                                 if (slot < 0) {
+                                     s_ovf = 1;
+                                     return;
+                                 }
+                                 if (fresh && atomicAdd(&s_nd, 1) + 1 > limit) s_ovf = 1;
+                             });
+        __syncthreads();
+        if (s_ovf) {
+            if (threadIdx.x == 0) {
+                if (retry_level == 0) {
+                    retry_list[atomicAdd(&ctr->retry_rows, 1)] = (int32_t)g;
+                } else {
+                    nnzrow[g] = 0;
+                    distinct[g] = -1;
+                    atomicAdd(&ctr->overflow_rows, 1);
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        // in-place compaction of the selected entries (each moves left)
+        const uint32_t ms = (uint32_t)S.min_shared;
+        int64_t nsel = 0;
+        for (int c = 0; c < T; c += BLOCK) {
+            const int q = c + threadIdx.x;
+            const uint64_t v = q < T ? tab[q] : kEmpty64;
+            const int64_t take = (v != kEmpty64 && (uint32_t)v >= ms) ? 1 : 0;
+            int64_t tot;
+            const int64_t ex = block_exclusive_sum<BLOCK>(take, s_tmp, &tot);   // barriers: all reads done
+            if (take) tab[nsel + ex] = v;
+            nsel += tot;
+            __syncthreads();
+        }
+        int P = 1;
+        while (P < nsel) P <<= 1;
+        for (int q = (int)nsel + threadIdx.x; q < P; q += BLOCK) tab[q] = kEmpty64;
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int idx = threadIdx.x; idx < P; idx += BLOCK) {
+                    const int ixj = idx ^ jj;
+                    if (ixj > idx) {
+                        const uint64_t a = tab[idx], b = tab[ixj];
+                        if ((a > b) == ((idx & k) == 0)) {
+                            tab[idx] = b;
+                            tab[ixj] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        int32_t* out = scratch + soff[g];
+        for (int r = threadIdx.x; r < nsel; r += BLOCK) out[r] = (int32_t)(tab[r] >> 32);
+        if (threadIdx.x == 0) {
+            nnzrow[g] = nsel;
+            distinct[g] = s_nd;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bins for the numeric phase by output size and path, ESC routing.
+// ---------------------------------------------------------------------------
+constexpr int kBinBlock = 256;
+
+__global__ __launch_bounds__(kBinBlock) void k_ov_bin_numeric(
+    const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
+    const int64_t* __restrict__ flops_row, const int32_t* __restrict__ distinct,
+    const int64_t* __restrict__ nnzrow, int32_t* __restrict__ num_list, int32_t* __restrict__ esc_list,
+    int64_t* __restrict__ esc_off, OvCounters* __restrict__ ctr, NumBins bins) {
+    __shared__ int32_t s_cnt[kMaxBins + 1], s_base[kMaxBins + 1];   // last slot: ESC
+    __shared__ unsigned long long s_flops;
+    __shared__ int64_t s_flops_base;
+    if (threadIdx.x <= kMaxBins) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_flops = 0;
+    __syncthreads();
+    const int64_t g = blockIdx.x * (int64_t)kBinBlock + threadIdx.x;
+    int b = -1, pos = 0;
+    int64_t foff = 0;
+    if (g < total_rows) {
+        const int64_t fl = flops_row[g];
+        const int64_t nz = nnzrow[g];
+        const bool bits = sets[find_set(set_base, nsets, g)].use_bits;
+        const int b0 = bits ? bins.nh : 0;
+        const int b1 = bits ? bins.nh + bins.nb : bins.nh;
+        if (fl > 0 && (distinct[g] < 0 || b1 == b0 || nz > bins.d[b1 - 1])) {
+            b = kMaxBins;
+            foff = (int64_t)atomicAdd(&s_flops, (unsigned long long)fl);
+        } else if (nz > 0) {
+            b = b0;
+            while (bins.d[b] < nz) ++b;
+        }
+        if (b >= 0) pos = atomicAdd(&s_cnt[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxBins && s_cnt[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&ctr->num_count[threadIdx.x], s_cnt[threadIdx.x]);
+    if (threadIdx.x == kMaxBins && s_cnt[kMaxBins] > 0) {
+        s_base[kMaxBins] = atomicAdd(&ctr->esc_rows, s_cnt[kMaxBins]);
+        s_flops_base = atomic_add(&ctr->esc_flops, (int64_t)s_flops);
+    }
+    __syncthreads();
+    if (b == kMaxBins) {
+        esc_list[s_base[b] + pos] = (int32_t)g;
+        esc_off[g] = s_flops_base + foff;
+    } else if (b >= 0) {
+        num_list[(int64_t)b * total_rows + s_base[b] + pos] = (int32_t)g;
+    }
+}
+
+// Scratch range of a row for its output columns: at most min(products, n)
+// distinct columns, and each kept one needs min_shared products.
+__global__ void k_ov_scratch_bound(const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
+                                   int64_t total_rows, const int64_t* __restrict__ flops_row,
+                                   int64_t* __restrict__ bound) {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total_rows;
          g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t fl = flops_row[g];
-        if (fl <= 0) continue;
-        const int32_t d = distinct[g];
-        const int lg = ceil_log2_i64(d < 1 ? 1 : d) + load_log2;
-        if (d < 0 || lg > max_log2) {
-            const int32_t pos = atomicAdd(&ctr->esc_rows, 1);
-            esc_list[pos] = (int32_t)g;
-            esc_off[g] = atomic_add(&ctr->esc_flops, fl);
+        const OvSet& S = sets[find_set(set_base, nsets, g)];
+        const int64_t a = flops_row[g] / S.min_shared;
+        bound[g] = a < S.n ? a : S.n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Numeric phase.  The row's output columns are its sorted list in scratch;
+// one pass over the products counts every listed j and keeps its two
+// smallest seed candidates (t << 32) | p_j, t = index of k in row i
+// (monotone in k), with an atomicMin cascade (the value displaced from m1
+// moves on to m2).  The rank r of a listed column j comes from
+//   bitmap path: a bitmap of the listed columns and a per-word popcount
+//                prefix: r = prefix[j / 32] + popcount(lower bits of word);
+//   hash path:   a small LDS hash from j to r.
+// LDS: chunk arrays | m1, m2 (D u64) | cnt (D i32) | map.
+// ---------------------------------------------------------------------------
+template <int BLOCK, bool BITS>
+__global__ __launch_bounds__(BLOCK) void k_ov_numeric(
+    const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
+    const int32_t* __restrict__ list, int Dmax, int load_pct, const int64_t* __restrict__ nnzrow,
+    const int64_t* __restrict__ soff, const int32_t* __restrict__ scratch, const uint64_t* __restrict__ seg,
+    const int2* __restrict__ at, const int64_t* __restrict__ G) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t* c_start = reinterpret_cast<int64_t*>(smem);
+    int64_t* c_off = c_start + BLOCK;
+    uint64_t* m1 = reinterpret_cast<uint64_t*>(c_off + BLOCK);
+    uint64_t* m2 = m1 + Dmax;
+    int32_t* cnt = reinterpret_cast<int32_t*>(m2 + Dmax);
+    int32_t* map = cnt + Dmax;   // BITS: bitmap (words) + prefix (words); else keys (T) + rank (T)
+    __shared__ int64_t s_tmp[BLOCK / kWave + 1];
+
+    const int64_t g = list[blockIdx.x];
+    const int s = find_set(set_base, nsets, g);
+    const OvSet& S = sets[s];
+    const int64_t i = g - S.row_base;
+    const int64_t lo = S.a_rowptr[i];
+    const int L = (int)(S.a_rowptr[i + 1] - lo);
+    const int nsel = (int)nnzrow[g];
+    const int32_t* sel = scratch + soff[g];
+    const int words = S.words;
+    const uint32_t T = BITS ? 0u : (uint32_t)table_slots(nsel, load_pct);
+    uint32_t* bm = reinterpret_cast<uint32_t*>(map);
+    int32_t* pre = map + words;
+    int32_t* keys = map;
+    int32_t* rank = map + T;
+    if (BITS) {
+        for (int q = threadIdx.x; q < words; q += BLOCK) bm[q] = 0u;
+    } else {
+        for (uint32_t q = threadIdx.x; q < T; q += BLOCK) keys[q] = -1;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nsel; r += BLOCK) {
+        const int32_t j = sel[r];
+        if (BITS) {
+            atomicOr(&bm[j >> 5], 1u << (j & 31));
         } else {
-            const int l = lg < min_log2 ? min_log2 : lg;
-            const int32_t pos = atomicAdd(&ctr->num_count[l], 1);
-            num_list[(int64_t)l * total_rows + pos] = (int32_t)g;
+            const int slot = table_insert(keys, T, j);
+            if (slot >= 0) rank[slot] = r;
         }
+        cnt[r] = 0;
+        m1[r] = kEmpty64;
+        m2[r] = kEmpty64;
+    }
+    __syncthreads();
+    if (BITS) {
+        int64_t base = 0;
+        for (int c = 0; c < words; c += BLOCK) {
+            const int w = c + threadIdx.x;
+            const int64_t v = w < words ? __popc(bm[w]) : 0;
+            int64_t tot;
+            const int64_t ex = block_exclusive_sum<BLOCK>(v, s_tmp, &tot);
+            if (w < words) pre[w] = (int32_t)(base + ex);
+            base += tot;
+        }
+        __syncthreads();
+    }
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, nullptr,
+                         [&](int t, int2 jp, int64_t) {
+                             int r;
+                             if (BITS) {
+                                 const uint32_t word = bm[jp.x >> 5];
+                                 const uint32_t bit = 1u << (jp.x & 31);
+                                 if (!(word & bit)) return;
+                                 r = pre[jp.x >> 5] + __popc(word & (bit - 1u));
+                             } else {
+                                 const int slot = table_find(keys, T, jp.x);
+                                 if (slot < 0) return;
+                                 r = rank[slot];
+                             }
+                             atomicAdd(&cnt[r], 1);
+                             const uint64_t x = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
+                             const uint64_t old = atomicMin(&m1[r], x);
+                             const uint64_t rej = old > x ? old : x;
+                             if (rej != kEmpty64) atomicMin(&m2[r], rej);
+                         });
+    __syncthreads();
+    const int64_t off = G[g] - G[S.row_base];
+    int4* seed4 = reinterpret_cast<int4*>(S.c_seed);
+    for (int r = threadIdx.x; r < nsel; r += BLOCK) {
+        const uint64_t a = m1[r], b = m2[r];
+        const int32_t pi0 = S.a_val[lo + (int64_t)(a >> 32)];
+        const int32_t pj0 = (int32_t)(uint32_t)a;
+        int32_t pi1 = -1, pj1 = -1;
+        if (b != kEmpty64) {
+            pi1 = S.a_val[lo + (int64_t)(b >> 32)];
+            pj1 = (int32_t)(uint32_t)b;
+        }
+        S.c_col[off + r] = sel[r];
+        S.c_count[off + r] = cnt[r];
+        seed4[off + r] = make_int4(pi0, pj0, pi1, pj1);
     }
 }
 
@@ -328,103 +702,6 @@ __global__ void k_ov_write_rowptr(const OvSet* __restrict__ sets, int nsets,
 }
 
 // ---------------------------------------------------------------------------
-// Numeric phase: counts and the two smallest-k seeds per (i, j), sorted
-// output.  A seed candidate is packed as (t << 32) | p_j where t is the
-// index of k in row i (monotone in k); the two smallest survive an
-// atomicMin cascade (the value displaced from m1 moves on to m2).
-// ---------------------------------------------------------------------------
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_ov_numeric(
-    const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
-    const int32_t* __restrict__ list, int logT, const uint64_t* __restrict__ seg,
-    const int2* __restrict__ at, const int64_t* __restrict__ G) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int T = 1 << logT;
-    uint64_t* m1 = reinterpret_cast<uint64_t*>(smem);
-    uint64_t* m2 = m1 + T;
-    uint64_t* sortbuf = m2 + T;                                   // T/2
-    int64_t* c_start = reinterpret_cast<int64_t*>(sortbuf + T / 2);
-    int64_t* c_off = c_start + BLOCK;
-    int32_t* keys = reinterpret_cast<int32_t*>(c_off + BLOCK);
-    int32_t* cnt = keys + T;
-    __shared__ int64_t s_tmp[BLOCK / kWave + 1];
-    __shared__ int32_t s_nsel;
-
-    const int64_t g = list[blockIdx.x];
-    const int s = find_set(set_base, nsets, g);
-    const OvSet& S = sets[s];
-    const int64_t i = g - S.row_base;
-    const int64_t lo = S.a_rowptr[i];
-    const int L = (int)(S.a_rowptr[i + 1] - lo);
-    for (int q = threadIdx.x; q < T; q += BLOCK) {
-        keys[q] = -1;
-        cnt[q] = 0;
-        m1[q] = kEmpty64;
-        m2[q] = kEmpty64;
-    }
-    if (threadIdx.x == 0) s_nsel = 0;
-    __syncthreads();
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, c_start, c_off, s_tmp, nullptr,
-                         [&](int t, int64_t e, int64_t) {
-                             const int2 jp = at[e];
-                             int fresh;
-                             const int slot = table_insert(keys, logT, jp.x, &fresh);
-                             if (slot < 0) return;  // cannot happen: the table holds 2x the distinct keys
-                             atomicAdd(&cnt[slot], 1);
-                             const uint64_t x = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
-                             const uint64_t old = atomicMin(&m1[slot], x);
-                             const uint64_t rej = old > x ? old : x;
-                             if (rej != kEmpty64) atomicMin(&m2[slot], rej);
-                         });
-    __syncthreads();
-    for (int q = threadIdx.x; q < T; q += BLOCK) {
-        if (keys[q] != -1 && cnt[q] >= S.min_shared) {
-            const int p = atomicAdd(&s_nsel, 1);
-            sortbuf[p] = ((uint64_t)(uint32_t)keys[q] << 32) | (uint64_t)q;
-        }
-    }
-    __syncthreads();
-    const int nsel = s_nsel;
-    int P = 1;
-    while (P < nsel) P <<= 1;
-    for (int q = nsel + threadIdx.x; q < P; q += BLOCK) sortbuf[q] = kEmpty64;
-    __syncthreads();
-    // bitonic sort of sortbuf[0, P) ascending
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int idx = threadIdx.x; idx < P; idx += BLOCK) {
-                const int ixj = idx ^ jj;
-                if (ixj > idx) {
-                    const uint64_t a = sortbuf[idx], b = sortbuf[ixj];
-                    const bool up = (idx & k) == 0;
-                    if ((a > b) == up) {
-                        sortbuf[idx] = b;
-                        sortbuf[ixj] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    const int64_t off = G[g] - G[S.row_base];
-    int4* seed4 = reinterpret_cast<int4*>(S.c_seed);
-    for (int r = threadIdx.x; r < nsel; r += BLOCK) {
-        const int slot = (int)(uint32_t)sortbuf[r];
-        const uint64_t a = m1[slot], b = m2[slot];
-        const int32_t pi0 = S.a_val[lo + (int64_t)(a >> 32)];
-        const int32_t pj0 = (int32_t)(uint32_t)a;
-        int32_t pi1 = -1, pj1 = -1;
-        if (b != kEmpty64) {
-            pi1 = S.a_val[lo + (int64_t)(b >> 32)];
-            pj1 = (int32_t)(uint32_t)b;
-        }
-        S.c_col[off + r] = keys[slot];
-        S.c_count[off + r] = cnt[slot];
-        seed4[off + r] = make_int4(pi0, pj0, pi1, pj1);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // ESC (expand - sort - compress) for rows too dense for an LDS table.
 // ---------------------------------------------------------------------------
 constexpr int kEscBlock = 256;
@@ -442,36 +719,12 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int64_t lo = S.a_rowptr[i];
     const int L = (int)(S.a_rowptr[i + 1] - lo);
     const int64_t base = esc_off[g];
-    // walk_products numbers products per chunk; keep a running base so that
-    // the expanded order is t-major over the whole row.
-    int64_t chunk_base = 0;
-    for (int cbase = 0; cbase < L; cbase += kEscBlock) {
-        const int cl = min(kEscBlock, L - cbase);
-        int64_t len = 0, st = 0;
-        if ((int)threadIdx.x < cl) {
-            const uint64_t sg = seg[S.nnz_base + lo + cbase + threadIdx.x];
-            st = (int64_t)(sg >> 24);
-            len = (int64_t)(sg & 0xFFFFFFull);
-        }
-        int64_t tot;
-        const int64_t ex = block_exclusive_sum<kEscBlock>(len, s_tmp, &tot);
-        c_start[threadIdx.x] = st;
-        c_off[threadIdx.x] = ex;
-        __syncthreads();
-        for (int64_t q = threadIdx.x; q < tot; q += kEscBlock) {
-            int a = 0, b = cl - 1;
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (c_off[mid] <= q) a = mid; else b = mid - 1;
-            }
-            const int2 jp = at[c_start[a] + (q - c_off[a])];
-            const int64_t dst = base + chunk_base + q;
-            keys0[dst] = (uint32_t)jp.x;
-            pay0[dst] = ((uint64_t)(uint32_t)(cbase + a) << 32) | (uint64_t)(uint32_t)jp.y;
-        }
-        chunk_base += tot;
-        __syncthreads();
-    }
+    // products land at their t-major index, so the expansion is ordered by k
+    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, nullptr,
+                             [&](int t, int2 jp, int64_t q) {
+                                 keys0[base + q] = (uint32_t)jp.x;
+                                 pay0[base + q] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
+                             });
 }
 
 // Stable LSD radix sort (8-bit digits) of one row's expanded products by j.
@@ -553,10 +806,24 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_sort(
     }
 }
 
-__device__ __forceinline__ int64_t run_length(const uint32_t* k, int64_t e, int64_t F) {
-    int64_t r = e + 1;
-    while (r < F && k[r] == k[e]) ++r;
-    return r - e;
+// Runs of equal keys in one sorted ESC row, tile by tile: each element learns
+// the start of its run from an inclusive max-scan of start positions (carried
+// across tiles); the run's last element then knows its length.
+template <int BLOCK>
+__device__ __forceinline__ int64_t block_inclusive_max(int64_t v, int64_t* tmp) {
+    constexpr int W = BLOCK / kWave;
+    const int lane = lane_id(), w = wave_id();
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t y = __shfl_up(v, d, kWave);
+        if (lane >= d) v = y > v ? y : v;
+    }
+    if (lane == kWave - 1) tmp[w] = v;
+    __syncthreads();
+    int64_t pre = -1;
+    for (int q = 0; q < w; ++q) pre = tmp[q] > pre ? tmp[q] : pre;
+    __syncthreads();
+    (void)W;
+    return v > pre ? v : pre;
 }
 
 __global__ __launch_bounds__(kEscBlock) void k_esc_count(
@@ -564,18 +831,29 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_count(
     const int32_t* __restrict__ list, const int64_t* __restrict__ esc_off,
     const int64_t* __restrict__ flops_row, const uint32_t* __restrict__ keys0,
     int64_t* __restrict__ nnzrow, int32_t* __restrict__ distinct) {
-    __shared__ int64_t s_red;
+    __shared__ int64_t s_tmp[kEscBlock / kWave + 1];
+    __shared__ int64_t s_red, s_last;
     const int64_t g = list[blockIdx.x];
     const int s = find_set(set_base, nsets, g);
     const int32_t ms = sets[s].min_shared;
     const uint32_t* k = keys0 + esc_off[g];
     const int64_t F = flops_row[g];
-    int64_t runs = 0, sel = 0;
-    for (int64_t e = threadIdx.x; e < F; e += kEscBlock) {
-        if (e == 0 || k[e] != k[e - 1]) {
+    int64_t runs = 0, sel = 0, carry = -1;
+    for (int64_t tile = 0; tile < F; tile += kEscBlock) {
+        const int64_t e = tile + threadIdx.x;
+        const bool in = e < F;
+        const bool start = in && (e == 0 || k[e] != k[e - 1]);
+        const bool end = in && (e == F - 1 || k[e + 1] != k[e]);
+        int64_t st = block_inclusive_max<kEscBlock>(start ? e : -1, s_tmp);
+        st = st > carry ? st : carry;
+        if (end) {
             ++runs;
-            if (run_length(k, e, F) >= ms) ++sel;
+            if (e - st + 1 >= ms) ++sel;
         }
+        if (threadIdx.x == kEscBlock - 1) s_last = st;
+        __syncthreads();
+        carry = s_last;
+        __syncthreads();
     }
     runs = block_sum_lds(runs, &s_red);
     sel = block_sum_lds(sel, &s_red);
@@ -591,6 +869,7 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_emit(
     const int64_t* __restrict__ flops_row, const uint32_t* __restrict__ keys0,
     const uint64_t* __restrict__ pay0, const int64_t* __restrict__ G) {
     __shared__ int64_t s_tmp[kEscBlock / kWave + 1];
+    __shared__ int64_t s_last;
     const int64_t g = list[blockIdx.x];
     const int s = find_set(set_base, nsets, g);
     const OvSet& S = sets[s];
@@ -601,23 +880,24 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_emit(
     const int64_t F = flops_row[g];
     const int64_t off0 = G[g] - G[S.row_base];
     int4* seed4 = reinterpret_cast<int4*>(S.c_seed);
-    int64_t carry = 0;
+    int64_t carry = -1, written = 0;
     for (int64_t tile = 0; tile < F; tile += kEscBlock) {
         const int64_t e = tile + threadIdx.x;
-        int64_t rl = 0;
-        int64_t take = 0;
-        if (e < F && (e == 0 || k[e] != k[e - 1])) {
-            rl = run_length(k, e, F);
-            take = rl >= S.min_shared ? 1 : 0;
-        }
+        const bool in = e < F;
+        const bool start = in && (e == 0 || k[e] != k[e - 1]);
+        const bool end = in && (e == F - 1 || k[e + 1] != k[e]);
+        int64_t st = block_inclusive_max<kEscBlock>(start ? e : -1, s_tmp);
+        st = st > carry ? st : carry;
+        const int64_t rl = end ? e - st + 1 : 0;
+        const int64_t take = (end && rl >= S.min_shared) ? 1 : 0;
         int64_t tot;
         const int64_t ex = block_exclusive_sum<kEscBlock>(take, s_tmp, &tot);
         if (take) {
-            const int64_t o = off0 + carry + ex;
-            const uint64_t a = p[e];
+            const int64_t o = off0 + written + ex;
+            const uint64_t a = p[st];
             int32_t pi1 = -1, pj1 = -1;
             if (rl >= 2) {
-                const uint64_t b = p[e + 1];
+                const uint64_t b = p[st + 1];
                 pi1 = S.a_val[lo + (int64_t)(b >> 32)];
                 pj1 = (int32_t)(uint32_t)b;
             }
@@ -625,67 +905,160 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_emit(
             S.c_count[o] = (int32_t)rl;
             seed4[o] = make_int4(S.a_val[lo + (int64_t)(a >> 32)], (int32_t)(uint32_t)a, pi1, pj1);
         }
-        carry += tot;
+        written += tot;
+        if (threadIdx.x == kEscBlock - 1) s_last = st;
+        __syncthreads();
+        carry = s_last;
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
-template <int BLOCK>
-static size_t sym_lds(int logT) { return (size_t)BLOCK * 16 + ((size_t)8 << logT); }
-template <int BLOCK>
-static size_t num_lds(int logT) {
-    return ((size_t)1 << logT) * (8 + 8 + 4 + 4 + 4) + (size_t)BLOCK * 16;
+// Dynamic LDS budget per workgroup: the 160 KB of a gfx950 CU minus room
+// for the kernels' static LDS.
+constexpr size_t kLdsLimit = 158 * 1024;
+
+static size_t sym_hash_lds(int block, int T) { return (size_t)block * 16 + (size_t)T * 8; }
+static size_t sym_bits_lds(int block, int planes, int words) {
+    return (size_t)block * 16 + (size_t)planes * words * 4;
+}
+// Numeric LDS for rows with at most D output entries: chunk arrays,
+// m1/m2/cnt, and the column map (bitmap + prefix, or hash keys + ranks).
+static size_t num_lds(int block, int D, int load_pct, bool bits, int words) {
+    const size_t map = bits ? (size_t)words * 8 : (size_t)table_slots(D, load_pct) * 8;
+    return (size_t)block * 16 + (size_t)D * 20 + map;
+}
+
+// Workgroup width for a launch whose LDS footprint is `lds` at 256 threads:
+// few workgroups fit a CU when the footprint is large, so those get more
+// threads (more loads in flight per CU).
+static int wide_block(int base, size_t lds) {
+    if (lds > 80 * 1024) return 1024;
+    if (lds > 40 * 1024) return std::max(base, 512);
+    return base;
 }
 
 template <int BLOCK>
-static int launch_symbolic(const OvSet* d_sets, int nsets, const int64_t* d_base, const int32_t* list,
-                           int count, int logT, int limit, const uint64_t* seg, const int2* at,
-                           int64_t* nnzrow, int32_t* distinct, OvCounters* ctr, hipStream_t st) {
-    const size_t lds = sym_lds<BLOCK>(logT);
-    (void)hipFuncSetAttribute((const void*)k_ov_symbolic<BLOCK>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_ov_symbolic<BLOCK>, dim3(count), dim3(BLOCK), lds, st, d_sets, nsets, d_base,
-                       list, logT, limit, seg, at, nnzrow, distinct, ctr);
+static int allow_lds_ov() {
+    static bool done = false;
+    if (!done) {
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_sym_hash<BLOCK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kLdsLimit));
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_sym_bits<BLOCK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kLdsLimit));
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_numeric<BLOCK, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_numeric<BLOCK, false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+        done = true;
+    }
+    return DIBELLA_OK;
+}
+
+struct OvWork {   // device arrays shared by the launches of one call
+    const OvSet* d_sets;
+    int nsets;
+    const int64_t* d_base;
+    int32_t* retry_list;
+    const uint64_t* seg;
+    const int2* at;
+    const int64_t* soff;
+    int32_t* scratch;
+    int64_t* nnzrow;
+    int32_t* distinct;
+    OvCounters* ctr;
+    const int64_t* G;
+};
+
+struct SymArgs {
+    const int32_t* list;
+    const int32_t* dcount;
+    int hcount, grid, T, limit, level;
+};
+
+template <int BLOCK>
+static int launch_sym_hash(const OvWork& W, const SymArgs& a, hipStream_t st) {
+    DB_TRY(allow_lds_ov<BLOCK>());
+    hipLaunchKernelGGL(k_ov_sym_hash<BLOCK>, dim3(a.grid), dim3(BLOCK), sym_hash_lds(BLOCK, a.T), st, W.d_sets,
+                       W.nsets, W.d_base, a.list, a.dcount, a.hcount, a.T, a.limit, a.level, W.retry_list, W.seg,
+                       W.at, W.soff, W.scratch, W.nnzrow, W.distinct, W.ctr);
     DB_HIP(hipGetLastError());
     return DIBELLA_OK;
 }
 
 template <int BLOCK>
-static int launch_numeric(const OvSet* d_sets, int nsets, const int64_t* d_base, const int32_t* list,
-                          int count, int logT, const uint64_t* seg, const int2* at, const int64_t* G,
-                          hipStream_t st) {
-    const size_t lds = num_lds<BLOCK>(logT);
-    (void)hipFuncSetAttribute((const void*)k_ov_numeric<BLOCK>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_ov_numeric<BLOCK>, dim3(count), dim3(BLOCK), lds, st, d_sets, nsets, d_base,
-                       list, logT, seg, at, G);
+static int launch_sym_bits(const OvWork& W, const int32_t* list, int count, int planes, int words,
+                           hipStream_t st) {
+    DB_TRY(allow_lds_ov<BLOCK>());
+    hipLaunchKernelGGL(k_ov_sym_bits<BLOCK>, dim3(count), dim3(BLOCK), sym_bits_lds(BLOCK, planes, words), st,
+                       W.d_sets, W.nsets, W.d_base, list, W.seg, W.at, W.soff, W.scratch, W.nnzrow, W.distinct);
     DB_HIP(hipGetLastError());
     return DIBELLA_OK;
 }
 
-static int dispatch_symbolic(int block, const OvSet* d_sets, int nsets, const int64_t* d_base,
-                             const int32_t* list, int count, int logT, int limit, const uint64_t* seg,
-                             const int2* at, int64_t* nnzrow, int32_t* distinct, OvCounters* ctr,
+template <int BLOCK>
+static int launch_numeric(const OvWork& W, const int32_t* list, int count, int D, int load_pct, bool bits,
+                          int words, hipStream_t st) {
+    DB_TRY(allow_lds_ov<BLOCK>());
+    const size_t lds = num_lds(BLOCK, D, load_pct, bits, words);
+    if (bits)
+        hipLaunchKernelGGL((k_ov_numeric<BLOCK, true>), dim3(count), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
+                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G);
+    else
+        hipLaunchKernelGGL((k_ov_numeric<BLOCK, false>), dim3(count), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
+                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G);
+    DB_HIP(hipGetLastError());
+    return DIBELLA_OK;
+}
+
+#define DB_DISPATCH_BLOCK(block, fn, ...)                          \
+    switch (block) {                                               \
+        case 64: return fn<64>(__VA_ARGS__);                       \
+        case 128: return fn<128>(__VA_ARGS__);                     \
+        case 512: return fn<512>(__VA_ARGS__);                     \
+        case 1024: return fn<1024>(__VA_ARGS__);                   \
+        default: return fn<256>(__VA_ARGS__);                      \
+    }
+
+static int dispatch_sym_hash(int block, const OvWork& W, const SymArgs& a, hipStream_t st) {
+    DB_DISPATCH_BLOCK(block, launch_sym_hash, W, a, st);
+}
+static int dispatch_sym_bits(int block, const OvWork& W, const int32_t* list, int count, int planes, int words,
                              hipStream_t st) {
-    switch (block) {
-        case 64: return launch_symbolic<64>(d_sets, nsets, d_base, list, count, logT, limit, seg, at, nnzrow, distinct, ctr, st);
-        case 128: return launch_symbolic<128>(d_sets, nsets, d_base, list, count, logT, limit, seg, at, nnzrow, distinct, ctr, st);
-        case 512: return launch_symbolic<512>(d_sets, nsets, d_base, list, count, logT, limit, seg, at, nnzrow, distinct, ctr, st);
-        default: return launch_symbolic<256>(d_sets, nsets, d_base, list, count, logT, limit, seg, at, nnzrow, distinct, ctr, st);
-    }
+    DB_DISPATCH_BLOCK(block, launch_sym_bits, W, list, count, planes, words, st);
+}
+static int dispatch_numeric(int block, const OvWork& W, const int32_t* list, int count, int D, int load_pct,
+                            bool bits, int words, hipStream_t st) {
+    DB_DISPATCH_BLOCK(block, launch_numeric, W, list, count, D, load_pct, bits, words, st);
 }
 
-static int dispatch_numeric(int block, const OvSet* d_sets, int nsets, const int64_t* d_base,
-                            const int32_t* list, int count, int logT, const uint64_t* seg, const int2* at,
-                            const int64_t* G, hipStream_t st) {
-    switch (block) {
-        case 64: return launch_numeric<64>(d_sets, nsets, d_base, list, count, logT, seg, at, G, st);
-        case 128: return launch_numeric<128>(d_sets, nsets, d_base, list, count, logT, seg, at, G, st);
-        case 512: return launch_numeric<512>(d_sets, nsets, d_base, list, count, logT, seg, at, G, st);
-        default: return launch_numeric<256>(d_sets, nsets, d_base, list, count, logT, seg, at, G, st);
+// Numeric bin bounds that fit the LDS: hash bins, then bitmap bins for a
+// bitmap of `words` words (none if words == 0).
+static NumBins numeric_bins(const dibella_tuning& tn, int words) {
+    static const int bounds[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 5120, 6144, 8192};
+    NumBins b;
+    std::memset(&b, 0, sizeof(b));
+    int k = 0;   // next free entry of b.d
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool bits = pass == 1;
+        if (bits && words == 0) break;
+        int n = 0, last = 0;
+        for (int d : bounds) {
+            if (d > tn.num_max_entries) break;
+            if (num_lds(1024, d, tn.load_pct, bits, words) > kLdsLimit) break;
+            b.d[k++] = d;
+            ++n;
+            last = d;
+        }
+        if (tn.num_max_entries > last && num_lds(1024, tn.num_max_entries, tn.load_pct, bits, words) <= kLdsLimit) {
+            b.d[k++] = tn.num_max_entries;
+            ++n;
+        }
+        if (bits) b.nb = n; else b.nh = n;
     }
+    return b;
 }
 
 static const char* describe_bad(int32_t bad) {
@@ -706,6 +1079,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     std::vector<OvSet> hs(nsets);
     std::vector<int64_t> base(nsets + 1, 0);
     int64_t total_rows = 0, total_m = 0, total_nnz = 0;
+    int bits_words = 0, bits_planes = 0;   // largest bitmap over the bitmap-path sets
     for (int s = 0; s < nsets; ++s) {
         const dibella_csr& a = A[s];
         if (a.nrows < 0 || a.ncols < 0 || a.nnz < 0) {
@@ -742,6 +1116,15 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         o.nnz_base = total_nnz;
         o.min_shared = min_shared[s];
         o.id_bits = std::max(1, ceil_log2_i64(std::max<int64_t>(a.nrows, 2)));
+        o.words = (int32_t)((a.nrows + 31) / 32);
+        o.use_bits = (min_shared[s] <= kMaxPlanes && o.words <= tn.bits_max_words &&
+                      sym_bits_lds(1024, min_shared[s], o.words) <= kLdsLimit)
+                         ? 1
+                         : 0;
+        if (o.use_bits) {
+            bits_words = std::max(bits_words, o.words);
+            bits_planes = std::max(bits_planes, (int)o.min_shared);
+        }
         base[s] = total_rows;
         total_rows += a.nrows;
         total_m += a.ncols;
@@ -761,6 +1144,11 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         C[s].count = nullptr;
         C[s].seed = nullptr;
     }
+    const NumBins bins = numeric_bins(tn, bits_words);
+    if (bins.nh == 0) {
+        set_error("tuning leaves no numeric table that fits the LDS");
+        return DIBELLA_EINVAL;
+    }
 
     // ---- workspace
     OvSet* d_sets;
@@ -777,25 +1165,29 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     int64_t* t_rowptr;
     int2* at;
     uint64_t* seg;
-    int64_t *flops_row, *nnzrow, *G, *esc_off;
-    int32_t *distinct, *sym_list, *num_list, *esc_list;
+    int64_t *flops_row, *nnzrow, *G, *esc_off, *sbound, *soff;
+    int32_t *distinct, *sym_list, *num_list, *esc_list, *retry_list, *slot_of;
     DB_TRY(ar.work_n(total_m, &cnt));
     DB_TRY(ar.work_n(total_m + 1, &t_rowptr));
     DB_TRY(ar.work_n(total_nnz, &at));
     DB_TRY(ar.work_n(total_nnz, &seg));
+    DB_TRY(ar.work_n(total_nnz, &slot_of));
     DB_TRY(ar.work_n(total_rows, &flops_row));
     DB_TRY(ar.work_n(total_rows, &nnzrow));
     DB_TRY(ar.work_n(total_rows + 1, &G));
     DB_TRY(ar.work_n(total_rows, &esc_off));
+    DB_TRY(ar.work_n(total_rows, &sbound));
+    DB_TRY(ar.work_n(total_rows + 1, &soff));
     DB_TRY(ar.work_n(total_rows, &distinct));
     DB_TRY(ar.work_n((size_t)total_rows * kMaxLog2, &sym_list));
-    DB_TRY(ar.work_n((size_t)total_rows * kMaxLog2, &num_list));
+    DB_TRY(ar.work_n((size_t)total_rows * kMaxBins, &num_list));
     DB_TRY(ar.work_n(total_rows, &esc_list));
+    DB_TRY(ar.work_n(total_rows, &retry_list));
 
     // ---- upload descriptors
     HostStage& hst = host_stage();
     const size_t desc_bytes = sizeof(OvSet) * nsets + sizeof(int64_t) * (nsets + 1);
-    const size_t back_bytes = sizeof(OvCounters) + sizeof(int32_t) * nsets + sizeof(int64_t) * nsets;
+    const size_t back_bytes = sizeof(OvCounters) + sizeof(int32_t) * nsets + sizeof(int64_t) * (nsets + 1);
     DB_TRY(hst.reserve(desc_bytes + back_bytes + 64));
     char* hbuf = static_cast<char*>(hst.ptr);
     std::memcpy(hbuf, hs.data(), sizeof(OvSet) * nsets);
@@ -809,7 +1201,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(fill_i64(nnzrow, 0, total_rows, st));
     DB_TRY(fill_i32(distinct, 0, total_rows, st));
 
-    // ---- validate + transpose + row costs
+    // ---- validate + transpose + row costs + scratch ranges
     int tok = -1;
     DB_TRY(timing_begin(kPhTranspose, st, &tok));
     constexpr int WPB = 4;
@@ -817,26 +1209,30 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
     if (total_rows > 0) {
         hipLaunchKernelGGL(k_ov_hist<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets,
-                           d_base, total_rows, cnt, d_flags, checks);
+                           d_base, total_rows, cnt, slot_of, d_flags, checks);
         DB_HIP(hipGetLastError());
     }
     DB_TRY(scan_exclusive(cnt, t_rowptr, total_m, nullptr, ar));
-    const int min_log2 = tn.min_table_log2, load_log2 = tn.load_log2;
     if (total_rows > 0) {
-        hipLaunchKernelGGL(k_ov_scatter<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets,
-                           d_base, total_rows, t_rowptr, cnt, at, seg, flops_row, sym_list, d_ctr,
-                           min_log2, tn.sym_max_log2, load_log2);
+        hipLaunchKernelGGL(k_ov_scatter<WPB>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
+                           dim3(WPB * kWave), 0, st, d_sets, nsets, d_base, total_rows, t_rowptr, slot_of, at, seg,
+                           flops_row, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct);
+        hipLaunchKernelGGL(k_ov_scratch_bound, dim3(grid_for(total_rows, 256, 4096)), dim3(256), 0, st, d_sets,
+                           nsets, d_base, total_rows, flops_row, sbound);
         DB_HIP(hipGetLastError());
     }
+    DB_TRY(scan_exclusive(sbound, soff, total_rows, nullptr, ar));
     DB_TRY(timing_end(tok, st));
-    // ---- sync 1: validity and bin sizes
+    // ---- sync 1: validity, bin sizes, scratch size
     char* back = hbuf + desc_bytes;
     OvCounters* h_ctr = reinterpret_cast<OvCounters*>(back);
     int32_t* h_flags = reinterpret_cast<int32_t*>(back + sizeof(OvCounters));
     int64_t* h_set_nnz = reinterpret_cast<int64_t*>(back + sizeof(OvCounters) + sizeof(int32_t) * nsets);
     DB_HIP(hipMemcpyAsync(h_ctr, d_ctr, sizeof(OvCounters), hipMemcpyDeviceToHost, st));
     DB_HIP(hipMemcpyAsync(h_flags, d_flags, sizeof(int32_t) * nsets, hipMemcpyDeviceToHost, st));
+    DB_HIP(hipMemcpyAsync(h_set_nnz + nsets, soff + total_rows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DB_TRY(sync_stream(st));
+    const int64_t scratch_words = h_set_nnz[nsets];
     for (int s = 0; s < nsets; ++s) {
         if (h_flags[s]) {
             set_error("set " + std::to_string(s) + ": " + describe_bad(h_flags[s]));
@@ -849,24 +1245,46 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         return DIBELLA_EOVERFLOW;
     }
     stt.products = h_ctr->products;
+    int32_t* scratch;
+    DB_TRY(ar.work_n(scratch_words, &scratch));
+    OvWork W{d_sets, nsets, d_base, retry_list, seg, at, soff, scratch, nnzrow, distinct, d_ctr, G};
 
-    // ---- symbolic, largest tables first
-    const int sym_max = tn.sym_max_log2;
-    for (int lg = sym_max; lg >= min_log2; --lg) {
+    // ---- symbolic: bitmap rows; hash rows by first-level table (largest
+    // first), then the retry level
+    if (h_ctr->sym_count[kBitsClass] > 0) {
+        const int count = h_ctr->sym_count[kBitsClass];
+        const int blk = wide_block(tn.sym_block, sym_bits_lds(256, bits_planes, bits_words));
+        DB_TRY(timing_begin(kPhSymbolic, st, &tok));
+        DB_TRY(dispatch_sym_bits(blk, W, sym_list + (int64_t)kBitsClass * total_rows, count, bits_planes,
+                                 bits_words, st));
+        DB_TRY(timing_end(tok, st));
+    }
+    bool any_hash = false;
+    for (int lg = tn.sym_first_log2; lg >= 6; --lg) {
         const int count = h_ctr->sym_count[lg];
         if (!count) continue;
+        any_hash = true;
         const int T = 1 << lg;
-        int limit = T + 1;  // smaller tables are sized to never fill
-        if (lg == sym_max) limit = std::min(T * 3 / 4, T - tn.sym_block - 1);
+        const int limit = (int)((int64_t)T * tn.load_pct / 100);
         DB_TRY(timing_begin(kPhSymbolic, st, &tok));
-        DB_TRY(dispatch_symbolic(tn.sym_block, d_sets, nsets, d_base, sym_list + (int64_t)lg * total_rows,
-                                 count, lg, limit, seg, at, nnzrow, distinct, d_ctr, st));
+        DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
+                                 SymArgs{sym_list + (int64_t)lg * total_rows, nullptr, count, count, T, limit, 0},
+                                 st));
+        DB_TRY(timing_end(tok, st));
+    }
+    if (any_hash) {
+        const int T = 1 << tn.sym_max_log2;
+        const int limit = (int)((int64_t)T * tn.load_pct / 100);
+        const int grid = (int)std::min<int64_t>(total_rows, 512);
+        DB_TRY(timing_begin(kPhSymbolic, st, &tok));
+        DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
+                                 SymArgs{retry_list, &d_ctr->retry_rows, 0, grid, T, limit, 1}, st));
         DB_TRY(timing_end(tok, st));
     }
     if (total_rows > 0) {
-        hipLaunchKernelGGL(k_ov_bin_numeric, dim3(grid_for(total_rows, 256, 4096)), dim3(256), 0, st,
-                           total_rows, flops_row, distinct, num_list, esc_list, esc_off, d_ctr, min_log2,
-                           tn.num_max_log2, load_log2);
+        hipLaunchKernelGGL(k_ov_bin_numeric, dim3((unsigned)ceil_div(total_rows, kBinBlock)), dim3(kBinBlock), 0, st,
+                           d_sets, nsets, d_base, total_rows, flops_row, distinct, nnzrow, num_list, esc_list,
+                           esc_off, d_ctr, bins);
         DB_HIP(hipGetLastError());
     }
     DB_TRY(scan_exclusive(nnzrow, G, total_rows, nullptr, ar));
@@ -904,7 +1322,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
                                nsets, G, d_set_nnz);
             DB_HIP(hipGetLastError());
             DB_HIP(hipMemcpyAsync(h_set_nnz, d_set_nnz, sizeof(int64_t) * nsets, hipMemcpyDeviceToHost, st));
-            DB_TRY(sync_stream(st));  // sync 3 (only with overflowing rows)
+            DB_TRY(sync_stream(st));  // sync 3 (only with rows that overflow the retry table)
         }
     }
 
@@ -926,13 +1344,14 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     hipLaunchKernelGGL(k_ov_write_rowptr, dim3(grid_for(total_rows + nsets, 256, 4096)), dim3(256), 0, st,
                        d_sets, nsets, d_base, total_rows, G);
     DB_HIP(hipGetLastError());
-    const int num_max = tn.num_max_log2;
-    for (int lg = num_max; lg >= min_log2; --lg) {
-        const int count = h_ctr->num_count[lg];
+    for (int b = bins.nh + bins.nb - 1; b >= 0; --b) {
+        const int count = h_ctr->num_count[b];
         if (!count) continue;
+        const bool bits = b >= bins.nh;
+        const int blk = wide_block(tn.num_block, num_lds(256, bins.d[b], tn.load_pct, bits, bits_words));
         DB_TRY(timing_begin(kPhNumeric, st, &tok));
-        DB_TRY(dispatch_numeric(tn.num_block, d_sets, nsets, d_base, num_list + (int64_t)lg * total_rows,
-                                count, lg, seg, at, G, st));
+        DB_TRY(dispatch_numeric(blk, W, num_list + (int64_t)b * total_rows, count, bins.d[b], tn.load_pct, bits,
+                                bits_words, st));
         DB_TRY(timing_end(tok, st));
     }
     if (esc_rows > 0) {

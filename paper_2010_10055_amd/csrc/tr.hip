@@ -101,14 +101,27 @@ __global__ __launch_bounds__(WPB* kWave) void k_tr_validate(const TrSet* __restr
     }
 }
 
+constexpr int kRowsPerBlock = 64;
+
+// Copy the entries with positive overhang; bin every non-empty row by
+// length (LDS counters, one global atomic per workgroup and bin).
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_tr_init_copy(
     const TrSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
     const uint8_t* __restrict__ rowok, const int64_t* __restrict__ rp, int32_t* __restrict__ ci,
     int32_t* __restrict__ va, int32_t* __restrict__ lists, TrState* __restrict__ state, int mid_cap) {
+    __shared__ int32_t s_cnt[3], s_base[3];
+    __shared__ int32_t s_bin[kRowsPerBlock], s_pos[kRowsPerBlock];
     const int lane = lane_id();
-    for (int64_t g = (int64_t)blockIdx.x * WPB + wave_id(); g < total_rows;
-         g += (int64_t)gridDim.x * WPB) {
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock;
+    for (int r = wave_id(); r < kRowsPerBlock; r += WPB) {
+        const int64_t g = row0 + r;
+        if (g >= total_rows) {
+            if (lane == 0) s_bin[r] = -1;
+            continue;
+        }
         const int64_t out0 = rp[g];
         const int64_t L = rp[g + 1] - out0;
         if (rowok[g]) {
@@ -135,11 +148,22 @@ __global__ __launch_bounds__(WPB* kWave) void k_tr_init_copy(
                 out += __popcll(mask);
             }
         }
-        if (lane == 0 && L > 0) {
-            const int bin = L <= kSmallCap ? 0 : (L <= mid_cap ? 1 : 2);
-            const int32_t pos = atomicAdd(&state->bin_count[bin], 1);
-            lists[(int64_t)bin * total_rows + pos] = (int32_t)g;
+        if (lane == 0) {
+            s_bin[r] = -1;
+            if (L > 0) {
+                const int bin = L <= kSmallCap ? 0 : (L <= mid_cap ? 1 : 2);
+                s_bin[r] = bin;
+                s_pos[r] = atomicAdd(&s_cnt[bin], 1);
+            }
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && s_cnt[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&state->bin_count[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    for (int r = threadIdx.x; r < kRowsPerBlock; r += WPB * kWave) {
+        const int b = s_bin[r];
+        if (b >= 0) lists[(int64_t)b * total_rows + s_base[b] + s_pos[r]] = (int32_t)(row0 + r);
     }
 }
 
@@ -170,12 +194,18 @@ __device__ __forceinline__ void tr_row(const TrSet* __restrict__ sets, int nsets
                                        const int32_t* __restrict__ active, int64_t* __restrict__ deleted,
                                        TrState* __restrict__ state, uint32_t flags, int32_t* s_col,
                                        int32_t* s_val, uint32_t* s_N, int64_t* c_start, int64_t* c_off,
-                                       int64_t* s_tmp, int64_t* s_red64, int32_t* s_red32) {
+                                       int64_t* s_tmp, int64_t* s_red64, int32_t* s_red32, int* out_set,
+                                       int64_t* out_deleted, int64_t* out_triples) {
     const int s = find_set(set_base, nsets, g);
     const int64_t base = sets[s].row_base;
     const int32_t fuzz = sets[s].fuzz;
     const int64_t lo = rp[g];
     const int L = (int)(rp[g + 1] - lo);
+    if (threadIdx.x == 0) {
+        *out_set = s;
+        *out_deleted = 0;
+        *out_triples = 0;
+    }
     if (!active[s]) {
         for (int u = threadIdx.x; u < L; u += BLOCK) keep[lo + u] = 1;
         if (threadIdx.x == 0) keepcnt[g] = L;
@@ -260,8 +290,9 @@ __device__ __forceinline__ void tr_row(const TrSet* __restrict__ sets, int nsets
     kept = block_sum_lds(kept, s_red32);
     if (threadIdx.x == 0) {
         keepcnt[g] = kept;
-        if (L - kept) atomic_add(&deleted[s], (int64_t)(L - kept));
-        atomic_add(&state->triples_pass, triples);
+        *out_set = s;
+        *out_deleted = L - kept;
+        *out_triples = triples;
     }
 }
 
@@ -284,11 +315,30 @@ __global__ __launch_bounds__(BLOCK) void k_tr_mark(
     __shared__ int32_t s_red32;
     const int32_t count = state->bin_count[bin];
     const int32_t* rows = list + (int64_t)bin * total_rows;
+    // deletions per set and walks are summed by thread 0 over the rows of
+    // this workgroup and published when the set changes and at the end
+    int cur_set = -1;
+    int64_t acc_del = 0, acc_trip = 0;
     for (int32_t w = blockIdx.x; w < count; w += gridDim.x) {
+        int rs;
+        int64_t rd, rt;
         tr_row<BLOCK, MODE>(sets, nsets, set_base, rows[w], rp, ci, va, keep, keepcnt, nbuf, active,
                             deleted, state, flags, s_col, s_val, s_N, c_start, c_off, s_tmp, &s_red64,
-                            &s_red32);
+                            &s_red32, &rs, &rd, &rt);
+        if (threadIdx.x == 0) {
+            if (rs != cur_set) {
+                if (acc_del) atomic_add(&deleted[cur_set], acc_del);
+                cur_set = rs;
+                acc_del = 0;
+            }
+            acc_del += rd;
+            acc_trip += rt;
+        }
         __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (acc_del) atomic_add(&deleted[cur_set], acc_del);
+        if (acc_trip) atomic_add(&state->triples_pass, acc_trip);
     }
 }
 
@@ -419,22 +469,23 @@ struct TrBuffers {
 };
 
 template <int BLOCK>
-static void allow_lds() {
+static int allow_lds() {
     static bool done = false;
     if (!done) {
-        (void)hipFuncSetAttribute((const void*)k_tr_mark<BLOCK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  150 * 1024);
+        DB_HIP(hipFuncSetAttribute((const void*)k_tr_mark<BLOCK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   150 * 1024));
         done = true;
     }
+    return DIBELLA_OK;
 }
 
 // Called outside graph capture so that the attribute calls are not recorded.
-static void prepare_pass_kernels() {
+static int prepare_pass_kernels() {
     switch (tuning().tr_block) {
-        case 64: allow_lds<64>(); break;
-        case 128: allow_lds<128>(); break;
-        case 512: allow_lds<512>(); break;
-        default: allow_lds<256>(); break;
+        case 64: return allow_lds<64>();
+        case 128: return allow_lds<128>();
+        case 512: return allow_lds<512>();
+        default: return allow_lds<256>();
     }
 }
 
@@ -630,7 +681,8 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
     }
     DB_TRY(scan_exclusive_ws(B.keepcnt, B.rp[0], total_rows, nullptr, B.scan_tiles, st));
     if (total_rows > 0) {
-        hipLaunchKernelGGL(k_tr_init_copy<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets, d_base,
+        hipLaunchKernelGGL(k_tr_init_copy<WPB>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
+                           dim3(WPB * kWave), 0, st, d_sets, nsets, d_base,
                            total_rows, rowok, B.rp[0], B.ci[0], B.va[0], B.lists, B.state, B.mid_cap);
         DB_HIP(hipGetLastError());
     }
@@ -664,7 +716,7 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
         for (int b = 0; b < 3; ++b) B.grid[b] = std::min(h_state->bin_count[b], 256 * occ * 4);
     }
 
-    prepare_pass_kernels();
+    DB_TRY(prepare_pass_kernels());
     if (h_state->any_active) {
         if (flags & DIBELLA_TR_USE_GRAPH) {
             int U = std::max(1, std::min(16, tn.tr_graph_passes));

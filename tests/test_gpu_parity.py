@@ -65,22 +65,30 @@ def _run_overlap(pkg, A, ms):
 # Overlap
 # ---------------------------------------------------------------------------
 
-def test_overlap_tiny_workload(lib):
+# bits_max_words: 8192 = bitmap path for these sets, 0 = hash path only
+PATHS = [pytest.param(8192, id="bitmap"), pytest.param(0, id="hash")]
+
+
+@pytest.mark.parametrize("bits", PATHS)
+def test_overlap_tiny_workload(lib, bits):
     w = synth.make_workload("tiny")
-    C = _run_overlap(lib, w.A, w.min_shared)
+    with tuned(lib, bits_max_words=bits):
+        C = _run_overlap(lib, w.A, w.min_shared)
+        st = lib.last_stats()
     assert_overlap_equal(C, oracle.overlap(w.A, w.min_shared), "tiny")
-    st = lib.last_stats()
     assert st["products"] == synth.overlap_products(w.A)
 
 
+@pytest.mark.parametrize("bits", PATHS)
 @pytest.mark.parametrize("seed,n,m,density,ms", [
     (1, 300, 2000, 0.01, 1), (2, 500, 800, 0.02, 2), (3, 64, 64, 0.3, 1), (4, 1, 5, 0.6, 1),
-    (5, 257, 4097, 0.004, 3), (6, 1000, 30000, 0.001, 1),
+    (5, 257, 4097, 0.004, 3), (6, 1000, 30000, 0.001, 1), (7, 200, 300, 0.05, 4), (8, 150, 200, 0.08, 6),
 ])
-def test_overlap_random(lib, seed, n, m, density, ms):
+def test_overlap_random(lib, seed, n, m, density, ms, bits):
     rng = np.random.default_rng(seed)
     A = synth.random_a(rng, n, m, density)
-    C = _run_overlap(lib, A, ms)
+    with tuned(lib, bits_max_words=bits):
+        C = _run_overlap(lib, A, ms)
     assert_overlap_equal(C, oracle.overlap(A, ms), f"random{seed}")
 
 
@@ -98,33 +106,45 @@ def test_overlap_empty_rows_and_matrix(lib):
     assert_overlap_equal(_run_overlap(lib, A3, 1), oracle.overlap(A3, 1), "blank rows")
 
 
-def test_overlap_adversarial_dense(lib):
+@pytest.mark.parametrize("bits", PATHS)
+def test_overlap_adversarial_dense(lib, bits):
     rng = np.random.default_rng(9)
     # one k-mer in every read, one read with every k-mer
     A = synth.random_a(rng, 700, 900, 0.01, dense_rows=[17], dense_cols=[3, 500])
     for ms in (1, 2):
-        assert_overlap_equal(_run_overlap(lib, A, ms), oracle.overlap(A, ms), f"dense ms={ms}")
+        with tuned(lib, bits_max_words=bits):
+            C = _run_overlap(lib, A, ms)
+        assert_overlap_equal(C, oracle.overlap(A, ms), f"dense ms={ms}")
 
 
 def test_overlap_esc_and_overflow_paths(lib):
     rng = np.random.default_rng(10)
     A = synth.random_a(rng, 3000, 400, 0.02, dense_cols=[7, 8])
     ref = oracle.overlap(A, 1)
-    # numeric tables of at most 256 slots: rows with > 128 distinct go to ESC;
-    # symbolic tables of at most 1024 slots: rows with > ~700 distinct overflow
-    with tuned(lib, sym_max_log2=10, num_max_log2=8):
+    # numeric LDS tables for at most 256 distinct columns: larger rows go to
+    # ESC; symbolic tables of 256 then 1024 slots: rows with > 768 distinct
+    # overflow both and need the third sync
+    with tuned(lib, sym_first_log2=8, sym_max_log2=10, num_max_entries=256, bits_max_words=0):
         C = _run_overlap(lib, A, 1)
         st = lib.last_stats()
     assert st["esc_rows"] > 0
     assert st["host_syncs"] == 3
     assert_overlap_equal(C, ref, "esc")
+    # bitmap path: no overflow, rows with more than 256 output entries go to ESC
+    with tuned(lib, num_max_entries=256):
+        C = _run_overlap(lib, A, 1)
+        st = lib.last_stats()
+    assert st["esc_rows"] > 0
+    assert st["host_syncs"] == 2
+    assert_overlap_equal(C, ref, "esc bitmap")
 
 
+@pytest.mark.parametrize("bits", PATHS)
 @pytest.mark.parametrize("block", [64, 128, 512])
-def test_overlap_launch_shapes_give_same_bits(lib, block):
+def test_overlap_launch_shapes_give_same_bits(lib, block, bits):
     w = synth.make_workload("tiny")
     ref = oracle.overlap(w.A, 1)
-    with tuned(lib, sym_block=block, num_block=block, min_table_log2=5, load_log2=2):
+    with tuned(lib, sym_block=block, num_block=block, sym_first_log2=8, load_pct=50, bits_max_words=bits):
         assert_overlap_equal(_run_overlap(lib, w.A, 1), ref, f"block {block}")
 
 
@@ -134,9 +154,13 @@ def test_overlap_batched_equals_solo(lib):
     sets.append(synth.CSR(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32)))
     sets.append(synth.random_a(rng, 40, 30, 0.2))
     ms = [1, 2, 1, 1, 3]
-    Cs = lib.overlap_batched([lib.CSRTensors.from_numpy(a, _dev()) for a in sets], ms)
-    for s, (a, m) in enumerate(zip(sets, ms)):
-        assert_overlap_equal(Cs[s], oracle.overlap(a, m), f"set {s}")
+    # bits_max_words=2: the 40-read set takes the bitmap path, the 200-read
+    # sets the hash path, in the same launches
+    for bits in (8192, 2, 0):
+        with tuned(lib, bits_max_words=bits):
+            Cs = lib.overlap_batched([lib.CSRTensors.from_numpy(a, _dev()) for a in sets], ms)
+        for s, (a, m) in enumerate(zip(sets, ms)):
+            assert_overlap_equal(Cs[s], oracle.overlap(a, m), f"set {s} bits {bits}")
 
 
 def test_overlap_deterministic(lib):

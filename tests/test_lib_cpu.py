@@ -60,8 +60,8 @@ def test_tuning_roundtrip_and_range_checks():
     try:
         new = pkg.set_tuning(num_block=128, tr_lds_cap=2048)
         assert pkg.get_tuning() == new
-        for bad in ({"sym_block": 96}, {"num_max_log2": 13}, {"tr_graph_passes": 0},
-                    {"sym_max_log2": 15}, {"load_log2": 3}):
+        for bad in ({"sym_block": 96}, {"num_max_entries": 9000}, {"tr_graph_passes": 0},
+                    {"sym_max_log2": 15}, {"load_pct": 90}, {"sym_first_log2": 14}):
             with pytest.raises(pkg.DibellaError):
                 pkg.set_tuning(**bad)
         assert pkg.get_tuning() == new
