@@ -98,7 +98,8 @@ typedef void (*dibella_free_fn)(void* p, void* ctx);
  * is kept.  C rows are sorted by column.  Output arrays: rowptr[n+1],
  * col/count[nnz], seed[4*nnz].
  * Errors: EINVAL for a malformed A (rowptr, column order or range, negative
- * value) or min_shared < 1; EOVERFLOW if nrows >= 2^24 or nnz >= 2^40.
+ * value) or min_shared < 1; EOVERFLOW if nrows >= 2^24, nnz >= 2^40 or the
+ * columns of all sets of one call add up to 2^32 or more.
  * Host synchronisation: two stream syncs (three if some row needs more
  * distinct columns than one LDS table holds).
  */

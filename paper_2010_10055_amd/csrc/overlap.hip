@@ -27,6 +27,9 @@
 
 namespace dibella {
 
+int radix_sort_pairs(uint32_t* ka, uint64_t* va, uint32_t* kb, uint64_t* vb, int64_t n, int bits, int* in_b,
+                     Arena& ar);
+
 struct OvSet {
     const int64_t* a_rowptr;
     const int32_t* a_col;
@@ -160,15 +163,16 @@ __device__ __forceinline__ void planes_mark(uint32_t* B, int words, int planes, 
 }
 
 // ---------------------------------------------------------------------------
-// Step 1: validate A, histogram of columns (one wave per row); the returned
-// count is the entry's slot inside its A^T row.
+// Step 1: validate A (one wave per row) and lay out its entries as sort
+// pairs: key = global column, value = (position << 32) | read.  Sorting the
+// pairs by key (stable, rows in order) gives A^T: row k lists (read, position)
+// by increasing read.
 // ---------------------------------------------------------------------------
 template <int WPB>
-__global__ __launch_bounds__(WPB* kWave) void k_ov_hist(const OvSet* __restrict__ sets, int nsets,
-                                                        const int64_t* __restrict__ set_base,
-                                                        int64_t total_rows, int32_t* __restrict__ cnt,
-                                                        int32_t* __restrict__ slot, int32_t* __restrict__ flags,
-                                                        int checks) {
+__global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict__ sets, int nsets,
+                                                        const int64_t* __restrict__ set_base, int64_t total_rows,
+                                                        uint32_t* __restrict__ keys, uint64_t* __restrict__ pays,
+                                                        int32_t* __restrict__ flags, int checks) {
     const int lane = lane_id();
     for (int64_t g = (int64_t)blockIdx.x * WPB + wave_id(); g < total_rows;
          g += (int64_t)gridDim.x * WPB) {
@@ -186,15 +190,16 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_hist(const OvSet* __restrict_
         } else {
             for (int64_t e = lo + lane; e < hi; e += kWave) {
                 const int32_t k = S.a_col[e];
-                if (k < 0 || k >= S.m) {
-                    bad |= kBadCol;
-                } else {
-                    slot[S.nnz_base + e] = atomicAdd(&cnt[S.col_base + k], 1);
-                }
+                const int32_t v = S.a_val[e];
+                uint32_t key = 0u;
+                if (k < 0 || k >= S.m) bad |= kBadCol;
+                else key = (uint32_t)(S.col_base + k);
                 if (checks) {
                     if (e > lo && S.a_col[e - 1] >= k) bad |= kUnsorted;
-                    if (S.a_val[e] < 0) bad |= kNegative;
+                    if (v < 0) bad |= kNegative;
                 }
+                keys[S.nnz_base + e] = key;
+                pays[S.nnz_base + e] = ((uint64_t)(uint32_t)v << 32) | (uint64_t)(uint32_t)i;
             }
         }
         bad = wave_or(bad);
@@ -202,9 +207,22 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_hist(const OvSet* __restrict_
     }
 }
 
+// Row pointers of A^T from the sorted keys: every run boundary fills the
+// pointers of the columns it passes (empty columns included).
+__global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64_t total_m,
+                             int64_t* __restrict__ t_rowptr) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = keys[e];
+        const int64_t kp = e > 0 ? (int64_t)keys[e - 1] : -1;
+        for (int64_t c = kp + 1; c <= k; ++c) t_rowptr[c] = e;
+        if (e == n - 1)
+            for (int64_t c = k + 1; c <= total_m; ++c) t_rowptr[c] = n;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Step 3: scatter A^T, record each A entry's A^T segment, products per row,
-// and bin rows for the symbolic phase: bitmap-path rows in one class,
+// Step 3: record each A entry's A^T segment (start, length), products per
+// row, and bin rows for the symbolic phase: bitmap-path rows in one class,
 // hash-path rows by first-level table size.  A workgroup owns
 // kRowsPerBlock consecutive rows (one wave per row at a time); bin counts
 // and totals are gathered in LDS and published with one global atomic per
@@ -215,8 +233,8 @@ constexpr int kRowsPerBlock = 64;
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
-    const int64_t* __restrict__ t_rowptr, const int32_t* __restrict__ slot_of, int2* __restrict__ at,
-    uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row, int32_t* __restrict__ sym_list,
+    const int64_t* __restrict__ t_rowptr, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
+    int32_t* __restrict__ sym_list,
     OvCounters* __restrict__ ctr, int first_log2, int load_pct) {
     __shared__ int32_t s_cnt[kMaxLog2], s_base[kMaxLog2];
     __shared__ int32_t s_bin[kRowsPerBlock], s_pos[kRowsPerBlock];
@@ -249,7 +267,6 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
                     const int64_t gk = S.col_base + k;
                     const int64_t t0 = t_rowptr[gk];
                     const int64_t len = t_rowptr[gk + 1] - t0;
-                    at[t0 + slot_of[S.nnz_base + e]] = make_int2((int32_t)i, S.a_val[e]);
                     sg = ((uint64_t)t0 << 24) | (uint64_t)len;
                     fl += len;
                 }
@@ -1131,8 +1148,8 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         total_nnz += a.nnz;
     }
     base[nsets] = total_rows;
-    if (total_rows >= (int64_t(1) << 31) || total_nnz >= (int64_t(1) << 40)) {
-        set_error("batch too large: total rows must be < 2^31 and total nnz < 2^40");
+    if (total_rows >= (int64_t(1) << 31) || total_nnz >= (int64_t(1) << 40) || total_m >= (int64_t(1) << 32)) {
+        set_error("batch too large: total rows must be < 2^31, total columns < 2^32 and total nnz < 2^40");
         return DIBELLA_EOVERFLOW;
     }
     for (int s = 0; s < nsets; ++s) {
@@ -1161,17 +1178,18 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(ar.work_n(nsets, &d_flags));
     DB_TRY(ar.work_n(1, &d_ctr));
     DB_TRY(ar.work_n(nsets, &d_set_nnz));
-    int32_t* cnt;
     int64_t* t_rowptr;
-    int2* at;
+    uint32_t *keys_a, *keys_b;
+    uint64_t *pays_a, *pays_b;
     uint64_t* seg;
     int64_t *flops_row, *nnzrow, *G, *esc_off, *sbound, *soff;
-    int32_t *distinct, *sym_list, *num_list, *esc_list, *retry_list, *slot_of;
-    DB_TRY(ar.work_n(total_m, &cnt));
+    int32_t *distinct, *sym_list, *num_list, *esc_list, *retry_list;
     DB_TRY(ar.work_n(total_m + 1, &t_rowptr));
-    DB_TRY(ar.work_n(total_nnz, &at));
+    DB_TRY(ar.work_n(total_nnz, &keys_a));
+    DB_TRY(ar.work_n(total_nnz, &keys_b));
+    DB_TRY(ar.work_n(total_nnz, &pays_a));
+    DB_TRY(ar.work_n(total_nnz, &pays_b));
     DB_TRY(ar.work_n(total_nnz, &seg));
-    DB_TRY(ar.work_n(total_nnz, &slot_of));
     DB_TRY(ar.work_n(total_rows, &flops_row));
     DB_TRY(ar.work_n(total_rows, &nnzrow));
     DB_TRY(ar.work_n(total_rows + 1, &G));
@@ -1197,7 +1215,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
                           hipMemcpyHostToDevice, st));
     DB_TRY(fill_i32(d_flags, 0, nsets, st));
     DB_TRY(fill_i32(reinterpret_cast<int32_t*>(d_ctr), 0, sizeof(OvCounters) / 4, st));
-    DB_TRY(fill_i32(cnt, 0, total_m, st));
+    DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));
     DB_TRY(fill_i64(nnzrow, 0, total_rows, st));
     DB_TRY(fill_i32(distinct, 0, total_rows, st));
 
@@ -1208,14 +1226,25 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
     if (total_rows > 0) {
-        hipLaunchKernelGGL(k_ov_hist<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets,
-                           d_base, total_rows, cnt, slot_of, d_flags, checks);
+        hipLaunchKernelGGL(k_ov_keys<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets,
+                           d_base, total_rows, keys_a, pays_a, d_flags, checks);
         DB_HIP(hipGetLastError());
     }
-    DB_TRY(scan_exclusive(cnt, t_rowptr, total_m, nullptr, ar));
+    int in_b = 0;
+    DB_TRY(radix_sort_pairs(keys_a, pays_a, keys_b, pays_b, total_nnz, ceil_log2_i64(std::max<int64_t>(total_m, 1)),
+                            &in_b, ar));
+    const uint32_t* tkeys = in_b ? keys_b : keys_a;
+    const int2* at = reinterpret_cast<const int2*>(in_b ? pays_b : pays_a);
+    if (total_nnz > 0) {
+        hipLaunchKernelGGL(k_ov_trowptr, dim3(grid_for(total_nnz, 256, 1 << 16)), dim3(256), 0, st, tkeys, total_nnz,
+                           total_m, t_rowptr);
+        DB_HIP(hipGetLastError());
+    } else {
+        DB_TRY(fill_i64(t_rowptr, 0, total_m + 1, st));
+    }
     if (total_rows > 0) {
         hipLaunchKernelGGL(k_ov_scatter<WPB>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
-                           dim3(WPB * kWave), 0, st, d_sets, nsets, d_base, total_rows, t_rowptr, slot_of, at, seg,
+                           dim3(WPB * kWave), 0, st, d_sets, nsets, d_base, total_rows, t_rowptr, seg,
                            flops_row, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct);
         hipLaunchKernelGGL(k_ov_scratch_bound, dim3(grid_for(total_rows, 256, 4096)), dim3(256), 0, st, d_sets,
                            nsets, d_base, total_rows, flops_row, sbound);
