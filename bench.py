@@ -105,6 +105,103 @@ def cpu_baseline(w, budget_s: float):
                       f"plain C -O2, single thread"}
 
 
+def batch_compare(db, synth, nsets: int, steps: int, graph: bool, tune_budget: float = 0.0):
+    """The batching workload: `nsets` independent read sets (genomes
+    log-uniform in 50 kbp..5 Mbp, 10-50x, lognormal reads of mean 8 kbp,
+    15% error, k = 17, reliable [2, 8], min_shared 1, fuzz 1000): the plain
+    path (one overlap + one reduction call per set, one after the other) and
+    the batched path (one batched overlap call and one batched reduction
+    call for all sets), same stream.  Results are compared set by set."""
+    import torch
+    t0 = time.perf_counter()
+    ws = synth.batch_workloads(nsets, device="cuda:0")
+    log(f"  batch generation {time.perf_counter() - t0:.1f} s: reads {sum(w.A.nrows for w in ws)}")
+    As = [db.CSRTensors.from_numpy(w.A, "cuda:0") for w in ws]
+    Rs = [db.CSRTensors.from_numpy(w.R, "cuda:0") for w in ws]
+    ms = [w.min_shared for w in ws]
+    fz = [w.fuzz for w in ws]
+    products = sum(synth.overlap_products(w.A) for w in ws)
+
+    def plain():
+        out = []
+        for a, r, m, f in zip(As, Rs, ms, fz):
+            C = db.overlap(a, m)
+            S, _ = db.transitive_reduce(r, f, graph=graph)
+            out.append((C, S))
+        return out
+
+    def batched():
+        Cs = db.overlap_batched(As, ms)
+        Ss, _ = db.transitive_reduce_batched(Rs, fz, graph=graph)
+        return list(zip(Cs, Ss))
+
+    tuned = None
+    if tune_budget > 0:
+        from paper_2010_10055_amd import autotune
+
+        def fp(res):
+            return tuple((int(c.col.sum()), int(c.seed.sum()), int(s.val.sum()), s.nnz) for c, s in res)
+
+        key = autotune.workload_key("gfx950", [w.A for w in ws], ms)
+        t0 = time.perf_counter()
+        tuned = autotune.autotune(batched, fp, key, budget_s=tune_budget, repeats=2, log=log)
+        log(f"  autotune {time.perf_counter() - t0:.1f} s -> {tuned}")
+    res_p, res_b = plain(), batched()
+    torch.cuda.synchronize()
+    same = all(torch.equal(cp.col, cb.col) and torch.equal(cp.seed, cb.seed) and torch.equal(cp.count, cb.count)
+               and torch.equal(sp.col, sb.col) and torch.equal(sp.val, sb.val)
+               for (cp, sp), (cb, sb) in zip(res_p, res_b))
+    times = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / steps
+    return {"sets": nsets, "reads": sum(w.A.nrows for w in ws), "overlap_products": products,
+            "plain_ms": round(times["plain"] * 1e3, 3), "batched_ms": round(times["batched"] * 1e3, 3),
+            "speedup": round(times["plain"] / times["batched"], 3), "bit_identical": bool(same),
+            "graph": graph, "tuning": tuned}
+
+
+def serve_compare(njobs: int, seed: int = 5000):
+    """Serving: a Poisson stream of layout jobs (90% large-shaped read sets:
+    the large workload's recipe on a 2 Mbp genome, 40x; 10% tiny ones) drawn
+    from a pool of pre-generated device-resident instances.  The arrival rate
+    is fixed at 0.8x the measured capacity of the FIFO one-at-a-time executor;
+    the same trace runs through FIFO and through continuous batching."""
+    import numpy as np
+    import torch
+    from paper_2010_10055_amd import serve
+    t0 = time.perf_counter()
+    pool = serve.make_pool([("large", 6, seed, 0.04), ("tiny", 6, seed + 100, 1.0)], device="cuda:0")
+    log(f"  serve pool {time.perf_counter() - t0:.1f} s")
+    fifo = serve.gpu_executor(batched=False)
+    cont = serve.gpu_executor(batched=True)
+    rng = np.random.default_rng(seed)
+    probe = serve.draw_jobs(rng, pool, 40, rate=1e9)
+    fifo(probe[:4])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in probe:
+        fifo([j])
+    service = (time.perf_counter() - t0) / len(probe)
+    rate = 0.8 / service
+    jobs = serve.draw_jobs(np.random.default_rng(seed + 1), pool, njobs, rate=rate)
+    budget = 32 << 30
+    out = {"jobs": njobs, "rate_jobs_per_s": round(rate, 2), "fifo_service_ms": round(service * 1e3, 3),
+           "hbm_budget_gib": budget >> 30}
+    for name, ex, mb in (("fifo", fifo, 1), ("continuous", cont, 64)):
+        clock = serve.WallClock()
+        done = serve.serve(jobs, ex, clock, hbm_budget=budget, max_batch=mb)
+        s = serve.summarize(done, clock.now())
+        out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
+    out["p99_speedup"] = round(out["fifo"]["p99_ms"] / max(1e-9, out["continuous"]["p99_ms"]), 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +212,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--check", action="store_true", help="compare one step with the oracle first")
+    ap.add_argument("--batch-sets", type=int, default=64, help="sets of the batching comparison (0 = skip)")
+    ap.add_argument("--tune-budget", type=float, default=30.0, help="seconds of autotuning for the batch (0 = off)")
+    ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving comparison (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -128,6 +228,7 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    default_tuning = db.get_tuning()
     t0 = time.perf_counter()
     log(f"generating workload '{args.workload}' ...")
     w = synth.make_workload(args.workload, device=dev)
@@ -193,6 +294,18 @@ def main():
                 "ms_per_step": round(dom_ms, 4),
                 "records_per_step": phases[dominant][1] / args.steps}
 
+    batch = None
+    if args.batch_sets > 0:
+        log(f"batching comparison ({args.batch_sets} sets) ...")
+        batch = batch_compare(db, synth, args.batch_sets, max(1, min(args.steps, 5)), args.graph,
+                              args.tune_budget)
+        db.set_tuning(**default_tuning)
+
+    served = None
+    if args.serve_jobs > 0:
+        log(f"serving comparison ({args.serve_jobs} jobs) ...")
+        served = serve_compare(args.serve_jobs)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -213,6 +326,8 @@ def main():
                                                   ("transpose", "symbolic", "numeric", "esc")) * 1e-3),
         "host_syncs": {"overlap": ov_stats["host_syncs"], "tr": tr_stats["host_syncs"]},
         "roofline": roofline,
+        "batch": batch,
+        "serve": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

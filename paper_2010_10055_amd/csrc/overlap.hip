@@ -60,7 +60,22 @@ struct OvCounters {
     int32_t esc_rows;
     int32_t overflow_rows;         // hash rows that overflowed the retry table too
     int32_t pad;
+    int32_t qhead[64];             // work-queue heads of the persistent launches
 };
+
+// Queue heads: symbolic bitmap, symbolic hash classes, retry, numeric bins.
+constexpr int kQSymBits = 0, kQSymHash = 1, kQRetry = 1 + kMaxLog2, kQNumeric = 2 + kMaxLog2;
+static_assert(kQNumeric + kMaxBins <= 64, "queue heads");
+
+// Persistent workgroups drain a queue of `count` items: the next item index,
+// or -1 once the queue is empty.  Contains barriers (uniform).
+__device__ __forceinline__ int next_item(int32_t* head, int count, int32_t* s_item) {
+    if (threadIdx.x == 0) *s_item = atomicAdd(head, 1);
+    __syncthreads();
+    const int w = *s_item;
+    __syncthreads();
+    return w < count ? w : -1;
+}
 
 // Numeric bins: bin b holds rows with output size in (d[b-1], d[b]];
 // bins [0, nh) serve the hash path, bins [nh, nh + nb) the bitmap path.
@@ -373,15 +388,15 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
     const int32_t* __restrict__ list, const uint64_t* __restrict__ seg, const int2* __restrict__ at,
     const int64_t* __restrict__ soff, int32_t* __restrict__ scratch, int64_t* __restrict__ nnzrow,
-    int32_t* __restrict__ distinct) {
+    int32_t* __restrict__ distinct, int32_t* __restrict__ qhead, int count) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + BLOCK;
     uint32_t* B = reinterpret_cast<uint32_t*>(c_off + BLOCK);
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
-    __shared__ int32_t s_red;
-
-    const int64_t g = list[blockIdx.x];
+    __shared__ int32_t s_red, s_item;
+    for (int item = next_item(qhead, count, &s_item); item >= 0; item = next_item(qhead, count, &s_item)) {
+    const int64_t g = list[item];
     const int s = find_set(set_base, nsets, g);
     const OvSet& S = sets[s];
     const int64_t i = g - S.row_base;
@@ -416,6 +431,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
         nnzrow[g] = base;
         distinct[g] = d;
     }
+    __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -436,15 +453,16 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
     const int32_t* __restrict__ list, const int32_t* __restrict__ dcount, int hcount, int T, int limit,
     int retry_level, int32_t* __restrict__ retry_list, const uint64_t* __restrict__ seg,
     const int2* __restrict__ at, const int64_t* __restrict__ soff, int32_t* __restrict__ scratch,
-    int64_t* __restrict__ nnzrow, int32_t* __restrict__ distinct, OvCounters* __restrict__ ctr) {
+    int64_t* __restrict__ nnzrow, int32_t* __restrict__ distinct, OvCounters* __restrict__ ctr,
+    int32_t* __restrict__ qhead) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + BLOCK;
     uint64_t* tab = reinterpret_cast<uint64_t*>(c_off + BLOCK);
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
-    __shared__ int32_t s_nd, s_ovf;
+    __shared__ int32_t s_nd, s_ovf, s_item;
     const int items = dcount ? *dcount : hcount;
-    for (int w = blockIdx.x; w < items; w += gridDim.x) {
+    for (int w = next_item(qhead, items, &s_item); w >= 0; w = next_item(qhead, items, &s_item)) {
         const int64_t g = list[w];
         const int s = find_set(set_base, nsets, g);
         const OvSet& S = sets[s];
@@ -602,7 +620,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
     const int32_t* __restrict__ list, int Dmax, int load_pct, const int64_t* __restrict__ nnzrow,
     const int64_t* __restrict__ soff, const int32_t* __restrict__ scratch, const uint64_t* __restrict__ seg,
-    const int2* __restrict__ at, const int64_t* __restrict__ G) {
+    const int2* __restrict__ at, const int64_t* __restrict__ G, int32_t* __restrict__ qhead, int count) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + BLOCK;
@@ -611,8 +629,9 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     int32_t* cnt = reinterpret_cast<int32_t*>(m2 + Dmax);
     int32_t* map = cnt + Dmax;   // BITS: bitmap (words) + prefix (words); else keys (T) + rank (T)
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
-
-    const int64_t g = list[blockIdx.x];
+    __shared__ int32_t s_item;
+    for (int item = next_item(qhead, count, &s_item); item >= 0; item = next_item(qhead, count, &s_item)) {
+    const int64_t g = list[item];
     const int s = find_set(set_base, nsets, g);
     const OvSet& S = sets[s];
     const int64_t i = g - S.row_base;
@@ -691,6 +710,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
         S.c_col[off + r] = sel[r];
         S.c_count[off + r] = cnt[r];
         seed4[off + r] = make_int4(pi0, pj0, pi1, pj1);
+    }
+    __syncthreads();
     }
 }
 
@@ -992,15 +1013,34 @@ struct OvWork {   // device arrays shared by the launches of one call
 struct SymArgs {
     const int32_t* list;
     const int32_t* dcount;
-    int hcount, grid, T, limit, level;
+    int hcount, grid, T, limit, level, queue;
 };
+
+// Workgroups of a persistent launch: what fits the GPU at once (LDS and
+// waves per CU), never more than the items.
+static int persistent_grid(int count, int block, size_t lds) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                  ? prop.multiProcessorCount
+                  : 256;
+    }
+    const int by_lds = (int)std::max<size_t>(1, (160 * 1024) / (lds + 1024));
+    const int by_waves = std::max(1, 2048 / block);
+    const int64_t g = (int64_t)cus * std::min(by_lds, by_waves);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(count, g));
+}
 
 template <int BLOCK>
 static int launch_sym_hash(const OvWork& W, const SymArgs& a, hipStream_t st) {
     DB_TRY(allow_lds_ov<BLOCK>());
-    hipLaunchKernelGGL(k_ov_sym_hash<BLOCK>, dim3(a.grid), dim3(BLOCK), sym_hash_lds(BLOCK, a.T), st, W.d_sets,
+    const size_t lds = sym_hash_lds(BLOCK, a.T);
+    const int grid = a.dcount ? a.grid : persistent_grid(a.hcount, BLOCK, lds);
+    hipLaunchKernelGGL(k_ov_sym_hash<BLOCK>, dim3(grid), dim3(BLOCK), lds, st, W.d_sets,
                        W.nsets, W.d_base, a.list, a.dcount, a.hcount, a.T, a.limit, a.level, W.retry_list, W.seg,
-                       W.at, W.soff, W.scratch, W.nnzrow, W.distinct, W.ctr);
+                       W.at, W.soff, W.scratch, W.nnzrow, W.distinct, W.ctr, &W.ctr->qhead[a.queue]);
     DB_HIP(hipGetLastError());
     return DIBELLA_OK;
 }
@@ -1009,23 +1049,27 @@ template <int BLOCK>
 static int launch_sym_bits(const OvWork& W, const int32_t* list, int count, int planes, int words,
                            hipStream_t st) {
     DB_TRY(allow_lds_ov<BLOCK>());
-    hipLaunchKernelGGL(k_ov_sym_bits<BLOCK>, dim3(count), dim3(BLOCK), sym_bits_lds(BLOCK, planes, words), st,
-                       W.d_sets, W.nsets, W.d_base, list, W.seg, W.at, W.soff, W.scratch, W.nnzrow, W.distinct);
+    const size_t lds = sym_bits_lds(BLOCK, planes, words);
+    hipLaunchKernelGGL(k_ov_sym_bits<BLOCK>, dim3(persistent_grid(count, BLOCK, lds)), dim3(BLOCK), lds, st,
+                       W.d_sets, W.nsets, W.d_base, list, W.seg, W.at, W.soff, W.scratch, W.nnzrow, W.distinct,
+                       &W.ctr->qhead[kQSymBits], count);
     DB_HIP(hipGetLastError());
     return DIBELLA_OK;
 }
 
 template <int BLOCK>
 static int launch_numeric(const OvWork& W, const int32_t* list, int count, int D, int load_pct, bool bits,
-                          int words, hipStream_t st) {
+                          int words, int queue, hipStream_t st) {
     DB_TRY(allow_lds_ov<BLOCK>());
     const size_t lds = num_lds(BLOCK, D, load_pct, bits, words);
+    const int grid = persistent_grid(count, BLOCK, lds);
+    int32_t* qh = &W.ctr->qhead[queue];
     if (bits)
-        hipLaunchKernelGGL((k_ov_numeric<BLOCK, true>), dim3(count), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
-                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G);
+        hipLaunchKernelGGL((k_ov_numeric<BLOCK, true>), dim3(grid), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
+                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G, qh, count);
     else
-        hipLaunchKernelGGL((k_ov_numeric<BLOCK, false>), dim3(count), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
-                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G);
+        hipLaunchKernelGGL((k_ov_numeric<BLOCK, false>), dim3(grid), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
+                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G, qh, count);
     DB_HIP(hipGetLastError());
     return DIBELLA_OK;
 }
@@ -1047,8 +1091,8 @@ static int dispatch_sym_bits(int block, const OvWork& W, const int32_t* list, in
     DB_DISPATCH_BLOCK(block, launch_sym_bits, W, list, count, planes, words, st);
 }
 static int dispatch_numeric(int block, const OvWork& W, const int32_t* list, int count, int D, int load_pct,
-                            bool bits, int words, hipStream_t st) {
-    DB_DISPATCH_BLOCK(block, launch_numeric, W, list, count, D, load_pct, bits, words, st);
+                            bool bits, int words, int queue, hipStream_t st) {
+    DB_DISPATCH_BLOCK(block, launch_numeric, W, list, count, D, load_pct, bits, words, queue, st);
 }
 
 // Numeric bin bounds that fit the LDS: hash bins, then bitmap bins for a
@@ -1297,7 +1341,8 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         const int limit = (int)((int64_t)T * tn.load_pct / 100);
         DB_TRY(timing_begin(kPhSymbolic, st, &tok));
         DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
-                                 SymArgs{sym_list + (int64_t)lg * total_rows, nullptr, count, count, T, limit, 0},
+                                 SymArgs{sym_list + (int64_t)lg * total_rows, nullptr, count, count, T, limit, 0,
+                                         kQSymHash + lg},
                                  st));
         DB_TRY(timing_end(tok, st));
     }
@@ -1307,7 +1352,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         const int grid = (int)std::min<int64_t>(total_rows, 512);
         DB_TRY(timing_begin(kPhSymbolic, st, &tok));
         DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
-                                 SymArgs{retry_list, &d_ctr->retry_rows, 0, grid, T, limit, 1}, st));
+                                 SymArgs{retry_list, &d_ctr->retry_rows, 0, grid, T, limit, 1, kQRetry}, st));
         DB_TRY(timing_end(tok, st));
     }
     if (total_rows > 0) {
@@ -1380,7 +1425,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         const int blk = wide_block(tn.num_block, num_lds(256, bins.d[b], tn.load_pct, bits, bits_words));
         DB_TRY(timing_begin(kPhNumeric, st, &tok));
         DB_TRY(dispatch_numeric(blk, W, num_list + (int64_t)b * total_rows, count, bins.d[b], tn.load_pct, bits,
-                                bits_words, st));
+                                bits_words, kQNumeric + b, st));
         DB_TRY(timing_end(tok, st));
     }
     if (esc_rows > 0) {
