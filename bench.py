@@ -41,24 +41,48 @@ def source_hash(*names) -> str:
     return h.hexdigest()[:16]
 
 
-def phase_bytes(w, C_nnz, products, tr_stats):
-    """Algorithmic bytes per step of each timed phase (CSR Gustavson model)."""
-    n, nnzA = w.A.nrows, w.A.nnz
-    numeric = 8 * n + 8 * nnzA + 16 * nnzA + 8 * products + 24 * C_nnz
-    symbolic = 8 * n + 20 * nnzA + 4 * products + 8 * n
-    transpose = 8 * nnzA * 2 + 8 * nnzA + 4 * w.A.ncols * 2
+def kernel_bytes(w, C_nnz, products, tr_stats, sort_passes):
+    """Algorithmic bytes per step of each timed kernel.  The two products use
+    the CSR Gustavson model of a row-wise SpGEMM (symbolic: row pointers, A
+    columns and the A^T row-pointer pair per entry, 4 B per product;
+    numeric: the same plus A values, 8 B per product and 24 B per output
+    entry); the transpose kernels move what a sort of 12-byte (column,
+    read|position) pairs must; a reduction pass reads a row-pointer pair per
+    entry and 8 B per walk."""
+    n, nnzA, m = w.A.nrows, w.A.nnz, w.A.ncols
     trace = tr_stats["nnz_trace"]
     trip = tr_stats["triples_trace"]
-    mark = sum(16 * trace[p] + 8 * trip[p] for p in range(len(trip)))
-    compact = sum(8 * trace[p] + 8 * trace[p + 1] for p in range(len(trip)))
-    return {"numeric": numeric, "symbolic": symbolic, "transpose": transpose,
-            "tr_mark": mark, "tr_compact": compact}
+    sym = 8 * n + 20 * nnzA + 4 * products + 8 * n
+    radix = sort_passes > 0
+    return {
+        "keys": 8 * n + 8 * nnzA + 12 * nnzA,
+        "part_count": 4 * nnzA,
+        "part_scatter": 24 * nnzA,
+        "bucket_sort": (4 * nnzA + 4 * m) if radix else (24 * nnzA + 4 * m),
+        "sort_up": 4 * nnzA * sort_passes,
+        "sort_down": 24 * nnzA * sort_passes,
+        "segments": 16 * n + 28 * nnzA,
+        "sym_bits": sym,
+        "sym_hash": sym,
+        "numeric": 8 * n + 8 * nnzA + 16 * nnzA + 8 * products + 24 * C_nnz,
+        "tr_mark": sum(16 * trace[p] + 8 * trip[p] for p in range(len(trip))),
+        "tr_compact": sum(9 * trace[p] + 8 * trace[p + 1] for p in range(len(trip))),
+    }
+
+
+KERNEL_SOURCES = {"keys": ("overlap.hip",), "part_count": ("overlap.hip",), "part_scatter": ("overlap.hip",),
+                  "bucket_sort": ("overlap.hip",), "sort_up": ("sort.hip",), "sort_down": ("sort.hip",),
+                  "segments": ("overlap.hip",), "sym_bits": ("overlap.hip",),
+                  "sym_hash": ("overlap.hip",), "numeric": ("overlap.hip",), "esc": ("overlap.hip",),
+                  "tr_mark": ("tr.hip",), "tr_compact": ("tr.hip",)}
 
 
 def load_traffic(kernel: str, workload: str, src_hash: str):
-    """HBM bytes per step from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    path = os.path.join(PROFILES, f"{kernel}_{workload}_pmc.json")
+    """HBM bytes per launch (per phase for the numeric phase) from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source."""
+    phase = kernel == "numeric_phase"
+    path = os.path.join(PROFILES, f"{'numeric' if phase else kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     try:
@@ -67,7 +91,117 @@ def load_traffic(kernel: str, workload: str, src_hash: str):
         return None
     if d.get("source_hash") != src_hash:
         return None
-    return d.get("hbm_bytes_per_step")
+    return d.get("hbm_bytes_per_phase" if phase else "hbm_bytes_per_launch")
+
+
+KERNEL_NAMES = {"keys": "k_ov_keys", "part_count": "k_ov_part_count", "part_scatter": "k_ov_part_scatter",
+                "bucket_sort": "k_ov_bucket_sort", "sort_up": "k_rs_upsweep", "sort_down": "k_rs_downsweep",
+                "segments": "k_ov_scatter", "sym_bits": "k_ov_sym_bits",
+                "sym_hash": "k_ov_sym_hash", "numeric": "k_ov_numeric", "tr_mark": "k_tr_mark",
+                "tr_compact": "k_tr_compact"}
+CALIB_BYTES = 1 << 30
+
+
+def calib_copy():
+    """A plain device copy of known size (1 GiB read + 1 GiB written by one
+    elementwise kernel), the reference for scaling HBM counters."""
+    import torch
+    x = torch.ones(CALIB_BYTES // 4, dtype=torch.int32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.bitwise_or(x, 0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": CALIB_BYTES}), flush=True)
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    out = []
+    for f in glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True):
+        with open(f) as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def _counter_per_kernel(d, counter):
+    """{kernel name: [value per dispatch]} for one counter (KiB for the TCC
+    size counters) from a rocprofv3 --pmc CSV directory."""
+    per = {}
+    for r in _csv_rows(d, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        per.setdefault(r.get("Kernel_Name", ""), []).append(float(r["Counter_Value"]))
+    return per
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, command):
+    """Write the profiles/ summaries: per-kernel durations of the timed run
+    (rocprofv3 kernel stats) and, per main kernel, HBM bytes per launch from
+    FETCH_SIZE / WRITE_SIZE scaled by the counters of the calibration copy."""
+    import statistics
+    os.makedirs(PROFILES, exist_ok=True)
+    stats = _csv_rows(trace_dir, "kernel_stats.csv")
+    lines = [f"# rocprofv3 kernel statistics, workload '{workload}'", f"# command: {command}",
+             f"{'kernel':64s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}"]
+    rows = sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0)))
+    for r in rows[:25]:
+        name = r.get("Name", "")[:64]
+        lines.append(f"{name:64s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r.get('Percentage', 0)):6.2f}")
+    # the numeric phase of one call: its k_ov_numeric launches overlap on
+    # several streams; its span runs from the first start to the last end
+    # among the launches that follow one k_ov_write_rowptr
+    spans, group, nlaunch = [], None, []
+    for r in sorted(_csv_rows(trace_dir, "kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"])):
+        name = r["Kernel_Name"]
+        if "k_ov_write_rowptr" in name:
+            if group:
+                spans.append(group[1] - group[0])
+                nlaunch.append(group[2])
+            group = [None, None, 0]
+        elif "k_ov_numeric" in name and group is not None:
+            t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            group = [t0 if group[0] is None else min(group[0], t0), t1 if group[1] is None else max(group[1], t1),
+                     group[2] + 1]
+    if group and group[0] is not None:
+        spans.append(group[1] - group[0])
+        nlaunch.append(group[2])
+    if spans:
+        lines.append("")
+        lines.append(f"numeric phase (k_ov_numeric launches of one call, overlapping on 3 streams): "
+                     f"{len(spans)} calls, {statistics.mean(nlaunch):.1f} launches per call, "
+                     f"span avg_us {statistics.mean(spans) / 1e3:.2f}")
+    with open(os.path.join(PROFILES, f"kernels_{workload}_trace.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    cf = _counter_per_kernel(cfetch_dir, "FETCH_SIZE")
+    cw = _counter_per_kernel(cwrite_dir, "WRITE_SIZE")
+    copy_fetch = max((max(v) for v in cf.values()), default=0.0) * 1024
+    copy_write = max((max(v) for v in cw.values()), default=0.0) * 1024
+    f_fetch = copy_fetch / CALIB_BYTES if copy_fetch else None
+    f_write = copy_write / CALIB_BYTES if copy_write else None
+    fetch = _counter_per_kernel(fetch_dir, "FETCH_SIZE")
+    write = _counter_per_kernel(write_dir, "WRITE_SIZE")
+    calls = sum(len(v) for n, v in fetch.items() if "k_ov_write_rowptr" in n)   # overlap calls profiled
+    for label, kname in KERNEL_NAMES.items():
+        fv = [x for n, v in fetch.items() if kname in n for x in v]
+        wv = [x for n, v in write.items() if kname in n for x in v]
+        if not fv or not wv or not f_fetch or not f_write:
+            continue
+        fb = statistics.mean(fv) * 1024 / f_fetch
+        wb = statistics.mean(wv) * 1024 / f_write
+        d = {"kernel": kname, "workload": workload, "command": command,
+             "source_hash": source_hash(*KERNEL_SOURCES[label]),
+             "fetch_KiB_per_dispatch_raw": statistics.mean(fv), "write_KiB_per_dispatch_raw": statistics.mean(wv),
+             "dispatches": len(fv), "copy_fetch_factor": f_fetch, "copy_write_factor": f_write,
+             "hbm_bytes_per_launch": fb + wb, "hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb}
+        if label == "numeric" and calls:
+            # all launches of the phase of one call
+            d["overlap_calls"] = calls
+            d["hbm_bytes_per_phase"] = (sum(fv) * 1024 / f_fetch + sum(wv) * 1024 / f_write) / calls
+        with open(os.path.join(PROFILES, f"{label}_{workload}_pmc.json"), "w") as f:
+            json.dump(d, f, indent=1)
+    print(f"summaries written to {PROFILES}")
 
 
 def cpu_baseline(w, budget_s: float):
@@ -215,7 +349,17 @@ def main():
     ap.add_argument("--batch-sets", type=int, default=64, help="sets of the batching comparison (0 = skip)")
     ap.add_argument("--tune-budget", type=float, default=30.0, help="seconds of autotuning for the batch (0 = off)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving comparison (0 = skip)")
+    ap.add_argument("--calib-copy", action="store_true", help="only run the 1 GiB copy used to scale counters")
+    ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
+                    help="write profiles/ summaries from rocprofv3 CSV directories")
+    ap.add_argument("--profile-command", default="", help="command recorded in the summaries")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, args.workload, args.profile_command)
+        return
+    if args.calib_copy:
+        calib_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -280,19 +424,31 @@ def main():
     value = per_step_products / (elapsed / args.steps)
 
     # roofline of the dominant kernel (largest measured time per step)
-    pb = phase_bytes(w, C.nnz, products, tr_stats)
     per_step_ms = {k: v[0] / args.steps for k, v in phases.items() if v[1] > 0}
+    launches = {k: v[1] / args.steps for k, v in phases.items() if v[1] > 0}
+    # radix passes of the transpose, if the library took that path (very many columns)
+    pb = kernel_bytes(w, C.nnz, products, tr_stats, int(round(launches.get("sort_down", 0))))
+    # the numeric launches of one call overlap on several streams: the phase
+    # (first launch to last, one record per call) is the unit that is timed
+    if "numeric_phase" in per_step_ms and "numeric" in pb:
+        pb["numeric_phase"] = pb.pop("numeric")
     dominant = max((k for k in per_step_ms if k in pb), key=lambda k: per_step_ms[k])
     dom_ms = per_step_ms[dominant]
     achieved = pb[dominant] / (dom_ms * 1e-3) / 1e9
-    src = {"numeric": ("overlap.hip",), "symbolic": ("overlap.hip",), "transpose": ("overlap.hip",),
-           "tr_mark": ("tr.hip",), "tr_compact": ("tr.hip", "runtime.hip")}[dominant]
-    traffic = load_traffic(dominant, args.workload, source_hash(*src))
+    traffic = load_traffic(dominant, args.workload,
+                           source_hash(*KERNEL_SOURCES["numeric" if dominant == "numeric_phase" else dominant]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dominant, "algorithmic_bytes_per_step": pb[dominant],
-                "ms_per_step": round(dom_ms, 4),
-                "records_per_step": phases[dominant][1] / args.steps}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic else None,
+                "traffic_GBps": round(traffic / (dom_ms / launches[dominant] * 1e-3) / 1e9, 1) if traffic else None,
+                "kernel": dominant, "launches_per_step": launches[dominant],
+                "algorithmic_bytes_per_launch": pb[dominant] / launches[dominant],
+                "avg_launch_ms": round(dom_ms / launches[dominant], 4)}
+    if dominant == "numeric_phase":
+        roofline["kernel_launches_per_phase"] = launches.get("numeric")
+    kernels = {k: {"ms_per_step": round(per_step_ms[k], 4), "launches_per_step": launches[k],
+                   "model_GBps": (round(pb[k] / (per_step_ms[k] * 1e-3) / 1e9, 1) if k in pb else None)}
+               for k in per_step_ms}
 
     batch = None
     if args.batch_sets > 0:
@@ -321,9 +477,12 @@ def main():
                    "min_shared": w.min_shared, "nnz_R": w.R.nnz, "nnz_S": S.nnz,
                    "tr_passes": it, "tr_walks": triples, "fuzz": w.fuzz, "graph": args.graph,
                    "parallelism": "single GPU"},
-        "phases_ms_per_step": {k: round(v, 4) for k, v in per_step_ms.items()},
-        "overlap_products_per_s": products / (sum(per_step_ms.get(k, 0) for k in
-                                                  ("transpose", "symbolic", "numeric", "esc")) * 1e-3),
+        "kernels": kernels,
+        "overlap_products_per_s_gpu_time": products / (sum(
+            per_step_ms.get(k, 0) for k in ("keys", "part_count", "part_scatter", "bucket_sort", "sort_up", "sort_down",
+                                             "segments", "sym_bits", "sym_hash",
+                                             "numeric_phase" if "numeric_phase" in per_step_ms else "numeric",
+                                             "esc")) * 1e-3),
         "host_syncs": {"overlap": ov_stats["host_syncs"], "tr": tr_stats["host_syncs"]},
         "roofline": roofline,
         "batch": batch,

@@ -98,8 +98,8 @@ typedef void (*dibella_free_fn)(void* p, void* ctx);
  * is kept.  C rows are sorted by column.  Output arrays: rowptr[n+1],
  * col/count[nnz], seed[4*nnz].
  * Errors: EINVAL for a malformed A (rowptr, column order or range, negative
- * value) or min_shared < 1; EOVERFLOW if nrows >= 2^24, nnz >= 2^40 or the
- * columns of all sets of one call add up to 2^32 or more.
+ * value) or min_shared < 1; EOVERFLOW if nrows >= 2^24, or if the entries
+ * or the columns of all sets of one call add up to 2^32 or more.
  * Host synchronisation: two stream syncs (three if some row needs more
  * distinct columns than one LDS table holds).
  */
@@ -191,17 +191,29 @@ typedef struct {
 int dibella_last_stats(dibella_stats* out);
 
 /* Kernel timing with HIP events recorded on the caller's stream around each
- * launch of the main kernels (per host thread).  Phases:
- *   0 transpose  (column histogram, scan, scatter of A^T)
- *   1 symbolic   (LDS-hash symbolic kernels, one record per table-size bin)
- *   2 numeric    (LDS-hash numeric kernels, one record per table-size bin)
- *   3 esc        (expand-sort-compress kernels of dense rows)
- *   4 tr_mark    (reduction pass kernels: N, row max, compare, flags)
- *   5 tr_compact (row-pointer scan and compaction of a pass)
+ * launch of the main kernels (per host thread).  One record per launch:
+ *   0 keys          validation of A and its (column, read|position) pairs
+ *   1 part_count    bucketed transpose: bucket histogram per chunk of pairs
+ *   2 part_scatter  bucketed transpose: pairs grouped by bucket
+ *   3 bucket_sort   bucketed transpose: per bucket, a counting sort by column
+ *                   giving the A^T row pointers and entries (radix case:
+ *                   the A^T row pointers from the sorted columns)
+ *   4 sort_up       radix case (very many columns or entries): digit histograms
+ *   5 sort_down     radix case: stable scatter (one launch per 8-bit pass)
+ *   6 segments      A^T segment per A entry, products per row, row bins
+ *   7 sym_bits      symbolic phase, bitmap path
+ *   8 sym_hash      symbolic phase, hash path (one launch per table size)
+ *   9 numeric       numeric phase (one launch per output-size bin)
+ *  10 esc           expand-sort-compress kernels of dense rows
+ *  11 tr_mark       reduction pass: N on the pattern of R, row max, compare
+ *  12 tr_compact    reduction pass: compaction of the kept entries
+ *  13 numeric_phase the whole numeric phase of one call, first launch to
+ *                   last (its launches overlap on several streams, so the
+ *                   sum of the records of label 9 exceeds this)
  * Passes run as captured graphs are not timed.  Enabling clears the
  * accumulators; collect waits for the recorded events, returns the summed
- * milliseconds and number of records per phase, and clears them. */
-#define DIBELLA_NUM_PHASES 8
+ * milliseconds and number of records per label, and clears them. */
+#define DIBELLA_NUM_PHASES 16
 typedef struct {
     double ms[DIBELLA_NUM_PHASES];
     int64_t records[DIBELLA_NUM_PHASES];

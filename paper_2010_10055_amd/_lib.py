@@ -29,7 +29,8 @@ EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batc
            "dibella_transitive_reduce_batched", "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
            "dibella_timing_collect"]
-PHASES = ["transpose", "symbolic", "numeric", "esc", "tr_mark", "tr_compact"]
+PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "sort_up", "sort_down", "segments", "sym_bits", "sym_hash", "numeric", "esc",
+          "tr_mark", "tr_compact", "numeric_phase"]
 
 
 class DibellaError(RuntimeError):
@@ -71,7 +72,7 @@ class _Stats(ctypes.Structure):
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("records", ctypes.c_int64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * 16), ("records", ctypes.c_int64 * 16)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

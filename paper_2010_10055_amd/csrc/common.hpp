@@ -100,8 +100,25 @@ int stage_done(hipStream_t s);       // record that the stage has been consumed
 
 int sync_stream(hipStream_t s);       // hipStreamSynchronize + counter
 
+// Streams that let independent launches of one call overlap: begin() makes
+// them wait for the work queued so far on `main`, end() makes `main` wait for
+// everything queued on them.  One set per host thread and device.
+constexpr int kSideStreams = 2;
+struct SideStreams {
+    hipStream_t s[kSideStreams];
+    hipEvent_t fork;
+    hipEvent_t join[kSideStreams];
+    int begin(hipStream_t main);
+    int end(hipStream_t main);
+};
+int side_streams(SideStreams** out);
+
 // Event timing of phases (no-ops unless enabled on this host thread).
-enum Phase { kPhTranspose = 0, kPhSymbolic, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact };
+// Timed kernels (labels of dibella_timing, see the header).
+enum Phase {
+    kPhKeys = 0, kPhPartCount, kPhPartScatter, kPhBucketSort, kPhSortUp, kPhSortDown, kPhSegments,
+    kPhSymBits, kPhSymHash, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact, kPhNumericAll
+};
 bool timing_on();
 int timing_begin(int phase, hipStream_t s, int* token);
 int timing_end(int token, hipStream_t s);
@@ -139,6 +156,15 @@ inline int grid_for(int64_t items, int block, int64_t cap = 1 << 20) {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// Load through a pointer known to address device (global) memory.  Pointers
+// read from descriptors are generic to the compiler; generic loads share a
+// wait counter with LDS operations, so a loop that mixes them with LDS
+// atomics waits for every load in flight.
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
 
 __device__ __forceinline__ int32_t atomic_add(int32_t* p, int32_t v) { return atomicAdd(p, v); }
 __device__ __forceinline__ uint32_t atomic_add(uint32_t* p, uint32_t v) { return atomicAdd(p, v); }

@@ -178,21 +178,24 @@ __device__ __forceinline__ void planes_mark(uint32_t* B, int words, int planes, 
 }
 
 // ---------------------------------------------------------------------------
-// Step 1: validate A (one wave per row) and lay out its entries as sort
-// pairs: key = global column, value = (position << 32) | read.  Sorting the
-// pairs by key (stable, rows in order) gives A^T: row k lists (read, position)
-// by increasing read.
+// Step 1: validate A (one wave per row) and lay out its entries as pairs
+// over the global entry space: key = global column, value =
+// (position << 32) | read.  Grouping the pairs by key gives A^T.
 // ---------------------------------------------------------------------------
+constexpr int kKeysIlp = 8;
+
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict__ sets, int nsets,
                                                         const int64_t* __restrict__ set_base, int64_t total_rows,
                                                         uint32_t* __restrict__ keys, uint64_t* __restrict__ pays,
                                                         int32_t* __restrict__ flags, int checks) {
     const int lane = lane_id();
-    for (int64_t g = (int64_t)blockIdx.x * WPB + wave_id(); g < total_rows;
+    // the row, its set and the set's fields are wave-uniform: kept in scalar
+    // registers so that the entry loads do not wait on them
+    for (int64_t g = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(wave_id()); g < total_rows;
          g += (int64_t)gridDim.x * WPB) {
         const int s = find_set(set_base, nsets, g);
-        const OvSet& S = sets[s];
+        const OvSet S = sets[s];
         const int64_t i = g - S.row_base;
         const int64_t lo = S.a_rowptr[i], hi = S.a_rowptr[i + 1];
         int32_t bad = 0;
@@ -203,18 +206,37 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
         } else if (hi - lo >= (int64_t(1) << 30)) {
             bad |= kLongRow;
         } else {
-            for (int64_t e = lo + lane; e < hi; e += kWave) {
-                const int32_t k = S.a_col[e];
-                const int32_t v = S.a_val[e];
-                uint32_t key = 0u;
-                if (k < 0 || k >= S.m) bad |= kBadCol;
-                else key = (uint32_t)(S.col_base + k);
-                if (checks) {
-                    if (e > lo && S.a_col[e - 1] >= k) bad |= kUnsorted;
-                    if (v < 0) bad |= kNegative;
+            int32_t prev_last = 0;   // column of the entry before this step's first
+            for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kKeysIlp) {
+                int32_t kk[kKeysIlp], vv[kKeysIlp];
+#pragma unroll
+                for (int q = 0; q < kKeysIlp; ++q) {
+                    const int64_t e = min(e0 + q * kWave + lane, hi - 1);   // clamped: no branch per load
+                    kk[q] = gload(S.a_col + e);
+                    vv[q] = gload(S.a_val + e);
                 }
-                keys[S.nnz_base + e] = key;
-                pays[S.nnz_base + e] = ((uint64_t)(uint32_t)v << 32) | (uint64_t)(uint32_t)i;
+#pragma unroll
+                for (int q = 0; q < kKeysIlp; ++q) {
+                    const int64_t e = e0 + q * kWave + lane;
+                    const bool in = e < hi;
+                    const int32_t k = kk[q];
+                    const bool ok = k >= 0 && k < S.m;
+                    if (checks) {
+                        // previous entry's column: from the lane below, or from
+                        // the last lane of the previous group of 64
+                        const int32_t up = __shfl_up(k, 1, kWave);
+                        const int32_t prev = lane ? up : prev_last;
+                        if (in && e > lo && prev >= k) bad |= kUnsorted;
+                        if (in && vv[q] < 0) bad |= kNegative;
+                        prev_last = __shfl(k, kWave - 1, kWave);
+                    }
+                    if (in) {
+                        if (!ok) bad |= kBadCol;
+                        // invalid columns get key 0: the call fails before A^T is used
+                        keys[S.nnz_base + e] = ok ? (uint32_t)(S.col_base + k) : 0u;
+                        pays[S.nnz_base + e] = ((uint64_t)(uint32_t)vv[q] << 32) | (uint64_t)(uint32_t)i;
+                    }
+                }
             }
         }
         bad = wave_or(bad);
@@ -222,16 +244,193 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
     }
 }
 
-// Row pointers of A^T from the sorted keys: every run boundary fills the
-// pointers of the columns it passes (empty columns included).
+// Row pointers of A^T from keys sorted by the radix path: every run boundary
+// fills the pointers of the columns it passes (empty columns included).
 __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64_t total_m,
-                             int64_t* __restrict__ t_rowptr) {
+                             uint32_t* __restrict__ t_rowptr) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = keys[e];
         const int64_t kp = e > 0 ? (int64_t)keys[e - 1] : -1;
-        for (int64_t c = kp + 1; c <= k; ++c) t_rowptr[c] = e;
+        for (int64_t c = kp + 1; c <= k; ++c) t_rowptr[c] = (uint32_t)e;
         if (e == n - 1)
-            for (int64_t c = k + 1; c <= total_m; ++c) t_rowptr[c] = n;
+            for (int64_t c = k + 1; c <= total_m; ++c) t_rowptr[c] = (uint32_t)n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 2: group the pairs by column with a two-pass bucketed counting sort
+// (at most 4096 buckets of 2^low columns, low <= 15):
+//   k_ov_part_count   per chunk of kChunk pairs, a bucket histogram
+//                     (bucket = key >> low), stored bucket-major;
+//   scan              -> first output slot of every (bucket, chunk);
+//   k_ov_part_scatter per chunk, the pairs are ordered by bucket in LDS and
+//                     written out as runs, so that stores coalesce;
+//   k_ov_bucket_sort  one workgroup per bucket counts its pairs per column in
+//                     LDS (2^low bins), scans the counts into the row
+//                     pointers of A^T and places each (read, position).
+// The order inside an A^T row is left free: nothing downstream depends on it.
+// Every pass takes the same chunks, so a malformed A (reported after the
+// first synchronisation) can only over-count: writes are clamped to `cap`.
+// ---------------------------------------------------------------------------
+constexpr int kPartBlock = 1024;
+constexpr int kPartIlp = 8;
+constexpr int kChunk = kPartBlock * kPartIlp;
+constexpr int kBucketBlock = 1024;
+constexpr int64_t kMaxBuckets = 3840;
+
+inline size_t part_scatter_lds(int64_t nbuckets) {
+    return (size_t)kChunk * 12 + (size_t)nbuckets * 16;
+}
+
+__global__ __launch_bounds__(kPartBlock) void k_ov_part_count(const uint32_t* __restrict__ keys, int64_t n,
+                                                              int low, int nbuckets,
+                                                              int32_t* __restrict__ counts) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
+    const int64_t nchunks = gridDim.x;
+    // keys of a malformed A may be unset: the bucket is clamped into range
+    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) hist[b] = 0u;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t c1 = min(c0 + kChunk, n);
+    uint32_t kk[kPartIlp];
+#pragma unroll
+    for (int q = 0; q < kPartIlp; ++q) kk[q] = keys[min(c0 + q * kPartBlock + threadIdx.x, c1 - 1)];
+#pragma unroll
+    for (int q = 0; q < kPartIlp; ++q)
+        atomicAdd(&hist[min(kk[q] >> low, (uint32_t)nbuckets - 1u)], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock)
+        counts[(int64_t)b * nchunks + blockIdx.x] = (int32_t)hist[b];
+}
+
+__global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
+    const uint32_t* __restrict__ keys, const uint64_t* __restrict__ pays, int64_t n, int low, int nbuckets,
+    const int64_t* __restrict__ offsets, int64_t cap, uint32_t* __restrict__ skey, uint64_t* __restrict__ spay) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t* st_pay = reinterpret_cast<uint64_t*>(smem);                 // [kChunk]
+    uint32_t* st_key = reinterpret_cast<uint32_t*>(st_pay + kChunk);      // [kChunk]
+    uint32_t* lcnt = st_key + kChunk;                                     // [nbuckets] count, then cursor
+    uint32_t* loff = lcnt + nbuckets;                                     // [nbuckets] chunk-local start
+    int64_t* gpos = reinterpret_cast<int64_t*>(loff + nbuckets);             // [nbuckets], 8-byte aligned
+    __shared__ uint32_t s_tmp[kPartBlock / kWave + 1];
+    const int64_t nchunks = gridDim.x;
+    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) {
+        lcnt[b] = 0u;
+        gpos[b] = offsets[(int64_t)b * nchunks + blockIdx.x];
+    }
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t c1 = min(c0 + kChunk, n);
+    uint32_t kk[kPartIlp], rk[kPartIlp];
+    uint64_t pp[kPartIlp];
+#pragma unroll
+    for (int q = 0; q < kPartIlp; ++q) {
+        const int64_t e = min(c0 + q * kPartBlock + threadIdx.x, c1 - 1);
+        // keys of a malformed A may be unset: the bucket is clamped into range
+        kk[q] = min(keys[e], ((uint32_t)nbuckets << low) - 1u);
+        pp[q] = pays[e];
+    }
+    // rank of each pair among the chunk's pairs of its bucket
+#pragma unroll
+    for (int q = 0; q < kPartIlp; ++q)
+        rk[q] = atomicAdd(&lcnt[kk[q] >> low], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+    __syncthreads();
+    // chunk-local bucket starts: each thread scans a run of consecutive buckets
+    const int per = (nbuckets + kPartBlock - 1) / kPartBlock;
+    const int b0 = threadIdx.x * per;
+    uint32_t local = 0;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < nbuckets) local += lcnt[b0 + q];
+    uint32_t tot;
+    uint32_t run = block_exclusive_sum<kPartBlock>(local, s_tmp, &tot);
+    for (int q = 0; q < per; ++q) {
+        if (b0 + q >= nbuckets) break;
+        loff[b0 + q] = run;
+        run += lcnt[b0 + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPartIlp; ++q) {
+        if (c0 + q * kPartBlock + threadIdx.x >= c1) continue;
+        const uint32_t slot = loff[kk[q] >> low] + rk[q];
+        st_key[slot] = kk[q];
+        st_pay[slot] = pp[q];
+    }
+    __syncthreads();
+    // consecutive slots of one bucket go to consecutive output positions
+    for (uint32_t slot = threadIdx.x; slot < tot; slot += kPartBlock) {
+        const uint32_t key = st_key[slot];
+        const int b = (int)(key >> low);
+        const int64_t pos = gpos[b] + (slot - loff[b]);
+        if (pos < cap) {
+            skey[pos] = key;
+            spay[pos] = st_pay[slot];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
+    const int64_t* __restrict__ offsets, int64_t nchunks, int low, int64_t total_m, int64_t cap,
+    const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint32_t* __restrict__ t_rowptr,
+    uint64_t* __restrict__ at) {
+    const int64_t total_valid = min(offsets[(int64_t)gridDim.x * nchunks], cap);
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
+    __shared__ int64_t s_tmp[kBucketBlock / kWave + 1];
+    const int b = blockIdx.x;
+    const int bins = 1 << low;
+    const int64_t bs = min(offsets[(int64_t)b * nchunks], cap);
+    const int64_t be = min(offsets[(int64_t)(b + 1) * nchunks], cap);
+    for (int c = threadIdx.x; c < bins; c += kBucketBlock) hist[c] = 0u;
+    __syncthreads();
+    const uint32_t mask = (uint32_t)bins - 1u;
+    for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
+        uint32_t kk[kPartIlp];
+#pragma unroll
+        for (int q = 0; q < kPartIlp; ++q)
+            kk[q] = skey[min(e0 + q * kBucketBlock + threadIdx.x, be - 1)];   // clamped: no branch
+#pragma unroll
+        for (int q = 0; q < kPartIlp; ++q)
+            atomicAdd(&hist[kk[q] & mask], e0 + q * kBucketBlock + threadIdx.x < be ? 1u : 0u);
+    }
+    __syncthreads();
+    // exclusive scan of the bins: each thread owns `per` consecutive bins
+    const int per = bins >= kBucketBlock ? bins / kBucketBlock : 1;
+    const int c0 = threadIdx.x * per;
+    int64_t local = 0;
+    for (int q = 0; q < per; ++q)
+        if (c0 + q < bins) local += hist[c0 + q];
+    int64_t tot;
+    int64_t run = block_exclusive_sum<kBucketBlock>(local, s_tmp, &tot);
+    const int64_t col0 = (int64_t)b << low;
+    for (int q = 0; q < per; ++q) {
+        const int c = c0 + q;
+        if (c >= bins) break;
+        const uint32_t h = hist[c];
+        const int64_t start = bs + run;
+        if (col0 + c < total_m) t_rowptr[col0 + c] = (uint32_t)start;
+        hist[c] = (uint32_t)start;   // becomes the cursor of column c
+        run += h;
+    }
+    // the last bucket also closes A^T
+    if (col0 + bins >= total_m && threadIdx.x == 0) t_rowptr[total_m] = (uint32_t)total_valid;
+    __syncthreads();
+    for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
+        uint32_t kk[kPartIlp], pos[kPartIlp];
+        uint64_t pp[kPartIlp];
+#pragma unroll
+        for (int q = 0; q < kPartIlp; ++q) {
+            const int64_t e = min(e0 + q * kBucketBlock + threadIdx.x, be - 1);   // clamped: no branch
+            kk[q] = skey[e];
+            pp[q] = spay[e];
+        }
+#pragma unroll
+        for (int q = 0; q < kPartIlp; ++q)
+            pos[q] = atomicAdd(&hist[kk[q] & mask], e0 + q * kBucketBlock + threadIdx.x < be ? 1u : 0u);
+#pragma unroll
+        for (int q = 0; q < kPartIlp; ++q)
+            if (e0 + q * kBucketBlock + threadIdx.x < be && pos[q] < cap) at[pos[q]] = pp[q];
     }
 }
 
@@ -244,11 +443,13 @@ __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64
 // workgroup and counter.
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerBlock = 64;
+constexpr int kSegWaves = 16;
+constexpr int kSegIlp = 8;
 
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
-    const int64_t* __restrict__ t_rowptr, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
+    const uint32_t* __restrict__ t_rowptr, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
     int32_t* __restrict__ sym_list,
     OvCounters* __restrict__ ctr, int first_log2, int load_pct) {
     __shared__ int32_t s_cnt[kMaxLog2], s_base[kMaxLog2];
@@ -263,29 +464,44 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     }
     __syncthreads();
     const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock;
-    for (int r = wave_id(); r < kRowsPerBlock; r += WPB) {
+    // rows are wave-uniform (scalar registers); kSegIlp entries per lane per
+    // step with all column loads, then all row-pointer gathers, in flight
+    for (int r = __builtin_amdgcn_readfirstlane(wave_id()); r < kRowsPerBlock; r += WPB) {
         const int64_t g = row0 + r;
         if (g >= total_rows) {
             if (lane == 0) s_bin[r] = -1;
             continue;
         }
         const int s = find_set(set_base, nsets, g);
-        const OvSet& S = sets[s];
+        const OvSet S = sets[s];
         const int64_t i = g - S.row_base;
         const int64_t lo = S.a_rowptr[i], hi = S.a_rowptr[i + 1];
         int64_t fl = 0;
         if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
-            for (int64_t e = lo + lane; e < hi; e += kWave) {
-                const int32_t k = S.a_col[e];
-                uint64_t sg = 0;
-                if (k >= 0 && k < S.m) {
-                    const int64_t gk = S.col_base + k;
-                    const int64_t t0 = t_rowptr[gk];
-                    const int64_t len = t_rowptr[gk + 1] - t0;
-                    sg = ((uint64_t)t0 << 24) | (uint64_t)len;
-                    fl += len;
+            for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kSegIlp) {
+                int32_t kk[kSegIlp];
+                uint32_t t0[kSegIlp], t1[kSegIlp];
+#pragma unroll
+                for (int q = 0; q < kSegIlp; ++q) kk[q] = gload(S.a_col + min(e0 + q * kWave + lane, hi - 1));
+#pragma unroll
+                for (int q = 0; q < kSegIlp; ++q) {
+                    const int32_t k = kk[q];
+                    const int64_t gk = (k >= 0 && k < S.m) ? S.col_base + k : 0;   // in range for the load
+                    t0[q] = t_rowptr[gk];
+                    t1[q] = t_rowptr[gk + 1];
                 }
-                seg[S.nnz_base + e] = sg;
+#pragma unroll
+                for (int q = 0; q < kSegIlp; ++q) {
+                    const int64_t e = e0 + q * kWave + lane;
+                    if (e >= hi) continue;
+                    uint64_t sg = 0;
+                    if (kk[q] >= 0 && kk[q] < S.m) {
+                        const int64_t len = (int64_t)t1[q] - (int64_t)t0[q];
+                        sg = ((uint64_t)t0[q] << 24) | (uint64_t)len;
+                        fl += len;
+                    }
+                    seg[S.nnz_base + e] = sg;
+                }
             }
         }
         fl = wave_sum(fl);
@@ -323,18 +539,27 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
 // ---------------------------------------------------------------------------
 // Shared product walk: the A entries t of row i are taken in chunks of
 // BLOCK; seg[t] gives the A^T segment (start, length) of entry t, and the
-// products of the chunk are numbered t-major.  Each thread takes PER
-// products per step, resolves their t by binary search over the chunk's
-// prefix sums and issues all PER gathers of A^T pairs before handing them
-// to f(t, (j, p_j), q), so that PER independent loads are in flight.
-// The block must call it uniformly.  `stop` (LDS flag) abandons the walk.
+// products of the chunk are numbered t-major.  Products are handed out in
+// windows of kWalkWin: every thread first writes its entry's index
+// over its products' slots of the window (an LDS expansion, so that a
+// product finds its t with one LDS read), then each thread takes kPer
+// products per step and issues all their gathers of A^T pairs before
+// handing them to f(t, (j, p_j), q), so that kPer independent loads are in
+// flight.  The block must call it uniformly.  `stop` (LDS flag) abandons
+// the walk.  LDS: c_start, c_off (BLOCK int64 each), tbuf (kWalkWin u16),
+// carved from the front of the dynamic LDS by walk_lds().
 // ---------------------------------------------------------------------------
 constexpr int kPer = 4;
+constexpr int kWalkWin = 2048;
+
+__host__ __device__ constexpr size_t walk_lds(int block) { return (size_t)block * 16 + (size_t)kWalkWin * 2; }
 
 template <int BLOCK, class F>
 __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
                                               const int2* __restrict__ at, int64_t* c_start, int64_t* c_off,
-                                              int64_t* s_tmp, const int32_t* stop, F&& f) {
+                                              uint16_t* tbuf, int64_t* s_tmp, const int32_t* stop, F&& f) {
+    static_assert(BLOCK <= 65536, "entry index kept in 16 bits");
+    constexpr int64_t W = kWalkWin;
     int64_t done = 0;   // products of earlier chunks
     for (int cbase = 0; cbase < L; cbase += BLOCK) {
         const int cl = min(BLOCK, L - cbase);
@@ -348,31 +573,36 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
         const int64_t ex = block_exclusive_sum<BLOCK>(len, s_tmp, &tot);
         c_start[threadIdx.x] = st;
         c_off[threadIdx.x] = ex;
-        __syncthreads();
-        for (int64_t q0 = threadIdx.x; q0 < tot; q0 += (int64_t)BLOCK * kPer) {
-            if (stop && *(volatile const int32_t*)stop) break;
-            int tt[kPer];
-            int2 jp[kPer];
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int64_t q = q0 + (int64_t)u * BLOCK;
-                tt[u] = -1;
-                if (q < tot) {
-                    int lo = 0, hi = cl - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (c_off[mid] <= q) lo = mid; else hi = mid - 1;
-                    }
-                    tt[u] = lo;
-                    jp[u] = at[c_start[lo] + (q - c_off[lo])];
-                }
+        for (int64_t w0 = 0; w0 < tot; w0 += W) {
+            const int64_t w1 = min(w0 + W, tot);
+            {
+                const int64_t a = max(ex, w0), b = min(ex + len, w1);
+                for (int64_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)threadIdx.x;
             }
+            __syncthreads();
+            for (int64_t q0 = w0 + threadIdx.x; q0 < w1; q0 += (int64_t)BLOCK * kPer) {
+                if (stop && *(volatile const int32_t*)stop) break;
+                int tt[kPer];
+                int2 jp[kPer];
 #pragma unroll
-            for (int u = 0; u < kPer; ++u)
-                if (tt[u] >= 0) f(cbase + tt[u], jp[u], done + q0 + (int64_t)u * BLOCK);
+                for (int u = 0; u < kPer; ++u) {
+                    const int64_t q = q0 + (int64_t)u * BLOCK;
+                    tt[u] = -1;
+                    if (q < w1) {
+                        const int t = tbuf[q - w0];
+                        tt[u] = t;
+                        jp[u] = at[c_start[t] + (q - c_off[t])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kPer; ++u)
+                    if (tt[u] >= 0) f(cbase + tt[u], jp[u], done + q0 + (int64_t)u * BLOCK);
+            }
+            __syncthreads();
+            if (stop && *(volatile const int32_t*)stop) break;
         }
         done += tot;
-        __syncthreads();
+        if (tot == 0) __syncthreads();   // c_start/c_off are rewritten by the next chunk
         if (stop && *(volatile const int32_t*)stop) break;
     }
 }
@@ -392,7 +622,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + BLOCK;
-    uint32_t* B = reinterpret_cast<uint32_t*>(c_off + BLOCK);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + BLOCK);
+    uint32_t* B = reinterpret_cast<uint32_t*>(smem + walk_lds(BLOCK));
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int32_t s_red, s_item;
     for (int item = next_item(qhead, count, &s_item); item >= 0; item = next_item(qhead, count, &s_item)) {
@@ -406,7 +637,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     const int planes = S.min_shared;
     for (int q = threadIdx.x; q < planes * words; q += BLOCK) B[q] = 0u;
     __syncthreads();
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, nullptr,
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
                          [&](int, int2 jp, int64_t) { planes_mark(B, words, planes, jp.x); });
     __syncthreads();
     const uint32_t* out_plane = B + (planes - 1) * words;
@@ -458,7 +689,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + BLOCK;
-    uint64_t* tab = reinterpret_cast<uint64_t*>(c_off + BLOCK);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + BLOCK);
+    uint64_t* tab = reinterpret_cast<uint64_t*>(smem + walk_lds(BLOCK));
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int32_t s_nd, s_ovf, s_item;
     const int items = dcount ? *dcount : hcount;
@@ -475,7 +707,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
             s_ovf = 0;
         }
         __syncthreads();
-        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, &s_ovf,
+        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, &s_ovf,
                              [&](int, int2 jp, int64_t) {
                                  int fresh;
                                  const int slot = table64_add(tab, (uint32_t)T, jp.x, &fresh);
@@ -624,7 +856,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + BLOCK;
-    uint64_t* m1 = reinterpret_cast<uint64_t*>(c_off + BLOCK);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + BLOCK);
+    uint64_t* m1 = reinterpret_cast<uint64_t*>(smem + walk_lds(BLOCK));
     uint64_t* m2 = m1 + Dmax;
     int32_t* cnt = reinterpret_cast<int32_t*>(m2 + Dmax);
     int32_t* map = cnt + Dmax;   // BITS: bitmap (words) + prefix (words); else keys (T) + rank (T)
@@ -676,7 +909,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
         }
         __syncthreads();
     }
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, nullptr,
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
                          [&](int t, int2 jp, int64_t) {
                              int r;
                              if (BITS) {
@@ -691,6 +924,10 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
                              }
                              atomicAdd(&cnt[r], 1);
                              const uint64_t x = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
+                             // m2 only decreases: a candidate above it now can never
+                             // be one of the two smallest (all candidates of a column
+                             // differ in t), so most products skip the cascade
+                             if (x > *(volatile const uint64_t*)&m2[r]) return;
                              const uint64_t old = atomicMin(&m1[r], x);
                              const uint64_t rej = old > x ? old : x;
                              if (rej != kEmpty64) atomicMin(&m2[r], rej);
@@ -749,6 +986,7 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int32_t* __restrict__ list, const int64_t* __restrict__ esc_off, const uint64_t* __restrict__ seg,
     const int2* __restrict__ at, uint32_t* __restrict__ keys0, uint64_t* __restrict__ pay0) {
     __shared__ int64_t c_start[kEscBlock], c_off[kEscBlock];
+    __shared__ uint16_t tbuf[kWalkWin];
     __shared__ int64_t s_tmp[kEscBlock / kWave + 1];
     const int64_t g = list[blockIdx.x];
     const int s = find_set(set_base, nsets, g);
@@ -758,7 +996,7 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int L = (int)(S.a_rowptr[i + 1] - lo);
     const int64_t base = esc_off[g];
     // products land at their t-major index, so the expansion is ordered by k
-    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_start, c_off, s_tmp, nullptr,
+    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
                              [&](int t, int2 jp, int64_t q) {
                                  keys0[base + q] = (uint32_t)jp.x;
                                  pay0[base + q] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
@@ -958,15 +1196,15 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_emit(
 // for the kernels' static LDS.
 constexpr size_t kLdsLimit = 158 * 1024;
 
-static size_t sym_hash_lds(int block, int T) { return (size_t)block * 16 + (size_t)T * 8; }
+static size_t sym_hash_lds(int block, int T) { return walk_lds(block) + (size_t)T * 8; }
 static size_t sym_bits_lds(int block, int planes, int words) {
-    return (size_t)block * 16 + (size_t)planes * words * 4;
+    return walk_lds(block) + (size_t)planes * words * 4;
 }
 // Numeric LDS for rows with at most D output entries: chunk arrays,
 // m1/m2/cnt, and the column map (bitmap + prefix, or hash keys + ranks).
 static size_t num_lds(int block, int D, int load_pct, bool bits, int words) {
     const size_t map = bits ? (size_t)words * 8 : (size_t)table_slots(D, load_pct) * 8;
-    return (size_t)block * 16 + (size_t)D * 20 + map;
+    return walk_lds(block) + (size_t)D * 20 + map;
 }
 
 // Workgroup width for a launch whose LDS footprint is `lds` at 256 threads:
@@ -976,6 +1214,15 @@ static int wide_block(int base, size_t lds) {
     if (lds > 80 * 1024) return 1024;
     if (lds > 40 * 1024) return std::max(base, 512);
     return base;
+}
+
+// A launch asking for more LDS than a workgroup may hold is refused here.
+static int check_lds(size_t lds) {
+    if (lds > kLdsLimit) {
+        set_error("internal: launch needs " + std::to_string(lds) + " bytes of LDS");
+        return DIBELLA_EDEVICE;
+    }
+    return DIBELLA_OK;
 }
 
 template <int BLOCK>
@@ -1037,6 +1284,7 @@ template <int BLOCK>
 static int launch_sym_hash(const OvWork& W, const SymArgs& a, hipStream_t st) {
     DB_TRY(allow_lds_ov<BLOCK>());
     const size_t lds = sym_hash_lds(BLOCK, a.T);
+    DB_TRY(check_lds(lds));
     const int grid = a.dcount ? a.grid : persistent_grid(a.hcount, BLOCK, lds);
     hipLaunchKernelGGL(k_ov_sym_hash<BLOCK>, dim3(grid), dim3(BLOCK), lds, st, W.d_sets,
                        W.nsets, W.d_base, a.list, a.dcount, a.hcount, a.T, a.limit, a.level, W.retry_list, W.seg,
@@ -1050,6 +1298,7 @@ static int launch_sym_bits(const OvWork& W, const int32_t* list, int count, int 
                            hipStream_t st) {
     DB_TRY(allow_lds_ov<BLOCK>());
     const size_t lds = sym_bits_lds(BLOCK, planes, words);
+    DB_TRY(check_lds(lds));
     hipLaunchKernelGGL(k_ov_sym_bits<BLOCK>, dim3(persistent_grid(count, BLOCK, lds)), dim3(BLOCK), lds, st,
                        W.d_sets, W.nsets, W.d_base, list, W.seg, W.at, W.soff, W.scratch, W.nnzrow, W.distinct,
                        &W.ctr->qhead[kQSymBits], count);
@@ -1062,6 +1311,7 @@ static int launch_numeric(const OvWork& W, const int32_t* list, int count, int D
                           int words, int queue, hipStream_t st) {
     DB_TRY(allow_lds_ov<BLOCK>());
     const size_t lds = num_lds(BLOCK, D, load_pct, bits, words);
+    DB_TRY(check_lds(lds));
     const int grid = persistent_grid(count, BLOCK, lds);
     int32_t* qh = &W.ctr->qhead[queue];
     if (bits)
@@ -1192,8 +1442,8 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         total_nnz += a.nnz;
     }
     base[nsets] = total_rows;
-    if (total_rows >= (int64_t(1) << 31) || total_nnz >= (int64_t(1) << 40) || total_m >= (int64_t(1) << 32)) {
-        set_error("batch too large: total rows must be < 2^31, total columns < 2^32 and total nnz < 2^40");
+    if (total_rows >= (int64_t(1) << 31) || total_nnz >= (int64_t(1) << 32) || total_m >= (int64_t(1) << 32)) {
+        set_error("batch too large: total rows must be < 2^31, total columns and total nnz < 2^32");
         return DIBELLA_EOVERFLOW;
     }
     for (int s = 0; s < nsets; ++s) {
@@ -1222,7 +1472,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(ar.work_n(nsets, &d_flags));
     DB_TRY(ar.work_n(1, &d_ctr));
     DB_TRY(ar.work_n(nsets, &d_set_nnz));
-    int64_t* t_rowptr;
+    uint32_t* t_rowptr;   // 32-bit offsets (total nnz < 2^32): half the footprint of the gathers
     uint32_t *keys_a, *keys_b;
     uint64_t *pays_a, *pays_b;
     uint64_t* seg;
@@ -1231,8 +1481,8 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(ar.work_n(total_m + 1, &t_rowptr));
     DB_TRY(ar.work_n(total_nnz, &keys_a));
     DB_TRY(ar.work_n(total_nnz, &keys_b));
-    DB_TRY(ar.work_n(total_nnz, &pays_a));
     DB_TRY(ar.work_n(total_nnz, &pays_b));
+    DB_TRY(ar.work_n(total_nnz, &pays_a));
     DB_TRY(ar.work_n(total_nnz, &seg));
     DB_TRY(ar.work_n(total_rows, &flops_row));
     DB_TRY(ar.work_n(total_rows, &nnzrow));
@@ -1259,43 +1509,91 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
                           hipMemcpyHostToDevice, st));
     DB_TRY(fill_i32(d_flags, 0, nsets, st));
     DB_TRY(fill_i32(reinterpret_cast<int32_t*>(d_ctr), 0, sizeof(OvCounters) / 4, st));
-    DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));
     DB_TRY(fill_i64(nnzrow, 0, total_rows, st));
     DB_TRY(fill_i32(distinct, 0, total_rows, st));
 
     // ---- validate + transpose + row costs + scratch ranges
     int tok = -1;
-    DB_TRY(timing_begin(kPhTranspose, st, &tok));
     constexpr int WPB = 4;
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
+    const int col_bits = ceil_log2_i64(std::max<int64_t>(total_m, 2));
+    const int low = std::min(15, std::max(10, col_bits - 8));
+    const int64_t nbuckets = ceil_div(total_m, int64_t(1) << low);
+    const int64_t nchunks = ceil_div(total_nnz, kChunk);
+    // bucketed path: bucket cursors fit beside the staging in LDS, entries
+    // index in 31 bits, and the (bucket, chunk) count table stays small
+    const bool bucketed = nbuckets <= kMaxBuckets && total_nnz < (int64_t(1) << 31) &&
+                          nbuckets * nchunks <= std::max<int64_t>(int64_t(1) << 22, total_nnz / 4);
+    if (bucketed) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(t_rowptr), 0, total_m + 1, st));
+    else DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
     if (total_rows > 0) {
-        hipLaunchKernelGGL(k_ov_keys<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets,
-                           d_base, total_rows, keys_a, pays_a, d_flags, checks);
+        DB_TRY(timing_begin(kPhKeys, st, &tok));
+        hipLaunchKernelGGL(k_ov_keys<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets, d_base,
+                           total_rows, keys_a, pays_a, d_flags, checks);
         DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
     }
-    int in_b = 0;
-    DB_TRY(radix_sort_pairs(keys_a, pays_a, keys_b, pays_b, total_nnz, ceil_log2_i64(std::max<int64_t>(total_m, 1)),
-                            &in_b, ar));
-    const uint32_t* tkeys = in_b ? keys_b : keys_a;
-    const int2* at = reinterpret_cast<const int2*>(in_b ? pays_b : pays_a);
-    if (total_nnz > 0) {
-        hipLaunchKernelGGL(k_ov_trowptr, dim3(grid_for(total_nnz, 256, 1 << 16)), dim3(256), 0, st, tkeys, total_nnz,
-                           total_m, t_rowptr);
+    const int2* at = nullptr;
+    if (bucketed && total_nnz > 0) {
+        int32_t* pcounts;
+        int64_t* poffs;
+        const int64_t ncount = nbuckets * nchunks;
+        DB_TRY(ar.work_n(ncount, &pcounts));
+        DB_TRY(ar.work_n(ncount + 1, &poffs));
+        DB_TRY(timing_begin(kPhPartCount, st, &tok));
+        hipLaunchKernelGGL(k_ov_part_count, dim3((unsigned)nchunks), dim3(kPartBlock), (size_t)nbuckets * 4, st,
+                           keys_a, total_nnz, low, (int)nbuckets, pcounts);
         DB_HIP(hipGetLastError());
-    } else {
-        DB_TRY(fill_i64(t_rowptr, 0, total_m + 1, st));
+        DB_TRY(timing_end(tok, st));
+        DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, ar));
+        static bool lds_ok = false;
+        if (!lds_ok) {
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kLdsLimit));
+            lds_ok = true;
+        }
+        DB_TRY(timing_begin(kPhPartScatter, st, &tok));
+        hipLaunchKernelGGL(k_ov_part_scatter, dim3((unsigned)nchunks), dim3(kPartBlock), part_scatter_lds(nbuckets),
+                           st, keys_a, pays_a, total_nnz, low, (int)nbuckets, poffs, total_nnz, keys_b, pays_b);
+        DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
+        // A^T pairs land in pays_a, free once the partition has read it
+        DB_TRY(timing_begin(kPhBucketSort, st, &tok));
+        hipLaunchKernelGGL(k_ov_bucket_sort, dim3((unsigned)nbuckets), dim3(kBucketBlock), (size_t)4 << low, st,
+                           poffs, nchunks, low, total_m, total_nnz, keys_b, pays_b, t_rowptr, pays_a);
+        DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
+        at = reinterpret_cast<const int2*>(pays_a);
+    } else if (!bucketed) {
+        // very many columns: LSD radix sort of the pairs by column
+        int in_b = 0;
+        DB_TRY(radix_sort_pairs(keys_a, pays_a, keys_b, pays_b, total_nnz, col_bits, &in_b, ar));
+        const uint32_t* tkeys = in_b ? keys_b : keys_a;
+        at = reinterpret_cast<const int2*>(in_b ? pays_b : pays_a);
+        if (total_nnz > 0) {
+            DB_TRY(timing_begin(kPhBucketSort, st, &tok));
+            hipLaunchKernelGGL(k_ov_trowptr, dim3(grid_for(total_nnz, 256, 1 << 16)), dim3(256), 0, st, tkeys,
+                               total_nnz, total_m, t_rowptr);
+            DB_HIP(hipGetLastError());
+            DB_TRY(timing_end(tok, st));
+        } else {
+            DB_TRY(fill_i32(reinterpret_cast<int32_t*>(t_rowptr), 0, total_m + 1, st));
+        }
     }
     if (total_rows > 0) {
-        hipLaunchKernelGGL(k_ov_scatter<WPB>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
-                           dim3(WPB * kWave), 0, st, d_sets, nsets, d_base, total_rows, t_rowptr, seg,
+        DB_TRY(timing_begin(kPhSegments, st, &tok));
+        hipLaunchKernelGGL(k_ov_scatter<kSegWaves>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
+                           dim3(kSegWaves * kWave), 0, st, d_sets, nsets, d_base, total_rows, t_rowptr, seg,
                            flops_row, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct);
+        DB_TRY(timing_end(tok, st));
         hipLaunchKernelGGL(k_ov_scratch_bound, dim3(grid_for(total_rows, 256, 4096)), dim3(256), 0, st, d_sets,
                            nsets, d_base, total_rows, flops_row, sbound);
         DB_HIP(hipGetLastError());
     }
     DB_TRY(scan_exclusive(sbound, soff, total_rows, nullptr, ar));
-    DB_TRY(timing_end(tok, st));
     // ---- sync 1: validity, bin sizes, scratch size
     char* back = hbuf + desc_bytes;
     OvCounters* h_ctr = reinterpret_cast<OvCounters*>(back);
@@ -1327,7 +1625,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     if (h_ctr->sym_count[kBitsClass] > 0) {
         const int count = h_ctr->sym_count[kBitsClass];
         const int blk = wide_block(tn.sym_block, sym_bits_lds(256, bits_planes, bits_words));
-        DB_TRY(timing_begin(kPhSymbolic, st, &tok));
+        DB_TRY(timing_begin(kPhSymBits, st, &tok));
         DB_TRY(dispatch_sym_bits(blk, W, sym_list + (int64_t)kBitsClass * total_rows, count, bits_planes,
                                  bits_words, st));
         DB_TRY(timing_end(tok, st));
@@ -1339,7 +1637,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         any_hash = true;
         const int T = 1 << lg;
         const int limit = (int)((int64_t)T * tn.load_pct / 100);
-        DB_TRY(timing_begin(kPhSymbolic, st, &tok));
+        DB_TRY(timing_begin(kPhSymHash, st, &tok));
         DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
                                  SymArgs{sym_list + (int64_t)lg * total_rows, nullptr, count, count, T, limit, 0,
                                          kQSymHash + lg},
@@ -1350,7 +1648,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         const int T = 1 << tn.sym_max_log2;
         const int limit = (int)((int64_t)T * tn.load_pct / 100);
         const int grid = (int)std::min<int64_t>(total_rows, 512);
-        DB_TRY(timing_begin(kPhSymbolic, st, &tok));
+        DB_TRY(timing_begin(kPhSymHash, st, &tok));
         DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
                                  SymArgs{retry_list, &d_ctr->retry_rows, 0, grid, T, limit, 1, kQRetry}, st));
         DB_TRY(timing_end(tok, st));
@@ -1418,16 +1716,29 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     hipLaunchKernelGGL(k_ov_write_rowptr, dim3(grid_for(total_rows + nsets, 256, 4096)), dim3(256), 0, st,
                        d_sets, nsets, d_base, total_rows, G);
     DB_HIP(hipGetLastError());
+    // numeric bins (largest tables first) spread over the caller's stream and
+    // the side streams, so that the few rows of the large bins overlap with
+    // the many of the small ones instead of leaving the GPU to a tail
+    SideStreams* side = nullptr;
+    DB_TRY(side_streams(&side));
+    int tok_all = -1;
+    DB_TRY(timing_begin(kPhNumericAll, st, &tok_all));
+    DB_TRY(side->begin(st));
+    int lane_k = 0;
     for (int b = bins.nh + bins.nb - 1; b >= 0; --b) {
         const int count = h_ctr->num_count[b];
         if (!count) continue;
         const bool bits = b >= bins.nh;
         const int blk = wide_block(tn.num_block, num_lds(256, bins.d[b], tn.load_pct, bits, bits_words));
-        DB_TRY(timing_begin(kPhNumeric, st, &tok));
+        hipStream_t ls = lane_k == 0 ? st : side->s[lane_k - 1];
+        lane_k = (lane_k + 1) % (kSideStreams + 1);
+        DB_TRY(timing_begin(kPhNumeric, ls, &tok));
         DB_TRY(dispatch_numeric(blk, W, num_list + (int64_t)b * total_rows, count, bins.d[b], tn.load_pct, bits,
-                                bits_words, kQNumeric + b, st));
-        DB_TRY(timing_end(tok, st));
+                                bits_words, kQNumeric + b, ls));
+        DB_TRY(timing_end(tok, ls));
     }
+    DB_TRY(side->end(st));
+    DB_TRY(timing_end(tok_all, st));
     if (esc_rows > 0) {
         DB_TRY(timing_begin(kPhEsc, st, &tok));
         hipLaunchKernelGGL(k_esc_emit, dim3(esc_rows), dim3(kEscBlock), 0, st, d_sets, nsets, d_base,

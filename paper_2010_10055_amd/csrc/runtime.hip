@@ -107,6 +107,51 @@ int stage_done(hipStream_t s) {
     return DIBELLA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Side streams (per host thread and device, default priority, non-blocking)
+// ---------------------------------------------------------------------------
+namespace {
+struct SideSet {
+    int dev = -1;
+    SideStreams ss;
+};
+}  // namespace
+
+int side_streams(SideStreams** out) {
+    static thread_local std::vector<SideSet> sets;
+    int dev = 0;
+    DB_HIP(hipGetDevice(&dev));
+    for (auto& x : sets)
+        if (x.dev == dev) {
+            *out = &x.ss;
+            return DIBELLA_OK;
+        }
+    SideSet x;
+    x.dev = dev;
+    for (int k = 0; k < kSideStreams; ++k) {
+        DB_HIP(hipStreamCreateWithFlags(&x.ss.s[k], hipStreamNonBlocking));
+        DB_HIP(hipEventCreateWithFlags(&x.ss.join[k], hipEventDisableTiming));
+    }
+    DB_HIP(hipEventCreateWithFlags(&x.ss.fork, hipEventDisableTiming));
+    sets.push_back(x);
+    *out = &sets.back().ss;
+    return DIBELLA_OK;
+}
+
+int SideStreams::begin(hipStream_t main) {
+    DB_HIP(hipEventRecord(fork, main));
+    for (int k = 0; k < kSideStreams; ++k) DB_HIP(hipStreamWaitEvent(s[k], fork, 0));
+    return DIBELLA_OK;
+}
+
+int SideStreams::end(hipStream_t main) {
+    for (int k = 0; k < kSideStreams; ++k) {
+        DB_HIP(hipEventRecord(join[k], s[k]));
+        DB_HIP(hipStreamWaitEvent(main, join[k], 0));
+    }
+    return DIBELLA_OK;
+}
+
 int sync_stream(hipStream_t s) {
     DB_HIP(hipStreamSynchronize(s));
     stats().host_syncs++;

@@ -112,13 +112,18 @@ int radix_sort_pairs(uint32_t* ka, uint64_t* va, uint32_t* kb, uint64_t* vb, int
     uint32_t *kin = ka, *kout = kb;
     uint64_t *vin = va, *vout = vb;
     for (int p = 0; p < passes; ++p) {
+        int tok = -1;
+        DB_TRY(timing_begin(kPhSortUp, st, &tok));
         hipLaunchKernelGGL(k_rs_upsweep, dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, kin, n, 8 * p, ntiles,
                            counts);
         DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
         DB_TRY(scan_exclusive_ws(counts, offsets, 256 * ntiles, nullptr, scan_tiles, st));
+        DB_TRY(timing_begin(kPhSortDown, st, &tok));
         hipLaunchKernelGGL(k_rs_downsweep, dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, kin, vin, n, 8 * p,
                            ntiles, offsets, kout, vout);
         DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
         uint32_t* tk = kin; kin = kout; kout = tk;
         uint64_t* tv = vin; vin = vout; vout = tv;
     }

@@ -494,6 +494,8 @@ static int launch_pass_marks(const TrBuffers& B, int src, hipStream_t st) {
     const size_t lds_small = (size_t)BLOCK * 16 + (size_t)kSmallCap * 12;
     const size_t lds_mid = (size_t)BLOCK * 16 + (size_t)B.mid_cap * 12;
     const size_t lds_big = (size_t)BLOCK * 16;
+    int tok = -1;
+    DB_TRY(timing_begin(kPhTrMark, st, &tok));
     if (B.grid[0] > 0)
         hipLaunchKernelGGL((k_tr_mark<BLOCK, 0>), dim3(B.grid[0]), dim3(BLOCK), lds_small, st, B.d_sets, B.nsets,
                            B.d_base, B.lists, 0, B.total_rows, kSmallCap, B.rp[src], B.ci[src], B.va[src], B.keep,
@@ -507,29 +509,29 @@ static int launch_pass_marks(const TrBuffers& B, int src, hipStream_t st) {
                            B.d_base, B.lists, 2, B.total_rows, 0, B.rp[src], B.ci[src], B.va[src], B.keep,
                            B.keepcnt, B.nbuf, B.active, B.deleted, B.state, B.flags);
     DB_HIP(hipGetLastError());
+    DB_TRY(timing_end(tok, st));
     return DIBELLA_OK;
 }
 
 // Enqueue one pass reading buffer `src` and writing buffer 1 - src.
 static int enqueue_pass(const TrBuffers& B, int src, hipStream_t st) {
-    int tok = -1;
-    DB_TRY(timing_begin(kPhTrMark, st, &tok));
     switch (tuning().tr_block) {
         case 64: DB_TRY(launch_pass_marks<64>(B, src, st)); break;
         case 128: DB_TRY(launch_pass_marks<128>(B, src, st)); break;
         case 512: DB_TRY(launch_pass_marks<512>(B, src, st)); break;
         default: DB_TRY(launch_pass_marks<256>(B, src, st)); break;
     }
-    DB_TRY(timing_end(tok, st));
     const int dst = 1 - src;
-    DB_TRY(timing_begin(kPhTrCompact, st, &tok));
     DB_TRY(scan_exclusive_ws(B.keepcnt, B.rp[dst], B.total_rows, &B.state->any_active, B.scan_tiles, st));
     constexpr int WPB = 4;
-    if (B.total_rows > 0)
+    int tok = -1;
+    if (B.total_rows > 0) {
+        DB_TRY(timing_begin(kPhTrCompact, st, &tok));
         hipLaunchKernelGGL(k_tr_compact<WPB>, dim3(grid_for(B.total_rows, WPB, 1 << 16)), dim3(WPB * kWave), 0, st,
                            B.total_rows, B.rp[src], B.ci[src], B.va[src], B.keep, B.rp[dst], B.ci[dst],
                            B.va[dst], B.state);
-    DB_TRY(timing_end(tok, st));
+        DB_TRY(timing_end(tok, st));
+    }
     hipLaunchKernelGGL(k_tr_update, dim3(1), dim3(256), 0, st, B.d_sets, B.nsets, B.rp[dst], B.total_rows,
                        B.active, B.iters, B.deleted, B.set_nnz, B.state);
     DB_HIP(hipGetLastError());

@@ -92,6 +92,35 @@ def test_overlap_random(lib, seed, n, m, density, ms, bits):
     assert_overlap_equal(C, oracle.overlap(A, ms), f"random{seed}")
 
 
+def test_overlap_many_columns_radix_transpose(lib):
+    """More than 2^27 columns: the transpose falls back to the radix sort."""
+    rng = np.random.default_rng(21)
+    n, m = 400, (1 << 27) + 17
+    rows, cols = [], []
+    shared = rng.choice(m, 300, replace=False)   # k-mers that several reads share
+    for i in range(n):
+        c = np.unique(np.concatenate([rng.choice(shared, 6), rng.integers(0, m, 4), [m - 1] if i % 50 == 0 else []]))
+        rows.append(np.full(c.size, i)); cols.append(c)
+    rows, cols = np.concatenate(rows), np.concatenate(cols).astype(np.int32)
+    vals = rng.integers(0, 10000, rows.size).astype(np.int32)
+    A = synth.coo_to_csr(n, m, rows, cols, vals)
+    assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "radix transpose")
+
+
+def test_overlap_many_rows_wide_partition(lib):
+    """Many short rows over 2^24 columns: the partition takes more rows per
+    workgroup so that its (bucket, workgroup) count table stays small."""
+    rng = np.random.default_rng(22)
+    n, m = 90000, 1 << 24
+    per = rng.integers(0, 3, n)
+    rows = np.repeat(np.arange(n), per)
+    cols = rng.integers(0, 1 << 14, rows.size) * 1024 + rng.integers(0, 2, rows.size)
+    key = np.unique(rows.astype(np.int64) * m + cols)   # one entry per (read, k-mer)
+    rows, cols = key // m, key % m
+    A = synth.coo_to_csr(n, m, rows, cols.astype(np.int32), rng.integers(0, 5000, rows.size).astype(np.int32))
+    assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "wide partition")
+
+
 def test_overlap_empty_rows_and_matrix(lib):
     A = synth.CSR(4, 7, np.zeros(5, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
     C = _run_overlap(lib, A, 1)
@@ -173,7 +202,7 @@ def test_overlap_deterministic(lib):
         assert torch.equal(getattr(C1, f), getattr(C2, f))
 
 
-@pytest.mark.parametrize("case", ["unsorted", "colrange", "negative", "rowptr", "min_shared"])
+@pytest.mark.parametrize("case", ["unsorted", "colrange", "negative", "rowptr", "overlap_rows", "min_shared"])
 def test_overlap_rejects_malformed(lib, case):
     rng = np.random.default_rng(12)
     A = synth.random_a(rng, 20, 50, 0.2)
@@ -188,6 +217,8 @@ def test_overlap_rejects_malformed(lib, case):
         val[5] = -1
     elif case == "rowptr":
         rowptr[-2] = rowptr[-1] + 5     # row ranges past nnz and decreasing
+    elif case == "overlap_rows":
+        rowptr[5] = rowptr[9]           # row 4 covers rows 5..8 too: more entries than A holds
     else:
         ms = 0
     bad = synth.CSR(20, 50, rowptr, col, val)
