@@ -61,7 +61,7 @@ def kernel_bytes(w, C_nnz, products, tr_stats, sort_passes):
         "bucket_sort": (4 * nnzA + 4 * m) if radix else (24 * nnzA + 4 * m),
         "sort_up": 4 * nnzA * sort_passes,
         "sort_down": 24 * nnzA * sort_passes,
-        "segments": 16 * n + 28 * nnzA,
+        "segments": 16 * n + 20 * nnzA,
         "sym_bits": sym,
         "sym_hash": sym,
         "numeric": 8 * n + 8 * nnzA + 16 * nnzA + 8 * products + 24 * C_nnz,

@@ -259,10 +259,11 @@ __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64
 
 // ---------------------------------------------------------------------------
 // Step 2: group the pairs by column with a two-pass bucketed counting sort
-// (at most 4096 buckets of 2^low columns, low <= 15):
-//   k_ov_part_count   per chunk of kChunk pairs, a bucket histogram
-//                     (bucket = key >> low), stored bucket-major;
-//   scan              -> first output slot of every (bucket, chunk);
+// (at most kMaxBuckets buckets of 2^low columns, low <= 15):
+//   k_ov_part_count   per workgroup (one or more chunks of kChunk pairs), a
+//                     bucket histogram (bucket = key >> low), stored
+//                     bucket-major;
+//   scan              -> first output slot of every (bucket, workgroup);
 //   k_ov_part_scatter per chunk, the pairs are ordered by bucket in LDS and
 //                     written out as runs, so that stores coalesce;
 //   k_ov_bucket_sort  one workgroup per bucket counts its pairs per column in
@@ -283,90 +284,99 @@ inline size_t part_scatter_lds(int64_t nbuckets) {
 }
 
 __global__ __launch_bounds__(kPartBlock) void k_ov_part_count(const uint32_t* __restrict__ keys, int64_t n,
-                                                              int low, int nbuckets,
+                                                              int per_block, int low, int nbuckets,
                                                               int32_t* __restrict__ counts) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
-    const int64_t nchunks = gridDim.x;
-    // keys of a malformed A may be unset: the bucket is clamped into range
+    const int64_t nblocks = gridDim.x;
     for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) hist[b] = 0u;
     __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    const int64_t c1 = min(c0 + kChunk, n);
-    uint32_t kk[kPartIlp];
+    for (int c = 0; c < per_block; ++c) {
+        const int64_t c0 = ((int64_t)blockIdx.x * per_block + c) * kChunk;
+        if (c0 >= n) break;
+        const int64_t c1 = min(c0 + kChunk, n);
+        uint32_t kk[kPartIlp];
 #pragma unroll
-    for (int q = 0; q < kPartIlp; ++q) kk[q] = keys[min(c0 + q * kPartBlock + threadIdx.x, c1 - 1)];
+        for (int q = 0; q < kPartIlp; ++q) kk[q] = keys[min(c0 + q * kPartBlock + threadIdx.x, c1 - 1)];
+        // keys of a malformed A may be unset: the bucket is clamped into range
 #pragma unroll
-    for (int q = 0; q < kPartIlp; ++q)
-        atomicAdd(&hist[min(kk[q] >> low, (uint32_t)nbuckets - 1u)], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+        for (int q = 0; q < kPartIlp; ++q)
+            atomicAdd(&hist[min(kk[q] >> low, (uint32_t)nbuckets - 1u)],
+                      c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+    }
     __syncthreads();
     for (int b = threadIdx.x; b < nbuckets; b += kPartBlock)
-        counts[(int64_t)b * nchunks + blockIdx.x] = (int32_t)hist[b];
+        counts[(int64_t)b * nblocks + blockIdx.x] = (int32_t)hist[b];
 }
 
 __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
-    const uint32_t* __restrict__ keys, const uint64_t* __restrict__ pays, int64_t n, int low, int nbuckets,
-    const int64_t* __restrict__ offsets, int64_t cap, uint32_t* __restrict__ skey, uint64_t* __restrict__ spay) {
+    const uint32_t* __restrict__ keys, const uint64_t* __restrict__ pays, int64_t n, int per_block, int low,
+    int nbuckets, const int64_t* __restrict__ offsets, int64_t cap, uint32_t* __restrict__ skey,
+    uint64_t* __restrict__ spay) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* st_pay = reinterpret_cast<uint64_t*>(smem);                 // [kChunk]
     uint32_t* st_key = reinterpret_cast<uint32_t*>(st_pay + kChunk);      // [kChunk]
     uint32_t* lcnt = st_key + kChunk;                                     // [nbuckets] count, then cursor
     uint32_t* loff = lcnt + nbuckets;                                     // [nbuckets] chunk-local start
-    int64_t* gpos = reinterpret_cast<int64_t*>(loff + nbuckets);             // [nbuckets], 8-byte aligned
+    int64_t* gpos = reinterpret_cast<int64_t*>(loff + nbuckets);          // [nbuckets], 8-byte aligned
     __shared__ uint32_t s_tmp[kPartBlock / kWave + 1];
-    const int64_t nchunks = gridDim.x;
-    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) {
-        lcnt[b] = 0u;
-        gpos[b] = offsets[(int64_t)b * nchunks + blockIdx.x];
-    }
-    __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    const int64_t c1 = min(c0 + kChunk, n);
-    uint32_t kk[kPartIlp], rk[kPartIlp];
-    uint64_t pp[kPartIlp];
-#pragma unroll
-    for (int q = 0; q < kPartIlp; ++q) {
-        const int64_t e = min(c0 + q * kPartBlock + threadIdx.x, c1 - 1);
-        // keys of a malformed A may be unset: the bucket is clamped into range
-        kk[q] = min(keys[e], ((uint32_t)nbuckets << low) - 1u);
-        pp[q] = pays[e];
-    }
-    // rank of each pair among the chunk's pairs of its bucket
-#pragma unroll
-    for (int q = 0; q < kPartIlp; ++q)
-        rk[q] = atomicAdd(&lcnt[kk[q] >> low], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
-    __syncthreads();
-    // chunk-local bucket starts: each thread scans a run of consecutive buckets
+    const int64_t nblocks = gridDim.x;
+    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) gpos[b] = offsets[(int64_t)b * nblocks + blockIdx.x];
     const int per = (nbuckets + kPartBlock - 1) / kPartBlock;
     const int b0 = threadIdx.x * per;
-    uint32_t local = 0;
-    for (int q = 0; q < per; ++q)
-        if (b0 + q < nbuckets) local += lcnt[b0 + q];
-    uint32_t tot;
-    uint32_t run = block_exclusive_sum<kPartBlock>(local, s_tmp, &tot);
-    for (int q = 0; q < per; ++q) {
-        if (b0 + q >= nbuckets) break;
-        loff[b0 + q] = run;
-        run += lcnt[b0 + q];
-    }
-    __syncthreads();
+    for (int c = 0; c < per_block; ++c) {
+        const int64_t c0 = ((int64_t)blockIdx.x * per_block + c) * kChunk;
+        if (c0 >= n) break;
+        const int64_t c1 = min(c0 + kChunk, n);
+        for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) lcnt[b] = 0u;
+        __syncthreads();
+        uint32_t kk[kPartIlp], rk[kPartIlp];
+        uint64_t pp[kPartIlp];
 #pragma unroll
-    for (int q = 0; q < kPartIlp; ++q) {
-        if (c0 + q * kPartBlock + threadIdx.x >= c1) continue;
-        const uint32_t slot = loff[kk[q] >> low] + rk[q];
-        st_key[slot] = kk[q];
-        st_pay[slot] = pp[q];
-    }
-    __syncthreads();
-    // consecutive slots of one bucket go to consecutive output positions
-    for (uint32_t slot = threadIdx.x; slot < tot; slot += kPartBlock) {
-        const uint32_t key = st_key[slot];
-        const int b = (int)(key >> low);
-        const int64_t pos = gpos[b] + (slot - loff[b]);
-        if (pos < cap) {
-            skey[pos] = key;
-            spay[pos] = st_pay[slot];
+        for (int q = 0; q < kPartIlp; ++q) {
+            const int64_t e = min(c0 + q * kPartBlock + threadIdx.x, c1 - 1);
+            // keys of a malformed A may be unset: the bucket is clamped into range
+            kk[q] = min(keys[e], ((uint32_t)nbuckets << low) - 1u);
+            pp[q] = pays[e];
         }
+        // rank of each pair among the chunk's pairs of its bucket
+#pragma unroll
+        for (int q = 0; q < kPartIlp; ++q)
+            rk[q] = atomicAdd(&lcnt[kk[q] >> low], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+        __syncthreads();
+        // chunk-local bucket starts: each thread scans a run of consecutive buckets
+        uint32_t local = 0;
+        for (int q = 0; q < per; ++q)
+            if (b0 + q < nbuckets) local += lcnt[b0 + q];
+        uint32_t tot;
+        uint32_t run = block_exclusive_sum<kPartBlock>(local, s_tmp, &tot);
+        for (int q = 0; q < per; ++q) {
+            if (b0 + q >= nbuckets) break;
+            loff[b0 + q] = run;
+            run += lcnt[b0 + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPartIlp; ++q) {
+            if (c0 + q * kPartBlock + threadIdx.x >= c1) continue;
+            const uint32_t slot = loff[kk[q] >> low] + rk[q];
+            st_key[slot] = kk[q];
+            st_pay[slot] = pp[q];
+        }
+        __syncthreads();
+        // consecutive slots of one bucket go to consecutive output positions
+        for (uint32_t slot = threadIdx.x; slot < tot; slot += kPartBlock) {
+            const uint32_t key = st_key[slot];
+            const int b = (int)(key >> low);
+            const int64_t pos = gpos[b] + (slot - loff[b]);
+            if (pos < cap) {
+                skey[pos] = key;
+                spay[pos] = st_pay[slot];
+            }
+        }
+        __syncthreads();
+        // the next chunk of this workgroup continues after this one's runs
+        for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) gpos[b] += lcnt[b];
     }
 }
 
@@ -374,6 +384,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
     const int64_t* __restrict__ offsets, int64_t nchunks, int low, int64_t total_m, int64_t cap,
     const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint32_t* __restrict__ t_rowptr,
     uint64_t* __restrict__ at) {
+    // offsets: bucket-major over the partition's workgroups (nchunks of them)
     const int64_t total_valid = min(offsets[(int64_t)gridDim.x * nchunks], cap);
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
@@ -1521,10 +1532,14 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     const int low = std::min(15, std::max(10, col_bits - 8));
     const int64_t nbuckets = ceil_div(total_m, int64_t(1) << low);
     const int64_t nchunks = ceil_div(total_nnz, kChunk);
-    // bucketed path: bucket cursors fit beside the staging in LDS, entries
-    // index in 31 bits, and the (bucket, chunk) count table stays small
-    const bool bucketed = nbuckets <= kMaxBuckets && total_nnz < (int64_t(1) << 31) &&
-                          nbuckets * nchunks <= std::max<int64_t>(int64_t(1) << 22, total_nnz / 4);
+    // bucketed path: bucket cursors fit beside the staging in LDS and entries
+    // index in 31 bits.  A partition workgroup takes several chunks when
+    // that keeps the (bucket, workgroup) count table small beside A.
+    const bool bucketed = nbuckets <= kMaxBuckets && total_nnz < (int64_t(1) << 31);
+    int per_block = 1;
+    while (nbuckets * ceil_div(nchunks, per_block) > std::max<int64_t>(int64_t(1) << 22, total_nnz / 8))
+        per_block *= 2;
+    const int64_t npart = ceil_div(nchunks, per_block);   // partition workgroups
     if (bucketed) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(t_rowptr), 0, total_m + 1, st));
     else DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
     if (total_rows > 0) {
@@ -1538,12 +1553,12 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     if (bucketed && total_nnz > 0) {
         int32_t* pcounts;
         int64_t* poffs;
-        const int64_t ncount = nbuckets * nchunks;
+        const int64_t ncount = nbuckets * npart;
         DB_TRY(ar.work_n(ncount, &pcounts));
         DB_TRY(ar.work_n(ncount + 1, &poffs));
         DB_TRY(timing_begin(kPhPartCount, st, &tok));
-        hipLaunchKernelGGL(k_ov_part_count, dim3((unsigned)nchunks), dim3(kPartBlock), (size_t)nbuckets * 4, st,
-                           keys_a, total_nnz, low, (int)nbuckets, pcounts);
+        hipLaunchKernelGGL(k_ov_part_count, dim3((unsigned)npart), dim3(kPartBlock), (size_t)nbuckets * 4, st,
+                           keys_a, total_nnz, per_block, low, (int)nbuckets, pcounts);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, ar));
@@ -1556,14 +1571,15 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
             lds_ok = true;
         }
         DB_TRY(timing_begin(kPhPartScatter, st, &tok));
-        hipLaunchKernelGGL(k_ov_part_scatter, dim3((unsigned)nchunks), dim3(kPartBlock), part_scatter_lds(nbuckets),
-                           st, keys_a, pays_a, total_nnz, low, (int)nbuckets, poffs, total_nnz, keys_b, pays_b);
+        hipLaunchKernelGGL(k_ov_part_scatter, dim3((unsigned)npart), dim3(kPartBlock), part_scatter_lds(nbuckets),
+                           st, keys_a, pays_a, total_nnz, per_block, low, (int)nbuckets, poffs, total_nnz, keys_b,
+                           pays_b);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         // A^T pairs land in pays_a, free once the partition has read it
         DB_TRY(timing_begin(kPhBucketSort, st, &tok));
         hipLaunchKernelGGL(k_ov_bucket_sort, dim3((unsigned)nbuckets), dim3(kBucketBlock), (size_t)4 << low, st,
-                           poffs, nchunks, low, total_m, total_nnz, keys_b, pays_b, t_rowptr, pays_a);
+                           poffs, npart, low, total_m, total_nnz, keys_b, pays_b, t_rowptr, pays_a);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         at = reinterpret_cast<const int2*>(pays_a);

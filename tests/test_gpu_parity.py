@@ -107,9 +107,8 @@ def test_overlap_many_columns_radix_transpose(lib):
     assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "radix transpose")
 
 
-def test_overlap_many_rows_wide_partition(lib):
-    """Many short rows over 2^24 columns: the partition takes more rows per
-    workgroup so that its (bucket, workgroup) count table stays small."""
+def test_overlap_many_short_rows(lib):
+    """Many short rows (0-2 entries) over 2^24 columns."""
     rng = np.random.default_rng(22)
     n, m = 90000, 1 << 24
     per = rng.integers(0, 3, n)
@@ -119,6 +118,23 @@ def test_overlap_many_rows_wide_partition(lib):
     rows, cols = key // m, key % m
     A = synth.coo_to_csr(n, m, rows, cols.astype(np.int32), rng.integers(0, 5000, rows.size).astype(np.int32))
     assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "wide partition")
+
+
+def test_overlap_wide_partition_several_chunks_per_workgroup(lib):
+    """About 1.2e8 columns and 9e6 entries: the transpose partition takes two
+    chunks per workgroup so that its (bucket, workgroup) count table stays
+    small beside A."""
+    rng = np.random.default_rng(23)
+    n, per, m = 20000, 470, 3800 << 15
+    pool = rng.choice(m, 6000, replace=False)          # k-mers shared by several reads
+    rows = np.repeat(np.arange(n, dtype=np.int64), per)
+    cols = rng.integers(0, m, rows.size)
+    shared = rng.random(rows.size) < 0.02
+    cols[shared] = rng.choice(pool, int(shared.sum()))
+    key = np.unique(rows * m + cols)
+    rows, cols = key // m, key % m
+    A = synth.coo_to_csr(n, m, rows, cols.astype(np.int32), rng.integers(0, 30000, rows.size).astype(np.int32))
+    assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "multi-chunk partition")
 
 
 def test_overlap_empty_rows_and_matrix(lib):
