@@ -167,7 +167,9 @@ typedef struct {
     int32_t num_max_entries;  /* most output entries a row may have in the numeric LDS path:
                                  256..8192 (capped by the LDS); larger rows go to ESC */
     int32_t load_pct;         /* hash-table load limit in percent: 40..85 */
-    int32_t tr_lds_cap;       /* longest row kept in LDS by a pass: 512..8192 */
+    int32_t tr_lds_cap;       /* longest row kept in LDS by a pass: 512..8192 (lowered in
+                                 steps of 512 until the pass fits the LDS: 6144 at 512
+                                 threads); longer rows keep their minima in global memory */
     int32_t tr_graph_passes;  /* passes per captured graph: 1..16 */
     int32_t bits_max_words;   /* bitmap path for sets with at most 32 * this many reads
                                  (and min_shared <= 4): 0..8192; 0 = hash path only */

@@ -55,7 +55,12 @@ class Arena {
     Arena& operator=(const Arena&) = delete;
 
     // Workspace: freed when the Arena dies.  bytes == 0 gives nullptr.
+    // Requests are carved from the reserved block while it has room, else
+    // requests up to 1 MB share 8 MB blocks (256-byte aligned).
     int work(size_t bytes, void** out);
+    // One allocation for the workspace a call is about to request.
+    int reserve(size_t bytes);
+    static size_t padded(size_t bytes) { return (bytes + kAlign - 1) / kAlign * kAlign; }
     // Caller-owned output: freed only if fail() was called.
     int output(size_t bytes, void** out);
     void fail() { failed_ = true; }
@@ -77,7 +82,15 @@ class Arena {
     }
 
   private:
+    static constexpr size_t kAlign = 256;
+    static constexpr size_t kSmallMax = 1 << 20;
+    static constexpr size_t kPoolBytes = 8 << 20;
+    int work_raw(size_t bytes, void** out);
     void release(void* p);
+    char* pool_ = nullptr;
+    size_t pool_used_ = 0;
+    char* res_ = nullptr;
+    size_t res_cap_ = 0, res_used_ = 0;
     dibella_alloc_fn alloc_;
     dibella_free_fn free_;
     void* ctx_;

@@ -1472,6 +1472,34 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         return DIBELLA_EINVAL;
     }
 
+    const int col_bits = ceil_log2_i64(std::max<int64_t>(total_m, 2));
+    // 2^14 columns per bucket keeps two pass-2 workgroups per CU; 2^15 when
+    // the bucket count would not fit the partition's LDS
+    int low = std::min(14, std::max(10, col_bits - 8));
+    if (ceil_div(total_m, int64_t(1) << low) > kMaxBuckets) low = 15;
+    const int64_t nbuckets = ceil_div(total_m, int64_t(1) << low);
+    const int64_t nchunks = ceil_div(total_nnz, kChunk);
+    // bucketed path: bucket cursors fit beside the staging in LDS and entries
+    // index in 31 bits.  A partition workgroup takes several chunks when
+    // that keeps the (bucket, workgroup) count table small beside A.
+    const bool bucketed = nbuckets <= kMaxBuckets && total_nnz < (int64_t(1) << 31);
+    int per_block = 1;
+    while (nbuckets * ceil_div(nchunks, per_block) > std::max<int64_t>(int64_t(1) << 22, total_nnz / 8))
+        per_block *= 2;
+    const int64_t npart = ceil_div(nchunks, per_block);   // partition workgroups
+    // ---- workspace: one reservation for everything requested before the
+    // first synchronisation (allocator calls cost host time each)
+    {
+        const size_t P = Arena::padded(1);
+        auto pad = [](size_t b) { return Arena::padded(b); };
+        size_t est = pad(sizeof(OvSet) * nsets) + 2 * pad(8 * (nsets + 1)) + pad(4 * nsets) + pad(sizeof(OvCounters));
+        est += pad(4 * (total_m + 1)) + 2 * pad(4 * total_nnz) + 3 * pad(8 * total_nnz);
+        est += 7 * pad(8 * (total_rows + 1)) + 3 * pad(4 * total_rows);
+        est += pad(4 * total_rows * kMaxLog2) + pad(4 * total_rows * kMaxBins);
+        est += pad(4 * nbuckets * npart) + pad(8 * (nbuckets * npart + 1));
+        est += 4 * pad(8 * scan_workspace_elems(std::max<int64_t>(total_rows, nbuckets * npart))) + 16 * P;
+        DB_TRY(ar.reserve(est));
+    }
     // ---- workspace
     OvSet* d_sets;
     int64_t* d_base;
@@ -1528,18 +1556,6 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     constexpr int WPB = 4;
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
-    const int col_bits = ceil_log2_i64(std::max<int64_t>(total_m, 2));
-    const int low = std::min(15, std::max(10, col_bits - 8));
-    const int64_t nbuckets = ceil_div(total_m, int64_t(1) << low);
-    const int64_t nchunks = ceil_div(total_nnz, kChunk);
-    // bucketed path: bucket cursors fit beside the staging in LDS and entries
-    // index in 31 bits.  A partition workgroup takes several chunks when
-    // that keeps the (bucket, workgroup) count table small beside A.
-    const bool bucketed = nbuckets <= kMaxBuckets && total_nnz < (int64_t(1) << 31);
-    int per_block = 1;
-    while (nbuckets * ceil_div(nchunks, per_block) > std::max<int64_t>(int64_t(1) << 22, total_nnz / 8))
-        per_block *= 2;
-    const int64_t npart = ceil_div(nchunks, per_block);   // partition workgroups
     if (bucketed) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(t_rowptr), 0, total_m + 1, st));
     else DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
     if (total_rows > 0) {

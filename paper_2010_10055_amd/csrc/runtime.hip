@@ -35,6 +35,38 @@ dibella_stats& stats() {
 int Arena::work(size_t bytes, void** out) {
     *out = nullptr;
     if (bytes == 0) return DIBELLA_OK;
+    // small requests are carved from pooled blocks: one allocator call
+    // serves many of them (allocator callbacks cost host time per call)
+    const size_t need = (bytes + kAlign - 1) / kAlign * kAlign;
+    if (res_ && res_used_ + need <= res_cap_) {
+        *out = res_ + res_used_;
+        res_used_ += need;
+        return DIBELLA_OK;
+    }
+    if (need <= kSmallMax) {
+        if (!pool_ || pool_used_ + need > kPoolBytes) {
+            void* blk = nullptr;
+            DB_TRY(work_raw(kPoolBytes, &blk));
+            pool_ = static_cast<char*>(blk);
+            pool_used_ = 0;
+        }
+        *out = pool_ + pool_used_;
+        pool_used_ += need;
+        return DIBELLA_OK;
+    }
+    return work_raw(bytes, out);
+}
+
+int Arena::reserve(size_t bytes) {
+    void* blk = nullptr;
+    DB_TRY(work_raw(bytes, &blk));
+    res_ = static_cast<char*>(blk);
+    res_cap_ = bytes;
+    res_used_ = 0;
+    return DIBELLA_OK;
+}
+
+int Arena::work_raw(size_t bytes, void** out) {
     void* p = nullptr;
     if (alloc_) {
         p = alloc_(bytes, ctx_);

@@ -52,6 +52,24 @@ enum : int32_t { kTrBadRowptr = 1, kTrBadCol = 2, kTrUnsorted = 4, kTrDiagonal =
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kSmallCap = 512;
+constexpr size_t kTrLdsLimit = 150 * 1024;
+constexpr int kTrWin = 2048;   // walks per LDS expansion window
+constexpr int kTrPer = 4;      // walks per thread in flight
+
+// Hash slots for a row of at most `cap` entries (load <= 1/2).
+__host__ __device__ constexpr int tr_hash_slots(int cap) {
+    int h = 1;
+    while (h < 2 * cap) h <<= 1;
+    return h;
+}
+__device__ __forceinline__ uint32_t tr_hash(int32_t j, int slots) {
+    return ((uint32_t)j * 0x9E3779B1u) >> (32 - __ffs(slots) + 1) & (uint32_t)(slots - 1);
+}
+// Dynamic LDS of a pass launch: chunk arrays, the row (col, val, N), the
+// hash of its columns (MODE 0) and the expansion window.
+__host__ __device__ constexpr size_t tr_mark_lds(int block, int cap) {
+    return (size_t)block * 16 + (size_t)cap * 12 + (cap ? (size_t)tr_hash_slots(cap) * 4 : 0) + (size_t)kTrWin * 2;
+}
 
 __device__ __forceinline__ int32_t wave_or32(int32_t v) {
     for (int d = kWave / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, kWave);
@@ -193,7 +211,8 @@ __device__ __forceinline__ void tr_row(const TrSet* __restrict__ sets, int nsets
                                        int64_t* __restrict__ keepcnt, uint32_t* __restrict__ nbuf,
                                        const int32_t* __restrict__ active, int64_t* __restrict__ deleted,
                                        TrState* __restrict__ state, uint32_t flags, int32_t* s_col,
-                                       int32_t* s_val, uint32_t* s_N, int64_t* c_start, int64_t* c_off,
+                                       int32_t* s_val, uint32_t* s_N, int32_t* s_hash, int hslots,
+                                       int64_t* c_start, int64_t* c_off, uint16_t* tbuf,
                                        int64_t* s_tmp, int64_t* s_red64, int32_t* s_red32, int* out_set,
                                        int64_t* out_deleted, int64_t* out_triples) {
     const int s = find_set(set_base, nsets, g);
@@ -226,6 +245,13 @@ __device__ __forceinline__ void tr_row(const TrSet* __restrict__ sets, int nsets
         col = s_col;
         val = s_val;
         N = s_N;
+        // LDS hash of the row's columns -> position in the row (linear probing)
+        for (int h = threadIdx.x; h < hslots; h += BLOCK) s_hash[h] = -1;
+        __syncthreads();
+        for (int u = threadIdx.x; u < L; u += BLOCK) {
+            uint32_t h = tr_hash(ci[lo + u], hslots);
+            while (atomicCAS(&s_hash[h], -1, u) != -1) h = (h + 1) & (uint32_t)(hslots - 1);
+        }
     } else {
         for (int u = threadIdx.x; u < L; u += BLOCK) {
             nbuf[lo + u] = kInf;
@@ -239,6 +265,9 @@ __device__ __forceinline__ void tr_row(const TrSet* __restrict__ sets, int nsets
     vmax = block_max_lds(vmax, s_red32);   // contains barriers
     const bool variant_b = flags & DIBELLA_TR_VARIANT_B;
     int64_t triples = 0;
+    // walks i -> k -> j: the row's entries k in chunks of BLOCK, their walks
+    // numbered k-major and handed out through an LDS expansion of entry
+    // indices (one LDS read per walk), kTrPer walks per thread in flight
     for (int cbase = 0; cbase < L; cbase += BLOCK) {
         const int cl = min(BLOCK, L - cbase);
         int64_t deg = 0, st = 0;
@@ -252,30 +281,61 @@ __device__ __forceinline__ void tr_row(const TrSet* __restrict__ sets, int nsets
         c_start[threadIdx.x] = st;
         c_off[threadIdx.x] = ex;
         triples += tot;
-        __syncthreads();
-        for (int64_t q = threadIdx.x; q < tot; q += BLOCK) {
-            int a = 0, b = cl - 1;
-            while (a < b) {
-                const int mid = (a + b + 1) >> 1;
-                if (c_off[mid] <= q) a = mid; else b = mid - 1;
+        for (int64_t w0 = 0; w0 < tot; w0 += kTrWin) {
+            const int64_t w1 = min(w0 + (int64_t)kTrWin, tot);
+            {
+                const int64_t a = max(ex, w0), b = min(ex + deg, w1);
+                for (int64_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)threadIdx.x;
             }
-            const int64_t f = c_start[a] + (q - c_off[a]);
-            const int32_t vik = val[cbase + a];
-            const int32_t vkj = va[f];
-            if ((vik & 1) != ((vkj >> 1) & 1)) continue;   // heads at k not opposite: not a walk
-            const int32_t j = ci[f];
-            int x = 0, y = L;                               // lower_bound of j in the row
-            while (x < y) {
-                const int mid = (x + y) >> 1;
-                if (col[mid] < j) x = mid + 1; else y = mid;
+            __syncthreads();
+            for (int64_t q0 = w0 + threadIdx.x; q0 < w1; q0 += (int64_t)BLOCK * kTrPer) {
+                int tt[kTrPer];
+                int32_t vkj[kTrPer], jj[kTrPer];
+#pragma unroll
+                for (int u = 0; u < kTrPer; ++u) {
+                    const int64_t q = q0 + (int64_t)u * BLOCK;
+                    tt[u] = -1;
+                    if (q < w1) {
+                        const int t = tbuf[q - w0];
+                        const int64_t f = c_start[t] + (q - c_off[t]);
+                        tt[u] = t;
+                        vkj[u] = va[f];
+                        jj[u] = ci[f];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kTrPer; ++u) {
+                    if (tt[u] < 0) continue;
+                    const int32_t vik = val[cbase + tt[u]];
+                    if ((vik & 1) != ((vkj[u] >> 1) & 1)) continue;   // heads at k not opposite: not a walk
+                    const int32_t j = jj[u];
+                    int x;
+                    if (MODE == 0) {
+                        uint32_t h = tr_hash(j, hslots);
+                        for (;;) {
+                            x = s_hash[h];
+                            if (x < 0 || col[x] == j) break;
+                            h = (h + 1) & (uint32_t)(hslots - 1);
+                        }
+                        if (x < 0) continue;
+                    } else {
+                        int a = 0, b = L;                               // lower_bound of j in the row
+                        while (a < b) {
+                            const int mid = (a + b) >> 1;
+                            if (col[mid] < j) a = mid + 1; else b = mid;
+                        }
+                        if (a >= L || col[a] != j) continue;
+                        x = a;
+                    }
+                    const uint32_t key = ((uint32_t)((vik >> 2) + (vkj[u] >> 2)) << 2) | (uint32_t)(vik & 2) |
+                                         (uint32_t)(vkj[u] & 1);
+                    if (variant_b && (key & 3u) != (uint32_t)(val[x] & 3)) continue;
+                    atomicMin(&N[x], key);
+                }
             }
-            if (x >= L || col[x] != j) continue;
-            const uint32_t key = ((uint32_t)((vik >> 2) + (vkj >> 2)) << 2) | (uint32_t)(vik & 2) |
-                                 (uint32_t)(vkj & 1);
-            if (variant_b && (key & 3u) != (uint32_t)(val[x] & 3)) continue;
-            atomicMin(&N[x], key);
+            __syncthreads();
         }
-        __syncthreads();
+        if (tot == 0) __syncthreads();   // c_start/c_off are rewritten by the next chunk
     }
     const bool edge_rule = flags & DIBELLA_TR_RULE_EDGE;
     int32_t kept = 0;
@@ -310,6 +370,9 @@ __global__ __launch_bounds__(BLOCK) void k_tr_mark(
     int32_t* s_col = reinterpret_cast<int32_t*>(c_off + BLOCK);
     int32_t* s_val = s_col + (MODE == 0 ? cap : 0);
     uint32_t* s_N = reinterpret_cast<uint32_t*>(s_val + (MODE == 0 ? cap : 0));
+    const int hslots = MODE == 0 ? tr_hash_slots(cap) : 0;
+    int32_t* s_hash = reinterpret_cast<int32_t*>(s_N + (MODE == 0 ? cap : 0));
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(s_hash + hslots);
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int64_t s_red64;
     __shared__ int32_t s_red32;
@@ -323,8 +386,8 @@ __global__ __launch_bounds__(BLOCK) void k_tr_mark(
         int rs;
         int64_t rd, rt;
         tr_row<BLOCK, MODE>(sets, nsets, set_base, rows[w], rp, ci, va, keep, keepcnt, nbuf, active,
-                            deleted, state, flags, s_col, s_val, s_N, c_start, c_off, s_tmp, &s_red64,
-                            &s_red32, &rs, &rd, &rt);
+                            deleted, state, flags, s_col, s_val, s_N, s_hash, hslots, c_start, c_off, tbuf,
+                            s_tmp, &s_red64, &s_red32, &rs, &rd, &rt);
         if (threadIdx.x == 0) {
             if (rs != cur_set) {
                 if (acc_del) atomic_add(&deleted[cur_set], acc_del);
@@ -473,7 +536,7 @@ static int allow_lds() {
     static bool done = false;
     if (!done) {
         DB_HIP(hipFuncSetAttribute((const void*)k_tr_mark<BLOCK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   150 * 1024));
+                                   (int)kTrLdsLimit));
         done = true;
     }
     return DIBELLA_OK;
@@ -491,9 +554,9 @@ static int prepare_pass_kernels() {
 
 template <int BLOCK>
 static int launch_pass_marks(const TrBuffers& B, int src, hipStream_t st) {
-    const size_t lds_small = (size_t)BLOCK * 16 + (size_t)kSmallCap * 12;
-    const size_t lds_mid = (size_t)BLOCK * 16 + (size_t)B.mid_cap * 12;
-    const size_t lds_big = (size_t)BLOCK * 16;
+    const size_t lds_small = tr_mark_lds(BLOCK, kSmallCap);
+    const size_t lds_mid = tr_mark_lds(BLOCK, B.mid_cap);
+    const size_t lds_big = tr_mark_lds(BLOCK, 0);
     int tok = -1;
     DB_TRY(timing_begin(kPhTrMark, st, &tok));
     if (B.grid[0] > 0)
@@ -631,6 +694,14 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
     int32_t* d_flags;
     int64_t* ent_base;
     uint8_t* rowok;
+    {   // one reservation for the call's workspace (allocator calls cost host time each)
+        auto pad = [](size_t b) { return Arena::padded(b); };
+        size_t est = pad(sizeof(TrSet) * nsets) + 8 * pad(8 * (nsets + 1)) + pad(sizeof(TrState));
+        est += pad(8 * total_rows) + pad(total_rows) + pad(12 * total_rows) + 2 * pad(8 * (total_rows + 1));
+        est += 4 * pad(4 * total_nnz) + pad(total_nnz) + pad(4 * total_nnz);
+        est += 4 * pad(8 * scan_workspace_elems(total_rows + 1)) + 4096;
+        DB_TRY(ar.reserve(est));
+    }
     DB_TRY(ar.work_n(nsets, &d_sets));
     DB_TRY(ar.work_n(nsets + 1, &d_base));
     DB_TRY(ar.work_n(nsets, &d_flags));
@@ -656,7 +727,9 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
     B.nsets = nsets;
     B.total_rows = total_rows;
     B.flags = flags;
+    // rows up to mid_cap are kept in LDS; the cap shrinks until the launch fits
     B.mid_cap = std::max(tn.tr_lds_cap, kSmallCap);
+    while (B.mid_cap > kSmallCap && tr_mark_lds(tn.tr_block, B.mid_cap) > kTrLdsLimit) B.mid_cap -= 512;
 
     HostStage& hst = host_stage();
     const size_t desc_bytes = sizeof(TrSet) * nsets + sizeof(int64_t) * (nsets + 1);
