@@ -259,7 +259,7 @@ __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64
 
 // ---------------------------------------------------------------------------
 // Step 2: group the pairs by column with a two-pass bucketed counting sort
-// (at most kMaxBuckets buckets of 2^low columns, low <= 15):
+// (at most kMaxBuckets buckets of 2^low columns, low <= kMaxLow):
 //   k_ov_part_count   per workgroup (one or more chunks of kChunk pairs), a
 //                     bucket histogram (bucket = key >> low), stored
 //                     bucket-major;
@@ -267,8 +267,9 @@ __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64
 //   k_ov_part_scatter per chunk, the pairs are ordered by bucket in LDS and
 //                     written out as runs, so that stores coalesce;
 //   k_ov_bucket_sort  one workgroup per bucket counts its pairs per column in
-//                     LDS (2^low bins), scans the counts into the row
-//                     pointers of A^T and places each (read, position).
+//                     LDS (2^low bins, in sweeps of 2^15 for wider buckets),
+//                     scans the counts into the row pointers of A^T and
+//                     places each (read, position).
 // The order inside an A^T row is left free: nothing downstream depends on it.
 // Every pass takes the same chunks, so a malformed A (reported after the
 // first synchronisation) can only over-count: writes are clamped to `cap`.
@@ -278,6 +279,8 @@ constexpr int kPartIlp = 8;
 constexpr int kChunk = kPartBlock * kPartIlp;
 constexpr int kBucketBlock = 1024;
 constexpr int64_t kMaxBuckets = 3840;
+constexpr int kBucketBits = 15;   // LDS histogram of a pass-2 workgroup: 2^15 columns (128 KB)
+constexpr int kMaxLow = 17;       // widest bucket: 4 sweeps of 2^15 columns
 
 inline size_t part_scatter_lds(int64_t nbuckets) {
     return (size_t)kChunk * 12 + (size_t)nbuckets * 16;
@@ -380,6 +383,7 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
     }
 }
 
+template <bool SWEEPS>
 __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
     const int64_t* __restrict__ offsets, int64_t nchunks, int low, int64_t total_m, int64_t cap,
     const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint32_t* __restrict__ t_rowptr,
@@ -390,59 +394,74 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
     __shared__ int64_t s_tmp[kBucketBlock / kWave + 1];
     const int b = blockIdx.x;
-    const int bins = 1 << low;
+    // a bucket wider than the LDS histogram (2^kBucketBits bins) is sorted
+    // in sweeps over its pairs, one range of 2^kBucketBits columns each
+    const int sub = SWEEPS ? kBucketBits : low;
+    const int sweeps = SWEEPS ? 1 << (low - sub) : 1;
+    const int bins = 1 << sub;
+    const uint32_t lmask = (uint32_t)(1u << low) - 1u, smask = (uint32_t)bins - 1u;
     const int64_t bs = min(offsets[(int64_t)b * nchunks], cap);
     const int64_t be = min(offsets[(int64_t)(b + 1) * nchunks], cap);
-    for (int c = threadIdx.x; c < bins; c += kBucketBlock) hist[c] = 0u;
-    __syncthreads();
-    const uint32_t mask = (uint32_t)bins - 1u;
-    for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
-        uint32_t kk[kPartIlp];
-#pragma unroll
-        for (int q = 0; q < kPartIlp; ++q)
-            kk[q] = skey[min(e0 + q * kBucketBlock + threadIdx.x, be - 1)];   // clamped: no branch
-#pragma unroll
-        for (int q = 0; q < kPartIlp; ++q)
-            atomicAdd(&hist[kk[q] & mask], e0 + q * kBucketBlock + threadIdx.x < be ? 1u : 0u);
-    }
-    __syncthreads();
-    // exclusive scan of the bins: each thread owns `per` consecutive bins
+    const int64_t col_b = (int64_t)b << low;
     const int per = bins >= kBucketBlock ? bins / kBucketBlock : 1;
     const int c0 = threadIdx.x * per;
-    int64_t local = 0;
-    for (int q = 0; q < per; ++q)
-        if (c0 + q < bins) local += hist[c0 + q];
-    int64_t tot;
-    int64_t run = block_exclusive_sum<kBucketBlock>(local, s_tmp, &tot);
-    const int64_t col0 = (int64_t)b << low;
-    for (int q = 0; q < per; ++q) {
-        const int c = c0 + q;
-        if (c >= bins) break;
-        const uint32_t h = hist[c];
-        const int64_t start = bs + run;
-        if (col0 + c < total_m) t_rowptr[col0 + c] = (uint32_t)start;
-        hist[c] = (uint32_t)start;   // becomes the cursor of column c
-        run += h;
+    int64_t base = bs;   // first slot of this sweep's columns
+    for (int h = 0; h < sweeps; ++h) {
+        for (int c = threadIdx.x; c < bins; c += kBucketBlock) hist[c] = 0u;
+        __syncthreads();
+        for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
+            uint32_t kk[kPartIlp];
+#pragma unroll
+            for (int q = 0; q < kPartIlp; ++q)
+                kk[q] = skey[min(e0 + q * kBucketBlock + threadIdx.x, be - 1)] & lmask;   // clamped: no branch
+#pragma unroll
+            for (int q = 0; q < kPartIlp; ++q)
+                atomicAdd(&hist[kk[q] & smask],
+                          (e0 + q * kBucketBlock + threadIdx.x < be && (!SWEEPS || (int)(kk[q] >> sub) == h))
+                              ? 1u : 0u);
+        }
+        __syncthreads();
+        // exclusive scan of the bins: each thread owns `per` consecutive bins
+        int64_t local = 0;
+        for (int q = 0; q < per; ++q)
+            if (c0 + q < bins) local += hist[c0 + q];
+        int64_t tot;
+        int64_t run = block_exclusive_sum<kBucketBlock>(local, s_tmp, &tot);
+        const int64_t col0 = col_b + ((int64_t)h << sub);
+        for (int q = 0; q < per; ++q) {
+            const int c = c0 + q;
+            if (c >= bins) break;
+            const uint32_t n_c = hist[c];
+            const int64_t start = base + run;
+            if (col0 + c < total_m) t_rowptr[col0 + c] = (uint32_t)start;
+            hist[c] = (uint32_t)start;   // becomes the cursor of column c
+            run += n_c;
+        }
+        __syncthreads();
+        for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
+            uint32_t kk[kPartIlp], pos[kPartIlp];
+            uint64_t pp[kPartIlp];
+#pragma unroll
+            for (int q = 0; q < kPartIlp; ++q) {
+                const int64_t e = min(e0 + q * kBucketBlock + threadIdx.x, be - 1);   // clamped: no branch
+                kk[q] = skey[e] & lmask;
+                pp[q] = !SWEEPS || (int)(kk[q] >> sub) == h ? spay[e] : 0ull;
+            }
+            bool mine[kPartIlp];
+#pragma unroll
+            for (int q = 0; q < kPartIlp; ++q) {
+                mine[q] = e0 + q * kBucketBlock + threadIdx.x < be && (!SWEEPS || (int)(kk[q] >> sub) == h);
+                pos[q] = atomicAdd(&hist[kk[q] & smask], mine[q] ? 1u : 0u);
+            }
+#pragma unroll
+            for (int q = 0; q < kPartIlp; ++q)
+                if (mine[q] && pos[q] < cap) at[pos[q]] = pp[q];
+        }
+        base += tot;
+        __syncthreads();
     }
     // the last bucket also closes A^T
-    if (col0 + bins >= total_m && threadIdx.x == 0) t_rowptr[total_m] = (uint32_t)total_valid;
-    __syncthreads();
-    for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
-        uint32_t kk[kPartIlp], pos[kPartIlp];
-        uint64_t pp[kPartIlp];
-#pragma unroll
-        for (int q = 0; q < kPartIlp; ++q) {
-            const int64_t e = min(e0 + q * kBucketBlock + threadIdx.x, be - 1);   // clamped: no branch
-            kk[q] = skey[e];
-            pp[q] = spay[e];
-        }
-#pragma unroll
-        for (int q = 0; q < kPartIlp; ++q)
-            pos[q] = atomicAdd(&hist[kk[q] & mask], e0 + q * kBucketBlock + threadIdx.x < be ? 1u : 0u);
-#pragma unroll
-        for (int q = 0; q < kPartIlp; ++q)
-            if (e0 + q * kBucketBlock + threadIdx.x < be && pos[q] < cap) at[pos[q]] = pp[q];
-    }
+    if (col_b + ((int64_t)1 << low) >= total_m && threadIdx.x == 0) t_rowptr[total_m] = (uint32_t)total_valid;
 }
 
 // ---------------------------------------------------------------------------
@@ -1476,7 +1495,9 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     // 2^14 columns per bucket keeps two pass-2 workgroups per CU; 2^15 when
     // the bucket count would not fit the partition's LDS
     int low = std::min(14, std::max(10, col_bits - 8));
-    if (ceil_div(total_m, int64_t(1) << low) > kMaxBuckets) low = 15;
+    // wider buckets when the count would not fit the partition's LDS (pass 2
+    // sorts buckets wider than 2^15 columns in sweeps)
+    while (low < kMaxLow && ceil_div(total_m, int64_t(1) << low) > kMaxBuckets) ++low;
     const int64_t nbuckets = ceil_div(total_m, int64_t(1) << low);
     const int64_t nchunks = ceil_div(total_nnz, kChunk);
     // bucketed path: bucket cursors fit beside the staging in LDS and entries
@@ -1582,8 +1603,10 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         if (!lds_ok) {
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
             lds_ok = true;
         }
         DB_TRY(timing_begin(kPhPartScatter, st, &tok));
@@ -1594,8 +1617,14 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         DB_TRY(timing_end(tok, st));
         // A^T pairs land in pays_a, free once the partition has read it
         DB_TRY(timing_begin(kPhBucketSort, st, &tok));
-        hipLaunchKernelGGL(k_ov_bucket_sort, dim3((unsigned)nbuckets), dim3(kBucketBlock), (size_t)4 << low, st,
-                           poffs, npart, low, total_m, total_nnz, keys_b, pays_b, t_rowptr, pays_a);
+        if (low > kBucketBits)
+            hipLaunchKernelGGL(k_ov_bucket_sort<true>, dim3((unsigned)nbuckets), dim3(kBucketBlock),
+                               (size_t)4 << kBucketBits, st, poffs, npart, low, total_m, total_nnz, keys_b, pays_b,
+                               t_rowptr, pays_a);
+        else
+            hipLaunchKernelGGL(k_ov_bucket_sort<false>, dim3((unsigned)nbuckets), dim3(kBucketBlock),
+                               (size_t)4 << low, st, poffs, npart, low, total_m, total_nnz, keys_b, pays_b,
+                               t_rowptr, pays_a);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         at = reinterpret_cast<const int2*>(pays_a);

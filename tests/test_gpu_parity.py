@@ -92,10 +92,14 @@ def test_overlap_random(lib, seed, n, m, density, ms, bits):
     assert_overlap_equal(C, oracle.overlap(A, ms), f"random{seed}")
 
 
-def test_overlap_many_columns_radix_transpose(lib):
-    """More than 2^27 columns: the transpose falls back to the radix sort."""
+@pytest.mark.parametrize("m", [pytest.param((1 << 27) + 17, id="two-sweep-buckets"),
+                               pytest.param(3840 * (1 << 17) + 5, id="radix")])
+def test_overlap_very_wide_transpose(lib, m):
+    """Very wide A: 2^27 + 17 columns give pass-2 buckets of 2^16 columns
+    sorted in two sweeps; just over 3840 * 2^17 columns the transpose takes
+    the radix sort."""
     rng = np.random.default_rng(21)
-    n, m = 400, (1 << 27) + 17
+    n = 400
     rows, cols = [], []
     shared = rng.choice(m, 300, replace=False)   # k-mers that several reads share
     for i in range(n):
@@ -104,7 +108,7 @@ def test_overlap_many_columns_radix_transpose(lib):
     rows, cols = np.concatenate(rows), np.concatenate(cols).astype(np.int32)
     vals = rng.integers(0, 10000, rows.size).astype(np.int32)
     A = synth.coo_to_csr(n, m, rows, cols, vals)
-    assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "radix transpose")
+    assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), f"wide transpose m={m}")
 
 
 def test_overlap_many_short_rows(lib):

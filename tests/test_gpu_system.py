@@ -1,4 +1,6 @@
 """GPU system tests: the mid-size workload against the oracle at full size,
+the large workload at full size against the oracle on sampled rows of C and
+on the whole reduction,
 the serving loop (each job's result in the mix equals its solo result,
 tolerance 0), the autotuner (tuned configurations reproduce the default
 bits), and batched graph-captured reductions."""
@@ -38,6 +40,44 @@ def test_mid_workload_full_parity(db):
     assert _eq(C.count, ref.count) and _eq(C.seed, ref.seed)
     print("  oracle reduction ...", flush=True)
     Sref, it_ref, _ = oracle.transitive_reduce(w.R, w.fuzz)
+    assert it == it_ref
+    assert _eq(S.rowptr, Sref.rowptr) and _eq(S.col, Sref.col) and _eq(S.val, Sref.val)
+
+
+@pytest.mark.timeout(900)
+def test_large_workload_sampled_parity(db):
+    """One GPU's share of the large run at full size: the GPU computes all of
+    C and the reduction to its fixed point; the oracle recomputes a sample of
+    C's rows (random rows, the longest rows, the first and last) and the whole
+    reduction."""
+    print("large workload: generating (k-mer counting on the GPU)", flush=True)
+    w = synth.make_workload("large", device="cuda:0")
+    A, R = w.A, w.R
+    print(f"  reads {A.nrows} kmers {A.ncols} nnz(A) {A.nnz} nnz(R) {R.nnz}", flush=True)
+    C = db.overlap(db.CSRTensors.from_numpy(A, "cuda:0"), w.min_shared)
+    st = db.last_stats()
+    print(f"  GPU overlap: nnz(C) {C.nnz}, products {st['products']}", flush=True)
+    S, it = db.transitive_reduce(db.CSRTensors.from_numpy(R, "cuda:0"), w.fuzz)
+    torch.cuda.synchronize()
+    print(f"  GPU reduction: nnz(S) {S.nnz}, passes {it}", flush=True)
+    assert st["products"] == synth.overlap_products(A)
+    rng = np.random.default_rng(31)
+    lens = np.diff(A.rowptr)
+    rows = np.unique(np.concatenate([rng.choice(A.nrows, 300, replace=False), np.argsort(lens)[-8:],
+                                     [0, A.nrows - 1]])).astype(np.int64)
+    print(f"  oracle overlap on {rows.size} rows ...", flush=True)
+    ref = oracle.overlap(A, w.min_shared, rows=rows)
+    rp = C.rowptr.cpu().numpy()
+    col, cnt, seed = C.col.cpu().numpy(), C.count.cpu().numpy(), C.seed.cpu().numpy().reshape(-1, 4)
+    for q, i in enumerate(rows):
+        a, b = rp[i], rp[i + 1]
+        x, y = ref.rowptr[q], ref.rowptr[q + 1]
+        assert b - a == y - x, f"row {i}: {b - a} entries vs {y - x}"
+        assert np.array_equal(col[a:b], ref.col[x:y]), f"row {i} col"
+        assert np.array_equal(cnt[a:b], ref.count[x:y]), f"row {i} count"
+        assert np.array_equal(seed[a:b], ref.seed[x:y]), f"row {i} seed"
+    print("  oracle reduction ...", flush=True)
+    Sref, it_ref, _ = oracle.transitive_reduce(R, w.fuzz)
     assert it == it_ref
     assert _eq(S.rowptr, Sref.rowptr) and _eq(S.col, Sref.col) and _eq(S.val, Sref.val)
 
