@@ -17,6 +17,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dibella_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# A separately built oracle library to load instead (the tests that plant
+# mistakes in a copy of the oracle source point this at the planted build).
+_LIB_OVERRIDE = os.environ.get("DIBELLA_ORACLE_LIB")
 
 VARIANT_B = 0x1
 RULE_EDGE = 0x2
@@ -37,9 +40,12 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        if _LIB_OVERRIDE:
+            lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB_PATH):
+                build()
+            lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         i64, i32, u32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
         lib.oracle_overlap_rows.argtypes = [i64, i64, P, P, P, i32, P, i64, P,

@@ -227,6 +227,23 @@ def test_worked_example_end_heads_must_match():
     assert _s_dense(S)[2, 0] == 80
 
 
+@pytest.mark.parametrize("rule", ["row", "edge"])
+def test_comparison_is_inclusive_at_equality(rule):
+    # Triangle 0 -> 1 -> 2 with the chord 0 -> 2 (uniform orientation).  The
+    # walk's overhang sum is a + b.  I = M >= N (Alg. TransitiveReduction):
+    # the chord goes when a + b equals M exactly and stays when it is one
+    # above.  M_02 = max overhang of row 0 + x (row rule) or R_02 + x (edge
+    # rule).
+    a, c, x = 300, 500, 1000
+    M = (max(a, c) if rule == "row" else c) + x
+    for b, gone in ((M - a, True), (M - a + 1, False)):
+        R = _dense_to_r([[0, a, c], [0, 0, b], [0, 0, 0]])
+        S, _, _ = oracle.transitive_reduce(R, x, "A", rule)
+        assert (_s_dense(S)[0, 2] == 0) == gone, (rule, b)
+        marks = oracle.tr_pass_marks(R, x, "A", rule)
+        assert bool(marks[1]) == gone     # row 0 holds (0,1) then (0,2)
+
+
 def _dense_from_bf(D, n):
     out = np.zeros((n, n), np.int64) - 1
     for i in range(n):

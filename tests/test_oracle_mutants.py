@@ -1,0 +1,101 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle source (a dropped term,
+a wrong comparison, a swapped operand, a wrong index or order), builds it,
+and runs the oracle pin suite (tests/test_oracle.py) against it in a child
+process: the suite must fail.  The unedited source, built the same way, must
+pass.  Everything here runs on the CPU.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dibella_oracle.c")
+
+# (id, text in the oracle source, replacement); the first occurrence is edited
+MUTANTS = [
+    # overlap: add (count, seeds) and the order of k
+    ("seed-keeps-one", "if (c < 2) {", "if (c < 1) {"),
+    ("seed-pair-swapped", "seeds[4 * j + 2 * c + 0] = val[e];\n                    seeds[4 * j + 2 * c + 1] = t_pos[f];",
+     "seeds[4 * j + 2 * c + 0] = t_pos[f];\n                    seeds[4 * j + 2 * c + 1] = val[e];"),
+    ("min-shared-strict", "if (count[j] >= min_shared) {", "if (count[j] > min_shared) {"),
+    ("diagonal-dropped", "int32_t j = t_read[f];\n                if (count[j] == 0) {",
+     "int32_t j = t_read[f];\n                if (j == (int32_t)i) continue;\n                if (count[j] == 0) {"),
+    ("k-walked-descending", "for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {\n            int32_t k = col[e];\n            for (int64_t f = t_rowptr[k];",
+     "for (int64_t e = rowptr[i + 1] - 1; e >= rowptr[i]; --e) {\n            int32_t k = col[e];\n            for (int64_t f = t_rowptr[k];"),
+    ("count-double", "int32_t c = count[j]++;", "int32_t c = count[j]; count[j] += 2;"),
+    # reduction: the MinPlus semiring
+    ("walk-check-inverted", "if (dst_of(r_ik) != src_of(r_kj)) return INF_KEY;", "if (dst_of(r_ik) == src_of(r_kj)) return INF_KEY;"),
+    ("walk-check-wrong-heads", "if (dst_of(r_ik) != src_of(r_kj)) return INF_KEY;", "if (src_of(r_ik) != dst_of(r_kj)) return INF_KEY;"),
+    ("sum-drops-term", "uint32_t sum = (uint32_t)(oh_of(r_ik) + oh_of(r_kj));", "uint32_t sum = (uint32_t)(oh_of(r_kj));"),
+    ("end-code-swapped", "return (sum << 2) | (uint32_t)(src_of(r_ik) << 1) | (uint32_t)dst_of(r_kj);",
+     "return (sum << 2) | (uint32_t)(dst_of(r_kj) << 1) | (uint32_t)src_of(r_ik);"),
+    ("add-is-max", "static uint32_t minplus_add(uint32_t a, uint32_t b) { return a < b ? a : b; }",
+     "static uint32_t minplus_add(uint32_t a, uint32_t b) { return (a == INF_KEY) ? b : (b == INF_KEY ? a : (a > b ? a : b)); }"),
+    # reduction: v, M, I and the loop
+    ("row-max-is-first", "if (oh_of(va[e]) > v[i]) v[i] = oh_of(va[e]);", "if (v[i] == 0) v[i] = oh_of(va[e]);"),
+    ("fuzz-not-added", "if (v[i] != 0) v[i] += fuzz;", "if (v[i] != 0) v[i] += 0;"),
+    ("edge-rule-no-fuzz", "(int64_t)oh_of(va[e]) + fuzz : (int64_t)v[i];", "(int64_t)oh_of(va[e]) : (int64_t)v[i];"),
+    ("compare-strict", "(int64_t)(nij >> 2) <= mij;", "(int64_t)(nij >> 2) < mij;"),
+    ("end-check-dropped", "int transitive = nij != INF_KEY && (int32_t)(nij & 3u) == code_of(va[e]) &&",
+     "int transitive = nij != INF_KEY &&"),
+    ("contained-kept", "if (oh_of(val[e]) > 0) { ci[nnz] = col[e];", "if (oh_of(val[e]) >= 0) { ci[nnz] = col[e];"),
+    ("one-pass-only", "} while (nnz != prev);", "} while (0);"),
+    ("variant-b-inverted", "(rcode[j] < 0 || (int32_t)(key & 3u) != rcode[j])", "(rcode[j] < 0 || (int32_t)(key & 3u) == rcode[j])"),
+    # one-pass marks used for sampled checks
+    ("marks-compare-strict", "(int64_t)(nij >> 2) <= mij);", "(int64_t)(nij >> 2) < mij);"),
+    ("marks-row-max-unset", "if (vi != 0) vi += fuzz;", "if (vi != 0) vi += fuzz + 1;"),
+]
+
+
+def _build(text, out_dir, name):
+    c = os.path.join(out_dir, name + ".c")
+    so = os.path.join(out_dir, name + ".so")
+    with open(c, "w") as f:
+        f.write(text)
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", so, c])
+    return so
+
+
+def _run_pins(so):
+    # one thread per child: the children run side by side
+    env = dict(os.environ, DIBELLA_ORACLE_LIB=so, PYTHONDONTWRITEBYTECODE="1", OMP_NUM_THREADS="1",
+               MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join("tests", "test_oracle.py"), "-x", "-q",
+                        "-p", "no:cacheprovider", "-m", "not gpu"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout[-3000:] + r.stderr[-2000:]
+
+
+@pytest.fixture(scope="module")
+def outcomes(tmp_path_factory):
+    """Build the control and every planted copy, then run the pin suite
+    against each of them, several child processes at a time."""
+    from concurrent.futures import ThreadPoolExecutor
+    with open(SRC) as f:
+        text = f.read()
+    d = str(tmp_path_factory.mktemp("oracle_mutants"))
+    jobs = {"control": text}
+    for mid, old, new in MUTANTS:
+        jobs[mid] = text.replace(old, new, 1) if old in text else None
+    libs = {mid: (_build(src, d, mid) if src is not None else None) for mid, src in jobs.items()}
+    workers = max(1, min(8, (os.cpu_count() or 2) // 2))
+    with ThreadPoolExecutor(workers) as ex:
+        futs = {mid: ex.submit(_run_pins, so) for mid, so in libs.items() if so}
+        return {mid: f.result() for mid, f in futs.items()}
+
+
+def test_unedited_oracle_passes_the_pins(outcomes):
+    rc, out = outcomes["control"]
+    assert rc == 0, out
+
+
+@pytest.mark.parametrize("mid,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(outcomes, mid, old, new):
+    assert mid in outcomes, f"{mid}: the text to edit is not in the oracle source"
+    rc, out = outcomes[mid]
+    # a failing assertion, not a crash or a collection error
+    assert rc == 1 and " failed" in out, f"{mid}: the pins did not catch it (rc {rc})\n{out}"
