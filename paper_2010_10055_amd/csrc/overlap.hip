@@ -136,9 +136,9 @@ __device__ __forceinline__ int table_find(const int32_t* keys, uint32_t T, int32
 // Count one more occurrence of j in a table of u64 slots (j << 32) | count:
 // insertion is a 64-bit CAS, the count a 64-bit add.  Returns the slot or -1
 // (table full); *fresh = 1 if this call created the entry.
-__device__ __forceinline__ int table64_add(uint64_t* tab, uint32_t T, int32_t j, int* fresh) {
+__device__ __forceinline__ int table64_add(uint64_t* tab, uint32_t T, int32_t j, int* fresh, uint32_t amount = 1) {
     uint32_t h = hash_slot(j, T);
-    const uint64_t mine = ((uint64_t)(uint32_t)j << 32) | 1ull;
+    const uint64_t mine = ((uint64_t)(uint32_t)j << 32) | amount;
     *fresh = 0;
     for (uint32_t p = 0; p < T; ++p) {
         uint64_t v = tab[h];
@@ -150,7 +150,7 @@ __device__ __forceinline__ int table64_add(uint64_t* tab, uint32_t T, int32_t j,
             }
         }
         if ((int32_t)(v >> 32) == j) {
-            atomicAdd(&tab[h], 1ull);
+            atomicAdd(&tab[h], (uint64_t)amount);
             return (int)h;
         }
         if (++h == T) h = 0;
@@ -568,54 +568,102 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
 
 // ---------------------------------------------------------------------------
 // Shared product walk: the A entries t of row i are taken in chunks of
-// BLOCK; seg[t] gives the A^T segment (start, length) of entry t, and the
-// products of the chunk are numbered t-major.  Products are handed out in
-// windows of kWalkWin: every thread first writes its entry's index
-// over its products' slots of the window (an LDS expansion, so that a
-// product finds its t with one LDS read), then each thread takes kPer
-// products per step and issues all their gathers of A^T pairs before
-// handing them to f(t, (j, p_j), q), so that kPer independent loads are in
-// flight.  The block must call it uniformly.  `stop` (LDS flag) abandons
-// the walk.  LDS: c_start, c_off (BLOCK int64 each), tbuf (kWalkWin u16),
-// carved from the front of the dynamic LDS by walk_lds().
+// walk_chunk_of(BLOCK) entries (one per thread); seg[t] gives the A^T
+// segment (start, length) of entry t, and the products of the chunk are
+// numbered t-major.  Products are handed out in windows of
+// walk_win_of(BLOCK): every thread first writes its entry's chunk index over
+// its products' slots of the window (an LDS expansion, so that a product
+// finds its entry with one LDS read), then each thread takes walk_per(BLOCK)
+// products and issues all their gathers of A^T pairs before handing them to
+// f(t, (j, p_j), q), so that several independent loads are in flight per
+// thread.  The block must call it uniformly.  `stop` (LDS flag) abandons
+// the walk.  LDS: c_start, c_off (one int64 per chunk entry each) and tbuf
+// (one u16 per window product), carved from the front of the dynamic LDS by
+// walk_lds().  (Larger chunks and windows, 16 products per thread in
+// flight, measured no faster: the walks are bound by the number of distinct
+// cache lines they touch, and the larger area costs occupancy.)
 // ---------------------------------------------------------------------------
-constexpr int kPer = 4;
+__host__ __device__ constexpr int walk_chunk_of(int block) { return block; }
+__host__ __device__ constexpr int walk_win_of(int) { return 2048; }
+__host__ __device__ constexpr size_t walk_lds(int block) {
+    return (size_t)walk_chunk_of(block) * 16 + (size_t)walk_win_of(block) * 2;
+}
+__host__ __device__ constexpr int walk_per(int) { return 4; }
+// the ESC expansion's static walk area
+constexpr int kWalkChunk = 256;
 constexpr int kWalkWin = 2048;
 
-__host__ __device__ constexpr size_t walk_lds(int block) { return (size_t)block * 16 + (size_t)kWalkWin * 2; }
+// Loads the chunk's segments, numbers its products (t-major) and returns
+// the chunk's product count.  Each thread keeps its entries' offsets and
+// lengths for the window fills.
+template <int BLOCK, bool START>
+__device__ __forceinline__ int64_t walk_chunk(const uint64_t* __restrict__ rseg, int cbase, int cl,
+                                              int64_t* c_start, int64_t* c_off, int64_t* s_tmp,
+                                              int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
+                                              int64_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
+    constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
+    int64_t st[E], local = 0;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        const int e = (int)threadIdx.x * E + u;
+        my_len[u] = 0;
+        st[u] = 0;
+        if (e < cl) {
+            const uint64_t sg = rseg[cbase + e];
+            st[u] = (int64_t)(sg >> 24);
+            my_len[u] = (int64_t)(sg & 0xFFFFFFull);
+        }
+        local += my_len[u];
+    }
+    int64_t tot;
+    int64_t run = block_exclusive_sum<BLOCK>(local, s_tmp, &tot);
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        const int e = (int)threadIdx.x * E + u;
+        if (START) c_start[e] = st[u];
+        c_off[e] = run;
+        my_off[u] = run;
+        run += my_len[u];
+    }
+    return tot;
+}
+
+// Writes the chunk index of every product of the window [w0, w1).
+template <int BLOCK>
+__device__ __forceinline__ void walk_fill(uint16_t* tbuf, int64_t w0, int64_t w1,
+                                          const int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
+                                          const int64_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
+    constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        const int64_t a = max(my_off[u], w0), b = min(my_off[u] + my_len[u], w1);
+        for (int64_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)((int)threadIdx.x * E + u);
+    }
+}
 
 template <int BLOCK, class F>
 __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
                                               const int2* __restrict__ at, int64_t* c_start, int64_t* c_off,
                                               uint16_t* tbuf, int64_t* s_tmp, const int32_t* stop, F&& f) {
-    static_assert(BLOCK <= 65536, "entry index kept in 16 bits");
-    constexpr int64_t W = kWalkWin;
+    constexpr int CH = walk_chunk_of(BLOCK), WIN = walk_win_of(BLOCK);
+    static_assert(CH % BLOCK == 0 && CH <= 65536, "chunk index kept in 16 bits");
+    constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
+    constexpr int PER = walk_per(BLOCK);
     int64_t done = 0;   // products of earlier chunks
-    for (int cbase = 0; cbase < L; cbase += BLOCK) {
-        const int cl = min(BLOCK, L - cbase);
-        int64_t len = 0, st = 0;
-        if ((int)threadIdx.x < cl) {
-            const uint64_t sg = rseg[cbase + threadIdx.x];
-            st = (int64_t)(sg >> 24);
-            len = (int64_t)(sg & 0xFFFFFFull);
-        }
-        int64_t tot;
-        const int64_t ex = block_exclusive_sum<BLOCK>(len, s_tmp, &tot);
-        c_start[threadIdx.x] = st;
-        c_off[threadIdx.x] = ex;
-        for (int64_t w0 = 0; w0 < tot; w0 += W) {
-            const int64_t w1 = min(w0 + W, tot);
-            {
-                const int64_t a = max(ex, w0), b = min(ex + len, w1);
-                for (int64_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)threadIdx.x;
-            }
+    for (int cbase = 0; cbase < L; cbase += CH) {
+        const int cl = min(CH, L - cbase);
+        int64_t my_off[E], my_len[E];
+        const int64_t tot = walk_chunk<BLOCK, true>(rseg, cbase, cl, c_start, c_off, s_tmp, my_off, my_len);
+        for (int64_t w0 = 0; w0 < tot; w0 += WIN) {
+            const int64_t w1 = min(w0 + (int64_t)WIN, tot);
+            walk_fill<BLOCK>(tbuf, w0, w1, my_off, my_len);
             __syncthreads();
-            for (int64_t q0 = w0 + threadIdx.x; q0 < w1; q0 += (int64_t)BLOCK * kPer) {
+            for (int64_t q0 = w0 + threadIdx.x; q0 < w1; q0 += (int64_t)BLOCK * PER) {
                 if (stop && *(volatile const int32_t*)stop) break;
-                int tt[kPer];
-                int2 jp[kPer];
+                int tt[PER];
+                int2 jp[PER];
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) {
+                for (int u = 0; u < PER; ++u) {
                     const int64_t q = q0 + (int64_t)u * BLOCK;
                     tt[u] = -1;
                     if (q < w1) {
@@ -625,7 +673,7 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kPer; ++u)
+                for (int u = 0; u < PER; ++u)
                     if (tt[u] >= 0) f(cbase + tt[u], jp[u], done + q0 + (int64_t)u * BLOCK);
             }
             __syncthreads();
@@ -651,8 +699,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     int32_t* __restrict__ distinct, int32_t* __restrict__ qhead, int count) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
-    int64_t* c_off = c_start + BLOCK;
-    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + BLOCK);
+    int64_t* c_off = c_start + walk_chunk_of(BLOCK);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + walk_chunk_of(BLOCK));
     uint32_t* B = reinterpret_cast<uint32_t*>(smem + walk_lds(BLOCK));
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int32_t s_red, s_item;
@@ -667,8 +715,17 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     const int planes = S.min_shared;
     for (int q = threadIdx.x; q < planes * words; q += BLOCK) B[q] = 0u;
     __syncthreads();
+    // the diagonal (j = i) is a product of every entry of the row: it is
+    // left out of the walk (one LDS address hit by every segment) and set
+    // from its closed form, count = L
+    const int32_t self = (int32_t)i;
     walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
-                         [&](int, int2 jp, int64_t) { planes_mark(B, words, planes, jp.x); });
+                         [&](int, int2 jp, int64_t) {
+                             if (jp.x != self) planes_mark(B, words, planes, jp.x);
+                         });
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int p = 0; p < planes && p < L; ++p) B[p * words + (self >> 5)] |= 1u << (self & 31);
     __syncthreads();
     const uint32_t* out_plane = B + (planes - 1) * words;
     int32_t d = 0;
@@ -718,8 +775,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
     int32_t* __restrict__ qhead) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
-    int64_t* c_off = c_start + BLOCK;
-    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + BLOCK);
+    int64_t* c_off = c_start + walk_chunk_of(BLOCK);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + walk_chunk_of(BLOCK));
     uint64_t* tab = reinterpret_cast<uint64_t*>(smem + walk_lds(BLOCK));
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int32_t s_nd, s_ovf, s_item;
@@ -737,8 +794,10 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
             s_ovf = 0;
         }
         __syncthreads();
+        const int32_t self = (int32_t)i;
         walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, &s_ovf,
                              [&](int, int2 jp, int64_t) {
+                                 if (jp.x == self) return;   // the diagonal: added once below
                                  int fresh;
                                  const int slot = table64_add(tab, (uint32_t)T, jp.x, &fresh);
                                  if (slot < 0) {
@@ -747,6 +806,12 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
                                  }
                                  if (fresh && atomicAdd(&s_nd, 1) + 1 > limit) s_ovf = 1;
                              });
+        __syncthreads();
+        if (threadIdx.x == 0 && !s_ovf && L > 0) {   // the diagonal, count L
+            int fresh;
+            const int slot = table64_add(tab, (uint32_t)T, self, &fresh, (uint32_t)L);
+            if (slot < 0 || (fresh && ++s_nd > limit)) s_ovf = 1;
+        }
         __syncthreads();
         if (s_ovf) {
             if (threadIdx.x == 0) {
@@ -885,8 +950,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     const int2* __restrict__ at, const int64_t* __restrict__ G, int32_t* __restrict__ qhead, int count) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
-    int64_t* c_off = c_start + BLOCK;
-    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + BLOCK);
+    int64_t* c_off = c_start + walk_chunk_of(BLOCK);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + walk_chunk_of(BLOCK));
     uint64_t* m1 = reinterpret_cast<uint64_t*>(smem + walk_lds(BLOCK));
     uint64_t* m2 = m1 + Dmax;
     int32_t* cnt = reinterpret_cast<int32_t*>(m2 + Dmax);
@@ -939,16 +1004,19 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
         }
         __syncthreads();
     }
+    const int32_t self = (int32_t)i;   // the diagonal is written from its closed form below
     walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
                          [&](int t, int2 jp, int64_t) {
+                             const int32_t j = jp.x;
+                             if (j == self) return;
                              int r;
                              if (BITS) {
-                                 const uint32_t word = bm[jp.x >> 5];
-                                 const uint32_t bit = 1u << (jp.x & 31);
+                                 const uint32_t word = bm[j >> 5];
+                                 const uint32_t bit = 1u << (j & 31);
                                  if (!(word & bit)) return;
-                                 r = pre[jp.x >> 5] + __popc(word & (bit - 1u));
+                                 r = pre[j >> 5] + __popc(word & (bit - 1u));
                              } else {
-                                 const int slot = table_find(keys, T, jp.x);
+                                 const int slot = table_find(keys, T, j);
                                  if (slot < 0) return;
                                  r = rank[slot];
                              }
@@ -966,16 +1034,30 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     const int64_t off = G[g] - G[S.row_base];
     int4* seed4 = reinterpret_cast<int4*>(S.c_seed);
     for (int r = threadIdx.x; r < nsel; r += BLOCK) {
-        const uint64_t a = m1[r], b = m2[r];
-        const int32_t pi0 = S.a_val[lo + (int64_t)(a >> 32)];
-        const int32_t pj0 = (int32_t)(uint32_t)a;
-        int32_t pi1 = -1, pj1 = -1;
-        if (b != kEmpty64) {
-            pi1 = S.a_val[lo + (int64_t)(b >> 32)];
-            pj1 = (int32_t)(uint32_t)b;
+        const int32_t j = sel[r];
+        int32_t c, pi0, pj0, pi1 = -1, pj1 = -1;
+        if (j == self) {
+            // C_ii: every entry of the row pairs with itself; the seeds are
+            // its first two entries
+            c = L;
+            pi0 = pj0 = S.a_val[lo];
+            if (L >= 2) pi1 = pj1 = S.a_val[lo + 1];
+        } else if (m1[r] == kEmpty64) {
+            // a listed column always has a candidate; never index with the sentinel
+            c = cnt[r];
+            pi0 = pj0 = -1;
+        } else {
+            const uint64_t a = m1[r], b = m2[r];
+            c = cnt[r];
+            pi0 = S.a_val[lo + (int64_t)(a >> 32)];
+            pj0 = (int32_t)(uint32_t)a;
+            if (b != kEmpty64) {
+                pi1 = S.a_val[lo + (int64_t)(b >> 32)];
+                pj1 = (int32_t)(uint32_t)b;
+            }
         }
-        S.c_col[off + r] = sel[r];
-        S.c_count[off + r] = cnt[r];
+        S.c_col[off + r] = j;
+        S.c_count[off + r] = c;
         seed4[off + r] = make_int4(pi0, pj0, pi1, pj1);
     }
     __syncthreads();
@@ -1015,7 +1097,8 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
     const int32_t* __restrict__ list, const int64_t* __restrict__ esc_off, const uint64_t* __restrict__ seg,
     const int2* __restrict__ at, uint32_t* __restrict__ keys0, uint64_t* __restrict__ pay0) {
-    __shared__ int64_t c_start[kEscBlock], c_off[kEscBlock];
+    static_assert(walk_chunk_of(kEscBlock) == kWalkChunk && walk_win_of(kEscBlock) == kWalkWin, "walk area");
+    __shared__ int64_t c_start[kWalkChunk], c_off[kWalkChunk];
     __shared__ uint16_t tbuf[kWalkWin];
     __shared__ int64_t s_tmp[kEscBlock / kWave + 1];
     const int64_t g = list[blockIdx.x];
