@@ -703,7 +703,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + walk_chunk_of(BLOCK));
     uint32_t* B = reinterpret_cast<uint32_t*>(smem + walk_lds(BLOCK));
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
-    __shared__ int32_t s_red, s_item;
+    __shared__ int32_t s_item;
     for (int item = next_item(qhead, count, &s_item); item >= 0; item = next_item(qhead, count, &s_item)) {
     const int64_t g = list[item];
     const int s = find_set(set_base, nsets, g);
@@ -727,27 +727,28 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     if (threadIdx.x == 0)
         for (int p = 0; p < planes && p < L; ++p) B[p * words + (self >> 5)] |= 1u << (self & 31);
     __syncthreads();
+    // one block scan: each thread owns a run of consecutive words and counts
+    // the distinct columns (plane 0) in the high half and the output
+    // columns (last plane) in the low half of one 64-bit value
     const uint32_t* out_plane = B + (planes - 1) * words;
-    int32_t d = 0;
-    for (int w = threadIdx.x; w < words; w += BLOCK) d += __popc(B[w]);
-    d = block_sum_lds(d, &s_red);
+    const int per = (words + BLOCK - 1) / BLOCK;
+    const int w0 = (int)threadIdx.x * per, w1 = min(w0 + per, words);
+    int64_t both = 0;
+    for (int w = w0; w < w1; ++w) both += ((int64_t)__popc(B[w]) << 32) | (int64_t)__popc(out_plane[w]);
+    int64_t tot;
+    int64_t pos = block_exclusive_sum<BLOCK>(both, s_tmp, &tot) & 0xFFFFFFFFll;
     int32_t* out = scratch + soff[g];
-    int64_t base = 0;
-    for (int c = 0; c < words; c += BLOCK) {
-        const int w = c + threadIdx.x;
-        uint32_t bits = w < words ? out_plane[w] : 0u;
-        int64_t tot;
-        int64_t pos = base + block_exclusive_sum<BLOCK>((int64_t)__popc(bits), s_tmp, &tot);
+    for (int w = w0; w < w1; ++w) {
+        uint32_t bits = out_plane[w];
         while (bits) {
             const int b = __ffs(bits) - 1;
             out[pos++] = (w << 5) | b;
             bits &= bits - 1;
         }
-        base += tot;
     }
     if (threadIdx.x == 0) {
-        nnzrow[g] = base;
-        distinct[g] = d;
+        nnzrow[g] = tot & 0xFFFFFFFFll;
+        distinct[g] = (int32_t)(tot >> 32);
     }
     __syncthreads();
     }
@@ -947,7 +948,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
     const int32_t* __restrict__ list, int Dmax, int load_pct, const int64_t* __restrict__ nnzrow,
     const int64_t* __restrict__ soff, const int32_t* __restrict__ scratch, const uint64_t* __restrict__ seg,
-    const int2* __restrict__ at, const int64_t* __restrict__ G, int32_t* __restrict__ qhead, int count) {
+    const int2* __restrict__ at, const int64_t* __restrict__ G, int words_max, int32_t* __restrict__ qhead,
+    int count) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t* c_start = reinterpret_cast<int64_t*>(smem);
     int64_t* c_off = c_start + walk_chunk_of(BLOCK);
@@ -958,6 +960,12 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     int32_t* map = cnt + Dmax;   // BITS: bitmap (words) + prefix (words); else keys (T) + rank (T)
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int32_t s_item;
+    // BITS: the bitmap is cleared once here; each row then clears only the
+    // words of its own columns when it is done
+    if (BITS) {
+        uint32_t* bm0 = reinterpret_cast<uint32_t*>(cnt + Dmax);
+        for (int q = threadIdx.x; q < words_max; q += BLOCK) bm0[q] = 0u;
+    }
     for (int item = next_item(qhead, count, &s_item); item >= 0; item = next_item(qhead, count, &s_item)) {
     const int64_t g = list[item];
     const int s = find_set(set_base, nsets, g);
@@ -967,22 +975,22 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     const int L = (int)(S.a_rowptr[i + 1] - lo);
     const int nsel = (int)nnzrow[g];
     const int32_t* sel = scratch + soff[g];
-    const int words = S.words;
     const uint32_t T = BITS ? 0u : (uint32_t)table_slots(nsel, load_pct);
     uint32_t* bm = reinterpret_cast<uint32_t*>(map);
-    int32_t* pre = map + words;
+    int32_t* pre = map + words_max;
     int32_t* keys = map;
     int32_t* rank = map + T;
-    if (BITS) {
-        for (int q = threadIdx.x; q < words; q += BLOCK) bm[q] = 0u;
-    } else {
+    if (!BITS) {
         for (uint32_t q = threadIdx.x; q < T; q += BLOCK) keys[q] = -1;
+        __syncthreads();
     }
-    __syncthreads();
     for (int r = threadIdx.x; r < nsel; r += BLOCK) {
         const int32_t j = sel[r];
         if (BITS) {
+            // sel is sorted: the first listed column of a word has the
+            // word's smallest rank, so no scan over the words is needed
             atomicOr(&bm[j >> 5], 1u << (j & 31));
+            if (r == 0 || (sel[r - 1] >> 5) != (j >> 5)) pre[j >> 5] = r;
         } else {
             const int slot = table_insert(keys, T, j);
             if (slot >= 0) rank[slot] = r;
@@ -992,18 +1000,6 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
         m2[r] = kEmpty64;
     }
     __syncthreads();
-    if (BITS) {
-        int64_t base = 0;
-        for (int c = 0; c < words; c += BLOCK) {
-            const int w = c + threadIdx.x;
-            const int64_t v = w < words ? __popc(bm[w]) : 0;
-            int64_t tot;
-            const int64_t ex = block_exclusive_sum<BLOCK>(v, s_tmp, &tot);
-            if (w < words) pre[w] = (int32_t)(base + ex);
-            base += tot;
-        }
-        __syncthreads();
-    }
     const int32_t self = (int32_t)i;   // the diagonal is written from its closed form below
     walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
                          [&](int t, int2 jp, int64_t) {
@@ -1059,6 +1055,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
         S.c_col[off + r] = j;
         S.c_count[off + r] = c;
         seed4[off + r] = make_int4(pi0, pj0, pi1, pj1);
+        if (BITS) bm[j >> 5] = 0u;   // every read of the bitmap is done (barrier after the walk)
     }
     __syncthreads();
     }
@@ -1429,10 +1426,12 @@ static int launch_numeric(const OvWork& W, const int32_t* list, int count, int D
     int32_t* qh = &W.ctr->qhead[queue];
     if (bits)
         hipLaunchKernelGGL((k_ov_numeric<BLOCK, true>), dim3(grid), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
-                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G, qh, count);
+                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G, words, qh,
+                           count);
     else
         hipLaunchKernelGGL((k_ov_numeric<BLOCK, false>), dim3(grid), dim3(BLOCK), lds, st, W.d_sets, W.nsets,
-                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G, qh, count);
+                           W.d_base, list, D, load_pct, W.nnzrow, W.soff, W.scratch, W.seg, W.at, W.G, 0, qh,
+                           count);
     DB_HIP(hipGetLastError());
     return DIBELLA_OK;
 }
