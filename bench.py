@@ -103,15 +103,17 @@ CALIB_BYTES = 1 << 30
 
 
 def calib_copy():
-    """A plain device copy of known size (1 GiB read + 1 GiB written by one
-    elementwise kernel), the reference for scaling HBM counters."""
+    """Plain device kernels of known traffic, the references for scaling HBM
+    counters: a fill (1 GiB written), a sum (1 GiB read) and a copy (1 GiB
+    read + 1 GiB written)."""
     import torch
-    x = torch.ones(CALIB_BYTES // 4, dtype=torch.int32, device="cuda:0")
+    x = torch.ones(CALIB_BYTES // 4, dtype=torch.int32, device="cuda:0")      # fill: write only
     y = torch.empty_like(x)
     for _ in range(3):
-        torch.bitwise_or(x, 0, out=y)
+        s = x.sum()                                                           # read only
+        torch.bitwise_or(x, 0, out=y)                                         # copy
     torch.cuda.synchronize()
-    print(json.dumps({"calib_copy_bytes": CALIB_BYTES}), flush=True)
+    print(json.dumps({"calib_bytes": CALIB_BYTES, "sum": int(s)}), flush=True)
 
 
 def _csv_rows(d, suffix):
@@ -176,10 +178,16 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
         f.write("\n".join(lines) + "\n")
     cf = _counter_per_kernel(cfetch_dir, "FETCH_SIZE")
     cw = _counter_per_kernel(cwrite_dir, "WRITE_SIZE")
-    copy_fetch = max((max(v) for v in cf.values()), default=0.0) * 1024
-    copy_write = max((max(v) for v in cw.values()), default=0.0) * 1024
-    f_fetch = copy_fetch / CALIB_BYTES if copy_fetch else None
-    f_write = copy_write / CALIB_BYTES if copy_write else None
+
+    def ref(per, pattern):
+        return max((max(v) for n, v in per.items() if pattern in n), default=0.0) * 1024
+    # reads are scaled by the read-only sum, writes by the write-only fill
+    read_only, write_only = ref(cf, "reduce_kernel"), ref(cw, "FillFunctor")
+    copy_fetch, copy_write = ref(cf, "BitwiseOr"), ref(cw, "BitwiseOr")
+    f_fetch = read_only / CALIB_BYTES if read_only else None
+    f_write = write_only / CALIB_BYTES if write_only else None
+    print(f"calibration: sum FETCH {read_only / CALIB_BYTES:.3f}x, fill WRITE {write_only / CALIB_BYTES:.3f}x, "
+          f"copy FETCH {copy_fetch / CALIB_BYTES:.3f}x WRITE {copy_write / CALIB_BYTES:.3f}x")
     fetch = _counter_per_kernel(fetch_dir, "FETCH_SIZE")
     write = _counter_per_kernel(write_dir, "WRITE_SIZE")
     calls = sum(len(v) for n, v in fetch.items() if "k_ov_write_rowptr" in n)   # overlap calls profiled
@@ -193,7 +201,8 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
         d = {"kernel": kname, "workload": workload, "command": command,
              "source_hash": source_hash(*KERNEL_SOURCES[label]),
              "fetch_KiB_per_dispatch_raw": statistics.mean(fv), "write_KiB_per_dispatch_raw": statistics.mean(wv),
-             "dispatches": len(fv), "copy_fetch_factor": f_fetch, "copy_write_factor": f_write,
+             "dispatches": len(fv), "read_calibration_factor": f_fetch, "write_calibration_factor": f_write,
+             "copy_fetch_factor": copy_fetch / CALIB_BYTES, "copy_write_factor": copy_write / CALIB_BYTES,
              "hbm_bytes_per_launch": fb + wb, "hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb}
         if label == "numeric" and calls:
             # all launches of the phase of one call

@@ -17,7 +17,7 @@ void set_error(const std::string& msg) { error_slot() = msg; }
 
 dibella_tuning& tuning() {
     static dibella_tuning t = {
-        /*sym_block*/ 256, /*num_block*/ 256, /*tr_block*/ 256,
+        /*sym_block*/ 256, /*num_block*/ 256, /*tr_block*/ 128,
         /*sym_first_log2*/ 12, /*sym_max_log2*/ 14, /*num_max_entries*/ 5120,
         /*load_pct*/ 75, /*tr_lds_cap*/ 4096, /*tr_graph_passes*/ 4,
         /*bits_max_words*/ 8192};
