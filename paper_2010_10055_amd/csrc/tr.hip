@@ -818,11 +818,13 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
                 }
             }
         } else {
-            int src = 0;
+            // two passes per host synchronisation: a pass after convergence
+            // returns at once (every pass kernel checks the active flag),
+            // and a reduction that converges in two passes syncs once
             while (true) {
-                DB_TRY(enqueue_pass(B, src, st));
+                DB_TRY(enqueue_pass(B, 0, st));
+                DB_TRY(enqueue_pass(B, 1, st));
                 DB_TRY(read_back());
-                src = 1 - src;
                 if (!h_state->any_active) break;
                 if (h_state->pass > total_nnz + 2) {   // every productive pass deletes an entry
                     set_error("transitive reduction did not converge");

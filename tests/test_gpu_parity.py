@@ -266,6 +266,7 @@ def test_tr_tiny_workload(lib, policy, variant, rule):
     assert it == it_ref
     st = lib.last_stats()
     assert st["nnz_trace"] == list(trace)
+    assert st["host_syncs"] == 1 + (it + 1) // 2     # validation, then one per two passes
 
 
 @pytest.mark.parametrize("graph", [False, True])
