@@ -466,7 +466,8 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
 
 // ---------------------------------------------------------------------------
 // Step 3: record each A entry's A^T segment (start, length), products per
-// row, and bin rows for the symbolic phase: bitmap-path rows in one class,
+// row, the row's scratch range bound, and bin rows for the symbolic phase:
+// bitmap-path rows in one class,
 // hash-path rows by first-level table size.  A workgroup owns
 // kRowsPerBlock consecutive rows (one wave per row at a time); bin counts
 // and totals are gathered in LDS and published with one global atomic per
@@ -480,7 +481,7 @@ template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
     const uint32_t* __restrict__ t_rowptr, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
-    int32_t* __restrict__ sym_list,
+    int64_t* __restrict__ sbound, int32_t* __restrict__ sym_list,
     OvCounters* __restrict__ ctr, int first_log2, int load_pct) {
     __shared__ int32_t s_cnt[kMaxLog2], s_base[kMaxLog2];
     __shared__ int32_t s_bin[kRowsPerBlock], s_pos[kRowsPerBlock];
@@ -537,6 +538,10 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
         fl = wave_sum(fl);
         if (lane == 0) {
             flops_row[g] = fl;
+            // scratch range for the row's output columns: at most
+            // min(products / min_shared, n) of them
+            const int64_t bound = fl / S.min_shared;
+            sbound[g] = bound < S.n ? bound : S.n;
             s_bin[r] = -1;
             if (fl > 0) {
                 atomicAdd(&s_prod, (unsigned long long)fl);
@@ -919,18 +924,6 @@ __global__ __launch_bounds__(kBinBlock) void k_ov_bin_numeric(
     }
 }
 
-// Scratch range of a row for its output columns: at most min(products, n)
-// distinct columns, and each kept one needs min_shared products.
-__global__ void k_ov_scratch_bound(const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base,
-                                   int64_t total_rows, const int64_t* __restrict__ flops_row,
-                                   int64_t* __restrict__ bound) {
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total_rows;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const OvSet& S = sets[find_set(set_base, nsets, g)];
-        const int64_t a = flops_row[g] / S.min_shared;
-        bound[g] = a < S.n ? a : S.n;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Numeric phase.  The row's output columns are its sorted list in scratch;
@@ -1460,7 +1453,8 @@ static int dispatch_numeric(int block, const OvWork& W, const int32_t* list, int
 // Numeric bin bounds that fit the LDS: hash bins, then bitmap bins for a
 // bitmap of `words` words (none if words == 0).
 static NumBins numeric_bins(const dibella_tuning& tn, int words) {
-    static const int bounds[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 5120, 6144, 8192};
+    // few, wide bins: each bin is one launch, and launches cost a tail each
+    static const int bounds[] = {256, 1024, 2048, 4096, 8192};
     NumBins b;
     std::memset(&b, 0, sizeof(b));
     int k = 0;   // next free entry of b.d
@@ -1730,11 +1724,9 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         DB_TRY(timing_begin(kPhSegments, st, &tok));
         hipLaunchKernelGGL(k_ov_scatter<kSegWaves>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
                            dim3(kSegWaves * kWave), 0, st, d_sets, nsets, d_base, total_rows, t_rowptr, seg,
-                           flops_row, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct);
-        DB_TRY(timing_end(tok, st));
-        hipLaunchKernelGGL(k_ov_scratch_bound, dim3(grid_for(total_rows, 256, 4096)), dim3(256), 0, st, d_sets,
-                           nsets, d_base, total_rows, flops_row, sbound);
+                           flops_row, sbound, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct);
         DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
     }
     DB_TRY(scan_exclusive(sbound, soff, total_rows, nullptr, ar));
     // ---- sync 1: validity, bin sizes, scratch size
