@@ -281,6 +281,8 @@ constexpr int kBucketBlock = 1024;
 constexpr int64_t kMaxBuckets = 3840;
 constexpr int kBucketBits = 15;   // LDS histogram of a pass-2 workgroup: 2^15 columns (128 KB)
 constexpr int kMaxLow = 17;       // widest bucket: 4 sweeps of 2^15 columns
+constexpr int kStageBits = 12;    // staged sweeps: 2^12 columns ...
+constexpr int kStageCap = 17408;  // ... and at most this many pairs placed in LDS
 
 inline size_t part_scatter_lds(int64_t nbuckets) {
     return (size_t)kChunk * 12 + (size_t)nbuckets * 16;
@@ -383,20 +385,23 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
     }
 }
 
-template <bool SWEEPS>
+// STAGE: each sweep's pairs are placed in LDS first and written out as one
+// contiguous run (coalesced) when they fit kStageCap; sweeps of 2^sub columns.
+template <bool SWEEPS, bool STAGE>
 __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
-    const int64_t* __restrict__ offsets, int64_t nchunks, int low, int64_t total_m, int64_t cap,
+    const int64_t* __restrict__ offsets, int64_t nchunks, int low, int sub_bits, int64_t total_m, int64_t cap,
     const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint32_t* __restrict__ t_rowptr,
     uint64_t* __restrict__ at) {
     // offsets: bucket-major over the partition's workgroups (nchunks of them)
     const int64_t total_valid = min(offsets[(int64_t)gridDim.x * nchunks], cap);
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
+    uint64_t* stage = reinterpret_cast<uint64_t*>(hist + (STAGE ? (1 << sub_bits) : 0));
     __shared__ int64_t s_tmp[kBucketBlock / kWave + 1];
     const int b = blockIdx.x;
-    // a bucket wider than the LDS histogram (2^kBucketBits bins) is sorted
-    // in sweeps over its pairs, one range of 2^kBucketBits columns each
-    const int sub = SWEEPS ? kBucketBits : low;
+    // a bucket wider than the LDS histogram (2^sub_bits bins) is sorted in
+    // sweeps over its pairs, one range of 2^sub_bits columns each
+    const int sub = SWEEPS ? sub_bits : low;
     const int sweeps = SWEEPS ? 1 << (low - sub) : 1;
     const int bins = 1 << sub;
     const uint32_t lmask = (uint32_t)(1u << low) - 1u, smask = (uint32_t)bins - 1u;
@@ -453,9 +458,18 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
                 mine[q] = e0 + q * kBucketBlock + threadIdx.x < be && (!SWEEPS || (int)(kk[q] >> sub) == h);
                 pos[q] = atomicAdd(&hist[kk[q] & smask], mine[q] ? 1u : 0u);
             }
+            const bool staged = STAGE && tot <= kStageCap;
 #pragma unroll
-            for (int q = 0; q < kPartIlp; ++q)
-                if (mine[q] && pos[q] < cap) at[pos[q]] = pp[q];
+            for (int q = 0; q < kPartIlp; ++q) {
+                if (!mine[q]) continue;
+                if (staged) stage[pos[q] - base] = pp[q];
+                else if (pos[q] < cap) at[pos[q]] = pp[q];
+            }
+        }
+        if (STAGE && tot <= kStageCap) {
+            __syncthreads();
+            for (int64_t q = threadIdx.x; q < tot; q += kBucketBlock)
+                if (base + q < cap) at[base + q] = stage[q];
         }
         base += tot;
         __syncthreads();
@@ -1679,9 +1693,11 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         if (!lds_ok) {
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<false>,
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<false, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true>,
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
             lds_ok = true;
         }
@@ -1694,12 +1710,16 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         // A^T pairs land in pays_a, free once the partition has read it
         DB_TRY(timing_begin(kPhBucketSort, st, &tok));
         if (low > kBucketBits)
-            hipLaunchKernelGGL(k_ov_bucket_sort<true>, dim3((unsigned)nbuckets), dim3(kBucketBlock),
-                               (size_t)4 << kBucketBits, st, poffs, npart, low, total_m, total_nnz, keys_b, pays_b,
-                               t_rowptr, pays_a);
+            hipLaunchKernelGGL((k_ov_bucket_sort<true, false>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
+                               (size_t)4 << kBucketBits, st, poffs, npart, low, kBucketBits, total_m, total_nnz,
+                               keys_b, pays_b, t_rowptr, pays_a);
+        else if (low > kStageBits)
+            hipLaunchKernelGGL((k_ov_bucket_sort<true, true>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
+                               ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, poffs, npart, low, kStageBits,
+                               total_m, total_nnz, keys_b, pays_b, t_rowptr, pays_a);
         else
-            hipLaunchKernelGGL(k_ov_bucket_sort<false>, dim3((unsigned)nbuckets), dim3(kBucketBlock),
-                               (size_t)4 << low, st, poffs, npart, low, total_m, total_nnz, keys_b, pays_b,
+            hipLaunchKernelGGL((k_ov_bucket_sort<false, false>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
+                               (size_t)4 << low, st, poffs, npart, low, low, total_m, total_nnz, keys_b, pays_b,
                                t_rowptr, pays_a);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
