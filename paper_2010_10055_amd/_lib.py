@@ -151,6 +151,22 @@ class _Call:
         self.free_cb = FREE_FN(self.mem.free)
 
 
+_tls = threading.local()
+
+
+def _call_for(device: torch.device) -> _Call:
+    """The calling thread's callbacks for `device`, with an empty registry
+    (calls on one thread run one after another, so they can share them)."""
+    cache = getattr(_tls, "calls", None)
+    if cache is None:
+        cache = _tls.calls = {}
+    c = cache.get(device)
+    if c is None:
+        c = cache[device] = _Call(device)
+    c.mem.live.clear()
+    return c
+
+
 def _stream_handle(device: torch.device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -217,7 +233,7 @@ def overlap_batched(As: Sequence[CSRTensors], min_shared) -> List[OverlapCSR]:
     if isinstance(min_shared, int):
         min_shared = [min_shared] * n
     dev = _device_of(As)
-    call = _Call(dev)
+    call = _call_for(dev)
     ins = (_CSR * max(n, 1))(*[_csr_struct(a) for a in As])
     outs = (_OverlapOut * max(n, 1))()
     ms = (ctypes.c_int32 * max(n, 1))(*min_shared)
@@ -239,7 +255,7 @@ def overlap_batched(As: Sequence[CSRTensors], min_shared) -> List[OverlapCSR]:
 def overlap(A: CSRTensors, min_shared: int = 1) -> OverlapCSR:
     """C = A A^T over the overlap semiring (count + two seeds)."""
     dev = _device_of([A])
-    call = _Call(dev)
+    call = _call_for(dev)
     a = _csr_struct(A)
     o = _OverlapOut()
     with torch.cuda.device(dev):
@@ -267,7 +283,7 @@ def transitive_reduce_batched(Rs: Sequence[CSRTensors], fuzz, variant="A", rule=
     if isinstance(fuzz, int):
         fuzz = [fuzz] * n
     dev = _device_of(Rs)
-    call = _Call(dev)
+    call = _call_for(dev)
     ins = (_CSR * max(n, 1))(*[_csr_struct(r) for r in Rs])
     outs = (_CSROut * max(n, 1))()
     fz = (ctypes.c_int32 * max(n, 1))(*fuzz)
@@ -290,7 +306,7 @@ def transitive_reduce(R: CSRTensors, fuzz: int, variant="A", rule="row", graph=F
                       validate=True):
     """S = TR(R).  Returns (S, passes executed)."""
     dev = _device_of([R])
-    call = _Call(dev)
+    call = _call_for(dev)
     r = _csr_struct(R)
     o = _CSROut()
     it = ctypes.c_int32()
