@@ -155,6 +155,16 @@ def test_overlap_empty_rows_and_matrix(lib):
     assert_overlap_equal(_run_overlap(lib, A3, 1), oracle.overlap(A3, 1), "blank rows")
 
 
+@pytest.mark.parametrize("n,m", [(0, 0), (0, 5), (1, 1), (3, 0)])
+def test_overlap_degenerate_shapes(lib, n, m):
+    if n and m:
+        A = synth.CSR(n, m, np.array([0, 1], np.int64), np.zeros(1, np.int32), np.array([7], np.int32))
+    else:
+        A = synth.CSR(n, m, np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    C = _run_overlap(lib, A, 1)
+    assert_overlap_equal(C, oracle.overlap(A, 1), f"{n}x{m}")
+
+
 @pytest.mark.parametrize("bits", PATHS)
 def test_overlap_adversarial_dense(lib, bits):
     rng = np.random.default_rng(9)
@@ -315,6 +325,22 @@ def test_tr_long_rows_global_path(lib):
         S, it = _run_tr(lib, Rb, 50)
     assert_csr_equal(S, ref, "hubs")
     assert it == it_ref
+
+
+@pytest.mark.parametrize("case", ["0x0", "empty", "all-contained", "single-edge"])
+def test_tr_degenerate_inputs(lib, case):
+    if case == "0x0":
+        R = synth.CSR(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    elif case == "empty":
+        R = synth.CSR(5, 5, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    elif case == "all-contained":    # overhang 0 everywhere: everything is dropped first
+        R = synth.coo_to_csr(3, 3, [0, 1, 2], [1, 2, 0], [0 << 2, 0 << 2, 0 << 2])
+    else:
+        R = synth.coo_to_csr(2, 2, [0], [1], [(500 << 2) | 1])
+    S, it = _run_tr(lib, R, 1000)
+    ref, it_ref, _ = oracle.transitive_reduce(R, 1000)
+    assert_csr_equal(S, ref, case)
+    assert it == it_ref, (it, it_ref)
 
 
 @pytest.mark.parametrize("block", [64, 128, 512])
