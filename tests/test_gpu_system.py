@@ -1,6 +1,6 @@
 """GPU system tests: the mid-size workload against the oracle at full size,
 the large workload at full size against the oracle on sampled rows of C and
-on the whole reduction,
+on the whole reduction, the batching workload (64 sets) in full,
 the serving loop (each job's result in the mix equals its solo result,
 tolerance 0), the autotuner (tuned configurations reproduce the default
 bits), and batched graph-captured reductions."""
@@ -80,6 +80,30 @@ def test_large_workload_sampled_parity(db):
     Sref, it_ref, _ = oracle.transitive_reduce(R, w.fuzz)
     assert it == it_ref
     assert _eq(S.rowptr, Sref.rowptr) and _eq(S.col, Sref.col) and _eq(S.val, Sref.val)
+
+
+@pytest.mark.timeout(900)
+def test_batchset_workload_full_parity(db):
+    """The batching workload at full size (64 uneven read sets in one batched
+    overlap call and one batched, graph-captured reduction call) against the
+    oracle, set by set."""
+    print("batching workload: generating 64 sets", flush=True)
+    ws = synth.batch_workloads(64, device="cuda:0")
+    As = [db.CSRTensors.from_numpy(w.A, "cuda:0") for w in ws]
+    Rs = [db.CSRTensors.from_numpy(w.R, "cuda:0") for w in ws]
+    Cs = db.overlap_batched(As, [w.min_shared for w in ws])
+    Ss, its = db.transitive_reduce_batched(Rs, [w.fuzz for w in ws], graph=True)
+    torch.cuda.synchronize()
+    print(f"  reads {sum(w.A.nrows for w in ws)}, products {sum(synth.overlap_products(w.A) for w in ws)}; "
+          "oracle ...", flush=True)
+    for s, w in enumerate(ws):
+        ref = oracle.overlap(w.A, w.min_shared)
+        C = Cs[s]
+        assert _eq(C.rowptr, ref.rowptr) and _eq(C.col, ref.col), s
+        assert _eq(C.count, ref.count) and _eq(C.seed, ref.seed), s
+        Sref, it_ref, _ = oracle.transitive_reduce(w.R, w.fuzz)
+        assert its[s] == it_ref, s
+        assert _eq(Ss[s].rowptr, Sref.rowptr) and _eq(Ss[s].col, Sref.col) and _eq(Ss[s].val, Sref.val), s
 
 
 def test_serve_mix_equals_solo(db):
