@@ -44,7 +44,7 @@ def source_hash(*names) -> str:
 def kernel_bytes(w, C_nnz, products, tr_stats, sort_passes):
     """Algorithmic bytes per step of each timed kernel.  The two products use
     the CSR Gustavson model of a row-wise SpGEMM (symbolic: row pointers, A
-    columns and the A^T row-pointer pair per entry, 4 B per product;
+    columns and the column's A^T segment per entry, 4 B per product;
     numeric: the same plus A values, 8 B per product and 24 B per output
     entry); the transpose kernels move what a sort of 12-byte (column,
     read|position) pairs must; a reduction pass reads a row-pointer pair per
@@ -58,7 +58,7 @@ def kernel_bytes(w, C_nnz, products, tr_stats, sort_passes):
         "keys": 8 * n + 8 * nnzA + 12 * nnzA,
         "part_count": 4 * nnzA,
         "part_scatter": 24 * nnzA,
-        "bucket_sort": (4 * nnzA + 4 * m) if radix else (24 * nnzA + 4 * m),
+        "bucket_sort": (4 * nnzA + 8 * m) if radix else (24 * nnzA + 8 * m),
         "sort_up": 4 * nnzA * sort_passes,
         "sort_down": 24 * nnzA * sort_passes,
         "segments": 16 * n + 20 * nnzA,
@@ -94,11 +94,12 @@ def load_traffic(kernel: str, workload: str, src_hash: str):
     return d.get("hbm_bytes_per_phase" if phase else "hbm_bytes_per_launch")
 
 
-KERNEL_NAMES = {"keys": "k_ov_keys", "part_count": "k_ov_part_count", "part_scatter": "k_ov_part_scatter",
-                "bucket_sort": "k_ov_bucket_sort", "sort_up": "k_rs_upsweep", "sort_down": "k_rs_downsweep",
-                "segments": "k_ov_scatter", "sym_bits": "k_ov_sym_bits",
-                "sym_hash": "k_ov_sym_hash", "numeric": "k_ov_numeric", "tr_mark": "k_tr_mark",
-                "tr_compact": "k_tr_compact"}
+# the kernels of each timed unit (a unit of several kernels sums them per call)
+KERNEL_NAMES = {"keys": ("k_ov_keys",), "part_count": ("k_ov_part_count",), "part_scatter": ("k_ov_part_scatter",),
+                "bucket_sort": ("k_ov_bucket_sort", "k_ov_ct_from_rowptr"), "sort_up": ("k_rs_upsweep",),
+                "sort_down": ("k_rs_downsweep",), "segments": ("k_ov_seg_slices", "k_ov_scatter"),
+                "sym_bits": ("k_ov_sym_bits",), "sym_hash": ("k_ov_sym_hash",), "numeric": ("k_ov_numeric",),
+                "tr_mark": ("k_tr_mark",), "tr_compact": ("k_tr_compact",)}
 CALIB_BYTES = 1 << 30
 
 
@@ -191,17 +192,22 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
     fetch = _counter_per_kernel(fetch_dir, "FETCH_SIZE")
     write = _counter_per_kernel(write_dir, "WRITE_SIZE")
     calls = sum(len(v) for n, v in fetch.items() if "k_ov_write_rowptr" in n)   # overlap calls profiled
-    for label, kname in KERNEL_NAMES.items():
-        fv = [x for n, v in fetch.items() if kname in n for x in v]
-        wv = [x for n, v in write.items() if kname in n for x in v]
-        if not fv or not wv or not f_fetch or not f_write:
+    for label, knames in KERNEL_NAMES.items():
+        per_f = [[x for n, v in fetch.items() if k in n for x in v] for k in knames]
+        per_w = [[x for n, v in write.items() if k in n for x in v] for k in knames]
+        present = [i for i in range(len(knames)) if per_f[i] and per_w[i]]
+        if not present or not f_fetch or not f_write:
             continue
-        fb = statistics.mean(fv) * 1024 / f_fetch
-        wb = statistics.mean(wv) * 1024 / f_write
+        fv = [x for i in present for x in per_f[i]]
+        wv = [x for i in present for x in per_w[i]]
+        # one dispatch of each kernel of the unit per call
+        fb = sum(statistics.mean(per_f[i]) for i in present) * 1024 / f_fetch
+        wb = sum(statistics.mean(per_w[i]) for i in present) * 1024 / f_write
+        kname = "+".join(knames[i] for i in present)
         d = {"kernel": kname, "workload": workload, "command": command,
              "source_hash": source_hash(*KERNEL_SOURCES[label]),
-             "fetch_KiB_per_dispatch_raw": statistics.mean(fv), "write_KiB_per_dispatch_raw": statistics.mean(wv),
-             "dispatches": len(fv), "read_calibration_factor": f_fetch, "write_calibration_factor": f_write,
+             "fetch_KiB_per_call_raw": fb * f_fetch / 1024, "write_KiB_per_call_raw": wb * f_write / 1024,
+             "dispatches": len(per_f[present[0]]), "read_calibration_factor": f_fetch, "write_calibration_factor": f_write,
              "copy_fetch_factor": copy_fetch / CALIB_BYTES, "copy_write_factor": copy_write / CALIB_BYTES,
              "hbm_bytes_per_launch": fb + wb, "hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb}
         if label == "numeric" and calls:
@@ -211,6 +217,36 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
         with open(os.path.join(PROFILES, f"{label}_{workload}_pmc.json"), "w") as f:
             json.dump(d, f, indent=1)
     print(f"summaries written to {PROFILES}")
+
+
+def gather_probe():
+    """Random 8-byte gathers (torch indexing: indices read in order, one
+    random element each) over arrays from 2 MB to 4 GB: the rate at which the
+    GPU serves random lines by footprint.  A footprint within one XCD's L2
+    is served several times faster than anything larger; the 256 MB Infinity
+    Cache gives random lines no gain over HBM."""
+    import torch
+    m = 1 << 26
+    out = []
+    for mb in (2, 8, 32, 128, 256, 512, 1024, 4096):
+        n = mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.int64, device="cuda:0")
+        idx = torch.randint(0, n, (m,), device="cuda:0")
+        for _ in range(2):
+            a[idx]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = None
+        for _ in range(5):
+            e0.record()
+            a[idx]
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out.append({"array_MB": mb, "ms": round(best, 4), "G_gathers_per_s": round(m / best / 1e6, 2)})
+        log(f"  {mb:5d} MB: {m / best / 1e6:7.2f} G random 8-byte gathers/s")
+        del a, idx
+    print(json.dumps({"gather_probe": out}))
 
 
 def cpu_baseline(w, budget_s: float):
@@ -359,6 +395,7 @@ def main():
     ap.add_argument("--tune-budget", type=float, default=30.0, help="seconds of autotuning for the batch (0 = off)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving comparison (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true", help="only run the 1 GiB copy used to scale counters")
+    ap.add_argument("--gather-probe", action="store_true", help="only measure random-gather rates by footprint")
     ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/ summaries from rocprofv3 CSV directories")
     ap.add_argument("--profile-command", default="", help="command recorded in the summaries")
@@ -368,6 +405,9 @@ def main():
         return
     if args.calib_copy:
         calib_copy()
+        return
+    if args.gather_probe:
+        gather_probe()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",

@@ -177,10 +177,26 @@ __device__ __forceinline__ void planes_mark(uint32_t* B, int words, int planes, 
     }
 }
 
+// Column slices for the segment pass: the global columns are cut into
+// `count` ranges of about equal width, slice(c) = (c * mul) >> 32 with
+// mul = floor(2^32 * count / total columns), so slice(c) < count and is
+// monotone in c.  Each slice's share of the A^T row pointers is small
+// enough to stay in one XCD's L2 while that XCD works on the slice.
+struct SliceMap {
+    int32_t count;   // 0: no slices
+    uint32_t mul;
+};
+__host__ __device__ __forceinline__ int slice_of(int64_t c, SliceMap sm) {
+    return (int)(((uint64_t)c * sm.mul) >> 32);
+}
+
 // ---------------------------------------------------------------------------
 // Step 1: validate A (one wave per row) and lay out its entries as pairs
 // over the global entry space: key = global column, value =
-// (position << 32) | read.  Grouping the pairs by key gives A^T.
+// (position << 32) | read.  Grouping the pairs by key gives A^T.  With
+// slices, the row's slice boundaries are recorded as well: bnd[s] = first
+// entry of the row (relative to its start) whose column lies in slice s or
+// later, for s = 0..count (bnd[count] = row length).
 // ---------------------------------------------------------------------------
 constexpr int kKeysIlp = 8;
 
@@ -188,7 +204,8 @@ template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict__ sets, int nsets,
                                                         const int64_t* __restrict__ set_base, int64_t total_rows,
                                                         uint32_t* __restrict__ keys, uint64_t* __restrict__ pays,
-                                                        int32_t* __restrict__ flags, int checks) {
+                                                        int32_t* __restrict__ flags, int checks, SliceMap sm,
+                                                        int32_t* __restrict__ bnd) {
     const int lane = lane_id();
     // the row, its set and the set's fields are wave-uniform: kept in scalar
     // registers so that the entry loads do not wait on them
@@ -207,6 +224,8 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
             bad |= kLongRow;
         } else {
             int32_t prev_last = 0;   // column of the entry before this step's first
+            int prev_sl = -1;        // slice of the entry before this step's first
+            int32_t* rb = sm.count ? bnd + g * (sm.count + 1) : nullptr;
             for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kKeysIlp) {
                 int32_t kk[kKeysIlp], vv[kKeysIlp];
 #pragma unroll
@@ -236,8 +255,22 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
                         keys[S.nnz_base + e] = ok ? (uint32_t)(S.col_base + k) : 0u;
                         pays[S.nnz_base + e] = ((uint64_t)(uint32_t)vv[q] << 32) | (uint64_t)(uint32_t)i;
                     }
+                    if (rb) {
+                        // slices this entry opens: (slice of the previous entry, own slice];
+                        // an unsorted or invalid row writes an incomplete table, but the
+                        // call fails at the first synchronisation and every read of the
+                        // table is clamped to the row
+                        const int sl = ok ? slice_of(S.col_base + k, sm) : prev_sl;
+                        const int up = __shfl_up(sl, 1, kWave);
+                        const int psl = lane ? up : prev_sl;
+                        if (in)
+                            for (int b = max(psl, -1) + 1; b <= sl; ++b) rb[b] = (int32_t)(e - lo);
+                        prev_sl = __shfl(sl, kWave - 1, kWave);
+                    }
                 }
             }
+            if (rb)
+                for (int b = prev_sl + 1 + lane; b <= sm.count; b += kWave) rb[b] = (int32_t)(hi - lo);
         }
         bad = wave_or(bad);
         if (lane == 0 && bad) atomicOr(&flags[s], bad);
@@ -257,6 +290,12 @@ __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64
     }
 }
 
+// The A^T segment of every column, (start << 24) | length, from row pointers.
+__global__ void k_ov_ct_from_rowptr(const uint32_t* __restrict__ t_rowptr, int64_t total_m, uint64_t* __restrict__ ct) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total_m; c += (int64_t)gridDim.x * blockDim.x)
+        ct[c] = ((uint64_t)t_rowptr[c] << 24) | (uint64_t)(t_rowptr[c + 1] - t_rowptr[c]);
+}
+
 // ---------------------------------------------------------------------------
 // Step 2: group the pairs by column with a two-pass bucketed counting sort
 // (at most kMaxBuckets buckets of 2^low columns, low <= kMaxLow):
@@ -268,8 +307,9 @@ __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64
 //                     written out as runs, so that stores coalesce;
 //   k_ov_bucket_sort  one workgroup per bucket counts its pairs per column in
 //                     LDS (2^low bins, in sweeps of 2^15 for wider buckets),
-//                     scans the counts into the row pointers of A^T and
-//                     places each (read, position).
+//                     scans the counts into each column's A^T segment,
+//                     ct[c] = (start << 24) | length, and places each
+//                     (read, position).
 // The order inside an A^T row is left free: nothing downstream depends on it.
 // Every pass takes the same chunks, so a malformed A (reported after the
 // first synchronisation) can only over-count: writes are clamped to `cap`.
@@ -390,10 +430,9 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
 template <bool SWEEPS, bool STAGE>
 __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
     const int64_t* __restrict__ offsets, int64_t nchunks, int low, int sub_bits, int64_t total_m, int64_t cap,
-    const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint32_t* __restrict__ t_rowptr,
+    const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ ct,
     uint64_t* __restrict__ at) {
     // offsets: bucket-major over the partition's workgroups (nchunks of them)
-    const int64_t total_valid = min(offsets[(int64_t)gridDim.x * nchunks], cap);
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
     uint64_t* stage = reinterpret_cast<uint64_t*>(hist + (STAGE ? (1 << sub_bits) : 0));
@@ -438,7 +477,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
             if (c >= bins) break;
             const uint32_t n_c = hist[c];
             const int64_t start = base + run;
-            if (col0 + c < total_m) t_rowptr[col0 + c] = (uint32_t)start;
+            if (col0 + c < total_m) ct[col0 + c] = ((uint64_t)start << 24) | (uint64_t)n_c;
             hist[c] = (uint32_t)start;   // becomes the cursor of column c
             run += n_c;
         }
@@ -474,8 +513,6 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
         base += tot;
         __syncthreads();
     }
-    // the last bucket also closes A^T
-    if (col_b + ((int64_t)1 << low) >= total_m && threadIdx.x == 0) t_rowptr[total_m] = (uint32_t)total_valid;
 }
 
 // ---------------------------------------------------------------------------
@@ -491,12 +528,109 @@ constexpr int kRowsPerBlock = 64;
 constexpr int kSegWaves = 16;
 constexpr int kSegIlp = 8;
 
+// Sliced segment pass.  Workgroups are handed to the XCDs round-robin
+// (workgroup b runs on XCD b mod 8), so workgroup b takes slice
+// 8 * round + (b mod 8): at any time each XCD gathers column segments
+// (ct) from one slice only (at most 4 MB), which its L2 then holds, instead
+// of every XCD gathering from all of them.  A workgroup covers kSliceRows
+// rows: each wave takes its share of the rows, kSliceIlp at a time, one
+// lane per entry of a row's sub-range.  Products per (slice, row) go to
+// part[slice * rows + row]; k_ov_scatter sums them.
+constexpr int kSliceRows = 64;
+constexpr int kSliceBlock = 256;
+constexpr int kSliceIlp = 8;
+constexpr int kMaxSlices = 64;
+constexpr int64_t kSliceCols = int64_t(1) << 19;   // 4 MB of column segments: one L2
+
+__global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
+    const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
+    int64_t groups, SliceMap sm, const int32_t* __restrict__ bnd, const uint64_t* __restrict__ ct,
+    uint64_t* __restrict__ seg, int64_t* __restrict__ part) {
+    __shared__ int32_t s_len[kSliceRows];
+    __shared__ int64_t s_first[kSliceRows];        // global entry of the row's first entry in the slice
+    __shared__ const int32_t* s_col[kSliceRows];   // its column
+    __shared__ int64_t s_cb[kSliceRows], s_m[kSliceRows];
+    const int64_t b = blockIdx.x;
+    const int sl = (int)((b / 8) / groups) * 8 + (int)(b % 8);
+    const int64_t row0 = ((b / 8) % groups) * kSliceRows;
+    if (sl >= sm.count) return;   // uniform over the workgroup
+    if (threadIdx.x < kSliceRows) {
+        const int r = threadIdx.x;
+        const int64_t g = row0 + r;
+        s_len[r] = 0;
+        s_first[r] = 0;
+        s_col[r] = nullptr;
+        s_cb[r] = 0;
+        s_m[r] = 0;
+        if (g < total_rows) {
+            const int s = find_set(set_base, nsets, g);
+            const OvSet& S = sets[s];
+            const int64_t i = g - S.row_base;
+            const int64_t lo = S.a_rowptr[i], hi = S.a_rowptr[i + 1];
+            if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
+                const int32_t L = (int32_t)(hi - lo);
+                const int32_t* rb = bnd + g * (sm.count + 1);
+                const int32_t a = min(max(rb[sl], 0), L);
+                const int32_t z = min(max(rb[sl + 1], a), L);
+                s_len[r] = z - a;
+                s_first[r] = S.nnz_base + lo + a;
+                s_col[r] = S.a_col + lo + a;
+                s_cb[r] = S.col_base;
+                s_m[r] = S.m;
+            }
+        }
+    }
+    __syncthreads();
+    // each wave takes kSliceRows / waves rows, kSliceIlp of them at a time;
+    // the lanes take consecutive entries of a row (coalesced column loads
+    // and segment stores)
+    constexpr int W = kSliceBlock / kWave, RPW = kSliceRows / W;
+    static_assert(RPW % kSliceIlp == 0, "rows per wave");
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(wave_id());
+    for (int j0 = 0; j0 < RPW; j0 += kSliceIlp) {
+        int len[kSliceIlp], most = 0;
+#pragma unroll
+        for (int u = 0; u < kSliceIlp; ++u) {
+            len[u] = s_len[w * RPW + j0 + u];
+            most = max(most, len[u]);
+        }
+        int64_t fl[kSliceIlp];
+#pragma unroll
+        for (int u = 0; u < kSliceIlp; ++u) fl[u] = 0;
+        for (int o = lane; o - lane < most; o += kWave) {
+            int32_t kk[kSliceIlp];
+#pragma unroll
+            for (int u = 0; u < kSliceIlp; ++u)
+                kk[u] = o < len[u] ? __builtin_nontemporal_load(s_col[w * RPW + j0 + u] + o) : -1;
+            uint64_t sg[kSliceIlp];
+#pragma unroll
+            for (int u = 0; u < kSliceIlp; ++u) {
+                const int r = w * RPW + j0 + u;
+                sg[u] = (kk[u] >= 0 && kk[u] < s_m[r]) ? ct[s_cb[r] + kk[u]] : 0ull;   // invalid: empty
+            }
+#pragma unroll
+            for (int u = 0; u < kSliceIlp; ++u) {
+                if (o >= len[u]) continue;
+                fl[u] += (int64_t)(sg[u] & 0xFFFFFFull);
+                seg[s_first[w * RPW + j0 + u] + o] = sg[u];   // ordinary store: L2 merges the lines
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSliceIlp; ++u) {
+            const int64_t t = wave_sum(fl[u]);
+            const int64_t g = row0 + w * RPW + j0 + u;
+            if (lane == 0 && g < total_rows) part[(int64_t)sl * total_rows + g] = t;
+        }
+    }
+}
+
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
-    const uint32_t* __restrict__ t_rowptr, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
+    const uint64_t* __restrict__ ct, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
     int64_t* __restrict__ sbound, int32_t* __restrict__ sym_list,
-    OvCounters* __restrict__ ctr, int first_log2, int load_pct) {
+    OvCounters* __restrict__ ctr, int first_log2, int load_pct, const int64_t* __restrict__ part, int nslices) {
     __shared__ int32_t s_cnt[kMaxLog2], s_base[kMaxLog2];
     __shared__ int32_t s_bin[kRowsPerBlock], s_pos[kRowsPerBlock];
     __shared__ unsigned long long s_prod;
@@ -522,30 +656,28 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
         const int64_t i = g - S.row_base;
         const int64_t lo = S.a_rowptr[i], hi = S.a_rowptr[i + 1];
         int64_t fl = 0;
-        if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
+        if (part) {
+            // the segments are written by the sliced pass: sum its partial products
+            if (lane < nslices) fl = part[(int64_t)lane * total_rows + g];
+        } else if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
             for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kSegIlp) {
                 int32_t kk[kSegIlp];
-                uint32_t t0[kSegIlp], t1[kSegIlp];
+                uint64_t sg[kSegIlp];
 #pragma unroll
                 for (int q = 0; q < kSegIlp; ++q) kk[q] = gload(S.a_col + min(e0 + q * kWave + lane, hi - 1));
 #pragma unroll
                 for (int q = 0; q < kSegIlp; ++q) {
                     const int32_t k = kk[q];
                     const int64_t gk = (k >= 0 && k < S.m) ? S.col_base + k : 0;   // in range for the load
-                    t0[q] = t_rowptr[gk];
-                    t1[q] = t_rowptr[gk + 1];
+                    sg[q] = ct[gk];
                 }
 #pragma unroll
                 for (int q = 0; q < kSegIlp; ++q) {
                     const int64_t e = e0 + q * kWave + lane;
                     if (e >= hi) continue;
-                    uint64_t sg = 0;
-                    if (kk[q] >= 0 && kk[q] < S.m) {
-                        const int64_t len = (int64_t)t1[q] - (int64_t)t0[q];
-                        sg = ((uint64_t)t0[q] << 24) | (uint64_t)len;
-                        fl += len;
-                    }
-                    seg[S.nnz_base + e] = sg;
+                    if (!(kk[q] >= 0 && kk[q] < S.m)) sg[q] = 0;   // invalid column: empty segment
+                    fl += (int64_t)(sg[q] & 0xFFFFFFull);
+                    seg[S.nnz_base + e] = sg[q];
                 }
             }
         }
@@ -587,60 +719,64 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
 
 // ---------------------------------------------------------------------------
 // Shared product walk: the A entries t of row i are taken in chunks of
-// walk_chunk_of(BLOCK) entries (one per thread); seg[t] gives the A^T
+// walk_chunk_of(BLOCK) entries (two per thread); seg[t] gives the A^T
 // segment (start, length) of entry t, and the products of the chunk are
 // numbered t-major.  Products are handed out in windows of
-// walk_win_of(BLOCK): every thread first writes its entry's chunk index over
-// its products' slots of the window (an LDS expansion, so that a product
-// finds its entry with one LDS read), then each thread takes walk_per(BLOCK)
-// products and issues all their gathers of A^T pairs before handing them to
-// f(t, (j, p_j), q), so that several independent loads are in flight per
-// thread.  The block must call it uniformly.  `stop` (LDS flag) abandons
-// the walk.  LDS: c_start, c_off (one int64 per chunk entry each) and tbuf
-// (one u16 per window product), carved from the front of the dynamic LDS by
-// walk_lds().  (Larger chunks and windows, 16 products per thread in
-// flight, measured no faster: the walks are bound by the number of distinct
-// cache lines they touch, and the larger area costs occupancy.)
+// walk_win_of(BLOCK): every thread first writes its entries' chunk indices
+// over their products' slots of the window (an LDS expansion, so that a
+// product finds its entry with one LDS read), then each thread takes
+// walk_per(BLOCK) products and issues all their gathers of A^T pairs before
+// handing them to f(t, (j, p_j), q), so that several independent loads are
+// in flight per thread.  The segments of the next chunk are loaded before
+// the gathers of the current one, so the two loads overlap instead of
+// following each other.  The block must call it uniformly.  `stop` (LDS
+// flag) abandons the walk.  LDS: c_base (one int64 per chunk entry: segment
+// start minus the entry's first product number, so a product q of entry t
+// sits at A^T[c_base[t] + q]) and tbuf (one u16 per window product), carved
+// from the front of the dynamic LDS by walk_lds().
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int walk_chunk_of(int block) { return block; }
-__host__ __device__ constexpr int walk_win_of(int) { return 2048; }
+__host__ __device__ constexpr int walk_chunk_of(int block) { return 2 * block; }
+__host__ __device__ constexpr int walk_win_of(int block) { return block * 8 < 4096 ? block * 8 : 4096; }
 __host__ __device__ constexpr size_t walk_lds(int block) {
-    return (size_t)walk_chunk_of(block) * 16 + (size_t)walk_win_of(block) * 2;
+    return (size_t)walk_chunk_of(block) * 8 + (size_t)walk_win_of(block) * 2;
 }
-__host__ __device__ constexpr int walk_per(int) { return 4; }
+__host__ __device__ constexpr int walk_per(int block) { return walk_win_of(block) / block; }
 // the ESC expansion's static walk area
-constexpr int kWalkChunk = 256;
+constexpr int kWalkChunk = 512;
 constexpr int kWalkWin = 2048;
 
-// Loads the chunk's segments, numbers its products (t-major) and returns
-// the chunk's product count.  Each thread keeps its entries' offsets and
-// lengths for the window fills.
-template <int BLOCK, bool START>
-__device__ __forceinline__ int64_t walk_chunk(const uint64_t* __restrict__ rseg, int cbase, int cl,
-                                              int64_t* c_start, int64_t* c_off, int64_t* s_tmp,
-                                              int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
-                                              int64_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
+// Loads the segments of the chunk's entries owned by this thread (length 0
+// past the end of the row).
+template <int BLOCK>
+__device__ __forceinline__ void walk_load(const uint64_t* __restrict__ rseg, int cbase, int cl,
+                                          uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK]) {
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
-    int64_t st[E], local = 0;
 #pragma unroll
     for (int u = 0; u < E; ++u) {
         const int e = (int)threadIdx.x * E + u;
-        my_len[u] = 0;
-        st[u] = 0;
-        if (e < cl) {
-            const uint64_t sg = rseg[cbase + e];
-            st[u] = (int64_t)(sg >> 24);
-            my_len[u] = (int64_t)(sg & 0xFFFFFFull);
-        }
+        sg[u] = e < cl ? rseg[cbase + e] : 0ull;
+    }
+}
+
+// Numbers the chunk's products (t-major) from its loaded segments, writes
+// c_base and returns the chunk's product count.  Each thread keeps its
+// entries' offsets and lengths for the window fills.
+template <int BLOCK>
+__device__ __forceinline__ int64_t walk_chunk(const uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK], int64_t* c_base,
+                                              int64_t* s_tmp, int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
+                                              int64_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
+    constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
+    int64_t local = 0;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        my_len[u] = (int64_t)(sg[u] & 0xFFFFFFull);
         local += my_len[u];
     }
     int64_t tot;
     int64_t run = block_exclusive_sum<BLOCK>(local, s_tmp, &tot);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
-        const int e = (int)threadIdx.x * E + u;
-        if (START) c_start[e] = st[u];
-        c_off[e] = run;
+        c_base[(int)threadIdx.x * E + u] = (int64_t)(sg[u] >> 24) - run;
         my_off[u] = run;
         run += my_len[u];
     }
@@ -662,23 +798,27 @@ __device__ __forceinline__ void walk_fill(uint16_t* tbuf, int64_t w0, int64_t w1
 
 template <int BLOCK, class F>
 __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
-                                              const int2* __restrict__ at, int64_t* c_start, int64_t* c_off,
-                                              uint16_t* tbuf, int64_t* s_tmp, const int32_t* stop, F&& f) {
+                                              const int2* __restrict__ at, int64_t* c_base, uint16_t* tbuf,
+                                              int64_t* s_tmp, const int32_t* stop, F&& f) {
     constexpr int CH = walk_chunk_of(BLOCK), WIN = walk_win_of(BLOCK);
     static_assert(CH % BLOCK == 0 && CH <= 65536, "chunk index kept in 16 bits");
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
     constexpr int PER = walk_per(BLOCK);
+    static_assert(PER * BLOCK == WIN, "one gather round per window");
     int64_t done = 0;   // products of earlier chunks
+    uint64_t sg[E];
+    walk_load<BLOCK>(rseg, 0, min(CH, L), sg);
     for (int cbase = 0; cbase < L; cbase += CH) {
-        const int cl = min(CH, L - cbase);
         int64_t my_off[E], my_len[E];
-        const int64_t tot = walk_chunk<BLOCK, true>(rseg, cbase, cl, c_start, c_off, s_tmp, my_off, my_len);
+        const int64_t tot = walk_chunk<BLOCK>(sg, c_base, s_tmp, my_off, my_len);
+        const int nbase = cbase + CH;
+        walk_load<BLOCK>(rseg, nbase, nbase < L ? min(CH, L - nbase) : 0, sg);
         for (int64_t w0 = 0; w0 < tot; w0 += WIN) {
             const int64_t w1 = min(w0 + (int64_t)WIN, tot);
             walk_fill<BLOCK>(tbuf, w0, w1, my_off, my_len);
             __syncthreads();
-            for (int64_t q0 = w0 + threadIdx.x; q0 < w1; q0 += (int64_t)BLOCK * PER) {
-                if (stop && *(volatile const int32_t*)stop) break;
+            if (!(stop && *(volatile const int32_t*)stop)) {
+                const int64_t q0 = w0 + threadIdx.x;
                 int tt[PER];
                 int2 jp[PER];
 #pragma unroll
@@ -688,7 +828,7 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
                     if (q < w1) {
                         const int t = tbuf[q - w0];
                         tt[u] = t;
-                        jp[u] = at[c_start[t] + (q - c_off[t])];
+                        jp[u] = at[c_base[t] + q];
                     }
                 }
 #pragma unroll
@@ -699,7 +839,7 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
             if (stop && *(volatile const int32_t*)stop) break;
         }
         done += tot;
-        if (tot == 0) __syncthreads();   // c_start/c_off are rewritten by the next chunk
+        if (tot == 0) __syncthreads();   // c_base is rewritten by the next chunk
         if (stop && *(volatile const int32_t*)stop) break;
     }
 }
@@ -717,9 +857,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     const int64_t* __restrict__ soff, int32_t* __restrict__ scratch, int64_t* __restrict__ nnzrow,
     int32_t* __restrict__ distinct, int32_t* __restrict__ qhead, int count) {
     extern __shared__ __align__(16) unsigned char smem[];
-    int64_t* c_start = reinterpret_cast<int64_t*>(smem);
-    int64_t* c_off = c_start + walk_chunk_of(BLOCK);
-    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + walk_chunk_of(BLOCK));
+    int64_t* c_base = reinterpret_cast<int64_t*>(smem);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_base + walk_chunk_of(BLOCK));
     uint32_t* B = reinterpret_cast<uint32_t*>(smem + walk_lds(BLOCK));
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int32_t s_item;
@@ -738,7 +877,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     // left out of the walk (one LDS address hit by every segment) and set
     // from its closed form, count = L
     const int32_t self = (int32_t)i;
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr,
                          [&](int, int2 jp, int64_t) {
                              if (jp.x != self) planes_mark(B, words, planes, jp.x);
                          });
@@ -794,9 +933,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
     int64_t* __restrict__ nnzrow, int32_t* __restrict__ distinct, OvCounters* __restrict__ ctr,
     int32_t* __restrict__ qhead) {
     extern __shared__ __align__(16) unsigned char smem[];
-    int64_t* c_start = reinterpret_cast<int64_t*>(smem);
-    int64_t* c_off = c_start + walk_chunk_of(BLOCK);
-    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + walk_chunk_of(BLOCK));
+    int64_t* c_base = reinterpret_cast<int64_t*>(smem);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_base + walk_chunk_of(BLOCK));
     uint64_t* tab = reinterpret_cast<uint64_t*>(smem + walk_lds(BLOCK));
     __shared__ int64_t s_tmp[BLOCK / kWave + 1];
     __shared__ int32_t s_nd, s_ovf, s_item;
@@ -815,7 +953,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
         }
         __syncthreads();
         const int32_t self = (int32_t)i;
-        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, &s_ovf,
+        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, &s_ovf,
                              [&](int, int2 jp, int64_t) {
                                  if (jp.x == self) return;   // the diagonal: added once below
                                  int fresh;
@@ -958,9 +1096,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     const int2* __restrict__ at, const int64_t* __restrict__ G, int words_max, int32_t* __restrict__ qhead,
     int count) {
     extern __shared__ __align__(16) unsigned char smem[];
-    int64_t* c_start = reinterpret_cast<int64_t*>(smem);
-    int64_t* c_off = c_start + walk_chunk_of(BLOCK);
-    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_off + walk_chunk_of(BLOCK));
+    int64_t* c_base = reinterpret_cast<int64_t*>(smem);
+    uint16_t* tbuf = reinterpret_cast<uint16_t*>(c_base + walk_chunk_of(BLOCK));
     uint64_t* m1 = reinterpret_cast<uint64_t*>(smem + walk_lds(BLOCK));
     uint64_t* m2 = m1 + Dmax;
     int32_t* cnt = reinterpret_cast<int32_t*>(m2 + Dmax);
@@ -1008,7 +1145,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     }
     __syncthreads();
     const int32_t self = (int32_t)i;   // the diagonal is written from its closed form below
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr,
                          [&](int t, int2 jp, int64_t) {
                              const int32_t j = jp.x;
                              if (j == self) return;
@@ -1102,7 +1239,7 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int32_t* __restrict__ list, const int64_t* __restrict__ esc_off, const uint64_t* __restrict__ seg,
     const int2* __restrict__ at, uint32_t* __restrict__ keys0, uint64_t* __restrict__ pay0) {
     static_assert(walk_chunk_of(kEscBlock) == kWalkChunk && walk_win_of(kEscBlock) == kWalkWin, "walk area");
-    __shared__ int64_t c_start[kWalkChunk], c_off[kWalkChunk];
+    __shared__ int64_t c_base[kWalkChunk];
     __shared__ uint16_t tbuf[kWalkWin];
     __shared__ int64_t s_tmp[kEscBlock / kWave + 1];
     const int64_t g = list[blockIdx.x];
@@ -1113,7 +1250,7 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int L = (int)(S.a_rowptr[i + 1] - lo);
     const int64_t base = esc_off[g];
     // products land at their t-major index, so the expansion is ordered by k
-    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_start, c_off, tbuf, s_tmp, nullptr,
+    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr,
                              [&](int t, int2 jp, int64_t q) {
                                  keys0[base + q] = (uint32_t)jp.x;
                                  pay0[base + q] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
@@ -1598,16 +1735,31 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     while (nbuckets * ceil_div(nchunks, per_block) > std::max<int64_t>(int64_t(1) << 22, total_nnz / 8))
         per_block *= 2;
     const int64_t npart = ceil_div(nchunks, per_block);   // partition workgroups
+    // column slices for the segment pass: 8 per round, each at most
+    // kSliceCols columns wide; only where the row pointers outgrow an L2
+    SliceMap sm{0, 0u};
+    {
+        const int64_t rounds = ceil_div(total_m, 8 * kSliceCols);
+        // (total_nnz < 2^31 keeps a workgroup's flat entry numbers in 32 bits)
+        if (total_rows > 0 && total_nnz > 0 && total_nnz < (int64_t(1) << 31) && total_m >= 4 * kSliceCols &&
+            rounds * 8 <= kMaxSlices) {
+            sm.count = (int32_t)(rounds * 8);
+            sm.mul = (uint32_t)(((uint64_t)sm.count << 32) / (uint64_t)total_m);
+        }
+    }
+    const int64_t slice_groups = ceil_div(total_rows, kSliceRows);
     // ---- workspace: one reservation for everything requested before the
     // first synchronisation (allocator calls cost host time each)
     {
         const size_t P = Arena::padded(1);
         auto pad = [](size_t b) { return Arena::padded(b); };
         size_t est = pad(sizeof(OvSet) * nsets) + 2 * pad(8 * (nsets + 1)) + pad(4 * nsets) + pad(sizeof(OvCounters));
-        est += pad(4 * (total_m + 1)) + 2 * pad(4 * total_nnz) + 3 * pad(8 * total_nnz);
+        est += pad(8 * std::max<int64_t>(total_m, 1)) + (bucketed ? 0 : pad(4 * (total_m + 1)));
+        est += 2 * pad(4 * total_nnz) + 3 * pad(8 * total_nnz);
         est += 7 * pad(8 * (total_rows + 1)) + 3 * pad(4 * total_rows);
         est += pad(4 * total_rows * kMaxLog2) + pad(4 * total_rows * kMaxBins);
         est += pad(4 * nbuckets * npart) + pad(8 * (nbuckets * npart + 1));
+        if (sm.count) est += pad(4 * total_rows * (sm.count + 1)) + pad(8 * total_rows * sm.count);
         est += 4 * pad(8 * scan_workspace_elems(std::max<int64_t>(total_rows, nbuckets * npart))) + 16 * P;
         DB_TRY(ar.reserve(est));
     }
@@ -1622,13 +1774,13 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(ar.work_n(nsets, &d_flags));
     DB_TRY(ar.work_n(1, &d_ctr));
     DB_TRY(ar.work_n(nsets, &d_set_nnz));
-    uint32_t* t_rowptr;   // 32-bit offsets (total nnz < 2^32): half the footprint of the gathers
+    uint64_t* ct;   // per column: A^T segment (start << 24) | length (at least one slot)
     uint32_t *keys_a, *keys_b;
     uint64_t *pays_a, *pays_b;
     uint64_t* seg;
     int64_t *flops_row, *nnzrow, *G, *esc_off, *sbound, *soff;
     int32_t *distinct, *sym_list, *num_list, *esc_list, *retry_list;
-    DB_TRY(ar.work_n(total_m + 1, &t_rowptr));
+    DB_TRY(ar.work_n(std::max<int64_t>(total_m, 1), &ct));
     DB_TRY(ar.work_n(total_nnz, &keys_a));
     DB_TRY(ar.work_n(total_nnz, &keys_b));
     DB_TRY(ar.work_n(total_nnz, &pays_b));
@@ -1645,6 +1797,12 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(ar.work_n((size_t)total_rows * kMaxBins, &num_list));
     DB_TRY(ar.work_n(total_rows, &esc_list));
     DB_TRY(ar.work_n(total_rows, &retry_list));
+    int32_t* bnd = nullptr;
+    int64_t* part = nullptr;
+    if (sm.count) {
+        DB_TRY(ar.work_n((size_t)total_rows * (sm.count + 1), &bnd));
+        DB_TRY(ar.work_n((size_t)total_rows * sm.count, &part));
+    }
 
     // ---- upload descriptors
     HostStage& hst = host_stage();
@@ -1667,12 +1825,13 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     constexpr int WPB = 4;
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
-    if (bucketed) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(t_rowptr), 0, total_m + 1, st));
+    // empty segments where no pass writes them (the bucket sort writes every column of a non-empty A)
+    if (bucketed && total_nnz == 0) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(ct), 0, 2 * std::max<int64_t>(total_m, 1), st));
     else DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
     if (total_rows > 0) {
         DB_TRY(timing_begin(kPhKeys, st, &tok));
         hipLaunchKernelGGL(k_ov_keys<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets, d_base,
-                           total_rows, keys_a, pays_a, d_flags, checks);
+                           total_rows, keys_a, pays_a, d_flags, checks, sm, bnd);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
     }
@@ -1712,15 +1871,15 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         if (low > kBucketBits)
             hipLaunchKernelGGL((k_ov_bucket_sort<true, false>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
                                (size_t)4 << kBucketBits, st, poffs, npart, low, kBucketBits, total_m, total_nnz,
-                               keys_b, pays_b, t_rowptr, pays_a);
+                               keys_b, pays_b, ct, pays_a);
         else if (low > kStageBits)
             hipLaunchKernelGGL((k_ov_bucket_sort<true, true>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
                                ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, poffs, npart, low, kStageBits,
-                               total_m, total_nnz, keys_b, pays_b, t_rowptr, pays_a);
+                               total_m, total_nnz, keys_b, pays_b, ct, pays_a);
         else
             hipLaunchKernelGGL((k_ov_bucket_sort<false, false>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
                                (size_t)4 << low, st, poffs, npart, low, low, total_m, total_nnz, keys_b, pays_b,
-                               t_rowptr, pays_a);
+                               ct, pays_a);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         at = reinterpret_cast<const int2*>(pays_a);
@@ -1731,20 +1890,31 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         const uint32_t* tkeys = in_b ? keys_b : keys_a;
         at = reinterpret_cast<const int2*>(in_b ? pays_b : pays_a);
         if (total_nnz > 0) {
+            uint32_t* t_rowptr;
+            DB_TRY(ar.work_n(total_m + 1, &t_rowptr));
             DB_TRY(timing_begin(kPhBucketSort, st, &tok));
             hipLaunchKernelGGL(k_ov_trowptr, dim3(grid_for(total_nnz, 256, 1 << 16)), dim3(256), 0, st, tkeys,
                                total_nnz, total_m, t_rowptr);
             DB_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_ov_ct_from_rowptr, dim3(grid_for(total_m, 256, 1 << 16)), dim3(256), 0, st,
+                               t_rowptr, total_m, ct);
+            DB_HIP(hipGetLastError());
             DB_TRY(timing_end(tok, st));
         } else {
-            DB_TRY(fill_i32(reinterpret_cast<int32_t*>(t_rowptr), 0, total_m + 1, st));
+            DB_TRY(fill_i32(reinterpret_cast<int32_t*>(ct), 0, 2 * std::max<int64_t>(total_m, 1), st));
         }
     }
     if (total_rows > 0) {
         DB_TRY(timing_begin(kPhSegments, st, &tok));
+        if (sm.count) {
+            const int64_t nblk = (int64_t)(sm.count / 8) * 8 * slice_groups;
+            hipLaunchKernelGGL(k_ov_seg_slices, dim3((unsigned)nblk), dim3(kSliceBlock), 0, st, d_sets, nsets, d_base,
+                               total_rows, slice_groups, sm, bnd, ct, seg, part);
+            DB_HIP(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_ov_scatter<kSegWaves>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
-                           dim3(kSegWaves * kWave), 0, st, d_sets, nsets, d_base, total_rows, t_rowptr, seg,
-                           flops_row, sbound, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct);
+                           dim3(kSegWaves * kWave), 0, st, d_sets, nsets, d_base, total_rows, ct, seg,
+                           flops_row, sbound, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct, part, sm.count);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
     }

@@ -141,6 +141,51 @@ def test_overlap_wide_partition_several_chunks_per_workgroup(lib):
     assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "multi-chunk partition")
 
 
+def _sliced_a(rng, n, m):
+    """Rows of four kinds over m columns: spread over all of them, confined
+    to one narrow range (one slice), empty, and one entry at column m - 1;
+    a pool of shared columns gives every kind overlaps."""
+    pool = np.unique(np.concatenate([rng.choice(m, 400, replace=False), [0, m - 1]]))
+    rows, cols = [], []
+    for i in range(n):
+        kind = i % 7
+        if kind == 0:
+            c = np.zeros(0, np.int64)
+        elif kind == 1:
+            lo = int(rng.integers(0, m - 3000))
+            c = lo + rng.choice(3000, 25, replace=False)
+        elif kind == 2:
+            c = np.array([m - 1])
+        else:
+            c = np.concatenate([rng.choice(pool, 12), rng.integers(0, m, int(rng.integers(1, 90)))])
+        c = np.unique(c)
+        rows.append(np.full(c.size, i)); cols.append(c)
+    rows, cols = np.concatenate(rows), np.concatenate(cols).astype(np.int32)
+    return synth.coo_to_csr(n, m, rows, cols, rng.integers(0, 20000, rows.size).astype(np.int32))
+
+
+@pytest.mark.parametrize("m", [pytest.param((1 << 21) - 1, id="unsliced-narrow"), pytest.param(1 << 21, id="8-slices"),
+                               pytest.param(5 * (1 << 21) + 3, id="24-slices"), pytest.param(1 << 25, id="64-slices"),
+                               pytest.param((1 << 25) + 1, id="unsliced-wide")])
+def test_overlap_sliced_segments(lib, m):
+    """2^21 .. 2^25 columns: the segment pass runs per column slice (8 to 64
+    slices of at most 2^19 columns); one column fewer or more and it runs per
+    row."""
+    A = _sliced_a(np.random.default_rng(31), 3001, m)
+    assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), f"sliced m={m}")
+    assert_overlap_equal(_run_overlap(lib, A, 2), oracle.overlap(A, 2), f"sliced m={m} ms 2")
+
+
+def test_overlap_batched_sliced_segments(lib):
+    """Sets of 1.5e6, 2e3 and 1.5e6 columns: together they are wide enough
+    for the sliced segment pass, whose slices then cut across sets."""
+    rng = np.random.default_rng(32)
+    sets = [_sliced_a(rng, 700, 1500000), synth.random_a(rng, 60, 2000, 0.01), _sliced_a(rng, 900, 1500001)]
+    Cs = lib.overlap_batched([lib.CSRTensors.from_numpy(a, _dev()) for a in sets], [1, 1, 2])
+    for s, (a, ms) in enumerate(zip(sets, [1, 1, 2])):
+        assert_overlap_equal(Cs[s], oracle.overlap(a, ms), f"set {s}")
+
+
 def test_overlap_empty_rows_and_matrix(lib):
     A = synth.CSR(4, 7, np.zeros(5, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
     C = _run_overlap(lib, A, 1)
