@@ -260,27 +260,41 @@ def cpu_baseline(w, budget_s: float):
     a = np.bincount(A.col, minlength=A.ncols).astype(np.int64)
     row_products = np.add.reduceat(a[A.col], A.rowptr[:-1]) if A.nnz else np.zeros(A.nrows, np.int64)
     row_products[np.diff(A.rowptr) == 0] = 0
-    # calibrate on a few rows, then size the sample to ~budget/2 seconds
+    # every call first builds A^T (a fixed cost, timed on an empty row
+    # selection); the product rate comes from a few rows beyond that, and
+    # the sample is sized to about budget/2 seconds in all
     t0 = time.perf_counter()
-    oracle.overlap(A, w.min_shared, rows=np.arange(min(50, A.nrows)))
+    oracle.overlap(A, w.min_shared, rows=np.arange(0))
+    t_fixed = time.perf_counter() - t0
+    ncal = min(200, A.nrows)
+    t0 = time.perf_counter()
+    oracle.overlap(A, w.min_shared, rows=np.arange(ncal))
     t_cal = time.perf_counter() - t0
-    prod_cal = int(row_products[:min(50, A.nrows)].sum())
-    rate = prod_cal / max(t_cal, 1e-6)
-    want = rate * budget_s * 0.5
+    prod_cal = int(row_products[:ncal].sum())
+    rate = prod_cal / max(t_cal - t_fixed, 1e-3)
+    want = rate * max(budget_s * 0.5 - t_fixed, 1.0)
     csum = np.cumsum(row_products)
-    nrows = int(min(A.nrows, max(50, np.searchsorted(csum, want) + 1)))
+    nrows = int(min(A.nrows, max(ncal, np.searchsorted(csum, want) + 1)))
     rows = np.arange(nrows)
-    t0 = time.perf_counter()
-    oracle.overlap(A, w.min_shared, rows=rows)
-    t_ov = time.perf_counter() - t0
     prod = int(row_products[:nrows].sum())
-    t0 = time.perf_counter()
-    _, _, _, walks = oracle.transitive_reduce(w.R, w.fuzz, with_walks=True)
-    t_tr = time.perf_counter() - t0
-    value = (prod + walks) / (t_ov + t_tr)
+    # a whole step shorter than budget/2 is run again until the sample
+    # reaches it
+    reps, t_ov, t_tr, walks = 0, 0.0, 0.0, 0
+    while True:
+        t0 = time.perf_counter()
+        oracle.overlap(A, w.min_shared, rows=rows)
+        t_ov += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, _, _, walks = oracle.transitive_reduce(w.R, w.fuzz, with_walks=True)
+        t_tr += time.perf_counter() - t0
+        reps += 1
+        if nrows < A.nrows or t_ov + t_tr >= budget_s * 0.5 or reps >= 8:
+            break
+    value = reps * (prod + walks) / (t_ov + t_tr)
+    times = f" x{reps} (whole step)" if reps > 1 else ""
     return {"value": value, "unit": "products/s", "cores": 1, "kind": "oracle",
-            "sample": f"A*A^T rows 0..{nrows - 1} of {A.nrows} ({prod} products, {t_ov:.1f} s) + "
-                      f"full reduction of R ({w.R.nnz} entries, {walks} walks, {t_tr:.1f} s); "
+            "sample": f"A*A^T rows 0..{nrows - 1} of {A.nrows} ({prod} products) + full reduction of R "
+                      f"({w.R.nnz} entries, {walks} walks){times}: {t_ov:.1f} s + {t_tr:.1f} s; "
                       f"plain C -O2, single thread"}
 
 
