@@ -100,16 +100,22 @@ class Arena {
     std::vector<void*> outputs_;
 };
 
-// Pinned host staging per host thread.  begin() waits until the previous
-// call's uploads from it have executed.
+// Pinned host staging per host thread: a ring of slots, one per call.
+// reserve() moves to the next slot and waits only until that slot's last
+// call (kStageSlots calls back) has executed its uploads and readbacks, so
+// the host can queue a call while the previous ones still run.
+constexpr int kStageSlots = 4;
 struct HostStage {
-    void* ptr = nullptr;
+    void* ptr = nullptr;   // the current slot
     size_t bytes = 0;
-    hipEvent_t last_use = nullptr;
+    int cur = -1;
+    void* slot_ptr[kStageSlots] = {};
+    size_t slot_bytes[kStageSlots] = {};
+    hipEvent_t slot_use[kStageSlots] = {};
     int reserve(size_t need);
 };
 HostStage& host_stage();
-int stage_done(hipStream_t s);       // record that the stage has been consumed
+int stage_done(hipStream_t s);       // record that the current slot has been consumed
 
 int sync_stream(hipStream_t s);       // hipStreamSynchronize + counter
 

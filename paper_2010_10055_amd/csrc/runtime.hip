@@ -120,22 +120,27 @@ HostStage& host_stage() {
 }
 
 int HostStage::reserve(size_t need) {
-    if (last_use) DB_HIP(hipEventSynchronize(last_use));
-    if (need <= bytes) return DIBELLA_OK;
-    if (ptr) DB_HIP(hipHostFree(ptr));
-    ptr = nullptr;
-    bytes = 0;
-    size_t cap = 4096;
-    while (cap < need) cap <<= 1;
-    DB_HIP(hipHostMalloc(&ptr, cap, hipHostMallocDefault));
-    bytes = cap;
+    cur = (cur + 1) % kStageSlots;
+    if (slot_use[cur]) DB_HIP(hipEventSynchronize(slot_use[cur]));
+    if (need > slot_bytes[cur]) {
+        if (slot_ptr[cur]) DB_HIP(hipHostFree(slot_ptr[cur]));
+        slot_ptr[cur] = nullptr;
+        slot_bytes[cur] = 0;
+        size_t cap = 4096;
+        while (cap < need) cap <<= 1;
+        DB_HIP(hipHostMalloc(&slot_ptr[cur], cap, hipHostMallocDefault));
+        slot_bytes[cur] = cap;
+    }
+    ptr = slot_ptr[cur];
+    bytes = slot_bytes[cur];
     return DIBELLA_OK;
 }
 
 int stage_done(hipStream_t s) {
     HostStage& st = host_stage();
-    if (!st.last_use) DB_HIP(hipEventCreateWithFlags(&st.last_use, hipEventDisableTiming));
-    DB_HIP(hipEventRecord(st.last_use, s));
+    if (st.cur < 0) return DIBELLA_OK;
+    if (!st.slot_use[st.cur]) DB_HIP(hipEventCreateWithFlags(&st.slot_use[st.cur], hipEventDisableTiming));
+    DB_HIP(hipEventRecord(st.slot_use[st.cur], s));
     return DIBELLA_OK;
 }
 
