@@ -219,6 +219,26 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
     print(f"summaries written to {PROFILES}")
 
 
+def copy_rate() -> float:
+    """GB/s of a 1 GiB device-to-device copy (1 GiB read + 1 GiB written),
+    best of five."""
+    import torch
+    x = torch.ones(CALIB_BYTES // 4, dtype=torch.int32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(5):
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    return 2 * CALIB_BYTES / (best * 1e-3) / 1e9
+
+
 def gather_probe():
     """Random 8-byte gathers (torch indexing: indices read in order, one
     random element each) over arrays from 2 MB to 4 GB: the rate at which the
@@ -296,6 +316,37 @@ def cpu_baseline(w, budget_s: float):
             "sample": f"A*A^T rows 0..{nrows - 1} of {A.nrows} ({prod} products) + full reduction of R "
                       f"({w.R.nnz} entries, {walks} walks){times}: {t_ov:.1f} s + {t_tr:.1f} s; "
                       f"plain C -O2, single thread"}
+
+
+def cpu_parallel(w, threads: int = 0):
+    """The same oracle on all host cores: every A*A^T row once, split into one
+    contiguous row range per thread (balanced by products); each thread makes
+    one oracle call, which builds its own A^T first.  ctypes releases the
+    interpreter lock during the call, so the threads run in parallel."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    if threads <= 0:
+        try:
+            threads = len(os.sched_getaffinity(0))
+        except AttributeError:
+            threads = os.cpu_count() or 1
+        threads = max(1, min(16, threads))
+    A = w.A
+    a = np.bincount(A.col, minlength=A.ncols).astype(np.int64)
+    row_products = np.add.reduceat(a[A.col], A.rowptr[:-1]) if A.nnz else np.zeros(A.nrows, np.int64)
+    row_products[np.diff(A.rowptr) == 0] = 0
+    csum = np.cumsum(row_products)
+    total = int(csum[-1]) if csum.size else 0
+    cuts = [0] + [int(np.searchsorted(csum, total * q / threads)) for q in range(1, threads)] + [A.nrows]
+    ranges = [np.arange(cuts[q], cuts[q + 1]) for q in range(threads) if cuts[q + 1] > cuts[q]]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(len(ranges)) as ex:
+        list(ex.map(lambda r: oracle.overlap(A, w.min_shared, rows=r), ranges))
+    t = time.perf_counter() - t0
+    return {"value": total / t, "unit": "products/s", "cores": len(ranges), "kind": "oracle",
+            "sample": f"every A*A^T row ({total} products) in {len(ranges)} row ranges, one thread and one "
+                      f"A^T build each: {t:.1f} s; plain C -O2"}
 
 
 def batch_compare(db, synth, nsets: int, steps: int, graph: bool, tune_budget: float = 0.0):
@@ -509,6 +560,10 @@ def main():
                 "avg_launch_ms": round(dom_ms / launches[dominant], 4)}
     if dominant == "numeric_phase":
         roofline["kernel_launches_per_phase"] = launches.get("numeric")
+    if traffic:
+        roofline["overfetch"] = round(traffic / (pb[dominant] / launches[dominant]), 3)
+    # what this machine streams (a 1 GiB device copy, read + write) beside the published peak
+    roofline["copy_GBps_measured"] = round(copy_rate(), 1)
     kernels = {k: {"ms_per_step": round(per_step_ms[k], 4), "launches_per_step": launches[k],
                    "model_GBps": (round(pb[k] / (per_step_ms[k] * 1e-3) / 1e9, 1) if k in pb else None)}
                for k in per_step_ms}
@@ -525,10 +580,12 @@ def main():
         log(f"serving comparison ({args.serve_jobs} jobs) ...")
         served = serve_compare(args.serve_jobs)
 
-    cpu = None
+    cpu = cpu_par = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(w, args.cpu_budget)
+        log("cpu baseline on all host cores (oracle, row ranges on threads) ...")
+        cpu_par = cpu_parallel(w)
 
     out = {
         "metric": "semiring products/s (A*A^T multiplies + transitive-reduction walks)",
@@ -546,11 +603,16 @@ def main():
                                              "segments", "sym_bits", "sym_hash",
                                              "numeric_phase" if "numeric_phase" in per_step_ms else "numeric",
                                              "esc")) * 1e-3),
+        "overlap_products_per_s_numeric_phase": (products / (per_step_ms["numeric_phase"] * 1e-3)
+                                                 if "numeric_phase" in per_step_ms else None),
+        "tr_walks_per_s_mark": (triples / (per_step_ms["tr_mark"] * 1e-3) if "tr_mark" in per_step_ms else None),
+        "tr_nnz_trace": [int(x) for x in tr_stats["nnz_trace"]],
         "host_syncs": {"overlap": ov_stats["host_syncs"], "tr": tr_stats["host_syncs"]},
         "roofline": roofline,
         "batch": batch,
         "serve": served,
         "cpu_baseline": cpu,
+        "cpu_parallel": cpu_par,
     }
     print(json.dumps(out), flush=True)
 

@@ -104,7 +104,7 @@ int dibella_set_tuning(const dibella_tuning* t) {
         set_error("dibella_set_tuning: value outside the supported range");
         return DIBELLA_EINVAL;
     }
-    tuning() = *t;
+    tuning_store(*t);
     return DIBELLA_OK;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -38,7 +39,8 @@ std::string& error_slot();
 // ---------------------------------------------------------------------------
 // Tuning (process wide) and per-thread statistics
 // ---------------------------------------------------------------------------
-dibella_tuning& tuning();
+dibella_tuning tuning();                    // a copy of the process-wide tunables (under a lock)
+void tuning_store(const dibella_tuning& t);
 dibella_stats& stats();
 
 // ---------------------------------------------------------------------------

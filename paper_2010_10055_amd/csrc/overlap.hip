@@ -1481,8 +1481,9 @@ static int check_lds(size_t lds) {
 
 template <int BLOCK>
 static int allow_lds_ov() {
-    static bool done = false;
-    if (!done) {
+    // the attribute calls are idempotent: threads racing here may both make them
+    static std::atomic<bool> done{false};
+    if (!done.load(std::memory_order_acquire)) {
         DB_HIP(hipFuncSetAttribute((const void*)k_ov_sym_hash<BLOCK>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)kLdsLimit));
         DB_HIP(hipFuncSetAttribute((const void*)k_ov_sym_bits<BLOCK>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1491,7 +1492,7 @@ static int allow_lds_ov() {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
         DB_HIP(hipFuncSetAttribute((const void*)k_ov_numeric<BLOCK, false>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-        done = true;
+        done.store(true, std::memory_order_release);
     }
     return DIBELLA_OK;
 }
@@ -1520,13 +1521,15 @@ struct SymArgs {
 // Workgroups of a persistent launch: what fits the GPU at once (LDS and
 // waves per CU), never more than the items.
 static int persistent_grid(int count, int block, size_t lds) {
-    static int cus = 0;
+    static std::atomic<int> cus_cached{0};
+    int cus = cus_cached.load(std::memory_order_relaxed);
     if (!cus) {
         int dev = 0;
         hipDeviceProp_t prop;
         cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
                   ? prop.multiProcessorCount
                   : 256;
+        cus_cached.store(cus, std::memory_order_relaxed);
     }
     const int by_lds = (int)std::max<size_t>(1, (160 * 1024) / (lds + 1024));
     const int by_waves = std::max(1, 2048 / block);
@@ -1848,8 +1851,8 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, ar));
-        static bool lds_ok = false;
-        if (!lds_ok) {
+        static std::atomic<bool> lds_ok{false};
+        if (!lds_ok.load(std::memory_order_acquire)) {
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kLdsLimit));
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<false, false>,
@@ -1858,7 +1861,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            lds_ok = true;
+            lds_ok.store(true, std::memory_order_release);
         }
         DB_TRY(timing_begin(kPhPartScatter, st, &tok));
         hipLaunchKernelGGL(k_ov_part_scatter, dim3((unsigned)npart), dim3(kPartBlock), part_scatter_lds(nbuckets),

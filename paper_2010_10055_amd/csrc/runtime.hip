@@ -3,6 +3,7 @@
 #include "common.hpp"
 
 #include <cstring>
+#include <mutex>
 
 namespace dibella {
 
@@ -15,13 +16,30 @@ std::string& error_slot() {
 }
 void set_error(const std::string& msg) { error_slot() = msg; }
 
-dibella_tuning& tuning() {
+namespace {
+std::mutex& tuning_mutex() {
+    static std::mutex mu;
+    return mu;
+}
+dibella_tuning& tuning_slot() {
     static dibella_tuning t = {
         /*sym_block*/ 256, /*num_block*/ 256, /*tr_block*/ 128,
         /*sym_first_log2*/ 12, /*sym_max_log2*/ 14, /*num_max_entries*/ 5120,
         /*load_pct*/ 75, /*tr_lds_cap*/ 4096, /*tr_graph_passes*/ 4,
         /*bits_max_words*/ 8192};
     return t;
+}
+}  // namespace
+
+// Each call takes one copy at its start, so a concurrent set_tuning never
+// changes the shapes within a call.
+dibella_tuning tuning() {
+    std::lock_guard<std::mutex> lock(tuning_mutex());
+    return tuning_slot();
+}
+void tuning_store(const dibella_tuning& t) {
+    std::lock_guard<std::mutex> lock(tuning_mutex());
+    tuning_slot() = t;
 }
 
 dibella_stats& stats() {

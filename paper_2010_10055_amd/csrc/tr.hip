@@ -509,6 +509,7 @@ __global__ void k_tr_ent_base(const TrSet* __restrict__ sets, int nsets, const i
 // Host driver
 // ---------------------------------------------------------------------------
 struct TrBuffers {
+    int block;   // workgroup width of the mark kernel (the call's tuning)
     const TrSet* d_sets;
     const int64_t* d_base;
     int nsets;
@@ -533,18 +534,18 @@ struct TrBuffers {
 
 template <int BLOCK>
 static int allow_lds() {
-    static bool done = false;
-    if (!done) {
+    static std::atomic<bool> done{false};   // idempotent: racing threads may both set it
+    if (!done.load(std::memory_order_acquire)) {
         DB_HIP(hipFuncSetAttribute((const void*)k_tr_mark<BLOCK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)kTrLdsLimit));
-        done = true;
+        done.store(true, std::memory_order_release);
     }
     return DIBELLA_OK;
 }
 
 // Called outside graph capture so that the attribute calls are not recorded.
-static int prepare_pass_kernels() {
-    switch (tuning().tr_block) {
+static int prepare_pass_kernels(int block) {
+    switch (block) {
         case 64: return allow_lds<64>();
         case 128: return allow_lds<128>();
         case 512: return allow_lds<512>();
@@ -578,7 +579,7 @@ static int launch_pass_marks(const TrBuffers& B, int src, hipStream_t st) {
 
 // Enqueue one pass reading buffer `src` and writing buffer 1 - src.
 static int enqueue_pass(const TrBuffers& B, int src, hipStream_t st) {
-    switch (tuning().tr_block) {
+    switch (B.block) {
         case 64: DB_TRY(launch_pass_marks<64>(B, src, st)); break;
         case 128: DB_TRY(launch_pass_marks<128>(B, src, st)); break;
         case 512: DB_TRY(launch_pass_marks<512>(B, src, st)); break;
@@ -689,6 +690,7 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
 
     TrBuffers B;
     std::memset(&B, 0, sizeof(B));
+    B.block = tn.tr_block;
     TrSet* d_sets;
     int64_t* d_base;
     int32_t* d_flags;
@@ -791,7 +793,7 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
         for (int b = 0; b < 3; ++b) B.grid[b] = std::min(h_state->bin_count[b], 256 * occ * 4);
     }
 
-    DB_TRY(prepare_pass_kernels());
+    DB_TRY(prepare_pass_kernels(B.block));
     if (h_state->any_active) {
         if (flags & DIBELLA_TR_USE_GRAPH) {
             int U = std::max(1, std::min(16, tn.tr_graph_passes));

@@ -277,6 +277,43 @@ def test_overlap_deterministic(lib):
         assert torch.equal(getattr(C1, f), getattr(C2, f))
 
 
+def test_calls_from_two_threads_on_two_streams(lib):
+    """Two host threads, each on its own stream, run overlap and reduction
+    calls on different inputs at the same time; every result matches the
+    oracle."""
+    import threading
+    ws = [synth.make_workload("tiny", seed=900 + t) for t in range(2)]
+    refs = [(oracle.overlap(w.A, 1), oracle.transitive_reduce(w.R, w.fuzz)) for w in ws]
+    errors = []
+
+    def work(t):
+        try:
+            dev = _dev()
+            stream = torch.cuda.Stream(device=dev)
+            A = lib.CSRTensors.from_numpy(ws[t].A, dev)
+            R = lib.CSRTensors.from_numpy(ws[t].R, dev)
+            stream.wait_stream(torch.cuda.current_stream(dev))   # the uploads
+            with torch.cuda.stream(stream):
+                for rep in range(6):
+                    C = lib.overlap(A, 1)
+                    S, it = lib.transitive_reduce(R, ws[t].fuzz)
+                    stream.synchronize()
+                    (cref, (sref, it_ref, _)) = refs[t]
+                    assert np.array_equal(_np(C.col), cref.col) and np.array_equal(_np(C.seed), cref.seed)
+                    assert np.array_equal(_np(S.col), sref.col) and np.array_equal(_np(S.val), sref.val)
+                    assert it == it_ref
+        except Exception as e:   # reported by the main thread
+            errors.append(f"thread {t}: {e!r}")
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    assert not any(th.is_alive() for th in threads), "a thread did not finish"
+    assert not errors, errors
+
+
 @pytest.mark.parametrize("case", ["unsorted", "colrange", "negative", "rowptr", "overlap_rows", "min_shared"])
 def test_overlap_rejects_malformed(lib, case):
     rng = np.random.default_rng(12)
