@@ -186,6 +186,11 @@ template <class T>
 __device__ __forceinline__ T gload(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;
 }
+// The same, marked as streamed (read once).
+template <class T>
+__device__ __forceinline__ T gload_nt(const T* p) {
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+}
 
 __device__ __forceinline__ int32_t atomic_add(int32_t* p, int32_t v) { return atomicAdd(p, v); }
 __device__ __forceinline__ uint32_t atomic_add(uint32_t* p, uint32_t v) { return atomicAdd(p, v); }

@@ -186,6 +186,15 @@ struct SliceMap {
     int32_t count;   // 0: no slices
     uint32_t mul;
 };
+
+// A^T column records (8 B per column): (start << 24) | length; a column of
+// exactly two pairs (r0, p0), (r1, p1) instead holds
+// kPairTag | ((p0 ^ p1) << 24) | (r0 ^ r1) (reads < 2^24, positions
+// < 2^31): an entry of that column, knowing its own read and position,
+// recovers the other pair.  The segment word of such an entry is
+// kPairTag | (position << 24) | read of the other pair, so the walk has both
+// products of the entry (itself and the other read) without gathering A^T.
+constexpr uint64_t kPairTag = 1ull << 63;
 __host__ __device__ __forceinline__ int slice_of(int64_t c, SliceMap sm) {
     return (int)(((uint64_t)c * sm.mul) >> 32);
 }
@@ -290,10 +299,24 @@ __global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64
     }
 }
 
-// The A^T segment of every column, (start << 24) | length, from row pointers.
-__global__ void k_ov_ct_from_rowptr(const uint32_t* __restrict__ t_rowptr, int64_t total_m, uint64_t* __restrict__ ct) {
+// Column records (segments only) from row pointers.
+__global__ void k_ov_rec_from_rowptr(const uint32_t* __restrict__ t_rowptr, int64_t total_m,
+                                     uint64_t* __restrict__ rec) {
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total_m; c += (int64_t)gridDim.x * blockDim.x)
-        ct[c] = ((uint64_t)t_rowptr[c] << 24) | (uint64_t)(t_rowptr[c + 1] - t_rowptr[c]);
+        rec[c] = ((uint64_t)t_rowptr[c] << 24) | (uint64_t)(t_rowptr[c + 1] - t_rowptr[c]);
+}
+
+// The segment word of an A entry (set-local read i, position p) from its
+// column's record, and the entry's product count.
+__device__ __forceinline__ uint64_t seg_word(uint64_t r, uint32_t i, int32_t p, int64_t* len) {
+    if (r & kPairTag) {
+        *len = 2;
+        const uint64_t read = (r ^ i) & 0xFFFFFFull;
+        const uint64_t pos = ((r >> 24) ^ (uint64_t)(uint32_t)p) & 0x7FFFFFFFull;
+        return kPairTag | (pos << 24) | read;
+    }
+    *len = (int64_t)(r & 0xFFFFFFull);
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -307,9 +330,9 @@ __global__ void k_ov_ct_from_rowptr(const uint32_t* __restrict__ t_rowptr, int64
 //                     written out as runs, so that stores coalesce;
 //   k_ov_bucket_sort  one workgroup per bucket counts its pairs per column in
 //                     LDS (2^low bins, in sweeps of 2^15 for wider buckets),
-//                     scans the counts into each column's A^T segment,
-//                     ct[c] = (start << 24) | length, and places each
-//                     (read, position).
+//                     scans the counts into the column starts, places each
+//                     (read, position) and writes every column's record
+//                     (its segment, or its two pairs; see kPairTag).
 // The order inside an A^T row is left free: nothing downstream depends on it.
 // Every pass takes the same chunks, so a malformed A (reported after the
 // first synchronisation) can only over-count: writes are clamped to `cap`.
@@ -427,10 +450,12 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
 
 // STAGE: each sweep's pairs are placed in LDS first and written out as one
 // contiguous run (coalesced) when they fit kStageCap; sweeps of 2^sub columns.
+// Only a staged sweep writes the two-pair records (otherwise every column
+// gets its segment).
 template <bool SWEEPS, bool STAGE>
 __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
     const int64_t* __restrict__ offsets, int64_t nchunks, int low, int sub_bits, int64_t total_m, int64_t cap,
-    const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ ct,
+    const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ rec,
     uint64_t* __restrict__ at) {
     // offsets: bucket-major over the partition's workgroups (nchunks of them)
     extern __shared__ __align__(16) unsigned char smem[];
@@ -477,10 +502,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
             if (c >= bins) break;
             const uint32_t n_c = hist[c];
             const int64_t start = base + run;
-            if (col0 + c < total_m) ct[col0 + c] = ((uint64_t)start << 24) | (uint64_t)n_c;
             hist[c] = (uint32_t)start;   // becomes the cursor of column c
             run += n_c;
         }
+        const bool staged = STAGE && tot <= kStageCap;
         __syncthreads();
         for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
             uint32_t kk[kPartIlp], pos[kPartIlp];
@@ -497,7 +522,6 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
                 mine[q] = e0 + q * kBucketBlock + threadIdx.x < be && (!SWEEPS || (int)(kk[q] >> sub) == h);
                 pos[q] = atomicAdd(&hist[kk[q] & smask], mine[q] ? 1u : 0u);
             }
-            const bool staged = STAGE && tot <= kStageCap;
 #pragma unroll
             for (int q = 0; q < kPartIlp; ++q) {
                 if (!mine[q]) continue;
@@ -505,10 +529,25 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
                 else if (pos[q] < cap) at[pos[q]] = pp[q];
             }
         }
-        if (STAGE && tot <= kStageCap) {
-            __syncthreads();
+        __syncthreads();
+        if (staged)
             for (int64_t q = threadIdx.x; q < tot; q += kBucketBlock)
                 if (base + q < cap) at[base + q] = stage[q];
+        // column records: the cursors now hold the column ends, so column c
+        // spans [end of c - 1, end of c); a column of two pairs carries them
+        // (from the stage) so that a walk needs no A^T gather for it
+        for (int q = 0; q < per; ++q) {
+            const int c = c0 + q;
+            if (c >= bins || col0 + c >= total_m) break;
+            const uint32_t end = hist[c];
+            const uint32_t start = c ? hist[c - 1] : (uint32_t)base;
+            const uint32_t n_c = end - start;
+            uint64_t r = ((uint64_t)start << 24) | (uint64_t)n_c;
+            if (staged && n_c == 2) {
+                const uint64_t x = stage[start - base] ^ stage[start - base + 1];   // pairs: (pos << 32) | read
+                r = kPairTag | ((x >> 32) << 24) | (x & 0xFFFFFFull);
+            }
+            rec[col0 + c] = r;
         }
         base += tot;
         __syncthreads();
@@ -530,9 +569,9 @@ constexpr int kSegIlp = 8;
 
 // Sliced segment pass.  Workgroups are handed to the XCDs round-robin
 // (workgroup b runs on XCD b mod 8), so workgroup b takes slice
-// 8 * round + (b mod 8): at any time each XCD gathers column segments
-// (ct) from one slice only (at most 4 MB), which its L2 then holds, instead
-// of every XCD gathering from all of them.  A workgroup covers kSliceRows
+// 8 * round + (b mod 8): at any time each XCD gathers column records from
+// one slice only (at most 4 MB), which its L2 then holds, instead of every
+// XCD gathering from all of them.  A workgroup covers kSliceRows
 // rows: each wave takes its share of the rows, kSliceIlp at a time, one
 // lane per entry of a row's sub-range.  Products per (slice, row) go to
 // part[slice * rows + row]; k_ov_scatter sums them.
@@ -540,16 +579,21 @@ constexpr int kSliceRows = 64;
 constexpr int kSliceBlock = 256;
 constexpr int kSliceIlp = 8;
 constexpr int kMaxSlices = 64;
-constexpr int64_t kSliceCols = int64_t(1) << 19;   // 4 MB of column segments: one L2
+constexpr int64_t kSliceCols = int64_t(1) << 19;   // 4 MB of column records: one L2
+// a readable word for the loads of rows with no entries in a slice (their
+// values are never used)
+__device__ const int32_t kSliceNone[1] = {0};
 
 __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
-    int64_t groups, SliceMap sm, const int32_t* __restrict__ bnd, const uint64_t* __restrict__ ct,
+    int64_t groups, SliceMap sm, const int32_t* __restrict__ bnd, const uint64_t* __restrict__ rec,
     uint64_t* __restrict__ seg, int64_t* __restrict__ part) {
     __shared__ int32_t s_len[kSliceRows];
     __shared__ int64_t s_first[kSliceRows];        // global entry of the row's first entry in the slice
     __shared__ const int32_t* s_col[kSliceRows];   // its column
+    __shared__ const int32_t* s_val[kSliceRows];   // its position
     __shared__ int64_t s_cb[kSliceRows], s_m[kSliceRows];
+    __shared__ uint32_t s_i[kSliceRows];            // set-local row
     const int64_t b = blockIdx.x;
     const int sl = (int)((b / 8) / groups) * 8 + (int)(b % 8);
     const int64_t row0 = ((b / 8) % groups) * kSliceRows;
@@ -559,9 +603,11 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
         const int64_t g = row0 + r;
         s_len[r] = 0;
         s_first[r] = 0;
-        s_col[r] = nullptr;
+        s_col[r] = kSliceNone;
+        s_val[r] = kSliceNone;
         s_cb[r] = 0;
         s_m[r] = 0;
+        s_i[r] = 0;
         if (g < total_rows) {
             const int s = find_set(set_base, nsets, g);
             const OvSet& S = sets[s];
@@ -574,9 +620,13 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
                 const int32_t z = min(max(rb[sl + 1], a), L);
                 s_len[r] = z - a;
                 s_first[r] = S.nnz_base + lo + a;
-                s_col[r] = S.a_col + lo + a;
+                if (z > a) {
+                    s_col[r] = S.a_col + lo + a;
+                    s_val[r] = S.a_val + lo + a;
+                }
                 s_cb[r] = S.col_base;
                 s_m[r] = S.m;
+                s_i[r] = (uint32_t)i;
             }
         }
     }
@@ -599,21 +649,30 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
 #pragma unroll
         for (int u = 0; u < kSliceIlp; ++u) fl[u] = 0;
         for (int o = lane; o - lane < most; o += kWave) {
-            int32_t kk[kSliceIlp];
+            // unconditional loads from clamped addresses: no load waits on another
+            int32_t kk[kSliceIlp], vv[kSliceIlp];
 #pragma unroll
-            for (int u = 0; u < kSliceIlp; ++u)
-                kk[u] = o < len[u] ? __builtin_nontemporal_load(s_col[w * RPW + j0 + u] + o) : -1;
-            uint64_t sg[kSliceIlp];
+            for (int u = 0; u < kSliceIlp; ++u) {
+                const int idx = min(o, max(len[u] - 1, 0));
+                kk[u] = gload_nt(s_col[w * RPW + j0 + u] + idx);
+                vv[u] = gload_nt(s_val[w * RPW + j0 + u] + idx);
+            }
+            uint64_t rc[kSliceIlp];
+            bool ok[kSliceIlp];
 #pragma unroll
             for (int u = 0; u < kSliceIlp; ++u) {
                 const int r = w * RPW + j0 + u;
-                sg[u] = (kk[u] >= 0 && kk[u] < s_m[r]) ? ct[s_cb[r] + kk[u]] : 0ull;   // invalid: empty
+                ok[u] = kk[u] >= 0 && kk[u] < s_m[r];
+                rc[u] = gload(rec + (ok[u] ? s_cb[r] + kk[u] : 0));
             }
 #pragma unroll
             for (int u = 0; u < kSliceIlp; ++u) {
                 if (o >= len[u]) continue;
-                fl[u] += (int64_t)(sg[u] & 0xFFFFFFull);
-                seg[s_first[w * RPW + j0 + u] + o] = sg[u];   // ordinary store: L2 merges the lines
+                const int r = w * RPW + j0 + u;
+                int64_t n_p;
+                const uint64_t sg = seg_word(ok[u] ? rc[u] : 0ull, s_i[r], vv[u], &n_p);   // invalid column: empty
+                fl[u] += n_p;
+                seg[s_first[r] + o] = sg;   // ordinary store: L2 merges the lines
             }
         }
 #pragma unroll
@@ -628,7 +687,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
-    const uint64_t* __restrict__ ct, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
+    const uint64_t* __restrict__ rec, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
     int64_t* __restrict__ sbound, int32_t* __restrict__ sym_list,
     OvCounters* __restrict__ ctr, int first_log2, int load_pct, const int64_t* __restrict__ part, int nslices) {
     __shared__ int32_t s_cnt[kMaxLog2], s_base[kMaxLog2];
@@ -661,23 +720,28 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
             if (lane < nslices) fl = part[(int64_t)lane * total_rows + g];
         } else if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
             for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kSegIlp) {
-                int32_t kk[kSegIlp];
-                uint64_t sg[kSegIlp];
+                int32_t kk[kSegIlp], vv[kSegIlp];
+                uint64_t rc[kSegIlp];
 #pragma unroll
-                for (int q = 0; q < kSegIlp; ++q) kk[q] = gload(S.a_col + min(e0 + q * kWave + lane, hi - 1));
+                for (int q = 0; q < kSegIlp; ++q) {
+                    kk[q] = gload(S.a_col + min(e0 + q * kWave + lane, hi - 1));
+                    vv[q] = gload(S.a_val + min(e0 + q * kWave + lane, hi - 1));
+                }
 #pragma unroll
                 for (int q = 0; q < kSegIlp; ++q) {
                     const int32_t k = kk[q];
                     const int64_t gk = (k >= 0 && k < S.m) ? S.col_base + k : 0;   // in range for the load
-                    sg[q] = ct[gk];
+                    rc[q] = rec[gk];
                 }
 #pragma unroll
                 for (int q = 0; q < kSegIlp; ++q) {
                     const int64_t e = e0 + q * kWave + lane;
                     if (e >= hi) continue;
-                    if (!(kk[q] >= 0 && kk[q] < S.m)) sg[q] = 0;   // invalid column: empty segment
-                    fl += (int64_t)(sg[q] & 0xFFFFFFull);
-                    seg[S.nnz_base + e] = sg[q];
+                    if (!(kk[q] >= 0 && kk[q] < S.m)) rc[q] = 0ull;   // invalid column: empty segment
+                    int64_t n_p;
+                    const uint64_t sg = seg_word(rc[q], (uint32_t)i, vv[q], &n_p);
+                    fl += n_p;
+                    seg[S.nnz_base + e] = sg;
                 }
             }
         }
@@ -758,9 +822,20 @@ __device__ __forceinline__ void walk_load(const uint64_t* __restrict__ rseg, int
     }
 }
 
-// Numbers the chunk's products (t-major) from its loaded segments, writes
-// c_base and returns the chunk's product count.  Each thread keeps its
+// Numbers the chunk's products (t-major) from its loaded segment words,
+// writes c_base and returns the chunk's product count.  An entry whose word
+// carries its column's other pair (kPairTag) has two products, itself and
+// that pair; its c_base holds the pair as kInlineBase - ((position << 24) |
+// read) (reads < 2^24, positions < 2^31), which lies at or below -2^62,
+// far below every real base (those exceed -2^31).  Each thread keeps its
 // entries' offsets and lengths for the window fills.
+constexpr int64_t kInlineBase = -(int64_t(1) << 62);
+constexpr int64_t kInlineBelow = -(int64_t(1) << 32);
+__device__ __forceinline__ int64_t inline_base(uint64_t word) { return kInlineBase - (int64_t)(word & ~kPairTag); }
+__device__ __forceinline__ int2 inline_pair(int64_t cb) {
+    const uint64_t v = (uint64_t)(kInlineBase - cb);
+    return make_int2((int)(v & 0xFFFFFFull), (int)(v >> 24));
+}
 template <int BLOCK>
 __device__ __forceinline__ int64_t walk_chunk(const uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK], int64_t* c_base,
                                               int64_t* s_tmp, int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
@@ -769,37 +844,44 @@ __device__ __forceinline__ int64_t walk_chunk(const uint64_t (&sg)[walk_chunk_of
     int64_t local = 0;
 #pragma unroll
     for (int u = 0; u < E; ++u) {
-        my_len[u] = (int64_t)(sg[u] & 0xFFFFFFull);
+        my_len[u] = (sg[u] & kPairTag) ? 2 : (int64_t)(sg[u] & 0xFFFFFFull);
         local += my_len[u];
     }
     int64_t tot;
     int64_t run = block_exclusive_sum<BLOCK>(local, s_tmp, &tot);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
-        c_base[(int)threadIdx.x * E + u] = (int64_t)(sg[u] >> 24) - run;
+        c_base[(int)threadIdx.x * E + u] = (sg[u] & kPairTag) ? inline_base(sg[u]) : (int64_t)(sg[u] >> 24) - run;
         my_off[u] = run;
         run += my_len[u];
     }
     return tot;
 }
 
-// Writes the chunk index of every product of the window [w0, w1).
+// Writes the chunk index of every product of the window [w0, w1); the
+// second product of a two-pair entry (its other pair) is flagged with bit 15.
 template <int BLOCK>
-__device__ __forceinline__ void walk_fill(uint16_t* tbuf, int64_t w0, int64_t w1,
+__device__ __forceinline__ void walk_fill(uint16_t* tbuf, const int64_t* c_base, int64_t w0, int64_t w1,
                                           const int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
                                           const int64_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
+    static_assert(walk_chunk_of(BLOCK) <= 0x8000, "chunk index below the flag bit");
 #pragma unroll
     for (int u = 0; u < E; ++u) {
+        const int idx = (int)threadIdx.x * E + u;
         const int64_t a = max(my_off[u], w0), b = min(my_off[u] + my_len[u], w1);
-        for (int64_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)((int)threadIdx.x * E + u);
+        const int64_t second = c_base[idx] <= kInlineBelow ? my_off[u] + 1 : -1;
+        for (int64_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)(idx | (q == second ? 0x8000 : 0));
     }
 }
 
+// self: the row's read; rval: the row's positions, needed only by callers
+// that use the row's own products (nullptr: their position reads 0).
 template <int BLOCK, class F>
 __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
                                               const int2* __restrict__ at, int64_t* c_base, uint16_t* tbuf,
-                                              int64_t* s_tmp, const int32_t* stop, F&& f) {
+                                              int64_t* s_tmp, const int32_t* stop, int32_t self,
+                                              const int32_t* __restrict__ rval, F&& f) {
     constexpr int CH = walk_chunk_of(BLOCK), WIN = walk_win_of(BLOCK);
     static_assert(CH % BLOCK == 0 && CH <= 65536, "chunk index kept in 16 bits");
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
@@ -815,10 +897,12 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
         walk_load<BLOCK>(rseg, nbase, nbase < L ? min(CH, L - nbase) : 0, sg);
         for (int64_t w0 = 0; w0 < tot; w0 += WIN) {
             const int64_t w1 = min(w0 + (int64_t)WIN, tot);
-            walk_fill<BLOCK>(tbuf, w0, w1, my_off, my_len);
+            walk_fill<BLOCK>(tbuf, c_base, w0, w1, my_off, my_len);
             __syncthreads();
             if (!(stop && *(volatile const int32_t*)stop)) {
                 const int64_t q0 = w0 + threadIdx.x;
+                // the loads write only their own registers (an inline value
+                // written there instead would make every later load wait)
                 int tt[PER];
                 int2 jp[PER];
 #pragma unroll
@@ -826,14 +910,23 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
                     const int64_t q = q0 + (int64_t)u * BLOCK;
                     tt[u] = -1;
                     if (q < w1) {
-                        const int t = tbuf[q - w0];
-                        tt[u] = t;
-                        jp[u] = at[c_base[t] + q];
+                        const int tv = tbuf[q - w0];
+                        const int64_t cb = c_base[tv & 0x7FFF];
+                        tt[u] = tv;
+                        if (cb > kInlineBelow) jp[u] = at[cb + q];
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < PER; ++u)
-                    if (tt[u] >= 0) f(cbase + tt[u], jp[u], done + q0 + (int64_t)u * BLOCK);
+                for (int u = 0; u < PER; ++u) {
+                    if (tt[u] < 0) continue;
+                    const int t = tt[u] & 0x7FFF;
+                    const int64_t cb = c_base[t];
+                    int2 v = jp[u];
+                    if (cb <= kInlineBelow)
+                        v = (tt[u] & 0x8000) ? inline_pair(cb)   // the column's other pair
+                                             : make_int2(self, rval ? rval[cbase + t] : 0);   // the entry itself
+                    f(cbase + t, v, done + q0 + (int64_t)u * BLOCK);
+                }
             }
             __syncthreads();
             if (stop && *(volatile const int32_t*)stop) break;
@@ -877,7 +970,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     // left out of the walk (one LDS address hit by every segment) and set
     // from its closed form, count = L
     const int32_t self = (int32_t)i;
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr,
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr,
                          [&](int, int2 jp, int64_t) {
                              if (jp.x != self) planes_mark(B, words, planes, jp.x);
                          });
@@ -953,7 +1046,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
         }
         __syncthreads();
         const int32_t self = (int32_t)i;
-        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, &s_ovf,
+        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, &s_ovf, self, nullptr,
                              [&](int, int2 jp, int64_t) {
                                  if (jp.x == self) return;   // the diagonal: added once below
                                  int fresh;
@@ -1145,7 +1238,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     }
     __syncthreads();
     const int32_t self = (int32_t)i;   // the diagonal is written from its closed form below
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr,
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr,
                          [&](int t, int2 jp, int64_t) {
                              const int32_t j = jp.x;
                              if (j == self) return;
@@ -1250,8 +1343,8 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int L = (int)(S.a_rowptr[i + 1] - lo);
     const int64_t base = esc_off[g];
     // products land at their t-major index, so the expansion is ordered by k
-    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr,
-                             [&](int t, int2 jp, int64_t q) {
+    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, (int32_t)i,
+                             S.a_val + lo, [&](int t, int2 jp, int64_t q) {
                                  keys0[base + q] = (uint32_t)jp.x;
                                  pay0[base + q] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
                              });
@@ -1777,13 +1870,13 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(ar.work_n(nsets, &d_flags));
     DB_TRY(ar.work_n(1, &d_ctr));
     DB_TRY(ar.work_n(nsets, &d_set_nnz));
-    uint64_t* ct;   // per column: A^T segment (start << 24) | length (at least one slot)
+    uint64_t* rec;   // per column: its record (at least one slot)
     uint32_t *keys_a, *keys_b;
     uint64_t *pays_a, *pays_b;
     uint64_t* seg;
     int64_t *flops_row, *nnzrow, *G, *esc_off, *sbound, *soff;
     int32_t *distinct, *sym_list, *num_list, *esc_list, *retry_list;
-    DB_TRY(ar.work_n(std::max<int64_t>(total_m, 1), &ct));
+    DB_TRY(ar.work_n(std::max<int64_t>(total_m, 1), &rec));
     DB_TRY(ar.work_n(total_nnz, &keys_a));
     DB_TRY(ar.work_n(total_nnz, &keys_b));
     DB_TRY(ar.work_n(total_nnz, &pays_b));
@@ -1829,7 +1922,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
     // empty segments where no pass writes them (the bucket sort writes every column of a non-empty A)
-    if (bucketed && total_nnz == 0) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(ct), 0, 2 * std::max<int64_t>(total_m, 1), st));
+    if (bucketed && total_nnz == 0) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(rec), 0, 2 * std::max<int64_t>(total_m, 1), st));
     else DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
     if (total_rows > 0) {
         DB_TRY(timing_begin(kPhKeys, st, &tok));
@@ -1855,8 +1948,6 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         if (!lds_ok.load(std::memory_order_acquire)) {
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<false, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
             DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, true>,
@@ -1874,15 +1965,11 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         if (low > kBucketBits)
             hipLaunchKernelGGL((k_ov_bucket_sort<true, false>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
                                (size_t)4 << kBucketBits, st, poffs, npart, low, kBucketBits, total_m, total_nnz,
-                               keys_b, pays_b, ct, pays_a);
-        else if (low > kStageBits)
+                               keys_b, pays_b, rec, pays_a);
+        else   // staged sweeps of 2^12 columns (one sweep for narrower buckets)
             hipLaunchKernelGGL((k_ov_bucket_sort<true, true>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
-                               ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, poffs, npart, low, kStageBits,
-                               total_m, total_nnz, keys_b, pays_b, ct, pays_a);
-        else
-            hipLaunchKernelGGL((k_ov_bucket_sort<false, false>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
-                               (size_t)4 << low, st, poffs, npart, low, low, total_m, total_nnz, keys_b, pays_b,
-                               ct, pays_a);
+                               ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, poffs, npart, low,
+                               std::min(low, kStageBits), total_m, total_nnz, keys_b, pays_b, rec, pays_a);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         at = reinterpret_cast<const int2*>(pays_a);
@@ -1899,12 +1986,12 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
             hipLaunchKernelGGL(k_ov_trowptr, dim3(grid_for(total_nnz, 256, 1 << 16)), dim3(256), 0, st, tkeys,
                                total_nnz, total_m, t_rowptr);
             DB_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_ov_ct_from_rowptr, dim3(grid_for(total_m, 256, 1 << 16)), dim3(256), 0, st,
-                               t_rowptr, total_m, ct);
+            hipLaunchKernelGGL(k_ov_rec_from_rowptr, dim3(grid_for(total_m, 256, 1 << 16)), dim3(256), 0, st,
+                               t_rowptr, total_m, rec);
             DB_HIP(hipGetLastError());
             DB_TRY(timing_end(tok, st));
         } else {
-            DB_TRY(fill_i32(reinterpret_cast<int32_t*>(ct), 0, 2 * std::max<int64_t>(total_m, 1), st));
+            DB_TRY(fill_i32(reinterpret_cast<int32_t*>(rec), 0, 2 * std::max<int64_t>(total_m, 1), st));
         }
     }
     if (total_rows > 0) {
@@ -1912,11 +1999,11 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         if (sm.count) {
             const int64_t nblk = (int64_t)(sm.count / 8) * 8 * slice_groups;
             hipLaunchKernelGGL(k_ov_seg_slices, dim3((unsigned)nblk), dim3(kSliceBlock), 0, st, d_sets, nsets, d_base,
-                               total_rows, slice_groups, sm, bnd, ct, seg, part);
+                               total_rows, slice_groups, sm, bnd, rec, seg, part);
             DB_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_ov_scatter<kSegWaves>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
-                           dim3(kSegWaves * kWave), 0, st, d_sets, nsets, d_base, total_rows, ct, seg,
+                           dim3(kSegWaves * kWave), 0, st, d_sets, nsets, d_base, total_rows, rec, seg,
                            flops_row, sbound, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct, part, sm.count);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
