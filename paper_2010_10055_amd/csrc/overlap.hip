@@ -836,19 +836,22 @@ __device__ __forceinline__ int2 inline_pair(int64_t cb) {
     const uint64_t v = (uint64_t)(kInlineBase - cb);
     return make_int2((int)(v & 0xFFFFFFull), (int)(v >> 24));
 }
+// Chunk-local counts are 32-bit: a row's products stay below 2^31 (a call
+// with a larger row fails before any walk), and 64-bit counters here had
+// cost the walking kernels a third of their occupancy in registers.
 template <int BLOCK>
-__device__ __forceinline__ int64_t walk_chunk(const uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK], int64_t* c_base,
-                                              int64_t* s_tmp, int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
-                                              int64_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
+__device__ __forceinline__ int32_t walk_chunk(const uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK], int64_t* c_base,
+                                              int64_t* s_tmp, int32_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
+                                              int32_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
-    int64_t local = 0;
+    int32_t local = 0;
 #pragma unroll
     for (int u = 0; u < E; ++u) {
-        my_len[u] = (sg[u] & kPairTag) ? 2 : (int64_t)(sg[u] & 0xFFFFFFull);
+        my_len[u] = (sg[u] & kPairTag) ? 2 : (int32_t)(sg[u] & 0xFFFFFFull);
         local += my_len[u];
     }
-    int64_t tot;
-    int64_t run = block_exclusive_sum<BLOCK>(local, s_tmp, &tot);
+    int32_t tot;
+    int32_t run = block_exclusive_sum<BLOCK>(local, reinterpret_cast<int32_t*>(s_tmp), &tot);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
         c_base[(int)threadIdx.x * E + u] = (sg[u] & kPairTag) ? inline_base(sg[u]) : (int64_t)(sg[u] >> 24) - run;
@@ -861,23 +864,24 @@ __device__ __forceinline__ int64_t walk_chunk(const uint64_t (&sg)[walk_chunk_of
 // Writes the chunk index of every product of the window [w0, w1); the
 // second product of a two-pair entry (its other pair) is flagged with bit 15.
 template <int BLOCK>
-__device__ __forceinline__ void walk_fill(uint16_t* tbuf, const int64_t* c_base, int64_t w0, int64_t w1,
-                                          const int64_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
-                                          const int64_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
+__device__ __forceinline__ void walk_fill(uint16_t* tbuf, const int64_t* c_base, int32_t w0, int32_t w1,
+                                          const int32_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
+                                          const int32_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
     static_assert(walk_chunk_of(BLOCK) <= 0x8000, "chunk index below the flag bit");
 #pragma unroll
     for (int u = 0; u < E; ++u) {
         const int idx = (int)threadIdx.x * E + u;
-        const int64_t a = max(my_off[u], w0), b = min(my_off[u] + my_len[u], w1);
-        const int64_t second = c_base[idx] <= kInlineBelow ? my_off[u] + 1 : -1;
-        for (int64_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)(idx | (q == second ? 0x8000 : 0));
+        const int32_t a = max(my_off[u], w0), b = min(my_off[u] + my_len[u], w1);
+        const int32_t second = c_base[idx] <= kInlineBelow ? my_off[u] + 1 : -1;
+        for (int32_t q = a; q < b; ++q) tbuf[q - w0] = (uint16_t)(idx | (q == second ? 0x8000 : 0));
     }
 }
 
 // self: the row's read; rval: the row's positions, needed only by callers
-// that use the row's own products (nullptr: their position reads 0).
-template <int BLOCK, class F>
+// that use the row's own products (nullptr: their position reads 0).  PER:
+// gathers per thread and round (a kernel short of registers takes fewer).
+template <int BLOCK, int PER = walk_per(BLOCK), class F>
 __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
                                               const int2* __restrict__ at, int64_t* c_base, uint16_t* tbuf,
                                               int64_t* s_tmp, const int32_t* stop, int32_t self,
@@ -885,29 +889,28 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
     constexpr int CH = walk_chunk_of(BLOCK), WIN = walk_win_of(BLOCK);
     static_assert(CH % BLOCK == 0 && CH <= 65536, "chunk index kept in 16 bits");
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
-    constexpr int PER = walk_per(BLOCK);
-    static_assert(PER * BLOCK == WIN, "one gather round per window");
-    int64_t done = 0;   // products of earlier chunks
+    static_assert(WIN % (PER * BLOCK) == 0, "whole gather rounds per window");
+    int32_t done = 0;   // products of earlier chunks
     uint64_t sg[E];
     walk_load<BLOCK>(rseg, 0, min(CH, L), sg);
     for (int cbase = 0; cbase < L; cbase += CH) {
-        int64_t my_off[E], my_len[E];
-        const int64_t tot = walk_chunk<BLOCK>(sg, c_base, s_tmp, my_off, my_len);
+        int32_t my_off[E], my_len[E];
+        const int32_t tot = walk_chunk<BLOCK>(sg, c_base, s_tmp, my_off, my_len);
         const int nbase = cbase + CH;
         walk_load<BLOCK>(rseg, nbase, nbase < L ? min(CH, L - nbase) : 0, sg);
-        for (int64_t w0 = 0; w0 < tot; w0 += WIN) {
-            const int64_t w1 = min(w0 + (int64_t)WIN, tot);
+        for (int32_t w0 = 0; w0 < tot; w0 += WIN) {
+            const int32_t w1 = min(w0 + WIN, tot);
             walk_fill<BLOCK>(tbuf, c_base, w0, w1, my_off, my_len);
             __syncthreads();
-            if (!(stop && *(volatile const int32_t*)stop)) {
-                const int64_t q0 = w0 + threadIdx.x;
+            for (int32_t q0 = w0 + (int32_t)threadIdx.x; q0 < w1; q0 += BLOCK * PER) {
+                if (stop && *(volatile const int32_t*)stop) break;
                 // the loads write only their own registers (an inline value
                 // written there instead would make every later load wait)
                 int tt[PER];
                 int2 jp[PER];
 #pragma unroll
                 for (int u = 0; u < PER; ++u) {
-                    const int64_t q = q0 + (int64_t)u * BLOCK;
+                    const int32_t q = q0 + u * BLOCK;
                     tt[u] = -1;
                     if (q < w1) {
                         const int tv = tbuf[q - w0];
@@ -925,7 +928,7 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
                     if (cb <= kInlineBelow)
                         v = (tt[u] & 0x8000) ? inline_pair(cb)   // the column's other pair
                                              : make_int2(self, rval ? rval[cbase + t] : 0);   // the entry itself
-                    f(cbase + t, v, done + q0 + (int64_t)u * BLOCK);
+                    f(cbase + t, v, (int64_t)(done + q0 + u * BLOCK));
                 }
             }
             __syncthreads();
@@ -1179,7 +1182,8 @@ __global__ __launch_bounds__(kBinBlock) void k_ov_bin_numeric(
 //   bitmap path: a bitmap of the listed columns and a per-word popcount
 //                prefix: r = prefix[j / 32] + popcount(lower bits of word);
 //   hash path:   a small LDS hash from j to r.
-// LDS: chunk arrays | m1, m2 (D u64) | cnt (D i32) | map.
+// LDS: chunk arrays | m1, m2 (D u64) | cnt (D i32) | map (bitmap path:
+// u32 words, then a u16 rank prefix per word).
 // ---------------------------------------------------------------------------
 template <int BLOCK, bool BITS>
 __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
@@ -1214,7 +1218,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     const int32_t* sel = scratch + soff[g];
     const uint32_t T = BITS ? 0u : (uint32_t)table_slots(nsel, load_pct);
     uint32_t* bm = reinterpret_cast<uint32_t*>(map);
-    int32_t* pre = map + words_max;
+    uint16_t* pre = reinterpret_cast<uint16_t*>(map + words_max);   // ranks < num_max_entries <= 8192
     int32_t* keys = map;
     int32_t* rank = map + T;
     if (!BITS) {
@@ -1227,7 +1231,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
             // sel is sorted: the first listed column of a word has the
             // word's smallest rank, so no scan over the words is needed
             atomicOr(&bm[j >> 5], 1u << (j & 31));
-            if (r == 0 || (sel[r - 1] >> 5) != (j >> 5)) pre[j >> 5] = r;
+            if (r == 0 || (sel[r - 1] >> 5) != (j >> 5)) pre[j >> 5] = (uint16_t)r;
         } else {
             const int slot = table_insert(keys, T, j);
             if (slot >= 0) rank[slot] = r;
@@ -1238,8 +1242,9 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     }
     __syncthreads();
     const int32_t self = (int32_t)i;   // the diagonal is written from its closed form below
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr,
-                         [&](int t, int2 jp, int64_t) {
+    // four gathers per round: eight would take the registers of half the workgroups
+    walk_products<BLOCK, 4>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr,
+                            [&](int t, int2 jp, int64_t) {
                              const int32_t j = jp.x;
                              if (j == self) return;
                              int r;
@@ -1247,7 +1252,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
                                  const uint32_t word = bm[j >> 5];
                                  const uint32_t bit = 1u << (j & 31);
                                  if (!(word & bit)) return;
-                                 r = pre[j >> 5] + __popc(word & (bit - 1u));
+                                 r = (int)pre[j >> 5] + __popc(word & (bit - 1u));
                              } else {
                                  const int slot = table_find(keys, T, j);
                                  if (slot < 0) return;
@@ -1550,7 +1555,8 @@ static size_t sym_bits_lds(int block, int planes, int words) {
 // Numeric LDS for rows with at most D output entries: chunk arrays,
 // m1/m2/cnt, and the column map (bitmap + prefix, or hash keys + ranks).
 static size_t num_lds(int block, int D, int load_pct, bool bits, int words) {
-    const size_t map = bits ? (size_t)words * 8 : (size_t)table_slots(D, load_pct) * 8;
+    // bitmap path: u32 bitmap words + u16 rank prefixes; hash path: keys + ranks
+    const size_t map = bits ? (((size_t)words * 6 + 7) & ~(size_t)7) : (size_t)table_slots(D, load_pct) * 8;
     return walk_lds(block) + (size_t)D * 20 + map;
 }
 
