@@ -645,7 +645,9 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
             len[u] = s_len[w * RPW + j0 + u];
             most = max(most, len[u]);
         }
-        int64_t fl[kSliceIlp];
+        // products per (slice, row) in 32 bits, saturating at 2^31: a row
+        // that large then still fails the product check of the call
+        uint32_t fl[kSliceIlp];
 #pragma unroll
         for (int u = 0; u < kSliceIlp; ++u) fl[u] = 0;
         for (int o = lane; o - lane < most; o += kWave) {
@@ -658,26 +660,26 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
                 vv[u] = gload_nt(s_val[w * RPW + j0 + u] + idx);
             }
             uint64_t rc[kSliceIlp];
-            bool ok[kSliceIlp];
 #pragma unroll
             for (int u = 0; u < kSliceIlp; ++u) {
                 const int r = w * RPW + j0 + u;
-                ok[u] = kk[u] >= 0 && kk[u] < s_m[r];
-                rc[u] = gload(rec + (ok[u] ? s_cb[r] + kk[u] : 0));
+                const bool ok = kk[u] >= 0 && kk[u] < s_m[r];
+                rc[u] = gload(rec + (ok ? s_cb[r] + kk[u] : 0));
             }
 #pragma unroll
             for (int u = 0; u < kSliceIlp; ++u) {
                 if (o >= len[u]) continue;
                 const int r = w * RPW + j0 + u;
+                const bool ok = kk[u] >= 0 && kk[u] < s_m[r];
                 int64_t n_p;
-                const uint64_t sg = seg_word(ok[u] ? rc[u] : 0ull, s_i[r], vv[u], &n_p);   // invalid column: empty
-                fl[u] += n_p;
+                const uint64_t sg = seg_word(ok ? rc[u] : 0ull, s_i[r], vv[u], &n_p);   // invalid column: empty
+                fl[u] = min(fl[u] + (uint32_t)n_p, 1u << 31);   // fl <= 2^31, n_p < 2^24: no wrap
                 seg[s_first[r] + o] = sg;   // ordinary store: L2 merges the lines
             }
         }
 #pragma unroll
         for (int u = 0; u < kSliceIlp; ++u) {
-            const int64_t t = wave_sum(fl[u]);
+            const int64_t t = wave_sum((int64_t)fl[u]);
             const int64_t g = row0 + w * RPW + j0 + u;
             if (lane == 0 && g < total_rows) part[(int64_t)sl * total_rows + g] = t;
         }
@@ -1821,9 +1823,10 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     }
 
     const int col_bits = ceil_log2_i64(std::max<int64_t>(total_m, 2));
-    // 2^14 columns per bucket keeps two pass-2 workgroups per CU; 2^15 when
-    // the bucket count would not fit the partition's LDS
-    int low = std::min(14, std::max(10, col_bits - 8));
+    // buckets of at most 2^13 columns: pass 2 then sorts each in two staged
+    // sweeps (2^14 took four sweeps, each re-reading the bucket's keys, and
+    // left a half-empty last round of workgroups on mid)
+    int low = std::min(13, std::max(10, col_bits - 8));
     // wider buckets when the count would not fit the partition's LDS (pass 2
     // sorts buckets wider than 2^15 columns in sweeps)
     while (low < kMaxLow && ceil_div(total_m, int64_t(1) << low) > kMaxBuckets) ++low;
