@@ -190,10 +190,10 @@ struct SliceMap {
 // A^T column records (8 B per column): (start << 24) | length; a column of
 // exactly two pairs (r0, p0), (r1, p1) instead holds
 // kPairTag | ((p0 ^ p1) << 24) | (r0 ^ r1) (reads < 2^24, positions
-// < 2^31): an entry of that column, knowing its own read and position,
-// recovers the other pair.  The segment word of such an entry is
-// kPairTag | (position << 24) | read of the other pair, so the walk has both
-// products of the entry (itself and the other read) without gathering A^T.
+// < 2^31).  An A entry's segment word is its column's record: an entry of
+// a two-pair column, knowing its own read and position, recovers the other
+// pair, so the walk has both products of the entry (itself and the other
+// read) without gathering A^T.
 constexpr uint64_t kPairTag = 1ull << 63;
 __host__ __device__ __forceinline__ int slice_of(int64_t c, SliceMap sm) {
     return (int)(((uint64_t)c * sm.mul) >> 32);
@@ -306,17 +306,9 @@ __global__ void k_ov_rec_from_rowptr(const uint32_t* __restrict__ t_rowptr, int6
         rec[c] = ((uint64_t)t_rowptr[c] << 24) | (uint64_t)(t_rowptr[c + 1] - t_rowptr[c]);
 }
 
-// The segment word of an A entry (set-local read i, position p) from its
-// column's record, and the entry's product count.
-__device__ __forceinline__ uint64_t seg_word(uint64_t r, uint32_t i, int32_t p, int64_t* len) {
-    if (r & kPairTag) {
-        *len = 2;
-        const uint64_t read = (r ^ i) & 0xFFFFFFull;
-        const uint64_t pos = ((r >> 24) ^ (uint64_t)(uint32_t)p) & 0x7FFFFFFFull;
-        return kPairTag | (pos << 24) | read;
-    }
-    *len = (int64_t)(r & 0xFFFFFFull);
-    return r;
+// Products of an A entry whose column has record r.
+__device__ __forceinline__ int64_t rec_products(uint64_t r) {
+    return (r & kPairTag) ? 2 : (int64_t)(r & 0xFFFFFFull);
 }
 
 // ---------------------------------------------------------------------------
@@ -591,9 +583,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
     __shared__ int32_t s_len[kSliceRows];
     __shared__ int64_t s_first[kSliceRows];        // global entry of the row's first entry in the slice
     __shared__ const int32_t* s_col[kSliceRows];   // its column
-    __shared__ const int32_t* s_val[kSliceRows];   // its position
     __shared__ int64_t s_cb[kSliceRows], s_m[kSliceRows];
-    __shared__ uint32_t s_i[kSliceRows];            // set-local row
     const int64_t b = blockIdx.x;
     const int sl = (int)((b / 8) / groups) * 8 + (int)(b % 8);
     const int64_t row0 = ((b / 8) % groups) * kSliceRows;
@@ -604,10 +594,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
         s_len[r] = 0;
         s_first[r] = 0;
         s_col[r] = kSliceNone;
-        s_val[r] = kSliceNone;
         s_cb[r] = 0;
         s_m[r] = 0;
-        s_i[r] = 0;
         if (g < total_rows) {
             const int s = find_set(set_base, nsets, g);
             const OvSet& S = sets[s];
@@ -620,13 +608,9 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
                 const int32_t z = min(max(rb[sl + 1], a), L);
                 s_len[r] = z - a;
                 s_first[r] = S.nnz_base + lo + a;
-                if (z > a) {
-                    s_col[r] = S.a_col + lo + a;
-                    s_val[r] = S.a_val + lo + a;
-                }
+                if (z > a) s_col[r] = S.a_col + lo + a;
                 s_cb[r] = S.col_base;
                 s_m[r] = S.m;
-                s_i[r] = (uint32_t)i;
             }
         }
     }
@@ -652,13 +636,10 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
         for (int u = 0; u < kSliceIlp; ++u) fl[u] = 0;
         for (int o = lane; o - lane < most; o += kWave) {
             // unconditional loads from clamped addresses: no load waits on another
-            int32_t kk[kSliceIlp], vv[kSliceIlp];
+            int32_t kk[kSliceIlp];
 #pragma unroll
-            for (int u = 0; u < kSliceIlp; ++u) {
-                const int idx = min(o, max(len[u] - 1, 0));
-                kk[u] = gload_nt(s_col[w * RPW + j0 + u] + idx);
-                vv[u] = gload_nt(s_val[w * RPW + j0 + u] + idx);
-            }
+            for (int u = 0; u < kSliceIlp; ++u)
+                kk[u] = gload_nt(s_col[w * RPW + j0 + u] + min(o, max(len[u] - 1, 0)));
             uint64_t rc[kSliceIlp];
 #pragma unroll
             for (int u = 0; u < kSliceIlp; ++u) {
@@ -671,9 +652,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
                 if (o >= len[u]) continue;
                 const int r = w * RPW + j0 + u;
                 const bool ok = kk[u] >= 0 && kk[u] < s_m[r];
-                int64_t n_p;
-                const uint64_t sg = seg_word(ok ? rc[u] : 0ull, s_i[r], vv[u], &n_p);   // invalid column: empty
-                fl[u] = min(fl[u] + (uint32_t)n_p, 1u << 31);   // fl <= 2^31, n_p < 2^24: no wrap
+                const uint64_t sg = ok ? rc[u] : 0ull;   // invalid column: empty segment
+                fl[u] = min(fl[u] + (uint32_t)rec_products(sg), 1u << 31);   // fl <= 2^31, products < 2^24: no wrap
                 seg[s_first[r] + o] = sg;   // ordinary store: L2 merges the lines
             }
         }
@@ -722,13 +702,10 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
             if (lane < nslices) fl = part[(int64_t)lane * total_rows + g];
         } else if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
             for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kSegIlp) {
-                int32_t kk[kSegIlp], vv[kSegIlp];
+                int32_t kk[kSegIlp];
                 uint64_t rc[kSegIlp];
 #pragma unroll
-                for (int q = 0; q < kSegIlp; ++q) {
-                    kk[q] = gload(S.a_col + min(e0 + q * kWave + lane, hi - 1));
-                    vv[q] = gload(S.a_val + min(e0 + q * kWave + lane, hi - 1));
-                }
+                for (int q = 0; q < kSegIlp; ++q) kk[q] = gload(S.a_col + min(e0 + q * kWave + lane, hi - 1));
 #pragma unroll
                 for (int q = 0; q < kSegIlp; ++q) {
                     const int32_t k = kk[q];
@@ -740,9 +717,8 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
                     const int64_t e = e0 + q * kWave + lane;
                     if (e >= hi) continue;
                     if (!(kk[q] >= 0 && kk[q] < S.m)) rc[q] = 0ull;   // invalid column: empty segment
-                    int64_t n_p;
-                    const uint64_t sg = seg_word(rc[q], (uint32_t)i, vv[q], &n_p);
-                    fl += n_p;
+                    const uint64_t sg = rc[q];
+                    fl += rec_products(sg);
                     seg[S.nnz_base + e] = sg;
                 }
             }
@@ -812,28 +788,30 @@ constexpr int kWalkChunk = 512;
 constexpr int kWalkWin = 2048;
 
 // Loads the segments of the chunk's entries owned by this thread (length 0
-// past the end of the row).
+// past the end of the row) and, given the row's positions, their positions.
 template <int BLOCK>
-__device__ __forceinline__ void walk_load(const uint64_t* __restrict__ rseg, int cbase, int cl,
-                                          uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK]) {
+__device__ __forceinline__ void walk_load(const uint64_t* __restrict__ rseg, const int32_t* __restrict__ rval,
+                                          int cbase, int cl, uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK],
+                                          int32_t (&pv)[walk_chunk_of(BLOCK) / BLOCK]) {
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
 #pragma unroll
     for (int u = 0; u < E; ++u) {
         const int e = (int)threadIdx.x * E + u;
         sg[u] = e < cl ? rseg[cbase + e] : 0ull;
+        pv[u] = (rval && e < cl) ? rval[cbase + e] : 0;
     }
 }
 
 // Numbers the chunk's products (t-major) from its loaded segment words,
-// writes c_base and returns the chunk's product count.  An entry whose word
-// carries its column's other pair (kPairTag) has two products, itself and
-// that pair; its c_base holds the pair as kInlineBase - ((position << 24) |
-// read) (reads < 2^24, positions < 2^31), which lies at or below -2^62,
-// far below every real base (those exceed -2^31).  Each thread keeps its
+// writes c_base and returns the chunk's product count.  An entry of a
+// two-pair column (kPairTag) has two products, itself and the other pair;
+// the other pair follows from the column's XORs and the entry's own read
+// and position (position 0 unless the row's positions were loaded), and its
+// c_base holds it as kInlineBase - ((position << 24) | read) (< 2^55), at or
+// below -2^62, far below every real base (those exceed -2^31).  Each thread keeps its
 // entries' offsets and lengths for the window fills.
 constexpr int64_t kInlineBase = -(int64_t(1) << 62);
 constexpr int64_t kInlineBelow = -(int64_t(1) << 32);
-__device__ __forceinline__ int64_t inline_base(uint64_t word) { return kInlineBase - (int64_t)(word & ~kPairTag); }
 __device__ __forceinline__ int2 inline_pair(int64_t cb) {
     const uint64_t v = (uint64_t)(kInlineBase - cb);
     return make_int2((int)(v & 0xFFFFFFull), (int)(v >> 24));
@@ -842,8 +820,10 @@ __device__ __forceinline__ int2 inline_pair(int64_t cb) {
 // with a larger row fails before any walk), and 64-bit counters here had
 // cost the walking kernels a third of their occupancy in registers.
 template <int BLOCK>
-__device__ __forceinline__ int32_t walk_chunk(const uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK], int64_t* c_base,
-                                              int64_t* s_tmp, int32_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
+__device__ __forceinline__ int32_t walk_chunk(const uint64_t (&sg)[walk_chunk_of(BLOCK) / BLOCK],
+                                              const int32_t (&pv)[walk_chunk_of(BLOCK) / BLOCK], int32_t self,
+                                              int64_t* c_base, int64_t* s_tmp,
+                                              int32_t (&my_off)[walk_chunk_of(BLOCK) / BLOCK],
                                               int32_t (&my_len)[walk_chunk_of(BLOCK) / BLOCK]) {
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
     int32_t local = 0;
@@ -856,7 +836,13 @@ __device__ __forceinline__ int32_t walk_chunk(const uint64_t (&sg)[walk_chunk_of
     int32_t run = block_exclusive_sum<BLOCK>(local, reinterpret_cast<int32_t*>(s_tmp), &tot);
 #pragma unroll
     for (int u = 0; u < E; ++u) {
-        c_base[(int)threadIdx.x * E + u] = (sg[u] & kPairTag) ? inline_base(sg[u]) : (int64_t)(sg[u] >> 24) - run;
+        int64_t cb = (int64_t)(sg[u] >> 24) - run;
+        if (sg[u] & kPairTag) {
+            const uint64_t read = (sg[u] ^ (uint64_t)(uint32_t)self) & 0xFFFFFFull;
+            const uint64_t pos = ((sg[u] >> 24) ^ (uint64_t)(uint32_t)pv[u]) & 0x7FFFFFFFull;
+            cb = kInlineBase - (int64_t)((pos << 24) | read);
+        }
+        c_base[(int)threadIdx.x * E + u] = cb;
         my_off[u] = run;
         run += my_len[u];
     }
@@ -880,26 +866,31 @@ __device__ __forceinline__ void walk_fill(uint16_t* tbuf, const int64_t* c_base,
     }
 }
 
-// self: the row's read; rval: the row's positions, needed only by callers
-// that use the row's own products (nullptr: their position reads 0).  PER:
-// gathers per thread and round (a kernel short of registers takes fewer).
+// f(t, (j, p_j), q).  self: the row's read.  rval: the row's positions,
+// loaded with the segments so that the other pair of a two-pair column
+// comes with its position (without it that position reads wrong: for
+// callers that use only j).  own: given, the row's own products come with
+// their positions too (else 0).  PER: gathers per thread and round (a kernel
+// short of registers takes fewer).
 template <int BLOCK, int PER = walk_per(BLOCK), class F>
 __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
                                               const int2* __restrict__ at, int64_t* c_base, uint16_t* tbuf,
                                               int64_t* s_tmp, const int32_t* stop, int32_t self,
-                                              const int32_t* __restrict__ rval, F&& f) {
+                                              const int32_t* __restrict__ rval, const int32_t* __restrict__ own,
+                                              F&& f) {
     constexpr int CH = walk_chunk_of(BLOCK), WIN = walk_win_of(BLOCK);
     static_assert(CH % BLOCK == 0 && CH <= 65536, "chunk index kept in 16 bits");
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
     static_assert(WIN % (PER * BLOCK) == 0, "whole gather rounds per window");
     int32_t done = 0;   // products of earlier chunks
     uint64_t sg[E];
-    walk_load<BLOCK>(rseg, 0, min(CH, L), sg);
+    int32_t pv[E];
+    walk_load<BLOCK>(rseg, rval, 0, min(CH, L), sg, pv);
     for (int cbase = 0; cbase < L; cbase += CH) {
         int32_t my_off[E], my_len[E];
-        const int32_t tot = walk_chunk<BLOCK>(sg, c_base, s_tmp, my_off, my_len);
+        const int32_t tot = walk_chunk<BLOCK>(sg, pv, self, c_base, s_tmp, my_off, my_len);
         const int nbase = cbase + CH;
-        walk_load<BLOCK>(rseg, nbase, nbase < L ? min(CH, L - nbase) : 0, sg);
+        walk_load<BLOCK>(rseg, rval, nbase, nbase < L ? min(CH, L - nbase) : 0, sg, pv);
         for (int32_t w0 = 0; w0 < tot; w0 += WIN) {
             const int32_t w1 = min(w0 + WIN, tot);
             walk_fill<BLOCK>(tbuf, c_base, w0, w1, my_off, my_len);
@@ -929,7 +920,7 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
                     int2 v = jp[u];
                     if (cb <= kInlineBelow)
                         v = (tt[u] & 0x8000) ? inline_pair(cb)   // the column's other pair
-                                             : make_int2(self, rval ? rval[cbase + t] : 0);   // the entry itself
+                                             : make_int2(self, own ? own[cbase + t] : 0);   // the entry itself
                     f(cbase + t, v, (int64_t)(done + q0 + u * BLOCK));
                 }
             }
@@ -975,7 +966,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     // left out of the walk (one LDS address hit by every segment) and set
     // from its closed form, count = L
     const int32_t self = (int32_t)i;
-    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr,
+    walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr, nullptr,
                          [&](int, int2 jp, int64_t) {
                              if (jp.x != self) planes_mark(B, words, planes, jp.x);
                          });
@@ -1051,7 +1042,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
         }
         __syncthreads();
         const int32_t self = (int32_t)i;
-        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, &s_ovf, self, nullptr,
+        walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, &s_ovf, self, nullptr, nullptr,
                              [&](int, int2 jp, int64_t) {
                                  if (jp.x == self) return;   // the diagonal: added once below
                                  int fresh;
@@ -1245,8 +1236,8 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     __syncthreads();
     const int32_t self = (int32_t)i;   // the diagonal is written from its closed form below
     // four gathers per round: eight would take the registers of half the workgroups
-    walk_products<BLOCK, 4>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr,
-                            [&](int t, int2 jp, int64_t) {
+    walk_products<BLOCK, 4>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, S.a_val + lo,
+                            nullptr, [&](int t, int2 jp, int64_t) {
                              const int32_t j = jp.x;
                              if (j == self) return;
                              int r;
@@ -1351,7 +1342,7 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int64_t base = esc_off[g];
     // products land at their t-major index, so the expansion is ordered by k
     walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, (int32_t)i,
-                             S.a_val + lo, [&](int t, int2 jp, int64_t q) {
+                             S.a_val + lo, S.a_val + lo, [&](int t, int2 jp, int64_t q) {
                                  keys0[base + q] = (uint32_t)jp.x;
                                  pay0[base + q] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
                              });
