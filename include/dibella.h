@@ -198,8 +198,8 @@ int dibella_last_stats(dibella_stats* out);
  *   1 part_count    bucketed transpose: bucket histogram per chunk of pairs
  *   2 part_scatter  bucketed transpose: pairs grouped by bucket
  *   3 bucket_sort   bucketed transpose: per bucket, a counting sort by column
- *                   giving the A^T row pointers and entries (radix case:
- *                   the A^T row pointers from the sorted columns)
+ *                   giving the A^T entries and one record per column (radix
+ *                   case: the records from the sorted columns)
  *   4 sort_up       radix case (very many columns or entries): digit histograms
  *   5 sort_down     radix case: stable scatter (one launch per 8-bit pass)
  *   6 segments      A^T segment per A entry, products per row, row bins

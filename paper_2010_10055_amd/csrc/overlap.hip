@@ -369,9 +369,13 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_count(const uint32_t* __
         counts[(int64_t)b * nblocks + blockIdx.x] = (int32_t)hist[b];
 }
 
+// K: the width of the keys written out; pass 2 reads only their low `low`
+// bits, so buckets of at most 2^16 columns take 16-bit keys (half the key
+// bytes of both passes).
+template <class K>
 __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
     const uint32_t* __restrict__ keys, const uint64_t* __restrict__ pays, int64_t n, int per_block, int low,
-    int nbuckets, const int64_t* __restrict__ offsets, int64_t cap, uint32_t* __restrict__ skey,
+    int nbuckets, const int64_t* __restrict__ offsets, int64_t cap, K* __restrict__ skey,
     uint64_t* __restrict__ spay) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* st_pay = reinterpret_cast<uint64_t*>(smem);                 // [kChunk]
@@ -430,7 +434,7 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
             const int b = (int)(key >> low);
             const int64_t pos = gpos[b] + (slot - loff[b]);
             if (pos < cap) {
-                skey[pos] = key;
+                skey[pos] = (K)key;
                 spay[pos] = st_pay[slot];
             }
         }
@@ -444,10 +448,10 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
 // contiguous run (coalesced) when they fit kStageCap; sweeps of 2^sub columns.
 // Only a staged sweep writes the two-pair records (otherwise every column
 // gets its segment).
-template <bool SWEEPS, bool STAGE>
+template <bool SWEEPS, bool STAGE, class K>
 __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
     const int64_t* __restrict__ offsets, int64_t nchunks, int low, int sub_bits, int64_t total_m, int64_t cap,
-    const uint32_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ rec,
+    const K* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ rec,
     uint64_t* __restrict__ at) {
     // offsets: bucket-major over the partition's workgroups (nchunks of them)
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1946,30 +1950,41 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, ar));
         static std::atomic<bool> lds_ok{false};
         if (!lds_ok.load(std::memory_order_acquire)) {
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, false>,
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<uint16_t>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, true>,
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<uint32_t>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, false, uint32_t>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, true, uint16_t>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
             lds_ok.store(true, std::memory_order_release);
         }
+        // buckets of at most 2^15 columns: 16-bit keys between the passes
+        const bool narrow = low <= kBucketBits;
+        uint16_t* keys_b16 = reinterpret_cast<uint16_t*>(keys_b);
         DB_TRY(timing_begin(kPhPartScatter, st, &tok));
-        hipLaunchKernelGGL(k_ov_part_scatter, dim3((unsigned)npart), dim3(kPartBlock), part_scatter_lds(nbuckets),
-                           st, keys_a, pays_a, total_nnz, per_block, low, (int)nbuckets, poffs, total_nnz, keys_b,
-                           pays_b);
+        if (narrow)
+            hipLaunchKernelGGL(k_ov_part_scatter<uint16_t>, dim3((unsigned)npart), dim3(kPartBlock),
+                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low,
+                               (int)nbuckets, poffs, total_nnz, keys_b16, pays_b);
+        else
+            hipLaunchKernelGGL(k_ov_part_scatter<uint32_t>, dim3((unsigned)npart), dim3(kPartBlock),
+                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low,
+                               (int)nbuckets, poffs, total_nnz, keys_b, pays_b);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         // A^T pairs land in pays_a, free once the partition has read it
         DB_TRY(timing_begin(kPhBucketSort, st, &tok));
-        if (low > kBucketBits)
-            hipLaunchKernelGGL((k_ov_bucket_sort<true, false>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
-                               (size_t)4 << kBucketBits, st, poffs, npart, low, kBucketBits, total_m, total_nnz,
-                               keys_b, pays_b, rec, pays_a);
+        if (!narrow)
+            hipLaunchKernelGGL((k_ov_bucket_sort<true, false, uint32_t>), dim3((unsigned)nbuckets),
+                               dim3(kBucketBlock), (size_t)4 << kBucketBits, st, poffs, npart, low, kBucketBits,
+                               total_m, total_nnz, keys_b, pays_b, rec, pays_a);
         else   // staged sweeps of 2^12 columns (one sweep for narrower buckets)
-            hipLaunchKernelGGL((k_ov_bucket_sort<true, true>), dim3((unsigned)nbuckets), dim3(kBucketBlock),
-                               ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, poffs, npart, low,
-                               std::min(low, kStageBits), total_m, total_nnz, keys_b, pays_b, rec, pays_a);
+            hipLaunchKernelGGL((k_ov_bucket_sort<true, true, uint16_t>), dim3((unsigned)nbuckets),
+                               dim3(kBucketBlock), ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, poffs,
+                               npart, low, std::min(low, kStageBits), total_m, total_nnz, keys_b16, pays_b, rec,
+                               pays_a);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         at = reinterpret_cast<const int2*>(pays_a);
