@@ -126,8 +126,10 @@ int dibella_overlap(const dibella_csr* A, int32_t min_shared, dibella_overlap_ou
  * nothing.  S has R's layout.
  * Errors: EINVAL for a malformed or non-square R, a diagonal entry, an
  * overhang >= 2^28, or fuzz outside [0, 2^30).
- * Host synchronisation: one stream sync to validate R, then one per two
- * passes (per captured graph of passes with DIBELLA_TR_USE_GRAPH).
+ * Host synchronisation: one stream sync per two passes (per captured graph
+ * of passes with DIBELLA_TR_USE_GRAPH); the first also reads the validity
+ * of R, and a malformed R runs no pass.  A reduction that converges in two
+ * passes syncs once.
  */
 int dibella_transitive_reduce(const dibella_csr* R, int32_t fuzz, uint32_t flags,
                               dibella_csr_out* S, int32_t* iterations,

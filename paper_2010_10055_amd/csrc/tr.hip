@@ -185,10 +185,20 @@ __global__ __launch_bounds__(WPB* kWave) void k_tr_init_copy(
     }
 }
 
+// The passes run only if every set passed validation: a malformed call is
+// reported after the first synchronisation, with no pass having run (every
+// pass kernel returns at once while nothing is active).
 __global__ void k_tr_init_state(TrState* __restrict__ state, const int64_t* __restrict__ rp,
-                                int64_t total_rows, int32_t max_passes, int32_t nsets) {
+                                int64_t total_rows, int32_t max_passes, int32_t nsets,
+                                const int32_t* __restrict__ flags) {
+    __shared__ int32_t s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < nsets; s += blockDim.x)
+        if (flags[s]) atomicOr(&s_bad, 1);
+    __syncthreads();
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        state->any_active = nsets > 0 ? 1 : 0;
+        state->any_active = (nsets > 0 && !s_bad) ? 1 : 0;
         state->result_buf = 0;
         state->pass = 0;
         state->max_passes = max_passes;
@@ -765,7 +775,7 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
     }
     const uint32_t maxp = flags >> 16;
     hipLaunchKernelGGL(k_tr_init_state, dim3(1), dim3(64), 0, st, B.state, B.rp[0], total_rows, (int32_t)maxp,
-                       nsets);
+                       nsets, d_flags);
     DB_HIP(hipGetLastError());
 
     char* back = hbuf + desc_bytes;
@@ -780,21 +790,27 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
         DB_HIP(hipMemcpyAsync(h_set_nnz, B.set_nnz, sizeof(int64_t) * nsets, hipMemcpyDeviceToHost, st));
         return sync_stream(st);
     };
-    // Sync: validity, bin sizes (launch grids).
-    DB_TRY(read_back());
-    for (int s = 0; s < nsets; ++s) {
-        if (h_flags[s]) {
-            set_error("set " + std::to_string(s) + ": " + describe_tr_bad(h_flags[s]));
-            return DIBELLA_EINVAL;
-        }
-    }
+    // Persistent grids sized from bounds the host knows (the bin sizes are
+    // read on the device), so the first passes follow validation without a
+    // synchronisation: at most nnz / (cap + 1) rows are longer than a cap.
     {
         const int occ = 8;   // resident blocks per CU assumed when sizing persistent grids
-        for (int b = 0; b < 3; ++b) B.grid[b] = std::min(h_state->bin_count[b], 256 * occ * 4);
+        const int64_t cap_grid = 256 * occ * 4;
+        const int64_t bound[3] = {total_rows, total_nnz / (kSmallCap + 1), total_nnz / (B.mid_cap + 1)};
+        for (int b = 0; b < 3; ++b) B.grid[b] = (int)std::min(bound[b], cap_grid);
     }
+    auto check_valid = [&]() -> int {
+        for (int s = 0; s < nsets; ++s) {
+            if (h_flags[s]) {
+                set_error("set " + std::to_string(s) + ": " + describe_tr_bad(h_flags[s]));
+                return DIBELLA_EINVAL;
+            }
+        }
+        return DIBELLA_OK;
+    };
 
     DB_TRY(prepare_pass_kernels(B.block));
-    if (h_state->any_active) {
+    {
         if (flags & DIBELLA_TR_USE_GRAPH) {
             int U = std::max(1, std::min(16, tn.tr_graph_passes));
             if (U & 1) U += 1;   // even: every replay starts from buffer 0
@@ -813,6 +829,7 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
             while (true) {
                 DB_HIP(hipGraphLaunch(gh.exec, st));
                 DB_TRY(read_back());
+                DB_TRY(check_valid());
                 if (!h_state->any_active) break;
                 if (h_state->pass > total_nnz + 2) {
                     set_error("transitive reduction did not converge");
@@ -827,6 +844,7 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
                 DB_TRY(enqueue_pass(B, 0, st));
                 DB_TRY(enqueue_pass(B, 1, st));
                 DB_TRY(read_back());
+                DB_TRY(check_valid());
                 if (!h_state->any_active) break;
                 if (h_state->pass > total_nnz + 2) {   // every productive pass deletes an entry
                     set_error("transitive reduction did not converge");
