@@ -243,6 +243,31 @@ def test_overlap_esc_and_overflow_paths(lib):
     assert_overlap_equal(C, ref, "esc bitmap")
 
 
+def test_overlap_esc_rows_with_two_pair_columns(lib):
+    """Rows whose output exceeds the numeric tables go through
+    expand-sort-compress while many of their columns hold exactly two pairs
+    (carried inline, not gathered): the expansion must give both products of
+    such an entry, each with its position."""
+    rng = np.random.default_rng(33)
+    n, pool = 600, 50
+    rows, cols = [], []
+    for i in range(n):
+        own = [pool + 3 * i + q for q in range(3)]                            # shared with the next read only
+        prev = [pool + 3 * ((i - 1) % n) + q for q in range(3)]
+        c = np.unique(np.concatenate([own, prev, rng.choice(pool, 40, replace=False)]))
+        rows.append(np.full(c.size, i)); cols.append(c)
+    m = pool + 3 * n
+    rows, cols = np.concatenate(rows), np.concatenate(cols).astype(np.int32)
+    A = synth.coo_to_csr(n, m, rows, cols, rng.integers(0, 50000, rows.size).astype(np.int32))
+    ref = oracle.overlap(A, 1)
+    with tuned(lib, num_max_entries=256):
+        C = _run_overlap(lib, A, 1)
+        st = lib.last_stats()
+    assert st["esc_rows"] > 0
+    assert_overlap_equal(C, ref, "esc with two-pair columns")
+    assert_overlap_equal(_run_overlap(lib, A, 2), oracle.overlap(A, 2), "two-pair columns, min_shared 2")
+
+
 @pytest.mark.parametrize("bits", PATHS)
 @pytest.mark.parametrize("block", [64, 128, 512])
 def test_overlap_launch_shapes_give_same_bits(lib, block, bits):
