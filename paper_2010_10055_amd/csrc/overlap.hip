@@ -3,10 +3,11 @@
 // two smallest shared k-mer columns.
 //
 // Pipeline (one launch per step for all sets of a batch):
-//   validate + column histogram (the returned count is each entry's slot in
-//   its A^T row)  ->  scan  ->  scatter A^T (read, pos) pairs, per-entry A^T
-//   segment (start, length), products per row, row bins  ->  symbolic  ->
-//   bins by output size  ->  scan to row pointers  ->  numeric.
+//   validate A and lay out its (column, read|position) pairs  ->  two-pass
+//   bucketed counting sort by column: A^T and one record per column (a
+//   column of two pairs carries them)  ->  per A entry its segment word (per
+//   XCD column slice), products per row, row bins  ->  symbolic  ->  bins by
+//   output size  ->  scan to C's row pointers  ->  numeric.
 // Symbolic and numeric walk the products of one row per workgroup:
 //   * bitmap path (sets whose read count fits an LDS bitmap): the symbolic
 //     phase marks every column j in 1..4 bit planes ("seen >= p times"); the
@@ -180,7 +181,7 @@ __device__ __forceinline__ void planes_mark(uint32_t* B, int words, int planes, 
 // Column slices for the segment pass: the global columns are cut into
 // `count` ranges of about equal width, slice(c) = (c * mul) >> 32 with
 // mul = floor(2^32 * count / total columns), so slice(c) < count and is
-// monotone in c.  Each slice's share of the A^T row pointers is small
+// monotone in c.  Each slice's share of the A^T column records is small
 // enough to stay in one XCD's L2 while that XCD works on the slice.
 struct SliceMap {
     int32_t count;   // 0: no slices
@@ -551,13 +552,14 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
 }
 
 // ---------------------------------------------------------------------------
-// Step 3: record each A entry's A^T segment (start, length), products per
+// Step 3: each A entry's segment word (its column's record), products per
 // row, the row's scratch range bound, and bin rows for the symbolic phase:
-// bitmap-path rows in one class,
-// hash-path rows by first-level table size.  A workgroup owns
-// kRowsPerBlock consecutive rows (one wave per row at a time); bin counts
-// and totals are gathered in LDS and published with one global atomic per
-// workgroup and counter.
+// bitmap-path rows in one class, hash-path rows by first-level table size.
+// k_ov_scatter: a workgroup owns kRowsPerBlock consecutive rows (one wave
+// per row at a time); bin counts and totals are gathered in LDS and
+// published with one global atomic per workgroup and counter.  With column
+// slices the segment words come from k_ov_seg_slices first and k_ov_scatter
+// only sums its products per (slice, row).
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerBlock = 64;
 constexpr int kSegWaves = 16;
