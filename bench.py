@@ -77,12 +77,12 @@ KERNEL_SOURCES = {"keys": ("overlap.hip",), "part_count": ("overlap.hip",), "par
                   "tr_mark": ("tr.hip",), "tr_compact": ("tr.hip",)}
 
 
-def load_traffic(kernel: str, workload: str, src_hash: str):
+def load_traffic(kernel: str, workload: str, src_hash: str, profiles: str = PROFILES):
     """HBM bytes per launch (per phase for the numeric phase) from the
     committed rocprofv3 counter summary, if it was taken on the current
     kernel source."""
     phase = kernel == "numeric_phase"
-    path = os.path.join(PROFILES, f"{'numeric' if phase else kernel}_{workload}_pmc.json")
+    path = os.path.join(profiles, f"{'numeric' if phase else kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     try:
@@ -138,12 +138,13 @@ def _counter_per_kernel(d, counter):
     return per
 
 
-def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, command):
+def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, command,
+                       out_dir: str = PROFILES):
     """Write the profiles/ summaries: per-kernel durations of the timed run
     (rocprofv3 kernel stats) and, per main kernel, HBM bytes per launch from
     FETCH_SIZE / WRITE_SIZE scaled by the counters of the calibration copy."""
     import statistics
-    os.makedirs(PROFILES, exist_ok=True)
+    os.makedirs(out_dir, exist_ok=True)
     stats = _csv_rows(trace_dir, "kernel_stats.csv")
     lines = [f"# rocprofv3 kernel statistics, workload '{workload}'", f"# command: {command}",
              f"{'kernel':64s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}"]
@@ -175,7 +176,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
         lines.append(f"numeric phase (k_ov_numeric launches of one call, overlapping on 3 streams): "
                      f"{len(spans)} calls, {statistics.mean(nlaunch):.1f} launches per call, "
                      f"span avg_us {statistics.mean(spans) / 1e3:.2f}")
-    with open(os.path.join(PROFILES, f"kernels_{workload}_trace.txt"), "w") as f:
+    with open(os.path.join(out_dir, f"kernels_{workload}_trace.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     cf = _counter_per_kernel(cfetch_dir, "FETCH_SIZE")
     cw = _counter_per_kernel(cwrite_dir, "WRITE_SIZE")
@@ -214,9 +215,9 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
             # all launches of the phase of one call
             d["overlap_calls"] = calls
             d["hbm_bytes_per_phase"] = (sum(fv) * 1024 / f_fetch + sum(wv) * 1024 / f_write) / calls
-        with open(os.path.join(PROFILES, f"{label}_{workload}_pmc.json"), "w") as f:
+        with open(os.path.join(out_dir, f"{label}_{workload}_pmc.json"), "w") as f:
             json.dump(d, f, indent=1)
-    print(f"summaries written to {PROFILES}")
+    print(f"summaries written to {out_dir}")
 
 
 def copy_rate() -> float:
