@@ -149,10 +149,35 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
     lines = [f"# rocprofv3 kernel statistics, workload '{workload}'", f"# command: {command}",
              f"{'kernel':64s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}"]
     rows = sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0)))
-    for r in rows[:25]:
+    ours = [r for r in rows if "dibella::" in r.get("Name", "")]
+    others = [r for r in rows if "dibella::" not in r.get("Name", "")]
+
+    def row_line(r):
         name = r.get("Name", "")[:64]
-        lines.append(f"{name:64s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
-                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r.get('Percentage', 0)):6.2f}")
+        return (f"{name:64s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                f"{float(r['AverageNs']) / 1e3:10.2f} {float(r.get('Percentage', 0)):6.2f}")
+    lines.append("## library kernels (all)")
+    lines.extend(row_line(r) for r in ours)
+    lines.append("## other kernels (workload generation, torch plumbing; largest 10)")
+    lines.extend(row_line(r) for r in others[:10])
+    # per call of the library: k_ov_write_rowptr runs once per overlap call,
+    # k_tr_init_state once per reduction call
+    def calls_of(marker):
+        return sum(int(r["Calls"]) for r in ours if marker in r["Name"])
+    n_ov, n_tr = calls_of("k_ov_write_rowptr"), calls_of("k_tr_init_state")
+    if n_ov or n_tr:
+        lines.append("")
+        lines.append(f"## timed units, kernel time per call ({n_ov} overlap calls, {n_tr} reduction calls)")
+        lines.append(f"{'unit':14s} {'kernels':44s} {'launches/call':>13s} {'ms/call':>9s}")
+        for label, knames in KERNEL_NAMES.items():
+            n = n_tr if label.startswith("tr_") else n_ov
+            hit = [r for r in ours if any(k in r["Name"] for k in knames)]
+            if not hit or not n:
+                continue
+            tot = sum(float(r["TotalDurationNs"]) for r in hit)
+            launches = sum(int(r["Calls"]) for r in hit)
+            note = "  (launches overlap: the phase span is below)" if label == "numeric" else ""
+            lines.append(f"{label:14s} {'+'.join(knames):44s} {launches / n:13.1f} {tot / n / 1e6:9.3f}{note}")
     # the numeric phase of one call: its k_ov_numeric launches overlap on
     # several streams; its span runs from the first start to the last end
     # among the launches that follow one k_ov_write_rowptr

@@ -37,10 +37,18 @@ def profile_dirs(tmp_path):
     trace = tmp_path / "trace"
     _write_csv(str(trace / "host" / "1_kernel_stats.csv"),
                ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
-               [{"Name": "void k_ov_numeric<256>(Args)", "Calls": 4, "TotalDurationNs": 400000,
+               [{"Name": "void dibella::k_ov_numeric<256>(Args)", "Calls": 4, "TotalDurationNs": 400000,
                  "AverageNs": 100000, "Percentage": 80.0},
-                {"Name": "void k_tr_mark<0>(Args)", "Calls": 2, "TotalDurationNs": 100000,
-                 "AverageNs": 50000, "Percentage": 20.0}])
+                {"Name": "void dibella::k_tr_mark<128, 0>(Args)", "Calls": 4, "TotalDurationNs": 100000,
+                 "AverageNs": 25000, "Percentage": 10.0},
+                {"Name": "void dibella::k_tr_mark<128, 1>(Args)", "Calls": 2, "TotalDurationNs": 20000,
+                 "AverageNs": 10000, "Percentage": 2.0},
+                {"Name": "dibella::k_ov_write_rowptr(Args)", "Calls": 2, "TotalDurationNs": 6000,
+                 "AverageNs": 3000, "Percentage": 0.5},
+                {"Name": "dibella::k_tr_init_state(Args)", "Calls": 2, "TotalDurationNs": 4000,
+                 "AverageNs": 2000, "Percentage": 0.4},
+                {"Name": "void at::native::vectorized_elementwise_kernel<4>(Args)", "Calls": 9,
+                 "TotalDurationNs": 900000, "AverageNs": 100000, "Percentage": 70.0}])
     # two overlap calls: the first one's numeric launches overlap on three
     # streams (span 10 us .. 80 us), the second has a single launch of 20 us
     ev = [("k_ov_write_rowptr", 0, 5000), ("k_ov_numeric<256>", 10000, 50000),
@@ -76,8 +84,18 @@ def test_summaries_from_synthetic_rocprof_output(profile_dirs):
                              str(p / "cwrite"), "t", "python3 bench.py --steps 2", out_dir=out)
     text = open(os.path.join(out, "kernels_t_trace.txt")).read()
     assert "# command: python3 bench.py --steps 2" in text
-    # kernels sorted by total time
-    assert text.index("k_ov_numeric") < text.index("k_tr_mark")
+    # library kernels first, each sorted by total time, then the others
+    assert text.index("k_ov_numeric") < text.index("k_tr_mark<128, 0>") < text.index("k_tr_mark<128, 1>")
+    assert text.index("## library kernels") < text.index("k_tr_init_state") < text.index("## other kernels")
+    assert text.index("## other kernels") < text.index("vectorized_elementwise_kernel")
+    # per call: two overlap calls, two reduction calls; a unit sums all of
+    # its kernels' launches
+    block = text[text.index("## timed units"):].split("\n\n")[0].splitlines()[2:]
+    units = {ln.split()[0]: ln.split()[2:4] for ln in block}
+    assert "(2 overlap calls, 2 reduction calls)" in text
+    assert units["tr_mark"] == ["3.0", "0.060"]        # 6 launches, 120 us over 2 calls
+    assert units["numeric"] == ["2.0", "0.200"]        # 4 launches, 400 us over 2 calls
+    assert "keys" not in units
     # spans 70 us and 20 us, 3 and 1 launches per call
     assert "2 calls, 2.0 launches per call, span avg_us 45.00" in text
 
