@@ -364,6 +364,23 @@ def test_overlap_rejects_malformed(lib, case):
     assert ei.value.status == -1
 
 
+def test_overlap_batched_rejects_one_malformed_set(lib):
+    rng = np.random.default_rng(21)
+    sets = [synth.random_a(rng, 20 + 5 * s, 50, 0.2) for s in range(4)]
+    bad = sets[2]
+    col = bad.col.copy()
+    col[3] = 50                                   # column out of range in set 2 only
+    sets_bad = sets[:2] + [synth.CSR(bad.nrows, 50, bad.rowptr, col, bad.val)] + sets[3:]
+    print("overlap batch of 4, set 2 malformed", flush=True)
+    with pytest.raises(lib.DibellaError) as ei:
+        lib.overlap_batched([lib.CSRTensors.from_numpy(a, _dev()) for a in sets_bad], [1] * 4)
+    assert ei.value.status == -1 and "set 2" in str(ei.value)
+    # the library keeps no state from the rejected call
+    Cs = lib.overlap_batched([lib.CSRTensors.from_numpy(a, _dev()) for a in sets], [1] * 4)
+    for s, a in enumerate(sets):
+        assert_overlap_equal(Cs[s], oracle.overlap(a, 1), f"set {s}")
+
+
 # ---------------------------------------------------------------------------
 # Transitive reduction
 # ---------------------------------------------------------------------------
@@ -514,3 +531,26 @@ def test_tr_rejects_malformed(lib, case):
     with pytest.raises(lib.DibellaError) as ei:
         _run_tr(lib, bad, fuzz)
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_tr_batched_rejects_one_malformed_set(lib, graph):
+    rng = np.random.default_rng(22)
+    Rs = [synth.random_r(rng, 30 + 4 * s, 0.2) for s in range(4)]
+    bad = Rs[2]
+    r = int(np.argmax(np.diff(bad.rowptr)))
+    col = bad.col.copy()
+    a, b = int(bad.rowptr[r]), int(bad.rowptr[r + 1])
+    col[a] = r                                    # a diagonal entry in set 2 only
+    col[a:b] = np.sort(col[a:b])
+    Rs_bad = Rs[:2] + [synth.CSR(bad.nrows, bad.ncols, bad.rowptr, col, bad.val)] + Rs[3:]
+    print(f"tr batch of 4, set 2 malformed, graph={graph}", flush=True)
+    with pytest.raises(lib.DibellaError) as ei:
+        lib.transitive_reduce_batched([lib.CSRTensors.from_numpy(x, _dev()) for x in Rs_bad], [10] * 4, graph=graph)
+    assert ei.value.status == -1 and "set 2" in str(ei.value)
+    Ss, its = lib.transitive_reduce_batched([lib.CSRTensors.from_numpy(x, _dev()) for x in Rs], [10] * 4,
+                                            graph=graph)
+    for s, x in enumerate(Rs):
+        ref, it_ref, _ = oracle.transitive_reduce(x, 10)
+        assert_csr_equal(Ss[s], ref, f"set {s}")
+        assert its[s] == it_ref
