@@ -540,10 +540,37 @@ def main():
         if not ok:
             sys.exit(1)
 
-    log(f"warmup {args.warmup} ...")
-    for _ in range(args.warmup):
-        step()
+    def units(phases, nsteps, C, tr_stats):
+        """ms and launches per step of every recorded unit, the algorithmic
+        bytes of each, and the unit with the largest time."""
+        per_step_ms = {k: v[0] / nsteps for k, v in phases.items() if v[1] > 0}
+        launches = {k: v[1] / nsteps for k, v in phases.items() if v[1] > 0}
+        # radix passes of the transpose, if the library took that path (very many columns)
+        pb = kernel_bytes(w, C.nnz, products, tr_stats, int(round(launches.get("sort_down", 0))))
+        # the numeric launches of one call overlap on several streams: the phase
+        # (first launch to last, one record per call) is the unit that is timed
+        if "numeric_phase" in per_step_ms and "numeric" in pb:
+            pb["numeric_phase"] = pb.pop("numeric")
+        dominant = max((k for k in per_step_ms if k in pb), key=lambda k: per_step_ms[k])
+        return per_step_ms, launches, pb, dominant
+
+    # every unit's events are recorded over the warmup steps after the first
+    # (the per-unit table, and the choice of the dominant unit); the timed
+    # steps record only the dominant unit's, so that the events of the other
+    # units cost the timed steps no host time
+    prof_steps = max(args.warmup - 1, 1) if args.warmup > 0 else 0
+    log(f"warmup {args.warmup} ({prof_steps} with every unit timed) ...")
+    for i in range(args.warmup):
+        if i == args.warmup - prof_steps:
+            torch.cuda.synchronize()
+            _lib.timing_enable(True)
+        C, S, it = step()
     torch.cuda.synchronize()
+    if prof_steps:
+        unit_phases = _lib.timing_collect()
+        _lib.timing_enable(False)
+        per_step_ms, launches, pb, dominant = units(unit_phases, prof_steps, C, db.last_stats())
+        _lib.timing_select([dominant])
     _lib.timing_enable(True)
     log(f"timing {args.steps} steps ...")
     torch.cuda.synchronize()
@@ -554,6 +581,7 @@ def main():
     elapsed = time.perf_counter() - t0
     phases = _lib.timing_collect()
     _lib.timing_enable(False)
+    _lib.timing_select(None)
     tr_stats = db.last_stats()          # last call = the reduction
     db.overlap(A, w.min_shared)
     ov_stats = db.last_stats()
@@ -562,18 +590,14 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     per_step_products = products + triples
     value = per_step_products / (elapsed / args.steps)
+    if not prof_steps:
+        per_step_ms, launches, pb, dominant = units(phases, args.steps, C, tr_stats)
 
-    # roofline of the dominant kernel (largest measured time per step)
-    per_step_ms = {k: v[0] / args.steps for k, v in phases.items() if v[1] > 0}
-    launches = {k: v[1] / args.steps for k, v in phases.items() if v[1] > 0}
-    # radix passes of the transpose, if the library took that path (very many columns)
-    pb = kernel_bytes(w, C.nnz, products, tr_stats, int(round(launches.get("sort_down", 0))))
-    # the numeric launches of one call overlap on several streams: the phase
-    # (first launch to last, one record per call) is the unit that is timed
-    if "numeric_phase" in per_step_ms and "numeric" in pb:
-        pb["numeric_phase"] = pb.pop("numeric")
-    dominant = max((k for k in per_step_ms if k in pb), key=lambda k: per_step_ms[k])
-    dom_ms = per_step_ms[dominant]
+    # roofline of the dominant kernel, from its events over the timed steps
+    if phases[dominant][1] == 0:
+        raise RuntimeError(f"no timing records of '{dominant}' over the timed steps")
+    dom_ms = phases[dominant][0] / args.steps
+    launches = dict(launches, **{dominant: phases[dominant][1] / args.steps})
     achieved = pb[dominant] / (dom_ms * 1e-3) / 1e9
     traffic = load_traffic(dominant, args.workload,
                            source_hash(*KERNEL_SOURCES["numeric" if dominant == "numeric_phase" else dominant]))
@@ -593,6 +617,8 @@ def main():
     kernels = {k: {"ms_per_step": round(per_step_ms[k], 4), "launches_per_step": launches[k],
                    "model_GBps": (round(pb[k] / (per_step_ms[k] * 1e-3) / 1e9, 1) if k in pb else None)}
                for k in per_step_ms}
+    kernels_timed_over = (f"{prof_steps} warmup steps (every unit's events)" if prof_steps
+                          else f"the {args.steps} timed steps")
 
     batch = None
     if args.batch_sets > 0:
@@ -624,12 +650,14 @@ def main():
                    "tr_passes": it, "tr_walks": triples, "fuzz": w.fuzz, "graph": args.graph,
                    "parallelism": "single GPU"},
         "kernels": kernels,
+        "kernels_timed_over": kernels_timed_over,
         "overlap_products_per_s_gpu_time": products / (sum(
             per_step_ms.get(k, 0) for k in ("keys", "part_count", "part_scatter", "bucket_sort", "sort_up", "sort_down",
                                              "segments", "sym_bits", "sym_hash",
                                              "numeric_phase" if "numeric_phase" in per_step_ms else "numeric",
                                              "esc")) * 1e-3),
-        "overlap_products_per_s_numeric_phase": (products / (per_step_ms["numeric_phase"] * 1e-3)
+        "overlap_products_per_s_numeric_phase": (products / (dom_ms * 1e-3) if dominant == "numeric_phase" else
+                                                 products / (per_step_ms["numeric_phase"] * 1e-3)
                                                  if "numeric_phase" in per_step_ms else None),
         "tr_walks_per_s_mark": (triples / (per_step_ms["tr_mark"] * 1e-3) if "tr_mark" in per_step_ms else None),
         "tr_nnz_trace": [int(x) for x in tr_stats["nnz_trace"]],

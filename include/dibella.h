@@ -224,6 +224,11 @@ typedef struct {
 } dibella_timing;
 
 int dibella_timing_enable(int on);
+/* Labels recorded while timing is enabled on this host thread: bit i selects
+ * label i (all labels by default).  A launch whose label is not selected
+ * records no events and costs no host time.  Bits at DIBELLA_NUM_PHASES or
+ * above are rejected with EINVAL.  Records already taken are kept. */
+int dibella_timing_select(uint32_t label_mask);
 int dibella_timing_collect(dibella_timing* out);
 
 #ifdef __cplusplus

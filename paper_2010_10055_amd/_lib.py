@@ -28,7 +28,7 @@ TR_USE_GRAPH = 0x8
 EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batched",
            "dibella_transitive_reduce_batched", "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
-           "dibella_timing_collect"]
+           "dibella_timing_select", "dibella_timing_collect"]
 PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "sort_up", "sort_down", "segments", "sym_bits", "sym_hash", "numeric", "esc",
           "tr_mark", "tr_compact", "numeric_phase"]
 
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dibella_set_tuning.argtypes = [P]
     lib.dibella_last_stats.argtypes = [P]
     lib.dibella_timing_enable.argtypes = [ctypes.c_int]
+    lib.dibella_timing_select.argtypes = [ctypes.c_uint32]
     lib.dibella_timing_collect.argtypes = [P]
     return lib
 
@@ -347,6 +348,17 @@ def set_tuning(**kw) -> dict:
 def timing_enable(on: bool = True) -> None:
     """Record HIP events around the main kernels of later calls on this thread."""
     _check(lib().dibella_timing_enable(1 if on else 0))
+
+
+def timing_select(labels=None) -> None:
+    """Record only these labels (names of PHASES) from now on; None = all."""
+    if labels is None:
+        mask = (1 << len(PHASES)) - 1
+    else:
+        mask = 0
+        for name in labels:
+            mask |= 1 << PHASES.index(name)
+    _check(lib().dibella_timing_select(mask))
 
 
 def timing_collect() -> dict:

@@ -113,6 +113,12 @@ int dibella_timing_enable(int on) {
     return DIBELLA_OK;
 }
 
+int dibella_timing_select(uint32_t label_mask) {
+    if (label_mask >> DIBELLA_NUM_PHASES) return DIBELLA_EINVAL;
+    timing_set_mask(label_mask);
+    return DIBELLA_OK;
+}
+
 int dibella_timing_collect(dibella_timing* out) {
     if (!out) return DIBELLA_EINVAL;
     return timing_collect(out);

@@ -144,6 +144,7 @@ bool timing_on();
 int timing_begin(int phase, hipStream_t s, int* token);
 int timing_end(int token, hipStream_t s);
 void timing_set_enabled(bool on);
+void timing_set_mask(uint32_t mask);
 int timing_collect(dibella_timing* out);
 
 // ---------------------------------------------------------------------------

@@ -223,6 +223,7 @@ struct TimingRec {
 };
 struct TimingState {
     bool on = false;
+    uint32_t mask = ~0u;   // labels recorded while on (bit i = label i)
     std::vector<TimingRec> recs;
     std::vector<hipEvent_t> pool;
     ~TimingState() {
@@ -254,7 +255,7 @@ bool timing_on() { return tstate().on; }
 int timing_begin(int phase, hipStream_t s, int* token) {
     *token = -1;
     TimingState& t = tstate();
-    if (!t.on) return DIBELLA_OK;
+    if (!t.on || phase < 0 || phase >= 32 || !((t.mask >> phase) & 1u)) return DIBELLA_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     DB_HIP(hipStreamIsCapturing(s, &cs));
     if (cs != hipStreamCaptureStatusNone) return DIBELLA_OK;
@@ -272,6 +273,8 @@ int timing_end(int token, hipStream_t s) {
     DB_HIP(hipEventRecord(tstate().recs[token].b, s));
     return DIBELLA_OK;
 }
+
+void timing_set_mask(uint32_t mask) { tstate().mask = mask; }
 
 void timing_set_enabled(bool on) {
     TimingState& t = tstate();

@@ -554,3 +554,35 @@ def test_tr_batched_rejects_one_malformed_set(lib, graph):
         ref, it_ref, _ = oracle.transitive_reduce(x, 10)
         assert_csr_equal(Ss[s], ref, f"set {s}")
         assert its[s] == it_ref
+
+
+def test_timing_records_only_selected_labels(lib):
+    from paper_2010_10055_amd import _lib
+    w = synth.make_workload("tiny", seed=31)
+    A = lib.CSRTensors.from_numpy(w.A, _dev())
+    R = lib.CSRTensors.from_numpy(w.R, _dev())
+    ref = oracle.overlap(w.A, w.min_shared)
+    Sref, _, _ = oracle.transitive_reduce(w.R, w.fuzz)
+    print("timing: all labels, then numeric_phase only", flush=True)
+    try:
+        _lib.timing_enable(True)
+        C = lib.overlap(A, w.min_shared)
+        S, _ = lib.transitive_reduce(R, w.fuzz)
+        every = _lib.timing_collect()
+        for name in ("keys", "segments", "numeric_phase", "tr_mark", "tr_compact"):
+            assert every[name][1] > 0, name
+        assert_overlap_equal(C, ref, "all labels")
+        assert_csr_equal(S, Sref, "all labels")
+
+        _lib.timing_select(["numeric_phase"])
+        for _ in range(2):
+            C = lib.overlap(A, w.min_shared)
+            S, _ = lib.transitive_reduce(R, w.fuzz)
+        only = _lib.timing_collect()
+        assert only["numeric_phase"][1] == 2 and only["numeric_phase"][0] > 0
+        assert all(v[1] == 0 for k, v in only.items() if k != "numeric_phase"), only
+        assert_overlap_equal(C, ref, "numeric_phase only")
+        assert_csr_equal(S, Sref, "numeric_phase only")
+    finally:
+        _lib.timing_enable(False)
+        _lib.timing_select(None)
