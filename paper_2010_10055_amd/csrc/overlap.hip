@@ -371,8 +371,8 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_count(const uint32_t* __
 }
 
 // K: the width of the keys written out; pass 2 reads only their low `low`
-// bits, so buckets of at most 2^16 columns take 16-bit keys (half the key
-// bytes of both passes).
+// bits, so the buckets that pass 2 sorts in staged sweeps (at most 2^15
+// columns) take 16-bit keys (half the key bytes of both passes).
 template <class K>
 __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
     const uint32_t* __restrict__ keys, const uint64_t* __restrict__ pays, int64_t n, int per_block, int low,
