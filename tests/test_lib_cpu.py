@@ -79,3 +79,12 @@ def test_timing_label_selection_range(lib):
         _lib.timing_select(["no_such_label"])
     _lib.timing_select(None)
     assert lib.dibella_timing_select((1 << 16) - 1) == _lib.OK
+
+
+def test_timing_labels_match_the_header():
+    from paper_2010_10055_amd import _lib
+    text = open(os.path.join(ROOT, "include", "dibella.h")).read()
+    block = text[text.index("Kernel timing with HIP events"):text.index("#define DIBELLA_NUM_PHASES")]
+    labels = dict((int(n), name) for n, name in re.findall(r"^\s*\*\s+(\d+)\s+(\w+)", block, re.M))
+    assert [labels[i] for i in range(len(labels))] == _lib.PHASES
+    assert len(_lib.PHASES) <= int(re.search(r"#define DIBELLA_NUM_PHASES (\d+)", text).group(1))
