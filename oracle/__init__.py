@@ -17,14 +17,24 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dibella_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-# A separately built oracle library to load instead (the tests that plant
-# mistakes in a copy of the oracle source point this at the planted build).
-_LIB_OVERRIDE = os.environ.get("DIBELLA_ORACLE_LIB")
+# A separately built oracle library to load instead: set only by an explicit
+# use_library() call (the test that plants mistakes in copies of the oracle
+# source calls it in its own child processes, never through the environment).
+_LIB_OVERRIDE = None
 
 VARIANT_B = 0x1
 RULE_EDGE = 0x2
 
 _lib = None
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of its source (for the child
+    processes of the planted-mistake test).  Must be called before any use."""
+    global _LIB_OVERRIDE, _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _LIB_OVERRIDE = path
 
 
 def build(force: bool = True) -> str:
@@ -50,6 +60,9 @@ def _load():
         i64, i32, u32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
         lib.oracle_overlap_rows.argtypes = [i64, i64, P, P, P, i32, P, i64, P,
                                             P, P, P, P]
+        lib.oracle_transpose.argtypes = [i64, i64, P, P, P, P, P, P]
+        lib.oracle_overlap_rows_t.argtypes = [i64, i64, P, P, P, P, P, P, i32, P, i64, P,
+                                              P, P, P, P]
         lib.oracle_transitive_reduce.argtypes = [i64, P, P, P, i32, u32, P, P, P, P, P, P, i32, P]
         lib.oracle_tr_pass_marks.argtypes = [i64, P, P, P, i32, u32, P, i64, P]
         lib.oracle_free.argtypes = [P]
@@ -79,9 +92,24 @@ def _csr_arrays(M):
             np.ascontiguousarray(M.val, dtype=np.int32))
 
 
-def overlap(A, min_shared: int = 1, rows=None):
+def transpose(A):
+    """A^T of A: SimpleNamespace(rowptr int64[m+1], read int32[nnz], pos
+    int32[nnz]), rows in increasing read order.  Can be passed to overlap()
+    by several threads at once (it is only read)."""
+    lib = _load()
+    rp, ci, va = _csr_arrays(A)
+    t_rp = np.zeros(A.ncols + 1, np.int64)
+    t_read = np.zeros(ci.size, np.int32)
+    t_pos = np.zeros(ci.size, np.int32)
+    lib.oracle_transpose(A.nrows, A.ncols, _ptr(rp), _ptr(ci), _ptr(va), _ptr(t_rp), _ptr(t_read),
+                         _ptr(t_pos))
+    return SimpleNamespace(rowptr=t_rp, read=t_read, pos=t_pos)
+
+
+def overlap(A, min_shared: int = 1, rows=None, at=None):
     """C = A A^T over the overlap semiring.  rows: optional row subset
-    (the result then has len(rows) rows, in that order)."""
+    (the result then has len(rows) rows, in that order).  at: A^T from
+    transpose(A) (else the call builds its own)."""
     lib = _load()
     rp, ci, va = _csr_arrays(A)
     if rows is None:
@@ -92,10 +120,17 @@ def overlap(A, min_shared: int = 1, rows=None):
     out_rp = np.zeros(nout + 1, np.int64)
     pc, pn, ps = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
     nnz = ctypes.c_int64()
-    lib.oracle_overlap_rows(A.nrows, A.ncols, _ptr(rp), _ptr(ci), _ptr(va), int(min_shared),
-                            _ptr(sel) if sel is not None else None, nsel, _ptr(out_rp),
-                            ctypes.byref(pc), ctypes.byref(pn), ctypes.byref(ps),
-                            ctypes.byref(nnz))
+    if at is None:
+        lib.oracle_overlap_rows(A.nrows, A.ncols, _ptr(rp), _ptr(ci), _ptr(va), int(min_shared),
+                                _ptr(sel) if sel is not None else None, nsel, _ptr(out_rp),
+                                ctypes.byref(pc), ctypes.byref(pn), ctypes.byref(ps),
+                                ctypes.byref(nnz))
+    else:
+        lib.oracle_overlap_rows_t(A.nrows, A.ncols, _ptr(rp), _ptr(ci), _ptr(va), _ptr(at.rowptr),
+                                  _ptr(at.read), _ptr(at.pos), int(min_shared),
+                                  _ptr(sel) if sel is not None else None, nsel, _ptr(out_rp),
+                                  ctypes.byref(pc), ctypes.byref(pn), ctypes.byref(ps),
+                                  ctypes.byref(nnz))
     return SimpleNamespace(nrows=nout, ncols=A.nrows, rowptr=out_rp,
                            col=_take(lib, pc, nnz.value, np.int32),
                            count=_take(lib, pn, nnz.value, np.int32),

@@ -60,22 +60,27 @@ static int cmp_i32(const void* a, const void* b) {
     return (x > y) - (x < y);
 }
 
-/* Rows `sel[0..nsel)` of C = A A^T (nsel < 0: all rows, in order).
+/* A^T into caller arrays t_rowptr[m+1], t_read[nnz], t_pos[nnz], so that
+ * several row ranges (threads) can share one transpose. */
+int oracle_transpose(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                     const int32_t* val, int64_t* t_rowptr, int32_t* t_read, int32_t* t_pos) {
+    transpose(n, m, rowptr, col, val, t_rowptr, t_read, t_pos);
+    return 0;
+}
+
+/* Rows `sel[0..nsel)` of C = A A^T (nsel < 0: all rows, in order), given
+ * A^T (as built by oracle_transpose; it is only read).
  * Per row: walk k in A_i in increasing order, and for every (j, p_j) in row k
  * of A^T, add 1 to the count of C_ij and append (A_ik, p_j) while fewer than
  * two pairs are stored.  Keep entries with count >= min_shared, sorted by j.
  * Outputs: out_rowptr[nrows_out+1], *out_col, *out_count, *out_seed (4 per
  * entry: p_i0, p_j0, p_i1, p_j1, -1 where absent). */
-int oracle_overlap_rows(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
-                        const int32_t* val, int32_t min_shared, const int64_t* sel, int64_t nsel,
-                        int64_t* out_rowptr, int32_t** out_col, int32_t** out_count,
-                        int32_t** out_seed, int64_t* out_nnz) {
-    int64_t nnz_a = rowptr[n];
-    int64_t* t_rowptr = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(m + 1));
-    int32_t* t_read = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)nnz_a);
-    int32_t* t_pos = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)nnz_a);
-    transpose(n, m, rowptr, col, val, t_rowptr, t_read, t_pos);
-
+int oracle_overlap_rows_t(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                          const int32_t* val, const int64_t* t_rowptr, const int32_t* t_read,
+                          const int32_t* t_pos, int32_t min_shared, const int64_t* sel, int64_t nsel,
+                          int64_t* out_rowptr, int32_t** out_col, int32_t** out_count,
+                          int32_t** out_seed, int64_t* out_nnz) {
+    (void)m;
     int32_t* count = (int32_t*)calloc((size_t)(n ? n : 1), sizeof(int32_t));
     int32_t* seeds = (int32_t*)xmalloc(sizeof(int32_t) * 4 * (size_t)(n ? n : 1));
     int32_t* touched = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(n ? n : 1));
@@ -122,9 +127,25 @@ int oracle_overlap_rows(int64_t n, int64_t m, const int64_t* rowptr, const int32
         }
         out_rowptr[r + 1] = nnz;
     }
-    free(t_rowptr); free(t_read); free(t_pos); free(count); free(seeds); free(touched);
+    free(count); free(seeds); free(touched);
     *out_col = oc; *out_count = on; *out_seed = os; *out_nnz = nnz;
     return 0;
+}
+
+/* The same, building A^T first (one call, one transpose). */
+int oracle_overlap_rows(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,
+                        const int32_t* val, int32_t min_shared, const int64_t* sel, int64_t nsel,
+                        int64_t* out_rowptr, int32_t** out_col, int32_t** out_count,
+                        int32_t** out_seed, int64_t* out_nnz) {
+    int64_t nnz_a = rowptr[n];
+    int64_t* t_rowptr = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(m + 1));
+    int32_t* t_read = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)nnz_a);
+    int32_t* t_pos = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)nnz_a);
+    transpose(n, m, rowptr, col, val, t_rowptr, t_read, t_pos);
+    int r = oracle_overlap_rows_t(n, m, rowptr, col, val, t_rowptr, t_read, t_pos, min_shared, sel,
+                                  nsel, out_rowptr, out_col, out_count, out_seed, out_nnz);
+    free(t_rowptr); free(t_read); free(t_pos);
+    return r;
 }
 
 int oracle_overlap(int64_t n, int64_t m, const int64_t* rowptr, const int32_t* col,

@@ -135,6 +135,36 @@ def test_overlap_row_subset_matches_full():
         assert np.array_equal(full.seed[a:b], sub.seed[c:d])
 
 
+def test_transpose_lists_each_column_by_read():
+    """A^T built once: row k lists (read, position) of every A entry in column
+    k, reads increasing (checked against a direct scipy transpose)."""
+    rng = np.random.default_rng(41)
+    A = synth.random_a(rng, 120, 400, 0.03)
+    at = oracle.transpose(A)
+    n = A.nrows
+    rows = np.repeat(np.arange(n), np.diff(A.rowptr))
+    T = sp.csr_matrix((A.val.astype(np.int64) + 1, (A.col, rows)), shape=(A.ncols, n))
+    T.sort_indices()
+    assert np.array_equal(at.rowptr, T.indptr)
+    assert np.array_equal(at.read, T.indices)
+    assert np.array_equal(at.pos.astype(np.int64), T.data - 1)
+
+
+def test_overlap_with_shared_transpose_in_row_ranges():
+    """Row ranges computed with one shared A^T (as threads do) concatenate to
+    the full product."""
+    w = synth.make_workload("tiny")
+    full = oracle.overlap(w.A, 1)
+    at = oracle.transpose(w.A)
+    cuts = [0, 37, 38, 120, w.A.nrows]
+    parts = [oracle.overlap(w.A, 1, rows=np.arange(a, b), at=at) for a, b in zip(cuts[:-1], cuts[1:])]
+    assert np.array_equal(np.concatenate([p.col for p in parts]), full.col)
+    assert np.array_equal(np.concatenate([p.count for p in parts]), full.count)
+    assert np.array_equal(np.concatenate([p.seed for p in parts]), full.seed)
+    lens = np.concatenate([np.diff(p.rowptr) for p in parts])
+    assert np.array_equal(lens, np.diff(full.rowptr))
+
+
 def test_overlap_empty_inputs():
     A = synth.CSR(3, 5, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
     C = oracle.overlap(A, 1)

@@ -60,12 +60,20 @@ def _build(text, out_dir, name):
     return so
 
 
+# The child loads the planted build explicitly (oracle.use_library) before
+# running the pins in-process: no environment variable swaps the oracle.
+_CHILD = (
+    "import sys, pytest, oracle\n"
+    "oracle.use_library(sys.argv[1])\n"
+    "sys.exit(pytest.main([sys.argv[2], '-x', '-q', '-p', 'no:cacheprovider', '-m', 'not gpu']))\n"
+)
+
+
 def _run_pins(so):
     # one thread per child: the children run side by side
-    env = dict(os.environ, DIBELLA_ORACLE_LIB=so, PYTHONDONTWRITEBYTECODE="1", OMP_NUM_THREADS="1",
-               MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join("tests", "test_oracle.py"), "-x", "-q",
-                        "-p", "no:cacheprovider", "-m", "not gpu"],
+    env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1", OMP_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               OPENBLAS_NUM_THREADS="1", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", _CHILD, so, os.path.join("tests", "test_oracle.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout[-3000:] + r.stderr[-2000:]
 
