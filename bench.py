@@ -41,26 +41,27 @@ def source_hash(*names) -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_bytes(w, C_nnz, products, tr_stats, sort_passes):
+def kernel_bytes(w, C_nnz, products, tr_stats):
     """Algorithmic bytes per step of each timed kernel.  The two products use
     the CSR Gustavson model of a row-wise SpGEMM (symbolic: row pointers, A
     columns and the column's A^T segment per entry, 4 B per product;
     numeric: the same plus A values, 8 B per product and 24 B per output
-    entry); the transpose kernels move what a sort of 12-byte (column,
-    read|position) pairs must; a reduction pass reads a row-pointer pair per
-    entry and 8 B per walk."""
+    entry); every partition pass of the transpose moves what a pass over
+    12-byte (column, read|position) pairs must (12 B in, 12 B out; its count
+    pass reads the 4-byte keys) and the last pass also writes 8 B per column
+    record; a reduction pass reads a row-pointer pair per entry and 8 B per
+    walk."""
     n, nnzA, m = w.A.nrows, w.A.nnz, w.A.ncols
     trace = tr_stats["nnz_trace"]
     trip = tr_stats["triples_trace"]
     sym = 8 * n + 20 * nnzA + 4 * products + 8 * n
-    radix = sort_passes > 0
     return {
         "keys": 8 * n + 8 * nnzA + 12 * nnzA,
         "part_count": 4 * nnzA,
         "part_scatter": 24 * nnzA,
-        "bucket_sort": (4 * nnzA + 8 * m) if radix else (24 * nnzA + 8 * m),
-        "sort_up": 4 * nnzA * sort_passes,
-        "sort_down": 24 * nnzA * sort_passes,
+        "part2_count": 4 * nnzA,
+        "part2_scatter": 24 * nnzA,
+        "bucket_sort": 24 * nnzA + 8 * m,
         "segments": 16 * n + 20 * nnzA,
         "sym_bits": sym,
         "sym_hash": sym,
@@ -71,7 +72,7 @@ def kernel_bytes(w, C_nnz, products, tr_stats, sort_passes):
 
 
 KERNEL_SOURCES = {"keys": ("overlap.hip",), "part_count": ("overlap.hip",), "part_scatter": ("overlap.hip",),
-                  "bucket_sort": ("overlap.hip",), "sort_up": ("sort.hip",), "sort_down": ("sort.hip",),
+                  "bucket_sort": ("overlap.hip",), "part2_count": ("overlap.hip",), "part2_scatter": ("overlap.hip",),
                   "segments": ("overlap.hip",), "sym_bits": ("overlap.hip",),
                   "sym_hash": ("overlap.hip",), "numeric": ("overlap.hip",), "esc": ("overlap.hip",),
                   "tr_mark": ("tr.hip",), "tr_compact": ("tr.hip",)}
@@ -95,9 +96,10 @@ def load_traffic(kernel: str, workload: str, src_hash: str, profiles: str = PROF
 
 
 # the kernels of each timed unit (a unit of several kernels sums them per call)
-KERNEL_NAMES = {"keys": ("k_ov_keys",), "part_count": ("k_ov_part_count",), "part_scatter": ("k_ov_part_scatter",),
-                "bucket_sort": ("k_ov_bucket_sort", "k_ov_ct_from_rowptr"), "sort_up": ("k_rs_upsweep",),
-                "sort_down": ("k_rs_downsweep",), "segments": ("k_ov_seg_slices", "k_ov_scatter"),
+KERNEL_NAMES = {"keys": ("k_ov_keys",), "part_count": ("k_ov_part_count<false>",),
+                "part_scatter": ("k_ov_part_scatter<false",), "part2_count": ("k_ov_part_count<true>",),
+                "part2_scatter": ("k_ov_part_scatter<true",), "bucket_sort": ("k_ov_bucket_sort",),
+                "segments": ("k_ov_seg_slices", "k_ov_scatter"),
                 "sym_bits": ("k_ov_sym_bits",), "sym_hash": ("k_ov_sym_hash",), "numeric": ("k_ov_numeric",),
                 "tr_mark": ("k_tr_mark",), "tr_compact": ("k_tr_compact",)}
 CALIB_BYTES = 1 << 30
@@ -545,8 +547,7 @@ def main():
         bytes of each, and the unit with the largest time."""
         per_step_ms = {k: v[0] / nsteps for k, v in phases.items() if v[1] > 0}
         launches = {k: v[1] / nsteps for k, v in phases.items() if v[1] > 0}
-        # radix passes of the transpose, if the library took that path (very many columns)
-        pb = kernel_bytes(w, C.nnz, products, tr_stats, int(round(launches.get("sort_down", 0))))
+        pb = kernel_bytes(w, C.nnz, products, tr_stats)
         # the numeric launches of one call overlap on several streams: the phase
         # (first launch to last, one record per call) is the unit that is timed
         if "numeric_phase" in per_step_ms and "numeric" in pb:
@@ -652,7 +653,7 @@ def main():
         "kernels": kernels,
         "kernels_timed_over": kernels_timed_over,
         "overlap_products_per_s_gpu_time": products / (sum(
-            per_step_ms.get(k, 0) for k in ("keys", "part_count", "part_scatter", "bucket_sort", "sort_up", "sort_down",
+            per_step_ms.get(k, 0) for k in ("keys", "part_count", "part_scatter", "part2_count", "part2_scatter", "bucket_sort",
                                              "segments", "sym_bits", "sym_hash",
                                              "numeric_phase" if "numeric_phase" in per_step_ms else "numeric",
                                              "esc")) * 1e-3),

@@ -200,10 +200,12 @@ int dibella_last_stats(dibella_stats* out);
  *   1 part_count    bucketed transpose: bucket histogram per chunk of pairs
  *   2 part_scatter  bucketed transpose: pairs grouped by bucket
  *   3 bucket_sort   bucketed transpose: per bucket, a counting sort by column
- *                   giving the A^T entries and one record per column (radix
- *                   case: the records from the sorted columns)
- *   4 sort_up       radix case (very many columns or entries): digit histograms
- *   5 sort_down     radix case: stable scatter (one launch per 8-bit pass)
+ *                   in staged sweeps giving the A^T entries and one record
+ *                   per column
+ *   4 part2_count   three-level transpose (very many columns): per chunk of
+ *                   a segment, its bucket histogram
+ *   5 part2_scatter three-level transpose: pairs of each segment grouped by
+ *                   bucket
  *   6 segments      A^T segment per A entry, products per row, row bins
  *   7 sym_bits      symbolic phase, bitmap path
  *   8 sym_hash      symbolic phase, hash path (one launch per table size)

@@ -29,8 +29,8 @@ EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batc
            "dibella_transitive_reduce_batched", "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
            "dibella_timing_select", "dibella_timing_collect"]
-PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "sort_up", "sort_down", "segments", "sym_bits", "sym_hash", "numeric", "esc",
-          "tr_mark", "tr_compact", "numeric_phase"]
+PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "part2_count", "part2_scatter", "segments", "sym_bits",
+          "sym_hash", "numeric", "esc", "tr_mark", "tr_compact", "numeric_phase"]
 
 
 class DibellaError(RuntimeError):

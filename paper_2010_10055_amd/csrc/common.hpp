@@ -137,7 +137,7 @@ int side_streams(SideStreams** out);
 // Event timing of phases (no-ops unless enabled on this host thread).
 // Timed kernels (labels of dibella_timing, see the header).
 enum Phase {
-    kPhKeys = 0, kPhPartCount, kPhPartScatter, kPhBucketSort, kPhSortUp, kPhSortDown, kPhSegments,
+    kPhKeys = 0, kPhPartCount, kPhPartScatter, kPhBucketSort, kPhPart2Count, kPhPart2Scatter, kPhSegments,
     kPhSymBits, kPhSymHash, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact, kPhNumericAll
 };
 bool timing_on();

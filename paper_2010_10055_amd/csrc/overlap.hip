@@ -3,9 +3,9 @@
 // two smallest shared k-mer columns.
 //
 // Pipeline (one launch per step for all sets of a batch):
-//   validate A and lay out its (column, read|position) pairs  ->  two-pass
-//   bucketed counting sort by column: A^T and one record per column (a
-//   column of two pairs carries them)  ->  per A entry its segment word (per
+//   validate A and lay out its (column, read|position) pairs  ->  bucketed
+//   counting sort by column in two or three passes: A^T and one record per
+//   column (a column of two pairs carries them)  ->  per A entry its segment word (per
 //   XCD column slice), products per row, row bins  ->  symbolic  ->  bins by
 //   output size  ->  scan to C's row pointers  ->  numeric.
 // Symbolic and numeric walk the products of one row per workgroup:
@@ -27,9 +27,6 @@
 #include <cstring>
 
 namespace dibella {
-
-int radix_sort_pairs(uint32_t* ka, uint64_t* va, uint32_t* kb, uint64_t* vb, int64_t n, int bits, int* in_b,
-                     Arena& ar);
 
 struct OvSet {
     const int64_t* a_rowptr;
@@ -204,11 +201,20 @@ __host__ __device__ __forceinline__ int slice_of(int64_t c, SliceMap sm) {
 // Step 1: validate A (one wave per row) and lay out its entries as pairs
 // over the global entry space: key = global column, value =
 // (position << 32) | read.  Grouping the pairs by key gives A^T.  With
-// slices, the row's slice boundaries are recorded as well: bnd[s] = first
-// entry of the row (relative to its start) whose column lies in slice s or
-// later, for s = 0..count (bnd[count] = row length).
+// slices, the row's slice boundaries are recorded as well, slice-major:
+// bnd[s * rows + g] = first entry of row g (relative to its start) whose
+// column lies in slice s or later, for s = 0..count (s = count: the row
+// length).
 // ---------------------------------------------------------------------------
 constexpr int kKeysIlp = 8;
+
+// Workgroup b runs on XCD b mod 8 (dispatch is round-robin over the 8 XCDs):
+// numbering the workgroups XCD by XCD gives each XCD one contiguous range of
+// rows, so that the slice-major boundary writes of neighbouring rows (one
+// 64-byte line holds 16 of them) meet in one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
+    return (grid & 7) ? b : (b & 7) * (grid >> 3) + (b >> 3);
+}
 
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict__ sets, int nsets,
@@ -219,8 +225,8 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
     const int lane = lane_id();
     // the row, its set and the set's fields are wave-uniform: kept in scalar
     // registers so that the entry loads do not wait on them
-    for (int64_t g = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(wave_id()); g < total_rows;
-         g += (int64_t)gridDim.x * WPB) {
+    for (int64_t g = xcd_block(blockIdx.x, gridDim.x) * WPB + __builtin_amdgcn_readfirstlane(wave_id());
+         g < total_rows; g += (int64_t)gridDim.x * WPB) {
         const int s = find_set(set_base, nsets, g);
         const OvSet S = sets[s];
         const int64_t i = g - S.row_base;
@@ -235,7 +241,7 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
         } else {
             int32_t prev_last = 0;   // column of the entry before this step's first
             int prev_sl = -1;        // slice of the entry before this step's first
-            int32_t* rb = sm.count ? bnd + g * (sm.count + 1) : nullptr;
+            int32_t* rb = sm.count ? bnd + g : nullptr;   // boundary b at rb[b * total_rows]
             for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kKeysIlp) {
                 int32_t kk[kKeysIlp], vv[kKeysIlp];
 #pragma unroll
@@ -274,37 +280,17 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
                         const int up = __shfl_up(sl, 1, kWave);
                         const int psl = lane ? up : prev_sl;
                         if (in)
-                            for (int b = max(psl, -1) + 1; b <= sl; ++b) rb[b] = (int32_t)(e - lo);
+                            for (int b = max(psl, -1) + 1; b <= sl; ++b) rb[(int64_t)b * total_rows] = (int32_t)(e - lo);
                         prev_sl = __shfl(sl, kWave - 1, kWave);
                     }
                 }
             }
             if (rb)
-                for (int b = prev_sl + 1 + lane; b <= sm.count; b += kWave) rb[b] = (int32_t)(hi - lo);
+                for (int b = prev_sl + 1 + lane; b <= sm.count; b += kWave) rb[(int64_t)b * total_rows] = (int32_t)(hi - lo);
         }
         bad = wave_or(bad);
         if (lane == 0 && bad) atomicOr(&flags[s], bad);
     }
-}
-
-// Row pointers of A^T from keys sorted by the radix path: every run boundary
-// fills the pointers of the columns it passes (empty columns included).
-__global__ void k_ov_trowptr(const uint32_t* __restrict__ keys, int64_t n, int64_t total_m,
-                             uint32_t* __restrict__ t_rowptr) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = keys[e];
-        const int64_t kp = e > 0 ? (int64_t)keys[e - 1] : -1;
-        for (int64_t c = kp + 1; c <= k; ++c) t_rowptr[c] = (uint32_t)e;
-        if (e == n - 1)
-            for (int64_t c = k + 1; c <= total_m; ++c) t_rowptr[c] = (uint32_t)n;
-    }
-}
-
-// Column records (segments only) from row pointers.
-__global__ void k_ov_rec_from_rowptr(const uint32_t* __restrict__ t_rowptr, int64_t total_m,
-                                     uint64_t* __restrict__ rec) {
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total_m; c += (int64_t)gridDim.x * blockDim.x)
-        rec[c] = ((uint64_t)t_rowptr[c] << 24) | (uint64_t)(t_rowptr[c + 1] - t_rowptr[c]);
 }
 
 // Products of an A entry whose column has record r.
@@ -313,19 +299,24 @@ __device__ __forceinline__ int64_t rec_products(uint64_t r) {
 }
 
 // ---------------------------------------------------------------------------
-// Step 2: group the pairs by column with a two-pass bucketed counting sort
-// (at most kMaxBuckets buckets of 2^low columns, low <= kMaxLow):
+// Step 2: group the pairs by column with a bucketed counting sort, in two
+// levels while the buckets (at most kMaxBuckets of 2^low columns, low <= 13)
+// fit one partition, else in three:
 //   k_ov_part_count   per workgroup (one or more chunks of kChunk pairs), a
 //                     bucket histogram (bucket = key >> low), stored
 //                     bucket-major;
 //   scan              -> first output slot of every (bucket, workgroup);
 //   k_ov_part_scatter per chunk, the pairs are ordered by bucket in LDS and
 //                     written out as runs, so that stores coalesce;
+//   (three levels: the first partition makes segments of 2^lowc columns;
+//   the same two kernels in segmented mode then partition every segment
+//   into buckets of 2^12 columns, see PartSeg)
 //   k_ov_bucket_sort  one workgroup per bucket counts its pairs per column in
-//                     LDS (2^low bins, in sweeps of 2^15 for wider buckets),
-//                     scans the counts into the column starts, places each
-//                     (read, position) and writes every column's record
-//                     (its segment, or its two pairs; see kPairTag).
+//                     LDS in staged sweeps of 2^12 columns, scans the counts
+//                     into the column starts, places each (read, position)
+//                     in LDS, writes the sweep out as one run and writes
+//                     every column's record (its segment, or its two pairs;
+//                     see kPairTag).
 // The order inside an A^T row is left free: nothing downstream depends on it.
 // Every pass takes the same chunks, so a malformed A (reported after the
 // first synchronisation) can only over-count: writes are clamped to `cap`.
@@ -335,48 +326,108 @@ constexpr int kPartIlp = 8;
 constexpr int kChunk = kPartBlock * kPartIlp;
 constexpr int kBucketBlock = 1024;
 constexpr int64_t kMaxBuckets = 3840;
-constexpr int kBucketBits = 15;   // LDS histogram of a pass-2 workgroup: 2^15 columns (128 KB)
-constexpr int kMaxLow = 17;       // widest bucket: 4 sweeps of 2^15 columns
+constexpr int kTwoLevelLow = 13;  // two levels: buckets of at most 2^13 columns
 constexpr int kStageBits = 12;    // staged sweeps: 2^12 columns ...
 constexpr int kStageCap = 17408;  // ... and at most this many pairs placed in LDS
+constexpr int kCoarseLow = 20;    // three levels: segments of 2^20 columns (or wider, see the driver)
 
 inline size_t part_scatter_lds(int64_t nbuckets) {
     return (size_t)kChunk * 12 + (size_t)nbuckets * 16;
 }
 
+// Segmented partition (the middle level of the three-level transpose): the
+// input is already grouped by coarse bucket (segment c holds the pairs of
+// columns [c << lowc, (c + 1) << lowc)), and every segment is partitioned on
+// its own into F = 2^(lowc - low) fine buckets.  Segment c is cut into
+// nch_c = chunk_base[c + 1] - chunk_base[c] chunks of kChunk pairs; its count
+// table is fine-bucket-major over its chunks, starting at entry
+// chunk_base[c] * F, so that one exclusive scan over all tables gives every
+// (segment, fine bucket, chunk) its output position directly.
+struct PartSeg {
+    const int64_t* seg_start;    // [nseg + 1] first pair of each segment
+    const int64_t* chunk_base;   // [nseg + 1] first chunk of each segment
+    int32_t nseg;
+};
+
+// Pair range and count-table layout of one chunk.  Flat mode: chunk
+// blockIdx.x * per_block + c over [0, n), table entry of bucket b at
+// b * gridDim.x + blockIdx.x.  Segmented mode (one chunk per workgroup): the
+// workgroup's chunk u within its segment sg, table entry of bucket b at
+// chunk_base[sg] * nbuckets + b * nch_sg + u.  Returns false when the
+// workgroup has no chunk.
+struct ChunkPos {
+    int64_t c0, c1;        // pairs [c0, c1)
+    int64_t tab0, tstride; // table entry of bucket b: tab0 + b * tstride
+};
+template <bool SEG>
+__device__ __forceinline__ bool chunk_pos(int64_t n, int per_block, int c, int nbuckets, const PartSeg& ps,
+                                          ChunkPos* cp) {
+    if (!SEG) {
+        cp->c0 = ((int64_t)blockIdx.x * per_block + c) * kChunk;
+        cp->c1 = min(cp->c0 + kChunk, n);
+        cp->tab0 = blockIdx.x;
+        cp->tstride = gridDim.x;
+        return cp->c0 < n;
+    }
+    const int64_t q = blockIdx.x;
+    if (q >= ps.chunk_base[ps.nseg]) return false;
+    const int sg = find_set(ps.chunk_base, ps.nseg, q);
+    const int64_t cb = ps.chunk_base[sg], nch = ps.chunk_base[sg + 1] - cb;
+    cp->c0 = ps.seg_start[sg] + (q - cb) * kChunk;
+    cp->c1 = min(cp->c0 + kChunk, ps.seg_start[sg + 1]);
+    cp->tab0 = cb * nbuckets + (q - cb);
+    cp->tstride = nch;
+    return true;
+}
+
+// Bucket of a key: flat mode, key >> low clamped into range (keys of a
+// malformed A may be unset); segmented mode, its fine bucket within the
+// segment.
+template <bool SEG>
+__device__ __forceinline__ uint32_t bucket_of(uint32_t key, int low, int nbuckets) {
+    return SEG ? (key >> low) & (uint32_t)(nbuckets - 1) : min(key >> low, (uint32_t)nbuckets - 1u);
+}
+
+template <bool SEG>
 __global__ __launch_bounds__(kPartBlock) void k_ov_part_count(const uint32_t* __restrict__ keys, int64_t n,
                                                               int per_block, int low, int nbuckets,
-                                                              int32_t* __restrict__ counts) {
+                                                              PartSeg ps, int32_t* __restrict__ counts) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
-    const int64_t nblocks = gridDim.x;
+    ChunkPos cp;
+    if (SEG && !chunk_pos<SEG>(n, 1, 0, nbuckets, ps, &cp)) {
+        // surplus workgroups (the grid is sized from a bound) zero the unused
+        // tail of the table, which the scan reads
+        const int64_t q = (int64_t)blockIdx.x - ps.chunk_base[ps.nseg];
+        const int64_t t0 = (ps.chunk_base[ps.nseg] + q) * nbuckets;
+        for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) counts[t0 + b] = 0;
+        return;
+    }
     for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) hist[b] = 0u;
     __syncthreads();
-    for (int c = 0; c < per_block; ++c) {
-        const int64_t c0 = ((int64_t)blockIdx.x * per_block + c) * kChunk;
-        if (c0 >= n) break;
-        const int64_t c1 = min(c0 + kChunk, n);
+    for (int c = 0; c < (SEG ? 1 : per_block); ++c) {
+        if (!chunk_pos<SEG>(n, per_block, c, nbuckets, ps, &cp)) break;
+        const int64_t c0 = cp.c0, c1 = cp.c1;
         uint32_t kk[kPartIlp];
 #pragma unroll
         for (int q = 0; q < kPartIlp; ++q) kk[q] = keys[min(c0 + q * kPartBlock + threadIdx.x, c1 - 1)];
-        // keys of a malformed A may be unset: the bucket is clamped into range
 #pragma unroll
         for (int q = 0; q < kPartIlp; ++q)
-            atomicAdd(&hist[min(kk[q] >> low, (uint32_t)nbuckets - 1u)],
-                      c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+            atomicAdd(&hist[bucket_of<SEG>(kk[q], low, nbuckets)], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock)
-        counts[(int64_t)b * nblocks + blockIdx.x] = (int32_t)hist[b];
+    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) counts[cp.tab0 + (int64_t)b * cp.tstride] = (int32_t)hist[b];
 }
 
-// K: the width of the keys written out; pass 2 reads only their low `low`
-// bits, so the buckets that pass 2 sorts in staged sweeps (at most 2^15
-// columns) take 16-bit keys (half the key bytes of both passes).
-template <class K>
+// K: the width of the keys written out; the next pass reads only their low
+// bits, so where it needs at most 16 of them (buckets of at most 2^15
+// columns sorted in staged sweeps) 16-bit keys halve the key bytes of both
+// passes.  SEG: segmented mode (see PartSeg; one chunk per workgroup, a
+// surplus workgroup does nothing).
+template <bool SEG, class K>
 __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
     const uint32_t* __restrict__ keys, const uint64_t* __restrict__ pays, int64_t n, int per_block, int low,
-    int nbuckets, const int64_t* __restrict__ offsets, int64_t cap, K* __restrict__ skey,
+    int nbuckets, PartSeg ps, const int64_t* __restrict__ offsets, int64_t cap, K* __restrict__ skey,
     uint64_t* __restrict__ spay) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* st_pay = reinterpret_cast<uint64_t*>(smem);                 // [kChunk]
@@ -385,14 +436,14 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
     uint32_t* loff = lcnt + nbuckets;                                     // [nbuckets] chunk-local start
     int64_t* gpos = reinterpret_cast<int64_t*>(loff + nbuckets);          // [nbuckets], 8-byte aligned
     __shared__ uint32_t s_tmp[kPartBlock / kWave + 1];
-    const int64_t nblocks = gridDim.x;
-    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) gpos[b] = offsets[(int64_t)b * nblocks + blockIdx.x];
+    ChunkPos cp;
+    if (!chunk_pos<SEG>(n, per_block, 0, nbuckets, ps, &cp)) return;   // uniform over the workgroup
+    for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) gpos[b] = offsets[cp.tab0 + (int64_t)b * cp.tstride];
     const int per = (nbuckets + kPartBlock - 1) / kPartBlock;
     const int b0 = threadIdx.x * per;
-    for (int c = 0; c < per_block; ++c) {
-        const int64_t c0 = ((int64_t)blockIdx.x * per_block + c) * kChunk;
-        if (c0 >= n) break;
-        const int64_t c1 = min(c0 + kChunk, n);
+    for (int c = 0; c < (SEG ? 1 : per_block); ++c) {
+        if (c > 0 && !chunk_pos<SEG>(n, per_block, c, nbuckets, ps, &cp)) break;
+        const int64_t c0 = cp.c0, c1 = cp.c1;
         for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) lcnt[b] = 0u;
         __syncthreads();
         uint32_t kk[kPartIlp], rk[kPartIlp];
@@ -400,14 +451,15 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
 #pragma unroll
         for (int q = 0; q < kPartIlp; ++q) {
             const int64_t e = min(c0 + q * kPartBlock + threadIdx.x, c1 - 1);
-            // keys of a malformed A may be unset: the bucket is clamped into range
-            kk[q] = min(keys[e], ((uint32_t)nbuckets << low) - 1u);
+            // flat mode: keys of a malformed A may be unset, the bucket is clamped into range
+            kk[q] = SEG ? keys[e] : min(keys[e], ((uint32_t)nbuckets << low) - 1u);
             pp[q] = pays[e];
         }
         // rank of each pair among the chunk's pairs of its bucket
 #pragma unroll
         for (int q = 0; q < kPartIlp; ++q)
-            rk[q] = atomicAdd(&lcnt[kk[q] >> low], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+            rk[q] = atomicAdd(&lcnt[bucket_of<SEG>(kk[q], low, nbuckets)],
+                              c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
         __syncthreads();
         // chunk-local bucket starts: each thread scans a run of consecutive buckets
         uint32_t local = 0;
@@ -424,7 +476,7 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
 #pragma unroll
         for (int q = 0; q < kPartIlp; ++q) {
             if (c0 + q * kPartBlock + threadIdx.x >= c1) continue;
-            const uint32_t slot = loff[kk[q] >> low] + rk[q];
+            const uint32_t slot = loff[bucket_of<SEG>(kk[q], low, nbuckets)] + rk[q];
             st_key[slot] = kk[q];
             st_pay[slot] = pp[q];
         }
@@ -432,7 +484,7 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
         // consecutive slots of one bucket go to consecutive output positions
         for (uint32_t slot = threadIdx.x; slot < tot; slot += kPartBlock) {
             const uint32_t key = st_key[slot];
-            const int b = (int)(key >> low);
+            const int b = (int)bucket_of<SEG>(key, low, nbuckets);
             const int64_t pos = gpos[b] + (slot - loff[b]);
             if (pos < cap) {
                 skey[pos] = (K)key;
@@ -445,29 +497,65 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_scatter(
     }
 }
 
-// STAGE: each sweep's pairs are placed in LDS first and written out as one
-// contiguous run (coalesced) when they fit kStageCap; sweeps of 2^sub columns.
-// Only a staged sweep writes the two-pair records (otherwise every column
-// gets its segment).
-template <bool SWEEPS, bool STAGE, class K>
+// Three-level transpose, between the levels: the segments (coarse buckets)
+// from the first level's scanned table and their chunk counts, scanned into
+// chunk_base (one workgroup).
+constexpr int kSegChunkBlock = 1024;
+__global__ __launch_bounds__(kSegChunkBlock) void k_ov_seg_chunks(const int64_t* __restrict__ offs1, int64_t npart1,
+                                                                  int nseg, int64_t cap,
+                                                                  int64_t* __restrict__ seg_start,
+                                                                  int64_t* __restrict__ chunk_base) {
+    __shared__ int64_t s_tmp[kSegChunkBlock / kWave + 1];
+    int64_t carry = 0;
+    for (int c0 = 0; c0 <= nseg; c0 += kSegChunkBlock) {
+        const int c = c0 + (int)threadIdx.x;
+        int64_t st = 0, nch = 0;
+        if (c <= nseg) {
+            st = min(offs1[(int64_t)c * npart1], cap);
+            seg_start[c] = st;
+            if (c < nseg) nch = (min(offs1[(int64_t)(c + 1) * npart1], cap) - st + kChunk - 1) / kChunk;
+        }
+        int64_t tot;
+        const int64_t ex = block_exclusive_sum<kSegChunkBlock>(nch, s_tmp, &tot);
+        if (c <= nseg) chunk_base[c] = carry + ex;
+        carry += tot;
+    }
+}
+
+// Start of every fine bucket b = sg * F + f (its first chunk's table entry
+// in the scanned second-level table), and the end of the last one.
+__global__ void k_ov_fine_start(const int64_t* __restrict__ offs2, const int64_t* __restrict__ chunk_base, int nseg,
+                                int F, int64_t nfine, int64_t* __restrict__ fine_start) {
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b <= nfine; b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sg = b / F, f = b % F;
+        int64_t e;
+        if (sg >= nseg) e = chunk_base[nseg] * F;
+        else e = chunk_base[sg] * F + f * (chunk_base[sg + 1] - chunk_base[sg]);
+        fine_start[b] = offs2[e];
+    }
+}
+
+// One workgroup per bucket of 2^low columns (first pair at
+// start[b * stride], 16-bit keys holding at least the low `low` bits), sorted
+// in sweeps of 2^sub columns (sub = min(low, 12)): per sweep the pairs of its
+// columns are counted, placed in LDS and written out as one contiguous run
+// (coalesced) when they fit kStageCap, else placed directly.  Only a staged
+// sweep writes the two-pair records (otherwise every column gets its
+// segment).
 __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
-    const int64_t* __restrict__ offsets, int64_t nchunks, int low, int sub_bits, int64_t total_m, int64_t cap,
-    const K* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ rec,
+    const int64_t* __restrict__ start, int64_t stride, int low, int sub, int64_t total_m, int64_t cap,
+    const uint16_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ rec,
     uint64_t* __restrict__ at) {
-    // offsets: bucket-major over the partition's workgroups (nchunks of them)
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
-    uint64_t* stage = reinterpret_cast<uint64_t*>(hist + (STAGE ? (1 << sub_bits) : 0));
+    uint64_t* stage = reinterpret_cast<uint64_t*>(hist + (1 << sub));
     __shared__ int64_t s_tmp[kBucketBlock / kWave + 1];
     const int b = blockIdx.x;
-    // a bucket wider than the LDS histogram (2^sub_bits bins) is sorted in
-    // sweeps over its pairs, one range of 2^sub_bits columns each
-    const int sub = SWEEPS ? sub_bits : low;
-    const int sweeps = SWEEPS ? 1 << (low - sub) : 1;
+    const int sweeps = 1 << (low - sub);
     const int bins = 1 << sub;
     const uint32_t lmask = (uint32_t)(1u << low) - 1u, smask = (uint32_t)bins - 1u;
-    const int64_t bs = min(offsets[(int64_t)b * nchunks], cap);
-    const int64_t be = min(offsets[(int64_t)(b + 1) * nchunks], cap);
+    const int64_t bs = min(start[(int64_t)b * stride], cap);
+    const int64_t be = min(start[(int64_t)(b + 1) * stride], cap);
     const int64_t col_b = (int64_t)b << low;
     const int per = bins >= kBucketBlock ? bins / kBucketBlock : 1;
     const int c0 = threadIdx.x * per;
@@ -483,8 +571,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
 #pragma unroll
             for (int q = 0; q < kPartIlp; ++q)
                 atomicAdd(&hist[kk[q] & smask],
-                          (e0 + q * kBucketBlock + threadIdx.x < be && (!SWEEPS || (int)(kk[q] >> sub) == h))
-                              ? 1u : 0u);
+                          (e0 + q * kBucketBlock + threadIdx.x < be && (int)(kk[q] >> sub) == h) ? 1u : 0u);
         }
         __syncthreads();
         // exclusive scan of the bins: each thread owns `per` consecutive bins
@@ -498,11 +585,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
             const int c = c0 + q;
             if (c >= bins) break;
             const uint32_t n_c = hist[c];
-            const int64_t start = base + run;
-            hist[c] = (uint32_t)start;   // becomes the cursor of column c
+            hist[c] = (uint32_t)(base + run);   // becomes the cursor of column c (< 2^32)
             run += n_c;
         }
-        const bool staged = STAGE && tot <= kStageCap;
+        const bool staged = tot <= kStageCap;
         __syncthreads();
         for (int64_t e0 = bs; e0 < be; e0 += kBucketBlock * kPartIlp) {
             uint32_t kk[kPartIlp], pos[kPartIlp];
@@ -511,12 +597,12 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
             for (int q = 0; q < kPartIlp; ++q) {
                 const int64_t e = min(e0 + q * kBucketBlock + threadIdx.x, be - 1);   // clamped: no branch
                 kk[q] = skey[e] & lmask;
-                pp[q] = !SWEEPS || (int)(kk[q] >> sub) == h ? spay[e] : 0ull;
+                pp[q] = (int)(kk[q] >> sub) == h ? spay[e] : 0ull;
             }
             bool mine[kPartIlp];
 #pragma unroll
             for (int q = 0; q < kPartIlp; ++q) {
-                mine[q] = e0 + q * kBucketBlock + threadIdx.x < be && (!SWEEPS || (int)(kk[q] >> sub) == h);
+                mine[q] = e0 + q * kBucketBlock + threadIdx.x < be && (int)(kk[q] >> sub) == h;
                 pos[q] = atomicAdd(&hist[kk[q] & smask], mine[q] ? 1u : 0u);
             }
 #pragma unroll
@@ -537,11 +623,11 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
             const int c = c0 + q;
             if (c >= bins || col0 + c >= total_m) break;
             const uint32_t end = hist[c];
-            const uint32_t start = c ? hist[c - 1] : (uint32_t)base;
-            const uint32_t n_c = end - start;
-            uint64_t r = ((uint64_t)start << 24) | (uint64_t)n_c;
+            const uint32_t first = c ? hist[c - 1] : (uint32_t)base;
+            const uint32_t n_c = end - first;
+            uint64_t r = ((uint64_t)first << 24) | (uint64_t)n_c;
             if (staged && n_c == 2) {
-                const uint64_t x = stage[start - base] ^ stage[start - base + 1];   // pairs: (pos << 32) | read
+                const uint64_t x = stage[first - base] ^ stage[first - base + 1];   // pairs: (pos << 32) | read
                 r = kPairTag | ((x >> 32) << 24) | (x & 0xFFFFFFull);
             }
             rec[col0 + c] = r;
@@ -569,14 +655,19 @@ constexpr int kSegIlp = 8;
 // (workgroup b runs on XCD b mod 8), so workgroup b takes slice
 // 8 * round + (b mod 8): at any time each XCD gathers column records from
 // one slice only (at most 4 MB), which its L2 then holds, instead of every
-// XCD gathering from all of them.  A workgroup covers kSliceRows
-// rows: each wave takes its share of the rows, kSliceIlp at a time, one
-// lane per entry of a row's sub-range.  Products per (slice, row) go to
-// part[slice * rows + row]; k_ov_scatter sums them.
+// XCD gathering from all of them.  A workgroup covers the sub-ranges of
+// kSliceRows rows in its slice; those are short (a row spreads its entries
+// over all slices), so the workgroup numbers their entries consecutively
+// (a scan of the 64 lengths) and every thread takes entries by number,
+// kSliceIlp at a time, finding the row with a search over the 64 starts:
+// consecutive threads read consecutive columns and write consecutive
+// segment words.  Products per (slice, row) go to part[slice * rows + row]
+// (32 bits, saturated at 2^31: a row that large fails the call anyway);
+// k_ov_scatter sums them.
 constexpr int kSliceRows = 64;
 constexpr int kSliceBlock = 256;
-constexpr int kSliceIlp = 8;
-constexpr int kMaxSlices = 64;
+constexpr int kSliceIlp = 4;
+constexpr int kMaxSlices = 8192;                   // 2^32 columns at kSliceCols each
 constexpr int64_t kSliceCols = int64_t(1) << 19;   // 4 MB of column records: one L2
 // a readable word for the loads of rows with no entries in a slice (their
 // values are never used)
@@ -585,23 +676,26 @@ __device__ const int32_t kSliceNone[1] = {0};
 __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
     int64_t groups, SliceMap sm, const int32_t* __restrict__ bnd, const uint64_t* __restrict__ rec,
-    uint64_t* __restrict__ seg, int64_t* __restrict__ part) {
-    __shared__ int32_t s_len[kSliceRows];
+    uint64_t* __restrict__ seg, uint32_t* __restrict__ part) {
+    __shared__ int32_t s_pre[kSliceRows + 1];      // first flat number of each row's sub-range
     __shared__ int64_t s_first[kSliceRows];        // global entry of the row's first entry in the slice
     __shared__ const int32_t* s_col[kSliceRows];   // its column
     __shared__ int64_t s_cb[kSliceRows], s_m[kSliceRows];
+    __shared__ unsigned long long s_prod[kSliceRows];
+    __shared__ int32_t s_tmp[kSliceBlock / kWave + 1];
     const int64_t b = blockIdx.x;
     const int sl = (int)((b / 8) / groups) * 8 + (int)(b % 8);
     const int64_t row0 = ((b / 8) % groups) * kSliceRows;
     if (sl >= sm.count) return;   // uniform over the workgroup
+    int32_t len = 0;
     if (threadIdx.x < kSliceRows) {
         const int r = threadIdx.x;
         const int64_t g = row0 + r;
-        s_len[r] = 0;
         s_first[r] = 0;
         s_col[r] = kSliceNone;
         s_cb[r] = 0;
         s_m[r] = 0;
+        s_prod[r] = 0;
         if (g < total_rows) {
             const int s = find_set(set_base, nsets, g);
             const OvSet& S = sets[s];
@@ -609,10 +703,9 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
             const int64_t lo = S.a_rowptr[i], hi = S.a_rowptr[i + 1];
             if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
                 const int32_t L = (int32_t)(hi - lo);
-                const int32_t* rb = bnd + g * (sm.count + 1);
-                const int32_t a = min(max(rb[sl], 0), L);
-                const int32_t z = min(max(rb[sl + 1], a), L);
-                s_len[r] = z - a;
+                const int32_t a = min(max(bnd[(int64_t)sl * total_rows + g], 0), L);
+                const int32_t z = min(max(bnd[(int64_t)(sl + 1) * total_rows + g], a), L);
+                len = z - a;
                 s_first[r] = S.nnz_base + lo + a;
                 if (z > a) s_col[r] = S.a_col + lo + a;
                 s_cb[r] = S.col_base;
@@ -620,55 +713,43 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
             }
         }
     }
+    // sub-range lengths are below 2^30 each and the call's entries below
+    // 2^31, so the workgroup's numbering fits 32 bits
+    int32_t tot;
+    const int32_t ex = block_exclusive_sum<kSliceBlock>(len, s_tmp, &tot);
+    if (threadIdx.x < kSliceRows) s_pre[threadIdx.x] = ex;
     __syncthreads();
-    // each wave takes kSliceRows / waves rows, kSliceIlp of them at a time;
-    // the lanes take consecutive entries of a row (coalesced column loads
-    // and segment stores)
-    constexpr int W = kSliceBlock / kWave, RPW = kSliceRows / W;
-    static_assert(RPW % kSliceIlp == 0, "rows per wave");
-    const int lane = lane_id();
-    const int w = __builtin_amdgcn_readfirstlane(wave_id());
-    for (int j0 = 0; j0 < RPW; j0 += kSliceIlp) {
-        int len[kSliceIlp], most = 0;
+    for (int32_t q0 = threadIdx.x; q0 < tot; q0 += kSliceBlock * kSliceIlp) {
+        // unconditional loads from clamped addresses: no load waits on another
+        int rr[kSliceIlp];
+        int32_t oo[kSliceIlp], kk[kSliceIlp];
 #pragma unroll
         for (int u = 0; u < kSliceIlp; ++u) {
-            len[u] = s_len[w * RPW + j0 + u];
-            most = max(most, len[u]);
+            const int32_t q = min(q0 + u * kSliceBlock, tot - 1);
+            rr[u] = upper_index(s_pre, kSliceRows, q);   // the last row starting at or before q: non-empty
+            oo[u] = q - s_pre[rr[u]];
+            kk[u] = gload_nt(s_col[rr[u]] + oo[u]);
         }
-        // products per (slice, row) in 32 bits, saturating at 2^31: a row
-        // that large then still fails the product check of the call
-        uint32_t fl[kSliceIlp];
+        uint64_t rc[kSliceIlp];
 #pragma unroll
-        for (int u = 0; u < kSliceIlp; ++u) fl[u] = 0;
-        for (int o = lane; o - lane < most; o += kWave) {
-            // unconditional loads from clamped addresses: no load waits on another
-            int32_t kk[kSliceIlp];
-#pragma unroll
-            for (int u = 0; u < kSliceIlp; ++u)
-                kk[u] = gload_nt(s_col[w * RPW + j0 + u] + min(o, max(len[u] - 1, 0)));
-            uint64_t rc[kSliceIlp];
-#pragma unroll
-            for (int u = 0; u < kSliceIlp; ++u) {
-                const int r = w * RPW + j0 + u;
-                const bool ok = kk[u] >= 0 && kk[u] < s_m[r];
-                rc[u] = gload(rec + (ok ? s_cb[r] + kk[u] : 0));
-            }
-#pragma unroll
-            for (int u = 0; u < kSliceIlp; ++u) {
-                if (o >= len[u]) continue;
-                const int r = w * RPW + j0 + u;
-                const bool ok = kk[u] >= 0 && kk[u] < s_m[r];
-                const uint64_t sg = ok ? rc[u] : 0ull;   // invalid column: empty segment
-                fl[u] = min(fl[u] + (uint32_t)rec_products(sg), 1u << 31);   // fl <= 2^31, products < 2^24: no wrap
-                seg[s_first[r] + o] = sg;   // ordinary store: L2 merges the lines
-            }
+        for (int u = 0; u < kSliceIlp; ++u) {
+            const bool ok = kk[u] >= 0 && kk[u] < s_m[rr[u]];
+            rc[u] = gload(rec + (ok ? s_cb[rr[u]] + kk[u] : 0));
         }
 #pragma unroll
         for (int u = 0; u < kSliceIlp; ++u) {
-            const int64_t t = wave_sum((int64_t)fl[u]);
-            const int64_t g = row0 + w * RPW + j0 + u;
-            if (lane == 0 && g < total_rows) part[(int64_t)sl * total_rows + g] = t;
+            if (q0 + u * kSliceBlock >= tot) continue;
+            const bool ok = kk[u] >= 0 && kk[u] < s_m[rr[u]];
+            const uint64_t sg = ok ? rc[u] : 0ull;   // invalid column: empty segment
+            atomicAdd(&s_prod[rr[u]], (unsigned long long)rec_products(sg));
+            seg[s_first[rr[u]] + oo[u]] = sg;   // ordinary store: L2 merges the lines
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < kSliceRows) {
+        const int64_t g = row0 + threadIdx.x;
+        const unsigned long long p = s_prod[threadIdx.x];
+        if (g < total_rows) part[(int64_t)sl * total_rows + g] = (uint32_t)(p < (1ull << 31) ? p : (1ull << 31));
     }
 }
 
@@ -677,7 +758,7 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
     const uint64_t* __restrict__ rec, uint64_t* __restrict__ seg, int64_t* __restrict__ flops_row,
     int64_t* __restrict__ sbound, int32_t* __restrict__ sym_list,
-    OvCounters* __restrict__ ctr, int first_log2, int load_pct, const int64_t* __restrict__ part, int nslices) {
+    OvCounters* __restrict__ ctr, int first_log2, int load_pct, const uint32_t* __restrict__ part, int nslices) {
     __shared__ int32_t s_cnt[kMaxLog2], s_base[kMaxLog2];
     __shared__ int32_t s_bin[kRowsPerBlock], s_pos[kRowsPerBlock];
     __shared__ unsigned long long s_prod;
@@ -705,7 +786,7 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
         int64_t fl = 0;
         if (part) {
             // the segments are written by the sliced pass: sum its partial products
-            if (lane < nslices) fl = part[(int64_t)lane * total_rows + g];
+            for (int q = lane; q < nslices; q += kWave) fl += part[(int64_t)q * total_rows + g];
         } else if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
             for (int64_t e0 = lo; e0 < hi; e0 += (int64_t)kWave * kSegIlp) {
                 int32_t kk[kSegIlp];
@@ -1819,34 +1900,50 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         return DIBELLA_EINVAL;
     }
 
+    // ---- transpose plan.  Two levels (partition the pairs into buckets of
+    // 2^low columns, then a staged counting sort per bucket) while the
+    // buckets fit one partition; three levels beyond that (partition into
+    // segments of 2^lowc columns, partition every segment into buckets of
+    // 2^12 columns, staged sort per bucket), so that every bucket is sorted
+    // in staged sweeps with 16-bit keys and its two-pair columns carry
+    // their pairs.
     const int col_bits = ceil_log2_i64(std::max<int64_t>(total_m, 2));
-    // buckets of at most 2^13 columns: pass 2 then sorts each in two staged
-    // sweeps (2^14 took four sweeps, each re-reading the bucket's keys, and
-    // left a half-empty last round of workgroups on mid)
-    int low = std::min(13, std::max(10, col_bits - 8));
-    // wider buckets when the count would not fit the partition's LDS (pass 2
-    // sorts buckets wider than 2^15 columns in sweeps)
-    while (low < kMaxLow && ceil_div(total_m, int64_t(1) << low) > kMaxBuckets) ++low;
-    const int64_t nbuckets = ceil_div(total_m, int64_t(1) << low);
+    // buckets of at most 2^13 columns: the last level then sorts each in two
+    // staged sweeps (2^14 took four sweeps, each re-reading the bucket's
+    // keys, and left a half-empty last round of workgroups on mid)
+    int low = std::min(kTwoLevelLow, std::max(10, col_bits - 8));
+    const bool three = ceil_div(total_m, int64_t(1) << kTwoLevelLow) > kMaxBuckets;
+    int lowc = kCoarseLow;
+    if (three) {
+        low = kStageBits;
+        while (ceil_div(total_m, int64_t(1) << lowc) > kMaxBuckets) ++lowc;
+    }
+    const int fine_per = three ? 1 << (lowc - low) : 0;                               // buckets per segment
+    const int64_t nbuckets = ceil_div(total_m, int64_t(1) << (three ? lowc : low));   // first level
+    const int64_t nsort = ceil_div(total_m, int64_t(1) << low);                       // sorted by the last level
     const int64_t nchunks = ceil_div(total_nnz, kChunk);
-    // bucketed path: bucket cursors fit beside the staging in LDS and entries
-    // index in 31 bits.  A partition workgroup takes several chunks when
-    // that keeps the (bucket, workgroup) count table small beside A.
-    const bool bucketed = nbuckets <= kMaxBuckets && total_nnz < (int64_t(1) << 31);
+    // A first-level workgroup takes several chunks when that keeps the
+    // (bucket, workgroup) count table small beside A.
     int per_block = 1;
     while (nbuckets * ceil_div(nchunks, per_block) > std::max<int64_t>(int64_t(1) << 22, total_nnz / 8))
         per_block *= 2;
-    const int64_t npart = ceil_div(nchunks, per_block);   // partition workgroups
+    const int64_t npart = ceil_div(nchunks, per_block);   // first-level workgroups
+    // second level: one chunk per workgroup, segments cut separately (at
+    // most one partial chunk per segment)
+    const int64_t nchunks2 = three ? nchunks + nbuckets : 0;
+    const int64_t ncount2 = nchunks2 * fine_per;
     // column slices for the segment pass: 8 per round, each at most
-    // kSliceCols columns wide; only where the row pointers outgrow an L2
+    // kSliceCols columns wide; only where the column records outgrow an L2
+    // and the slice tables ((2S + 1) int32 per row) stay within
+    // max(4 nnz, 2^24) entries
     SliceMap sm{0, 0u};
     {
-        const int64_t rounds = ceil_div(total_m, 8 * kSliceCols);
+        const int64_t S = ceil_div(total_m, 8 * kSliceCols) * 8;
         // (total_nnz < 2^31 keeps a workgroup's flat entry numbers in 32 bits)
         if (total_rows > 0 && total_nnz > 0 && total_nnz < (int64_t(1) << 31) && total_m >= 4 * kSliceCols &&
-            rounds * 8 <= kMaxSlices) {
-            sm.count = (int32_t)(rounds * 8);
-            sm.mul = (uint32_t)(((uint64_t)sm.count << 32) / (uint64_t)total_m);
+            S <= kMaxSlices && (2 * S + 1) * total_rows <= std::max<int64_t>(4 * total_nnz, int64_t(1) << 24)) {
+            sm.count = (int32_t)S;
+            sm.mul = (uint32_t)(((uint64_t)S << 32) / (uint64_t)total_m);
         }
     }
     const int64_t slice_groups = ceil_div(total_rows, kSliceRows);
@@ -1856,13 +1953,16 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         const size_t P = Arena::padded(1);
         auto pad = [](size_t b) { return Arena::padded(b); };
         size_t est = pad(sizeof(OvSet) * nsets) + 2 * pad(8 * (nsets + 1)) + pad(4 * nsets) + pad(sizeof(OvCounters));
-        est += pad(8 * std::max<int64_t>(total_m, 1)) + (bucketed ? 0 : pad(4 * (total_m + 1)));
+        est += pad(8 * std::max<int64_t>(total_m, 1));
         est += 2 * pad(4 * total_nnz) + 3 * pad(8 * total_nnz);
         est += 7 * pad(8 * (total_rows + 1)) + 3 * pad(4 * total_rows);
         est += pad(4 * total_rows * kMaxLog2) + pad(4 * total_rows * kMaxBins);
         est += pad(4 * nbuckets * npart) + pad(8 * (nbuckets * npart + 1));
-        if (sm.count) est += pad(4 * total_rows * (sm.count + 1)) + pad(8 * total_rows * sm.count);
-        est += 4 * pad(8 * scan_workspace_elems(std::max<int64_t>(total_rows, nbuckets * npart))) + 16 * P;
+        if (three)
+            est += pad(4 * ncount2) + pad(8 * (ncount2 + 1)) + 2 * pad(8 * (nbuckets + 1)) +
+                   pad(8 * (nbuckets * fine_per + 1));
+        if (sm.count) est += pad(4 * total_rows * (sm.count + 1)) + pad(4 * total_rows * sm.count);
+        est += 4 * pad(8 * scan_workspace_elems(std::max({total_rows, nbuckets * npart, ncount2}))) + 16 * P;
         DB_TRY(ar.reserve(est));
     }
     // ---- workspace
@@ -1900,7 +2000,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(ar.work_n(total_rows, &esc_list));
     DB_TRY(ar.work_n(total_rows, &retry_list));
     int32_t* bnd = nullptr;
-    int64_t* part = nullptr;
+    uint32_t* part = nullptr;
     if (sm.count) {
         DB_TRY(ar.work_n((size_t)total_rows * (sm.count + 1), &bnd));
         DB_TRY(ar.work_n((size_t)total_rows * sm.count, &part));
@@ -1928,7 +2028,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
     // empty segments where no pass writes them (the bucket sort writes every column of a non-empty A)
-    if (bucketed && total_nnz == 0) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(rec), 0, 2 * std::max<int64_t>(total_m, 1), st));
+    if (total_nnz == 0) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(rec), 0, 2 * std::max<int64_t>(total_m, 1), st));
     else DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
     if (total_rows > 0) {
         DB_TRY(timing_begin(kPhKeys, st, &tok));
@@ -1938,78 +2038,91 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         DB_TRY(timing_end(tok, st));
     }
     const int2* at = nullptr;
-    if (bucketed && total_nnz > 0) {
+    if (total_nnz > 0) {
+        static std::atomic<bool> lds_ok{false};
+        if (!lds_ok.load(std::memory_order_acquire)) {
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<false, uint16_t>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<false, uint32_t>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<true, uint16_t>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+            lds_ok.store(true, std::memory_order_release);
+        }
+        const PartSeg flat{nullptr, nullptr, 0};
         int32_t* pcounts;
         int64_t* poffs;
         const int64_t ncount = nbuckets * npart;
         DB_TRY(ar.work_n(ncount, &pcounts));
         DB_TRY(ar.work_n(ncount + 1, &poffs));
+        const int low1 = three ? lowc : low;
         DB_TRY(timing_begin(kPhPartCount, st, &tok));
-        hipLaunchKernelGGL(k_ov_part_count, dim3((unsigned)npart), dim3(kPartBlock), (size_t)nbuckets * 4, st,
-                           keys_a, total_nnz, per_block, low, (int)nbuckets, pcounts);
+        hipLaunchKernelGGL(k_ov_part_count<false>, dim3((unsigned)npart), dim3(kPartBlock), (size_t)nbuckets * 4, st,
+                           keys_a, total_nnz, per_block, low1, (int)nbuckets, flat, pcounts);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, ar));
-        static std::atomic<bool> lds_ok{false};
-        if (!lds_ok.load(std::memory_order_acquire)) {
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<uint16_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<uint32_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, false, uint32_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort<true, true, uint16_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            lds_ok.store(true, std::memory_order_release);
-        }
-        // buckets of at most 2^15 columns: 16-bit keys between the passes
-        const bool narrow = low <= kBucketBits;
+        uint16_t* keys_a16 = reinterpret_cast<uint16_t*>(keys_a);
         uint16_t* keys_b16 = reinterpret_cast<uint16_t*>(keys_b);
         DB_TRY(timing_begin(kPhPartScatter, st, &tok));
-        if (narrow)
-            hipLaunchKernelGGL(k_ov_part_scatter<uint16_t>, dim3((unsigned)npart), dim3(kPartBlock),
-                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low,
-                               (int)nbuckets, poffs, total_nnz, keys_b16, pays_b);
-        else
-            hipLaunchKernelGGL(k_ov_part_scatter<uint32_t>, dim3((unsigned)npart), dim3(kPartBlock),
-                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low,
-                               (int)nbuckets, poffs, total_nnz, keys_b, pays_b);
+        if (!three)   // the last level reads the low `low` <= 13 bits: 16-bit keys
+            hipLaunchKernelGGL((k_ov_part_scatter<false, uint16_t>), dim3((unsigned)npart), dim3(kPartBlock),
+                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low1,
+                               (int)nbuckets, flat, poffs, total_nnz, keys_b16, pays_b);
+        else          // the second level needs lowc bits
+            hipLaunchKernelGGL((k_ov_part_scatter<false, uint32_t>), dim3((unsigned)npart), dim3(kPartBlock),
+                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low1,
+                               (int)nbuckets, flat, poffs, total_nnz, keys_b, pays_b);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
-        // A^T pairs land in pays_a, free once the partition has read it
-        DB_TRY(timing_begin(kPhBucketSort, st, &tok));
-        if (!narrow)
-            hipLaunchKernelGGL((k_ov_bucket_sort<true, false, uint32_t>), dim3((unsigned)nbuckets),
-                               dim3(kBucketBlock), (size_t)4 << kBucketBits, st, poffs, npart, low, kBucketBits,
-                               total_m, total_nnz, keys_b, pays_b, rec, pays_a);
-        else   // staged sweeps of 2^12 columns (one sweep for narrower buckets)
-            hipLaunchKernelGGL((k_ov_bucket_sort<true, true, uint16_t>), dim3((unsigned)nbuckets),
-                               dim3(kBucketBlock), ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, poffs,
-                               npart, low, std::min(low, kStageBits), total_m, total_nnz, keys_b16, pays_b, rec,
-                               pays_a);
-        DB_HIP(hipGetLastError());
-        DB_TRY(timing_end(tok, st));
-        at = reinterpret_cast<const int2*>(pays_a);
-    } else if (!bucketed) {
-        // very many columns: LSD radix sort of the pairs by column
-        int in_b = 0;
-        DB_TRY(radix_sort_pairs(keys_a, pays_a, keys_b, pays_b, total_nnz, col_bits, &in_b, ar));
-        const uint32_t* tkeys = in_b ? keys_b : keys_a;
-        at = reinterpret_cast<const int2*>(in_b ? pays_b : pays_a);
-        if (total_nnz > 0) {
-            uint32_t* t_rowptr;
-            DB_TRY(ar.work_n(total_m + 1, &t_rowptr));
-            DB_TRY(timing_begin(kPhBucketSort, st, &tok));
-            hipLaunchKernelGGL(k_ov_trowptr, dim3(grid_for(total_nnz, 256, 1 << 16)), dim3(256), 0, st, tkeys,
-                               total_nnz, total_m, t_rowptr);
+        const int64_t* sort_start = poffs;   // first pair of bucket b: sort_start[b * sort_stride]
+        int64_t sort_stride = npart;
+        const uint16_t* sort_keys = keys_b16;
+        const uint64_t* sort_pays = pays_b;
+        uint64_t* at_out = pays_a;           // A^T goes where the sort's input is not
+        if (three) {
+            int64_t *seg_start, *chunk_base, *fine_start, *poffs2;
+            int32_t* pcounts2;
+            DB_TRY(ar.work_n(nbuckets + 1, &seg_start));
+            DB_TRY(ar.work_n(nbuckets + 1, &chunk_base));
+            DB_TRY(ar.work_n(nbuckets * fine_per + 1, &fine_start));
+            DB_TRY(ar.work_n(ncount2, &pcounts2));
+            DB_TRY(ar.work_n(ncount2 + 1, &poffs2));
+            hipLaunchKernelGGL(k_ov_seg_chunks, dim3(1), dim3(kSegChunkBlock), 0, st, poffs, npart, (int)nbuckets,
+                               total_nnz, seg_start, chunk_base);
             DB_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_ov_rec_from_rowptr, dim3(grid_for(total_m, 256, 1 << 16)), dim3(256), 0, st,
-                               t_rowptr, total_m, rec);
+            const PartSeg ps{seg_start, chunk_base, (int32_t)nbuckets};
+            DB_TRY(timing_begin(kPhPart2Count, st, &tok));
+            hipLaunchKernelGGL(k_ov_part_count<true>, dim3((unsigned)nchunks2), dim3(kPartBlock),
+                               (size_t)fine_per * 4, st, keys_b, total_nnz, 1, low, fine_per, ps, pcounts2);
             DB_HIP(hipGetLastError());
             DB_TRY(timing_end(tok, st));
-        } else {
-            DB_TRY(fill_i32(reinterpret_cast<int32_t*>(rec), 0, 2 * std::max<int64_t>(total_m, 1), st));
+            DB_TRY(scan_exclusive(pcounts2, poffs2, ncount2, nullptr, ar));
+            DB_TRY(timing_begin(kPhPart2Scatter, st, &tok));
+            hipLaunchKernelGGL((k_ov_part_scatter<true, uint16_t>), dim3((unsigned)nchunks2), dim3(kPartBlock),
+                               part_scatter_lds(fine_per), st, keys_b, pays_b, total_nnz, 1, low, fine_per, ps,
+                               poffs2, total_nnz, keys_a16, pays_a);
+            DB_HIP(hipGetLastError());
+            DB_TRY(timing_end(tok, st));
+            hipLaunchKernelGGL(k_ov_fine_start, dim3(grid_for(nbuckets * fine_per + 1, 256, 4096)), dim3(256), 0, st,
+                               poffs2, chunk_base, (int)nbuckets, fine_per, nbuckets * fine_per, fine_start);
+            DB_HIP(hipGetLastError());
+            sort_start = fine_start;
+            sort_stride = 1;
+            sort_keys = keys_a16;
+            sort_pays = pays_a;
+            at_out = pays_b;
         }
+        // staged sweeps of 2^12 columns (one sweep for buckets of at most that)
+        DB_TRY(timing_begin(kPhBucketSort, st, &tok));
+        hipLaunchKernelGGL((k_ov_bucket_sort), dim3((unsigned)nsort), dim3(kBucketBlock),
+                           ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, sort_start, sort_stride, low,
+                           std::min(low, kStageBits), total_m, total_nnz, sort_keys, sort_pays, rec, at_out);
+        DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
+        at = reinterpret_cast<const int2*>(at_out);
     }
     if (total_rows > 0) {
         DB_TRY(timing_begin(kPhSegments, st, &tok));

@@ -92,12 +92,14 @@ def test_overlap_random(lib, seed, n, m, density, ms, bits):
     assert_overlap_equal(C, oracle.overlap(A, ms), f"random{seed}")
 
 
-@pytest.mark.parametrize("m", [pytest.param((1 << 27) + 17, id="two-sweep-buckets"),
-                               pytest.param(3840 * (1 << 17) + 5, id="radix")])
+@pytest.mark.parametrize("m", [pytest.param(3840 * (1 << 13), id="two-level-widest"),
+                               pytest.param(3840 * (1 << 13) + 1, id="three-level-narrowest"),
+                               pytest.param((1 << 27) + 17, id="three-level-129-segments"),
+                               pytest.param(3840 * (1 << 17) + 5, id="three-level-480-segments")])
 def test_overlap_very_wide_transpose(lib, m):
-    """Very wide A: 2^27 + 17 columns give pass-2 buckets of 2^16 columns
-    sorted in two sweeps; just over 3840 * 2^17 columns the transpose takes
-    the radix sort."""
+    """Very wide A: up to 3840 buckets of 2^13 columns the transpose takes two
+    levels; one column more and it partitions into segments of 2^20 columns
+    first, then every segment into buckets of 2^12 columns (three levels)."""
     rng = np.random.default_rng(21)
     n = 400
     rows, cols = [], []
@@ -166,14 +168,24 @@ def _sliced_a(rng, n, m):
 
 @pytest.mark.parametrize("m", [pytest.param((1 << 21) - 1, id="unsliced-narrow"), pytest.param(1 << 21, id="8-slices"),
                                pytest.param(5 * (1 << 21) + 3, id="24-slices"), pytest.param(1 << 25, id="64-slices"),
-                               pytest.param((1 << 25) + 1, id="unsliced-wide")])
+                               pytest.param((1 << 25) + 1, id="72-slices"), pytest.param((1 << 26) + 5, id="136-slices")])
 def test_overlap_sliced_segments(lib, m):
-    """2^21 .. 2^25 columns: the segment pass runs per column slice (8 to 64
-    slices of at most 2^19 columns); one column fewer or more and it runs per
-    row."""
+    """From 2^21 columns the segment pass runs per column slice (rounds of 8
+    slices of at most 2^19 columns); one column fewer and it runs per row."""
     A = _sliced_a(np.random.default_rng(31), 3001, m)
     assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), f"sliced m={m}")
     assert_overlap_equal(_run_overlap(lib, A, 2), oracle.overlap(A, 2), f"sliced m={m} ms 2")
+
+
+def test_overlap_unsliced_when_slice_tables_outgrow_a(lib):
+    """3e5 rows of one entry over 2^27 columns: the slice tables (2 * 256 + 1
+    int32 per row) would outgrow max(4 nnz, 2^24) entries, so the segment
+    pass runs per row."""
+    rng = np.random.default_rng(33)
+    n, m = 300000, 1 << 27
+    cols = rng.integers(0, 1 << 12, n) * (m >> 12) + rng.integers(0, 3, n)   # few distinct columns: overlaps
+    A = synth.coo_to_csr(n, m, np.arange(n), cols.astype(np.int32), rng.integers(0, 9000, n).astype(np.int32))
+    assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), "unsliced many rows")
 
 
 def test_overlap_batched_sliced_segments(lib):
