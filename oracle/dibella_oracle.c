@@ -346,3 +346,79 @@ int oracle_tr_pass_marks(int64_t n, const int64_t* rowptr, const int32_t* col,
     free(acc); free(rcode);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Overlap graph R from the seeds stored in C (Sec. IV-D, IV-E)             */
+/* ------------------------------------------------------------------------ */
+/* The reduction needs, per read pair, the overlap suffix and the overlap
+ * orientation, derived in place from the alignment coordinates stored with
+ * the pair.  Here the coordinates are the first stored seed of C_ij, with no
+ * alignment in between: each seed value is (position << 1) | strand, where
+ * strand says whether the read holds the shared canonical k-mer as is (0) or
+ * as its reverse complement (1).  The two reads are reverse-complementary
+ * iff the strands differ.  Extending the seed without gaps to both read ends
+ * places read j (reverse complemented if the pair is) in the frame of read
+ * i at offset d: d = p_i - p_j, or d = p_i + p_j + k - L_j for a
+ * reverse-complementary pair.  The alignment then starts at s_i = max(0, d)
+ * in i and s_j = max(0, -d) in j, and the overlap has length
+ * min(L_i, d + L_j) - max(0, d).  Pairs whose overlap is shorter than
+ * min_overlap are not kept.  A contained overlap (the overlap is all of one
+ * read) is kept with value 0 (the reduction discards it).  Otherwise the
+ * four categories of overlap give the pair's code and suffix:
+ *   not reverse complement, s_i > s_j: forward  -> code (0,0), suffix of j past i
+ *   not reverse complement, s_i < s_j: reverse  -> code (1,1), suffix of j before i
+ *   reverse complement,     s_i > s_j: inner    -> code (0,1), suffix of j past i
+ *   reverse complement,     s_i < s_j: outer    -> code (1,0), suffix of j before i
+ * (s_i > s_j: read i comes first in its own frame, so the walk i -> j keeps
+ * i as sequenced and continues with j in the pair's relative orientation;
+ * otherwise the walk i -> j runs the other way and takes both reads
+ * reverse complemented.)  The diagonal of C is not part of R.
+ * Output: R as CSR with val = (suffix << 2) | code, rows sorted.  Returns 0,
+ * or -1 if a seed of an off-diagonal entry is missing or outside its read. */
+int oracle_r_from_seeds(int64_t n, const int64_t* c_rowptr, const int32_t* c_col,
+                        const int32_t* c_seed, const int32_t* read_len, int32_t k,
+                        int32_t min_overlap, int64_t* out_rowptr, int32_t** out_col,
+                        int32_t** out_val, int64_t* out_nnz) {
+    int64_t cap = c_rowptr[n] ? c_rowptr[n] : 1, nnz = 0;
+    int32_t* oc = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
+    int32_t* ov = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
+    out_rowptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t e = c_rowptr[i]; e < c_rowptr[i + 1]; ++e) {
+            int64_t j = c_col[e];
+            if (j == i) continue;
+            int32_t a = c_seed[4 * e + 0], b = c_seed[4 * e + 1];
+            int64_t li = read_len[i], lj = read_len[j];
+            if (a < 0 || b < 0) { free(oc); free(ov); return -1; }
+            int64_t pi = a >> 1, pj = b >> 1;
+            int rc = (a & 1) != (b & 1);
+            if (pi + k > li || pj + k > lj) { free(oc); free(ov); return -1; }
+            int64_t d = rc ? pi + pj + k - lj : pi - pj;
+            int64_t lo = d > 0 ? d : 0, hi = d + lj < li ? d + lj : li;
+            int64_t overlap = hi - lo;
+            if (overlap < min_overlap) continue;
+            int32_t value;
+            if (overlap == li || overlap == lj) {
+                value = 0;                                   /* contained overlap */
+            } else {
+                int64_t si = d > 0 ? d : 0, sj = d < 0 ? -d : 0;
+                int64_t suffix;
+                int32_t code;
+                if (si > sj) {                               /* forward or inner */
+                    suffix = d + lj - li;
+                    code = rc ? 1 : 0;                       /* (0,0) or (0,1) */
+                } else {                                     /* reverse or outer */
+                    suffix = -d;
+                    code = rc ? 2 : 3;                       /* (1,0) or (1,1) */
+                }
+                value = (int32_t)((suffix << 2) | code);
+            }
+            oc[nnz] = (int32_t)j;
+            ov[nnz] = value;
+            nnz++;
+        }
+        out_rowptr[i + 1] = nnz;
+    }
+    *out_col = oc; *out_val = ov; *out_nnz = nnz;
+    return 0;
+}

@@ -223,13 +223,16 @@ class CSR:
 
 
 def kmer_matrix(reads: Reads, k: int = K_DEFAULT, lo: int = 2, hi: int = 8,
-                device: str = "cpu") -> tuple:
+                device: str = "cpu", strand_bit: bool = False) -> tuple:
     """Build A from reads.  Returns (A, kmer_codes) where kmer_codes[c] is the
     canonical 2-bit code of column c (ascending).
 
     Frequency = occurrences of the canonical k-mer over all reads (repeats
     inside a read count); a k-mer is reliable if lo <= frequency <= hi.
     Column order = ascending canonical code among reliable k-mers.
+    strand_bit: A's value is (position << 1) | strand instead of the
+    position, strand = 1 where the read holds the reverse complement of the
+    canonical k-mer (the orientation the overlap graph is derived from).
     """
     import torch
     dev = torch.device(device)
@@ -249,11 +252,14 @@ def kmer_matrix(reads: Reads, k: int = K_DEFAULT, lo: int = 2, hi: int = 8,
         fwd = (fwd << 2) | w
         rc = rc | ((3 - w) << (2 * q))
     canon = torch.minimum(fwd, rc)
+    strand = (rc < fwd) if strand_bit else None
     del fwd, rc
     rid = torch.repeat_interleave(torch.arange(n, device=dev), lens)[:W]
     pos = torch.arange(W, device=dev) - offs[rid]
     valid = pos + k <= lens[rid]
     canon, rid, pos = canon[valid], rid[valid], pos[valid]
+    if strand is not None:
+        pos = (pos << 1) | strand[valid].to(torch.int64)
     uniq, inv, cnt = torch.unique(canon, sorted=True, return_inverse=True, return_counts=True)
     reliable = (cnt >= lo) & (cnt <= hi)
     colmap = torch.cumsum(reliable.to(torch.int64), 0) - 1
@@ -457,7 +463,7 @@ def _families_to_cover(rng, genome_len, fraction, unit_range, div_range, copies_
 
 
 def make_workload(name: str, seed: Optional[int] = None, device: str = "cpu",
-                  policy: str = "edges", scale: float = 1.0, **over) -> Workload:
+                  policy: str = "edges", scale: float = 1.0, strand_bit: bool = False, **over) -> Workload:
     """Build one of the named workloads.
 
     tiny   100 kbp iid genome, 200 reads U{2..8} kbp, 15% error, k=17,
@@ -473,6 +479,7 @@ def make_workload(name: str, seed: Optional[int] = None, device: str = "cpu",
            [50 kbp, 5 Mbp], 10-50x, lognormal(mean 8 kbp), 15% error, else as
            tiny (reliable [2,8], min_shared 1, R from overlaps >= 1 bp).
     `scale` multiplies the genome length (coverage and read lengths kept).
+    `strand_bit`: A's values carry the k-mer strand (see kmer_matrix).
     """
     base_seed = {"tiny": 1000, "mid": 2000, "large": 3000, "batchset": 4000}[name]
     rng = np.random.default_rng(base_seed if seed is None else seed)
@@ -503,7 +510,7 @@ def make_workload(name: str, seed: Optional[int] = None, device: str = "cpu",
     else:
         reads = sample_reads(rng, g, coverage=p["coverage"],
                              length_lognormal_mean=p["mean_len"], error_rate=p["err"])
-    A, _ = kmer_matrix(reads, K_DEFAULT, p["lo"], p["hi"], device=device)
+    A, _ = kmer_matrix(reads, K_DEFAULT, p["lo"], p["hi"], device=device, strand_bit=strand_bit)
     R = overlap_graph(reads.start, reads.end, reads.strand,
                       min_overlap=p["min_overlap"], policy=policy)
     return Workload(name, reads, A, R, p["min_shared"], p["fuzz"], K_DEFAULT,

@@ -6,6 +6,7 @@ for the diagonal and the total count, the paper's worked example, networkx's
 transitive reduction of DAGs, and the exact string graph of error-free reads.
 """
 import json
+import types
 import os
 
 import numpy as np
@@ -398,3 +399,119 @@ def test_tr_contained_entries_dropped():
     assert trace[0] == 2
     assert {(0, 1), (1, 2)}.isdisjoint({(i, int(S.col[e])) for i in range(3)
                                         for e in range(int(S.rowptr[i]), int(S.rowptr[i + 1]))})
+
+
+# ---------------------------------------------------------------------------
+# Overlap graph from the seeds of C
+# ---------------------------------------------------------------------------
+
+def _reads_from(seqs):
+    """Reads object holding the given base arrays (truth fields unused)."""
+    lens = np.array([s.size for s in seqs], np.int64)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    z = np.zeros(len(seqs), np.int64)
+    return synth.Reads(np.concatenate(seqs).astype(np.uint8), offs, z, z, z.astype(np.int8))
+
+
+def _canonical_kmers_unique(g, k=17):
+    codes = np.zeros(g.size - k + 1, np.int64)
+    rcs = np.zeros_like(codes)
+    for q in range(k):
+        w = g[q:q + codes.size].astype(np.int64)
+        codes = (codes << 2) | w
+        rcs = rcs | ((3 - w) << (2 * q))
+    canon = np.minimum(codes, rcs)
+    return np.unique(canon).size == canon.size
+
+
+@pytest.mark.parametrize("seed", [61, 66])
+def test_r_from_seeds_equals_truth_on_error_free_reads(seed):
+    """Error-free reads of a genome whose canonical 17-mers are all distinct:
+    every seed places its pair exactly, so R from the seeds of C must equal
+    the overlap graph from the true coordinates (pairs overlapping by at
+    least min_overlap; contained pairs carry value 0), both strands mixed."""
+    rng = np.random.default_rng(seed)
+    g = synth.random_genome(rng, 80_000)
+    assert _canonical_kmers_unique(g)   # (seeds chosen so that no 17-mer recurs)
+    reads = synth.sample_reads(rng, g, n_reads=120, length_uniform=(1500, 7000), error_rate=0.0)
+    A, _ = synth.kmer_matrix(reads, 17, 2, 1000, strand_bit=True)
+    C = oracle.overlap(A, 1)
+    lens = np.diff(reads.offsets)
+    R = oracle.r_from_seeds(C, lens, 17, 100)
+    T = synth.overlap_graph(reads.start, reads.end, reads.strand, min_overlap=100, policy="edges")
+    tval = np.where((T.val >> 2) == 0, 0, T.val)
+    assert R.col.size > 500 and np.count_nonzero(R.val == 0) > 10
+    assert np.array_equal(R.rowptr, T.rowptr)
+    assert np.array_equal(R.col, T.col)
+    assert np.array_equal(R.val, tval)
+
+
+def test_r_from_seeds_four_overlap_categories():
+    """Hand-built pairs of each category of overlap (Sec. IV-E): forward /
+    reverse (same strand, read i's alignment starting after / before read
+    j's), inner / outer (reverse-complementary), and contained pairs."""
+    rng = np.random.default_rng(63)
+    g = synth.random_genome(rng, 9000)
+    assert _canonical_kmers_unique(g)
+    rcv = synth.revcomp
+    # (read i, read j, expected value of R_ij): suffix << 2 | code (o_i << 1 | o_j)
+    cases = [
+        ("forward", g[0:3000], g[1000:5000], (2000 << 2) | 0b00),
+        ("reverse", g[1000:5000], g[0:3000], (1000 << 2) | 0b11),
+        ("inner", g[0:3000], rcv(g[1000:5000]), (2000 << 2) | 0b01),
+        ("outer", g[1000:5000], rcv(g[0:3000]), (1000 << 2) | 0b10),
+        ("inner, i reverse complemented", rcv(g[1000:5000]), g[0:3000], (1000 << 2) | 0b01),
+        ("contained", g[0:5000], g[1000:3000], 0),
+        ("contained, reverse complement", rcv(g[1000:3000]), g[0:5000], 0),
+    ]
+    for name, si, sj, want in cases:
+        A, _ = synth.kmer_matrix(_reads_from([si, sj]), 17, 2, 10, strand_bit=True)
+        C = oracle.overlap(A, 1)
+        R = oracle.r_from_seeds(C, [si.size, sj.size], 17, 100)
+        assert list(R.rowptr) == [0, 1, 2], name
+        assert int(R.col[0]) == 1 and int(R.val[0]) == want, (name, int(R.val[0]) >> 2, int(R.val[0]) & 3)
+
+
+def test_r_from_seeds_keeps_an_overlap_of_exactly_min_overlap():
+    rng = np.random.default_rng(63)
+    g = synth.random_genome(rng, 9000)
+    si, sj = g[0:3000], g[1000:5000]            # overlap of 2000 bases
+    A, _ = synth.kmer_matrix(_reads_from([si, sj]), 17, 2, 10, strand_bit=True)
+    C = oracle.overlap(A, 1)
+    assert oracle.r_from_seeds(C, [3000, 4000], 17, 2000).col.size == 2
+    assert oracle.r_from_seeds(C, [3000, 4000], 17, 2001).col.size == 0
+
+
+def test_r_from_seeds_is_transpose_consistent_on_noisy_reads():
+    """With errors the placement is approximate, but C_ji holds C_ij's seeds
+    swapped, so every dovetail pair is described the same way from both
+    ends: the reverse edge has code (1 - o_j, 1 - o_i) and both edges span
+    L_i + suffix_ij = L_j + suffix_ji bases."""
+    w = synth.make_workload("tiny", strand_bit=True)
+    C = oracle.overlap(w.A, w.min_shared)
+    lens = np.diff(w.reads.offsets)
+    R = oracle.r_from_seeds(C, lens, w.k, 200)
+    n = R.nrows
+    val = {}
+    for i in range(n):
+        for e in range(R.rowptr[i], R.rowptr[i + 1]):
+            val[(i, int(R.col[e]))] = int(R.val[e])
+    dovetails = 0
+    for (i, j), v in val.items():
+        assert (j, i) in val
+        u = val[(j, i)]
+        if v == 0 or u == 0:
+            assert v == 0 and u == 0
+            continue
+        dovetails += 1
+        assert (u & 3) == ((1 - (v & 1)) << 1 | (1 - ((v >> 1) & 1)))
+        assert lens[i] + (v >> 2) == lens[j] + (u >> 2)
+    assert dovetails > 1000
+
+
+def test_r_from_seeds_rejects_a_seed_outside_its_read():
+    C = types.SimpleNamespace(nrows=2, rowptr=np.array([0, 1, 2]), col=np.array([1, 0], np.int32),
+                              seed=np.array([[10 << 1, 5 << 1, -1, -1], [5 << 1, 10 << 1, -1, -1]], np.int32))
+    oracle.r_from_seeds(C, [100, 100], 17, 10)
+    with pytest.raises(ValueError):
+        oracle.r_from_seeds(C, [100, 20], 17, 10)

@@ -45,6 +45,20 @@ MUTANTS = [
     ("contained-kept", "if (oh_of(val[e]) > 0) { ci[nnz] = col[e];", "if (oh_of(val[e]) >= 0) { ci[nnz] = col[e];"),
     ("one-pass-only", "} while (nnz != prev);", "} while (0);"),
     ("variant-b-inverted", "(rcode[j] < 0 || (int32_t)(key & 3u) != rcode[j])", "(rcode[j] < 0 || (int32_t)(key & 3u) == rcode[j])"),
+    # overlap graph from the seeds of C
+    ("rfs-strand-ignored", "int rc = (a & 1) != (b & 1);", "int rc = 0;"),
+    ("rfs-rc-offset", "int64_t d = rc ? pi + pj + k - lj : pi - pj;", "int64_t d = rc ? pi + pj - lj : pi - pj;"),
+    ("rfs-offset-sign", "int64_t d = rc ? pi + pj + k - lj : pi - pj;", "int64_t d = rc ? pi + pj + k - lj : pj - pi;"),
+    ("rfs-inner-code", "code = rc ? 1 : 0;                       /* (0,0) or (0,1) */",
+     "code = rc ? 2 : 0;                       /* (0,0) or (0,1) */"),
+    ("rfs-outer-code", "code = rc ? 2 : 3;                       /* (1,0) or (1,1) */",
+     "code = rc ? 1 : 3;                       /* (1,0) or (1,1) */"),
+    ("rfs-suffix-past", "suffix = d + lj - li;", "suffix = d + lj;"),
+    ("rfs-suffix-before", "suffix = -d;", "suffix = li - d - lj;"),
+    ("rfs-contained-kept", "if (overlap == li || overlap == lj) {", "if (0) {"),
+    ("rfs-min-overlap-strict", "if (overlap < min_overlap) continue;", "if (overlap <= min_overlap) continue;"),
+    ("rfs-second-seed", "int32_t a = c_seed[4 * e + 0], b = c_seed[4 * e + 1];",
+     "int32_t a = c_seed[4 * e + 1], b = c_seed[4 * e + 0];"),
     # one-pass marks used for sampled checks
     ("marks-compare-strict", "(int64_t)(nij >> 2) <= mij);", "(int64_t)(nij >> 2) < mij);"),
     ("marks-row-max-unset", "if (vi != 0) vi += fuzz;", "if (vi != 0) vi += fuzz + 1;"),
