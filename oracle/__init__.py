@@ -65,7 +65,7 @@ def _load():
                                               P, P, P, P]
         lib.oracle_transitive_reduce.argtypes = [i64, P, P, P, i32, u32, P, P, P, P, P, P, i32, P]
         lib.oracle_tr_pass_marks.argtypes = [i64, P, P, P, i32, u32, P, i64, P]
-        lib.oracle_r_from_seeds.argtypes = [i64, P, P, P, P, i32, i32, P, P, P, P]
+        lib.oracle_r_from_seeds.argtypes = [i64, P, P, P, P, i32, i32, i32, P, P, P, P]
         lib.oracle_free.argtypes = [P]
         _lib = lib
     return _lib
@@ -178,12 +178,13 @@ def tr_pass_marks(R, fuzz: int, variant: str = "A", rule: str = "row", rows=None
     return mark
 
 
-def r_from_seeds(C, read_len, k: int, min_overlap: int):
+def r_from_seeds(C, read_len, k: int, min_overlap: int, max_drift: int = -1):
     """Overlap graph R from the first seed of every off-diagonal entry of C
     (seed values (position << 1) | strand): suffix and code by the four
     overlap categories; pairs overlapping by fewer than min_overlap bases
-    dropped, contained pairs kept with value 0.  Raises ValueError on a
-    missing or out-of-range seed."""
+    dropped, contained pairs kept with value 0.  max_drift >= 0: a pair is
+    kept only if its second seed agrees (same orientation, offset within
+    max_drift bases).  Raises ValueError on a missing or out-of-range seed."""
     lib = _load()
     n = int(C.nrows)
     rp = np.ascontiguousarray(C.rowptr, dtype=np.int64)
@@ -194,7 +195,8 @@ def r_from_seeds(C, read_len, k: int, min_overlap: int):
     pc, pv = ctypes.c_void_p(), ctypes.c_void_p()
     nnz = ctypes.c_int64()
     r = lib.oracle_r_from_seeds(n, _ptr(rp), _ptr(ci), _ptr(sd), _ptr(ln), int(k), int(min_overlap),
-                                _ptr(out_rp), ctypes.byref(pc), ctypes.byref(pv), ctypes.byref(nnz))
+                                int(max_drift), _ptr(out_rp), ctypes.byref(pc), ctypes.byref(pv),
+                                ctypes.byref(nnz))
     if r != 0:
         raise ValueError("a seed of C is missing or lies outside its read")
     return SimpleNamespace(nrows=n, ncols=n, rowptr=out_rp, col=_take(lib, pc, nnz.value, np.int32),

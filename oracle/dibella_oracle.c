@@ -361,8 +361,12 @@ int oracle_tr_pass_marks(int64_t n, const int64_t* rowptr, const int32_t* col,
  * i at offset d: d = p_i - p_j, or d = p_i + p_j + k - L_j for a
  * reverse-complementary pair.  The alignment then starts at s_i = max(0, d)
  * in i and s_j = max(0, -d) in j, and the overlap has length
- * min(L_i, d + L_j) - max(0, d).  Pairs whose overlap is shorter than
- * min_overlap are not kept.  A contained overlap (the overlap is all of one
+ * min(L_i, d + L_j) - max(0, d).  With max_drift >= 0 a pair is kept only
+ * if C holds its second seed too, placing the pair in the same relative
+ * orientation at an offset within max_drift bases of the first (two
+ * independent k-mers agree on the overlap; an unrelated second hit does
+ * not): this stands in for the alignment that prunes C into R.  Pairs whose
+ * overlap is shorter than min_overlap are not kept.  A contained overlap (the overlap is all of one
  * read) is kept with value 0 (the reduction discards it).  Otherwise the
  * four categories of overlap give the pair's code and suffix:
  *   not reverse complement, s_i > s_j: forward  -> code (0,0), suffix of j past i
@@ -375,10 +379,18 @@ int oracle_tr_pass_marks(int64_t n, const int64_t* rowptr, const int32_t* col,
  * reverse complemented.)  The diagonal of C is not part of R.
  * Output: R as CSR with val = (suffix << 2) | code, rows sorted.  Returns 0,
  * or -1 if a seed of an off-diagonal entry is missing or outside its read. */
+/* Offset of read j in read i's frame from one seed (a, b), and whether the
+ * pair is reverse-complementary. */
+static int64_t seed_offset(int32_t a, int32_t b, int64_t lj, int32_t k, int* rc) {
+    int64_t pi = a >> 1, pj = b >> 1;
+    *rc = (a & 1) != (b & 1);
+    return *rc ? pi + pj + k - lj : pi - pj;
+}
+
 int oracle_r_from_seeds(int64_t n, const int64_t* c_rowptr, const int32_t* c_col,
                         const int32_t* c_seed, const int32_t* read_len, int32_t k,
-                        int32_t min_overlap, int64_t* out_rowptr, int32_t** out_col,
-                        int32_t** out_val, int64_t* out_nnz) {
+                        int32_t min_overlap, int32_t max_drift, int64_t* out_rowptr,
+                        int32_t** out_col, int32_t** out_val, int64_t* out_nnz) {
     int64_t cap = c_rowptr[n] ? c_rowptr[n] : 1, nnz = 0;
     int32_t* oc = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
     int32_t* ov = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
@@ -391,9 +403,17 @@ int oracle_r_from_seeds(int64_t n, const int64_t* c_rowptr, const int32_t* c_col
             int64_t li = read_len[i], lj = read_len[j];
             if (a < 0 || b < 0) { free(oc); free(ov); return -1; }
             int64_t pi = a >> 1, pj = b >> 1;
-            int rc = (a & 1) != (b & 1);
             if (pi + k > li || pj + k > lj) { free(oc); free(ov); return -1; }
-            int64_t d = rc ? pi + pj + k - lj : pi - pj;
+            int rc;
+            int64_t d = seed_offset(a, b, lj, k, &rc);
+            if (max_drift >= 0) {                            /* the second seed must agree */
+                int32_t a1 = c_seed[4 * e + 2], b1 = c_seed[4 * e + 3];
+                if (a1 < 0 || b1 < 0) continue;
+                if ((a1 >> 1) + k > li || (b1 >> 1) + k > lj) { free(oc); free(ov); return -1; }
+                int rc1;
+                int64_t d1 = seed_offset(a1, b1, lj, k, &rc1);
+                if (rc1 != rc || d1 - d > max_drift || d - d1 > max_drift) continue;
+            }
             int64_t lo = d > 0 ? d : 0, hi = d + lj < li ? d + lj : li;
             int64_t overlap = hi - lo;
             if (overlap < min_overlap) continue;

@@ -437,13 +437,16 @@ def test_r_from_seeds_equals_truth_on_error_free_reads(seed):
     A, _ = synth.kmer_matrix(reads, 17, 2, 1000, strand_bit=True)
     C = oracle.overlap(A, 1)
     lens = np.diff(reads.offsets)
-    R = oracle.r_from_seeds(C, lens, 17, 100)
     T = synth.overlap_graph(reads.start, reads.end, reads.strand, min_overlap=100, policy="edges")
     tval = np.where((T.val >> 2) == 0, 0, T.val)
-    assert R.col.size > 500 and np.count_nonzero(R.val == 0) > 10
-    assert np.array_equal(R.rowptr, T.rowptr)
-    assert np.array_equal(R.col, T.col)
-    assert np.array_equal(R.val, tval)
+    # one seed, or both seeds at zero drift (exact reads: every shared k-mer
+    # gives the same offset)
+    for drift in (-1, 0):
+        R = oracle.r_from_seeds(C, lens, 17, 100, drift)
+        assert R.col.size > 500 and np.count_nonzero(R.val == 0) > 10
+        assert np.array_equal(R.rowptr, T.rowptr)
+        assert np.array_equal(R.col, T.col)
+        assert np.array_equal(R.val, tval)
 
 
 def test_r_from_seeds_four_overlap_categories():
@@ -490,7 +493,8 @@ def test_r_from_seeds_is_transpose_consistent_on_noisy_reads():
     w = synth.make_workload("tiny", strand_bit=True)
     C = oracle.overlap(w.A, w.min_shared)
     lens = np.diff(w.reads.offsets)
-    R = oracle.r_from_seeds(C, lens, w.k, 200)
+    R = oracle.r_from_seeds(C, lens, w.k, 200, 150)
+    assert R.col.size < oracle.r_from_seeds(C, lens, w.k, 200).col.size
     n = R.nrows
     val = {}
     for i in range(n):
@@ -507,6 +511,27 @@ def test_r_from_seeds_is_transpose_consistent_on_noisy_reads():
         assert (u & 3) == ((1 - (v & 1)) << 1 | (1 - ((v >> 1) & 1)))
         assert lens[i] + (v >> 2) == lens[j] + (u >> 2)
     assert dovetails > 1000
+
+
+def test_r_from_seeds_second_seed_must_agree():
+    """max_drift >= 0: the pair is kept only if its second seed exists, has
+    the same relative orientation and an offset within max_drift bases of
+    the first seed's; max_drift < 0 uses the first seed alone."""
+    def c_of(s0, s1):
+        seed = np.array([list(s0) + list(s1), list(s0[::-1]) + list(s1[::-1])], np.int32)
+        return types.SimpleNamespace(nrows=2, rowptr=np.array([0, 1, 2]), col=np.array([1, 0], np.int32), seed=seed)
+    L = [5000, 5000]
+    base = (1500 << 1, 500 << 1)                       # offset 1000, same strand
+    cases = [((3000 << 1, 2000 << 1), 0, True),        # offset 1000: agrees exactly
+             ((3000 << 1, 2030 << 1), 30, True),       # offset 970: within 30
+             ((3000 << 1, 2031 << 1), 30, False),      # offset 969: beyond 30
+             ((2030 << 1, 3000 << 1), 30, False),      # offset -970: far off
+             (((3000 << 1) | 1, 2000 << 1), 1000, False),   # other orientation
+             ((-1, -1), 1000, False)]                  # no second seed
+    for s1, drift, kept in cases:
+        C = c_of(base, s1)
+        assert oracle.r_from_seeds(C, L, 17, 100, drift).col.size == (2 if kept else 0), (s1, drift)
+        assert oracle.r_from_seeds(C, L, 17, 100, -1).col.size == 2
 
 
 def test_r_from_seeds_rejects_a_seed_outside_its_read():

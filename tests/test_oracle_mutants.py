@@ -46,9 +46,9 @@ MUTANTS = [
     ("one-pass-only", "} while (nnz != prev);", "} while (0);"),
     ("variant-b-inverted", "(rcode[j] < 0 || (int32_t)(key & 3u) != rcode[j])", "(rcode[j] < 0 || (int32_t)(key & 3u) == rcode[j])"),
     # overlap graph from the seeds of C
-    ("rfs-strand-ignored", "int rc = (a & 1) != (b & 1);", "int rc = 0;"),
-    ("rfs-rc-offset", "int64_t d = rc ? pi + pj + k - lj : pi - pj;", "int64_t d = rc ? pi + pj - lj : pi - pj;"),
-    ("rfs-offset-sign", "int64_t d = rc ? pi + pj + k - lj : pi - pj;", "int64_t d = rc ? pi + pj + k - lj : pj - pi;"),
+    ("rfs-strand-ignored", "*rc = (a & 1) != (b & 1);", "*rc = 0;"),
+    ("rfs-rc-offset", "return *rc ? pi + pj + k - lj : pi - pj;", "return *rc ? pi + pj - lj : pi - pj;"),
+    ("rfs-offset-sign", "return *rc ? pi + pj + k - lj : pi - pj;", "return *rc ? pi + pj + k - lj : pj - pi;"),
     ("rfs-inner-code", "code = rc ? 1 : 0;                       /* (0,0) or (0,1) */",
      "code = rc ? 2 : 0;                       /* (0,0) or (0,1) */"),
     ("rfs-outer-code", "code = rc ? 2 : 3;                       /* (1,0) or (1,1) */",
@@ -59,6 +59,13 @@ MUTANTS = [
     ("rfs-min-overlap-strict", "if (overlap < min_overlap) continue;", "if (overlap <= min_overlap) continue;"),
     ("rfs-second-seed", "int32_t a = c_seed[4 * e + 0], b = c_seed[4 * e + 1];",
      "int32_t a = c_seed[4 * e + 1], b = c_seed[4 * e + 0];"),
+    ("rfs-drift-unchecked", "if (rc1 != rc || d1 - d > max_drift || d - d1 > max_drift) continue;",
+     "if (rc1 != rc) continue;"),
+    ("rfs-drift-orientation-ignored", "if (rc1 != rc || d1 - d > max_drift || d - d1 > max_drift) continue;",
+     "if (d1 - d > max_drift || d - d1 > max_drift) continue;"),
+    ("rfs-drift-strict", "if (rc1 != rc || d1 - d > max_drift || d - d1 > max_drift) continue;",
+     "if (rc1 != rc || d1 - d >= max_drift || d - d1 >= max_drift) continue;"),
+    ("rfs-no-second-seed-kept", "if (a1 < 0 || b1 < 0) continue;", "if (a1 < 0 || b1 < 0) a1 = a, b1 = b;"),
     # one-pass marks used for sampled checks
     ("marks-compare-strict", "(int64_t)(nij >> 2) <= mij);", "(int64_t)(nij >> 2) < mij);"),
     ("marks-row-max-unset", "if (vi != 0) vi += fuzz;", "if (vi != 0) vi += fuzz + 1;"),
