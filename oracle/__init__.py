@@ -65,7 +65,7 @@ def _load():
                                               P, P, P, P]
         lib.oracle_transitive_reduce.argtypes = [i64, P, P, P, i32, u32, P, P, P, P, P, P, i32, P]
         lib.oracle_tr_pass_marks.argtypes = [i64, P, P, P, i32, u32, P, i64, P]
-        lib.oracle_r_from_seeds.argtypes = [i64, P, P, P, P, i32, i32, i32, P, P, P, P]
+        lib.oracle_r_from_seeds.argtypes = [i64, P, P, P, P, P, i32, i32, i32, i32, P, P, P, P]
         lib.oracle_free.argtypes = [P]
         _lib = lib
     return _lib
@@ -178,25 +178,28 @@ def tr_pass_marks(R, fuzz: int, variant: str = "A", rule: str = "row", rows=None
     return mark
 
 
-def r_from_seeds(C, read_len, k: int, min_overlap: int, max_drift: int = -1):
+def r_from_seeds(C, read_len, k: int, min_overlap: int, max_drift: int = -1, min_density: int = 0):
     """Overlap graph R from the first seed of every off-diagonal entry of C
     (seed values (position << 1) | strand): suffix and code by the four
     overlap categories; pairs overlapping by fewer than min_overlap bases
     dropped, contained pairs kept with value 0.  max_drift >= 0: a pair is
     kept only if its second seed agrees (same orientation, offset within
-    max_drift bases).  Raises ValueError on a missing or out-of-range seed."""
+    max_drift bases).  min_density > 0: a pair is kept only if it shares at
+    least min_density k-mers per 10 kbp of its overlap.  Raises ValueError on
+    a missing or out-of-range seed."""
     lib = _load()
     n = int(C.nrows)
     rp = np.ascontiguousarray(C.rowptr, dtype=np.int64)
     ci = np.ascontiguousarray(C.col, dtype=np.int32)
+    cn = np.ascontiguousarray(C.count, dtype=np.int32)
     sd = np.ascontiguousarray(np.asarray(C.seed).reshape(-1), dtype=np.int32)
     ln = np.ascontiguousarray(read_len, dtype=np.int32)
     out_rp = np.zeros(n + 1, np.int64)
     pc, pv = ctypes.c_void_p(), ctypes.c_void_p()
     nnz = ctypes.c_int64()
-    r = lib.oracle_r_from_seeds(n, _ptr(rp), _ptr(ci), _ptr(sd), _ptr(ln), int(k), int(min_overlap),
-                                int(max_drift), _ptr(out_rp), ctypes.byref(pc), ctypes.byref(pv),
-                                ctypes.byref(nnz))
+    r = lib.oracle_r_from_seeds(n, _ptr(rp), _ptr(ci), _ptr(cn), _ptr(sd), _ptr(ln), int(k), int(min_overlap),
+                                int(max_drift), int(min_density), _ptr(out_rp), ctypes.byref(pc),
+                                ctypes.byref(pv), ctypes.byref(nnz))
     if r != 0:
         raise ValueError("a seed of C is missing or lies outside its read")
     return SimpleNamespace(nrows=n, ncols=n, rowptr=out_rp, col=_take(lib, pc, nnz.value, np.int32),

@@ -365,8 +365,13 @@ int oracle_tr_pass_marks(int64_t n, const int64_t* rowptr, const int32_t* col,
  * if C holds its second seed too, placing the pair in the same relative
  * orientation at an offset within max_drift bases of the first (two
  * independent k-mers agree on the overlap; an unrelated second hit does
- * not): this stands in for the alignment that prunes C into R.  Pairs whose
- * overlap is shorter than min_overlap are not kept.  A contained overlap (the overlap is all of one
+ * not).  With min_density > 0 a pair is kept only if it shares at least
+ * min_density k-mers per 10 kbp of its overlap (count * 10000 >=
+ * min_density * overlap): a true overlap shares k-mers all along its
+ * length at a rate the error rate fixes, a pair that only shares a repeat
+ * does so along the repeat alone.  Both tests stand in for the alignment
+ * that prunes C into R.  Pairs whose overlap is shorter than min_overlap
+ * are not kept.  A contained overlap (the overlap is all of one
  * read) is kept with value 0 (the reduction discards it).  Otherwise the
  * four categories of overlap give the pair's code and suffix:
  *   not reverse complement, s_i > s_j: forward  -> code (0,0), suffix of j past i
@@ -388,9 +393,10 @@ static int64_t seed_offset(int32_t a, int32_t b, int64_t lj, int32_t k, int* rc)
 }
 
 int oracle_r_from_seeds(int64_t n, const int64_t* c_rowptr, const int32_t* c_col,
-                        const int32_t* c_seed, const int32_t* read_len, int32_t k,
-                        int32_t min_overlap, int32_t max_drift, int64_t* out_rowptr,
-                        int32_t** out_col, int32_t** out_val, int64_t* out_nnz) {
+                        const int32_t* c_count, const int32_t* c_seed, const int32_t* read_len,
+                        int32_t k, int32_t min_overlap, int32_t max_drift, int32_t min_density,
+                        int64_t* out_rowptr, int32_t** out_col, int32_t** out_val,
+                        int64_t* out_nnz) {
     int64_t cap = c_rowptr[n] ? c_rowptr[n] : 1, nnz = 0;
     int32_t* oc = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
     int32_t* ov = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
@@ -417,6 +423,7 @@ int oracle_r_from_seeds(int64_t n, const int64_t* c_rowptr, const int32_t* c_col
             int64_t lo = d > 0 ? d : 0, hi = d + lj < li ? d + lj : li;
             int64_t overlap = hi - lo;
             if (overlap < min_overlap) continue;
+            if (min_density > 0 && (int64_t)c_count[e] * 10000 < (int64_t)min_density * overlap) continue;
             int32_t value;
             if (overlap == li || overlap == lj) {
                 value = 0;                                   /* contained overlap */

@@ -440,9 +440,10 @@ def test_r_from_seeds_equals_truth_on_error_free_reads(seed):
     T = synth.overlap_graph(reads.start, reads.end, reads.strand, min_overlap=100, policy="edges")
     tval = np.where((T.val >> 2) == 0, 0, T.val)
     # one seed, or both seeds at zero drift (exact reads: every shared k-mer
-    # gives the same offset)
-    for drift in (-1, 0):
-        R = oracle.r_from_seeds(C, lens, 17, 100, drift)
+    # gives the same offset), or a density exact reads far exceed (every
+    # position of the overlap but the last 16 starts a shared k-mer)
+    for drift, density in ((-1, 0), (0, 0), (0, 5000)):
+        R = oracle.r_from_seeds(C, lens, 17, 100, drift, density)
         assert R.col.size > 500 and np.count_nonzero(R.val == 0) > 10
         assert np.array_equal(R.rowptr, T.rowptr)
         assert np.array_equal(R.col, T.col)
@@ -493,8 +494,9 @@ def test_r_from_seeds_is_transpose_consistent_on_noisy_reads():
     w = synth.make_workload("tiny", strand_bit=True)
     C = oracle.overlap(w.A, w.min_shared)
     lens = np.diff(w.reads.offsets)
-    R = oracle.r_from_seeds(C, lens, w.k, 200, 150)
-    assert R.col.size < oracle.r_from_seeds(C, lens, w.k, 200).col.size
+    R = oracle.r_from_seeds(C, lens, w.k, 200, 150, 16)
+    assert R.col.size < oracle.r_from_seeds(C, lens, w.k, 200, 150).col.size < \
+        oracle.r_from_seeds(C, lens, w.k, 200).col.size
     n = R.nrows
     val = {}
     for i in range(n):
@@ -519,7 +521,8 @@ def test_r_from_seeds_second_seed_must_agree():
     the first seed's; max_drift < 0 uses the first seed alone."""
     def c_of(s0, s1):
         seed = np.array([list(s0) + list(s1), list(s0[::-1]) + list(s1[::-1])], np.int32)
-        return types.SimpleNamespace(nrows=2, rowptr=np.array([0, 1, 2]), col=np.array([1, 0], np.int32), seed=seed)
+        return types.SimpleNamespace(nrows=2, rowptr=np.array([0, 1, 2]), col=np.array([1, 0], np.int32),
+                                     count=np.array([2, 2], np.int32), seed=seed)
     L = [5000, 5000]
     base = (1500 << 1, 500 << 1)                       # offset 1000, same strand
     cases = [((3000 << 1, 2000 << 1), 0, True),        # offset 1000: agrees exactly
@@ -534,8 +537,22 @@ def test_r_from_seeds_second_seed_must_agree():
         assert oracle.r_from_seeds(C, L, 17, 100, -1).col.size == 2
 
 
+def test_r_from_seeds_density_of_shared_kmers():
+    """min_density > 0: kept iff count * 10000 >= min_density * overlap, the
+    overlap being the placed one (here 4000 bases)."""
+    L = [5000, 5000]
+    seed = np.array([[1500 << 1, 500 << 1, 3000 << 1, 2000 << 1], [500 << 1, 1500 << 1, 2000 << 1, 3000 << 1]],
+                    np.int32)                                   # offset 1000: overlap 4000
+    for count, density, kept in ((20, 50, True), (19, 50, False), (2, 5, True), (1, 5, False), (1, 0, True)):
+        C = types.SimpleNamespace(nrows=2, rowptr=np.array([0, 1, 2]), col=np.array([1, 0], np.int32),
+                                  count=np.array([count, count], np.int32), seed=seed)
+        got = oracle.r_from_seeds(C, L, 17, 100, 0, density).col.size
+        assert got == (2 if kept else 0), (count, density)
+
+
 def test_r_from_seeds_rejects_a_seed_outside_its_read():
     C = types.SimpleNamespace(nrows=2, rowptr=np.array([0, 1, 2]), col=np.array([1, 0], np.int32),
+                              count=np.array([1, 1], np.int32),
                               seed=np.array([[10 << 1, 5 << 1, -1, -1], [5 << 1, 10 << 1, -1, -1]], np.int32))
     oracle.r_from_seeds(C, [100, 100], 17, 10)
     with pytest.raises(ValueError):

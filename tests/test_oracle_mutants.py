@@ -66,6 +66,12 @@ MUTANTS = [
     ("rfs-drift-strict", "if (rc1 != rc || d1 - d > max_drift || d - d1 > max_drift) continue;",
      "if (rc1 != rc || d1 - d >= max_drift || d - d1 >= max_drift) continue;"),
     ("rfs-no-second-seed-kept", "if (a1 < 0 || b1 < 0) continue;", "if (a1 < 0 || b1 < 0) a1 = a, b1 = b;"),
+    ("rfs-density-unchecked", "if (min_density > 0 && (int64_t)c_count[e] * 10000 < (int64_t)min_density * overlap) continue;",
+     "if (0) continue;"),
+    ("rfs-density-strict", "if (min_density > 0 && (int64_t)c_count[e] * 10000 < (int64_t)min_density * overlap) continue;",
+     "if (min_density > 0 && (int64_t)c_count[e] * 10000 <= (int64_t)min_density * overlap) continue;"),
+    ("rfs-density-per-kbp", "if (min_density > 0 && (int64_t)c_count[e] * 10000 < (int64_t)min_density * overlap) continue;",
+     "if (min_density > 0 && (int64_t)c_count[e] * 1000 < (int64_t)min_density * overlap) continue;"),
     # one-pass marks used for sampled checks
     ("marks-compare-strict", "(int64_t)(nij >> 2) <= mij);", "(int64_t)(nij >> 2) < mij);"),
     ("marks-row-max-unset", "if (vi != 0) vi += fuzz;", "if (vi != 0) vi += fuzz + 1;"),
