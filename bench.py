@@ -3,15 +3,18 @@
 A step is one pass of the whole hot path over one read set:
     C = A A^T            (overlap: count + two seeds, LDS-hash / ESC SpGEMM)
     S = TR(R)            (transitive reduction to the fixed point)
-on the mid-size long-read workload (10 Mbp genome with 300 copies of a 2 kbp
-repeat at 1% divergence, 30x lognormal reads of mean 10 kbp, 15% error,
-k = 17, reliable k-mers in [2, 30], min_shared 2, fuzz 1000).  Inputs are
-resident in HBM before timing starts.
+on one GPU's share of a large run by default (50 Mbp genome with 5% repeats
+from 1-6 kbp families at 0.5-3% divergence, 40x lognormal reads of mean
+12 kbp, 12% error, k = 17, reliable k-mers in [2, 40], min_shared 2; R = the
+true overlaps of at least 1 kbp among the candidate pairs of C, fuzz 1000).
+Inputs are resident in HBM before timing starts.
 
 value = semiring products per second = (A A^T multiplies + walks examined by
 all reduction passes) / step time.  The JSON line also carries the roofline
 of the dominant kernel (measured with HIP events on the library's stream,
-over the timed steps) and the CPU oracle timed on a bounded sample.
+over the timed steps), the CPU oracle timed on bounded samples, the
+batching comparison (64 uneven sets, graph-captured reductions) and the
+serving comparison (continuous batching vs FIFO on the same trace).
 """
 from __future__ import annotations
 
@@ -297,93 +300,118 @@ def gather_probe():
     print(json.dumps({"gather_probe": out}))
 
 
-def cpu_baseline(w, budget_s: float):
-    """Oracle (plain C, one thread) on a bounded sample of the same workload:
-    the overlap rows of a prefix of reads, then the full reduction of R if it
-    fits the remaining budget."""
+def _row_products(A):
     import numpy as np
-    import oracle
-    from paper_2010_10055_amd import synth
-    A = w.A
     a = np.bincount(A.col, minlength=A.ncols).astype(np.int64)
-    row_products = np.add.reduceat(a[A.col], A.rowptr[:-1]) if A.nnz else np.zeros(A.nrows, np.int64)
-    row_products[np.diff(A.rowptr) == 0] = 0
-    # every call first builds A^T (a fixed cost, timed on an empty row
-    # selection); the product rate comes from a few rows beyond that, and
-    # the sample is sized to about budget/2 seconds in all
-    t0 = time.perf_counter()
-    oracle.overlap(A, w.min_shared, rows=np.arange(0))
-    t_fixed = time.perf_counter() - t0
-    ncal = min(200, A.nrows)
-    t0 = time.perf_counter()
-    oracle.overlap(A, w.min_shared, rows=np.arange(ncal))
-    t_cal = time.perf_counter() - t0
-    prod_cal = int(row_products[:ncal].sum())
-    rate = prod_cal / max(t_cal - t_fixed, 1e-3)
-    want = rate * max(budget_s * 0.5 - t_fixed, 1.0)
-    csum = np.cumsum(row_products)
-    nrows = int(min(A.nrows, max(ncal, np.searchsorted(csum, want) + 1)))
-    rows = np.arange(nrows)
-    prod = int(row_products[:nrows].sum())
-    # a whole step shorter than budget/2 is run again until the sample
-    # reaches it
-    reps, t_ov, t_tr, walks = 0, 0.0, 0.0, 0
-    while True:
-        t0 = time.perf_counter()
-        oracle.overlap(A, w.min_shared, rows=rows)
-        t_ov += time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _, _, _, walks = oracle.transitive_reduce(w.R, w.fuzz, with_walks=True)
-        t_tr += time.perf_counter() - t0
-        reps += 1
-        if nrows < A.nrows or t_ov + t_tr >= budget_s * 0.5 or reps >= 8:
-            break
-    value = reps * (prod + walks) / (t_ov + t_tr)
-    times = f" x{reps} (whole step)" if reps > 1 else ""
-    return {"value": value, "unit": "products/s", "cores": 1, "kind": "oracle",
-            "sample": f"A*A^T rows 0..{nrows - 1} of {A.nrows} ({prod} products) + full reduction of R "
-                      f"({w.R.nnz} entries, {walks} walks){times}: {t_ov:.1f} s + {t_tr:.1f} s; "
-                      f"plain C -O2, single thread"}
+    rp = np.add.reduceat(a[A.col], A.rowptr[:-1]) if A.nnz else np.zeros(A.nrows, np.int64)
+    rp[np.diff(A.rowptr) == 0] = 0
+    return rp
 
 
-def cpu_parallel(w, threads: int = 0):
-    """The same oracle on all host cores: every A*A^T row once, split into one
-    contiguous row range per thread (balanced by products); each thread makes
-    one oracle call, which builds its own A^T first.  ctypes releases the
-    interpreter lock during the call, so the threads run in parallel."""
+def _row_walks(R):
+    """Walks i -> k -> j a reduction pass examines per row of R."""
+    import numpy as np
+    deg = np.diff(R.rowptr).astype(np.int64)
+    per_entry = deg[R.col] if R.col.size else np.zeros(0, np.int64)
+    out = np.zeros(R.nrows, np.int64)
+    if R.col.size:
+        nz = deg > 0
+        out[nz] = np.add.reduceat(per_entry, R.rowptr[:-1][nz])
+    return out
+
+
+def _spread_rows(weights, want, nblocks=64):
+    """About `want` of the total weight in `nblocks` row blocks spread evenly
+    over the rows (rows are in random genome order, blocks avoid any bias of
+    a prefix)."""
+    import numpy as np
+    n = weights.size
+    total = max(int(weights.sum()), 1)
+    frac = min(1.0, want / total)
+    rows = []
+    for b in range(nblocks):
+        lo, hi = b * n // nblocks, (b + 1) * n // nblocks
+        cs = np.cumsum(weights[lo:hi])
+        take = int(np.searchsorted(cs, cs[-1] * frac if cs.size else 0)) + 1 if cs.size else 0
+        rows.append(np.arange(lo, min(hi, lo + max(take, 1))))
+    return np.unique(np.concatenate(rows)).astype(np.int64)
+
+
+def cpu_legs(w, R, tr_stats, budget_s: float, threads: int = 0):
+    """The oracle (plain C -O2) on the host's cores, on bounded samples of
+    the same step: A^T built once (timed; every oracle row call needs it),
+    a sample of A A^T rows spread over the matrix, and one reduction pass
+    over a sample of R's rows.  Each rate scales its part of the whole step
+    (all products, the walks of all passes); the step estimate is the
+    transpose plus both scaled parts.  Single thread: `cpu_baseline`; the
+    same with the sampled rows in row ranges on all host cores (threads
+    sharing A^T): `cpu_parallel`."""
     import numpy as np
     import oracle
     from concurrent.futures import ThreadPoolExecutor
+    A = w.A
     if threads <= 0:
         try:
             threads = len(os.sched_getaffinity(0))
         except AttributeError:
             threads = os.cpu_count() or 1
         threads = max(1, min(16, threads))
-    A = w.A
-    a = np.bincount(A.col, minlength=A.ncols).astype(np.int64)
-    row_products = np.add.reduceat(a[A.col], A.rowptr[:-1]) if A.nnz else np.zeros(A.nrows, np.int64)
-    row_products[np.diff(A.rowptr) == 0] = 0
-    csum = np.cumsum(row_products)
-    total = int(csum[-1]) if csum.size else 0
-    cuts = [0] + [int(np.searchsorted(csum, total * q / threads)) for q in range(1, threads)] + [A.nrows]
-    ranges = [np.arange(cuts[q], cuts[q + 1]) for q in range(threads) if cuts[q + 1] > cuts[q]]
+    rprod = _row_products(A)
+    rwalk = _row_walks(R)
+    products = int(rprod.sum())
+    walks_all = int(tr_stats["triples"])
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(len(ranges)) as ex:
-        list(ex.map(lambda r: oracle.overlap(A, w.min_shared, rows=r), ranges))
-    t = time.perf_counter() - t0
-    return {"value": total / t, "unit": "products/s", "cores": len(ranges), "kind": "oracle",
-            "sample": f"every A*A^T row ({total} products) in {len(ranges)} row ranges, one thread and one "
-                      f"A^T build each: {t:.1f} s; plain C -O2"}
+    at = oracle.transpose(A)
+    t_at = time.perf_counter() - t0
+    # calibrate the row rate on a few rows, then size the samples
+    cal = _spread_rows(rprod, 2e6)
+    t0 = time.perf_counter()
+    oracle.overlap(A, w.min_shared, rows=cal, at=at)
+    rate = max(int(rprod[cal].sum()), 1) / max(time.perf_counter() - t0, 1e-4)
+    tcal = _spread_rows(rwalk, 2e6)
+    t0 = time.perf_counter()
+    oracle.tr_pass_marks(R, w.fuzz, rows=tcal)
+    trate = max(int(rwalk[tcal].sum()), 1) / max(time.perf_counter() - t0, 1e-4)
+    part = budget_s * 0.3
+
+    def run(nthreads):
+        rows = _spread_rows(rprod, rate * part * nthreads)
+        trows = _spread_rows(rwalk, trate * part * 0.3 * nthreads)
+        chunks = [c for c in np.array_split(rows, nthreads) if c.size]
+        tchunks = [c for c in np.array_split(trows, nthreads) if c.size]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(len(chunks)) as ex:
+            list(ex.map(lambda r: oracle.overlap(A, w.min_shared, rows=r, at=at), chunks))
+        t_rows = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(len(tchunks)) as ex:
+            list(ex.map(lambda r: oracle.tr_pass_marks(R, w.fuzz, rows=r), tchunks))
+        t_tr = time.perf_counter() - t0
+        p_s, w_s = int(rprod[rows].sum()), int(rwalk[trows].sum())
+        step = t_at + t_rows * products / max(p_s, 1) + t_tr * walks_all / max(w_s, 1)
+        return {"value": (products + walks_all) / step, "unit": "products/s", "cores": len(chunks),
+                "kind": "oracle",
+                "sample": (f"A^T built once in {t_at:.1f} s (single thread); A*A^T rows: {rows.size} of {A.nrows} in "
+                           f"64 blocks spread over the matrix ({p_s} of {products} products) in {t_rows:.1f} s; "
+                           f"one reduction pass over {trows.size} of {R.nrows} rows of R ({w_s} walks) in "
+                           f"{t_tr:.1f} s; whole step scaled by products and by the walks of all {len(tr_stats['triples_trace'])} "
+                           f"passes ({walks_all}): {step:.1f} s; plain C -O2, {len(chunks)} thread(s)"),
+                "step_s_estimated": round(step, 2)}
+    single = run(1)
+    multi = run(threads) if threads > 1 else None
+    del at
+    return single, multi
 
 
-def batch_compare(db, synth, nsets: int, steps: int, graph: bool, tune_budget: float = 0.0):
+def batch_compare(db, synth, nsets: int, steps: int, tune_budget: float = 0.0):
     """The batching workload: `nsets` independent read sets (genomes
     log-uniform in 50 kbp..5 Mbp, 10-50x, lognormal reads of mean 8 kbp,
     15% error, k = 17, reliable [2, 8], min_shared 1, fuzz 1000): the plain
     path (one overlap + one reduction call per set, one after the other) and
     the batched path (one batched overlap call and one batched reduction
-    call for all sets), same stream.  Results are compared set by set."""
+    call for all sets), same stream.  The reductions run as captured HIP
+    graphs (the batching workload's recipe); the same comparison without
+    graphs is reported beside it.  Results are compared set by set."""
     import torch
     t0 = time.perf_counter()
     ws = synth.batch_workloads(nsets, device="cuda:0")
@@ -394,83 +422,106 @@ def batch_compare(db, synth, nsets: int, steps: int, graph: bool, tune_budget: f
     fz = [w.fuzz for w in ws]
     products = sum(synth.overlap_products(w.A) for w in ws)
 
-    def plain():
+    def plain(graph):
         out = []
         for a, r, m, f in zip(As, Rs, ms, fz):
             C = db.overlap(a, m)
-            S, _ = db.transitive_reduce(r, f, graph=graph)
-            out.append((C, S))
+            S, it = db.transitive_reduce(r, f, graph=graph)
+            out.append((C, S, it))
         return out
 
-    def batched():
+    def batched(graph):
         Cs = db.overlap_batched(As, ms)
-        Ss, _ = db.transitive_reduce_batched(Rs, fz, graph=graph)
-        return list(zip(Cs, Ss))
+        Ss, its = db.transitive_reduce_batched(Rs, fz, graph=graph)
+        return list(zip(Cs, Ss, its))
 
     tuned = None
     if tune_budget > 0:
         from paper_2010_10055_amd import autotune
-
-        def fp(res):
-            return tuple((int(c.col.sum()), int(c.seed.sum()), int(s.val.sum()), s.nnz) for c, s in res)
-
         key = autotune.workload_key("gfx950", [w.A for w in ws], ms)
         t0 = time.perf_counter()
-        tuned = autotune.autotune(batched, fp, key, budget_s=tune_budget, repeats=2, log=log)
+        tuned = autotune.autotune(lambda: batched(True), key, budget_s=tune_budget, repeats=2, log=log)
         log(f"  autotune {time.perf_counter() - t0:.1f} s -> {tuned}")
-    res_p, res_b = plain(), batched()
+    from paper_2010_10055_amd import autotune
+    ref = autotune.snapshot(plain(True))
+    same = autotune.results_equal(ref, batched(True)) and autotune.results_equal(ref, batched(False))
     torch.cuda.synchronize()
-    same = all(torch.equal(cp.col, cb.col) and torch.equal(cp.seed, cb.seed) and torch.equal(cp.count, cb.count)
-               and torch.equal(sp.col, sb.col) and torch.equal(sp.val, sb.val)
-               for (cp, sp), (cb, sb) in zip(res_p, res_b))
     times = {}
-    for name, fn in (("plain", plain), ("batched", batched)):
-        fn()
+    for name, fn, graph in (("plain", plain, True), ("batched", batched, True),
+                            ("plain_no_graph", plain, False), ("batched_no_graph", batched, False)):
+        fn(graph)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            fn()
+            fn(graph)
         torch.cuda.synchronize()
         times[name] = (time.perf_counter() - t0) / steps
-    return {"sets": nsets, "reads": sum(w.A.nrows for w in ws), "overlap_products": products,
+    return {"sets": nsets, "reads": sum(w.A.nrows for w in ws), "overlap_products": products, "graph": True,
             "plain_ms": round(times["plain"] * 1e3, 3), "batched_ms": round(times["batched"] * 1e3, 3),
             "speedup": round(times["plain"] / times["batched"], 3), "bit_identical": bool(same),
-            "graph": graph, "tuning": tuned}
+            "no_graph": {"plain_ms": round(times["plain_no_graph"] * 1e3, 3),
+                         "batched_ms": round(times["batched_no_graph"] * 1e3, 3),
+                         "speedup": round(times["plain_no_graph"] / times["batched_no_graph"], 3)},
+            "tuning": tuned}
 
 
-def serve_compare(njobs: int, seed: int = 5000):
-    """Serving: a Poisson stream of layout jobs (90% large-shaped read sets:
-    the large workload's recipe on a 2 Mbp genome, 40x; 10% tiny ones) drawn
-    from a pool of pre-generated device-resident instances.  The arrival rate
-    is fixed at 0.8x the measured capacity of the FIFO one-at-a-time executor;
-    the same trace runs through FIFO and through continuous batching."""
+def serve_compare(njobs: int, slots: int = 3, seed: int = 5000):
+    """Serving: Poisson streams of layout jobs (overlap, R from C's seeds on
+    the device, reduction): 90% of the jobs one of two instances of the
+    large workload's recipe (50 Mbp genome, 40x, ~167k reads), 10% of the
+    tiny one, all device resident.  FIFO (one slot: one job on the device at
+    a time) and continuous batching (`slots` slots, each a host thread with
+    its own stream) replay the same trace, at 0.8x the FIFO capacity
+    measured on a probe (latency) and at 1.5x (saturation: throughput).
+    Admission budget: the free device memory measured before the runs."""
     import numpy as np
     import torch
     from paper_2010_10055_amd import serve
     t0 = time.perf_counter()
-    pool = serve.make_pool([("large", 6, seed, 0.04), ("tiny", 6, seed + 100, 1.0)], device="cuda:0")
+    pool = serve.make_pool([("large", 2, seed, 1.0), ("tiny", 4, seed + 100, 1.0)], device="cuda:0", log=log)
     log(f"  serve pool {time.perf_counter() - t0:.1f} s")
-    fifo = serve.gpu_executor(batched=False)
-    cont = serve.gpu_executor(batched=True)
-    rng = np.random.default_rng(seed)
-    probe = serve.draw_jobs(rng, pool, 40, rate=1e9)
-    fifo(probe[:4])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for j in probe:
-        fifo([j])
-    service = (time.perf_counter() - t0) / len(probe)
-    rate = 0.8 / service
-    jobs = serve.draw_jobs(np.random.default_rng(seed + 1), pool, njobs, rate=rate)
-    budget = 32 << 30
-    out = {"jobs": njobs, "rate_jobs_per_s": round(rate, 2), "fifo_service_ms": round(service * 1e3, 3),
-           "hbm_budget_gib": budget >> 30}
-    for name, ex, mb in (("fifo", fifo, 1), ("continuous", cont, 64)):
-        clock = serve.WallClock()
-        done = serve.serve(jobs, ex, clock, hbm_budget=budget, max_batch=mb)
-        s = serve.summarize(done, clock.now())
-        out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
-    out["p99_speedup"] = round(out["fifo"]["p99_ms"] / max(1e-9, out["continuous"]["p99_ms"]), 3)
+    torch.cuda.empty_cache()
+    budget = serve.hbm_free_bytes()
+    clock = serve.WallClock()
+    # FIFO capacity on a probe of the same mix
+    probe = serve.draw_jobs(np.random.default_rng(seed), pool, 12, rate=1e9)
+    fifo = serve.GpuSlots(1, clock)
+    try:
+        for j in probe[:3]:
+            fifo.submit(j, 0)
+            fifo.wait(None)
+        t0 = time.perf_counter()
+        for j in probe:
+            fifo.submit(j, 0)
+            fifo.wait(None)
+        service = (time.perf_counter() - t0) / len(probe)
+    finally:
+        fifo.close()
+    out = {"jobs": njobs, "slots": slots, "fifo_service_ms": round(service * 1e3, 2),
+           "hbm_budget_gib": round(budget / 2**30, 1),
+           "job_mix": "90% large recipe (2 instances, 50 Mbp, 40x), 10% tiny (4 instances)"}
+    for label, factor in (("load_0.8", 0.8), ("load_1.5", 1.5)):
+        rate = factor / service
+        jobs = serve.draw_jobs(np.random.default_rng(seed + 1), pool, njobs, rate=rate)
+        res = {"rate_jobs_per_s": round(rate, 2)}
+        for name, nslots in (("fifo", 1), ("continuous", slots)):
+            clock = serve.WallClock()
+            ex = serve.GpuSlots(nslots, clock)
+            st = {}
+            try:
+                done = serve.serve(jobs, ex, clock, hbm_budget=budget, slots=nslots, stats=st)
+            finally:
+                ex.close()
+            s = serve.summarize(done, clock.now())
+            s.update(peak_running=st["peak_running"], peak_reserved_gib=round(st["peak_reserved"] / 2**30, 1))
+            res[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
+            log(f"  {label} {name}: {res[name]['jobs_per_s']} jobs/s, p50 {res[name]['p50_ms']} ms, "
+                f"p99 {res[name]['p99_ms']} ms")
+        res["throughput_ratio"] = round(res["continuous"]["jobs_per_s"] / max(1e-9, res["fifo"]["jobs_per_s"]), 3)
+        res["p99_ratio"] = round(res["fifo"]["p99_ms"] / max(1e-9, res["continuous"]["p99_ms"]), 3)
+        out[label] = res
+    del pool
+    torch.cuda.empty_cache()
     return out
 
 
@@ -479,15 +530,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
+    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large"])
     ap.add_argument("--graph", action="store_true", help="run reduction passes as captured HIP graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--check", action="store_true", help="compare one step with the oracle first")
     ap.add_argument("--batch-sets", type=int, default=64, help="sets of the batching comparison (0 = skip)")
     ap.add_argument("--tune-budget", type=float, default=30.0, help="seconds of autotuning for the batch (0 = off)")
-    ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving comparison (0 = skip)")
-    ap.add_argument("--calib-copy", action="store_true", help="only run the 1 GiB copy used to scale counters")
+    ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving comparison (0 = skip)")
+    ap.add_argument("--serve-slots", type=int, default=3, help="slots of continuous batching")
+    ap.add_argument("--calib-copy", action="store_true", help="only run the reference kernels used to scale counters")
     ap.add_argument("--gather-probe", action="store_true", help="only measure random-gather rates by footprint")
     ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/ summaries from rocprofv3 CSV directories")
@@ -515,15 +567,20 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     default_tuning = db.get_tuning()
-    t0 = time.perf_counter()
+    t_start = time.perf_counter()
     log(f"generating workload '{args.workload}' ...")
     w = synth.make_workload(args.workload, device=dev)
-    log(f"  {time.perf_counter() - t0:.1f} s: reads {w.A.nrows}, k-mers {w.A.ncols}, "
-        f"nnz(A) {w.A.nnz}, nnz(R) {w.R.nnz}")
     products = synth.overlap_products(w.A)
     A = db.CSRTensors.from_numpy(w.A, dev)
-    R = db.CSRTensors.from_numpy(w.R, dev)
+    # R: the overlap graph of the true coordinates restricted to the
+    # off-diagonal pattern of C (a perfect aligner's verdict on the candidates)
+    C0 = db.overlap(A, w.min_shared)
+    Rh = synth.restrict_to_pattern(w.R, C0.rowptr, C0.col, device=dev)
+    del C0
+    R = db.CSRTensors.from_numpy(Rh, dev)
     torch.cuda.synchronize()
+    log(f"  {time.perf_counter() - t_start:.1f} s: reads {w.A.nrows}, k-mers {w.A.ncols}, "
+        f"nnz(A) {w.A.nnz}, nnz(R) {Rh.nnz} (true overlaps {w.R.nnz}, restricted to the candidates)")
 
     def step():
         C = db.overlap(A, w.min_shared)
@@ -536,7 +593,7 @@ def main():
         ref = oracle.overlap(w.A, w.min_shared)
         ok = (np.array_equal(C.col.cpu().numpy(), ref.col) and
               np.array_equal(C.seed.cpu().numpy(), ref.seed))
-        Sref, it_ref, _ = oracle.transitive_reduce(w.R, w.fuzz)
+        Sref, it_ref, _ = oracle.transitive_reduce(Rh, w.fuzz)
         ok = ok and np.array_equal(S.col.cpu().numpy(), Sref.col) and it == it_ref
         log(f"check vs oracle: {'ok' if ok else 'MISMATCH'}")
         if not ok:
@@ -620,25 +677,27 @@ def main():
                for k in per_step_ms}
     kernels_timed_over = (f"{prof_steps} warmup steps (every unit's events)" if prof_steps
                           else f"the {args.steps} timed steps")
+    nnz_C = C.nnz
+    del C, S
+    log(f"  {ms_step:.2f} ms per step, {dominant} {dom_ms:.2f} ms ({achieved / HBM_PEAK_GBS:.3f} of the HBM peak)")
+
+    cpu = cpu_par = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on bounded samples, one thread, then all host cores) ...")
+        cpu, cpu_par = cpu_legs(w, Rh, tr_stats, args.cpu_budget)
 
     batch = None
     if args.batch_sets > 0:
         log(f"batching comparison ({args.batch_sets} sets) ...")
-        batch = batch_compare(db, synth, args.batch_sets, max(1, min(args.steps, 5)), args.graph,
-                              args.tune_budget)
+        batch = batch_compare(db, synth, args.batch_sets, max(1, min(args.steps, 5)), args.tune_budget)
         db.set_tuning(**default_tuning)
 
     served = None
     if args.serve_jobs > 0:
-        log(f"serving comparison ({args.serve_jobs} jobs) ...")
-        served = serve_compare(args.serve_jobs)
-
-    cpu = cpu_par = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(w, args.cpu_budget)
-        log("cpu baseline on all host cores (oracle, row ranges on threads) ...")
-        cpu_par = cpu_parallel(w)
+        log(f"serving comparison ({args.serve_jobs} jobs per run) ...")
+        del A, R
+        torch.cuda.empty_cache()
+        served = serve_compare(args.serve_jobs, args.serve_slots)
 
     out = {
         "metric": "semiring products/s (A*A^T multiplies + transitive-reduction walks)",
@@ -646,15 +705,16 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": args.workload, "reads": w.A.nrows, "kmers": w.A.ncols,
-                   "nnz_A": w.A.nnz, "overlap_products": products, "nnz_C": C.nnz,
-                   "min_shared": w.min_shared, "nnz_R": w.R.nnz, "nnz_S": S.nnz,
+                   "nnz_A": w.A.nnz, "overlap_products": products, "nnz_C": nnz_C,
+                   "min_shared": w.min_shared, "nnz_R": Rh.nnz, "nnz_S": int(tr_stats["nnz_trace"][-1]),
                    "tr_passes": it, "tr_walks": triples, "fuzz": w.fuzz, "graph": args.graph,
+                   "r_recipe": "true overlaps >= 1 kbp restricted to the off-diagonal pattern of C",
                    "parallelism": "single GPU"},
         "kernels": kernels,
         "kernels_timed_over": kernels_timed_over,
         "overlap_products_per_s_gpu_time": products / (sum(
-            per_step_ms.get(k, 0) for k in ("keys", "part_count", "part_scatter", "part2_count", "part2_scatter", "bucket_sort",
-                                             "segments", "sym_bits", "sym_hash",
+            per_step_ms.get(k, 0) for k in ("keys", "part_count", "part_scatter", "part2_count", "part2_scatter",
+                                             "bucket_sort", "segments", "sym_bits", "sym_hash",
                                              "numeric_phase" if "numeric_phase" in per_step_ms else "numeric",
                                              "esc")) * 1e-3),
         "overlap_products_per_s_numeric_phase": (products / (dom_ms * 1e-3) if dominant == "numeric_phase" else
@@ -668,6 +728,7 @@ def main():
         "serve": served,
         "cpu_baseline": cpu,
         "cpu_parallel": cpu_par,
+        "wall_s": round(time.perf_counter() - t_start, 1),
     }
     print(json.dumps(out), flush=True)
 

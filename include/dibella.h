@@ -152,6 +152,47 @@ int dibella_transitive_reduce_batched(const dibella_csr* R, int32_t nsets, const
                                       dibella_alloc_fn alloc, dibella_free_fn free_fn,
                                       void* ctx, void* hip_stream);
 
+/*
+ * dibella_r_from_seeds -- overlap graph R from the seeds stored in C
+ * (Sec. IV-E: the reduction's overlap suffix and orientation are derived in
+ * place from the coordinates stored with each read pair; Sec. IV-D: C keeps
+ * two k-mer positions per pair).  It stands between the two products where
+ * the paper aligns and prunes (that alignment is not part of this library).
+ *
+ * C: the output of dibella_overlap (borrowed, never written; col, count and
+ * seed are read) for an A whose
+ * values are (position << 1) | strand, strand = 1 where the read holds the
+ * reverse complement of the canonical k-mer.  read_len: device int32[n],
+ * the length of every read, in [0, 2^28).  k: the k-mer length, 1..32.
+ * For every off-diagonal entry, its first seed (smallest shared k-mer)
+ * places read j in read i's frame by ungapped extension: offset
+ * d = p_i - p_j, or p_i + p_j + k - L_j if the strands differ (the pair is
+ * reverse complementary).  With max_drift >= 0 the second seed must exist
+ * and place the pair in the same relative orientation at an offset within
+ * max_drift bases of d (two k-mers agreeing on the overlap, standing in for
+ * the alignment that prunes C); max_drift < 0 uses the first seed alone.
+ * The overlap [max(0, d), min(L_i, d + L_j)) must
+ * span at least min_overlap bases, else the entry is dropped; with
+ * min_density > 0 the pair must also share at least min_density k-mers per
+ * 10 kbp of that overlap (count * 10000 >= min_density * overlap: a true
+ * overlap shares k-mers all along it, a pair that only shares a repeat does
+ * not).  These tests stand in for the alignment that prunes C.  A contained
+ * overlap is kept with value 0 (the reduction discards it).  Otherwise the
+ * four overlap categories give val = (suffix << 2) | (o_i << 1) | o_j:
+ *   read i first (forward, inner):   suffix d + L_j - L_i, code (0, rc)
+ *   read j first (reverse, outer):   suffix -d,            code (1, 1 - rc)
+ * R is n x n in dibella_transitive_reduce's layout, rows sorted.
+ * Errors: EINVAL for a malformed C (row pointers, column range or order),
+ * a missing seed or one outside its read (position + k > length), a read
+ * length outside [0, 2^28), k outside [1, 32] or min_overlap < 0;
+ * EOVERFLOW if nrows >= 2^31.
+ * Host synchronisation: one stream sync (to size R).
+ */
+int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, int32_t k,
+                         int32_t min_overlap, int32_t max_drift, int32_t min_density,
+                         dibella_csr_out* R, dibella_alloc_fn alloc, dibella_free_fn free_fn,
+                         void* ctx, void* hip_stream);
+
 /* Message of the last nonzero status returned on this host thread. */
 const char* dibella_last_error(void);
 
@@ -216,6 +257,7 @@ int dibella_last_stats(dibella_stats* out);
  *  13 numeric_phase the whole numeric phase of one call, first launch to
  *                   last (its launches overlap on several streams, so the
  *                   sum of the records of label 9 exceeds this)
+ *  14 r_from_seeds  overlap graph from the seeds of C (both passes)
  * Passes run as captured graphs are not timed.  Enabling clears the
  * accumulators; collect waits for the recorded events, returns the summed
  * milliseconds and number of records per label, and clears them. */

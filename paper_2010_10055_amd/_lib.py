@@ -26,11 +26,11 @@ NO_VALIDATE = 0x4
 TR_USE_GRAPH = 0x8
 
 EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batched",
-           "dibella_transitive_reduce_batched", "dibella_last_error", "dibella_get_tuning",
+           "dibella_transitive_reduce_batched", "dibella_r_from_seeds", "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
            "dibella_timing_select", "dibella_timing_collect"]
 PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "part2_count", "part2_scatter", "segments", "sym_bits",
-          "sym_hash", "numeric", "esc", "tr_mark", "tr_compact", "numeric_phase"]
+          "sym_hash", "numeric", "esc", "tr_mark", "tr_compact", "numeric_phase", "r_from_seeds"]
 
 
 class DibellaError(RuntimeError):
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dibella_overlap_batched.argtypes = [P, i32, P, P, ALLOC_FN, FREE_FN, P, P]
     lib.dibella_transitive_reduce.argtypes = [P, i32, u32, P, P, ALLOC_FN, FREE_FN, P, P]
     lib.dibella_transitive_reduce_batched.argtypes = [P, i32, P, u32, P, P, ALLOC_FN, FREE_FN, P, P]
+    lib.dibella_r_from_seeds.argtypes = [P, P, i32, i32, i32, i32, P, ALLOC_FN, FREE_FN, P, P]
     for f in EXPORTS:
         getattr(lib, f).restype = ctypes.c_int
     lib.dibella_last_error.restype = ctypes.c_char_p
@@ -319,6 +320,37 @@ def transitive_reduce(R: CSRTensors, fuzz: int, variant="A", rule="row", graph=F
     S = CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
                    call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
     return S, int(it.value)
+
+
+def r_from_seeds(C: OverlapCSR, read_len: torch.Tensor, k: int, min_overlap: int,
+                 max_drift: int = -1, min_density: int = 0) -> CSRTensors:
+    """Overlap graph R from the first seed of every off-diagonal entry of C
+    (A's values being (position << 1) | strand): the suffix and orientation
+    code by the four overlap categories, pairs overlapping by fewer than
+    min_overlap bases dropped, contained pairs kept with value 0.  With
+    max_drift >= 0 the second seed must agree (same orientation, offset
+    within max_drift bases); with min_density > 0 the pair must share at
+    least min_density k-mers per 10 kbp of its overlap."""
+    dev = C.rowptr.device
+    if read_len.dtype != torch.int32 or not read_len.is_cuda or not read_len.is_contiguous():
+        raise TypeError("read_len must be a contiguous int32 device tensor")
+    if read_len.numel() != C.nrows:
+        raise ValueError("read_len must hold one length per row of C")
+    call = _call_for(dev)
+    for name, t, dt in (("rowptr", C.rowptr, torch.int64), ("col", C.col, torch.int32),
+                        ("count", C.count, torch.int32), ("seed", C.seed, torch.int32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"C.{name} must be a contiguous {dt} device tensor")
+    c = _OverlapOut(C.nrows, C.ncols, C.nnz, C.rowptr.data_ptr(), C.col.data_ptr() if C.nnz else None,
+                    C.count.data_ptr() if C.nnz else None, C.seed.data_ptr() if C.nnz else None)
+    o = _CSROut()
+    with torch.cuda.device(dev):
+        st = lib().dibella_r_from_seeds(ctypes.byref(c), read_len.data_ptr() if C.nrows else None, int(k),
+                                        int(min_overlap), int(max_drift), int(min_density), ctypes.byref(o),
+                                        call.alloc_cb, call.free_cb, None, _stream_handle(dev))
+    _check(st)
+    return CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                      call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
 
 
 def last_stats() -> dict:

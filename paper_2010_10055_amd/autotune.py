@@ -5,7 +5,8 @@ inputs (read count, k-mer entries per read, min_shared, number of sets).
 For a class the tuner runs a coordinate search over the tunable fields of
 dibella_tuning: every candidate configuration is timed on the caller's
 workload (median of a few runs on the device) and must reproduce the
-results of the starting configuration bit for bit, otherwise it is
+results of the starting configuration bit for bit (every output tensor
+equal element by element, every other output value equal), otherwise it is
 rejected.  The best configuration per class is kept in a JSON cache
 (path: $DIBELLA_TUNING_CACHE, else ~/.cache/dibella/tuning.json).
 """
@@ -70,6 +71,52 @@ def save_cache(cache: dict, path: Optional[str] = None) -> None:
     os.replace(tmp, path)
 
 
+def leaves(result) -> list:
+    """Every tensor and plain value in a result, in a fixed order: lists,
+    tuples, dicts and dataclasses (OverlapCSR, CSRTensors) are walked
+    recursively."""
+    import dataclasses
+    out = []
+
+    def walk(x):
+        if isinstance(x, (list, tuple)):
+            for y in x:
+                walk(y)
+        elif isinstance(x, dict):
+            for k in sorted(x):
+                walk(x[k])
+        elif dataclasses.is_dataclass(x) and not isinstance(x, type):
+            for f in dataclasses.fields(x):
+                walk(getattr(x, f.name))
+        else:
+            out.append(x)
+    walk(result)
+    return out
+
+
+def snapshot(result) -> list:
+    """A copy of a result's leaves that later calls cannot overwrite."""
+    return [x.clone() if hasattr(x, "clone") else x for x in leaves(result)]
+
+
+def results_equal(ref: list, result) -> bool:
+    """True if `result` has the same leaves as the snapshot `ref`: tensors of
+    equal dtype, shape and elements, other values equal."""
+    import torch
+    got = leaves(result)
+    if len(got) != len(ref):
+        return False
+    for a, b in zip(ref, got):
+        if isinstance(a, torch.Tensor) or isinstance(b, torch.Tensor):
+            if not (isinstance(a, torch.Tensor) and isinstance(b, torch.Tensor)):
+                return False
+            if a.dtype != b.dtype or a.shape != b.shape or not torch.equal(a, b):
+                return False
+        elif a != b:
+            return False
+    return True
+
+
 def coordinate_search(start: dict, space: Dict[str, Iterable[int]], measure: Callable[[dict], Optional[float]],
                       budget_s: float = 60.0, rounds: int = 2, log: Callable[[str], None] = lambda s: None):
     """Greedy coordinate descent.  measure(cfg) returns seconds, or None if
@@ -101,12 +148,13 @@ def coordinate_search(start: dict, space: Dict[str, Iterable[int]], measure: Cal
     return best, best_t, evals
 
 
-def autotune(run: Callable[[], object], fingerprint: Callable[[object], object], key: str,
-             budget_s: float = 60.0, repeats: int = 3, space: Optional[Dict[str, Iterable[int]]] = None,
-             cache_file: Optional[str] = None, force: bool = False, log: Callable[[str], None] = print) -> dict:
-    """Tune the library for `run` (a callable doing the work on the device)
-    and store the result under `key`.  `fingerprint(result)` must map a result
-    to something comparable: all candidates must match the first one."""
+def autotune(run: Callable[[], object], key: str, budget_s: float = 60.0, repeats: int = 3,
+             space: Optional[Dict[str, Iterable[int]]] = None, cache_file: Optional[str] = None,
+             force: bool = False, log: Callable[[str], None] = print) -> dict:
+    """Tune the library for `run` (a callable doing the work on the device
+    and returning its outputs) and store the result under `key`.  Every
+    candidate's outputs must equal the starting configuration's bit for bit
+    (results_equal), else the candidate is rejected."""
     import torch
     import paper_2010_10055_amd as db
     cache = load_cache(cache_file)
@@ -115,7 +163,7 @@ def autotune(run: Callable[[], object], fingerprint: Callable[[object], object],
         db.set_tuning(**cfg)
         return cfg
     start = db.get_tuning()
-    ref = fingerprint(run())
+    ref = snapshot(run())
     torch.cuda.synchronize()
 
     def measure(cfg):
@@ -124,9 +172,9 @@ def autotune(run: Callable[[], object], fingerprint: Callable[[object], object],
         except Exception:
             return None
         try:
-            got = fingerprint(run())
+            got = run()
             torch.cuda.synchronize()
-            if got != ref:
+            if not results_equal(ref, got):
                 log(f"  rejected {cfg}: results differ")
                 return None
             ts = []

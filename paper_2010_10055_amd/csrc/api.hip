@@ -7,8 +7,8 @@
 namespace dibella {
 int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibella_overlap_out* C,
                 uint32_t flags, Arena& ar);
-int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags, dibella_csr_out* S,
-           int32_t* iterations, Arena& ar);
+int r_from_seeds_run(const dibella_overlap_out* C, const int32_t* read_len, int32_t k, int32_t min_overlap,
+                     int32_t max_drift, int32_t min_density, dibella_csr_out* R, Arena& ar);
 }  // namespace dibella
 
 using namespace dibella;
@@ -82,6 +82,25 @@ int dibella_transitive_reduce_batched(const dibella_csr* R, int32_t nsets, const
             std::memset(&S[s], 0, sizeof(S[s]));
             iterations[s] = 0;
         }
+    return status;
+}
+
+int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, int32_t k, int32_t min_overlap,
+                         int32_t max_drift, int32_t min_density, dibella_csr_out* R, dibella_alloc_fn alloc,
+                         dibella_free_fn free_fn, void* ctx, void* hip_stream) {
+    reset_stats();
+    if (!C || !R || (alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("dibella_r_from_seeds: bad arguments");
+        return DIBELLA_EINVAL;
+    }
+    int status;
+    {
+        Arena ar(alloc, free_fn, ctx, static_cast<hipStream_t>(hip_stream));
+        status = guarded(ar, [&] {
+            return r_from_seeds_run(C, read_len, k, min_overlap, max_drift, min_density, R, ar);
+        });
+    }
+    if (status != DIBELLA_OK) std::memset(R, 0, sizeof(*R));
     return status;
 }
 

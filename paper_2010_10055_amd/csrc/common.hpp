@@ -121,6 +121,22 @@ int stage_done(hipStream_t s);       // record that the current slot has been co
 
 int sync_stream(hipStream_t s);       // hipStreamSynchronize + counter
 
+// A reduction writing into fixed buffers instead of allocating: host
+// staging in `host` (pageable, at least tr_fixed_host_bytes()), S into the
+// caller's arrays (capacity s_cap entries).  One set, no graphs.
+struct TrFixed {
+    void* host;
+    size_t host_bytes;
+    int64_t* s_rowptr;
+    int32_t* s_col;
+    int32_t* s_val;
+    int64_t s_cap;
+};
+int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags, dibella_csr_out* S,
+           int32_t* iterations, Arena& ar, const TrFixed* fixed = nullptr);
+size_t tr_workspace_bytes(int nsets, int64_t total_rows, int64_t total_nnz);
+size_t tr_fixed_host_bytes();
+
 // Streams that let independent launches of one call overlap: begin() makes
 // them wait for the work queued so far on `main`, end() makes `main` wait for
 // everything queued on them.  One set per host thread and device.
@@ -138,9 +154,16 @@ int side_streams(SideStreams** out);
 // Timed kernels (labels of dibella_timing, see the header).
 enum Phase {
     kPhKeys = 0, kPhPartCount, kPhPartScatter, kPhBucketSort, kPhPart2Count, kPhPart2Scatter, kPhSegments,
-    kPhSymBits, kPhSymHash, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact, kPhNumericAll
+    kPhSymBits, kPhSymHash, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact, kPhNumericAll, kPhRFromSeeds
 };
 bool timing_on();
+// While one lives on this host thread, no timing events are created or
+// recorded (for the call that allocates nothing).
+struct TimingPause {
+    TimingPause();
+    ~TimingPause();
+    bool was;
+};
 int timing_begin(int phase, hipStream_t s, int* token);
 int timing_end(int token, hipStream_t s);
 void timing_set_enabled(bool on);
@@ -211,6 +234,11 @@ __device__ __forceinline__ int find_set(const int64_t* base, int nsets, int64_t 
         if (base[mid] <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+__device__ __forceinline__ int32_t wave_or_i32(int32_t v) {
+    for (int d = kWave / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, kWave);
+    return v;
 }
 
 template <class T>

@@ -93,11 +93,6 @@ enum : int32_t {
 constexpr uint64_t kEmpty64 = ~0ull;
 constexpr int kMaxPlanes = 4;
 
-__device__ __forceinline__ int32_t wave_or(int32_t v) {
-    for (int d = kWave / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, kWave);
-    return v;
-}
-
 // Open addressing with linear probing over T slots (any T): the start slot
 // is the high part of (j * golden) * T.
 __device__ __forceinline__ uint32_t hash_slot(int32_t j, uint32_t T) {
@@ -288,7 +283,7 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
             if (rb)
                 for (int b = prev_sl + 1 + lane; b <= sm.count; b += kWave) rb[(int64_t)b * total_rows] = (int32_t)(hi - lo);
         }
-        bad = wave_or(bad);
+        bad = wave_or_i32(bad);
         if (lane == 0 && bad) atomicOr(&flags[s], bad);
     }
 }

@@ -223,6 +223,7 @@ struct TimingRec {
 };
 struct TimingState {
     bool on = false;
+    bool paused = false;
     uint32_t mask = ~0u;   // labels recorded while on (bit i = label i)
     std::vector<TimingRec> recs;
     std::vector<hipEvent_t> pool;
@@ -252,10 +253,13 @@ int take_event(hipEvent_t* e) {
 
 bool timing_on() { return tstate().on; }
 
+TimingPause::TimingPause() : was(tstate().paused) { tstate().paused = true; }
+TimingPause::~TimingPause() { tstate().paused = was; }
+
 int timing_begin(int phase, hipStream_t s, int* token) {
     *token = -1;
     TimingState& t = tstate();
-    if (!t.on || phase < 0 || phase >= 32 || !((t.mask >> phase) & 1u)) return DIBELLA_OK;
+    if (!t.on || t.paused || phase < 0 || phase >= 32 || !((t.mask >> phase) & 1u)) return DIBELLA_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     DB_HIP(hipStreamIsCapturing(s, &cs));
     if (cs != hipStreamCaptureStatusNone) return DIBELLA_OK;

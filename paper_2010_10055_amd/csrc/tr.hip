@@ -71,11 +71,6 @@ __host__ __device__ constexpr size_t tr_mark_lds(int block, int cap) {
     return (size_t)block * 16 + (size_t)cap * 12 + (cap ? (size_t)tr_hash_slots(cap) * 4 : 0) + (size_t)kTrWin * 2;
 }
 
-__device__ __forceinline__ int32_t wave_or32(int32_t v) {
-    for (int d = kWave / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, kWave);
-    return v;
-}
-
 // ---------------------------------------------------------------------------
 // Validation and the contained-overlap drop (wave per row).
 // ---------------------------------------------------------------------------
@@ -109,7 +104,7 @@ __global__ __launch_bounds__(WPB* kWave) void k_tr_validate(const TrSet* __restr
                 if ((v >> 2) > 0) ++kept;
             }
         }
-        bad = wave_or32(bad);
+        bad = wave_or_i32(bad);
         kept = wave_sum(kept);
         if (lane == 0) {
             rowok[g] = bad ? 0 : 1;
@@ -639,13 +634,39 @@ struct GraphHolder {
     }
 };
 
+// Workspace of a reduction call (one reservation; every request fits it).
+size_t tr_workspace_bytes(int nsets, int64_t total_rows, int64_t total_nnz) {
+    auto pad = [](size_t b) { return Arena::padded(b); };
+    size_t est = pad(sizeof(TrSet) * nsets) + 8 * pad(8 * (nsets + 1)) + pad(sizeof(TrState));
+    est += pad(8 * total_rows) + pad(total_rows) + pad(12 * total_rows) + 2 * pad(8 * (total_rows + 1));
+    est += 4 * pad(4 * total_nnz) + pad(total_nnz) + pad(4 * total_nnz);
+    est += 4 * pad(8 * scan_workspace_elems(total_rows + 1)) + 4096;
+    return est;
+}
+
+// Pinned-free staging bytes of a one-set call with fixed buffers.
+size_t tr_fixed_host_bytes() { return sizeof(TrSet) + 2 * sizeof(int64_t) + sizeof(TrState) + 16 + 64; }
+
 int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags, dibella_csr_out* S,
-           int32_t* iterations, Arena& ar) {
+           int32_t* iterations, Arena& ar, const TrFixed* fixed) {
     hipStream_t st = ar.stream();
     const dibella_tuning tn = tuning();
     dibella_stats& stt = stats();
-    std::vector<TrSet> hs(nsets);
-    std::vector<int64_t> base(nsets + 1, 0);
+    if (fixed && (nsets != 1 || (flags & DIBELLA_TR_USE_GRAPH))) {
+        set_error("a reduction into fixed buffers takes one set and no graphs");
+        return DIBELLA_EINVAL;
+    }
+    // one set: descriptors on the stack (no host allocation)
+    TrSet hs_one;
+    int64_t base_one[2] = {0, 0};
+    std::vector<TrSet> hs_many;
+    std::vector<int64_t> base_many;
+    if (nsets > 1) {
+        hs_many.resize(nsets);
+        base_many.assign(nsets + 1, 0);
+    }
+    TrSet* hs = nsets > 1 ? hs_many.data() : &hs_one;
+    int64_t* base = nsets > 1 ? base_many.data() : base_one;
     int64_t total_rows = 0, total_nnz = 0;
     for (int s = 0; s < nsets; ++s) {
         const dibella_csr& r = R[s];
@@ -706,14 +727,8 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
     int32_t* d_flags;
     int64_t* ent_base;
     uint8_t* rowok;
-    {   // one reservation for the call's workspace (allocator calls cost host time each)
-        auto pad = [](size_t b) { return Arena::padded(b); };
-        size_t est = pad(sizeof(TrSet) * nsets) + 8 * pad(8 * (nsets + 1)) + pad(sizeof(TrState));
-        est += pad(8 * total_rows) + pad(total_rows) + pad(12 * total_rows) + 2 * pad(8 * (total_rows + 1));
-        est += 4 * pad(4 * total_nnz) + pad(total_nnz) + pad(4 * total_nnz);
-        est += 4 * pad(8 * scan_workspace_elems(total_rows + 1)) + 4096;
-        DB_TRY(ar.reserve(est));
-    }
+    // one reservation for the call's workspace (allocator calls cost host time each)
+    DB_TRY(ar.reserve(tr_workspace_bytes(nsets, total_rows, total_nnz)));
     DB_TRY(ar.work_n(nsets, &d_sets));
     DB_TRY(ar.work_n(nsets + 1, &d_base));
     DB_TRY(ar.work_n(nsets, &d_flags));
@@ -743,13 +758,22 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
     B.mid_cap = std::max(tn.tr_lds_cap, kSmallCap);
     while (B.mid_cap > kSmallCap && tr_mark_lds(tn.tr_block, B.mid_cap) > kTrLdsLimit) B.mid_cap -= 512;
 
-    HostStage& hst = host_stage();
     const size_t desc_bytes = sizeof(TrSet) * nsets + sizeof(int64_t) * (nsets + 1);
     const size_t back_bytes = sizeof(TrState) + (sizeof(int32_t) * 2 + sizeof(int64_t)) * nsets;
-    DB_TRY(hst.reserve(desc_bytes + back_bytes + 64));
-    char* hbuf = static_cast<char*>(hst.ptr);
-    std::memcpy(hbuf, hs.data(), sizeof(TrSet) * nsets);
-    std::memcpy(hbuf + sizeof(TrSet) * nsets, base.data(), sizeof(int64_t) * (nsets + 1));
+    char* hbuf;
+    if (fixed) {   // pageable caller memory: the copies below complete before they return
+        if (fixed->host_bytes < desc_bytes + back_bytes + 64) {
+            set_error("internal: fixed host staging too small");
+            return DIBELLA_EDEVICE;
+        }
+        hbuf = static_cast<char*>(fixed->host);
+    } else {
+        HostStage& hst = host_stage();
+        DB_TRY(hst.reserve(desc_bytes + back_bytes + 64));
+        hbuf = static_cast<char*>(hst.ptr);
+    }
+    std::memcpy(hbuf, hs, sizeof(TrSet) * nsets);
+    std::memcpy(hbuf + sizeof(TrSet) * nsets, base, sizeof(int64_t) * (nsets + 1));
     DB_HIP(hipMemcpyAsync(d_sets, hbuf, sizeof(TrSet) * nsets, hipMemcpyHostToDevice, st));
     DB_HIP(hipMemcpyAsync(d_base, hbuf + sizeof(TrSet) * nsets, sizeof(int64_t) * (nsets + 1),
                           hipMemcpyHostToDevice, st));
@@ -863,16 +887,26 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
     // ---- outputs
     for (int s = 0; s < nsets; ++s) {
         const int64_t nz = h_state->pass > 0 ? h_set_nnz[s] : 0;
-        DB_TRY(ar.output_n(R[s].nrows + 1, &hs[s].s_rowptr));
-        DB_TRY(ar.output_n(nz, &hs[s].s_col));
-        DB_TRY(ar.output_n(nz, &hs[s].s_val));
+        if (fixed) {
+            if (nz > fixed->s_cap) {   // cannot happen while the capacity holds nnz(R)
+                set_error("internal: S exceeds the given capacity");
+                return DIBELLA_EDEVICE;
+            }
+            hs[s].s_rowptr = fixed->s_rowptr;
+            hs[s].s_col = nz ? fixed->s_col : nullptr;
+            hs[s].s_val = nz ? fixed->s_val : nullptr;
+        } else {
+            DB_TRY(ar.output_n(R[s].nrows + 1, &hs[s].s_rowptr));
+            DB_TRY(ar.output_n(nz, &hs[s].s_col));
+            DB_TRY(ar.output_n(nz, &hs[s].s_val));
+        }
         S[s].nnz = nz;
         S[s].rowptr = hs[s].s_rowptr;
         S[s].col = hs[s].s_col;
         S[s].val = hs[s].s_val;
         iterations[s] = h_iters[s];
     }
-    std::memcpy(hbuf, hs.data(), sizeof(TrSet) * nsets);
+    std::memcpy(hbuf, hs, sizeof(TrSet) * nsets);
     DB_HIP(hipMemcpyAsync(d_sets, hbuf, sizeof(TrSet) * nsets, hipMemcpyHostToDevice, st));
     int64_t total_out = 0;
     for (int s = 0; s < nsets; ++s) total_out += S[s].nnz;
@@ -884,7 +918,7 @@ int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags,
         hipLaunchKernelGGL(k_tr_out_entries, dim3(grid_for(total_out, 256, 8192)), dim3(256), 0, st, d_sets, nsets,
                            ent_base, total_out, B.ci[res], B.va[res]);
     DB_HIP(hipGetLastError());
-    DB_TRY(stage_done(st));
+    if (!fixed) DB_TRY(stage_done(st));
     return DIBELLA_OK;
 }
 

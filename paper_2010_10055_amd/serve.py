@@ -1,29 +1,34 @@
-"""Serving loop for layout jobs: overlap, then reduction, on one GPU.
+"""Serving loop for layout jobs: overlap, overlap graph, reduction, on one GPU.
 
-A job is one read set: C = A A^T, an overlap graph R built on the device
-from C, then S = TR(R).  Building R stands in for the pairwise alignment and
-pruning that sit between the two products in the paper's pipeline (out of
-scope here): an entry of C is kept if the two reads truly overlap by at
-least `min_overlap` bases, with overhang and orientation taken from the
-true read coordinates (the same rule as the generator's overlap graph).
+A job is one read set: C = A A^T, the overlap graph R built on the device
+from C's seeds (dibella_r_from_seeds: suffix and orientation from the first
+stored seed; the second seed's agreement and the density of shared k-mers
+along the overlap stand in for the alignment that prunes C in the paper's
+pipeline), then S = TR(R).  C, R and S stay on the device between the stages.
 
-Scheduling is continuous batching: jobs arrive over time (Poisson), wait in
-a queue, and whenever the executor is free it takes every waiting job that
-fits the HBM budget (estimated footprint of A, its transpose and sort
-buffers, C, R and scratch) up to `max_batch`, and runs them as one batched
-overlap call and one batched reduction call.  Jobs arriving meanwhile join
-the next step.  A job whose footprint exceeds the whole budget is rejected
-on its own.  `max_batch = 1` with plain calls is the FIFO baseline.
+Scheduling is continuous batching over `slots` execution slots.  Each slot
+is a host thread with its own HIP stream, so the work of admitted jobs
+overlaps on the device (the library is thread-safe per stream).  Jobs arrive
+over time (Poisson) and wait in a queue; whenever a slot is idle, the first
+waiting job (in arrival order) whose estimated footprint (A, its transpose
+and sort buffers, C, R and scratch) fits the HBM budget still unreserved is
+admitted on it.  The budget is the measured free device memory at the start
+of the run (or less, if the caller says so).  A job whose footprint exceeds
+the whole budget fails alone.  A job that arrives while others run starts as
+soon as a slot and memory allow, not when the running ones have finished.
+One slot is the FIFO baseline (a queue alone, one job on the device at a
+time), on the same scheduler and trace.
 
-The scheduler only needs an executor (run a list of jobs, return their
-results) and a clock, so it is tested on the CPU with a fake executor and a
-virtual clock.
+The scheduler needs an executor (submit a job to a slot; wait for finished
+jobs) and a clock, so it is tested on the CPU with a virtual-time executor
+and a virtual clock.
 """
 from __future__ import annotations
 
 import dataclasses
-import heapq
 import math
+import queue as _queue
+import threading
 import time
 from typing import Callable, List, Optional, Sequence
 
@@ -45,9 +50,10 @@ class Done:
     arrival: float
     start: float
     finish: float
-    batch: int
+    slot: int
     result: object = None
     error: Optional[str] = None
+    kind: str = "job"
 
     @property
     def latency(self) -> float:
@@ -98,162 +104,240 @@ class VirtualClock:
         self.t += dt
 
 
-def serve(jobs: Sequence[Job], execute: Callable[[List[Job]], List[object]], clock, hbm_budget: int,
-          max_batch: int = 64) -> List[Done]:
-    """Run `jobs` (sorted by arrival) through the continuous-batching loop.
-    execute(batch) runs a batch and returns one result per job (an exception
-    fails the whole batch, which is then retried job by job so that a bad job
-    fails alone)."""
+def serve(jobs: Sequence[Job], executor, clock, hbm_budget: int, slots: int = 4,
+          stats: Optional[dict] = None) -> List[Done]:
+    """Run `jobs` through continuous admission over `slots` slots.
+
+    executor.submit(job, slot) starts a job; executor.wait(timeout) blocks
+    until at least one job has finished or `timeout` seconds have passed
+    (None: until a job finishes) and returns [(jid, result, error, finish)]
+    for the finished ones.  `stats`, if given, receives the peak reserved
+    footprint and the peak number of jobs running at once."""
     order = sorted(jobs, key=lambda j: j.arrival)
-    queue: List[Job] = []
+    waiting: List[Job] = []
     done: List[Done] = []
+    idle = list(range(slots))
+    running = {}   # jid -> (job, slot, start)
+    reserved = 0
+    peak_reserved = peak_running = 0
     nxt = 0
-    nbatch = 0
-    while nxt < len(order) or queue:
+    while nxt < len(order) or waiting or running:
         now = clock.now()
         while nxt < len(order) and order[nxt].arrival <= now:
-            queue.append(order[nxt])
+            waiting.append(order[nxt])
             nxt += 1
-        if not queue:
-            clock.wait_until(order[nxt].arrival)
-            continue
-        batch: List[Job] = []
-        used = 0
+        # admission in arrival order: the first waiting jobs that fit a slot
+        # and the unreserved budget start now
         rest: List[Job] = []
-        for j in queue:
+        for j in waiting:
             if j.footprint > hbm_budget:
-                done.append(Done(j.jid, j.arrival, now, now, -1, None, "footprint exceeds the HBM budget"))
-            elif len(batch) < max_batch and used + j.footprint <= hbm_budget:
-                batch.append(j)
-                used += j.footprint
+                done.append(Done(j.jid, j.arrival, now, now, -1, None, "footprint exceeds the HBM budget", j.kind))
+            elif idle and reserved + j.footprint <= hbm_budget:
+                slot = idle.pop(0)
+                reserved += j.footprint
+                running[j.jid] = (j, slot, now)
+                executor.submit(j, slot)
             else:
                 rest.append(j)
-        queue = rest
-        if not batch:
-            continue
-        start = clock.now()
-        try:
-            results = execute(batch)
-            outcome = [(r, None) for r in results]
-        except Exception as ex:  # fall back to one job at a time
-            outcome = []
-            for j in batch:
-                try:
-                    outcome.append((execute([j])[0], None))
-                except Exception as ex1:
-                    outcome.append((None, f"{type(ex1).__name__}: {ex1}"))
-        finish = clock.now()
-        for j, (r, err) in zip(batch, outcome):
-            done.append(Done(j.jid, j.arrival, start, finish, nbatch, r, err))
-        nbatch += 1
+        waiting = rest
+        peak_reserved = max(peak_reserved, reserved)
+        peak_running = max(peak_running, len(running))
+        timeout = max(0.0, order[nxt].arrival - now) if nxt < len(order) else None
+        if running:
+            for jid, result, error, finish in executor.wait(timeout):
+                j, slot, start = running.pop(jid)
+                reserved -= j.footprint
+                idle.append(slot)
+                done.append(Done(jid, j.arrival, start, finish, slot, result, error, j.kind))
+        elif timeout is not None:
+            clock.wait_until(order[nxt].arrival)
+        else:   # nothing runs and nothing arrives: every waiting job was admitted or failed
+            assert not waiting
+    if stats is not None:
+        stats.update(peak_reserved=peak_reserved, peak_running=peak_running)
     return done
 
 
 def summarize(done: Sequence[Done], wall: float) -> dict:
     ok = [d for d in done if d.error is None]
     lat = np.array([d.latency for d in ok]) if ok else np.zeros(1)
-    return {"jobs": len(done), "ok": len(ok), "failed": len(done) - len(ok),
-            "jobs_per_s": len(ok) / wall if wall > 0 else float("inf"),
-            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_ms": float(lat.mean() * 1e3), "batches": len({d.batch for d in ok}),
-            "wall_s": wall}
+    out = {"jobs": len(done), "ok": len(ok), "failed": len(done) - len(ok),
+           "jobs_per_s": len(ok) / wall if wall > 0 else float("inf"),
+           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "mean_ms": float(lat.mean() * 1e3), "wall_s": wall}
+    kinds = sorted({d.kind for d in ok})
+    if len(kinds) > 1:
+        for k in kinds:
+            lk = np.array([d.latency for d in ok if d.kind == k])
+            out[f"p50_ms_{k}"] = float(np.percentile(lk, 50) * 1e3)
+            out[f"p99_ms_{k}"] = float(np.percentile(lk, 99) * 1e3)
+    return out
+
+
+class VirtualExecutor:
+    """Executor on a virtual clock (for the scheduler's CPU tests): a job
+    runs `run(payload)` at once and finishes `duration(job, running)` seconds
+    after its start, `running` being the number of jobs already running when
+    it starts; a job whose id is in `fail_ids` raises."""
+
+    def __init__(self, clock: VirtualClock, run: Callable, duration: Callable, fail_ids=()):
+        self.clock, self.run, self.duration, self.fail_ids = clock, run, duration, set(fail_ids)
+        self.pending = []   # (finish, seq, jid, result, error)
+        self.submitted = []  # (jid, slot, start)
+        self.seq = 0
+
+    def submit(self, job: Job, slot: int) -> None:
+        t = self.clock.now()
+        self.submitted.append((job.jid, slot, t))
+        try:
+            if job.jid in self.fail_ids:
+                raise RuntimeError("bad job")
+            res, err = self.run(job.payload), None
+        except Exception as ex:
+            res, err = None, f"{type(ex).__name__}: {ex}"
+        self.pending.append((t + self.duration(job, len(self.pending)), self.seq, job.jid, res, err))
+        self.seq += 1
+
+    def wait(self, timeout):
+        if not self.pending:
+            return []
+        first = min(self.pending)
+        deadline = math.inf if timeout is None else self.clock.now() + timeout
+        if first[0] > deadline:
+            self.clock.wait_until(deadline)
+            return []
+        self.clock.wait_until(first[0])
+        out = [p for p in self.pending if p[0] <= self.clock.now()]
+        self.pending = [p for p in self.pending if p[0] > self.clock.now()]
+        return [(jid, res, err, fin) for fin, _, jid, res, err in sorted(out)]
 
 
 # ---------------------------------------------------------------------------
-# GPU executor
+# GPU side
 # ---------------------------------------------------------------------------
 
 @dataclasses.dataclass
 class LayoutInputs:
-    """Device-resident inputs of one layout job."""
-    A: object                # CSRTensors
-    start: object            # int64 device tensor: true read starts
-    end: object              # int64 device tensor: true read ends
-    strand: object           # int64 device tensor: 0/1
+    """Device-resident inputs of one layout job (A with strand bits in its
+    values, read lengths) and its parameters; host copies for checking."""
+    A: object                # CSRTensors, values (position << 1) | strand
+    read_len: object         # int32 device tensor
+    k: int
     min_shared: int
-    fuzz: int
     min_overlap: int
+    max_drift: int
+    min_density: int
+    fuzz: int
+    host_A: object = None    # synth.CSR (for the oracle in tests)
+    host_len: object = None  # numpy int32
 
 
-def build_r_from_c(C, start, end, strand, min_overlap: int):
-    """Overlap graph from the candidate matrix C on the device (stand-in for
-    alignment + pruning): off-diagonal entries of C whose reads truly overlap
-    by >= min_overlap bases, packed (overhang << 2) | (o_src << 1) | o_dst as
-    in the generator (contained pairs get overhang 0)."""
-    import torch
+def density_threshold(error_rate: float, k: int, fraction: float = 0.4) -> int:
+    """Shared k-mers per 10 kbp a pair must reach: `fraction` of the rate at
+    which two reads with independent errors at `error_rate` share the k-mers
+    of a true overlap (a k-mer is shared where both reads hold it without
+    error: (1 - e)^(2k) per position)."""
+    return max(1, int(round(fraction * 10000 * (1.0 - error_rate) ** (2 * k))))
+
+
+def run_layout(inp: LayoutInputs):
+    """One job on the current stream: C = A A^T, R from C's seeds, S = TR(R).
+    Returns (C, R, S, passes); everything stays on the device."""
     import paper_2010_10055_amd as db
-    dev = C.col.device
-    n = C.nrows
-    counts = C.rowptr[1:] - C.rowptr[:-1]
-    r = torch.repeat_interleave(torch.arange(n, device=dev), counts)
-    c = C.col.to(torch.int64)
-    sr, er, orr = start[r], end[r], strand[r]
-    sc, ec, oc = start[c], end[c], strand[c]
-    ov = torch.minimum(er, ec) - torch.maximum(sr, sc)
-    keep = (r != c) & (ov >= min_overlap)
-    # r is the left read of the pair if it sorts first by (start, -end, index)
-    r_left = (sr < sc) | ((sr == sc) & ((er > ec) | ((er == ec) & (r < c))))
-    contained = torch.where(r_left, ec <= er, er <= ec)
-    oh = torch.where(r_left, ec - er, sr - sc)
-    oh = torch.where(contained, torch.zeros_like(oh), oh)
-    o_src = torch.where(r_left, orr, 1 - orr)
-    o_dst = torch.where(r_left, oc, 1 - oc)
-    val = ((oh << 2) | (o_src << 1) | o_dst).to(torch.int32)
-    r, c, val = r[keep], c[keep], val[keep]
-    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
-    rowptr[1:] = torch.cumsum(torch.bincount(r, minlength=n), 0)
-    return db.CSRTensors(n, n, rowptr, c.to(torch.int32), val)
+    C = db.overlap(inp.A, inp.min_shared)
+    R = db.r_from_seeds(C, inp.read_len, inp.k, inp.min_overlap, inp.max_drift, inp.min_density)
+    S, it = db.transitive_reduce(R, inp.fuzz)
+    return C, R, S, it
 
 
-def gpu_executor(batched: bool = True, graph: bool = False):
-    """execute(batch) for the GPU: overlap of all jobs, R on the device, then
-    the reduction of all jobs; batched calls when `batched`, else one job at
-    a time with plain calls.  Results: (C, S, passes) per job."""
+def hbm_free_bytes(device: str = "cuda:0") -> int:
+    """Device memory a run can still use: free memory plus what PyTorch's
+    caching allocator holds without using."""
     import torch
-    import paper_2010_10055_amd as db
-
-    def execute(batch: List[Job]):
-        ins = [j.payload for j in batch]
-        if batched and len(ins) > 1:
-            Cs = db.overlap_batched([x.A for x in ins], [x.min_shared for x in ins])
-            Rs = [build_r_from_c(C, x.start, x.end, x.strand, x.min_overlap) for C, x in zip(Cs, ins)]
-            Ss, its = db.transitive_reduce_batched(Rs, [x.fuzz for x in ins], graph=graph)
-        else:
-            Cs, Ss, its = [], [], []
-            for x in ins:
-                C = db.overlap(x.A, x.min_shared)
-                R = build_r_from_c(C, x.start, x.end, x.strand, x.min_overlap)
-                S, it = db.transitive_reduce(R, x.fuzz, graph=graph)
-                Cs.append(C)
-                Ss.append(S)
-                its.append(it)
-        torch.cuda.synchronize()
-        return list(zip(Cs, Ss, its))
-
-    return execute
+    free, _ = torch.cuda.mem_get_info(device)
+    return int(free + torch.cuda.memory_reserved(device) - torch.cuda.memory_allocated(device))
 
 
-def make_pool(kinds: Sequence[tuple], device: str = "cuda:0", log=lambda s: None):
+class GpuSlots:
+    """Executor with one host thread and one HIP stream (default priority)
+    per slot.  A worker runs its job on its stream, waits for that stream
+    only, and reports the finish time; results are kept only if asked
+    (config-3-sized results are gigabytes each)."""
+
+    def __init__(self, slots: int, clock, run: Callable = run_layout, keep_results: bool = False,
+                 device: str = "cuda:0"):
+        import torch
+        self.clock, self.run, self.keep, self.device = clock, run, keep_results, torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.inbox = [_queue.Queue() for _ in range(slots)]
+        self.finished = _queue.Queue()
+        self.threads = [threading.Thread(target=self._worker, args=(k,), daemon=True) for k in range(slots)]
+        for t in self.threads:
+            t.start()
+
+    def _worker(self, k: int) -> None:
+        import torch
+        s = self.streams[k]
+        while True:
+            job = self.inbox[k].get()
+            if job is None:
+                return
+            res = err = None
+            try:
+                with torch.cuda.device(self.device), torch.cuda.stream(s):
+                    res = self.run(job.payload)
+                s.synchronize()
+            except Exception as ex:
+                err = f"{type(ex).__name__}: {ex}"
+                try:
+                    s.synchronize()
+                except Exception:
+                    pass
+            fin = self.clock.now()
+            self.finished.put((job.jid, res if self.keep else None, err, fin))
+
+    def submit(self, job: Job, slot: int) -> None:
+        self.inbox[slot].put(job)
+
+    def wait(self, timeout):
+        try:
+            out = [self.finished.get(timeout=timeout)]
+        except _queue.Empty:
+            return []
+        while True:
+            try:
+                out.append(self.finished.get_nowait())
+            except _queue.Empty:
+                return out
+
+    def close(self) -> None:
+        for q in self.inbox:
+            q.put(None)
+        for t in self.threads:
+            t.join()
+
+
+def make_pool(kinds: Sequence[tuple], device: str = "cuda:0", min_overlap=None, max_drift: int = 150,
+              keep_host: bool = False, log=lambda s: None):
     """Pre-generated device-resident instances: kinds = [(name, count,
-    seed0, scale)] with workload names of the generator."""
+    seed0, scale)] with workload names of the generator, built with strand
+    bits in A's values.  Returns [(name, LayoutInputs, footprint)]."""
     import torch
     import paper_2010_10055_amd as db
     from . import synth
     pool = []
     for name, count, seed0, scale in kinds:
         for q in range(count):
-            w = synth.make_workload(name, seed=seed0 + q, device=device, scale=scale)
-            rd = w.reads
-            mo = 1 if name == "tiny" else 1000
-            est_r = int(2 * 40 * rd.n)
-            inp = LayoutInputs(db.CSRTensors.from_numpy(w.A, device),
-                               torch.as_tensor(rd.start, device=device),
-                               torch.as_tensor(rd.end, device=device),
-                               torch.as_tensor(rd.strand.astype(np.int64), device=device),
-                               w.min_shared, w.fuzz, mo)
-            fp = footprint_bytes(w.A.nrows, w.A.nnz, synth.overlap_products(w.A), w.min_shared, est_r)
+            w = synth.make_workload(name, seed=seed0 + q, device=device, scale=scale, strand_bit=True)
+            lens = np.diff(w.reads.offsets).astype(np.int32)
+            mo = (1 if name == "tiny" else 1000) if min_overlap is None else min_overlap
+            inp = LayoutInputs(db.CSRTensors.from_numpy(w.A, device), torch.as_tensor(lens, device=device),
+                               w.k, w.min_shared, mo, max_drift, density_threshold(w.error_rate, w.k), w.fuzz,
+                               w.A if keep_host else None, lens if keep_host else None)
+            fp = footprint_bytes(w.A.nrows, w.A.nnz, synth.overlap_products(w.A), w.min_shared, 80 * w.A.nrows)
             pool.append((name, inp, fp))
-            log(f"  pool {name}#{q}: reads {w.A.nrows}, nnz(A) {w.A.nnz}, footprint {fp / 2**20:.1f} MiB")
+            log(f"  pool {name}#{q}: reads {w.A.nrows}, nnz(A) {w.A.nnz}, footprint {fp / 2**30:.2f} GiB")
+            del w
     return pool
 
 

@@ -356,6 +356,31 @@ def overlap_graph(start: np.ndarray, end: np.ndarray, strand: np.ndarray, *,
     return coo_to_csr(n, n, rows, cols, vals)
 
 
+def restrict_to_pattern(R: CSR, rowptr, col, device: str = "cpu") -> CSR:
+    """The entries of R whose (row, column) also appears in the pattern
+    (rowptr, col) of another n x n matrix, off the diagonal: the overlap
+    graph of the true coordinates restricted to the candidate pairs, i.e.
+    what a perfect aligner keeps of the candidates (a set intersection of
+    two given patterns; nothing of the products is computed here)."""
+    import torch
+    dev = torch.device(device)
+    n = R.nrows
+    rp = torch.as_tensor(np.asarray(R.rowptr), device=dev)
+    rr = torch.repeat_interleave(torch.arange(n, device=dev), rp[1:] - rp[:-1])
+    rkey = rr * n + torch.as_tensor(np.asarray(R.col), device=dev).to(torch.int64)
+    crp = torch.as_tensor(rowptr, device=dev).to(torch.int64)
+    cr = torch.repeat_interleave(torch.arange(n, device=dev), crp[1:] - crp[:-1])
+    cc = torch.as_tensor(col, device=dev).to(torch.int64)
+    off = cr != cc
+    ckey = cr[off] * n + cc[off]
+    keep = torch.isin(rkey, ckey)
+    rows = rr[keep]
+    out_rp = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    out_rp[1:] = torch.cumsum(torch.bincount(rows, minlength=n), 0)
+    kp = keep.cpu().numpy()
+    return CSR(n, n, out_rp.cpu().numpy(), np.asarray(R.col)[kp], np.asarray(R.val)[kp])
+
+
 def coo_to_csr(nrows: int, ncols: int, rows, cols, vals) -> CSR:
     rows = np.asarray(rows, np.int64)
     cols = np.asarray(cols, np.int64)
@@ -449,6 +474,7 @@ class Workload:
     lo: int
     hi: int
     genome_len: int
+    error_rate: float = 0.0
 
 
 def _families_to_cover(rng, genome_len, fraction, unit_range, div_range, copies_range):
@@ -514,7 +540,7 @@ def make_workload(name: str, seed: Optional[int] = None, device: str = "cpu",
     R = overlap_graph(reads.start, reads.end, reads.strand,
                       min_overlap=p["min_overlap"], policy=policy)
     return Workload(name, reads, A, R, p["min_shared"], p["fuzz"], K_DEFAULT,
-                    p["lo"], p["hi"], G)
+                    p["lo"], p["hi"], G, p["err"])
 
 
 def batch_workloads(count: int = 64, seed: int = 4000, device: str = "cpu",
