@@ -193,6 +193,29 @@ int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, 
                          dibella_csr_out* R, dibella_alloc_fn alloc, dibella_free_fn free_fn,
                          void* ctx, void* hip_stream);
 
+/*
+ * dibella_transitive_reduce_noalloc -- dibella_transitive_reduce for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  It makes no device or pinned host
+ * allocation: its workspace is a static device array of 64 MiB that every
+ * GPU the library runs on holds until the process ends, and S goes into the
+ * caller's arrays.  Same semantics, flags and errors as
+ * dibella_transitive_reduce for one set, plus:
+ *   s_rowptr: int64[nrows + 1]; s_col, s_val: int32[s_capacity] with
+ *   s_capacity >= nnz(R) (S never has more entries than R); on return
+ *   *s_nnz = nnz(S) and *iterations = passes.
+ *   EINVAL if the capacity is below nnz(R), if DIBELLA_TR_USE_GRAPH is set
+ *   (instantiating a graph allocates), or if R needs more than the 64 MiB of
+ *   workspace (about 21 bytes per entry and 37 per row).
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU
+ * (different streams or host threads) race and must be serialised by the
+ * caller.  No timing records are taken during the call.
+ */
+int dibella_transitive_reduce_noalloc(const dibella_csr* R, int32_t fuzz, uint32_t flags,
+                                      int64_t* s_rowptr, int32_t* s_col, int32_t* s_val,
+                                      int64_t s_capacity, int64_t* s_nnz, int32_t* iterations,
+                                      void* hip_stream);
+
 /* Message of the last nonzero status returned on this host thread. */
 const char* dibella_last_error(void);
 

@@ -26,7 +26,8 @@ NO_VALIDATE = 0x4
 TR_USE_GRAPH = 0x8
 
 EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batched",
-           "dibella_transitive_reduce_batched", "dibella_r_from_seeds", "dibella_last_error", "dibella_get_tuning",
+           "dibella_transitive_reduce_batched", "dibella_r_from_seeds", "dibella_transitive_reduce_noalloc",
+           "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
            "dibella_timing_select", "dibella_timing_collect"]
 PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "part2_count", "part2_scatter", "segments", "sym_bits",
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dibella_transitive_reduce.argtypes = [P, i32, u32, P, P, ALLOC_FN, FREE_FN, P, P]
     lib.dibella_transitive_reduce_batched.argtypes = [P, i32, P, u32, P, P, ALLOC_FN, FREE_FN, P, P]
     lib.dibella_r_from_seeds.argtypes = [P, P, i32, i32, i32, i32, P, ALLOC_FN, FREE_FN, P, P]
+    lib.dibella_transitive_reduce_noalloc.argtypes = [P, i32, u32, P, P, P, ctypes.c_int64, P, P, P]
     for f in EXPORTS:
         getattr(lib, f).restype = ctypes.c_int
     lib.dibella_last_error.restype = ctypes.c_char_p

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdibella.so")
-SOURCES = ["runtime.hip", "overlap.hip", "tr.hip", "rseeds.hip", "api.hip"]
+SOURCES = ["runtime.hip", "overlap.hip", "tr.hip", "rseeds.hip", "noalloc.hip", "api.hip"]
 ARCH = os.environ.get("DIBELLA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + os.path.join(ROOT, "include"),
          "-Wall", "-Wno-unused-function",
