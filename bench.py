@@ -465,20 +465,26 @@ def batch_compare(db, synth, nsets: int, steps: int, tune_budget: float = 0.0):
             "tuning": tuned}
 
 
-def serve_compare(njobs: int, slots: int = 3, seed: int = 5000):
+def serve_compare(w_main, njobs: int, slots: int = 3, seed: int = 5000):
     """Serving: Poisson streams of layout jobs (overlap, R from C's seeds on
     the device, reduction): 90% of the jobs one of two instances of the
-    large workload's recipe (50 Mbp genome, 40x, ~167k reads), 10% of the
-    tiny one, all device resident.  FIFO (one slot: one job on the device at
+    large workload's recipe (50 Mbp genome, 40x, ~167k reads: the timed
+    step's reads and one more seed), 10% of the tiny one, all device
+    resident, A with strand bits.  FIFO (one slot: one job on the device at
     a time) and continuous batching (`slots` slots, each a host thread with
     its own stream) replay the same trace, at 0.8x the FIFO capacity
     measured on a probe (latency) and at 1.5x (saturation: throughput).
     Admission budget: the free device memory measured before the runs."""
+    import dataclasses
     import numpy as np
     import torch
-    from paper_2010_10055_amd import serve
+    from paper_2010_10055_amd import serve, synth
     t0 = time.perf_counter()
-    pool = serve.make_pool([("large", 2, seed, 1.0), ("tiny", 4, seed + 100, 1.0)], device="cuda:0", log=log)
+    A1, _ = synth.kmer_matrix(w_main.reads, w_main.k, w_main.lo, w_main.hi, device="cuda:0", strand_bit=True)
+    pool = [serve.pool_entry(dataclasses.replace(w_main, A=A1), "cuda:0")]
+    del A1
+    log(f"  pool {w_main.name}#0 from the timed step's reads: footprint {pool[0][2] / 2**30:.2f} GiB")
+    pool += serve.make_pool([(w_main.name, 1, seed, 1.0), ("tiny", 4, seed + 100, 1.0)], device="cuda:0", log=log)
     log(f"  serve pool {time.perf_counter() - t0:.1f} s")
     torch.cuda.empty_cache()
     budget = serve.hbm_free_bytes()
@@ -497,9 +503,13 @@ def serve_compare(njobs: int, slots: int = 3, seed: int = 5000):
         service = (time.perf_counter() - t0) / len(probe)
     finally:
         fifo.close()
+    # work budget: one job that fills the GPU plus small ones beside it
+    work_cap = int(1.25 * max(p[3] for p in pool))
     out = {"jobs": njobs, "slots": slots, "fifo_service_ms": round(service * 1e3, 2),
-           "hbm_budget_gib": round(budget / 2**30, 1),
-           "job_mix": "90% large recipe (2 instances, 50 Mbp, 40x), 10% tiny (4 instances)"}
+           "hbm_budget_gib": round(budget / 2**30, 1), "work_cap_products": work_cap,
+           "job_mix": f"90% {w_main.name} recipe (2 instances), 10% tiny (4 instances); R from C's seeds",
+           "r_from_seeds": {"min_overlap": pool[0][1].min_overlap, "max_drift": pool[0][1].max_drift,
+                            "min_density_per_10kbp": pool[0][1].min_density}}
     for label, factor in (("load_0.8", 0.8), ("load_1.5", 1.5)):
         rate = factor / service
         jobs = serve.draw_jobs(np.random.default_rng(seed + 1), pool, njobs, rate=rate)
@@ -508,8 +518,15 @@ def serve_compare(njobs: int, slots: int = 3, seed: int = 5000):
             clock = serve.WallClock()
             ex = serve.GpuSlots(nslots, clock)
             st = {}
+            count = [0]
+
+            def progress(d, count=count, name=name):
+                count[0] += 1
+                if count[0] % 30 == 0:
+                    log(f"    {label} {name}: {count[0]} jobs done at {clock.now():.1f} s")
             try:
-                done = serve.serve(jobs, ex, clock, hbm_budget=budget, slots=nslots, stats=st)
+                done = serve.serve(jobs, ex, clock, hbm_budget=budget, slots=nslots, stats=st, on_done=progress,
+                                   work_cap=work_cap)
             finally:
                 ex.close()
             s = serve.summarize(done, clock.now())
@@ -697,7 +714,7 @@ def main():
         log(f"serving comparison ({args.serve_jobs} jobs per run) ...")
         del A, R
         torch.cuda.empty_cache()
-        served = serve_compare(args.serve_jobs, args.serve_slots)
+        served = serve_compare(w, args.serve_jobs, args.serve_slots)
 
     out = {
         "metric": "semiring products/s (A*A^T multiplies + transitive-reduction walks)",

@@ -12,9 +12,13 @@ overlaps on the device (the library is thread-safe per stream).  Jobs arrive
 over time (Poisson) and wait in a queue; whenever a slot is idle, the first
 waiting job (in arrival order) whose estimated footprint (A, its transpose
 and sort buffers, C, R and scratch) fits the HBM budget still unreserved is
-admitted on it.  The budget is the measured free device memory at the start
-of the run (or less, if the caller says so).  A job whose footprint exceeds
-the whole budget fails alone.  A job that arrives while others run starts as
+admitted on it, if its estimated work (semiring products) also fits the work
+budget beside the jobs already running.  The HBM budget is the measured free
+device memory at the start of the run (or less, if the caller says so).  The
+work budget keeps jobs that each fill the GPU from running side by side,
+where they only slow each other down, while small jobs still run beside
+them.  A job whose footprint exceeds the whole HBM budget fails alone; a job
+above the work budget runs when nothing else does.  A job that arrives while others run starts as
 soon as a slot and memory allow, not when the running ones have finished.
 One slot is the FIFO baseline (a queue alone, one job on the device at a
 time), on the same scheduler and trace.
@@ -42,6 +46,7 @@ class Job:
     payload: object         # executor-specific inputs
     footprint: int          # estimated device bytes while running
     kind: str = "job"
+    work: int = 0           # estimated device work (semiring products)
 
 
 @dataclasses.dataclass
@@ -105,20 +110,23 @@ class VirtualClock:
 
 
 def serve(jobs: Sequence[Job], executor, clock, hbm_budget: int, slots: int = 4,
-          stats: Optional[dict] = None) -> List[Done]:
-    """Run `jobs` through continuous admission over `slots` slots.
+          stats: Optional[dict] = None, on_done: Optional[Callable[[Done], None]] = None,
+          work_cap: Optional[int] = None) -> List[Done]:
+    """Run `jobs` through continuous admission over `slots` slots (work_cap:
+    the most estimated work running at once; None = no limit).
 
     executor.submit(job, slot) starts a job; executor.wait(timeout) blocks
     until at least one job has finished or `timeout` seconds have passed
     (None: until a job finishes) and returns [(jid, result, error, finish)]
     for the finished ones.  `stats`, if given, receives the peak reserved
-    footprint and the peak number of jobs running at once."""
+    footprint and the peak number of jobs running at once; `on_done` is
+    called with every finished job."""
     order = sorted(jobs, key=lambda j: j.arrival)
     waiting: List[Job] = []
     done: List[Done] = []
     idle = list(range(slots))
     running = {}   # jid -> (job, slot, start)
-    reserved = 0
+    reserved = working = 0
     peak_reserved = peak_running = 0
     nxt = 0
     while nxt < len(order) or waiting or running:
@@ -132,9 +140,11 @@ def serve(jobs: Sequence[Job], executor, clock, hbm_budget: int, slots: int = 4,
         for j in waiting:
             if j.footprint > hbm_budget:
                 done.append(Done(j.jid, j.arrival, now, now, -1, None, "footprint exceeds the HBM budget", j.kind))
-            elif idle and reserved + j.footprint <= hbm_budget:
+            elif (idle and reserved + j.footprint <= hbm_budget and
+                  (work_cap is None or not running or working + j.work <= work_cap)):
                 slot = idle.pop(0)
                 reserved += j.footprint
+                working += j.work
                 running[j.jid] = (j, slot, now)
                 executor.submit(j, slot)
             else:
@@ -147,8 +157,11 @@ def serve(jobs: Sequence[Job], executor, clock, hbm_budget: int, slots: int = 4,
             for jid, result, error, finish in executor.wait(timeout):
                 j, slot, start = running.pop(jid)
                 reserved -= j.footprint
+                working -= j.work
                 idle.append(slot)
                 done.append(Done(jid, j.arrival, start, finish, slot, result, error, j.kind))
+                if on_done:
+                    on_done(done[-1])
         elif timeout is not None:
             clock.wait_until(order[nxt].arrival)
         else:   # nothing runs and nothing arrives: every waiting job was admitted or failed
@@ -317,26 +330,35 @@ class GpuSlots:
             t.join()
 
 
+def pool_entry(w, device: str = "cuda:0", min_overlap=None, max_drift: int = 150, keep_host: bool = False):
+    """One device-resident job input from a generated workload whose A
+    carries strand bits in its values: (name, LayoutInputs, footprint,
+    products)."""
+    import torch
+    import paper_2010_10055_amd as db
+    from . import synth
+    lens = np.diff(w.reads.offsets).astype(np.int32)
+    mo = (1 if w.name == "tiny" else 1000) if min_overlap is None else min_overlap
+    inp = LayoutInputs(db.CSRTensors.from_numpy(w.A, device), torch.as_tensor(lens, device=device),
+                       w.k, w.min_shared, mo, max_drift, density_threshold(w.error_rate, w.k), w.fuzz,
+                       w.A if keep_host else None, lens if keep_host else None)
+    products = synth.overlap_products(w.A)
+    fp = footprint_bytes(w.A.nrows, w.A.nnz, products, w.min_shared, 80 * w.A.nrows)
+    return (w.name, inp, fp, products)
+
+
 def make_pool(kinds: Sequence[tuple], device: str = "cuda:0", min_overlap=None, max_drift: int = 150,
               keep_host: bool = False, log=lambda s: None):
     """Pre-generated device-resident instances: kinds = [(name, count,
     seed0, scale)] with workload names of the generator, built with strand
-    bits in A's values.  Returns [(name, LayoutInputs, footprint)]."""
-    import torch
-    import paper_2010_10055_amd as db
+    bits in A's values.  Returns [(name, LayoutInputs, footprint, products)]."""
     from . import synth
     pool = []
     for name, count, seed0, scale in kinds:
         for q in range(count):
             w = synth.make_workload(name, seed=seed0 + q, device=device, scale=scale, strand_bit=True)
-            lens = np.diff(w.reads.offsets).astype(np.int32)
-            mo = (1 if name == "tiny" else 1000) if min_overlap is None else min_overlap
-            inp = LayoutInputs(db.CSRTensors.from_numpy(w.A, device), torch.as_tensor(lens, device=device),
-                               w.k, w.min_shared, mo, max_drift, density_threshold(w.error_rate, w.k), w.fuzz,
-                               w.A if keep_host else None, lens if keep_host else None)
-            fp = footprint_bytes(w.A.nrows, w.A.nnz, synth.overlap_products(w.A), w.min_shared, 80 * w.A.nrows)
-            pool.append((name, inp, fp))
-            log(f"  pool {name}#{q}: reads {w.A.nrows}, nnz(A) {w.A.nnz}, footprint {fp / 2**30:.2f} GiB")
+            pool.append(pool_entry(w, device, min_overlap, max_drift, keep_host))
+            log(f"  pool {name}#{q}: reads {w.A.nrows}, nnz(A) {w.A.nnz}, footprint {pool[-1][2] / 2**30:.2f} GiB")
             del w
     return pool
 
@@ -351,6 +373,6 @@ def draw_jobs(rng: np.random.Generator, pool, count: int, rate: float, small_fra
     jobs = []
     for q in range(count):
         src = small if (small and (not large or rng.random() < small_fraction)) else large
-        name, inp, fp = src[int(rng.integers(0, len(src)))]
-        jobs.append(Job(q, float(times[q]), inp, fp, name))
+        name, inp, fp, work = src[int(rng.integers(0, len(src)))]
+        jobs.append(Job(q, float(times[q]), inp, fp, name, work))
     return jobs

@@ -106,6 +106,25 @@ def test_continuous_beats_fifo_under_load():
     assert res[4]["p99_ms"] < res[1]["p99_ms"]
 
 
+def test_work_budget_keeps_large_jobs_apart_but_lets_small_ones_run_beside():
+    """Two large jobs (work 100) never overlap under a work budget of 125;
+    small jobs (work 1) run beside a large one; a job above the budget runs
+    once nothing else does."""
+    clock = serve.VirtualClock()
+    ex = _executor(clock, base_s=0.020, share=0.0)
+    A = synth.random_a(np.random.default_rng(3), 10, 20, 0.2)
+    jobs = [serve.Job(0, 0.000, A, 1, "large", 100), serve.Job(1, 0.001, A, 1, "large", 100),
+            serve.Job(2, 0.002, A, 1, "small", 1), serve.Job(3, 0.003, A, 1, "small", 1),
+            serve.Job(4, 0.004, A, 1, "huge", 500)]
+    done = {d.jid: d for d in serve.serve(jobs, ex, clock, hbm_budget=100, slots=4, work_cap=125)}
+    assert done[1].start >= done[0].finish                     # the two large ones one after the other
+    assert done[2].start == 0.002 and done[2].start < done[0].finish   # small beside the first large
+    assert done[3].start == 0.003
+    others = [d for k, d in done.items() if k != 4]
+    assert all(done[4].start >= d.finish for d in others)     # above the budget: alone
+    assert all(d.error is None for d in done.values())
+
+
 def test_summary_splits_latency_by_kind():
     d = [serve.Done(0, 0.0, 0.0, 0.1, 0, kind="large"), serve.Done(1, 0.0, 0.0, 0.01, 1, kind="tiny")]
     s = serve.summarize(d, 1.0)
