@@ -2264,20 +2264,35 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     int tok_all = -1;
     DB_TRY(timing_begin(kPhNumericAll, st, &tok_all));
     DB_TRY(side->begin(st));
-    int lane_k = 0;
-    for (int b = bins.nh + bins.nb - 1; b >= 0; --b) {
-        const int count = h_ctr->num_count[b];
-        if (!count) continue;
-        const bool bits = b >= bins.nh;
-        const int blk = wide_block(tn.num_block, num_lds(256, bins.d[b], tn.load_pct, bits, bits_words));
-        hipStream_t ls = lane_k == 0 ? st : side->s[lane_k - 1];
-        lane_k = (lane_k + 1) % (kSideStreams + 1);
-        DB_TRY(timing_begin(kPhNumeric, ls, &tok));
-        DB_TRY(dispatch_numeric(blk, W, num_list + (int64_t)b * total_rows, count, bins.d[b], tn.load_pct, bits,
-                                bits_words, kQNumeric + b, ls));
-        DB_TRY(timing_end(tok, ls));
+    {
+        // the side streams are joined back into st on every way out of this
+        // block, so that no failure leaves work queued on them behind the
+        // workspace the caller's allocator reclaims
+        struct Join {
+            SideStreams* side;
+            hipStream_t st;
+            bool joined;
+            ~Join() {
+                if (!joined) (void)side->end(st);
+            }
+        } join{side, st, false};
+        int lane_k = 0;
+        for (int b = bins.nh + bins.nb - 1; b >= 0; --b) {
+            const int count = h_ctr->num_count[b];
+            if (!count) continue;
+            const bool bits = b >= bins.nh;
+            const int D = bins.d[b];
+            const int blk = wide_block(tn.num_block, num_lds(256, D, tn.load_pct, bits, bits_words));
+            hipStream_t ls = lane_k == 0 ? st : side->s[lane_k - 1];
+            lane_k = (lane_k + 1) % (kSideStreams + 1);
+            DB_TRY(timing_begin(kPhNumeric, ls, &tok));
+            DB_TRY(dispatch_numeric(blk, W, num_list + (int64_t)b * total_rows, count, D, tn.load_pct, bits,
+                                    bits_words, kQNumeric + b, ls));
+            DB_TRY(timing_end(tok, ls));
+        }
+        join.joined = true;
+        DB_TRY(side->end(st));
     }
-    DB_TRY(side->end(st));
     DB_TRY(timing_end(tok_all, st));
     if (esc_rows > 0) {
         DB_TRY(timing_begin(kPhEsc, st, &tok));
