@@ -108,18 +108,60 @@ KERNEL_NAMES = {"keys": ("k_ov_keys",), "part_count": ("k_ov_part_count<false>",
 CALIB_BYTES = 1 << 30
 
 
+# reference kernels of libdibella_calib.so: (name, bytes read, bytes written)
+# per launch as the access pattern fixes them; a 4-byte touch per 64- or
+# 128-byte line and a random 4-byte gather count as 4 bytes each
+CALIB_GATHERS = 1 << 24
+CALIB_CASES = (("k_calib_read", CALIB_BYTES, 0), ("k_calib_write", 0, CALIB_BYTES),
+               ("k_calib_copy", CALIB_BYTES, CALIB_BYTES),
+               ("k_calib_stride<64>", CALIB_BYTES // 64 * 4, 0), ("k_calib_stride<128>", CALIB_BYTES // 128 * 4, 0),
+               ("k_calib_gather", CALIB_GATHERS * 4, 0))
+
+
 def calib_copy():
     """Plain device kernels of known traffic, the references for scaling HBM
-    counters: a fill (1 GiB written), a sum (1 GiB read) and a copy (1 GiB
-    read + 1 GiB written)."""
+    counters (libdibella_calib.so, built beside the library): a 1 GiB read,
+    a 1 GiB write, a 1 GiB copy, one 4-byte read per 64 bytes and per 128
+    bytes over 1 GiB, and 2^24 random 4-byte gathers over 4 GiB.  Prints the
+    time of each (best of three)."""
+    import ctypes
     import torch
-    x = torch.ones(CALIB_BYTES // 4, dtype=torch.int32, device="cuda:0")      # fill: write only
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2010_10055_amd", "libdibella_calib.so"))
+    V, I64, I32, U64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    lib.calib_read.argtypes = [V, I64, V, V]
+    lib.calib_write.argtypes = [V, I64, V]
+    lib.calib_copy.argtypes = [V, V, I64, V]
+    lib.calib_stride.argtypes = [V, I64, I32, V, V]
+    lib.calib_gather.argtypes = [V, I64, I64, U64, V, V]
+    dev = "cuda:0"
+    x = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
-    for _ in range(3):
-        s = x.sum()                                                           # read only
-        torch.bitwise_or(x, 0, out=y)                                         # copy
+    big = torch.ones(4 * CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    out = torch.zeros(1, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
-    print(json.dumps({"calib_bytes": CALIB_BYTES, "sum": int(s)}), flush=True)
+    st = torch.cuda.current_stream().cuda_stream
+    cases = [("read", lambda: lib.calib_read(x.data_ptr(), CALIB_BYTES, out.data_ptr(), st)),
+             ("write", lambda: lib.calib_write(y.data_ptr(), CALIB_BYTES, st)),
+             ("copy", lambda: lib.calib_copy(x.data_ptr(), y.data_ptr(), CALIB_BYTES, st)),
+             ("stride64", lambda: lib.calib_stride(x.data_ptr(), CALIB_BYTES, 64, out.data_ptr(), st)),
+             ("stride128", lambda: lib.calib_stride(x.data_ptr(), CALIB_BYTES, 128, out.data_ptr(), st)),
+             ("gather4GiB", lambda: lib.calib_gather(big.data_ptr(), 4 * CALIB_BYTES, CALIB_GATHERS, 12345,
+                                                     out.data_ptr(), st))]
+    res = {}
+    for name, fn in cases:
+        best = None
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if fn() != 0:
+                raise RuntimeError(f"calibration kernel {name} failed")
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        res[name] = round(best, 4)
+        log(f"  calib {name}: {best:.3f} ms")
+    print(json.dumps({"calib_bytes": CALIB_BYTES, "calib_gathers": CALIB_GATHERS, "ms": res}), flush=True)
 
 
 def _csv_rows(d, suffix):
@@ -211,15 +253,24 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
     cf = _counter_per_kernel(cfetch_dir, "FETCH_SIZE")
     cw = _counter_per_kernel(cwrite_dir, "WRITE_SIZE")
 
-    def ref(per, pattern):
-        return max((max(v) for n, v in per.items() if pattern in n), default=0.0) * 1024
-    # reads are scaled by the read-only sum, writes by the write-only fill
-    read_only, write_only = ref(cf, "reduce_kernel"), ref(cw, "FillFunctor")
-    copy_fetch, copy_write = ref(cf, "BitwiseOr"), ref(cw, "BitwiseOr")
-    f_fetch = read_only / CALIB_BYTES if read_only else None
-    f_write = write_only / CALIB_BYTES if write_only else None
-    print(f"calibration: sum FETCH {read_only / CALIB_BYTES:.3f}x, fill WRITE {write_only / CALIB_BYTES:.3f}x, "
-          f"copy FETCH {copy_fetch / CALIB_BYTES:.3f}x WRITE {copy_write / CALIB_BYTES:.3f}x")
+    def ref(per, name):
+        """Mean counter bytes per dispatch of one calibration kernel."""
+        v = [x for n, vals in per.items() if name + "(" in n or n.endswith(name) for x in vals]
+        return statistics.mean(v) * 1024 if v else 0.0
+    # reads and writes are scaled by what the counters read for the plain
+    # copy kernel (1 GiB read, 1 GiB written); the other reference kernels
+    # are recorded beside it
+    copy_fetch, copy_write = ref(cf, "k_calib_copy"), ref(cw, "k_calib_copy")
+    f_fetch = copy_fetch / CALIB_BYTES if copy_fetch else None
+    f_write = copy_write / CALIB_BYTES if copy_write else None
+    refs = {}
+    for name, rd, wr in CALIB_CASES:
+        fb_, wb_ = ref(cf, name), ref(cw, name)
+        refs[name] = {"read_bytes": rd, "write_bytes": wr, "FETCH_SIZE_bytes": fb_, "WRITE_SIZE_bytes": wb_,
+                      "fetch_factor": round(fb_ / rd, 4) if rd else None,
+                      "write_factor": round(wb_ / wr, 4) if wr else None}
+    print("calibration: " + ", ".join(f"{k} FETCH {v['fetch_factor']} WRITE {v['write_factor']}"
+                                      for k, v in refs.items()))
     fetch = _counter_per_kernel(fetch_dir, "FETCH_SIZE")
     write = _counter_per_kernel(write_dir, "WRITE_SIZE")
     calls = sum(len(v) for n, v in fetch.items() if "k_ov_write_rowptr" in n)   # overlap calls profiled
@@ -238,9 +289,9 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
         d = {"kernel": kname, "workload": workload, "command": command,
              "source_hash": source_hash(*KERNEL_SOURCES[label]),
              "fetch_KiB_per_call_raw": fb * f_fetch / 1024, "write_KiB_per_call_raw": wb * f_write / 1024,
-             "dispatches": len(per_f[present[0]]), "read_calibration_factor": f_fetch, "write_calibration_factor": f_write,
-             "copy_fetch_factor": copy_fetch / CALIB_BYTES, "copy_write_factor": copy_write / CALIB_BYTES,
-             "hbm_bytes_per_launch": fb + wb, "hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb}
+             "dispatches": len(per_f[present[0]]), "read_calibration_factor": f_fetch,
+             "write_calibration_factor": f_write, "calibration_kernel": "k_calib_copy",
+             "reference_kernels": refs, "hbm_bytes_per_launch": fb + wb, "hbm_read_bytes_per_launch": fb, "hbm_write_bytes_per_launch": wb}
         if label == "numeric" and calls:
             # all launches of the phase of one call
             d["overlap_calls"] = calls
@@ -248,6 +299,42 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, 
         with open(os.path.join(out_dir, f"{label}_{workload}_pmc.json"), "w") as f:
             json.dump(d, f, indent=1)
     print(f"summaries written to {out_dir}")
+
+
+def summarize_raw(dirs, workload, command, out_dir: str = PROFILES):
+    """Write profiles/counters_raw_<workload>.txt: per kernel of the library
+    and per calibration kernel, the mean per dispatch of every counter found
+    in the given rocprofv3 --pmc CSV directories (raw TCC request counts, to
+    check how FETCH_SIZE / WRITE_SIZE weigh requests of each size)."""
+    import statistics
+    per = {}
+    for d in dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            name = r.get("Kernel_Name", "")
+            short = None
+            if "k_calib_" in name:
+                short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+            if short is None and "dibella::" in name:
+                short = name.split("(")[0].replace("void ", "").replace("dibella::", "")
+            if short is None:
+                continue
+            per.setdefault(short, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for v in per.values() for c in v})
+    known = {n: (rd, wr) for n, rd, wr in CALIB_CASES}
+    lines = [f"# rocprofv3 raw counters, mean per dispatch, workload '{workload}'", f"# command: {command}",
+             "# reference kernels (bytes read / written as their access pattern fixes them): " +
+             ", ".join(f"{n} {rd} / {wr}" for n, (rd, wr) in known.items()),
+             f"{'kernel':44s} {'dispatches':>10s} " + " ".join(f"{c:>26s}" for c in names)]
+    for k in sorted(per):
+        v = per[k]
+        nd = max(len(x) for x in v.values())
+        lines.append(f"{k[:44]:44s} {nd:10d} " + " ".join(
+            f"{statistics.mean(v[c]):26.1f}" if c in v else f"{'-':>26s}" for c in names))
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, f"counters_raw_{workload}.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"written {path}")
 
 
 def copy_rate() -> float:
@@ -561,9 +648,14 @@ def main():
     ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/ summaries from rocprofv3 CSV directories")
     ap.add_argument("--profile-command", default="", help="command recorded in the summaries")
+    ap.add_argument("--summarize-raw", nargs="+", metavar="DIR",
+                    help="write the raw-counter summary from rocprofv3 --pmc CSV directories")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles, args.workload, args.profile_command)
+        return
+    if args.summarize_raw:
+        summarize_raw(args.summarize_raw, args.workload, args.profile_command)
         return
     if args.calib_copy:
         calib_copy()

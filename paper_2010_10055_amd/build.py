@@ -1,4 +1,6 @@
-"""Build the HIP library (libdibella.so) for gfx950 with hipcc, in tree."""
+"""Build the HIP library (libdibella.so) for gfx950 with hipcc, in tree, and
+beside it the benchmark's counter-calibration kernels (libdibella_calib.so),
+which the library does not contain."""
 from __future__ import annotations
 
 import os
@@ -11,6 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdibella.so")
 SOURCES = ["runtime.hip", "overlap.hip", "tr.hip", "rseeds.hip", "noalloc.hip", "api.hip"]
+CALIB_SOURCE = "calib.hip"
+CALIB_OUT = os.path.join(HERE, "libdibella_calib.so")
 ARCH = os.environ.get("DIBELLA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + os.path.join(ROOT, "include"),
          "-Wall", "-Wno-unused-function",
@@ -29,17 +33,22 @@ def _compile(src: str, objdir: str) -> str:
     return obj
 
 
+def _link(objs, out: str) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    os.replace(tmp, out)
+
+
 def build(verbose: bool = True) -> str:
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, objdir), SOURCES))
-    tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
-    subprocess.check_call(cmd)
-    os.replace(tmp, OUT)
+    srcs = SOURCES + [CALIB_SOURCE]
+    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, objdir), srcs))
+    _link(objs[:len(SOURCES)], OUT)
+    _link(objs[len(SOURCES):], CALIB_OUT)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", os.path.basename(CALIB_OUT))
     return OUT
 
 

@@ -57,13 +57,16 @@ def profile_dirs(tmp_path):
           ("k_ov_numeric<256>", 110000, 130000)]
     _write_csv(str(trace / "host" / "1_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
                [{"Kernel_Name": f"void {n}(Args)", "Start_Timestamp": a, "End_Timestamp": b} for n, a, b in ev])
-    # calibration: the read-only sum fetches 1.25x its GiB, the fill writes 1.0x
+    # calibration: the copy kernel's 1 GiB read counts as 0.5 GiB in
+    # FETCH_SIZE (two dispatches, mean taken), its 1 GiB write as 1.25 GiB
     _counters(str(tmp_path / "cfetch"), "FETCH_SIZE",
-              {"void at::native::reduce_kernel<512>(Args)": [1.25 * KIB_PER_GIB, 1.0 * KIB_PER_GIB],
-               "void elementwise<BitwiseOrFunctor>(Args)": [2.5 * KIB_PER_GIB]})
+              {"void (anonymous namespace)::k_calib_copy(float4 const*, float4*, long)":
+                   [0.4 * KIB_PER_GIB, 0.6 * KIB_PER_GIB],
+               "(anonymous namespace)::k_calib_read(float4 const*, long, float*)": [0.5 * KIB_PER_GIB],
+               "void (anonymous namespace)::k_calib_stride<64>(float const*, long, float*)": [0.5 * KIB_PER_GIB]})
     _counters(str(tmp_path / "cwrite"), "WRITE_SIZE",
-              {"void vectorized<FillFunctor<int>>(Args)": [1.0 * KIB_PER_GIB],
-               "void elementwise<BitwiseOrFunctor>(Args)": [1.0 * KIB_PER_GIB]})
+              {"void (anonymous namespace)::k_calib_copy(float4 const*, float4*, long)": [1.25 * KIB_PER_GIB],
+               "(anonymous namespace)::k_calib_write(float4*, long, float)": [1.0 * KIB_PER_GIB]})
     _counters(str(tmp_path / "fetch"), "FETCH_SIZE",
               {"void k_ov_write_rowptr(Args)": [1.0, 1.0],
                "void k_ov_numeric<256>(Args)": [1000.0, 3000.0],
@@ -100,10 +103,16 @@ def test_summaries_from_synthetic_rocprof_output(profile_dirs):
     assert "2 calls, 2.0 launches per call, span avg_us 45.00" in text
 
     num = json.load(open(os.path.join(out, "numeric_t_pmc.json")))
-    f_read, f_write = 1.25, 1.0                          # the largest dispatch of each reference
+    f_read, f_write = 0.5, 1.25                          # the copy kernel, mean of its dispatches
     assert num["read_calibration_factor"] == pytest.approx(f_read)
     assert num["write_calibration_factor"] == pytest.approx(f_write)
-    assert num["copy_fetch_factor"] == pytest.approx(2.5)
+    assert num["calibration_kernel"] == "k_calib_copy"
+    refs = num["reference_kernels"]
+    assert refs["k_calib_read"]["fetch_factor"] == pytest.approx(0.5)
+    assert refs["k_calib_write"]["write_factor"] == pytest.approx(1.0)
+    # one 4-byte touch per 64 bytes over 1 GiB: 2^24 touches of 4 bytes
+    assert refs["k_calib_stride<64>"]["fetch_factor"] == pytest.approx(0.5 * (1 << 30) / ((1 << 24) * 4))
+    assert refs["k_calib_stride<128>"]["fetch_factor"] is None or refs["k_calib_stride<128>"]["FETCH_SIZE_bytes"] == 0
     # mean over the dispatches of the one kernel name, KiB -> bytes, / factor
     assert num["hbm_read_bytes_per_launch"] == pytest.approx(2000.0 * 1024 / f_read)
     assert num["hbm_write_bytes_per_launch"] == pytest.approx(200.0 * 1024 / f_write)
@@ -146,7 +155,8 @@ def test_committed_summaries_are_well_formed():
         assert s["command"] and s["kernel"] and len(s["source_hash"]) == 16
         assert s["hbm_bytes_per_launch"] == pytest.approx(s["hbm_read_bytes_per_launch"]
                                                           + s["hbm_write_bytes_per_launch"])
-        assert 0.5 < s["read_calibration_factor"] < 2 and 0.5 < s["write_calibration_factor"] < 2
+        assert 0.25 < s["read_calibration_factor"] < 2 and 0.25 < s["write_calibration_factor"] < 2
+        assert s["calibration_kernel"] == "k_calib_copy"
 
 
 @pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "4"})])
