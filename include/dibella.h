@@ -194,6 +194,36 @@ int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, 
                          void* ctx, void* hip_stream);
 
 /*
+ * dibella_overlap_graph_blocked -- the overlap graph R of A with C formed
+ * one block of rows at a time (Sec. VIII: to bound memory, only a region
+ * of the candidate overlap matrix exists at any time, and its spurious
+ * entries are removed before the next region is formed; Sec. IV-D, IV-E
+ * for the two steps).  A^T is built once.  Then for every block of
+ * block_rows consecutive reads (the last one shorter), that block's rows of
+ * C = A A^T are formed exactly as dibella_overlap forms them, turned into
+ * their rows of R exactly as dibella_r_from_seeds does, and released before
+ * the next block.  The result equals dibella_r_from_seeds(dibella_overlap(A,
+ * min_shared), read_len, k, min_overlap, max_drift, min_density) entry for
+ * entry.
+ *
+ * A, min_shared: as dibella_overlap (one set).  read_len, k, min_overlap,
+ * max_drift, min_density: as dibella_r_from_seeds.  block_rows >= 1 (a
+ * value >= nrows gives one block).  R: n x n, allocated through alloc;
+ * *nblocks (may be NULL) receives the number of blocks.  Peak workspace:
+ * what dibella_overlap needs for A^T, plus one block's row-phase workspace
+ * and C rows, plus R so far.
+ * Errors: those of dibella_overlap and dibella_r_from_seeds; EINVAL for
+ * block_rows < 1.  Host synchronisation: one stream sync to read A's row
+ * pointers, then per block the syncs of dibella_overlap's row phases (two,
+ * or three on retry-table overflow) and one of dibella_r_from_seeds.
+ */
+int dibella_overlap_graph_blocked(const dibella_csr* A, int32_t min_shared, const int32_t* read_len,
+                                  int32_t k, int32_t min_overlap, int32_t max_drift,
+                                  int32_t min_density, int64_t block_rows, dibella_csr_out* R,
+                                  int32_t* nblocks, dibella_alloc_fn alloc, dibella_free_fn free_fn,
+                                  void* ctx, void* hip_stream);
+
+/*
  * dibella_transitive_reduce_noalloc -- dibella_transitive_reduce for callers
  * that cannot allocate (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  It makes no device or pinned host

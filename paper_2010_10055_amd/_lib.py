@@ -26,7 +26,8 @@ NO_VALIDATE = 0x4
 TR_USE_GRAPH = 0x8
 
 EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batched",
-           "dibella_transitive_reduce_batched", "dibella_r_from_seeds", "dibella_transitive_reduce_noalloc",
+           "dibella_transitive_reduce_batched", "dibella_r_from_seeds", "dibella_overlap_graph_blocked",
+           "dibella_transitive_reduce_noalloc",
            "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
            "dibella_timing_select", "dibella_timing_collect"]
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dibella_transitive_reduce.argtypes = [P, i32, u32, P, P, ALLOC_FN, FREE_FN, P, P]
     lib.dibella_transitive_reduce_batched.argtypes = [P, i32, P, u32, P, P, ALLOC_FN, FREE_FN, P, P]
     lib.dibella_r_from_seeds.argtypes = [P, P, i32, i32, i32, i32, P, ALLOC_FN, FREE_FN, P, P]
+    lib.dibella_overlap_graph_blocked.argtypes = [P, i32, P, i32, i32, i32, i32, ctypes.c_int64, P, P, ALLOC_FN,
+                                                  FREE_FN, P, P]
     lib.dibella_transitive_reduce_noalloc.argtypes = [P, i32, u32, P, P, P, ctypes.c_int64, P, P, P]
     for f in EXPORTS:
         getattr(lib, f).restype = ctypes.c_int
@@ -353,6 +356,33 @@ def r_from_seeds(C: OverlapCSR, read_len: torch.Tensor, k: int, min_overlap: int
     _check(st)
     return CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
                       call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
+
+
+def overlap_graph_blocked(A: CSRTensors, min_shared: int, read_len: torch.Tensor, k: int, min_overlap: int,
+                          max_drift: int = -1, min_density: int = 0, block_rows: int = 1 << 30):
+    """The overlap graph R = r_from_seeds(overlap(A, min_shared), ...) with C
+    formed block_rows reads at a time (A^T built once; each block's rows of
+    C turned into R and released before the next block).  Returns (R, number
+    of blocks)."""
+    dev = _device_of([A])
+    if read_len.dtype != torch.int32 or not read_len.is_cuda or not read_len.is_contiguous():
+        raise TypeError("read_len must be a contiguous int32 device tensor")
+    if read_len.numel() != A.nrows:
+        raise ValueError("read_len must hold one length per row of A")
+    call = _call_for(dev)
+    a = _csr_struct(A)
+    o = _CSROut()
+    nb = ctypes.c_int32(0)
+    with torch.cuda.device(dev):
+        st = lib().dibella_overlap_graph_blocked(ctypes.byref(a), int(min_shared),
+                                                 read_len.data_ptr() if A.nrows else None, int(k), int(min_overlap),
+                                                 int(max_drift), int(min_density), int(block_rows), ctypes.byref(o),
+                                                 ctypes.byref(nb), call.alloc_cb, call.free_cb, None,
+                                                 _stream_handle(dev))
+    _check(st)
+    R = CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                   call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
+    return R, nb.value
 
 
 def last_stats() -> dict:

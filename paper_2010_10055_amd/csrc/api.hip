@@ -4,13 +4,6 @@
 
 #include <cstring>
 
-namespace dibella {
-int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibella_overlap_out* C,
-                uint32_t flags, Arena& ar);
-int r_from_seeds_run(const dibella_overlap_out* C, const int32_t* read_len, int32_t k, int32_t min_overlap,
-                     int32_t max_drift, int32_t min_density, dibella_csr_out* R, Arena& ar);
-}  // namespace dibella
-
 using namespace dibella;
 
 namespace {
@@ -93,14 +86,41 @@ int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, 
         set_error("dibella_r_from_seeds: bad arguments");
         return DIBELLA_EINVAL;
     }
+    if (C->ncols != C->nrows) {
+        set_error("dibella_r_from_seeds: C must be square");
+        return DIBELLA_EINVAL;
+    }
     int status;
     {
         Arena ar(alloc, free_fn, ctx, static_cast<hipStream_t>(hip_stream));
         status = guarded(ar, [&] {
-            return r_from_seeds_run(C, read_len, k, min_overlap, max_drift, min_density, R, ar);
+            return r_from_seeds_run(C, 0, read_len, k, min_overlap, max_drift, min_density, R, ar, ar, false);
         });
     }
     if (status != DIBELLA_OK) std::memset(R, 0, sizeof(*R));
+    return status;
+}
+
+int dibella_overlap_graph_blocked(const dibella_csr* A, int32_t min_shared, const int32_t* read_len, int32_t k,
+                                  int32_t min_overlap, int32_t max_drift, int32_t min_density, int64_t block_rows,
+                                  dibella_csr_out* R, int32_t* nblocks, dibella_alloc_fn alloc,
+                                  dibella_free_fn free_fn, void* ctx, void* hip_stream) {
+    reset_stats();
+    if (!A || !R || (alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("dibella_overlap_graph_blocked: bad arguments");
+        return DIBELLA_EINVAL;
+    }
+    int32_t nb = 0;
+    int status;
+    {
+        Arena ar(alloc, free_fn, ctx, static_cast<hipStream_t>(hip_stream));
+        status = guarded(ar, [&] {
+            return overlap_graph_blocked_run(A, min_shared, read_len, k, min_overlap, max_drift, min_density,
+                                             block_rows, R, &nb, ar);
+        });
+    }
+    if (status != DIBELLA_OK) std::memset(R, 0, sizeof(*R));
+    if (nblocks) *nblocks = status == DIBELLA_OK ? nb : 0;
     return status;
 }
 

@@ -67,6 +67,11 @@ class Arena {
     int output(size_t bytes, void** out);
     void fail() { failed_ = true; }
     hipStream_t stream() const { return stream_; }
+    // The allocator this arena draws from (for a nested arena whose
+    // workspace is released before this one's).
+    dibella_alloc_fn alloc_fn() const { return alloc_; }
+    dibella_free_fn free_fn() const { return free_; }
+    void* alloc_ctx() const { return ctx_; }
 
     template <class T>
     int work_n(size_t n, T** out) {
@@ -132,6 +137,19 @@ struct TrFixed {
     int32_t* s_val;
     int64_t s_cap;
 };
+// C = A A^T for nsets sets (dibella_overlap, dibella_overlap_batched).
+int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibella_overlap_out* C,
+                uint32_t flags, Arena& ar);
+// R from the seeds of C, whose row i is read row0 + i (dibella_r_from_seeds
+// with row0 = 0).  Workspace from ar; R's arrays from `out`, as outputs, or
+// as its workspace when out_as_work.
+int r_from_seeds_run(const dibella_overlap_out* C, int64_t row0, const int32_t* read_len, int32_t k,
+                     int32_t min_overlap, int32_t max_drift, int32_t min_density, dibella_csr_out* R, Arena& ar,
+                     Arena& out, bool out_as_work);
+// R from the seeds of C = A A^T, built block of rows by block of rows.
+int overlap_graph_blocked_run(const dibella_csr* A, int32_t min_shared, const int32_t* read_len, int32_t k,
+                              int32_t min_overlap, int32_t max_drift, int32_t min_density, int64_t block_rows,
+                              dibella_csr_out* R, int32_t* nblocks, Arena& ar);
 int tr_run(const dibella_csr* R, int nsets, const int32_t* fuzz, uint32_t flags, dibella_csr_out* S,
            int32_t* iterations, Arena& ar, const TrFixed* fixed = nullptr);
 size_t tr_workspace_bytes(int nsets, int64_t total_rows, int64_t total_nnz);

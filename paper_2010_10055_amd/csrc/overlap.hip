@@ -34,6 +34,8 @@ struct OvSet {
     const int32_t* a_val;
     int64_t n, m, nnz;
     int64_t row_base, col_base, nnz_base;
+    int64_t read_base;   // read id of the set's first row (a block of rows of a larger A: its first row)
+    int64_t nreads;      // reads on the A^T side: C's columns (n, or the whole A's rows for a block)
     int32_t min_shared;
     int32_t id_bits;   // bits needed for a read id of this set (ESC radix passes)
     int32_t words;     // 32-bit words of a bitmap over the set's reads
@@ -670,7 +672,7 @@ __device__ const int32_t kSliceNone[1] = {0};
 
 __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
     const OvSet* __restrict__ sets, int nsets, const int64_t* __restrict__ set_base, int64_t total_rows,
-    int64_t groups, SliceMap sm, const int32_t* __restrict__ bnd, const uint64_t* __restrict__ rec,
+    int64_t groups, SliceMap sm, const int32_t* __restrict__ bnd, int64_t bnd_stride, const uint64_t* __restrict__ rec,
     uint64_t* __restrict__ seg, uint32_t* __restrict__ part) {
     __shared__ int32_t s_pre[kSliceRows + 1];      // first flat number of each row's sub-range
     __shared__ int64_t s_first[kSliceRows];        // global entry of the row's first entry in the slice
@@ -698,8 +700,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_ov_seg_slices(
             const int64_t lo = S.a_rowptr[i], hi = S.a_rowptr[i + 1];
             if (!(lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30))) {
                 const int32_t L = (int32_t)(hi - lo);
-                const int32_t a = min(max(bnd[(int64_t)sl * total_rows + g], 0), L);
-                const int32_t z = min(max(bnd[(int64_t)(sl + 1) * total_rows + g], a), L);
+                const int32_t a = min(max(bnd[(int64_t)sl * bnd_stride + g], 0), L);
+                const int32_t z = min(max(bnd[(int64_t)(sl + 1) * bnd_stride + g], a), L);
                 len = z - a;
                 s_first[r] = S.nnz_base + lo + a;
                 if (z > a) s_col[r] = S.a_col + lo + a;
@@ -809,16 +811,16 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_scatter(
         if (lane == 0) {
             flops_row[g] = fl;
             // scratch range for the row's output columns: at most
-            // min(products / min_shared, n) of them
+            // min(products / min_shared, reads) of them
             const int64_t bound = fl / S.min_shared;
-            sbound[g] = bound < S.n ? bound : S.n;
+            sbound[g] = bound < S.nreads ? bound : S.nreads;
             s_bin[r] = -1;
             if (fl > 0) {
                 atomicAdd(&s_prod, (unsigned long long)fl);
                 atomic_max(&s_max, fl);
                 int lg = kBitsClass;
                 if (!S.use_bits) {
-                    const int64_t keys = fl < S.n ? fl : S.n;
+                    const int64_t keys = fl < S.nreads ? fl : S.nreads;
                     lg = ceil_log2_i64((keys * 100 + load_pct - 1) / load_pct);
                     lg = lg < 6 ? 6 : (lg > first_log2 ? first_log2 : lg);
                 }
@@ -1047,7 +1049,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_bits(
     // the diagonal (j = i) is a product of every entry of the row: it is
     // left out of the walk (one LDS address hit by every segment) and set
     // from its closed form, count = L
-    const int32_t self = (int32_t)i;
+    const int32_t self = (int32_t)(S.read_base + i);
     walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, nullptr, nullptr,
                          [&](int, int2 jp, int64_t) {
                              if (jp.x != self) planes_mark(B, words, planes, jp.x);
@@ -1123,7 +1125,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_sym_hash(
             s_ovf = 0;
         }
         __syncthreads();
-        const int32_t self = (int32_t)i;
+        const int32_t self = (int32_t)(S.read_base + i);
         walk_products<BLOCK>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, &s_ovf, self, nullptr, nullptr,
                              [&](int, int2 jp, int64_t) {
                                  if (jp.x == self) return;   // the diagonal: added once below
@@ -1316,7 +1318,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
         m2[r] = kEmpty64;
     }
     __syncthreads();
-    const int32_t self = (int32_t)i;   // the diagonal is written from its closed form below
+    const int32_t self = (int32_t)(S.read_base + i);   // the diagonal is written from its closed form below
     // four gathers per round: eight would take the registers of half the workgroups
     walk_products<BLOCK, 4>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, S.a_val + lo,
                             nullptr, [&](int t, int2 jp, int64_t) {
@@ -1423,7 +1425,7 @@ __global__ __launch_bounds__(kEscBlock) void k_esc_expand(
     const int L = (int)(S.a_rowptr[i + 1] - lo);
     const int64_t base = esc_off[g];
     // products land at their t-major index, so the expansion is ordered by k
-    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, (int32_t)i,
+    walk_products<kEscBlock>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, (int32_t)(S.read_base + i),
                              S.a_val + lo, S.a_val + lo, [&](int t, int2 jp, int64_t q) {
                                  keys0[base + q] = (uint32_t)jp.x;
                                  pay0[base + q] = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
@@ -1815,16 +1817,28 @@ static const char* describe_bad(int32_t bad) {
     return "malformed matrix";
 }
 
-int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibella_overlap_out* C,
-                uint32_t flags, Arena& ar) {
-    hipStream_t st = ar.stream();
-    const dibella_tuning tn = tuning();
-    dibella_stats& stt = stats();
-    // ---- host checks and set layout
-    std::vector<OvSet> hs(nsets);
-    std::vector<int64_t> base(nsets + 1, 0);
+// Host layout of a call's sets: checked sizes, global row, column and entry
+// bases, and the largest bitmap over the bitmap-path sets.
+struct OvLayout {
+    std::vector<OvSet> hs;
+    std::vector<int64_t> base;   // first global row of each set, then the total
     int64_t total_rows = 0, total_m = 0, total_nnz = 0;
-    int bits_words = 0, bits_planes = 0;   // largest bitmap over the bitmap-path sets
+    int bits_words = 0, bits_planes = 0;
+};
+
+// Whether a set of n reads takes the bitmap path.
+static int32_t use_bits_for(int64_t nreads, int32_t min_shared, const dibella_tuning& tn) {
+    const int32_t words = (int32_t)((nreads + 31) / 32);
+    return (min_shared <= kMaxPlanes && words <= tn.bits_max_words &&
+            sym_bits_lds(1024, min_shared, words) <= kLdsLimit)
+               ? 1
+               : 0;
+}
+
+static int ov_layout(const dibella_csr* A, int nsets, const int32_t* min_shared, const dibella_tuning& tn,
+                     OvLayout& L) {
+    L.hs.assign(nsets, OvSet{});
+    L.base.assign(nsets + 1, 0);
     for (int s = 0; s < nsets; ++s) {
         const dibella_csr& a = A[s];
         if (a.nrows < 0 || a.ncols < 0 || a.nnz < 0) {
@@ -1848,7 +1862,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
             set_error("set " + std::to_string(s) + ": entries in a matrix without rows");
             return DIBELLA_EINVAL;
         }
-        OvSet& o = hs[s];
+        OvSet& o = L.hs[s];
         std::memset(&o, 0, sizeof(o));
         o.a_rowptr = a.rowptr;
         o.a_col = a.col;
@@ -1856,45 +1870,70 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         o.n = a.nrows;
         o.m = a.ncols;
         o.nnz = a.nnz;
-        o.row_base = total_rows;
-        o.col_base = total_m;
-        o.nnz_base = total_nnz;
+        o.row_base = L.total_rows;
+        o.col_base = L.total_m;
+        o.nnz_base = L.total_nnz;
+        o.read_base = 0;
+        o.nreads = a.nrows;
         o.min_shared = min_shared[s];
         o.id_bits = std::max(1, ceil_log2_i64(std::max<int64_t>(a.nrows, 2)));
         o.words = (int32_t)((a.nrows + 31) / 32);
-        o.use_bits = (min_shared[s] <= kMaxPlanes && o.words <= tn.bits_max_words &&
-                      sym_bits_lds(1024, min_shared[s], o.words) <= kLdsLimit)
-                         ? 1
-                         : 0;
+        o.use_bits = use_bits_for(a.nrows, min_shared[s], tn);
         if (o.use_bits) {
-            bits_words = std::max(bits_words, o.words);
-            bits_planes = std::max(bits_planes, (int)o.min_shared);
+            L.bits_words = std::max(L.bits_words, o.words);
+            L.bits_planes = std::max(L.bits_planes, (int)o.min_shared);
         }
-        base[s] = total_rows;
-        total_rows += a.nrows;
-        total_m += a.ncols;
-        total_nnz += a.nnz;
+        L.base[s] = L.total_rows;
+        L.total_rows += a.nrows;
+        L.total_m += a.ncols;
+        L.total_nnz += a.nnz;
     }
-    base[nsets] = total_rows;
-    if (total_rows >= (int64_t(1) << 31) || total_nnz >= (int64_t(1) << 32) || total_m >= (int64_t(1) << 32)) {
+    L.base[nsets] = L.total_rows;
+    if (L.total_rows >= (int64_t(1) << 31) || L.total_nnz >= (int64_t(1) << 32) ||
+        L.total_m >= (int64_t(1) << 32)) {
         set_error("batch too large: total rows must be < 2^31, total columns and total nnz < 2^32");
         return DIBELLA_EOVERFLOW;
     }
-    for (int s = 0; s < nsets; ++s) {
-        C[s].nrows = A[s].nrows;
-        C[s].ncols = A[s].nrows;
-        C[s].nnz = 0;
-        C[s].rowptr = nullptr;
-        C[s].col = nullptr;
-        C[s].count = nullptr;
-        C[s].seed = nullptr;
-    }
-    const NumBins bins = numeric_bins(tn, bits_words);
-    if (bins.nh == 0) {
-        set_error("tuning leaves no numeric table that fits the LDS");
-        return DIBELLA_EINVAL;
-    }
+    return DIBELLA_OK;
+}
 
+// Column slices for the segment pass: 8 per round, each at most kSliceCols
+// columns wide; only where the column records outgrow an L2 and the slice
+// tables ((2S + 1) int32 per row) stay within max(4 nnz, 2^24) entries
+// (total_nnz < 2^31 keeps a workgroup's flat entry numbers in 32 bits).
+static SliceMap slice_plan(int64_t total_m, int64_t total_rows, int64_t total_nnz) {
+    SliceMap sm{0, 0u};
+    const int64_t S = ceil_div(total_m, 8 * kSliceCols) * 8;
+    if (total_rows > 0 && total_nnz > 0 && total_nnz < (int64_t(1) << 31) && total_m >= 4 * kSliceCols &&
+        S <= kMaxSlices && (2 * S + 1) * total_rows <= std::max<int64_t>(4 * total_nnz, int64_t(1) << 24)) {
+        sm.count = (int32_t)S;
+        sm.mul = (uint32_t)(((uint64_t)S << 32) / (uint64_t)total_m);
+    }
+    return sm;
+}
+
+// A^T of a call's sets and the slice table of their rows: what the row
+// phases read.
+struct OvTransposed {
+    const uint64_t* rec = nullptr;   // per column: its record (at least one slot)
+    const int2* at = nullptr;        // A^T pairs (read, position), column by column
+    const int32_t* bnd = nullptr;    // slice boundaries of every row, slice-major
+    int64_t bnd_stride = 0;          // rows per slice in bnd
+    SliceMap sm{0, 0u};
+    const int32_t* d_flags = nullptr;   // per set: the validation flags k_ov_keys raised
+    int nsets = 0;
+};
+
+// Steps O0 and O1 over every set of L (on the device as d_sets, d_base):
+// validate A, build A^T and, with slices, the rows' slice boundaries.  The
+// results come from `ar` (they live as long as it); the partition passes'
+// keys and pairs come from a scratch arena released on return (its frees
+// are ordered on the stream after the kernels that use them).
+static int ov_transpose(const OvLayout& L, const OvSet* d_sets, const int64_t* d_base, uint32_t flags, Arena& ar,
+                        OvTransposed* T) {
+    hipStream_t st = ar.stream();
+    const int nsets = (int)L.hs.size();
+    const int64_t total_rows = L.total_rows, total_m = L.total_m, total_nnz = L.total_nnz;
     // ---- transpose plan.  Two levels (partition the pairs into buckets of
     // 2^low columns, then a staged counting sort per bucket) while the
     // buckets fit one partition; three levels beyond that (partition into
@@ -1927,97 +1966,46 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     // most one partial chunk per segment)
     const int64_t nchunks2 = three ? nchunks + nbuckets : 0;
     const int64_t ncount2 = nchunks2 * fine_per;
-    // column slices for the segment pass: 8 per round, each at most
-    // kSliceCols columns wide; only where the column records outgrow an L2
-    // and the slice tables ((2S + 1) int32 per row) stay within
-    // max(4 nnz, 2^24) entries
-    SliceMap sm{0, 0u};
+    const SliceMap sm = slice_plan(total_m, total_rows, total_nnz);
+    // ---- what the row phases keep: one reservation
     {
-        const int64_t S = ceil_div(total_m, 8 * kSliceCols) * 8;
-        // (total_nnz < 2^31 keeps a workgroup's flat entry numbers in 32 bits)
-        if (total_rows > 0 && total_nnz > 0 && total_nnz < (int64_t(1) << 31) && total_m >= 4 * kSliceCols &&
-            S <= kMaxSlices && (2 * S + 1) * total_rows <= std::max<int64_t>(4 * total_nnz, int64_t(1) << 24)) {
-            sm.count = (int32_t)S;
-            sm.mul = (uint32_t)(((uint64_t)S << 32) / (uint64_t)total_m);
-        }
-    }
-    const int64_t slice_groups = ceil_div(total_rows, kSliceRows);
-    // ---- workspace: one reservation for everything requested before the
-    // first synchronisation (allocator calls cost host time each)
-    {
-        const size_t P = Arena::padded(1);
         auto pad = [](size_t b) { return Arena::padded(b); };
-        size_t est = pad(sizeof(OvSet) * nsets) + 2 * pad(8 * (nsets + 1)) + pad(4 * nsets) + pad(sizeof(OvCounters));
-        est += pad(8 * std::max<int64_t>(total_m, 1));
-        est += 2 * pad(4 * total_nnz) + 3 * pad(8 * total_nnz);
-        est += 7 * pad(8 * (total_rows + 1)) + 3 * pad(4 * total_rows);
-        est += pad(4 * total_rows * kMaxLog2) + pad(4 * total_rows * kMaxBins);
+        size_t est = pad(4 * nsets) + pad(8 * std::max<int64_t>(total_m, 1)) + pad(8 * total_nnz) + 4 * Arena::padded(1);
+        if (sm.count) est += pad(4 * total_rows * (sm.count + 1));
+        DB_TRY(ar.reserve(est));
+    }
+    int32_t* d_flags;
+    uint64_t* rec;
+    uint64_t* at_out;   // A^T: where the last pass writes
+    int32_t* bnd = nullptr;
+    DB_TRY(ar.work_n(nsets, &d_flags));
+    DB_TRY(ar.work_n(std::max<int64_t>(total_m, 1), &rec));
+    DB_TRY(ar.work_n(total_nnz, &at_out));
+    if (sm.count) DB_TRY(ar.work_n((size_t)total_rows * (sm.count + 1), &bnd));
+    // ---- the partition passes' buffers
+    Arena scr(ar.alloc_fn(), ar.free_fn(), ar.alloc_ctx(), st);
+    {
+        auto pad = [](size_t b) { return Arena::padded(b); };
+        size_t est = 2 * pad(4 * total_nnz) + pad(8 * total_nnz);
         est += pad(4 * nbuckets * npart) + pad(8 * (nbuckets * npart + 1));
         if (three)
             est += pad(4 * ncount2) + pad(8 * (ncount2 + 1)) + 2 * pad(8 * (nbuckets + 1)) +
                    pad(8 * (nbuckets * fine_per + 1));
-        if (sm.count) est += pad(4 * total_rows * (sm.count + 1)) + pad(4 * total_rows * sm.count);
-        est += 4 * pad(8 * scan_workspace_elems(std::max({total_rows, nbuckets * npart, ncount2}))) + 16 * P;
-        DB_TRY(ar.reserve(est));
+        est += 2 * pad(8 * scan_workspace_elems(std::max({nbuckets * npart, ncount2, int64_t(1)}))) +
+               8 * Arena::padded(1);
+        DB_TRY(scr.reserve(est));
     }
-    // ---- workspace
-    OvSet* d_sets;
-    int64_t* d_base;
-    int32_t* d_flags;
-    OvCounters* d_ctr;
-    int64_t* d_set_nnz;
-    DB_TRY(ar.work_n(nsets, &d_sets));
-    DB_TRY(ar.work_n(nsets + 1, &d_base));
-    DB_TRY(ar.work_n(nsets, &d_flags));
-    DB_TRY(ar.work_n(1, &d_ctr));
-    DB_TRY(ar.work_n(nsets, &d_set_nnz));
-    uint64_t* rec;   // per column: its record (at least one slot)
     uint32_t *keys_a, *keys_b;
-    uint64_t *pays_a, *pays_b;
-    uint64_t* seg;
-    int64_t *flops_row, *nnzrow, *G, *esc_off, *sbound, *soff;
-    int32_t *distinct, *sym_list, *num_list, *esc_list, *retry_list;
-    DB_TRY(ar.work_n(std::max<int64_t>(total_m, 1), &rec));
-    DB_TRY(ar.work_n(total_nnz, &keys_a));
-    DB_TRY(ar.work_n(total_nnz, &keys_b));
-    DB_TRY(ar.work_n(total_nnz, &pays_b));
-    DB_TRY(ar.work_n(total_nnz, &pays_a));
-    DB_TRY(ar.work_n(total_nnz, &seg));
-    DB_TRY(ar.work_n(total_rows, &flops_row));
-    DB_TRY(ar.work_n(total_rows, &nnzrow));
-    DB_TRY(ar.work_n(total_rows + 1, &G));
-    DB_TRY(ar.work_n(total_rows, &esc_off));
-    DB_TRY(ar.work_n(total_rows, &sbound));
-    DB_TRY(ar.work_n(total_rows + 1, &soff));
-    DB_TRY(ar.work_n(total_rows, &distinct));
-    DB_TRY(ar.work_n((size_t)total_rows * kMaxLog2, &sym_list));
-    DB_TRY(ar.work_n((size_t)total_rows * kMaxBins, &num_list));
-    DB_TRY(ar.work_n(total_rows, &esc_list));
-    DB_TRY(ar.work_n(total_rows, &retry_list));
-    int32_t* bnd = nullptr;
-    uint32_t* part = nullptr;
-    if (sm.count) {
-        DB_TRY(ar.work_n((size_t)total_rows * (sm.count + 1), &bnd));
-        DB_TRY(ar.work_n((size_t)total_rows * sm.count, &part));
-    }
-
-    // ---- upload descriptors
-    HostStage& hst = host_stage();
-    const size_t desc_bytes = sizeof(OvSet) * nsets + sizeof(int64_t) * (nsets + 1);
-    const size_t back_bytes = sizeof(OvCounters) + sizeof(int32_t) * nsets + sizeof(int64_t) * (nsets + 1);
-    DB_TRY(hst.reserve(desc_bytes + back_bytes + 64));
-    char* hbuf = static_cast<char*>(hst.ptr);
-    std::memcpy(hbuf, hs.data(), sizeof(OvSet) * nsets);
-    std::memcpy(hbuf + sizeof(OvSet) * nsets, base.data(), sizeof(int64_t) * (nsets + 1));
-    DB_HIP(hipMemcpyAsync(d_sets, hbuf, sizeof(OvSet) * nsets, hipMemcpyHostToDevice, st));
-    DB_HIP(hipMemcpyAsync(d_base, hbuf + sizeof(OvSet) * nsets, sizeof(int64_t) * (nsets + 1),
-                          hipMemcpyHostToDevice, st));
+    uint64_t* pays_x;   // the pairs buffer that is not A^T
+    DB_TRY(scr.work_n(total_nnz, &keys_a));
+    DB_TRY(scr.work_n(total_nnz, &keys_b));
+    DB_TRY(scr.work_n(total_nnz, &pays_x));
+    // the three-level sort ends in the second pairs buffer, the two-level
+    // one in the first
+    uint64_t* pays_a = three ? pays_x : at_out;
+    uint64_t* pays_b = three ? at_out : pays_x;
     DB_TRY(fill_i32(d_flags, 0, nsets, st));
-    DB_TRY(fill_i32(reinterpret_cast<int32_t*>(d_ctr), 0, sizeof(OvCounters) / 4, st));
-    DB_TRY(fill_i64(nnzrow, 0, total_rows, st));
-    DB_TRY(fill_i32(distinct, 0, total_rows, st));
 
-    // ---- validate + transpose + row costs + scratch ranges
     int tok = -1;
     constexpr int WPB = 4;
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
@@ -2032,7 +2020,6 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
     }
-    const int2* at = nullptr;
     if (total_nnz > 0) {
         static std::atomic<bool> lds_ok{false};
         if (!lds_ok.load(std::memory_order_acquire)) {
@@ -2050,15 +2037,15 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         int32_t* pcounts;
         int64_t* poffs;
         const int64_t ncount = nbuckets * npart;
-        DB_TRY(ar.work_n(ncount, &pcounts));
-        DB_TRY(ar.work_n(ncount + 1, &poffs));
+        DB_TRY(scr.work_n(ncount, &pcounts));
+        DB_TRY(scr.work_n(ncount + 1, &poffs));
         const int low1 = three ? lowc : low;
         DB_TRY(timing_begin(kPhPartCount, st, &tok));
         hipLaunchKernelGGL(k_ov_part_count<false>, dim3((unsigned)npart), dim3(kPartBlock), (size_t)nbuckets * 4, st,
                            keys_a, total_nnz, per_block, low1, (int)nbuckets, flat, pcounts);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
-        DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, ar));
+        DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, scr));
         uint16_t* keys_a16 = reinterpret_cast<uint16_t*>(keys_a);
         uint16_t* keys_b16 = reinterpret_cast<uint16_t*>(keys_b);
         DB_TRY(timing_begin(kPhPartScatter, st, &tok));
@@ -2076,15 +2063,14 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         int64_t sort_stride = npart;
         const uint16_t* sort_keys = keys_b16;
         const uint64_t* sort_pays = pays_b;
-        uint64_t* at_out = pays_a;           // A^T goes where the sort's input is not
         if (three) {
             int64_t *seg_start, *chunk_base, *fine_start, *poffs2;
             int32_t* pcounts2;
-            DB_TRY(ar.work_n(nbuckets + 1, &seg_start));
-            DB_TRY(ar.work_n(nbuckets + 1, &chunk_base));
-            DB_TRY(ar.work_n(nbuckets * fine_per + 1, &fine_start));
-            DB_TRY(ar.work_n(ncount2, &pcounts2));
-            DB_TRY(ar.work_n(ncount2 + 1, &poffs2));
+            DB_TRY(scr.work_n(nbuckets + 1, &seg_start));
+            DB_TRY(scr.work_n(nbuckets + 1, &chunk_base));
+            DB_TRY(scr.work_n(nbuckets * fine_per + 1, &fine_start));
+            DB_TRY(scr.work_n(ncount2, &pcounts2));
+            DB_TRY(scr.work_n(ncount2 + 1, &poffs2));
             hipLaunchKernelGGL(k_ov_seg_chunks, dim3(1), dim3(kSegChunkBlock), 0, st, poffs, npart, (int)nbuckets,
                                total_nnz, seg_start, chunk_base);
             DB_HIP(hipGetLastError());
@@ -2094,7 +2080,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
                                (size_t)fine_per * 4, st, keys_b, total_nnz, 1, low, fine_per, ps, pcounts2);
             DB_HIP(hipGetLastError());
             DB_TRY(timing_end(tok, st));
-            DB_TRY(scan_exclusive(pcounts2, poffs2, ncount2, nullptr, ar));
+            DB_TRY(scan_exclusive(pcounts2, poffs2, ncount2, nullptr, scr));
             DB_TRY(timing_begin(kPhPart2Scatter, st, &tok));
             hipLaunchKernelGGL((k_ov_part_scatter<true, uint16_t>), dim3((unsigned)nchunks2), dim3(kPartBlock),
                                part_scatter_lds(fine_per), st, keys_b, pays_b, total_nnz, 1, low, fine_per, ps,
@@ -2108,7 +2094,6 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
             sort_stride = 1;
             sort_keys = keys_a16;
             sort_pays = pays_a;
-            at_out = pays_b;
         }
         // staged sweeps of 2^12 columns (one sweep for buckets of at most that)
         DB_TRY(timing_begin(kPhBucketSort, st, &tok));
@@ -2117,18 +2102,92 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
                            std::min(low, kStageBits), total_m, total_nnz, sort_keys, sort_pays, rec, at_out);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
-        at = reinterpret_cast<const int2*>(at_out);
     }
+    T->rec = rec;
+    T->at = total_nnz > 0 ? reinterpret_cast<const int2*>(at_out) : nullptr;
+    T->bnd = bnd;
+    T->bnd_stride = total_rows;
+    T->sm = sm;
+    T->d_flags = d_flags;
+    T->nsets = nsets;
+    return DIBELLA_OK;
+}
+
+// Steps O2-O4 for the rows of R (on the device as d_rsets, d_rbase; every
+// set's A entries and columns are those T was built from, its rows those
+// whose outputs C receives): row costs and bins, symbolic, numeric.  `bnd`
+// is T's slice table at the first row of R (R's rows are consecutive rows
+// of T's); seg_entries: the A entries of R's rows.  C's arrays are outputs
+// of `ar`, or its workspace when c_as_work.
+static int ov_rows(OvLayout& R, OvSet* d_rsets, const int64_t* d_rbase, const OvTransposed& T, const int32_t* bnd,
+                   int64_t seg_entries, dibella_overlap_out* C, Arena& ar, bool c_as_work) {
+    hipStream_t st = ar.stream();
+    const dibella_tuning tn = tuning();
+    dibella_stats& stt = stats();
+    const int nsets = (int)R.hs.size();
+    const int64_t total_rows = R.total_rows;
+    const int64_t rows_nnz = seg_entries;   // one segment word per A entry of R's rows
+    const SliceMap sm = T.sm;
+    const NumBins bins = numeric_bins(tn, R.bits_words);
+    if (bins.nh == 0) {
+        set_error("tuning leaves no numeric table that fits the LDS");
+        return DIBELLA_EINVAL;
+    }
+    const int64_t slice_groups = ceil_div(total_rows, kSliceRows);
+    // ---- workspace: one reservation for everything requested before the
+    // first synchronisation (allocator calls cost host time each)
+    {
+        auto pad = [](size_t b) { return Arena::padded(b); };
+        size_t est = pad(sizeof(OvCounters)) + pad(8 * nsets) + pad(8 * rows_nnz);
+        est += 7 * pad(8 * (total_rows + 1)) + 3 * pad(4 * total_rows);
+        est += pad(4 * total_rows * kMaxLog2) + pad(4 * total_rows * kMaxBins);
+        if (sm.count) est += pad(4 * total_rows * sm.count);
+        est += 2 * pad(8 * scan_workspace_elems(std::max<int64_t>(total_rows, 1))) + 16 * Arena::padded(1);
+        DB_TRY(ar.reserve(est));
+    }
+    OvCounters* d_ctr;
+    int64_t* d_set_nnz;
+    uint64_t* seg;
+    int64_t *flops_row, *nnzrow, *G, *esc_off, *sbound, *soff;
+    int32_t *distinct, *sym_list, *num_list, *esc_list, *retry_list;
+    DB_TRY(ar.work_n(1, &d_ctr));
+    DB_TRY(ar.work_n(nsets, &d_set_nnz));
+    DB_TRY(ar.work_n(rows_nnz, &seg));
+    DB_TRY(ar.work_n(total_rows, &flops_row));
+    DB_TRY(ar.work_n(total_rows, &nnzrow));
+    DB_TRY(ar.work_n(total_rows + 1, &G));
+    DB_TRY(ar.work_n(total_rows, &esc_off));
+    DB_TRY(ar.work_n(total_rows, &sbound));
+    DB_TRY(ar.work_n(total_rows + 1, &soff));
+    DB_TRY(ar.work_n(total_rows, &distinct));
+    DB_TRY(ar.work_n((size_t)total_rows * kMaxLog2, &sym_list));
+    DB_TRY(ar.work_n((size_t)total_rows * kMaxBins, &num_list));
+    DB_TRY(ar.work_n(total_rows, &esc_list));
+    DB_TRY(ar.work_n(total_rows, &retry_list));
+    uint32_t* part = nullptr;
+    if (sm.count) DB_TRY(ar.work_n((size_t)total_rows * sm.count, &part));
+
+    HostStage& hst = host_stage();
+    const size_t desc_bytes = sizeof(OvSet) * nsets;
+    const size_t back_bytes = sizeof(OvCounters) + sizeof(int32_t) * T.nsets + sizeof(int64_t) * (nsets + 1);
+    DB_TRY(hst.reserve(desc_bytes + back_bytes + 64));
+    char* hbuf = static_cast<char*>(hst.ptr);
+    DB_TRY(fill_i32(reinterpret_cast<int32_t*>(d_ctr), 0, sizeof(OvCounters) / 4, st));
+    DB_TRY(fill_i64(nnzrow, 0, total_rows, st));
+    DB_TRY(fill_i32(distinct, 0, total_rows, st));
+
+    // ---- row costs + scratch ranges
+    int tok = -1;
     if (total_rows > 0) {
         DB_TRY(timing_begin(kPhSegments, st, &tok));
         if (sm.count) {
             const int64_t nblk = (int64_t)(sm.count / 8) * 8 * slice_groups;
-            hipLaunchKernelGGL(k_ov_seg_slices, dim3((unsigned)nblk), dim3(kSliceBlock), 0, st, d_sets, nsets, d_base,
-                               total_rows, slice_groups, sm, bnd, rec, seg, part);
+            hipLaunchKernelGGL(k_ov_seg_slices, dim3((unsigned)nblk), dim3(kSliceBlock), 0, st, d_rsets, nsets,
+                               d_rbase, total_rows, slice_groups, sm, bnd, T.bnd_stride, T.rec, seg, part);
             DB_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_ov_scatter<kSegWaves>, dim3((unsigned)ceil_div(total_rows, kRowsPerBlock)),
-                           dim3(kSegWaves * kWave), 0, st, d_sets, nsets, d_base, total_rows, rec, seg,
+                           dim3(kSegWaves * kWave), 0, st, d_rsets, nsets, d_rbase, total_rows, T.rec, seg,
                            flops_row, sbound, sym_list, d_ctr, tn.sym_first_log2, tn.load_pct, part, sm.count);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
@@ -2138,13 +2197,13 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     char* back = hbuf + desc_bytes;
     OvCounters* h_ctr = reinterpret_cast<OvCounters*>(back);
     int32_t* h_flags = reinterpret_cast<int32_t*>(back + sizeof(OvCounters));
-    int64_t* h_set_nnz = reinterpret_cast<int64_t*>(back + sizeof(OvCounters) + sizeof(int32_t) * nsets);
+    int64_t* h_set_nnz = reinterpret_cast<int64_t*>(back + sizeof(OvCounters) + sizeof(int32_t) * T.nsets);
     DB_HIP(hipMemcpyAsync(h_ctr, d_ctr, sizeof(OvCounters), hipMemcpyDeviceToHost, st));
-    DB_HIP(hipMemcpyAsync(h_flags, d_flags, sizeof(int32_t) * nsets, hipMemcpyDeviceToHost, st));
+    DB_HIP(hipMemcpyAsync(h_flags, T.d_flags, sizeof(int32_t) * T.nsets, hipMemcpyDeviceToHost, st));
     DB_HIP(hipMemcpyAsync(h_set_nnz + nsets, soff + total_rows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DB_TRY(sync_stream(st));
     const int64_t scratch_words = h_set_nnz[nsets];
-    for (int s = 0; s < nsets; ++s) {
+    for (int s = 0; s < T.nsets; ++s) {
         if (h_flags[s]) {
             set_error("set " + std::to_string(s) + ": " + describe_bad(h_flags[s]));
             return (h_flags[s] & kLongRow) && !(h_flags[s] & ~kLongRow) ? DIBELLA_EOVERFLOW
@@ -2155,19 +2214,19 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         set_error("a row needs 2^31 or more semiring products");
         return DIBELLA_EOVERFLOW;
     }
-    stt.products = h_ctr->products;
+    stt.products += h_ctr->products;
     int32_t* scratch;
     DB_TRY(ar.work_n(scratch_words, &scratch));
-    OvWork W{d_sets, nsets, d_base, retry_list, seg, at, soff, scratch, nnzrow, distinct, d_ctr, G};
+    OvWork W{d_rsets, nsets, d_rbase, retry_list, seg, T.at, soff, scratch, nnzrow, distinct, d_ctr, G};
 
     // ---- symbolic: bitmap rows; hash rows by first-level table (largest
     // first), then the retry level
     if (h_ctr->sym_count[kBitsClass] > 0) {
         const int count = h_ctr->sym_count[kBitsClass];
-        const int blk = wide_block(tn.sym_block, sym_bits_lds(256, bits_planes, bits_words));
+        const int blk = wide_block(tn.sym_block, sym_bits_lds(256, R.bits_planes, R.bits_words));
         DB_TRY(timing_begin(kPhSymBits, st, &tok));
-        DB_TRY(dispatch_sym_bits(blk, W, sym_list + (int64_t)kBitsClass * total_rows, count, bits_planes,
-                                 bits_words, st));
+        DB_TRY(dispatch_sym_bits(blk, W, sym_list + (int64_t)kBitsClass * total_rows, count, R.bits_planes,
+                                 R.bits_words, st));
         DB_TRY(timing_end(tok, st));
     }
     bool any_hash = false;
@@ -2175,32 +2234,32 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         const int count = h_ctr->sym_count[lg];
         if (!count) continue;
         any_hash = true;
-        const int T = 1 << lg;
-        const int limit = (int)((int64_t)T * tn.load_pct / 100);
+        const int Tn = 1 << lg;
+        const int limit = (int)((int64_t)Tn * tn.load_pct / 100);
         DB_TRY(timing_begin(kPhSymHash, st, &tok));
-        DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
-                                 SymArgs{sym_list + (int64_t)lg * total_rows, nullptr, count, count, T, limit, 0,
+        DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, Tn)), W,
+                                 SymArgs{sym_list + (int64_t)lg * total_rows, nullptr, count, count, Tn, limit, 0,
                                          kQSymHash + lg},
                                  st));
         DB_TRY(timing_end(tok, st));
     }
     if (any_hash) {
-        const int T = 1 << tn.sym_max_log2;
-        const int limit = (int)((int64_t)T * tn.load_pct / 100);
+        const int Tn = 1 << tn.sym_max_log2;
+        const int limit = (int)((int64_t)Tn * tn.load_pct / 100);
         const int grid = (int)std::min<int64_t>(total_rows, 512);
         DB_TRY(timing_begin(kPhSymHash, st, &tok));
-        DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, T)), W,
-                                 SymArgs{retry_list, &d_ctr->retry_rows, 0, grid, T, limit, 1, kQRetry}, st));
+        DB_TRY(dispatch_sym_hash(wide_block(tn.sym_block, sym_hash_lds(256, Tn)), W,
+                                 SymArgs{retry_list, &d_ctr->retry_rows, 0, grid, Tn, limit, 1, kQRetry}, st));
         DB_TRY(timing_end(tok, st));
     }
     if (total_rows > 0) {
         hipLaunchKernelGGL(k_ov_bin_numeric, dim3((unsigned)ceil_div(total_rows, kBinBlock)), dim3(kBinBlock), 0, st,
-                           d_sets, nsets, d_base, total_rows, flops_row, distinct, nnzrow, num_list, esc_list,
+                           d_rsets, nsets, d_rbase, total_rows, flops_row, distinct, nnzrow, num_list, esc_list,
                            esc_off, d_ctr, bins);
         DB_HIP(hipGetLastError());
     }
     DB_TRY(scan_exclusive(nnzrow, G, total_rows, nullptr, ar));
-    hipLaunchKernelGGL(k_ov_set_totals, dim3(grid_for(nsets, 64, 1024)), dim3(64), 0, st, d_sets, nsets, G,
+    hipLaunchKernelGGL(k_ov_set_totals, dim3(grid_for(nsets, 64, 1024)), dim3(64), 0, st, d_rsets, nsets, G,
                        d_set_nnz);
     DB_HIP(hipGetLastError());
     DB_HIP(hipMemcpyAsync(h_ctr, d_ctr, sizeof(OvCounters), hipMemcpyDeviceToHost, st));
@@ -2209,7 +2268,7 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
 
     // ---- ESC rows
     const int esc_rows = h_ctr->esc_rows;
-    stt.esc_rows = esc_rows;
+    stt.esc_rows += esc_rows;
     uint32_t *keys0 = nullptr, *keys1 = nullptr;
     uint64_t *pay0 = nullptr, *pay1 = nullptr;
     if (esc_rows > 0) {
@@ -2219,18 +2278,18 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
         DB_TRY(ar.work_n(ef, &pay0));
         DB_TRY(ar.work_n(ef, &pay1));
         DB_TRY(timing_begin(kPhEsc, st, &tok));
-        hipLaunchKernelGGL(k_esc_expand, dim3(esc_rows), dim3(kEscBlock), 0, st, d_sets, nsets, d_base,
-                           esc_list, esc_off, seg, at, keys0, pay0);
-        hipLaunchKernelGGL(k_esc_sort, dim3(esc_rows), dim3(kEscBlock), 0, st, d_sets, nsets, d_base,
+        hipLaunchKernelGGL(k_esc_expand, dim3(esc_rows), dim3(kEscBlock), 0, st, d_rsets, nsets, d_rbase,
+                           esc_list, esc_off, seg, T.at, keys0, pay0);
+        hipLaunchKernelGGL(k_esc_sort, dim3(esc_rows), dim3(kEscBlock), 0, st, d_rsets, nsets, d_rbase,
                            esc_list, esc_off, flops_row, keys0, pay0, keys1, pay1);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
         if (h_ctr->overflow_rows > 0) {
-            hipLaunchKernelGGL(k_esc_count, dim3(esc_rows), dim3(kEscBlock), 0, st, d_sets, nsets, d_base,
+            hipLaunchKernelGGL(k_esc_count, dim3(esc_rows), dim3(kEscBlock), 0, st, d_rsets, nsets, d_rbase,
                                esc_list, esc_off, flops_row, keys0, nnzrow, distinct);
             DB_HIP(hipGetLastError());
             DB_TRY(scan_exclusive(nnzrow, G, total_rows, nullptr, ar));
-            hipLaunchKernelGGL(k_ov_set_totals, dim3(grid_for(nsets, 64, 1024)), dim3(64), 0, st, d_sets,
+            hipLaunchKernelGGL(k_ov_set_totals, dim3(grid_for(nsets, 64, 1024)), dim3(64), 0, st, d_rsets,
                                nsets, G, d_set_nnz);
             DB_HIP(hipGetLastError());
             DB_HIP(hipMemcpyAsync(h_set_nnz, d_set_nnz, sizeof(int64_t) * nsets, hipMemcpyDeviceToHost, st));
@@ -2241,20 +2300,24 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     // ---- outputs
     for (int s = 0; s < nsets; ++s) {
         const int64_t nz = h_set_nnz[s];
-        DB_TRY(ar.output_n(A[s].nrows + 1, &hs[s].c_rowptr));
-        DB_TRY(ar.output_n(nz, &hs[s].c_col));
-        DB_TRY(ar.output_n(nz, &hs[s].c_count));
-        DB_TRY(ar.output_n(4 * nz, &hs[s].c_seed));
+        OvSet& o = R.hs[s];
+        auto take = [&](auto n, auto** p) { return c_as_work ? ar.work_n(n, p) : ar.output_n(n, p); };
+        DB_TRY(take(o.n + 1, &o.c_rowptr));
+        DB_TRY(take(nz, &o.c_col));
+        DB_TRY(take(nz, &o.c_count));
+        DB_TRY(take(4 * nz, &o.c_seed));
+        C[s].nrows = o.n;
+        C[s].ncols = o.nreads;
         C[s].nnz = nz;
-        C[s].rowptr = hs[s].c_rowptr;
-        C[s].col = hs[s].c_col;
-        C[s].count = hs[s].c_count;
-        C[s].seed = hs[s].c_seed;
+        C[s].rowptr = o.c_rowptr;
+        C[s].col = o.c_col;
+        C[s].count = o.c_count;
+        C[s].seed = o.c_seed;
     }
-    std::memcpy(hbuf, hs.data(), sizeof(OvSet) * nsets);
-    DB_HIP(hipMemcpyAsync(d_sets, hbuf, sizeof(OvSet) * nsets, hipMemcpyHostToDevice, st));
+    std::memcpy(hbuf, R.hs.data(), sizeof(OvSet) * nsets);
+    DB_HIP(hipMemcpyAsync(d_rsets, hbuf, sizeof(OvSet) * nsets, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_ov_write_rowptr, dim3(grid_for(total_rows + nsets, 256, 4096)), dim3(256), 0, st,
-                       d_sets, nsets, d_base, total_rows, G);
+                       d_rsets, nsets, d_rbase, total_rows, G);
     DB_HIP(hipGetLastError());
     // numeric bins (largest tables first) spread over the caller's stream and
     // the side streams, so that the few rows of the large bins overlap with
@@ -2282,12 +2345,12 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
             if (!count) continue;
             const bool bits = b >= bins.nh;
             const int D = bins.d[b];
-            const int blk = wide_block(tn.num_block, num_lds(256, D, tn.load_pct, bits, bits_words));
+            const int blk = wide_block(tn.num_block, num_lds(256, D, tn.load_pct, bits, R.bits_words));
             hipStream_t ls = lane_k == 0 ? st : side->s[lane_k - 1];
             lane_k = (lane_k + 1) % (kSideStreams + 1);
             DB_TRY(timing_begin(kPhNumeric, ls, &tok));
             DB_TRY(dispatch_numeric(blk, W, num_list + (int64_t)b * total_rows, count, D, tn.load_pct, bits,
-                                    bits_words, kQNumeric + b, ls));
+                                    R.bits_words, kQNumeric + b, ls));
             DB_TRY(timing_end(tok, ls));
         }
         join.joined = true;
@@ -2296,12 +2359,178 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
     DB_TRY(timing_end(tok_all, st));
     if (esc_rows > 0) {
         DB_TRY(timing_begin(kPhEsc, st, &tok));
-        hipLaunchKernelGGL(k_esc_emit, dim3(esc_rows), dim3(kEscBlock), 0, st, d_sets, nsets, d_base,
+        hipLaunchKernelGGL(k_esc_emit, dim3(esc_rows), dim3(kEscBlock), 0, st, d_rsets, nsets, d_rbase,
                            esc_list, esc_off, flops_row, keys0, pay0, G);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
     }
     DB_TRY(stage_done(st));
+    return DIBELLA_OK;
+}
+
+// Uploads a layout's sets and row bases into `ar`.
+static int upload_sets(const OvLayout& L, Arena& ar, OvSet** d_sets, int64_t** d_base) {
+    hipStream_t st = ar.stream();
+    const int nsets = (int)L.hs.size();
+    DB_TRY(ar.work_n(nsets, d_sets));
+    DB_TRY(ar.work_n(nsets + 1, d_base));
+    HostStage& hst = host_stage();
+    const size_t desc_bytes = sizeof(OvSet) * nsets + sizeof(int64_t) * (nsets + 1);
+    DB_TRY(hst.reserve(desc_bytes + 64));
+    char* hbuf = static_cast<char*>(hst.ptr);
+    std::memcpy(hbuf, L.hs.data(), sizeof(OvSet) * nsets);
+    std::memcpy(hbuf + sizeof(OvSet) * nsets, L.base.data(), sizeof(int64_t) * (nsets + 1));
+    DB_HIP(hipMemcpyAsync(*d_sets, hbuf, sizeof(OvSet) * nsets, hipMemcpyHostToDevice, st));
+    DB_HIP(hipMemcpyAsync(*d_base, hbuf + sizeof(OvSet) * nsets, sizeof(int64_t) * (nsets + 1),
+                          hipMemcpyHostToDevice, st));
+    DB_TRY(stage_done(st));
+    return DIBELLA_OK;
+}
+
+int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibella_overlap_out* C,
+                uint32_t flags, Arena& ar) {
+    const dibella_tuning tn = tuning();
+    OvLayout L;
+    DB_TRY(ov_layout(A, nsets, min_shared, tn, L));
+    for (int s = 0; s < nsets; ++s) {
+        C[s].nrows = A[s].nrows;
+        C[s].ncols = A[s].nrows;
+        C[s].nnz = 0;
+        C[s].rowptr = nullptr;
+        C[s].col = nullptr;
+        C[s].count = nullptr;
+        C[s].seed = nullptr;
+    }
+    if (numeric_bins(tn, L.bits_words).nh == 0) {
+        set_error("tuning leaves no numeric table that fits the LDS");
+        return DIBELLA_EINVAL;
+    }
+    OvSet* d_sets;
+    int64_t* d_base;
+    DB_TRY(upload_sets(L, ar, &d_sets, &d_base));
+    OvTransposed T;
+    DB_TRY(ov_transpose(L, d_sets, d_base, flags, ar, &T));
+    stats().products = 0;
+    stats().esc_rows = 0;
+    return ov_rows(L, d_sets, d_base, T, T.bnd, L.total_nnz, C, ar, false);
+}
+
+// out[i] = in[i] + add for i in [0, n]: a block's row pointers placed after
+// the entries of the blocks before it.
+__global__ void k_shift_rowptr(const int64_t* __restrict__ in, int64_t n, int64_t add, int64_t* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i] + add;
+}
+
+int overlap_graph_blocked_run(const dibella_csr* A, int32_t min_shared, const int32_t* read_len, int32_t k,
+                              int32_t min_overlap, int32_t max_drift, int32_t min_density, int64_t block_rows,
+                              dibella_csr_out* R, int32_t* nblocks, Arena& ar) {
+    hipStream_t st = ar.stream();
+    std::memset(R, 0, sizeof(*R));
+    *nblocks = 0;
+    if (block_rows < 1) {
+        set_error("dibella_overlap_graph_blocked: block_rows must be >= 1");
+        return DIBELLA_EINVAL;
+    }
+    if (k < 1 || k > 32 || min_overlap < 0) {
+        set_error("dibella_overlap_graph_blocked: k must be in [1, 32] and min_overlap >= 0");
+        return DIBELLA_EINVAL;
+    }
+    const dibella_tuning tn = tuning();
+    OvLayout L;
+    DB_TRY(ov_layout(A, 1, &min_shared, tn, L));
+    if (numeric_bins(tn, L.bits_words).nh == 0) {
+        set_error("tuning leaves no numeric table that fits the LDS");
+        return DIBELLA_EINVAL;
+    }
+    const int64_t n = A->nrows;
+    if (n > 0 && !read_len) {
+        set_error("dibella_overlap_graph_blocked: null pointer");
+        return DIBELLA_EINVAL;
+    }
+    OvSet* d_sets;
+    int64_t* d_base;
+    DB_TRY(upload_sets(L, ar, &d_sets, &d_base));
+    OvTransposed T;
+    DB_TRY(ov_transpose(L, d_sets, d_base, 0u, ar, &T));
+    stats().products = 0;
+    stats().esc_rows = 0;
+    // A's row pointers on the host (every block's first entry) and A's
+    // validation flags: a block's segment words are indexed from its first
+    // entry, so A must be known valid before any block runs
+    const int64_t nb = n > 0 ? ceil_div(n, block_rows) : 0;
+    std::vector<int64_t> rp(n + 1, 0);
+    if (n > 0) {
+        HostStage& hst = host_stage();
+        DB_TRY(hst.reserve(sizeof(int64_t) * (n + 1) + 64));
+        int32_t* h_flag = reinterpret_cast<int32_t*>(static_cast<char*>(hst.ptr) + sizeof(int64_t) * (n + 1));
+        DB_HIP(hipMemcpyAsync(hst.ptr, A->rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+        DB_HIP(hipMemcpyAsync(h_flag, T.d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        DB_TRY(sync_stream(st));
+        std::memcpy(rp.data(), hst.ptr, sizeof(int64_t) * (n + 1));
+        const int32_t bad = *h_flag;
+        DB_TRY(stage_done(st));
+        if (bad) {
+            set_error("set 0: " + std::string(describe_bad(bad)));
+            return (bad & kLongRow) && !(bad & ~kLongRow) ? DIBELLA_EOVERFLOW : DIBELLA_EINVAL;
+        }
+    }
+    std::vector<dibella_csr_out> parts(nb);
+    int64_t total = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t r0 = b * block_rows, r1 = std::min(n, r0 + block_rows);
+        OvLayout B;
+        B.hs = L.hs;
+        OvSet& o = B.hs[0];
+        o.a_rowptr = A->rowptr + r0;
+        o.n = r1 - r0;
+        o.row_base = 0;
+        o.nnz_base = -rp[r0];   // segment words of the block's entries from 0
+        o.read_base = r0;
+        B.base = {0, r1 - r0};
+        B.total_rows = r1 - r0;
+        B.total_m = L.total_m;
+        B.total_nnz = rp[r1] - rp[r0];
+        B.bits_words = L.bits_words;
+        B.bits_planes = L.bits_planes;
+        // the block's workspace and rows of C are released at the end of
+        // the block (in stream order: the next block's work comes after)
+        Arena blk(ar.alloc_fn(), ar.free_fn(), ar.alloc_ctx(), st);
+        OvSet* d_bs;
+        int64_t* d_bb;
+        DB_TRY(upload_sets(B, blk, &d_bs, &d_bb));
+        dibella_overlap_out Cb;
+        DB_TRY(ov_rows(B, d_bs, d_bb, T, T.bnd ? T.bnd + r0 : nullptr, B.total_nnz, &Cb, blk, true));
+        DB_TRY(r_from_seeds_run(&Cb, r0, read_len, k, min_overlap, max_drift, min_density, &parts[b], blk, ar,
+                                true));
+        total += parts[b].nnz;
+    }
+    // R: the blocks' rows one after the other
+    int64_t* rrp;
+    int32_t *rcol, *rval;
+    DB_TRY(ar.output_n(n + 1, &rrp));
+    DB_TRY(ar.output_n(total, &rcol));
+    DB_TRY(ar.output_n(total, &rval));
+    if (n == 0) DB_TRY(fill_i64(rrp, 0, 1, st));
+    int64_t off = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t r0 = b * block_rows;
+        const dibella_csr_out& P = parts[b];
+        hipLaunchKernelGGL(k_shift_rowptr, dim3(grid_for(P.nrows + 1, 256, 1024)), dim3(256), 0, st, P.rowptr,
+                           P.nrows, off, rrp + r0);
+        DB_HIP(hipGetLastError());
+        if (P.nnz > 0) {
+            DB_HIP(hipMemcpyAsync(rcol + off, P.col, sizeof(int32_t) * P.nnz, hipMemcpyDeviceToDevice, st));
+            DB_HIP(hipMemcpyAsync(rval + off, P.val, sizeof(int32_t) * P.nnz, hipMemcpyDeviceToDevice, st));
+        }
+        off += P.nnz;
+    }
+    R->nrows = R->ncols = n;
+    R->nnz = total;
+    R->rowptr = rrp;
+    R->col = rcol;
+    R->val = rval;
+    *nblocks = (int32_t)nb;
     return DIBELLA_OK;
 }
 

@@ -22,6 +22,8 @@
 // packed (suffix << 2) | code.  Two passes, one wave per row: the first
 // computes every entry's value (or -1 when dropped) and the row's count,
 // a scan gives R's row pointers, the second compacts with wave ballots.
+// C may hold a block of consecutive rows of the whole matrix: row i of C is
+// then read row0 + i, and its columns range over all reads.
 #include "common.hpp"
 
 #include <cstring>
@@ -47,7 +49,8 @@ __device__ __forceinline__ int64_t rs_offset(int32_t a, int32_t b, int64_t lj, i
 }
 
 template <int WPB>
-__global__ __launch_bounds__(WPB* kWave) void k_rs_mark(int64_t n, int64_t nnz, const int64_t* __restrict__ rp,
+__global__ __launch_bounds__(WPB* kWave) void k_rs_mark(int64_t n, int64_t row0, int64_t ncols, int64_t nnz,
+                                                        const int64_t* __restrict__ rp,
                                                         const int32_t* __restrict__ col,
                                                         const int32_t* __restrict__ count,
                                                         const int32_t* __restrict__ seed,
@@ -64,16 +67,16 @@ __global__ __launch_bounds__(WPB* kWave) void k_rs_mark(int64_t n, int64_t nnz, 
         if ((i == 0 && lo != 0) || (i == n - 1 && hi != nnz) || lo < 0 || hi < lo || hi > nnz) {
             bad |= kRsBadRowptr;
         } else {
-            const int64_t li = len[i];
+            const int64_t li = len[row0 + i];
             if (li < 0 || li >= kRsMaxLen) bad |= kRsBadLength;
             for (int64_t e = lo + lane; e < hi; e += kWave) {
                 const int32_t j = col[e];
                 int32_t out = -1;
-                if (j < 0 || j >= n) {
+                if (j < 0 || j >= ncols) {
                     bad |= kRsBadCol;
                 } else {
                     if (e > lo && col[e - 1] >= j) bad |= kRsUnsorted;
-                    if (j != i) {
+                    if (j != row0 + i) {
                         const int32_t a = seed[4 * e], b = seed[4 * e + 1];
                         const int32_t a1 = seed[4 * e + 2], b1 = seed[4 * e + 3];
                         const int64_t lj = len[j];
@@ -144,23 +147,25 @@ __global__ __launch_bounds__(WPB* kWave) void k_rs_write(int64_t n, const int64_
 
 static const char* describe_rs_bad(int32_t bad) {
     if (bad & kRsBadRowptr) return "row pointers of C are not a valid CSR row pointer array";
-    if (bad & kRsBadCol) return "a column index of C is outside [0, nrows)";
+    if (bad & kRsBadCol) return "a column index of C is outside [0, ncols)";
     if (bad & kRsUnsorted) return "columns of C are not strictly increasing within a row";
     if (bad & kRsBadLength) return "a read length is negative or >= 2^28";
     if (bad & kRsBadSeed) return "a seed of an off-diagonal entry is missing or lies outside its read";
     return "malformed input";
 }
 
-int r_from_seeds_run(const dibella_overlap_out* C, const int32_t* read_len, int32_t k, int32_t min_overlap,
-                     int32_t max_drift, int32_t min_density, dibella_csr_out* R, Arena& ar) {
+int r_from_seeds_run(const dibella_overlap_out* C, int64_t row0, const int32_t* read_len, int32_t k,
+                     int32_t min_overlap, int32_t max_drift, int32_t min_density, dibella_csr_out* R, Arena& ar,
+                     Arena& out, bool out_as_work) {
     hipStream_t st = ar.stream();
     std::memset(R, 0, sizeof(*R));
-    const int64_t n = C->nrows, nnz = C->nnz;
-    if (n < 0 || nnz < 0 || C->ncols != n || k < 1 || k > 32 || min_overlap < 0) {
-        set_error("dibella_r_from_seeds: C must be square with non-negative sizes, k in [1, 32], min_overlap >= 0");
+    const int64_t n = C->nrows, nnz = C->nnz, ncols = C->ncols;
+    if (n < 0 || nnz < 0 || row0 < 0 || ncols < row0 + n || k < 1 || k > 32 || min_overlap < 0) {
+        set_error("dibella_r_from_seeds: C must have non-negative sizes and a column per read of its rows, "
+                  "k in [1, 32], min_overlap >= 0");
         return DIBELLA_EINVAL;
     }
-    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) {
+    if (ncols >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 40)) {
         set_error("dibella_r_from_seeds: nrows must be < 2^31 and nnz < 2^40");
         return DIBELLA_EOVERFLOW;
     }
@@ -172,7 +177,8 @@ int r_from_seeds_run(const dibella_overlap_out* C, const int32_t* read_len, int3
         set_error("dibella_r_from_seeds: entries in a matrix without rows");
         return DIBELLA_EINVAL;
     }
-    R->nrows = R->ncols = n;
+    R->nrows = n;
+    R->ncols = ncols;
     int32_t* tmp;
     int64_t* cnt;
     int32_t* d_flags;
@@ -180,13 +186,15 @@ int r_from_seeds_run(const dibella_overlap_out* C, const int32_t* read_len, int3
     DB_TRY(ar.work_n(nnz, &tmp));
     DB_TRY(ar.work_n(n, &cnt));
     DB_TRY(ar.work_n(1, &d_flags));
-    DB_TRY(ar.output_n(n + 1, &rrp));   // R's row pointers: their size is known before the sync
+    // R's row pointers: their size is known before the sync
+    DB_TRY(out_as_work ? out.work_n(n + 1, &rrp) : out.output_n(n + 1, &rrp));
     DB_TRY(fill_i32(d_flags, 0, 1, st));
     constexpr int WPB = 4;
     int tok = -1;
     DB_TRY(timing_begin(kPhRFromSeeds, st, &tok));
     if (n > 0) {
-        hipLaunchKernelGGL(k_rs_mark<WPB>, dim3(grid_for(n, WPB, 1 << 16)), dim3(WPB * kWave), 0, st, n, nnz,
+        hipLaunchKernelGGL(k_rs_mark<WPB>, dim3(grid_for(n, WPB, 1 << 16)), dim3(WPB * kWave), 0, st, n, row0,
+                           ncols, nnz,
                            C->rowptr, C->col, C->count, C->seed, read_len, k, min_overlap, max_drift, min_density,
                            tmp, cnt, d_flags);
         DB_HIP(hipGetLastError());
@@ -206,8 +214,8 @@ int r_from_seeds_run(const dibella_overlap_out* C, const int32_t* read_len, int3
     }
     const int64_t rnnz = h[0];
     int32_t *rcol, *rval;
-    DB_TRY(ar.output_n(rnnz, &rcol));
-    DB_TRY(ar.output_n(rnnz, &rval));
+    DB_TRY(out_as_work ? out.work_n(rnnz, &rcol) : out.output_n(rnnz, &rcol));
+    DB_TRY(out_as_work ? out.work_n(rnnz, &rval) : out.output_n(rnnz, &rval));
     if (n > 0 && rnnz > 0) {
         DB_TRY(timing_begin(kPhRFromSeeds, st, &tok));
         hipLaunchKernelGGL(k_rs_write<WPB>, dim3(grid_for(n, WPB, 1 << 16)), dim3(WPB * kWave), 0, st, n, C->rowptr,
