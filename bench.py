@@ -552,7 +552,69 @@ def batch_compare(db, synth, nsets: int, steps: int, tune_budget: float = 0.0):
             "tuning": tuned}
 
 
-def serve_compare(w_main, njobs: int, slots: int = 3, seed: int = 5000):
+def main_pool_entry(w_main):
+    """The timed step's reads as a layout job: A rebuilt with strand bits in
+    its values (what R from C's seeds needs), device resident."""
+    import dataclasses
+    from paper_2010_10055_amd import serve, synth
+    A1, _ = synth.kmer_matrix(w_main.reads, w_main.k, w_main.lo, w_main.hi, device="cuda:0", strand_bit=True)
+    return serve.pool_entry(dataclasses.replace(w_main, A=A1), "cuda:0")
+
+
+def blocked_compare(inp, nblocks=(4, 16), reps: int = 2):
+    """The overlap graph of one layout job built whole (dibella_overlap, then
+    R from C's seeds) and blocked (dibella_overlap_graph_blocked: C formed a
+    block of reads at a time): best wall time of `reps` builds and the peak
+    device memory the build allocates beyond its inputs; every blocked R is
+    checked equal to the whole one."""
+    import torch
+    import paper_2010_10055_amd as db
+    A, L = inp.A, inp.read_len
+    rest = (inp.k, inp.min_overlap, inp.max_drift, inp.min_density)
+
+    def whole():
+        C = db.overlap(A, inp.min_shared)
+        return db.r_from_seeds(C, L, *rest), 1
+
+    def blocked(nb):
+        rows = -(-A.nrows // nb)
+        return lambda: db.overlap_graph_blocked(A, inp.min_shared, L, *rest, block_rows=rows)
+
+    def measure(fn):
+        R, nb = fn()
+        torch.cuda.synchronize()
+        del R
+        best = None
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            R, nb = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+            if _ < reps - 1:
+                del R
+        peak = torch.cuda.max_memory_allocated() - base
+        return R, nb, best, peak
+
+    Rw, _, tw, pw = measure(whole)
+    out = {"reads": A.nrows, "nnz_R": Rw.nnz,
+           "whole": {"ms": round(tw * 1e3, 2), "peak_gib": round(pw / 2**30, 2)}}
+    log(f"  whole: {tw * 1e3:.1f} ms, peak {pw / 2**30:.2f} GiB")
+    for nb in nblocks:
+        Rb, got, tb, pb = measure(blocked(nb))
+        same = all(torch.equal(a, b) for a, b in ((Rb.rowptr, Rw.rowptr), (Rb.col, Rw.col), (Rb.val, Rw.val)))
+        if not same:
+            raise RuntimeError(f"blocked overlap graph ({nb} blocks) differs from the whole one")
+        out[f"blocks_{got}"] = {"ms": round(tb * 1e3, 2), "peak_gib": round(pb / 2**30, 2), "equal_to_whole": same}
+        log(f"  {got} blocks: {tb * 1e3:.1f} ms, peak {pb / 2**30:.2f} GiB, R equal to the whole build")
+        del Rb
+    del Rw
+    return out
+
+
+def serve_compare(w_main, njobs: int, slots: int = 3, seed: int = 5000, main_entry=None):
     """Serving: Poisson streams of layout jobs (overlap, R from C's seeds on
     the device, reduction): 90% of the jobs one of two instances of the
     large workload's recipe (50 Mbp genome, 40x, ~167k reads: the timed
@@ -562,14 +624,11 @@ def serve_compare(w_main, njobs: int, slots: int = 3, seed: int = 5000):
     its own stream) replay the same trace, at 0.8x the FIFO capacity
     measured on a probe (latency) and at 1.5x (saturation: throughput).
     Admission budget: the free device memory measured before the runs."""
-    import dataclasses
     import numpy as np
     import torch
-    from paper_2010_10055_amd import serve, synth
+    from paper_2010_10055_amd import serve
     t0 = time.perf_counter()
-    A1, _ = synth.kmer_matrix(w_main.reads, w_main.k, w_main.lo, w_main.hi, device="cuda:0", strand_bit=True)
-    pool = [serve.pool_entry(dataclasses.replace(w_main, A=A1), "cuda:0")]
-    del A1
+    pool = [main_entry if main_entry is not None else main_pool_entry(w_main)]
     log(f"  pool {w_main.name}#0 from the timed step's reads: footprint {pool[0][2] / 2**30:.2f} GiB")
     pool += serve.make_pool([(w_main.name, 1, seed, 1.0), ("tiny", 4, seed + 100, 1.0)], device="cuda:0", log=log)
     log(f"  serve pool {time.perf_counter() - t0:.1f} s")
@@ -643,6 +702,8 @@ def main():
     ap.add_argument("--tune-budget", type=float, default=30.0, help="seconds of autotuning for the batch (0 = off)")
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving comparison (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=3, help="slots of continuous batching")
+    ap.add_argument("--blocks", type=int, nargs="*", default=[4, 16],
+                    help="block counts of the blocked overlap graph comparison (none = skip)")
     ap.add_argument("--calib-copy", action="store_true", help="only run the reference kernels used to scale counters")
     ap.add_argument("--gather-probe", action="store_true", help="only measure random-gather rates by footprint")
     ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
@@ -801,12 +862,18 @@ def main():
         batch = batch_compare(db, synth, args.batch_sets, max(1, min(args.steps, 5)), args.tune_budget)
         db.set_tuning(**default_tuning)
 
-    served = None
-    if args.serve_jobs > 0:
-        log(f"serving comparison ({args.serve_jobs} jobs per run) ...")
+    served = blocked = None
+    entry = None
+    if args.serve_jobs > 0 or args.blocks:
         del A, R
         torch.cuda.empty_cache()
-        served = serve_compare(w, args.serve_jobs, args.serve_slots)
+        entry = main_pool_entry(w)
+    if args.blocks:
+        log(f"blocked overlap graph ({args.blocks} blocks) vs whole ...")
+        blocked = blocked_compare(entry[1], tuple(args.blocks))
+    if args.serve_jobs > 0:
+        log(f"serving comparison ({args.serve_jobs} jobs per run) ...")
+        served = serve_compare(w, args.serve_jobs, args.serve_slots, main_entry=entry)
 
     out = {
         "metric": "semiring products/s (A*A^T multiplies + transitive-reduction walks)",
@@ -834,6 +901,7 @@ def main():
         "host_syncs": {"overlap": ov_stats["host_syncs"], "tr": tr_stats["host_syncs"]},
         "roofline": roofline,
         "batch": batch,
+        "blocked": blocked,
         "serve": served,
         "cpu_baseline": cpu,
         "cpu_parallel": cpu_par,
