@@ -209,13 +209,18 @@ int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, 
  * A, min_shared: as dibella_overlap (one set).  read_len, k, min_overlap,
  * max_drift, min_density: as dibella_r_from_seeds.  block_rows >= 1 (a
  * value >= nrows gives one block).  R: n x n, allocated through alloc;
- * *nblocks (may be NULL) receives the number of blocks.  Peak workspace:
- * what dibella_overlap needs for A^T, plus one block's row-phase workspace
- * and C rows, plus R so far.
+ * *nblocks (may be NULL) receives the number of blocks.  Where A has enough
+ * columns for the sliced segment pass, A^T is itself built over as many
+ * column ranges as there are blocks (at most one per slice), one range's
+ * partition buffers at a time.  Peak workspace: A^T (8 bytes per entry),
+ * the column records and slice table, plus the larger of one column range's
+ * partition buffers and one block's row-phase workspace and C rows, plus R
+ * so far.
  * Errors: those of dibella_overlap and dibella_r_from_seeds; EINVAL for
- * block_rows < 1.  Host synchronisation: one stream sync to read A's row
- * pointers, then per block the syncs of dibella_overlap's row phases (two,
- * or three on retry-table overflow) and one of dibella_r_from_seeds.
+ * block_rows < 1.  Host synchronisation: one stream sync for the column
+ * ranges' sizes (with column ranges), one to read A's row pointers, then per
+ * block the syncs of dibella_overlap's row phases (two, or three on
+ * retry-table overflow) and one of dibella_r_from_seeds.
  */
 int dibella_overlap_graph_blocked(const dibella_csr* A, int32_t min_shared, const int32_t* read_len,
                                   int32_t k, int32_t min_overlap, int32_t max_drift,

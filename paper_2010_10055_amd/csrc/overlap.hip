@@ -201,7 +201,8 @@ __host__ __device__ __forceinline__ int slice_of(int64_t c, SliceMap sm) {
 // slices, the row's slice boundaries are recorded as well, slice-major:
 // bnd[s * rows + g] = first entry of row g (relative to its start) whose
 // column lies in slice s or later, for s = 0..count (s = count: the row
-// length).
+// length).  Without `keys` only the checks and the boundaries are made (A^T
+// is then built column range by column range from the boundaries).
 // ---------------------------------------------------------------------------
 constexpr int kKeysIlp = 8;
 
@@ -265,8 +266,10 @@ __global__ __launch_bounds__(WPB* kWave) void k_ov_keys(const OvSet* __restrict_
                     if (in) {
                         if (!ok) bad |= kBadCol;
                         // invalid columns get key 0: the call fails before A^T is used
-                        keys[S.nnz_base + e] = ok ? (uint32_t)(S.col_base + k) : 0u;
-                        pays[S.nnz_base + e] = ((uint64_t)(uint32_t)vv[q] << 32) | (uint64_t)(uint32_t)i;
+                        if (keys) {
+                            keys[S.nnz_base + e] = ok ? (uint32_t)(S.col_base + k) : 0u;
+                            pays[S.nnz_base + e] = ((uint64_t)(uint32_t)vv[q] << 32) | (uint64_t)(uint32_t)i;
+                        }
                     }
                     if (rb) {
                         // slices this entry opens: (slice of the previous entry, own slice];
@@ -532,17 +535,69 @@ __global__ void k_ov_fine_start(const int64_t* __restrict__ offs2, const int64_t
     }
 }
 
+// A^T over column ranges (one set): the range [c0, c1) holds the columns of
+// slices [s0, s1), so row g's entries in it are [bnd[s0][g], bnd[s1][g]).
+// Boundaries of a row that failed validation may be incomplete: they are
+// clamped to the row, and the call fails before A^T is read.
+__device__ __forceinline__ int2 range_of_row(const int32_t* bnd, int64_t stride, int64_t g, int s0, int s1,
+                                             int32_t L) {
+    const int32_t a = min(max(bnd[(int64_t)s0 * stride + g], 0), L);
+    const int32_t z = min(max(bnd[(int64_t)s1 * stride + g], a), L);
+    return make_int2(a, z);
+}
+
+// Entries per row in the range, and the range's total.
+__global__ __launch_bounds__(256) void k_ov_range_count(const OvSet* __restrict__ sets, int64_t rows,
+                                                        const int32_t* __restrict__ bnd, int s0, int s1,
+                                                        int32_t* __restrict__ cnt) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < rows; g += (int64_t)gridDim.x * blockDim.x) {
+        const OvSet& S = sets[0];
+        const int64_t lo = S.a_rowptr[g], hi = S.a_rowptr[g + 1];
+        const int32_t L = (lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30)) ? 0 : (int32_t)(hi - lo);
+        const int2 r = range_of_row(bnd, rows, g, s0, s1, L);
+        cnt[g] = r.y - r.x;
+    }
+}
+
+// The range's pairs, row by row at off[g]: key = column - c0 (0 for a column
+// outside the range, which only a row that failed validation has), value =
+// (position << 32) | read.  Nothing is written at or past `cap` (the pairs
+// the host sized the buffers for; only an invalid A has more).
+__global__ __launch_bounds__(256) void k_ov_range_keys(const OvSet* __restrict__ sets, int64_t rows,
+                                                       const int32_t* __restrict__ bnd, int s0, int s1, int64_t c0,
+                                                       int64_t c1, const int64_t* __restrict__ off, int64_t cap,
+                                                       uint32_t* __restrict__ keys, uint64_t* __restrict__ pays) {
+    const int lane = lane_id();
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + __builtin_amdgcn_readfirstlane(wave_id());
+         g < rows; g += (int64_t)gridDim.x * (blockDim.x / kWave)) {
+        const OvSet& S = sets[0];
+        const int64_t lo = S.a_rowptr[g], hi = S.a_rowptr[g + 1];
+        const int32_t L = (lo < 0 || hi < lo || hi > S.nnz || hi - lo >= (int64_t(1) << 30)) ? 0 : (int32_t)(hi - lo);
+        const int2 r = range_of_row(bnd, rows, g, s0, s1, L);
+        const int64_t o = off[g] - r.x;
+        for (int32_t q = r.x + lane; q < r.y; q += kWave) {
+            if (o + q >= cap) break;
+            const int32_t k = gload(S.a_col + lo + q);
+            const int32_t v = gload(S.a_val + lo + q);
+            keys[o + q] = (k >= c0 && k < c1) ? (uint32_t)(k - c0) : 0u;
+            pays[o + q] = ((uint64_t)(uint32_t)v << 32) | (uint64_t)(uint32_t)g;
+        }
+    }
+}
+
 // One workgroup per bucket of 2^low columns (first pair at
 // start[b * stride], 16-bit keys holding at least the low `low` bits), sorted
 // in sweeps of 2^sub columns (sub = min(low, 12)): per sweep the pairs of its
 // columns are counted, placed in LDS and written out as one contiguous run
 // (coalesced) when they fit kStageCap, else placed directly.  Only a staged
 // sweep writes the two-pair records (otherwise every column gets its
-// segment).
+// segment).  The pairs land in at[] at their input positions; a record's
+// start is that position plus rec_base (A^T built column range by column
+// range: `at` points at the range's first slot, rec_base is its index).
 __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
     const int64_t* __restrict__ start, int64_t stride, int low, int sub, int64_t total_m, int64_t cap,
     const uint16_t* __restrict__ skey, const uint64_t* __restrict__ spay, uint64_t* __restrict__ rec,
-    uint64_t* __restrict__ at) {
+    uint64_t* __restrict__ at, int64_t rec_base) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem);
     uint64_t* stage = reinterpret_cast<uint64_t*>(hist + (1 << sub));
@@ -622,7 +677,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_ov_bucket_sort(
             const uint32_t end = hist[c];
             const uint32_t first = c ? hist[c - 1] : (uint32_t)base;
             const uint32_t n_c = end - first;
-            uint64_t r = ((uint64_t)first << 24) | (uint64_t)n_c;
+            uint64_t r = ((uint64_t)(first + rec_base) << 24) | (uint64_t)n_c;
             if (staged && n_c == 2) {
                 const uint64_t x = stage[first - base] ^ stage[first - base + 1];   // pairs: (pos << 32) | read
                 r = kPairTag | ((x >> 32) << 24) | (x & 0xFFFFFFull);
@@ -1924,49 +1979,175 @@ struct OvTransposed {
     int nsets = 0;
 };
 
+// Bucketed counting sort of N pairs by key (column in [0, M)): keys_a /
+// pays_a hold them; keys_b / pays_b are the partition passes' second
+// buffers.  Writes A^T to at_dest (the range's first slot; it may be pays_a
+// for a two-level sort or pays_b for a three-level one, the buffer the last
+// pass does not read) and every column's record to rec[0, M), starts
+// counted from rec_base.  Two levels (partition the pairs into buckets of
+// 2^low columns, then a staged counting sort per bucket) while the buckets
+// fit one partition; three levels beyond that (partition into segments of
+// 2^lowc columns, partition every segment into buckets of 2^12 columns,
+// staged sort per bucket), so that every bucket is sorted in staged sweeps
+// with 16-bit keys and its two-pair columns carry their pairs.  Tables come
+// from `scr`.
+struct SortPlan {
+    int low, lowc, fine_per, per_block;
+    bool three;
+    int64_t nbuckets, nsort, nchunks, npart, nchunks2, ncount2;
+};
+
+static SortPlan sort_plan(int64_t M, int64_t N) {
+    SortPlan P{};
+    const int col_bits = ceil_log2_i64(std::max<int64_t>(M, 2));
+    // buckets of at most 2^13 columns: the last level then sorts each in two
+    // staged sweeps (2^14 took four sweeps, each re-reading the bucket's
+    // keys, and left a half-empty last round of workgroups on mid)
+    P.low = std::min(kTwoLevelLow, std::max(10, col_bits - 8));
+    P.three = ceil_div(M, int64_t(1) << kTwoLevelLow) > kMaxBuckets;
+    P.lowc = kCoarseLow;
+    if (P.three) {
+        P.low = kStageBits;
+        while (ceil_div(M, int64_t(1) << P.lowc) > kMaxBuckets) ++P.lowc;
+    }
+    P.fine_per = P.three ? 1 << (P.lowc - P.low) : 0;                          // buckets per segment
+    P.nbuckets = ceil_div(M, int64_t(1) << (P.three ? P.lowc : P.low));       // first level
+    P.nsort = ceil_div(M, int64_t(1) << P.low);                               // sorted by the last level
+    P.nchunks = ceil_div(N, kChunk);
+    // A first-level workgroup takes several chunks when that keeps the
+    // (bucket, workgroup) count table small beside A.
+    P.per_block = 1;
+    while (P.nbuckets * ceil_div(P.nchunks, P.per_block) > std::max<int64_t>(int64_t(1) << 22, N / 8))
+        P.per_block *= 2;
+    P.npart = ceil_div(P.nchunks, P.per_block);   // first-level workgroups
+    // second level: one chunk per workgroup, segments cut separately (at
+    // most one partial chunk per segment)
+    P.nchunks2 = P.three ? P.nchunks + P.nbuckets : 0;
+    P.ncount2 = P.nchunks2 * P.fine_per;
+    return P;
+}
+
+// Bytes of the tables sort_pairs takes from its arena (plus the keys and
+// pairs buffers: 2 * 4 + 2 * 8 per pair, counted by the caller).
+static size_t sort_table_bytes(const SortPlan& P) {
+    auto pad = [](size_t b) { return Arena::padded(b); };
+    size_t est = pad(4 * P.nbuckets * P.npart) + pad(8 * (P.nbuckets * P.npart + 1));
+    if (P.three)
+        est += pad(4 * P.ncount2) + pad(8 * (P.ncount2 + 1)) + 2 * pad(8 * (P.nbuckets + 1)) +
+               pad(8 * (P.nbuckets * P.fine_per + 1));
+    est += 2 * pad(8 * scan_workspace_elems(std::max({P.nbuckets * P.npart, P.ncount2, int64_t(1)}))) +
+           8 * Arena::padded(1);
+    return est;
+}
+
+static int sort_pairs(const SortPlan& P, int64_t M, int64_t N, uint32_t* keys_a, uint32_t* keys_b, uint64_t* pays_a,
+                      uint64_t* pays_b, uint64_t* at_dest, uint64_t* rec, int64_t rec_base, Arena& scr) {
+    hipStream_t st = scr.stream();
+    if (N == 0) return DIBELLA_OK;
+    int tok = -1;
+    static std::atomic<bool> lds_ok{false};
+    if (!lds_ok.load(std::memory_order_acquire)) {
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<false, uint16_t>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<false, uint32_t>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<true, uint16_t>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+        DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kLdsLimit));
+        lds_ok.store(true, std::memory_order_release);
+    }
+    const bool three = P.three;
+    const int low = P.low, lowc = P.lowc, fine_per = P.fine_per, per_block = P.per_block;
+    const int64_t nbuckets = P.nbuckets, npart = P.npart, nchunks2 = P.nchunks2, ncount2 = P.ncount2;
+    const PartSeg flat{nullptr, nullptr, 0};
+    int32_t* pcounts;
+    int64_t* poffs;
+    const int64_t ncount = nbuckets * npart;
+    DB_TRY(scr.work_n(ncount, &pcounts));
+    DB_TRY(scr.work_n(ncount + 1, &poffs));
+    const int low1 = three ? lowc : low;
+    DB_TRY(timing_begin(kPhPartCount, st, &tok));
+    hipLaunchKernelGGL(k_ov_part_count<false>, dim3((unsigned)npart), dim3(kPartBlock), (size_t)nbuckets * 4, st,
+                       keys_a, N, per_block, low1, (int)nbuckets, flat, pcounts);
+    DB_HIP(hipGetLastError());
+    DB_TRY(timing_end(tok, st));
+    DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, scr));
+    uint16_t* keys_a16 = reinterpret_cast<uint16_t*>(keys_a);
+    uint16_t* keys_b16 = reinterpret_cast<uint16_t*>(keys_b);
+    DB_TRY(timing_begin(kPhPartScatter, st, &tok));
+    if (!three)   // the last level reads the low `low` <= 13 bits: 16-bit keys
+        hipLaunchKernelGGL((k_ov_part_scatter<false, uint16_t>), dim3((unsigned)npart), dim3(kPartBlock),
+                           part_scatter_lds(nbuckets), st, keys_a, pays_a, N, per_block, low1, (int)nbuckets, flat,
+                           poffs, N, keys_b16, pays_b);
+    else          // the second level needs lowc bits
+        hipLaunchKernelGGL((k_ov_part_scatter<false, uint32_t>), dim3((unsigned)npart), dim3(kPartBlock),
+                           part_scatter_lds(nbuckets), st, keys_a, pays_a, N, per_block, low1, (int)nbuckets, flat,
+                           poffs, N, keys_b, pays_b);
+    DB_HIP(hipGetLastError());
+    DB_TRY(timing_end(tok, st));
+    const int64_t* sort_start = poffs;   // first pair of bucket b: sort_start[b * sort_stride]
+    int64_t sort_stride = npart;
+    const uint16_t* sort_keys = keys_b16;
+    const uint64_t* sort_pays = pays_b;
+    if (three) {
+        int64_t *seg_start, *chunk_base, *fine_start, *poffs2;
+        int32_t* pcounts2;
+        DB_TRY(scr.work_n(nbuckets + 1, &seg_start));
+        DB_TRY(scr.work_n(nbuckets + 1, &chunk_base));
+        DB_TRY(scr.work_n(nbuckets * fine_per + 1, &fine_start));
+        DB_TRY(scr.work_n(ncount2, &pcounts2));
+        DB_TRY(scr.work_n(ncount2 + 1, &poffs2));
+        hipLaunchKernelGGL(k_ov_seg_chunks, dim3(1), dim3(kSegChunkBlock), 0, st, poffs, npart, (int)nbuckets, N,
+                           seg_start, chunk_base);
+        DB_HIP(hipGetLastError());
+        const PartSeg ps{seg_start, chunk_base, (int32_t)nbuckets};
+        DB_TRY(timing_begin(kPhPart2Count, st, &tok));
+        hipLaunchKernelGGL(k_ov_part_count<true>, dim3((unsigned)nchunks2), dim3(kPartBlock), (size_t)fine_per * 4,
+                           st, keys_b, N, 1, low, fine_per, ps, pcounts2);
+        DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
+        DB_TRY(scan_exclusive(pcounts2, poffs2, ncount2, nullptr, scr));
+        DB_TRY(timing_begin(kPhPart2Scatter, st, &tok));
+        hipLaunchKernelGGL((k_ov_part_scatter<true, uint16_t>), dim3((unsigned)nchunks2), dim3(kPartBlock),
+                           part_scatter_lds(fine_per), st, keys_b, pays_b, N, 1, low, fine_per, ps, poffs2, N,
+                           keys_a16, pays_a);
+        DB_HIP(hipGetLastError());
+        DB_TRY(timing_end(tok, st));
+        hipLaunchKernelGGL(k_ov_fine_start, dim3(grid_for(nbuckets * fine_per + 1, 256, 4096)), dim3(256), 0, st,
+                           poffs2, chunk_base, (int)nbuckets, fine_per, nbuckets * fine_per, fine_start);
+        DB_HIP(hipGetLastError());
+        sort_start = fine_start;
+        sort_stride = 1;
+        sort_keys = keys_a16;
+        sort_pays = pays_a;
+    }
+    // staged sweeps of 2^12 columns (one sweep for buckets of at most that)
+    DB_TRY(timing_begin(kPhBucketSort, st, &tok));
+    hipLaunchKernelGGL((k_ov_bucket_sort), dim3((unsigned)P.nsort), dim3(kBucketBlock),
+                       ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, sort_start, sort_stride, low,
+                       std::min(low, kStageBits), M, N, sort_keys, sort_pays, rec, at_dest, rec_base);
+    DB_HIP(hipGetLastError());
+    DB_TRY(timing_end(tok, st));
+    return DIBELLA_OK;
+}
+
 // Steps O0 and O1 over every set of L (on the device as d_sets, d_base):
 // validate A, build A^T and, with slices, the rows' slice boundaries.  The
 // results come from `ar` (they live as long as it); the partition passes'
 // keys and pairs come from a scratch arena released on return (its frees
-// are ordered on the stream after the kernels that use them).
+// are ordered on the stream after the kernels that use them).  With
+// col_ranges > 1 (one set with slices only) A^T is built over that many
+// column ranges of whole slices, one after the other, each range's pairs
+// gathered from the rows by their slice boundaries, so that the partition
+// buffers hold one range's pairs at a time.
 static int ov_transpose(const OvLayout& L, const OvSet* d_sets, const int64_t* d_base, uint32_t flags, Arena& ar,
-                        OvTransposed* T) {
+                        OvTransposed* T, int col_ranges = 1) {
     hipStream_t st = ar.stream();
     const int nsets = (int)L.hs.size();
     const int64_t total_rows = L.total_rows, total_m = L.total_m, total_nnz = L.total_nnz;
-    // ---- transpose plan.  Two levels (partition the pairs into buckets of
-    // 2^low columns, then a staged counting sort per bucket) while the
-    // buckets fit one partition; three levels beyond that (partition into
-    // segments of 2^lowc columns, partition every segment into buckets of
-    // 2^12 columns, staged sort per bucket), so that every bucket is sorted
-    // in staged sweeps with 16-bit keys and its two-pair columns carry
-    // their pairs.
-    const int col_bits = ceil_log2_i64(std::max<int64_t>(total_m, 2));
-    // buckets of at most 2^13 columns: the last level then sorts each in two
-    // staged sweeps (2^14 took four sweeps, each re-reading the bucket's
-    // keys, and left a half-empty last round of workgroups on mid)
-    int low = std::min(kTwoLevelLow, std::max(10, col_bits - 8));
-    const bool three = ceil_div(total_m, int64_t(1) << kTwoLevelLow) > kMaxBuckets;
-    int lowc = kCoarseLow;
-    if (three) {
-        low = kStageBits;
-        while (ceil_div(total_m, int64_t(1) << lowc) > kMaxBuckets) ++lowc;
-    }
-    const int fine_per = three ? 1 << (lowc - low) : 0;                               // buckets per segment
-    const int64_t nbuckets = ceil_div(total_m, int64_t(1) << (three ? lowc : low));   // first level
-    const int64_t nsort = ceil_div(total_m, int64_t(1) << low);                       // sorted by the last level
-    const int64_t nchunks = ceil_div(total_nnz, kChunk);
-    // A first-level workgroup takes several chunks when that keeps the
-    // (bucket, workgroup) count table small beside A.
-    int per_block = 1;
-    while (nbuckets * ceil_div(nchunks, per_block) > std::max<int64_t>(int64_t(1) << 22, total_nnz / 8))
-        per_block *= 2;
-    const int64_t npart = ceil_div(nchunks, per_block);   // first-level workgroups
-    // second level: one chunk per workgroup, segments cut separately (at
-    // most one partial chunk per segment)
-    const int64_t nchunks2 = three ? nchunks + nbuckets : 0;
-    const int64_t ncount2 = nchunks2 * fine_per;
     const SliceMap sm = slice_plan(total_m, total_rows, total_nnz);
+    const int K = (nsets == 1 && sm.count > 0 && total_nnz > 0) ? std::max(1, std::min(col_ranges, (int)sm.count)) : 1;
     // ---- what the row phases keep: one reservation
     {
         auto pad = [](size_t b) { return Arena::padded(b); };
@@ -1976,135 +2157,111 @@ static int ov_transpose(const OvLayout& L, const OvSet* d_sets, const int64_t* d
     }
     int32_t* d_flags;
     uint64_t* rec;
-    uint64_t* at_out;   // A^T: where the last pass writes
+    uint64_t* at = nullptr;   // A^T (K > 1: its own buffer; else the last pass's output buffer, below)
     int32_t* bnd = nullptr;
     DB_TRY(ar.work_n(nsets, &d_flags));
     DB_TRY(ar.work_n(std::max<int64_t>(total_m, 1), &rec));
-    DB_TRY(ar.work_n(total_nnz, &at_out));
+    if (K > 1) DB_TRY(ar.work_n(total_nnz, &at));
     if (sm.count) DB_TRY(ar.work_n((size_t)total_rows * (sm.count + 1), &bnd));
-    // ---- the partition passes' buffers
-    Arena scr(ar.alloc_fn(), ar.free_fn(), ar.alloc_ctx(), st);
-    {
-        auto pad = [](size_t b) { return Arena::padded(b); };
-        size_t est = 2 * pad(4 * total_nnz) + pad(8 * total_nnz);
-        est += pad(4 * nbuckets * npart) + pad(8 * (nbuckets * npart + 1));
-        if (three)
-            est += pad(4 * ncount2) + pad(8 * (ncount2 + 1)) + 2 * pad(8 * (nbuckets + 1)) +
-                   pad(8 * (nbuckets * fine_per + 1));
-        est += 2 * pad(8 * scan_workspace_elems(std::max({nbuckets * npart, ncount2, int64_t(1)}))) +
-               8 * Arena::padded(1);
-        DB_TRY(scr.reserve(est));
-    }
-    uint32_t *keys_a, *keys_b;
-    uint64_t* pays_x;   // the pairs buffer that is not A^T
-    DB_TRY(scr.work_n(total_nnz, &keys_a));
-    DB_TRY(scr.work_n(total_nnz, &keys_b));
-    DB_TRY(scr.work_n(total_nnz, &pays_x));
-    // the three-level sort ends in the second pairs buffer, the two-level
-    // one in the first
-    uint64_t* pays_a = three ? pays_x : at_out;
-    uint64_t* pays_b = three ? at_out : pays_x;
     DB_TRY(fill_i32(d_flags, 0, nsets, st));
-
     int tok = -1;
     constexpr int WPB = 4;
     const int grid_rows = grid_for(total_rows, WPB, 1 << 16);
     const int checks = (flags & DIBELLA_NO_VALIDATE) ? 0 : 1;
-    // empty segments where no pass writes them (the bucket sort writes every column of a non-empty A)
+    // empty segments where no pass writes them (the bucket sort writes every
+    // column of a range with entries)
     if (total_nnz == 0) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(rec), 0, 2 * std::max<int64_t>(total_m, 1), st));
-    else DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
-    if (total_rows > 0) {
+
+    if (K == 1) {
+        const SortPlan P = sort_plan(total_m, total_nnz);
+        Arena scr(ar.alloc_fn(), ar.free_fn(), ar.alloc_ctx(), st);
+        DB_TRY(scr.reserve(2 * Arena::padded(4 * total_nnz) + Arena::padded(8 * total_nnz) + sort_table_bytes(P)));
+        uint32_t *keys_a, *keys_b;
+        uint64_t* pays_x;   // the pairs buffer that does not end as A^T
+        DB_TRY(scr.work_n(total_nnz, &keys_a));
+        DB_TRY(scr.work_n(total_nnz, &keys_b));
+        DB_TRY(scr.work_n(total_nnz, &pays_x));
+        uint64_t* at_out;
+        DB_TRY(ar.work_n(total_nnz, &at_out));
+        // the three-level sort ends in the second pairs buffer, the two-level
+        // one in the first
+        uint64_t* pays_a = P.three ? pays_x : at_out;
+        uint64_t* pays_b = P.three ? at_out : pays_x;
+        if (total_nnz > 0) DB_TRY(fill_i32(reinterpret_cast<int32_t*>(keys_a), 0, total_nnz, st));   // keys of skipped entries
+        if (total_rows > 0) {
+            DB_TRY(timing_begin(kPhKeys, st, &tok));
+            hipLaunchKernelGGL(k_ov_keys<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets, d_base,
+                               total_rows, keys_a, pays_a, d_flags, checks, sm, bnd);
+            DB_HIP(hipGetLastError());
+            DB_TRY(timing_end(tok, st));
+        }
+        DB_TRY(sort_pairs(P, total_m, total_nnz, keys_a, keys_b, pays_a, pays_b, at_out, rec, 0, scr));
+        at = at_out;
+    } else {
+        // checks and slice boundaries only
         DB_TRY(timing_begin(kPhKeys, st, &tok));
         hipLaunchKernelGGL(k_ov_keys<WPB>, dim3(grid_rows), dim3(WPB * kWave), 0, st, d_sets, nsets, d_base,
-                           total_rows, keys_a, pays_a, d_flags, checks, sm, bnd);
+                           total_rows, (uint32_t*)nullptr, (uint64_t*)nullptr, d_flags, checks, sm, bnd);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
-    }
-    if (total_nnz > 0) {
-        static std::atomic<bool> lds_ok{false};
-        if (!lds_ok.load(std::memory_order_acquire)) {
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<false, uint16_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<false, uint32_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_part_scatter<true, uint16_t>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            DB_HIP(hipFuncSetAttribute((const void*)k_ov_bucket_sort,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-            lds_ok.store(true, std::memory_order_release);
+        // range k: slices [S k / K, S (k + 1) / K); its first column is the
+        // first c with slice_of(c) >= that slice
+        std::vector<int> s_of(K + 1);
+        std::vector<int64_t> c_of(K + 1);
+        for (int k = 0; k <= K; ++k) {
+            s_of[k] = (int)((int64_t)sm.count * k / K);
+            const uint64_t num = (uint64_t)s_of[k] << 32;
+            c_of[k] = k == K ? total_m : std::min<int64_t>(total_m, (int64_t)((num + sm.mul - 1) / sm.mul));
         }
-        const PartSeg flat{nullptr, nullptr, 0};
-        int32_t* pcounts;
-        int64_t* poffs;
-        const int64_t ncount = nbuckets * npart;
-        DB_TRY(scr.work_n(ncount, &pcounts));
-        DB_TRY(scr.work_n(ncount + 1, &poffs));
-        const int low1 = three ? lowc : low;
-        DB_TRY(timing_begin(kPhPartCount, st, &tok));
-        hipLaunchKernelGGL(k_ov_part_count<false>, dim3((unsigned)npart), dim3(kPartBlock), (size_t)nbuckets * 4, st,
-                           keys_a, total_nnz, per_block, low1, (int)nbuckets, flat, pcounts);
-        DB_HIP(hipGetLastError());
-        DB_TRY(timing_end(tok, st));
-        DB_TRY(scan_exclusive(pcounts, poffs, ncount, nullptr, scr));
-        uint16_t* keys_a16 = reinterpret_cast<uint16_t*>(keys_a);
-        uint16_t* keys_b16 = reinterpret_cast<uint16_t*>(keys_b);
-        DB_TRY(timing_begin(kPhPartScatter, st, &tok));
-        if (!three)   // the last level reads the low `low` <= 13 bits: 16-bit keys
-            hipLaunchKernelGGL((k_ov_part_scatter<false, uint16_t>), dim3((unsigned)npart), dim3(kPartBlock),
-                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low1,
-                               (int)nbuckets, flat, poffs, total_nnz, keys_b16, pays_b);
-        else          // the second level needs lowc bits
-            hipLaunchKernelGGL((k_ov_part_scatter<false, uint32_t>), dim3((unsigned)npart), dim3(kPartBlock),
-                               part_scatter_lds(nbuckets), st, keys_a, pays_a, total_nnz, per_block, low1,
-                               (int)nbuckets, flat, poffs, total_nnz, keys_b, pays_b);
-        DB_HIP(hipGetLastError());
-        DB_TRY(timing_end(tok, st));
-        const int64_t* sort_start = poffs;   // first pair of bucket b: sort_start[b * sort_stride]
-        int64_t sort_stride = npart;
-        const uint16_t* sort_keys = keys_b16;
-        const uint64_t* sort_pays = pays_b;
-        if (three) {
-            int64_t *seg_start, *chunk_base, *fine_start, *poffs2;
-            int32_t* pcounts2;
-            DB_TRY(scr.work_n(nbuckets + 1, &seg_start));
-            DB_TRY(scr.work_n(nbuckets + 1, &chunk_base));
-            DB_TRY(scr.work_n(nbuckets * fine_per + 1, &fine_start));
-            DB_TRY(scr.work_n(ncount2, &pcounts2));
-            DB_TRY(scr.work_n(ncount2 + 1, &poffs2));
-            hipLaunchKernelGGL(k_ov_seg_chunks, dim3(1), dim3(kSegChunkBlock), 0, st, poffs, npart, (int)nbuckets,
-                               total_nnz, seg_start, chunk_base);
+        // every range's pair count, read at one synchronisation
+        int32_t* cnt;
+        int64_t* off;
+        DB_TRY(ar.work_n(total_rows, &cnt));
+        DB_TRY(ar.work_n((size_t)(total_rows + 1) * K, &off));
+        for (int k = 0; k < K; ++k) {
+            hipLaunchKernelGGL(k_ov_range_count, dim3(grid_for(total_rows, 256, 4096)), dim3(256), 0, st, d_sets,
+                               total_rows, bnd, s_of[k], s_of[k + 1], cnt);
             DB_HIP(hipGetLastError());
-            const PartSeg ps{seg_start, chunk_base, (int32_t)nbuckets};
-            DB_TRY(timing_begin(kPhPart2Count, st, &tok));
-            hipLaunchKernelGGL(k_ov_part_count<true>, dim3((unsigned)nchunks2), dim3(kPartBlock),
-                               (size_t)fine_per * 4, st, keys_b, total_nnz, 1, low, fine_per, ps, pcounts2);
+            DB_TRY(scan_exclusive(cnt, off + (int64_t)(total_rows + 1) * k, total_rows, nullptr, ar));
+        }
+        HostStage& hst = host_stage();
+        DB_TRY(hst.reserve(sizeof(int64_t) * K + 64));
+        int64_t* h_tot = static_cast<int64_t*>(hst.ptr);
+        for (int k = 0; k < K; ++k)
+            DB_HIP(hipMemcpyAsync(h_tot + k, off + (int64_t)(total_rows + 1) * k + total_rows, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, st));
+        DB_TRY(sync_stream(st));
+        std::vector<int64_t> tot(h_tot, h_tot + K);
+        DB_TRY(stage_done(st));
+        int64_t base = 0;
+        for (int k = 0; k < K; ++k) {
+            const int64_t M = c_of[k + 1] - c_of[k], N = std::min(tot[k], total_nnz - base);
+            if (M <= 0) continue;
+            if (N <= 0) {
+                DB_TRY(fill_i32(reinterpret_cast<int32_t*>(rec + c_of[k]), 0, 2 * M, st));
+                continue;
+            }
+            const SortPlan P = sort_plan(M, N);
+            Arena scr(ar.alloc_fn(), ar.free_fn(), ar.alloc_ctx(), st);
+            DB_TRY(scr.reserve(2 * Arena::padded(4 * N) + 2 * Arena::padded(8 * N) + sort_table_bytes(P)));
+            uint32_t *keys_a, *keys_b;
+            uint64_t *pays_a, *pays_b;
+            DB_TRY(scr.work_n(N, &keys_a));
+            DB_TRY(scr.work_n(N, &keys_b));
+            DB_TRY(scr.work_n(N, &pays_a));
+            DB_TRY(scr.work_n(N, &pays_b));
+            DB_TRY(timing_begin(kPhKeys, st, &tok));
+            hipLaunchKernelGGL(k_ov_range_keys, dim3(grid_for(total_rows, 4, 1 << 16)), dim3(256), 0, st, d_sets,
+                               total_rows, bnd, s_of[k], s_of[k + 1], c_of[k], c_of[k + 1],
+                               off + (int64_t)(total_rows + 1) * k, N, keys_a, pays_a);
             DB_HIP(hipGetLastError());
             DB_TRY(timing_end(tok, st));
-            DB_TRY(scan_exclusive(pcounts2, poffs2, ncount2, nullptr, scr));
-            DB_TRY(timing_begin(kPhPart2Scatter, st, &tok));
-            hipLaunchKernelGGL((k_ov_part_scatter<true, uint16_t>), dim3((unsigned)nchunks2), dim3(kPartBlock),
-                               part_scatter_lds(fine_per), st, keys_b, pays_b, total_nnz, 1, low, fine_per, ps,
-                               poffs2, total_nnz, keys_a16, pays_a);
-            DB_HIP(hipGetLastError());
-            DB_TRY(timing_end(tok, st));
-            hipLaunchKernelGGL(k_ov_fine_start, dim3(grid_for(nbuckets * fine_per + 1, 256, 4096)), dim3(256), 0, st,
-                               poffs2, chunk_base, (int)nbuckets, fine_per, nbuckets * fine_per, fine_start);
-            DB_HIP(hipGetLastError());
-            sort_start = fine_start;
-            sort_stride = 1;
-            sort_keys = keys_a16;
-            sort_pays = pays_a;
+            DB_TRY(sort_pairs(P, M, N, keys_a, keys_b, pays_a, pays_b, at + base, rec + c_of[k], base, scr));
+            base += N;
         }
-        // staged sweeps of 2^12 columns (one sweep for buckets of at most that)
-        DB_TRY(timing_begin(kPhBucketSort, st, &tok));
-        hipLaunchKernelGGL((k_ov_bucket_sort), dim3((unsigned)nsort), dim3(kBucketBlock),
-                           ((size_t)4 << kStageBits) + (size_t)8 * kStageCap, st, sort_start, sort_stride, low,
-                           std::min(low, kStageBits), total_m, total_nnz, sort_keys, sort_pays, rec, at_out);
-        DB_HIP(hipGetLastError());
-        DB_TRY(timing_end(tok, st));
     }
     T->rec = rec;
-    T->at = total_nnz > 0 ? reinterpret_cast<const int2*>(at_out) : nullptr;
+    T->at = total_nnz > 0 ? reinterpret_cast<const int2*>(at) : nullptr;
     T->bnd = bnd;
     T->bnd_stride = total_rows;
     T->sm = sm;
@@ -2451,14 +2608,16 @@ int overlap_graph_blocked_run(const dibella_csr* A, int32_t min_shared, const in
     OvSet* d_sets;
     int64_t* d_base;
     DB_TRY(upload_sets(L, ar, &d_sets, &d_base));
+    // A^T over as many column ranges as there are blocks of rows, so that
+    // its partition buffers shrink with the blocks too
+    const int64_t nb = n > 0 ? ceil_div(n, block_rows) : 0;
     OvTransposed T;
-    DB_TRY(ov_transpose(L, d_sets, d_base, 0u, ar, &T));
+    DB_TRY(ov_transpose(L, d_sets, d_base, 0u, ar, &T, (int)std::min<int64_t>(nb, 1 << 20)));
     stats().products = 0;
     stats().esc_rows = 0;
     // A's row pointers on the host (every block's first entry) and A's
     // validation flags: a block's segment words are indexed from its first
     // entry, so A must be known valid before any block runs
-    const int64_t nb = n > 0 ? ceil_div(n, block_rows) : 0;
     std::vector<int64_t> rp(n + 1, 0);
     if (n > 0) {
         HostStage& hst = host_stage();

@@ -91,17 +91,24 @@ def test_blocked_graph_hash_path(db, tiny):
 @pytest.mark.timeout(900)
 def test_blocked_graph_mid_workload_sliced(db):
     """The mid-size workload: enough columns for the sliced segment pass, so
-    every block reads its rows' part of the slice table.  Blocks of 7000
-    reads against the oracle's R from the whole C."""
+    every block reads its rows' part of the slice table, and A^T is built
+    over as many column ranges of slices as there are blocks (5 ranges for
+    blocks of 7000 reads; 24, every slice, for blocks of 600).  Both against
+    the oracle's R from the whole C."""
     w = synth.make_workload("mid", device="cuda:0", strand_bit=True)
     print(f"mid: reads {w.A.nrows} nnz(A) {w.A.nnz} k-mers {w.A.ncols}", flush=True)
     A = db.CSRTensors.from_numpy(w.A, "cuda:0")
-    R, nb = db.overlap_graph_blocked(A, w.min_shared, _lens(w.reads), w.k, 1000, 100, 16, block_rows=7000)
-    torch.cuda.synchronize()
-    print(f"  {nb} blocks, nnz(R) {R.nnz}; oracle ...", flush=True)
+    got = {}
+    for block_rows in (7000, 600):
+        R, nb = db.overlap_graph_blocked(A, w.min_shared, _lens(w.reads), w.k, 1000, 100, 16, block_rows=block_rows)
+        torch.cuda.synchronize()
+        assert nb == -(-w.A.nrows // block_rows)
+        got[block_rows] = (R.rowptr.cpu().numpy(), R.col.cpu().numpy(), R.val.cpu().numpy())
+        print(f"  blocks of {block_rows}: {nb} blocks, nnz(R) {R.nnz}", flush=True)
+    print("  oracle ...", flush=True)
     ref = _oracle_r(w, 1000, 100, 16)
-    assert nb == -(-w.A.nrows // 7000)
-    assert _eq(R.rowptr, ref.rowptr) and _eq(R.col, ref.col) and _eq(R.val, ref.val)
+    for rp, col, val in got.values():
+        assert np.array_equal(rp, ref.rowptr) and np.array_equal(col, ref.col) and np.array_equal(val, ref.val)
 
 
 def test_blocked_graph_argument_errors(db, tiny):

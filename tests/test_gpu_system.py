@@ -76,9 +76,23 @@ def test_large_workload_full_parity(db):
     w = synth.make_workload("large", device="cuda:0")
     A, R = w.A, w.R
     print(f"  reads {A.nrows} kmers {A.ncols} nnz(A) {A.nnz} nnz(R) {R.nnz}", flush=True)
-    C = db.overlap(db.CSRTensors.from_numpy(A, "cuda:0"), w.min_shared)
+    Ad = db.CSRTensors.from_numpy(A, "cuda:0")
+    C = db.overlap(Ad, w.min_shared)
     st = db.last_stats()
     print(f"  GPU overlap: nnz(C) {C.nnz}, products {st['products']}", flush=True)
+    # the blocked overlap graph (4 blocks of reads, A^T over 4 column ranges
+    # of slices, three-level sorts per range) equals R from the seeds of this
+    # C, which the oracle checks in full below (A's values are positions here,
+    # so the strand bit R from seeds reads is the position's low bit: the
+    # same input for both builds)
+    lens = torch.as_tensor(np.diff(w.reads.offsets).astype(np.int32), device="cuda:0")
+    Rw = db.r_from_seeds(C, lens, w.k, 1000, 150, 52)
+    Rb, nb = db.overlap_graph_blocked(Ad, w.min_shared, lens, w.k, 1000, 150, 52, block_rows=-(-A.nrows // 4))
+    torch.cuda.synchronize()
+    print(f"  blocked overlap graph: {nb} blocks, nnz(R) {Rb.nnz} (whole {Rw.nnz})", flush=True)
+    assert nb == 4 and Rw.nnz > 0
+    assert all(torch.equal(x, y) for x, y in ((Rb.rowptr, Rw.rowptr), (Rb.col, Rw.col), (Rb.val, Rw.val)))
+    del Rw, Rb, Ad
     S, it = db.transitive_reduce(db.CSRTensors.from_numpy(R, "cuda:0"), w.fuzz)
     torch.cuda.synchronize()
     print(f"  GPU reduction: nnz(S) {S.nnz}, passes {it}", flush=True)
