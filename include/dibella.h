@@ -12,6 +12,13 @@
  *                              the MinPlus semiring algorithm).
  *   *_batched                  the same for many independent sets in one
  *                              set of launches.
+ *   dibella_r_from_seeds       the overlap graph R from the seeds stored in C
+ *                              (Sec. IV-D, IV-E).
+ *   dibella_overlap_graph_blocked
+ *                              R from A with C formed one block of reads at a
+ *                              time (Sec. VIII, future work).
+ *   dibella_transitive_reduce_noalloc
+ *                              the reduction for callers that cannot allocate.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -92,16 +99,21 @@ typedef void (*dibella_free_fn)(void* p, void* ctx);
  * A: reads x reliable k-mers; A_ik = start of k-mer k in read i (>= 0).
  * The multiply of the semiring pairs the two positions of a shared k-mer;
  * the add counts shared k-mers and keeps the position pairs of the two
- * smallest shared k-mer columns (the paper keeps "two positions" and leaves
- * their order to the library; this fixes it so C_ji is C_ij with each pair
- * swapped).  Entries with count < min_shared are not stored; the diagonal
+ * smallest shared k-mer columns (the paper keeps two position pairs per
+ * read pair and leaves which ones to the library; this fixes it so C_ji is
+ * C_ij with each pair swapped).  Entries with count < min_shared are not stored; the diagonal
  * is kept.  C rows are sorted by column.  Output arrays: rowptr[n+1],
  * col/count[nnz], seed[4*nnz].
  * Errors: EINVAL for a malformed A (rowptr, column order or range, negative
- * value) or min_shared < 1; EOVERFLOW if nrows >= 2^24, or if the entries
- * or the columns of all sets of one call add up to 2^32 or more.
+ * value) or min_shared < 1; EOVERFLOW if nrows >= 2^24 (two-pair column
+ * records hold read ids in 24 bits), if a row needs 2^31 semiring products
+ * or more, or if the entries or the columns of all sets of one call add up
+ * to 2^32 or more.
  * Host synchronisation: two stream syncs (three if some row needs more
- * distinct columns than one LDS table holds).
+ * distinct columns than one LDS table holds): the first reads the
+ * validation flags, the row-cost classes and the output-column scratch
+ * size, the second the exact size of C, so that neither C nor the scratch
+ * is allocated at its upper bound.
  */
 int dibella_overlap(const dibella_csr* A, int32_t min_shared, dibella_overlap_out* C,
                     dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx,
