@@ -66,6 +66,7 @@ def _load():
         lib.oracle_transitive_reduce.argtypes = [i64, P, P, P, i32, u32, P, P, P, P, P, P, i32, P]
         lib.oracle_tr_pass_marks.argtypes = [i64, P, P, P, i32, u32, P, i64, P]
         lib.oracle_r_from_seeds.argtypes = [i64, P, P, P, P, P, i32, i32, i32, i32, P, P, P, P]
+        lib.oracle_kmer_matrix.argtypes = [i64, P, P, i32, i32, i32, i32, P, P, P, P, P, P]
         lib.oracle_free.argtypes = [P]
         _lib = lib
     return _lib
@@ -204,3 +205,27 @@ def r_from_seeds(C, read_len, k: int, min_overlap: int, max_drift: int = -1, min
         raise ValueError("a seed of C is missing or lies outside its read")
     return SimpleNamespace(nrows=n, ncols=n, rowptr=out_rp, col=_take(lib, pc, nnz.value, np.int32),
                            val=_take(lib, pv, nnz.value, np.int32))
+
+
+def kmer_matrix(bases, offsets, k: int, lo: int, hi: int, strand_bit: bool = False):
+    """A from the reads (k-mer counting, reliable k-mers in [lo, hi], the
+    smallest position per read and k-mer; with strand_bit the values are
+    (position << 1) | strand).  Returns (A, codes): A with nrows, ncols,
+    rowptr, col, val; codes = the reliable canonical codes, ascending (A's
+    columns).  Raises ValueError on k outside [1, 31], bad bounds or a base
+    outside 0..3."""
+    lib = _load()
+    b = np.ascontiguousarray(bases, dtype=np.uint8)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(off) - 1
+    out_rp = np.zeros(n + 1, np.int64)
+    pc, pv, pk = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    m, nnz = ctypes.c_int64(), ctypes.c_int64()
+    r = lib.oracle_kmer_matrix(n, _ptr(b), _ptr(off), int(k), int(lo), int(hi), 1 if strand_bit else 0,
+                               _ptr(out_rp), ctypes.byref(pc), ctypes.byref(pv), ctypes.byref(pk),
+                               ctypes.byref(m), ctypes.byref(nnz))
+    if r != 0:
+        raise ValueError("k outside [1, 31], bounds outside 1 <= lo <= hi, or a base outside 0..3")
+    A = SimpleNamespace(nrows=n, ncols=m.value, nnz=nnz.value, rowptr=out_rp,
+                        col=_take(lib, pc, nnz.value, np.int32), val=_take(lib, pv, nnz.value, np.int32))
+    return A, _take(lib, pk, m.value, np.uint64)

@@ -449,3 +449,118 @@ int oracle_r_from_seeds(int64_t n, const int64_t* c_rowptr, const int32_t* c_col
     *out_col = oc; *out_val = ov; *out_nnz = nnz;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* A from the reads: k-mer counting, reliable k-mers, A (Sec. IV-C, Alg.     */
+/* diBELLA 2D: KmerCounter and GenerateA)                                    */
+/* ------------------------------------------------------------------------ */
+/* Every window of k bases (p + k <= L_i) of every read is a k-mer.  Bases
+ * are 2-bit codes A0 C1 G2 T3, the first base the most significant.  Its
+ * canonical form is the smaller of its code and its reverse complement's
+ * (the complement of each base, in reverse order); its strand is 1 when the
+ * reverse complement is the smaller (the read holds the canonical k-mer
+ * reverse complemented), else 0.  The frequency of a canonical k-mer is the
+ * number of windows of all reads that have it (repeats inside a read
+ * count); it is reliable when lo <= frequency <= hi.  The reliable k-mers,
+ * in increasing code order, are A's columns.  A_ic = the smallest position
+ * of k-mer c in read i, or (position << 1) | strand (the strand at that
+ * position) when strand_bit is set.
+ * Outputs: rowptr[n+1], *out_col, *out_val (nnz each), *out_codes (m
+ * reliable codes, ascending), *out_m, *out_nnz.  Returns 0, -1 for k outside
+ * [1, 31], lo < 1, hi < lo or a base outside 0..3. */
+typedef struct {
+    uint64_t code;
+    int64_t read;
+    int64_t pos;
+    int32_t strand;
+} oracle_window;
+
+static int cmp_window(const void* a, const void* b) {
+    const oracle_window* x = (const oracle_window*)a;
+    const oracle_window* y = (const oracle_window*)b;
+    if (x->code != y->code) return x->code < y->code ? -1 : 1;
+    if (x->read != y->read) return x->read < y->read ? -1 : 1;
+    return (x->pos > y->pos) - (x->pos < y->pos);
+}
+
+typedef struct {
+    int64_t read;
+    int64_t col;
+    int32_t val;
+} oracle_entry;
+
+static int cmp_entry(const void* a, const void* b) {
+    const oracle_entry* x = (const oracle_entry*)a;
+    const oracle_entry* y = (const oracle_entry*)b;
+    if (x->read != y->read) return x->read < y->read ? -1 : 1;
+    return (x->col > y->col) - (x->col < y->col);
+}
+
+int oracle_kmer_matrix(int64_t n, const uint8_t* bases, const int64_t* offsets, int32_t k, int32_t lo,
+                       int32_t hi, int32_t strand_bit, int64_t* out_rowptr, int32_t** out_col,
+                       int32_t** out_val, uint64_t** out_codes, int64_t* out_m, int64_t* out_nnz) {
+    if (k < 1 || k > 31 || lo < 1 || hi < lo) return -1;
+    /* every window: its canonical code, read, position and strand */
+    int64_t W = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t L = offsets[i + 1] - offsets[i];
+        if (L >= k) W += L - k + 1;
+    }
+    oracle_window* win = (oracle_window*)xmalloc(sizeof(oracle_window) * (size_t)(W ? W : 1));
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint8_t* s = bases + offsets[i];
+        int64_t L = offsets[i + 1] - offsets[i];
+        for (int64_t p = 0; p + k <= L; ++p) {
+            uint64_t fwd = 0, rc = 0;
+            for (int32_t q = 0; q < k; ++q) {
+                if (s[p + q] > 3) { free(win); return -1; }
+                fwd = (fwd << 2) | s[p + q];                          /* first base most significant */
+                rc |= (uint64_t)(3 - s[p + q]) << (2 * q);            /* complement, reversed */
+            }
+            win[w].code = rc < fwd ? rc : fwd;
+            win[w].strand = rc < fwd;
+            win[w].read = i;
+            win[w].pos = p;
+            ++w;
+        }
+    }
+    qsort(win, (size_t)W, sizeof(oracle_window), cmp_window);
+    /* frequencies (runs of equal codes), reliable k-mers and their columns;
+     * within a run the windows are in (read, position) order, so the first
+     * window of a read in a run has the read's smallest position */
+    oracle_entry* ent = (oracle_entry*)xmalloc(sizeof(oracle_entry) * (size_t)(W ? W : 1));
+    uint64_t* codes = (uint64_t*)xmalloc(sizeof(uint64_t) * (size_t)(W ? W : 1));
+    int64_t m = 0, nnz = 0;
+    for (int64_t a = 0; a < W;) {
+        int64_t b = a;
+        while (b < W && win[b].code == win[a].code) ++b;
+        int64_t freq = b - a;
+        if (freq >= lo && freq <= hi) {
+            codes[m] = win[a].code;
+            for (int64_t e = a; e < b; ++e) {
+                if (e > a && win[e].read == win[e - 1].read) continue;   /* not the read's first */
+                ent[nnz].read = win[e].read;
+                ent[nnz].col = m;
+                ent[nnz].val = strand_bit ? (int32_t)((win[e].pos << 1) | win[e].strand) : (int32_t)win[e].pos;
+                ++nnz;
+            }
+            ++m;
+        }
+        a = b;
+    }
+    free(win);
+    qsort(ent, (size_t)nnz, sizeof(oracle_entry), cmp_entry);
+    int32_t* oc = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(nnz ? nnz : 1));
+    int32_t* ov = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(nnz ? nnz : 1));
+    for (int64_t i = 0; i <= n; ++i) out_rowptr[i] = 0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        out_rowptr[ent[e].read + 1]++;
+        oc[e] = (int32_t)ent[e].col;
+        ov[e] = ent[e].val;
+    }
+    for (int64_t i = 0; i < n; ++i) out_rowptr[i + 1] += out_rowptr[i];
+    free(ent);
+    *out_col = oc; *out_val = ov; *out_codes = codes; *out_m = m; *out_nnz = nnz;
+    return 0;
+}

@@ -557,3 +557,109 @@ def test_r_from_seeds_rejects_a_seed_outside_its_read():
     oracle.r_from_seeds(C, [100, 100], 17, 10)
     with pytest.raises(ValueError):
         oracle.r_from_seeds(C, [100, 20], 17, 10)
+
+
+# ---------------------------------------------------------------------------
+# A from the reads (k-mer counting, reliable k-mers, A): pinned on the read
+# strings themselves (Python strings and a Counter, not 2-bit integers)
+# ---------------------------------------------------------------------------
+def _kmer_matrix_from_strings(seqs, k, lo, hi, strand_bit):
+    """A written from the definitions on strings: canonical = the smaller of
+    the k-mer and its reverse complement as strings over ACGT (string order
+    = the 2-bit code order), frequency over all windows, reliable in
+    [lo, hi], columns = reliable canonical strings in sorted order, value =
+    the first position of the k-mer in the read (with its strand: 1 when the
+    read holds the reverse complement)."""
+    from collections import Counter
+    comp = str.maketrans("ACGT", "TGCA")
+    freq = Counter()
+    per_read = []
+    for s in seqs:
+        first = {}
+        for p in range(len(s) - k + 1):
+            km = s[p:p + k]
+            rc = km.translate(comp)[::-1]
+            can = min(km, rc)
+            freq[can] += 1
+            if can not in first:
+                first[can] = (p, 1 if rc < km else 0)
+        per_read.append(first)
+    cols = sorted(c for c, f in freq.items() if lo <= f <= hi)
+    index = {c: q for q, c in enumerate(cols)}
+    rows = []
+    for first in per_read:
+        ent = sorted((index[c], (p << 1 | st) if strand_bit else p) for c, (p, st) in first.items() if c in index)
+        rows.append(ent)
+    codes = [int("".join("0123"["ACGT".index(ch)] for ch in c), 4) for c in cols]
+    return rows, np.array(codes, dtype=np.uint64)
+
+
+def _rows_of(A):
+    return [list(zip(A.col[A.rowptr[i]:A.rowptr[i + 1]].tolist(), A.val[A.rowptr[i]:A.rowptr[i + 1]].tolist()))
+            for i in range(A.nrows)]
+
+
+@pytest.mark.parametrize("seed,k,lo,hi,strand_bit", [
+    (0, 5, 2, 6, False), (1, 5, 2, 6, True), (2, 4, 1, 3, True), (3, 7, 2, 40, True), (4, 1, 1, 1000, True),
+    (5, 2, 3, 9, False)])
+def test_kmer_matrix_equals_strings(seed, k, lo, hi, strand_bit):
+    """Error-prone reads of a small genome with repeats, several k (even k
+    has palindromic k-mers: strand 0), bounds and value layouts; reads
+    shorter than k have empty rows."""
+    rng = np.random.default_rng(900 + seed)
+    g = synth.random_genome(rng, 1500)
+    g[700:760] = g[100:160]                      # a repeat
+    reads = synth.sample_reads(rng, g, n_reads=25, length_uniform=(3, 300), error_rate=0.1, min_len=3)
+    # and two reads without a window: k - 1 bases, and none
+    short = rng.integers(0, 4, size=k - 1, dtype=np.uint8)
+    bases = np.concatenate([reads.bases, short])
+    offsets = np.concatenate([reads.offsets, [len(bases), len(bases)]]).astype(np.int64)
+    seqs = [bruteforce.bases_to_str(bases[offsets[i]:offsets[i + 1]]) for i in range(len(offsets) - 1)]
+    A, codes = oracle.kmer_matrix(bases, offsets, k, lo, hi, strand_bit)
+    rows, ref_codes = _kmer_matrix_from_strings(seqs, k, lo, hi, strand_bit)
+    assert A.ncols == len(ref_codes) and np.array_equal(codes, ref_codes)
+    assert _rows_of(A) == rows
+    assert A.rowptr[0] == 0 and A.rowptr[-1] == A.nnz
+
+
+def test_kmer_matrix_palindromes_and_single_bases():
+    """k = 2 on "ACGT": AC/GT are each other's reverse complement (canonical
+    AC, strand 0 for AC, 1 for GT), CG is its own (strand 0).  k = 1: A and
+    T are one canonical base (A), C and G another (C)."""
+    bases = np.array([0, 1, 2, 3], np.uint8)      # ACGT
+    off = np.array([0, 4], np.int64)
+    A, codes = oracle.kmer_matrix(bases, off, 2, 1, 10, True)
+    # windows AC (code 1), CG (6, palindrome), GT (11 -> rc AC = 1, strand 1)
+    assert codes.tolist() == [1, 6]
+    assert _rows_of(A) == [[(0, 0 << 1 | 0), (1, 1 << 1 | 0)]]   # AC first at 0; CG at 1
+    A1, codes1 = oracle.kmer_matrix(bases, off, 1, 1, 10, True)
+    assert codes1.tolist() == [0, 1]                               # A (from A and T), C (from C and G)
+    assert _rows_of(A1) == [[(0, 0 << 1 | 0), (1, 1 << 1 | 0)]]
+
+
+def test_kmer_matrix_frequency_counts_repeats_inside_a_read():
+    """AAAAA with k = 3: three windows of one k-mer -> frequency 3; kept at
+    lo = hi = 3, dropped at hi = 2; the value is the first position."""
+    bases = np.zeros(5, np.uint8)
+    off = np.array([0, 5], np.int64)
+    A, codes = oracle.kmer_matrix(bases, off, 3, 3, 3)
+    assert codes.tolist() == [0] and _rows_of(A) == [[(0, 0)]]
+    A2, codes2 = oracle.kmer_matrix(bases, off, 3, 1, 2)
+    assert A2.ncols == 0 and A2.nnz == 0 and A2.rowptr.tolist() == [0, 0]
+
+
+def test_kmer_matrix_matches_the_generator_on_the_tiny_workload():
+    """The generator's A (torch.unique over canonical codes) is the oracle's."""
+    w = synth.make_workload("tiny", strand_bit=True)
+    A, codes = oracle.kmer_matrix(w.reads.bases, w.reads.offsets, w.k, w.lo, w.hi, True)
+    B, bcodes = synth.kmer_matrix(w.reads, w.k, w.lo, w.hi, strand_bit=True)
+    assert np.array_equal(A.rowptr, B.rowptr) and np.array_equal(A.col, B.col) and np.array_equal(A.val, B.val)
+    assert np.array_equal(codes, bcodes)
+
+
+@pytest.mark.parametrize("k,lo,hi,bad_base", [(0, 1, 2, False), (32, 1, 2, False), (5, 0, 2, False),
+                                              (5, 3, 2, False), (5, 1, 2, True)])
+def test_kmer_matrix_rejects_bad_arguments(k, lo, hi, bad_base):
+    bases = np.array([0, 1, 2, 3, 4 if bad_base else 0, 1, 2], np.uint8)
+    with pytest.raises(ValueError):
+        oracle.kmer_matrix(bases, np.array([0, 7], np.int64), k, lo, hi)

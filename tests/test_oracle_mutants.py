@@ -72,6 +72,17 @@ MUTANTS = [
      "if (min_density > 0 && (int64_t)c_count[e] * 10000 <= (int64_t)min_density * overlap) continue;"),
     ("rfs-density-per-kbp", "if (min_density > 0 && (int64_t)c_count[e] * 10000 < (int64_t)min_density * overlap) continue;",
      "if (min_density > 0 && (int64_t)c_count[e] * 1000 < (int64_t)min_density * overlap) continue;"),
+    # A from the reads
+    ("km-strand-inverted", "win[w].strand = rc < fwd;", "win[w].strand = rc > fwd;"),
+    ("km-not-canonical", "win[w].code = rc < fwd ? rc : fwd;", "win[w].code = fwd;"),
+    ("km-rc-not-reversed", "rc |= (uint64_t)(3 - s[p + q]) << (2 * q);", "rc = (rc << 2) | (uint64_t)(3 - s[p + q]);"),
+    ("km-rc-not-complemented", "rc |= (uint64_t)(3 - s[p + q]) << (2 * q);", "rc |= (uint64_t)s[p + q] << (2 * q);"),
+    ("km-bounds-strict", "if (freq >= lo && freq <= hi) {", "if (freq > lo && freq <= hi) {"),
+    ("km-upper-bound-dropped", "if (freq >= lo && freq <= hi) {", "if (freq >= lo) {"),
+    ("km-last-position", "if (e > a && win[e].read == win[e - 1].read) continue;",
+     "if (e + 1 < b && win[e].read == win[e + 1].read) continue;"),
+    ("km-last-base-first", "fwd = (fwd << 2) | s[p + q];", "fwd |= (uint64_t)s[p + q] << (2 * q);"),
+    ("km-window-past-end", "for (int64_t p = 0; p + k <= L; ++p) {", "for (int64_t p = 0; p + k < L; ++p) {"),
     # one-pass marks used for sampled checks
     ("marks-compare-strict", "(int64_t)(nij >> 2) <= mij);", "(int64_t)(nij >> 2) < mij);"),
     ("marks-row-max-unset", "if (vi != 0) vi += fuzz;", "if (vi != 0) vi += fuzz + 1;"),
