@@ -561,6 +561,56 @@ def main_pool_entry(w_main):
     return serve.pool_entry(dataclasses.replace(w_main, A=A1), "cuda:0")
 
 
+def kmer_compare(w, reps: int = 2):
+    """A from the timed step's reads on the device (dibella_kmer_matrix):
+    best wall time of `reps` builds, the library's per-stage event time, the
+    windows per second, and the result checked equal to the generator's A
+    (torch: canonical codes, torch.unique, a sort by read), whose time is
+    reported beside it."""
+    import numpy as np
+    import torch
+    import paper_2010_10055_amd as db
+    from paper_2010_10055_amd import _lib, synth
+    bases = torch.as_tensor(w.reads.bases, device="cuda:0")
+    offsets = torch.as_tensor(w.reads.offsets, device="cuda:0")
+    windows = int(np.maximum(np.diff(w.reads.offsets) - w.k + 1, 0).sum())
+    A, codes = db.kmer_matrix(bases, offsets, w.k, w.lo, w.hi)
+    torch.cuda.synchronize()
+    del A, codes
+    best = None
+    _lib.timing_enable(True)
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        A, codes = db.kmer_matrix(bases, offsets, w.k, w.lo, w.hi)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+        if _ < reps - 1:
+            del A, codes
+    ph = _lib.timing_collect()
+    _lib.timing_enable(False)
+    stages = {k: round(v[0] / reps, 3) for k, v in ph.items() if k.startswith("kmer_") and v[1]}
+    same = (A.ncols == w.A.ncols and np.array_equal(A.rowptr.cpu().numpy(), w.A.rowptr) and
+            np.array_equal(A.col.cpu().numpy(), w.A.col) and np.array_equal(A.val.cpu().numpy(), w.A.val))
+    if not same:
+        raise RuntimeError("the library's A differs from the generator's")
+    del A, codes
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    synth.kmer_matrix(w.reads, w.k, w.lo, w.hi, device="cuda:0")
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    del bases, offsets
+    torch.cuda.empty_cache()
+    out = {"reads": int(w.reads.n), "bases": int(len(w.reads.bases)), "windows": windows, "k": w.k,
+           "bounds": [w.lo, w.hi], "ms": round(best * 1e3, 2), "stage_ms": stages,
+           "windows_per_s": round(windows / best), "equal_to_generator": same,
+           "generator_ms": round(t_gen * 1e3, 1)}
+    log(f"  {best * 1e3:.1f} ms ({windows / best / 1e9:.2f} G windows/s), stages {stages}; "
+        f"generator (torch) {t_gen * 1e3:.0f} ms; A equal")
+    return out
+
+
 def blocked_compare(inp, nblocks=(4, 16), reps: int = 2):
     """The overlap graph of one layout job built whole (dibella_overlap, then
     R from C's seeds) and blocked (dibella_overlap_graph_blocked: C formed a
@@ -702,6 +752,7 @@ def main():
     ap.add_argument("--tune-budget", type=float, default=30.0, help="seconds of autotuning for the batch (0 = off)")
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving comparison (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=3, help="slots of continuous batching")
+    ap.add_argument("--no-kmer", action="store_true", help="skip the k-mer counting leg")
     ap.add_argument("--blocks", type=int, nargs="*", default=[4, 16],
                     help="block counts of the blocked overlap graph comparison (none = skip)")
     ap.add_argument("--calib-copy", action="store_true", help="only run the reference kernels used to scale counters")
@@ -862,6 +913,10 @@ def main():
         batch = batch_compare(db, synth, args.batch_sets, max(1, min(args.steps, 5)), args.tune_budget)
         db.set_tuning(**default_tuning)
 
+    kmer = None
+    if not args.no_kmer:
+        log("A from the reads on the device vs the generator ...")
+        kmer = kmer_compare(w)
     served = blocked = None
     entry = None
     if args.serve_jobs > 0 or args.blocks:
@@ -901,6 +956,7 @@ def main():
         "host_syncs": {"overlap": ov_stats["host_syncs"], "tr": tr_stats["host_syncs"]},
         "roofline": roofline,
         "batch": batch,
+        "kmer_matrix": kmer,
         "blocked": blocked,
         "serve": served,
         "cpu_baseline": cpu,

@@ -19,6 +19,9 @@
  *                              time (Sec. VIII, future work).
  *   dibella_transitive_reduce_noalloc
  *                              the reduction for callers that cannot allocate.
+ *   dibella_kmer_matrix        A from the reads: k-mer counting, reliable
+ *                              k-mers, A (Sec. IV-C; Algorithm "diBELLA 2D":
+ *                              KmerCounter and GenerateA).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -62,6 +65,8 @@ extern "C" {
 #define DIBELLA_TR_RULE_EDGE   0x2u  /* M_ij = overhang(R_ij) + fuzz (default: row max + fuzz) */
 #define DIBELLA_NO_VALIDATE    0x4u  /* skip the structural checks of the input */
 #define DIBELLA_TR_USE_GRAPH   0x8u  /* run the passes as captured HIP graphs */
+/* Flag of dibella_kmer_matrix. */
+#define DIBELLA_KMER_STRAND    0x1u  /* values (position << 1) | strand */
 /* Bits 16..31: stop after this many passes (0 = run to the fixed point). */
 #define DIBELLA_TR_MAX_PASSES(n) (((uint32_t)(n) & 0xFFFFu) << 16)
 
@@ -263,6 +268,35 @@ int dibella_transitive_reduce_noalloc(const dibella_csr* R, int32_t fuzz, uint32
                                       int64_t s_capacity, int64_t* s_nnz, int32_t* iterations,
                                       void* hip_stream);
 
+/*
+ * dibella_kmer_matrix -- A from the reads (Sec. IV-C; Algorithm "diBELLA 2D":
+ * KmerCounter and GenerateA).
+ *
+ * bases: device uint8[nbases], 2-bit codes A0 C1 G2 T3, the reads back to
+ * back; offsets: device int64[n + 1], read i = bases[offsets[i],
+ * offsets[i + 1]) (offsets[0] = 0, offsets[n] = nbases, non-decreasing).
+ * Every window of k bases of a read (position p, p + k <= length) is a
+ * k-mer; its canonical form is the smaller of its code (first base most
+ * significant) and its reverse complement's, its strand 1 when the reverse
+ * complement is the smaller.  A k-mer's frequency is its number of windows
+ * over all reads (repeats inside a read count); it is reliable when
+ * lo <= frequency <= hi.  The reliable k-mers, in increasing code order,
+ * are A's columns; A_ic = the smallest position of k-mer c in read i, or
+ * (position << 1) | strand (the strand at that position) with
+ * DIBELLA_KMER_STRAND.  A: n x m, rows sorted, allocated through alloc;
+ * *codes: device uint64[m], the reliable canonical codes (column order),
+ * allocated through alloc (NULL when m = 0).
+ * Errors: EINVAL for k outside [1, 31], lo < 1, hi < lo, malformed offsets
+ * or a base outside 0..3; EOVERFLOW for n >= 2^31, 2^32 windows or more, or
+ * 2^31 reliable k-mers or more.
+ * Host synchronisation: two stream syncs (the window count; the k-mer and
+ * entry counts).
+ */
+int dibella_kmer_matrix(const uint8_t* bases, const int64_t* offsets, int64_t nreads, int64_t nbases,
+                        int32_t k, int32_t lo, int32_t hi, uint32_t flags, dibella_csr_out* A,
+                        uint64_t** codes, dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx,
+                        void* hip_stream);
+
 /* Message of the last nonzero status returned on this host thread. */
 const char* dibella_last_error(void);
 
@@ -328,10 +362,14 @@ int dibella_last_stats(dibella_stats* out);
  *                   last (its launches overlap on several streams, so the
  *                   sum of the records of label 9 exceeds this)
  *  14 r_from_seeds  overlap graph from the seeds of C (both passes)
+ *  15 kmer_windows  A from the reads: window counts and canonical codes
+ *  16 kmer_sort     A from the reads: the radix sorts (by k-mer, by read)
+ *  17 kmer_runs     A from the reads: frequencies, columns, kept entries
+ *  18 kmer_rows     A from the reads: row pointers, columns and values
  * Passes run as captured graphs are not timed.  Enabling clears the
  * accumulators; collect waits for the recorded events, returns the summed
  * milliseconds and number of records per label, and clears them. */
-#define DIBELLA_NUM_PHASES 16
+#define DIBELLA_NUM_PHASES 20
 typedef struct {
     double ms[DIBELLA_NUM_PHASES];
     int64_t records[DIBELLA_NUM_PHASES];

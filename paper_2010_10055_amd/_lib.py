@@ -27,12 +27,14 @@ TR_USE_GRAPH = 0x8
 
 EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batched",
            "dibella_transitive_reduce_batched", "dibella_r_from_seeds", "dibella_overlap_graph_blocked",
-           "dibella_transitive_reduce_noalloc",
+           "dibella_transitive_reduce_noalloc", "dibella_kmer_matrix",
            "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
            "dibella_timing_select", "dibella_timing_collect"]
 PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "part2_count", "part2_scatter", "segments", "sym_bits",
-          "sym_hash", "numeric", "esc", "tr_mark", "tr_compact", "numeric_phase", "r_from_seeds"]
+          "sym_hash", "numeric", "esc", "tr_mark", "tr_compact", "numeric_phase", "r_from_seeds", "kmer_windows",
+          "kmer_sort", "kmer_runs", "kmer_rows"]
+NUM_PHASES = 20
 
 
 class DibellaError(RuntimeError):
@@ -74,7 +76,7 @@ class _Stats(ctypes.Structure):
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 16), ("records", ctypes.c_int64 * 16)]
+    _fields_ = [("ms", ctypes.c_double * NUM_PHASES), ("records", ctypes.c_int64 * NUM_PHASES)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -94,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dibella_overlap_graph_blocked.argtypes = [P, i32, P, i32, i32, i32, i32, ctypes.c_int64, P, P, ALLOC_FN,
                                                   FREE_FN, P, P]
     lib.dibella_transitive_reduce_noalloc.argtypes = [P, i32, u32, P, P, P, ctypes.c_int64, P, P, P]
+    lib.dibella_kmer_matrix.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, i32, i32, i32, u32, P, P, ALLOC_FN,
+                                        FREE_FN, P, P]
     for f in EXPORTS:
         getattr(lib, f).restype = ctypes.c_int
     lib.dibella_last_error.restype = ctypes.c_char_p
@@ -383,6 +387,36 @@ def overlap_graph_blocked(A: CSRTensors, min_shared: int, read_len: torch.Tensor
     R = CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
                    call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
     return R, nb.value
+
+
+KMER_STRAND = 0x1
+
+
+def kmer_matrix(bases: torch.Tensor, offsets: torch.Tensor, k: int, lo: int, hi: int, strand_bit: bool = False):
+    """A from the reads on the device: bases uint8 (A0 C1 G2 T3, reads back
+    to back), offsets int64[n + 1].  Reliable k-mers (frequency over all
+    windows in [lo, hi]) in code order are the columns; values are the
+    smallest position per read and k-mer (with strand_bit: (position << 1)
+    | strand).  Returns (A, codes): codes = the reliable canonical codes
+    (int64 tensor, column order)."""
+    if bases.dtype != torch.uint8 or not bases.is_cuda or not bases.is_contiguous():
+        raise TypeError("bases must be a contiguous uint8 device tensor")
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous() or offsets.numel() < 1:
+        raise TypeError("offsets must be a contiguous int64 device tensor of n + 1 entries")
+    dev = bases.device
+    call = _call_for(dev)
+    n = offsets.numel() - 1
+    o = _CSROut()
+    codes = ctypes.c_void_p()
+    with torch.cuda.device(dev):
+        st = lib().dibella_kmer_matrix(bases.data_ptr() if bases.numel() else None, offsets.data_ptr(), n,
+                                       bases.numel(), int(k), int(lo), int(hi), KMER_STRAND if strand_bit else 0,
+                                       ctypes.byref(o), ctypes.byref(codes), call.alloc_cb, call.free_cb, None,
+                                       _stream_handle(dev))
+    _check(st)
+    A = CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                   call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
+    return A, call.mem.take(codes.value, torch.int64, o.ncols)
 
 
 def last_stats() -> dict:

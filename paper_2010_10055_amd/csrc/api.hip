@@ -124,6 +124,29 @@ int dibella_overlap_graph_blocked(const dibella_csr* A, int32_t min_shared, cons
     return status;
 }
 
+int dibella_kmer_matrix(const uint8_t* bases, const int64_t* offsets, int64_t nreads, int64_t nbases, int32_t k,
+                        int32_t lo, int32_t hi, uint32_t flags, dibella_csr_out* A, uint64_t** codes,
+                        dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx, void* hip_stream) {
+    reset_stats();
+    if (!A || !codes || (alloc == nullptr) != (free_fn == nullptr) || (flags & ~DIBELLA_KMER_STRAND)) {
+        set_error("dibella_kmer_matrix: bad arguments");
+        return DIBELLA_EINVAL;
+    }
+    int64_t m = 0;
+    int status;
+    {
+        Arena ar(alloc, free_fn, ctx, static_cast<hipStream_t>(hip_stream));
+        status = guarded(ar, [&] {
+            return kmer_matrix_run(bases, offsets, nreads, nbases, k, lo, hi, flags, A, codes, &m, ar);
+        });
+    }
+    if (status != DIBELLA_OK) {
+        std::memset(A, 0, sizeof(*A));
+        *codes = nullptr;
+    }
+    return status;
+}
+
 const char* dibella_last_error(void) { return error_slot().c_str(); }
 
 int dibella_get_tuning(dibella_tuning* out) {

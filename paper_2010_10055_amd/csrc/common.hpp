@@ -146,6 +146,9 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
 int r_from_seeds_run(const dibella_overlap_out* C, int64_t row0, const int32_t* read_len, int32_t k,
                      int32_t min_overlap, int32_t max_drift, int32_t min_density, dibella_csr_out* R, Arena& ar,
                      Arena& out, bool out_as_work);
+// A from the reads (dibella_kmer_matrix).
+int kmer_matrix_run(const uint8_t* bases, const int64_t* offsets, int64_t n, int64_t nbases, int32_t k, int32_t lo,
+                    int32_t hi, uint32_t flags, dibella_csr_out* A, uint64_t** codes, int64_t* m, Arena& ar);
 // R from the seeds of C = A A^T, built block of rows by block of rows.
 int overlap_graph_blocked_run(const dibella_csr* A, int32_t min_shared, const int32_t* read_len, int32_t k,
                               int32_t min_overlap, int32_t max_drift, int32_t min_density, int64_t block_rows,
@@ -172,7 +175,8 @@ int side_streams(SideStreams** out);
 // Timed kernels (labels of dibella_timing, see the header).
 enum Phase {
     kPhKeys = 0, kPhPartCount, kPhPartScatter, kPhBucketSort, kPhPart2Count, kPhPart2Scatter, kPhSegments,
-    kPhSymBits, kPhSymHash, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact, kPhNumericAll, kPhRFromSeeds
+    kPhSymBits, kPhSymHash, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact, kPhNumericAll, kPhRFromSeeds,
+    kPhKmerWindows, kPhKmerSort, kPhKmerRuns, kPhKmerRows
 };
 bool timing_on();
 // While one lives on this host thread, no timing events are created or

@@ -71,14 +71,14 @@ def test_tuning_roundtrip_and_range_checks():
 
 def test_timing_label_selection_range(lib):
     from paper_2010_10055_amd import _lib
-    assert lib.dibella_timing_select(1 << 16) == _lib.EINVAL      # label bits beyond the 16 labels
+    assert lib.dibella_timing_select(1 << _lib.NUM_PHASES) == _lib.EINVAL   # label bits beyond the labels
     assert lib.dibella_timing_select(0xFFFFFFFF) == _lib.EINVAL
     assert lib.dibella_timing_select(0) == _lib.OK
     _lib.timing_select(["numeric_phase", "tr_mark"])
     with pytest.raises(ValueError):
         _lib.timing_select(["no_such_label"])
     _lib.timing_select(None)
-    assert lib.dibella_timing_select((1 << 16) - 1) == _lib.OK
+    assert lib.dibella_timing_select((1 << _lib.NUM_PHASES) - 1) == _lib.OK
 
 
 def test_timing_labels_match_the_header():
