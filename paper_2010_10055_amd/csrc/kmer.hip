@@ -33,9 +33,13 @@ enum : int32_t {
 // Stable device-wide LSD radix sort of (key, value) pairs, 8-bit digits.
 // Per pass: an upsweep histogram per tile of kTile keys (digit-major
 // counts[d * ntiles + tile]), an exclusive scan over them, and a downsweep
-// in which every wave ranks its lanes among equal digits with 8 ballots,
-// waves follow each other through LDS counters, and each element goes to
-// its digit's running slot: ranks follow input order inside a tile and
+// in which every wave ranks its lanes among equal digits of its 64
+// elements with 8 ballots, the counts of the tile's 64 groups of 64 are
+// scanned per digit in LDS (one thread per digit), each element's slot in
+// the tile (its digit's first slot, plus the digit's elements in the groups
+// before its own, plus its rank) places it in LDS in digit order, and the
+// tile is written out from there so that each digit's run of the tile
+// lands in consecutive places: ranks follow input order inside a tile and
 // tiles follow input order, so every pass is stable.
 // ---------------------------------------------------------------------------
 constexpr int kSortBlock = 256;
@@ -43,7 +47,7 @@ constexpr int kSortItems = 16;
 constexpr int kTile = kSortBlock * kSortItems;
 
 template <class K>
-__global__ __launch_bounds__(kSortBlock) void k_km_upsweep(const K* __restrict__ keys, int64_t n, int shift,
+__global__ __launch_bounds__(kSortBlock) void k_km_upsweep(const K* __restrict__ keys, int64_t n, K kmask, int shift,
                                                            int64_t ntiles, int32_t* __restrict__ counts) {
     __shared__ int32_t hist[256];
     hist[threadIdx.x] = 0;
@@ -51,7 +55,7 @@ __global__ __launch_bounds__(kSortBlock) void k_km_upsweep(const K* __restrict__
     const int64_t base = (int64_t)blockIdx.x * kTile;
     for (int q = 0; q < kSortItems; ++q) {
         const int64_t e = base + (int64_t)q * kSortBlock + threadIdx.x;
-        if (e < n) atomicAdd(&hist[(uint32_t)(keys[e] >> shift) & 255u], 1);
+        if (e < n) atomicAdd(&hist[(uint32_t)((keys[e] & kmask) >> shift) & 255u], 1);
     }
     __syncthreads();
     counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
@@ -59,19 +63,29 @@ __global__ __launch_bounds__(kSortBlock) void k_km_upsweep(const K* __restrict__
 
 template <class K, class V>
 __global__ __launch_bounds__(kSortBlock) void k_km_downsweep(const K* __restrict__ kin, const V* __restrict__ vin,
-                                                             int64_t n, int shift, int64_t ntiles,
+                                                             int64_t n, K kmask, int shift, int64_t ntiles,
                                                              const int64_t* __restrict__ offsets,
                                                              K* __restrict__ kout, V* __restrict__ vout) {
     constexpr int W = kSortBlock / kWave;
+    constexpr int G = kSortItems * W;   // (sub-tile, wave) groups of 64 elements, in element order
+    constexpr size_t kCnt = sizeof(uint16_t) * G * 256;
+    constexpr size_t kStage = (sizeof(K) + sizeof(V)) * kTile;
+    // cnt[g][d] (elements of digit d in group g, then the digit's elements
+    // in the groups before g; a digit's column is scanned by one thread)
+    // and, once every element knows its slot, the tile in digit order
+    __shared__ __align__(16) unsigned char smem[kCnt > kStage ? kCnt : kStage];
     __shared__ int64_t run[256];
-    __shared__ int32_t wcnt[W][256];
-    __shared__ int64_t wpre[W][256];
+    __shared__ int32_t tstart[256];
+    __shared__ int32_t s_tmp[kSortBlock / kWave + 1];
+    uint16_t(*cnt)[256] = reinterpret_cast<uint16_t(*)[256]>(smem);
+    K* skey = reinterpret_cast<K*>(smem);
+    V* sval = reinterpret_cast<V*>(smem + sizeof(K) * kTile);
     const int tid = threadIdx.x, w = wave_id();
     run[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x];
-    for (int q = 0; q < W; ++q) wcnt[q][tid] = 0;
+    for (int g = 0; g < G; ++g) cnt[g][tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    // all loads of the tile are issued before any ranking work
+    const int tn = (int)min<int64_t>(kTile, n - base);   // elements of this tile
     K keyr[kSortItems];
     V valr[kSortItems];
 #pragma unroll
@@ -80,10 +94,13 @@ __global__ __launch_bounds__(kSortBlock) void k_km_downsweep(const K* __restrict
         keyr[sub] = kin[e];
         valr[sub] = vin[e];
     }
+    // rank of each element among the equal digits of its wave and sub-tile
+    // (8 ballots); the group's count per digit goes to LDS from its first lane
+    uint32_t slot[kSortItems];   // first rank << 8 | digit, then the slot in the tile
 #pragma unroll
     for (int sub = 0; sub < kSortItems; ++sub) {
-        const bool valid = base + (int64_t)sub * kSortBlock + tid < n;
-        const int d = (int)((uint32_t)(keyr[sub] >> shift) & 255u);
+        const bool valid = sub * kSortBlock + tid < tn;
+        const int d = (int)((uint32_t)((keyr[sub] & kmask) >> shift) & 255u);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -92,28 +109,50 @@ __global__ __launch_bounds__(kSortBlock) void k_km_downsweep(const K* __restrict
             peers &= bit ? bal : ~bal;
         }
         const int rank = __popcll(peers & lanemask_lt());
-        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-        __syncthreads();
-        {
-            int64_t acc = run[tid];
-            for (int q = 0; q < W; ++q) {
-                wpre[q][tid] = acc;
-                acc += wcnt[q][tid];
-                wcnt[q][tid] = 0;
-            }
-            run[tid] = acc;
+        if (valid && rank == 0) cnt[sub * W + w][d] = (uint16_t)__popcll(peers);
+        slot[sub] = ((uint32_t)rank << 8) | (uint32_t)d;
+    }
+    __syncthreads();
+    // digit tid: its count in each group becomes its elements before it;
+    // the digits' totals give their first slots in the tile
+    int32_t total = 0;
+    for (int g = 0; g < G; ++g) {
+        const int32_t c = cnt[g][tid];
+        cnt[g][tid] = (uint16_t)total;
+        total += c;
+    }
+    int32_t all;
+    const int32_t first = block_exclusive_sum<kSortBlock>(total, s_tmp, &all);
+    tstart[tid] = first;
+    __syncthreads();
+#pragma unroll
+    for (int sub = 0; sub < kSortItems; ++sub) {
+        const int d = (int)(slot[sub] & 255u);
+        slot[sub] = (uint32_t)(tstart[d] + cnt[sub * W + w][d]) + (slot[sub] >> 8);
+    }
+    __syncthreads();   // cnt is overwritten by the staged tile from here on
+#pragma unroll
+    for (int sub = 0; sub < kSortItems; ++sub) {
+        if (sub * kSortBlock + tid < tn) {
+            skey[slot[sub]] = keyr[sub];
+            sval[slot[sub]] = valr[sub];
         }
-        __syncthreads();
-        if (valid) {
-            const int64_t pos = wpre[w][d] + rank;
-            kout[pos] = keyr[sub];
-            vout[pos] = valr[sub];
-        }
+    }
+    __syncthreads();
+    // the tile in digit order: consecutive slots of a digit go to
+    // consecutive places of its output run
+    for (int q = tid; q < tn; q += kSortBlock) {
+        const K key = skey[q];
+        const int d = (int)((uint32_t)((key & kmask) >> shift) & 255u);
+        const int64_t pos = run[d] + (q - tstart[d]);
+        kout[pos] = key;
+        vout[pos] = sval[q];
     }
 }
 
-// Sorts (ka, va) by the low `bits` bits of the keys with (kb, vb) as the
-// other buffer; *in_b = 1 if the result ended in (kb, vb).
+// Sorts (ka, va) by the low `bits` bits of the keys (bits above them are
+// carried along, not sorted by) with (kb, vb) as the other buffer; *in_b = 1
+// if the result ended in (kb, vb).
 template <class K, class V>
 static int radix_sort(K* ka, V* va, K* kb, V* vb, int64_t n, int bits, int* in_b, Arena& ar) {
     *in_b = 0;
@@ -127,17 +166,18 @@ static int radix_sort(K* ka, V* va, K* kb, V* vb, int64_t n, int bits, int* in_b
     DB_TRY(ar.work_n(256 * ntiles + 1, &offsets));
     DB_TRY(ar.work_n(scan_workspace_elems(256 * ntiles), &scan_ws));
     const int passes = (bits + 7) / 8;
+    const K kmask = bits >= (int)(8 * sizeof(K)) ? ~K(0) : (K(1) << bits) - 1;
     K *kin = ka, *kout = kb;
     V *vin = va, *vout = vb;
     int tok = -1;
     DB_TRY(timing_begin(kPhKmerSort, st, &tok));
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_km_upsweep<K>, dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, kin, n, 8 * p, ntiles,
-                           counts);
+        hipLaunchKernelGGL(k_km_upsweep<K>, dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, kin, n, kmask, 8 * p,
+                           ntiles, counts);
         DB_HIP(hipGetLastError());
         DB_TRY(scan_exclusive_ws(counts, offsets, 256 * ntiles, nullptr, scan_ws, st));
         hipLaunchKernelGGL((k_km_downsweep<K, V>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, st, kin, vin, n,
-                           8 * p, ntiles, offsets, kout, vout);
+                           kmask, 8 * p, ntiles, offsets, kout, vout);
         DB_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -162,48 +202,80 @@ __global__ void k_km_count(const int64_t* __restrict__ off, int64_t n, int64_t n
     }
 }
 
-// Every window of read i at woff[i] + p: its canonical code, its number and
-// its strand bit (one bit per window, set with the wave's ballot).  One
-// wave per read; lane l takes positions l, l + 64, ...: the k base loads of
-// the wave read one contiguous run of bytes each.
+// A window's sort key: its canonical code in the low 2k bits and its strand
+// in bit 63 (the sort reads only the low 2k bits, so the strand rides along).
+constexpr int kStrandBit = 63;
+
+// Every window of read i at woff[i] + p: key (canonical code, strand) and
+// its number.  One wave per read, in chunks of 64 * kWinPer windows: the
+// chunk's bases are staged in LDS with coalesced loads, each lane rolls the
+// codes of kWinPer consecutive windows (one new base per window), the keys
+// are staged in LDS and written out coalesced.
+constexpr int kWinPer = 8;
+constexpr int kWinChunk = kWave * kWinPer;
+// LDS written by some lanes of a wave and read by others: order the
+// accesses of the wave (its waves never wait for each other here, so a
+// workgroup barrier is not an option).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 template <int WPB>
 __global__ __launch_bounds__(WPB* kWave) void k_km_windows(const uint8_t* __restrict__ bases,
                                                            const int64_t* __restrict__ off,
                                                            const int64_t* __restrict__ woff, int64_t n, int32_t k,
                                                            uint64_t* __restrict__ keys, uint32_t* __restrict__ wid,
-                                                           uint32_t* __restrict__ sbits, int32_t* __restrict__ flags) {
-    const int lane = lane_id();
+                                                           int32_t* __restrict__ flags) {
+    __shared__ uint8_t s_base[WPB][kWinChunk + 32];
+    __shared__ uint64_t s_key[WPB][kWinChunk];
+    const int lane = lane_id(), wv = wave_id();
+    const uint64_t mask = (k == 32) ? ~0ull : ((1ull << (2 * k)) - 1);
     int32_t bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(wave_id()); i < n;
+    for (int64_t i = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(wv); i < n;
          i += (int64_t)gridDim.x * WPB) {
         const int64_t lo = off[i], base = woff[i], nw = woff[i + 1] - base;
-        for (int64_t p0 = 0; p0 < nw; p0 += kWave) {
-            const int64_t p = p0 + lane;
-            const bool valid = p < nw;
-            uint64_t fwd = 0, rc = 0;
-            if (valid) {
-                for (int q = 0; q < k; ++q) {
-                    uint32_t b = bases[lo + p + q];
-                    bad |= b > 3u ? kKmBadBase : 0;
-                    b &= 3u;
-                    fwd = (fwd << 2) | b;
-                    rc |= (uint64_t)(3u - b) << (2 * q);
+        for (int64_t p0 = 0; p0 < nw; p0 += kWinChunk) {
+            const int cw = (int)min<int64_t>(kWinChunk, nw - p0);   // windows of this chunk
+            const int cb = cw + k - 1;                              // their bases
+            // all the chunk's base loads in flight before any is used
+            constexpr int kLoads = (kWinChunk + 31 + kWave - 1) / kWave;
+            uint32_t bv[kLoads];
+#pragma unroll
+            for (int it = 0; it < kLoads; ++it) {
+                const int q = lane + it * kWave;
+                bv[it] = bases[lo + p0 + min(q, cb - 1)];   // clamped: no branch per load
+            }
+#pragma unroll
+            for (int it = 0; it < kLoads; ++it) {
+                const int q = lane + it * kWave;
+                if (q < cb) {
+                    bad |= bv[it] > 3u ? kKmBadBase : 0;
+                    s_base[wv][q] = (uint8_t)(bv[it] & 3u);
                 }
-                keys[base + p] = rc < fwd ? rc : fwd;
-                wid[base + p] = (uint32_t)(base + p);
             }
-            const uint64_t mask = __ballot(valid && rc < fwd);
-            // bits of windows base + p0 .. + 63, spread over up to three words
-            const int64_t w0 = base + p0;
-            const int sh = (int)(w0 & 31);
-            const int64_t word = w0 >> 5;
-            if (lane < 3 && mask) {
-                uint32_t part;
-                if (lane == 0) part = (uint32_t)(mask << sh);
-                else if (lane == 1) part = sh ? (uint32_t)(mask >> (32 - sh)) : (uint32_t)(mask >> 32);
-                else part = sh ? (uint32_t)(mask >> (64 - sh)) : 0u;
-                if (part) atomicOr(&sbits[word + lane], part);
+            wave_lds_sync();
+            const int j0 = lane * kWinPer;
+            if (j0 < cw) {
+                uint64_t fwd = 0, rc = 0;
+                for (int q = 0; q < k - 1; ++q) {
+                    const uint32_t b = s_base[wv][j0 + q];
+                    fwd = (fwd << 2) | b;
+                    rc = (rc >> 2) | ((uint64_t)(3u - b) << (2 * (k - 1)));
+                }
+                for (int j = j0; j < j0 + kWinPer && j < cw; ++j) {
+                    const uint32_t b = s_base[wv][j + k - 1];
+                    fwd = ((fwd << 2) | b) & mask;
+                    rc = (rc >> 2) | ((uint64_t)(3u - b) << (2 * (k - 1)));
+                    s_key[wv][j] = rc < fwd ? (rc | (1ull << kStrandBit)) : fwd;
+                }
             }
+            wave_lds_sync();
+            for (int q = lane; q < cw; q += kWave) {
+                keys[base + p0 + q] = s_key[wv][q];
+                wid[base + p0 + q] = (uint32_t)(base + p0 + q);
+            }
+            wave_lds_sync();
         }
     }
     bad = wave_or_i32(bad);
@@ -213,85 +285,100 @@ __global__ __launch_bounds__(WPB* kWave) void k_km_windows(const uint8_t* __rest
 // ---------------------------------------------------------------------------
 // Runs of equal k-mers
 // ---------------------------------------------------------------------------
-// The first element h <= e of e's run, or -1 when the run holds more than
-// hi elements before e (then it is not reliable).
-__device__ __forceinline__ int64_t run_head(const uint64_t* keys, int64_t e, int32_t hi) {
-    const uint64_t c = keys[e];
+// The read of window w (the last i with woff[i] <= w; woff[n] = W > w):
+// rtab[w >> kRtabShift] is the read holding window (w >> kRtabShift) <<
+// kRtabShift, and the reads from there on are stepped through (two loads
+// for reads longer than 2^kRtabShift windows, instead of a binary search of
+// some 18 dependent loads).
+constexpr int kRtabShift = 12;
+__device__ __forceinline__ int64_t read_of(const uint32_t* rtab, const int64_t* woff, int64_t w) {
+    int64_t r = rtab[w >> kRtabShift];
+    while (woff[r + 1] <= w) ++r;
+    return r;
+}
+
+// rtab[b] = the read holding window b << kRtabShift, for every b below
+// ceil(W / 2^kRtabShift): each read writes the b whose window it holds.
+__global__ void k_km_rtab(const int64_t* __restrict__ woff, int64_t n, uint32_t* __restrict__ rtab) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = woff[i], z = woff[i + 1];
+        for (int64_t b = (a + (int64_t(1) << kRtabShift) - 1) >> kRtabShift; (b << kRtabShift) < z; ++b)
+            rtab[b] = (uint32_t)i;
+    }
+}
+
+// The first element h <= e of e's run (equal codes under `mask`), or -1
+// when the run holds more than hi elements before e (then it is not
+// reliable).
+__device__ __forceinline__ int64_t run_head(const uint64_t* keys, uint64_t mask, int64_t e, int32_t hi) {
+    const uint64_t c = keys[e] & mask;
     int64_t h = e;
-    for (int32_t s = 0; h > 0 && keys[h - 1] == c; ++s) {
+    for (int32_t s = 0; h > 0 && (keys[h - 1] & mask) == c; ++s) {
         if (s >= hi) return -1;
         --h;
     }
     return h;
 }
 
-// rel[e] = 1 where e starts a run of length in [lo, hi] (the length read at
-// most hi + 1 elements far).
-__global__ void k_km_runs(const uint64_t* __restrict__ keys, int64_t W, int32_t lo, int32_t hi,
+// rel[e] = 1 where e starts a run (equal codes under `mask`) of length in
+// [lo, hi] (the length read at most hi + 1 elements far).
+__global__ void k_km_runs(const uint64_t* __restrict__ keys, int64_t W, uint64_t mask, int32_t lo, int32_t hi,
                           int32_t* __restrict__ rel) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < W; e += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t c = keys[e];
+        const uint64_t c = keys[e] & mask;
         int32_t r = 0;
-        if (e == 0 || keys[e - 1] != c) {
+        if (e == 0 || (keys[e - 1] & mask) != c) {
             int64_t len = 1;
-            while (len <= hi && e + len < W && keys[e + len] == c) ++len;
+            while (len <= hi && e + len < W && (keys[e + len] & mask) == c) ++len;
             r = (len >= lo && len <= hi) ? 1 : 0;
         }
         rel[e] = r;
     }
 }
 
-// The read of window w: the last i with woff[i] <= w (woff[n] = W > w).
-__device__ __forceinline__ int64_t read_of(const int64_t* woff, int64_t n, int64_t w) {
-    int64_t a = 0, b = n;   // woff[a] <= w < woff[b]
-    while (b - a > 1) {
-        const int64_t m = (a + b) >> 1;
-        if (woff[m] <= w) a = m;
-        else b = m;
-    }
-    return a;
-}
-
-// keep[e] = 1 for the first element of each read inside a reliable run
-// (the run is in window order: the element before e, if in the run, has a
-// smaller window, of the same read iff it is not before the read's first).
+// keep[e] = 1 for the first element of each read inside a reliable run (the
+// run is in window order: an element is its read's first in the run iff
+// the element before it holds a window of an earlier read); rd[e] = the
+// read of every element of a reliable run.
 __global__ void k_km_keep(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ wid, int64_t W,
-                          const int64_t* __restrict__ woff, int64_t n, int32_t hi, const int32_t* __restrict__ rel,
-                          int32_t* __restrict__ keep) {
+                          uint64_t mask, const uint32_t* __restrict__ rtab, const int64_t* __restrict__ woff,
+                          int32_t hi, const int32_t* __restrict__ rel, int32_t* __restrict__ keep,
+                          uint32_t* __restrict__ rd) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < W; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t h = run_head(keys, e, hi);
+        const int64_t h = run_head(keys, mask, e, hi);
         int32_t k = 0;
-        if (h >= 0 && rel[h]) k = (h == e || (int64_t)wid[e - 1] < woff[read_of(woff, n, wid[e])]) ? 1 : 0;
+        if (h >= 0 && rel[h]) {
+            const int64_t r = read_of(rtab, woff, wid[e]);
+            k = (h == e || (int64_t)wid[e - 1] < woff[r]) ? 1 : 0;
+            rd[e] = (uint32_t)r;
+        }
         keep[e] = k;
     }
 }
 
 // The kept elements as A entries in (column, read) order: key = read,
-// value = (column << 32) | (position, or (position << 1) | strand).
+// value = (column << 32) | (position, or (position << 1) | strand); a
+// reliable run's first element also writes the run's k-mer to codes.
 __global__ void k_km_emit(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ wid, int64_t W,
-                          const int64_t* __restrict__ woff, int64_t n, int32_t hi, const int64_t* __restrict__ colof,
-                          const int32_t* __restrict__ keep, const int64_t* __restrict__ kpos,
-                          const uint32_t* __restrict__ sbits, int strand_bit, uint32_t* __restrict__ rkey,
-                          uint64_t* __restrict__ rval) {
+                          uint64_t mask, const uint32_t* __restrict__ rd, const int64_t* __restrict__ woff,
+                          int32_t hi, const int64_t* __restrict__ colof, const int32_t* __restrict__ keep,
+                          const int64_t* __restrict__ kpos, int strand_bit, uint32_t* __restrict__ rkey,
+                          uint64_t* __restrict__ rval, uint64_t* __restrict__ codes) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < W; e += (int64_t)gridDim.x * blockDim.x) {
         if (!keep[e]) continue;
-        const int64_t h = run_head(keys, e, hi);   // >= 0: kept elements lie in reliable runs
+        const int64_t h = run_head(keys, mask, e, hi);   // >= 0: kept elements lie in reliable runs
+        const uint64_t key = keys[e];
+        const int64_t col = colof[h];
+        if (h == e) codes[col] = key & mask;
         const int64_t w = wid[e];
-        const int64_t r = read_of(woff, n, w);
+        const int64_t r = rd[e];
         const int64_t pos = w - woff[r];
-        const uint32_t strand = (sbits[w >> 5] >> (w & 31)) & 1u;
+        const uint32_t strand = (uint32_t)(key >> kStrandBit);
         const uint32_t v = strand_bit ? (uint32_t)((pos << 1) | strand) : (uint32_t)pos;
         const int64_t o = kpos[e];
         rkey[o] = (uint32_t)r;
-        rval[o] = ((uint64_t)(uint32_t)colof[h] << 32) | v;
+        rval[o] = ((uint64_t)(uint32_t)col << 32) | v;
     }
-}
-
-// codes[column] = the reliable run's k-mer.
-__global__ void k_km_codes(const uint64_t* __restrict__ keys, int64_t W, const int32_t* __restrict__ rel,
-                           const int64_t* __restrict__ colof, uint64_t* __restrict__ codes) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < W; e += (int64_t)gridDim.x * blockDim.x)
-        if (rel[e]) codes[colof[e]] = keys[e];
 }
 
 // A's row pointers from the entries sorted by read: rowptr[r] = the first
@@ -383,20 +470,23 @@ int kmer_matrix_run(const uint8_t* bases, const int64_t* offsets, int64_t n, int
     {
         Arena wk(ar.alloc_fn(), ar.free_fn(), ar.alloc_ctx(), st);
         uint64_t *keys[2];
-        uint32_t *wid[2], *sbits;
+        uint32_t *wid[2], *rtab;
         int32_t *rel, *keep;
         int64_t *colof, *kpos;
         DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &keys[0]));
         DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &keys[1]));
         DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &wid[0]));
         DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &wid[1]));
-        DB_TRY(wk.work_n(ceil_div(W, 32) + 3, &sbits));
-        DB_TRY(fill_i32(reinterpret_cast<int32_t*>(sbits), 0, ceil_div(W, 32) + 3, st));
+        DB_TRY(wk.work_n(ceil_div(W, int64_t(1) << kRtabShift) + 1, &rtab));
+        if (n > 0 && W > 0) {
+            hipLaunchKernelGGL(k_km_rtab, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, woff, n, rtab);
+            DB_HIP(hipGetLastError());
+        }
         constexpr int WPB = 4;
         DB_TRY(timing_begin(kPhKmerWindows, st, &tok));
         if (n > 0 && W > 0) {
             hipLaunchKernelGGL(k_km_windows<WPB>, dim3(grid_for(n, WPB, 1 << 16)), dim3(WPB * kWave), 0, st, bases,
-                               offsets, woff, n, k, keys[0], wid[0], sbits, d_flags);
+                               offsets, woff, n, k, keys[0], wid[0], d_flags);
             DB_HIP(hipGetLastError());
         }
         DB_TRY(timing_end(tok, st));
@@ -409,16 +499,17 @@ int kmer_matrix_run(const uint8_t* bases, const int64_t* offsets, int64_t n, int
         DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &keep));
         DB_TRY(wk.work_n(W + 1, &kpos));
         const int grid = grid_for(W, 256, 1 << 16);
+        const uint64_t cmask = (1ull << (2 * k)) - 1;   // k <= 31: the code bits
+        uint32_t* rd;
+        DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &rd));
         DB_TRY(timing_begin(kPhKmerRuns, st, &tok));
         if (W > 0) {
-            hipLaunchKernelGGL(k_km_runs, dim3(grid), dim3(256), 0, st, sk, W, lo, hi, rel);
+            hipLaunchKernelGGL(k_km_runs, dim3(grid), dim3(256), 0, st, sk, W, cmask, lo, hi, rel);
+            hipLaunchKernelGGL(k_km_keep, dim3(grid), dim3(256), 0, st, sk, sw, W, cmask, rtab, woff, hi, rel, keep,
+                               rd);
             DB_HIP(hipGetLastError());
         }
         DB_TRY(scan_exclusive(rel, colof, W, nullptr, wk));
-        if (W > 0) {
-            hipLaunchKernelGGL(k_km_keep, dim3(grid), dim3(256), 0, st, sk, sw, W, woff, n, hi, rel, keep);
-            DB_HIP(hipGetLastError());
-        }
         DB_TRY(scan_exclusive(keep, kpos, W, nullptr, wk));
         DB_TRY(timing_end(tok, st));
         // ---- sync 2: k-mers, entries, the bases' check
@@ -447,9 +538,8 @@ int kmer_matrix_run(const uint8_t* bases, const int64_t* offsets, int64_t n, int
         DB_TRY(ar.work_n(std::max<int64_t>(nnz, 1), &rval[1]));
         DB_TRY(timing_begin(kPhKmerRuns, st, &tok));
         if (W > 0) {
-            hipLaunchKernelGGL(k_km_codes, dim3(grid), dim3(256), 0, st, sk, W, rel, colof, codes);
-            hipLaunchKernelGGL(k_km_emit, dim3(grid), dim3(256), 0, st, sk, sw, W, woff, n, hi, colof, keep, kpos,
-                               sbits, strand_bit, rkey[0], rval[0]);
+            hipLaunchKernelGGL(k_km_emit, dim3(grid), dim3(256), 0, st, sk, sw, W, cmask, rd, woff, hi, colof, keep,
+                               kpos, strand_bit, rkey[0], rval[0], codes);
             DB_HIP(hipGetLastError());
         }
         DB_TRY(timing_end(tok, st));
