@@ -67,6 +67,9 @@ def _load():
         lib.oracle_tr_pass_marks.argtypes = [i64, P, P, P, i32, u32, P, i64, P]
         lib.oracle_r_from_seeds.argtypes = [i64, P, P, P, P, P, i32, i32, i32, i32, P, P, P, P]
         lib.oracle_kmer_matrix.argtypes = [i64, P, P, i32, i32, i32, i32, P, P, P, P, P, P]
+        lib.oracle_r_from_alignment.argtypes = [i64, P, P, P, P, P, i32, i32, i32, i32, i32, i32, P, P, P, P, P]
+        lib.oracle_xdrop_extend.argtypes = [P, i64, P, i64, i32, i32, i32, i32, P, P]
+        lib.oracle_xdrop_extend.restype = i64
         lib.oracle_free.argtypes = [P]
         _lib = lib
     return _lib
@@ -229,3 +232,50 @@ def kmer_matrix(bases, offsets, k: int, lo: int, hi: int, strand_bit: bool = Fal
     A = SimpleNamespace(nrows=n, ncols=m.value, nnz=nnz.value, rowptr=out_rp,
                         col=_take(lib, pc, nnz.value, np.int32), val=_take(lib, pv, nnz.value, np.int32))
     return A, _take(lib, pk, m.value, np.uint64)
+
+
+def r_from_alignment(C, bases, offsets, k: int, match: int = 1, mismatch: int = -1, gap: int = -2,
+                     xdrop: int = 25, min_score: int = 0):
+    """Seed-and-extend alignment of every off-diagonal entry of C from its
+    first seed (X-drop extension both ways, linear scores) and the graph R
+    from the alignment ends of the pairs scoring at least min_score.
+    Returns (R, score) with score[e] the score of C's entry e (0 on the
+    diagonal).  Raises ValueError on a missing or out-of-range seed, a base
+    outside 0..3, offsets that do not run from 0 up to len(bases) over
+    C.ncols reads, a read of 2^28 bases or more, or scores outside match in
+    [1, 7], mismatch in [-1024, 0], gap in [-1024, -1], xdrop in [0, 2^20]."""
+    lib = _load()
+    n = int(C.nrows)
+    rp = np.ascontiguousarray(C.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(C.col, dtype=np.int32)
+    sd = np.ascontiguousarray(np.asarray(C.seed).reshape(-1), dtype=np.int32)
+    b = np.ascontiguousarray(bases, dtype=np.uint8)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    ncols = int(getattr(C, "ncols", n))
+    if ncols != n or off.size != n + 1 or off[0] != 0 or off[-1] != b.size or np.any(np.diff(off) < 0):
+        raise ValueError("C must be square with one offset per read plus one, from 0 to len(bases), non-decreasing")
+    out_rp = np.zeros(n + 1, np.int64)
+    score = np.zeros(len(ci), np.int32)
+    pc, pv = ctypes.c_void_p(), ctypes.c_void_p()
+    nnz = ctypes.c_int64()
+    r = lib.oracle_r_from_alignment(n, _ptr(rp), _ptr(ci), _ptr(sd), _ptr(b), _ptr(off), int(k), int(match),
+                                    int(mismatch), int(gap), int(xdrop), int(min_score), _ptr(out_rp),
+                                    ctypes.byref(pc), ctypes.byref(pv), _ptr(score), ctypes.byref(nnz))
+    if r != 0:
+        raise ValueError("a seed of C is missing or outside its read, a base is outside 0..3, a read is too "
+                         "long or a score is out of range")
+    R = SimpleNamespace(nrows=n, ncols=n, nnz=nnz.value, rowptr=out_rp, col=_take(lib, pc, nnz.value, np.int32),
+                        val=_take(lib, pv, nnz.value, np.int32))
+    return R, score
+
+
+def xdrop_extend(a, b, match: int = 1, mismatch: int = -1, gap: int = -2, xdrop: int = 25):
+    """X-drop extension of base array a against b from their starts:
+    (best score, (i, j) of the first cell reaching it)."""
+    lib = _load()
+    aa = np.ascontiguousarray(a, dtype=np.uint8)
+    bb = np.ascontiguousarray(b, dtype=np.uint8)
+    ea, eb = ctypes.c_int64(), ctypes.c_int64()
+    s = lib.oracle_xdrop_extend(_ptr(aa), len(aa), _ptr(bb), len(bb), int(match), int(mismatch), int(gap),
+                                int(xdrop), ctypes.byref(ea), ctypes.byref(eb))
+    return int(s), (ea.value, eb.value)

@@ -564,3 +564,178 @@ int oracle_kmer_matrix(int64_t n, const uint8_t* bases, const int64_t* offsets, 
     *out_col = oc; *out_val = ov; *out_codes = codes; *out_m = m; *out_nnz = nnz;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Seed-and-extend alignment of C's read pairs and the graph R it gives     */
+/* (Sec. IV-D: each nonzero of C is aligned by extending its seed, and      */
+/* pruned when the score does not reach a threshold; Sec. IV-E: R's suffix   */
+/* and orientation come from the alignment coordinates)                     */
+/* ------------------------------------------------------------------------ */
+/* X-drop extension (Zhang, Schwartz, Wagner and Miller, 2000) of a against
+ * b from their starts: T(i, j) is the best score of aligning a[0, i) with
+ * b[0, j) (match `mat`, mismatch `mis`, a base against a gap `gap`; T(0, 0) =
+ * 0), computed anti-diagonal by anti-diagonal (d = i + j).  On anti-diagonal
+ * d the cells considered are those reachable from a live cell of d - 1 (i
+ * or i - 1 there) or d - 2 (i - 1 there); a cell whose score is below the
+ * best score of the earlier anti-diagonals minus X is dead, as are cells
+ * with no live predecessor.  The best score and the first cell (in
+ * anti-diagonal order, then i order) reaching it are the result.  The
+ * extension stops when two anti-diagonals in a row have no live cell, at
+ * the sequences' ends, or when the cells to consider on one anti-diagonal
+ * would exceed ORACLE_XD_BAND (then it keeps what it has). */
+#define ORACLE_XD_BAND 256
+#define ORACLE_XD_DEAD INT64_MIN
+
+static int64_t xdrop_extend(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int32_t mat, int32_t mis,
+                            int32_t gap, int32_t X, int64_t* ea, int64_t* eb) {
+    int64_t* dg[3];   /* anti-diagonals d - 2, d - 1, d, indexed by i */
+    for (int t = 0; t < 3; ++t) {
+        dg[t] = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)(m + 1));
+        for (int64_t i = 0; i <= m; ++i) dg[t][i] = ORACLE_XD_DEAD;
+    }
+    int64_t lo[3], hi[3];   /* live range of each kept anti-diagonal (lo > hi: none) */
+    int64_t best = 0;
+    *ea = 0; *eb = 0;
+    /* d = 0: the cell (0, 0) */
+    dg[2][0] = 0; lo[2] = 0; hi[2] = 0;
+    lo[1] = 1; hi[1] = 0;   /* d = -1: none */
+    lo[0] = 1; hi[0] = 0;   /* d = -2: none */
+    for (int64_t d = 1; d <= m + n; ++d) {
+        /* shift: d - 1 becomes d - 2, d becomes d - 1 */
+        int64_t* old = dg[0];
+        for (int64_t i = (lo[0] <= hi[0] ? lo[0] : 1); i <= hi[0]; ++i) old[i] = ORACLE_XD_DEAD;
+        dg[0] = dg[1]; lo[0] = lo[1]; hi[0] = hi[1];
+        dg[1] = dg[2]; lo[1] = lo[2]; hi[1] = hi[2];
+        dg[2] = old;
+        if (lo[0] > hi[0] && lo[1] > hi[1]) { lo[2] = 1; hi[2] = 0; break; }   /* two dead anti-diagonals */
+        int64_t from = INT64_MAX, to = INT64_MIN;
+        if (lo[1] <= hi[1]) { from = lo[1]; to = hi[1] + 1; }
+        if (lo[0] <= hi[0]) { if (lo[0] + 1 < from) from = lo[0] + 1; if (hi[0] + 1 > to) to = hi[0] + 1; }
+        if (from < d - n) from = d - n;
+        if (from < 0) from = 0;
+        if (to > m) to = m;
+        if (to > d) to = d;
+        lo[2] = 1; hi[2] = 0;
+        if (from > to) continue;
+        if (to - from + 1 > ORACLE_XD_BAND) break;
+        int64_t dbest = ORACLE_XD_DEAD, di = -1;
+        for (int64_t i = from; i <= to; ++i) {
+            int64_t j = d - i, v = ORACLE_XD_DEAD;
+            if (i >= 1 && j >= 1 && dg[0][i - 1] != ORACLE_XD_DEAD)
+                v = dg[0][i - 1] + (a[i - 1] == b[j - 1] ? mat : mis);
+            if (i >= 1 && dg[1][i - 1] != ORACLE_XD_DEAD && dg[1][i - 1] + gap > v) v = dg[1][i - 1] + gap;
+            if (j >= 1 && dg[1][i] != ORACLE_XD_DEAD && dg[1][i] + gap > v) v = dg[1][i] + gap;
+            if (v != ORACLE_XD_DEAD && v < best - X) v = ORACLE_XD_DEAD;   /* x-drop */
+            dg[2][i] = v;
+            if (v != ORACLE_XD_DEAD) {
+                if (lo[2] > hi[2]) lo[2] = i;
+                hi[2] = i;
+                if (v > dbest) { dbest = v; di = i; }
+            }
+        }
+        if (dbest != ORACLE_XD_DEAD && dbest > best) { best = dbest; *ea = di; *eb = d - di; }
+    }
+    for (int t = 0; t < 3; ++t) free(dg[t]);
+    return best;
+}
+
+/* For every off-diagonal entry of C (seeds (position << 1) | strand as in
+ * oracle_r_from_seeds): read j is taken as sequenced, or reverse
+ * complemented when the strands differ (j'); the first seed's k-mer sits at
+ * p_i in read i and at q = p_j, or L_j - k - p_j in j'.  The seed (k
+ * matches) is extended to the right (i after p_i + k against j' after
+ * q + k) and to the left (the reversed prefixes before p_i and q) by X-drop
+ * extension; the score is the two extensions' plus k * mat, and the
+ * alignment spans [bi, ei) of i and [bj, ej) of j'.  Pairs scoring below
+ * min_score are pruned.  The rest give R's entry from the alignment ends:
+ * one read contained in the other (its unaligned ends both within the
+ * other's) -> value 0; else read i first (bi > bj): suffix (L_j - ej) -
+ * (L_i - ei), code (0, rc); else suffix bj - bi, code (1, 1 - rc).
+ * Outputs as oracle_r_from_seeds, plus score[nnz(C)] (the score of every
+ * entry of C, 0 on the diagonal).  Returns 0, or -1 for a missing or
+ * out-of-range seed, a base outside 0..3 in any read, a read length of 2^28
+ * or more, or scores outside match in [1, 7], mismatch in [-1024, 0], gap in
+ * [-1024, -1], X in [0, 2^20] (the ranges keep every score within 32 bits). */
+static uint8_t seq_at(const uint8_t* s, int64_t L, int rc, int64_t x) {
+    return rc ? (uint8_t)(3 - s[L - 1 - x]) : s[x];
+}
+
+int oracle_r_from_alignment(int64_t n, const int64_t* c_rowptr, const int32_t* c_col, const int32_t* c_seed,
+                            const uint8_t* bases, const int64_t* offsets, int32_t k, int32_t mat, int32_t mis,
+                            int32_t gap, int32_t X, int32_t min_score, int64_t* out_rowptr, int32_t** out_col,
+                            int32_t** out_val, int32_t* out_score, int64_t* out_nnz) {
+    if (k < 1 || k > 32 || mat < 1 || mat > 7 || mis < -1024 || mis > 0 || gap < -1024 || gap > -1 || X < 0 ||
+        X > (1 << 20))
+        return -1;
+    for (int64_t r = 0; r < n; ++r) {
+        if (offsets[r + 1] - offsets[r] < 0 || offsets[r + 1] - offsets[r] >= ((int64_t)1 << 28)) return -1;
+        for (int64_t x = offsets[r]; x < offsets[r + 1]; ++x)
+            if (bases[x] > 3) return -1;
+    }
+    int64_t cap = 1024, nnz = 0;
+    int32_t* oc = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
+    int32_t* ov = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)cap);
+    out_rowptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint8_t* si = bases + offsets[i];
+        int64_t li = offsets[i + 1] - offsets[i];
+        for (int64_t e = c_rowptr[i]; e < c_rowptr[i + 1]; ++e) {
+            int32_t j = c_col[e];
+            out_score[e] = 0;
+            if (j == (int32_t)i) continue;
+            const uint8_t* sj = bases + offsets[j];
+            int64_t lj = offsets[j + 1] - offsets[j];
+            int32_t a = c_seed[4 * e + 0], b = c_seed[4 * e + 1];
+            if (a < 0 || b < 0 || (a >> 1) + k > li || (b >> 1) + k > lj) {
+                free(oc); free(ov);
+                return -1;
+            }
+            int rc = (a & 1) != (b & 1);
+            int64_t pi = a >> 1, q = rc ? lj - k - (b >> 1) : (b >> 1);
+            /* the oriented sequences of the two extensions */
+            int64_t mr = li - pi - k, nr = lj - q - k, ml = pi, nl = q;
+            uint8_t* ar = (uint8_t*)xmalloc((size_t)(mr + 1));
+            uint8_t* br = (uint8_t*)xmalloc((size_t)(nr + 1));
+            uint8_t* al = (uint8_t*)xmalloc((size_t)(ml + 1));
+            uint8_t* bl = (uint8_t*)xmalloc((size_t)(nl + 1));
+            for (int64_t x = 0; x < mr; ++x) ar[x] = si[pi + k + x];
+            for (int64_t x = 0; x < nr; ++x) br[x] = seq_at(sj, lj, rc, q + k + x);
+            for (int64_t x = 0; x < ml; ++x) al[x] = si[pi - 1 - x];
+            for (int64_t x = 0; x < nl; ++x) bl[x] = seq_at(sj, lj, rc, q - 1 - x);
+            int64_t ear, ebr, eal, ebl;
+            int64_t sr = xdrop_extend(ar, mr, br, nr, mat, mis, gap, X, &ear, &ebr);
+            int64_t sl = xdrop_extend(al, ml, bl, nl, mat, mis, gap, X, &eal, &ebl);
+            free(ar); free(br); free(al); free(bl);
+            int64_t score = sl + (int64_t)k * mat + sr;
+            out_score[e] = (int32_t)score;
+            if (score < min_score) continue;
+            int64_t bi = pi - eal, ei = pi + k + ear, bj = q - ebl, ej = q + k + ebr;
+            int64_t ri = li - ei, rj = lj - ej;   /* unaligned right ends */
+            int32_t val;
+            if ((bj >= bi && rj >= ri) || (bi >= bj && ri >= rj)) {
+                val = 0;                                            /* contained */
+            } else if (bi > bj) {
+                val = (int32_t)(((rj - ri) << 2) | (rc ? 1 : 0));  /* i first */
+            } else {
+                val = (int32_t)(((bj - bi) << 2) | (rc ? 2 : 3));  /* j first */
+            }
+            if (nnz == cap) {
+                cap *= 2;
+                oc = (int32_t*)realloc(oc, sizeof(int32_t) * (size_t)cap);
+                ov = (int32_t*)realloc(ov, sizeof(int32_t) * (size_t)cap);
+            }
+            oc[nnz] = j;
+            ov[nnz] = val;
+            ++nnz;
+        }
+        out_rowptr[i + 1] = nnz;
+    }
+    *out_col = oc; *out_val = ov; *out_nnz = nnz;
+    return 0;
+}
+
+/* X-drop extension of a against b (for the tests). */
+int64_t oracle_xdrop_extend(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, int32_t mat, int32_t mis,
+                            int32_t gap, int32_t X, int64_t* ea, int64_t* eb) {
+    return xdrop_extend(a, m, b, n, mat, mis, gap, X, ea, eb);
+}

@@ -663,3 +663,298 @@ def test_kmer_matrix_rejects_bad_arguments(k, lo, hi, bad_base):
     bases = np.array([0, 1, 2, 3, 4 if bad_base else 0, 1, 2], np.uint8)
     with pytest.raises(ValueError):
         oracle.kmer_matrix(bases, np.array([0, 7], np.int64), k, lo, hi)
+
+
+# ---------------------------------------------------------------------------
+# Seed-and-extend alignment of C's pairs, and R from its ends
+# (Sec. IV-D: Apply(C, Alignment()) and Prune(C, AlignmentScoreLessThan(t)))
+# ---------------------------------------------------------------------------
+
+def _full_dp_best(a, b, mat, mis, gap):
+    """Every cell of the extension table, no pruning: T(i, j) is the best
+    score of aligning a[:i] with b[:j] from T(0, 0) = 0.  Returns the largest
+    T and the first cell holding it, scanning i + j upward, then i upward."""
+    m, n = len(a), len(b)
+    T = [[0] * (n + 1) for _ in range(m + 1)]
+    for i in range(m + 1):
+        for j in range(n + 1):
+            if i == 0 and j == 0:
+                continue
+            cands = []
+            if i and j:
+                cands.append(T[i - 1][j - 1] + (mat if a[i - 1] == b[j - 1] else mis))
+            if i:
+                cands.append(T[i - 1][j] + gap)
+            if j:
+                cands.append(T[i][j - 1] + gap)
+            T[i][j] = max(cands)
+    best, at = 0, (0, 0)
+    for d in range(m + n + 1):
+        for i in range(max(0, d - n), min(m, d) + 1):
+            if T[i][d - i] > best:
+                best, at = T[i][d - i], (i, d - i)
+    return best, at
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_xdrop_with_unbounded_drop_is_the_full_table(seed):
+    """With X beyond any score range nothing is pruned: the extension's
+    best and its cell are those of the whole table (random and similar
+    pairs, several scoring schemes, empty sequences)."""
+    rng = np.random.default_rng(900 + seed)
+    for t in range(25):
+        m, n = int(rng.integers(0, 36)), int(rng.integers(0, 36))
+        a = rng.integers(0, 4, size=m, dtype=np.uint8)
+        if t % 2:                                    # b: a with substitutions and shifts
+            b = a.copy()
+            flip = rng.random(m) < 0.2
+            b[flip] = (b[flip] + 1) % 4
+            b = np.concatenate([b[: m // 3], rng.integers(0, 4, size=int(rng.integers(0, 3)), dtype=np.uint8),
+                                b[m // 3 + int(rng.integers(0, 2)):]])[:n] if m else b
+        else:
+            b = rng.integers(0, 4, size=n, dtype=np.uint8)
+        mat, mis, gap = int(rng.integers(1, 4)), -int(rng.integers(1, 4)), -int(rng.integers(1, 5))
+        got = oracle.xdrop_extend(a, b, mat, mis, gap, 10 ** 6)
+        assert got == _full_dp_best(list(a), list(b), mat, mis, gap), (seed, t, m, len(b))
+
+
+def test_xdrop_prunes_a_drop_beyond_x_and_keeps_one_of_exactly_x():
+    """50 matches, then 10 bases that cannot match (A against C), then 50
+    matches: crossing costs 10, so X = 10 reaches the far end (score 90)
+    and X = 9 stops after the first run (score 50)."""
+    rng = np.random.default_rng(910)
+    p1, p2 = rng.integers(0, 4, size=50, dtype=np.uint8), rng.integers(0, 4, size=50, dtype=np.uint8)
+    a = np.concatenate([p1, np.zeros(10, np.uint8), p2])
+    b = np.concatenate([p1, np.ones(10, np.uint8), p2])
+    assert oracle.xdrop_extend(a, b, 1, -1, -1, 10) == (90, (110, 110))
+    assert oracle.xdrop_extend(a, b, 1, -1, -1, 9) == (50, (50, 50))
+    assert oracle.xdrop_extend(a, b, 1, -1, -1, 10 ** 6) == _full_dp_best(list(a), list(b), 1, -1, -1)
+
+
+def test_xdrop_ends_at_the_last_match_before_unrelated_tails():
+    """Identical 300 bases followed by tails that never match (all A against
+    all C): the extension ends where the identical part does."""
+    rng = np.random.default_rng(911)
+    p = rng.integers(0, 4, size=300, dtype=np.uint8)
+    a = np.concatenate([p, np.zeros(500, np.uint8)])
+    b = np.concatenate([p, np.ones(400, np.uint8)])
+    for X in (1, 5, 50, 200):
+        assert oracle.xdrop_extend(a, b, 1, -1, -1, X) == (300, (300, 300))
+    assert oracle.xdrop_extend(a, b, 2, -3, -4, 25) == (600, (300, 300))
+
+
+def test_xdrop_band_limit():
+    """An anti-diagonal with more than 256 cells to consider ends the
+    extension with the best so far: with nothing pruned on two identical
+    3000-base sequences, anti-diagonal 256 would need 257 cells, so the best
+    is that of anti-diagonals 0..255, T(127, 127) = 127; with X = 50 the
+    band stays narrow and the extension reaches (3000, 3000)."""
+    rng = np.random.default_rng(912)
+    p = rng.integers(0, 4, size=3000, dtype=np.uint8)
+    assert oracle.xdrop_extend(p, p, 1, -1, -1, 10 ** 6) == (127, (127, 127))
+    assert oracle.xdrop_extend(p, p, 1, -1, -1, 50) == (3000, (3000, 3000))
+    # one sequence of 255 bases: every anti-diagonal has at most 256 cells
+    q = p[:255]
+    assert oracle.xdrop_extend(q, p, 1, -1, -1, 10 ** 6) == (255, (255, 255))
+
+
+def test_xdrop_ties_go_to_the_first_cell():
+    """Match 2, gaps -1: AC against CA reaches 1 at (1, 2) (a gap, then
+    A = A) and at (2, 1) (a gap, then C = C), both on anti-diagonal 3: the
+    smaller i is the end.  A best equalled on a later anti-diagonal does
+    not move the end; a larger one does."""
+    assert _full_dp_best([0, 1], [1, 0], 2, -1, -1) == (1, (1, 2))
+    assert oracle.xdrop_extend(np.array([0, 1], np.uint8), np.array([1, 0], np.uint8), 2, -1, -1, 100) == (1, (1, 2))
+    assert oracle.xdrop_extend(np.array([1, 0], np.uint8), np.array([0, 1], np.uint8), 2, -1, -1, 100) == (1, (1, 2))
+    # equal best on a later anti-diagonal: A,A against A,C,A -> 2 at (1,1), then (2,3): 2 + (-1) + 2 = 3
+    assert oracle.xdrop_extend(np.array([0, 0], np.uint8), np.array([0, 1, 0], np.uint8), 2, -1, -1, 100) == (3, (2, 3))
+    # A against A,C: 2 at (1,1); (1,2) = 1 is lower; the end stays (1,1)
+    assert oracle.xdrop_extend(np.array([0], np.uint8), np.array([0, 1], np.uint8), 2, -1, -1, 100) == (2, (1, 1))
+    # match 1, gap -1: A,C,G against A,G: 1 at (1,1), 0 at (2,1) and (1,2), then G = G:
+    # (3,2) = 1 on anti-diagonal 5 ties the best of anti-diagonal 2 and does not replace it
+    assert oracle.xdrop_extend(np.array([0, 1, 2], np.uint8), np.array([0, 2], np.uint8), 1, -1, -1, 100) == (1, (1, 1))
+
+
+def test_xdrop_empty_and_one_sided():
+    z = np.zeros(0, np.uint8)
+    assert oracle.xdrop_extend(z, z) == (0, (0, 0))
+    assert oracle.xdrop_extend(np.array([1, 2, 3], np.uint8), z) == (0, (0, 0))
+    assert oracle.xdrop_extend(z, np.array([1], np.uint8)) == (0, (0, 0))
+    assert oracle.xdrop_extend(np.array([2], np.uint8), np.array([2], np.uint8)) == (1, (1, 1))
+
+
+def _r_as_dict(R):
+    return {(i, int(R.col[e])): int(R.val[e]) for i in range(R.nrows) for e in range(R.rowptr[i], R.rowptr[i + 1])}
+
+
+@pytest.mark.parametrize("seed", [61, 66])
+def test_r_from_alignment_equals_truth_on_error_free_reads(seed):
+    """Error-free reads of a genome whose canonical 17-mers are all distinct:
+    every seed extends over exactly the true overlap (the reads end where it
+    does), so each pair's score is its overlap length and R from the
+    alignment ends is the overlap graph from the true coordinates."""
+    rng = np.random.default_rng(seed)
+    g = synth.random_genome(rng, 80_000)
+    assert _canonical_kmers_unique(g)
+    reads = synth.sample_reads(rng, g, n_reads=120, length_uniform=(1500, 7000), error_rate=0.0)
+    A, _ = synth.kmer_matrix(reads, 17, 2, 1000, strand_bit=True)
+    C = oracle.overlap(A, 1)
+    T = synth.overlap_graph(reads.start, reads.end, reads.strand, min_overlap=100, policy="edges")
+    tval = np.where((T.val >> 2) == 0, 0, T.val)
+    R, score = oracle.r_from_alignment(C, reads.bases, reads.offsets, 17, xdrop=50, min_score=100)
+    assert R.nnz > 500 and np.count_nonzero(R.val == 0) > 10
+    assert np.array_equal(R.rowptr, T.rowptr) and np.array_equal(R.col, T.col) and np.array_equal(R.val, tval)
+    rows = np.repeat(np.arange(C.nrows), np.diff(C.rowptr))
+    lo = np.maximum(reads.start[rows], reads.start[C.col])
+    hi = np.minimum(reads.end[rows], reads.end[C.col])
+    off = rows != C.col
+    assert np.array_equal(score[off], (hi - lo)[off]) and np.all(score[~off] == 0)
+
+
+def test_r_from_alignment_four_overlap_categories_with_errors():
+    """The hand-built pairs of each category (Sec. IV-E), error-free and
+    then with one substitution every 40 bases in read j: the alignment
+    still spans the whole overlap, so the suffix and code are exact; the
+    score is the overlap length, less two per substitution inside it."""
+    rng = np.random.default_rng(63)
+    g = synth.random_genome(rng, 9000)
+    assert _canonical_kmers_unique(g)
+    rcv = synth.revcomp
+    cases = [
+        ("forward", g[0:3000], g[1000:5000], (2000 << 2) | 0b00, 2000),
+        ("reverse", g[1000:5000], g[0:3000], (1000 << 2) | 0b11, 2000),
+        ("inner", g[0:3000], rcv(g[1000:5000]), (2000 << 2) | 0b01, 2000),
+        ("outer", g[1000:5000], rcv(g[0:3000]), (1000 << 2) | 0b10, 2000),
+        ("inner, i reverse complemented", rcv(g[1000:5000]), g[0:3000], (1000 << 2) | 0b01, 2000),
+        ("contained", g[0:5000], g[1000:3000], 0, 2000),
+        ("contained, reverse complement", rcv(g[1000:3000]), g[0:5000], 0, 2000),
+    ]
+    for name, si, sj, want, ov in cases:
+        for noisy in (False, True):
+            sj2 = sj.copy()
+            if noisy:          # substitutions away from both ends of j
+                pos = np.arange(20, sj2.size - 20, 40)
+                sj2[pos] = (sj2[pos] + 1) % 4
+            reads = _reads_from([si, sj2])
+            A, _ = synth.kmer_matrix(reads, 17, 2, 10, strand_bit=True)
+            C = oracle.overlap(A, 1)
+            R, score = oracle.r_from_alignment(C, reads.bases, reads.offsets, 17, xdrop=30, min_score=100)
+            assert list(R.rowptr) == [0, 1, 2], (name, noisy)
+            assert int(R.col[0]) == 1 and int(R.val[0]) == want, (name, noisy, int(R.val[0]) >> 2, int(R.val[0]) & 3)
+            assert score[0] == 0 and score[3] == 0          # the diagonal
+            if not noisy:
+                assert score[1:3].tolist() == [ov, ov], name
+            else:
+                # the substitutions of j that fall inside the overlap
+                assert score[1] == score[2] and ov - 2 * 60 < score[1] < ov - 2 * 40, (name, score)
+
+
+def test_r_from_alignment_keeps_a_score_of_exactly_min_score():
+    rng = np.random.default_rng(63)
+    g = synth.random_genome(rng, 9000)
+    reads = _reads_from([g[0:3000], g[1000:5000]])
+    A, _ = synth.kmer_matrix(reads, 17, 2, 10, strand_bit=True)
+    C = oracle.overlap(A, 1)
+    assert oracle.r_from_alignment(C, reads.bases, reads.offsets, 17, min_score=2000)[0].nnz == 2
+    assert oracle.r_from_alignment(C, reads.bases, reads.offsets, 17, min_score=2001)[0].nnz == 0
+
+
+def test_r_from_alignment_matches_full_tables_on_short_noisy_pairs():
+    """Short pairs (under 400 bases, so no anti-diagonal reaches the band
+    limit) with 10% substitutions and indels, X unbounded: each pair's score
+    and R entry follow from the whole extension tables of the two sides of
+    its seed, built here from the read strings (read j reverse complemented
+    when the strands differ)."""
+    rng = np.random.default_rng(64)
+    checked = 0
+    for t in range(12):
+        g = synth.random_genome(rng, 2000)
+        s0 = int(rng.integers(0, 400))
+        si = g[s0:s0 + int(rng.integers(150, 380))]
+        s1 = s0 + int(rng.integers(-100, 150))
+        s1 = max(0, s1)
+        sj = g[s1:s1 + int(rng.integers(150, 380))].copy()
+        flip = rng.random(sj.size) < 0.05
+        sj[flip] = (sj[flip] + 1) % 4
+        keep = rng.random(sj.size) > 0.03
+        sj = sj[keep]
+        rc = bool(t % 2)
+        if rc:
+            sj = synth.revcomp(sj)
+        reads = _reads_from([si, sj])
+        A, _ = synth.kmer_matrix(reads, 17, 2, 10, strand_bit=True)
+        C = oracle.overlap(A, 1)
+        R, score = oracle.r_from_alignment(C, reads.bases, reads.offsets, 17, 2, -3, -2, 10 ** 6, min_score=-10 ** 9)
+        Rd = _r_as_dict(R)
+        for i in range(2):
+            for e in range(C.rowptr[i], C.rowptr[i + 1]):
+                j = int(C.col[e])
+                if j == i:
+                    continue
+                x, y = reads.read(i), reads.read(j)
+                pa, pb = int(C.seed[e][0]), int(C.seed[e][1])
+                flipped = (pa & 1) != (pb & 1)
+                yo = synth.revcomp(y) if flipped else y
+                pi = pa >> 1
+                q = (len(y) - 17 - (pb >> 1)) if flipped else (pb >> 1)
+                sr, (ear, ebr) = _full_dp_best(list(x[pi + 17:]), list(yo[q + 17:]), 2, -3, -2)
+                sl, (eal, ebl) = _full_dp_best(list(x[:pi][::-1]), list(yo[:q][::-1]), 2, -3, -2)
+                assert score[e] == sl + 2 * 17 + sr
+                bi, bj = pi - eal, q - ebl                       # alignment starts
+                ri, rj = len(x) - (pi + 17 + ear), len(y) - (q + 17 + ebr)   # unaligned right ends
+                if (bi <= bj and ri <= rj) or (bj <= bi and rj <= ri):
+                    want = 0
+                elif bi > bj:        # forward (same strand) or inner
+                    want = ((rj - ri) << 2) | (1 if flipped else 0)
+                else:                # reverse or outer
+                    want = ((bj - bi) << 2) | (2 if flipped else 3)
+                assert Rd[(i, j)] == want, (t, i, j)
+                checked += 1
+    assert checked >= 16
+
+
+def test_r_from_alignment_on_noisy_reads_is_symmetric_and_finds_true_overlaps():
+    """15% errors: C_ji holds C_ij's seeds swapped, and the two extensions
+    of the swapped pair are the same tables transposed (and complemented
+    when the strands differ), so the scores agree both ways.  Scores where
+    unrelated bases lose on average (match 1, mismatch -1, gap -2): every
+    pair scoring at least 100 is a true overlap."""
+    w = synth.make_workload("tiny", strand_bit=True)
+    C = oracle.overlap(w.A, w.min_shared)
+    R, score = oracle.r_from_alignment(C, w.reads.bases, w.reads.offsets, w.k, 1, -1, -2, 25, min_score=100)
+    sc = {}
+    for i in range(C.nrows):
+        for e in range(C.rowptr[i], C.rowptr[i + 1]):
+            sc[(i, int(C.col[e]))] = int(score[e])
+    assert all(sc[(j, i)] == s for (i, j), s in sc.items())
+    st, en = w.reads.start, w.reads.end
+    Rd = _r_as_dict(R)
+    assert len(Rd) > 2000
+    true = sum(min(en[i], en[j]) - max(st[i], st[j]) > 0 for (i, j) in Rd)
+    assert true == len(Rd)
+    assert all((j, i) in Rd for (i, j) in Rd)
+
+
+def test_r_from_alignment_rejects_bad_arguments():
+    rng = np.random.default_rng(63)
+    g = synth.random_genome(rng, 9000)
+    reads = _reads_from([g[0:3000], g[1000:5000]])
+    A, _ = synth.kmer_matrix(reads, 17, 2, 10, strand_bit=True)
+    C = oracle.overlap(A, 1)
+    ok = dict(match=1, mismatch=-1, gap=-2, xdrop=25)
+    oracle.r_from_alignment(C, reads.bases, reads.offsets, 17, **ok)
+    for bad in (dict(match=0), dict(match=8), dict(mismatch=1), dict(mismatch=-1025), dict(gap=0),
+                dict(gap=-1025), dict(xdrop=-1), dict(xdrop=(1 << 20) + 1)):
+        with pytest.raises(ValueError):
+            oracle.r_from_alignment(C, reads.bases, reads.offsets, 17, **{**ok, **bad})
+    b = reads.bases.copy()
+    b[7] = 4                                           # a base outside 0..3
+    with pytest.raises(ValueError):
+        oracle.r_from_alignment(C, b, reads.offsets, 17, **ok)
+    with pytest.raises(ValueError):                    # offsets that do not end at the bases' end
+        oracle.r_from_alignment(C, reads.bases[:-1], reads.offsets, 17, **ok)
+    C2 = types.SimpleNamespace(**vars(C))
+    C2.seed = C.seed.copy()
+    C2.seed[1, 1] = (3990 << 1)                        # a seed past the end of read 1 (4000 bases)
+    with pytest.raises(ValueError):
+        oracle.r_from_alignment(C2, reads.bases, reads.offsets, 17, **ok)

@@ -86,6 +86,25 @@ MUTANTS = [
     # one-pass marks used for sampled checks
     ("marks-compare-strict", "(int64_t)(nij >> 2) <= mij);", "(int64_t)(nij >> 2) < mij);"),
     ("marks-row-max-unset", "if (vi != 0) vi += fuzz;", "if (vi != 0) vi += fuzz + 1;"),
+    # X-drop extension and R from the alignment
+    ("xd-drop-strict", "if (v != ORACLE_XD_DEAD && v < best - X) v = ORACLE_XD_DEAD;",
+     "if (v != ORACLE_XD_DEAD && v <= best - X) v = ORACLE_XD_DEAD;"),
+    ("xd-last-max-in-diagonal", "if (v > dbest) { dbest = v; di = i; }", "if (v >= dbest) { dbest = v; di = i; }"),
+    ("xd-later-diagonal-ties", "if (dbest != ORACLE_XD_DEAD && dbest > best)", "if (dbest != ORACLE_XD_DEAD && dbest >= best)"),
+    ("xd-match-inverted", "(a[i - 1] == b[j - 1] ? mat : mis)", "(a[i - 1] != b[j - 1] ? mat : mis)"),
+    ("xd-one-gap-direction", "if (j >= 1 && dg[1][i] != ORACLE_XD_DEAD", "if (0 && j >= 1 && dg[1][i] != ORACLE_XD_DEAD"),
+    ("xd-one-dead-diagonal-stops", "if (lo[0] > hi[0] && lo[1] > hi[1]) {", "if (lo[1] > hi[1]) {"),
+    ("xd-band-off-by-one", "if (to - from + 1 > ORACLE_XD_BAND) break;", "if (to - from + 1 >= ORACLE_XD_BAND) break;"),
+    ("al-rc-position-unflipped", "q = rc ? lj - k - (b >> 1) : (b >> 1);", "q = (b >> 1);"),
+    ("al-j-not-complemented", "return rc ? (uint8_t)(3 - s[L - 1 - x]) : s[x];", "return rc ? s[L - 1 - x] : s[x];"),
+    ("al-left-not-reversed", "for (int64_t x = 0; x < ml; ++x) al[x] = si[pi - 1 - x];",
+     "for (int64_t x = 0; x < ml; ++x) al[x] = si[x];"),
+    ("al-score-without-seed", "int64_t score = sl + (int64_t)k * mat + sr;", "int64_t score = sl + sr;"),
+    ("al-min-score-strict", "if (score < min_score) continue;", "if (score <= min_score) continue;"),
+    ("al-contained-one-way", "if ((bj >= bi && rj >= ri) || (bi >= bj && ri >= rj)) {", "if (bj >= bi && rj >= ri) {"),
+    ("al-suffix-past", "val = (int32_t)(((rj - ri) << 2) | (rc ? 1 : 0));", "val = (int32_t)((rj << 2) | (rc ? 1 : 0));"),
+    ("al-ends-swapped", "int64_t bi = pi - eal, ei = pi + k + ear, bj = q - ebl, ej = q + k + ebr;",
+     "int64_t bi = pi - ebl, ei = pi + k + ear, bj = q - eal, ej = q + k + ebr;"),
 ]
 
 
