@@ -14,6 +14,10 @@
  *                              set of launches.
  *   dibella_r_from_seeds       the overlap graph R from the seeds stored in C
  *                              (Sec. IV-D, IV-E).
+ *   dibella_r_from_alignment   R from a seed-and-extend alignment of every
+ *                              pair of C and the pruning of low scores
+ *                              (Sec. IV-D: Apply(C, Alignment()), Prune;
+ *                              Sec. IV-E for R's values).
  *   dibella_overlap_graph_blocked
  *                              R from A with C formed one block of reads at a
  *                              time (Sec. VIII, future work).
@@ -67,6 +71,12 @@ extern "C" {
 #define DIBELLA_TR_USE_GRAPH   0x8u  /* run the passes as captured HIP graphs */
 /* Flag of dibella_kmer_matrix. */
 #define DIBELLA_KMER_STRAND    0x1u  /* values (position << 1) | strand */
+/* Flags of dibella_r_from_alignment: lanes per extension (0 = chosen from
+ * the scores and X). */
+#define DIBELLA_ALIGN_GROUP_16   0x1u
+#define DIBELLA_ALIGN_GROUP_32   0x2u
+#define DIBELLA_ALIGN_GROUP_64   0x3u
+#define DIBELLA_ALIGN_GROUP_MASK 0x3u
 /* Bits 16..31: stop after this many passes (0 = run to the fixed point). */
 #define DIBELLA_TR_MAX_PASSES(n) (((uint32_t)(n) & 0xFFFFu) << 16)
 
@@ -174,7 +184,8 @@ int dibella_transitive_reduce_batched(const dibella_csr* R, int32_t nsets, const
  * (Sec. IV-E: the reduction's overlap suffix and orientation are derived in
  * place from the coordinates stored with each read pair; Sec. IV-D: C keeps
  * two k-mer positions per pair).  It stands between the two products where
- * the paper aligns and prunes (that alignment is not part of this library).
+ * the paper aligns and prunes, without aligning (dibella_r_from_alignment
+ * aligns).
  *
  * C: the output of dibella_overlap (borrowed, never written; col, count and
  * seed are read) for an A whose
@@ -209,6 +220,55 @@ int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, 
                          int32_t min_overlap, int32_t max_drift, int32_t min_density,
                          dibella_csr_out* R, dibella_alloc_fn alloc, dibella_free_fn free_fn,
                          void* ctx, void* hip_stream);
+
+/*
+ * dibella_r_from_alignment -- R from a seed-and-extend alignment of every
+ * pair of C (Sec. IV-D: the alignment is an element-wise operation on C
+ * that flags each entry by its score, and the entries scoring below the
+ * threshold are pruned; Sec. IV-E: the suffix and orientation of each kept
+ * pair come from its alignment coordinates).
+ *
+ * C: the output of dibella_overlap (square, borrowed; col and seed are
+ * read) for an A whose values are (position << 1) | strand.  bases: device
+ * uint8[nbases], 2-bit codes A0 C1 G2 T3, the reads back to back; offsets:
+ * device int64[n + 1], read i = bases[offsets[i], offsets[i + 1]),
+ * offsets[0] = 0, offsets[n] = nbases, non-decreasing, every read shorter
+ * than 2^28 bases.  For every off-diagonal entry C_ij the first seed (p_i,
+ * p_j) is extended both ways by X-drop extension (Zhang et al., 2000) of
+ * read i against read j, or its reverse complement j' when the seed's
+ * strands differ (the k-mer then sits at q = L_j - k - p_j in j', else
+ * q = p_j): to the right from p_i + k and q + k, to the left from p_i and q
+ * backwards.  Linear scores: match in [1, 7], mismatch in [-1024, 0], gap in
+ * [-1024, -1] per base against a gap; cells of the extension table are
+ * taken anti-diagonal by anti-diagonal, only those with a live predecessor
+ * on the two previous anti-diagonals, and a cell scoring below the best of
+ * the earlier anti-diagonals minus xdrop (in [0, 2^20]) is dead.  An
+ * extension stops after two anti-diagonals without a live cell, at the
+ * sequence ends, or before an anti-diagonal that would consider more than
+ * 256 cells; it gives its best score and the first cell reaching it
+ * (anti-diagonal order, then position in read i).  The pair's score is
+ * left + k * match + right; entries below min_score are dropped.  With the
+ * alignment spanning [b_i, e_i) of i and [b_j, e_j) of j' and r = L - e the
+ * unaligned right ends: one read's unaligned ends both within the other's
+ * (b_j >= b_i and r_j >= r_i, or b_i >= b_j and r_i >= r_j): contained,
+ * value 0; else read i first (b_i > b_j): suffix r_j - r_i, code (0, rc);
+ * else suffix b_j - b_i, code (1, 1 - rc); val = (suffix << 2) | code.
+ * R: n x n in dibella_transitive_reduce's layout, rows sorted, allocated
+ * through alloc.  score (may be NULL): *score receives device int32[nnz(C)],
+ * allocated through alloc, the score of every entry of C (0 on the
+ * diagonal; NULL when C is empty).  flags: DIBELLA_ALIGN_GROUP_* or 0.
+ * Errors: EINVAL for a malformed C (row pointers, column range or order), a
+ * non-square C, a missing seed or one outside its read, malformed offsets, a
+ * base outside 0..3, k outside [1, 32], scores or xdrop outside their
+ * ranges, unknown flags; EOVERFLOW if nrows >= 2^31 or nnz >= 2^40.
+ * Host synchronisation: two stream syncs (the checks of the reads and of C;
+ * the size of R).
+ */
+int dibella_r_from_alignment(const dibella_overlap_out* C, const uint8_t* bases, int64_t nbases,
+                             const int64_t* offsets, int32_t k, int32_t match, int32_t mismatch,
+                             int32_t gap, int32_t xdrop, int32_t min_score, uint32_t flags,
+                             dibella_csr_out* R, int32_t** score, dibella_alloc_fn alloc,
+                             dibella_free_fn free_fn, void* ctx, void* hip_stream);
 
 /*
  * dibella_overlap_graph_blocked -- the overlap graph R of A with C formed
@@ -366,6 +426,7 @@ int dibella_last_stats(dibella_stats* out);
  *  16 kmer_sort     A from the reads: the radix sorts (by k-mer, by read)
  *  17 kmer_runs     A from the reads: frequencies, columns, kept entries
  *  18 kmer_rows     A from the reads: row pointers, columns and values
+ *  19 align         R from the alignment: the X-drop extensions of all pairs
  * Passes run as captured graphs are not timed.  Enabling clears the
  * accumulators; collect waits for the recorded events, returns the summed
  * milliseconds and number of records per label, and clears them. */

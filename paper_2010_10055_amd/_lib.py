@@ -27,13 +27,13 @@ TR_USE_GRAPH = 0x8
 
 EXPORTS = ["dibella_overlap", "dibella_transitive_reduce", "dibella_overlap_batched",
            "dibella_transitive_reduce_batched", "dibella_r_from_seeds", "dibella_overlap_graph_blocked",
-           "dibella_transitive_reduce_noalloc", "dibella_kmer_matrix",
+           "dibella_transitive_reduce_noalloc", "dibella_kmer_matrix", "dibella_r_from_alignment",
            "dibella_last_error", "dibella_get_tuning",
            "dibella_set_tuning", "dibella_last_stats", "dibella_timing_enable",
            "dibella_timing_select", "dibella_timing_collect"]
 PHASES = ["keys", "part_count", "part_scatter", "bucket_sort", "part2_count", "part2_scatter", "segments", "sym_bits",
           "sym_hash", "numeric", "esc", "tr_mark", "tr_compact", "numeric_phase", "r_from_seeds", "kmer_windows",
-          "kmer_sort", "kmer_runs", "kmer_rows"]
+          "kmer_sort", "kmer_runs", "kmer_rows", "align"]
 NUM_PHASES = 20
 
 
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dibella_overlap_graph_blocked.argtypes = [P, i32, P, i32, i32, i32, i32, ctypes.c_int64, P, P, ALLOC_FN,
                                                   FREE_FN, P, P]
     lib.dibella_transitive_reduce_noalloc.argtypes = [P, i32, u32, P, P, P, ctypes.c_int64, P, P, P]
+    lib.dibella_r_from_alignment.argtypes = [P, P, ctypes.c_int64, P, i32, i32, i32, i32, i32, i32, u32, P, P,
+                                             ALLOC_FN, FREE_FN, P, P]
     lib.dibella_kmer_matrix.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, i32, i32, i32, u32, P, P, ALLOC_FN,
                                         FREE_FN, P, P]
     for f in EXPORTS:
@@ -417,6 +419,53 @@ def kmer_matrix(bases: torch.Tensor, offsets: torch.Tensor, k: int, lo: int, hi:
     A = CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
                    call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
     return A, call.mem.take(codes.value, torch.int64, o.ncols)
+
+
+ALIGN_GROUPS = {None: 0, 16: 0x1, 32: 0x2, 64: 0x3}
+
+
+def r_from_alignment(C: OverlapCSR, bases: torch.Tensor, offsets: torch.Tensor, k: int, match: int = 1,
+                     mismatch: int = -1, gap: int = -2, xdrop: int = 25, min_score: int = 0,
+                     group: int = None, with_score: bool = False):
+    """Overlap graph R from a seed-and-extend alignment of every pair of C
+    (A's values being (position << 1) | strand): X-drop extension both ways
+    from the first seed, read j reverse complemented when the strands
+    differ; pairs scoring below min_score dropped; the suffix and
+    orientation code from the alignment ends, contained pairs kept with
+    value 0.  bases uint8 (A0 C1 G2 T3, reads back to back), offsets
+    int64[n + 1].  group: lanes per extension (16, 32, 64; None = chosen
+    from the scores).  Returns R, or (R, score) with the int32 score of
+    every entry of C (0 on the diagonal)."""
+    dev = C.rowptr.device
+    if bases.dtype != torch.uint8 or not bases.is_cuda or not bases.is_contiguous():
+        raise TypeError("bases must be a contiguous uint8 device tensor")
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise TypeError("offsets must be a contiguous int64 device tensor")
+    if offsets.numel() != C.nrows + 1:
+        raise ValueError("offsets must hold one entry per row of C plus one")
+    if group not in ALIGN_GROUPS:
+        raise ValueError("group must be 16, 32, 64 or None")
+    call = _call_for(dev)
+    for name, t, dt in (("rowptr", C.rowptr, torch.int64), ("col", C.col, torch.int32),
+                        ("seed", C.seed, torch.int32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"C.{name} must be a contiguous {dt} device tensor")
+    c = _OverlapOut(C.nrows, C.ncols, C.nnz, C.rowptr.data_ptr(), C.col.data_ptr() if C.nnz else None,
+                    C.count.data_ptr() if C.nnz else None, C.seed.data_ptr() if C.nnz else None)
+    o = _CSROut()
+    sc = ctypes.c_void_p()
+    with torch.cuda.device(dev):
+        st = lib().dibella_r_from_alignment(ctypes.byref(c), bases.data_ptr() if bases.numel() else None,
+                                            bases.numel(), offsets.data_ptr(), int(k), int(match), int(mismatch),
+                                            int(gap), int(xdrop), int(min_score), ALIGN_GROUPS[group],
+                                            ctypes.byref(o), ctypes.byref(sc) if with_score else None,
+                                            call.alloc_cb, call.free_cb, None, _stream_handle(dev))
+    _check(st)
+    R = CSRTensors(o.nrows, o.ncols, call.mem.take(o.rowptr, torch.int64, o.nrows + 1),
+                   call.mem.take(o.col, torch.int32, o.nnz), call.mem.take(o.val, torch.int32, o.nnz))
+    if with_score:
+        return R, call.mem.take(sc.value, torch.int32, C.nnz)
+    return R
 
 
 def last_stats() -> dict:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdibella.so")
-SOURCES = ["runtime.hip", "overlap.hip", "tr.hip", "rseeds.hip", "noalloc.hip", "kmer.hip", "api.hip"]
+SOURCES = ["runtime.hip", "overlap.hip", "tr.hip", "rseeds.hip", "noalloc.hip", "kmer.hip", "align.hip", "api.hip"]
 CALIB_SOURCE = "calib.hip"
 CALIB_OUT = os.path.join(HERE, "libdibella_calib.so")
 ARCH = os.environ.get("DIBELLA_OFFLOAD_ARCH", "gfx950")

@@ -147,6 +147,30 @@ int dibella_kmer_matrix(const uint8_t* bases, const int64_t* offsets, int64_t nr
     return status;
 }
 
+int dibella_r_from_alignment(const dibella_overlap_out* C, const uint8_t* bases, int64_t nbases,
+                             const int64_t* offsets, int32_t k, int32_t match, int32_t mismatch, int32_t gap,
+                             int32_t xdrop, int32_t min_score, uint32_t flags, dibella_csr_out* R, int32_t** score,
+                             dibella_alloc_fn alloc, dibella_free_fn free_fn, void* ctx, void* hip_stream) {
+    reset_stats();
+    if (!C || !R || (alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("dibella_r_from_alignment: bad arguments");
+        return DIBELLA_EINVAL;
+    }
+    int status;
+    {
+        Arena ar(alloc, free_fn, ctx, static_cast<hipStream_t>(hip_stream));
+        status = guarded(ar, [&] {
+            return r_from_alignment_run(C, bases, nbases, offsets, k, match, mismatch, gap, xdrop, min_score, flags,
+                                        R, score, ar);
+        });
+    }
+    if (status != DIBELLA_OK) {
+        std::memset(R, 0, sizeof(*R));
+        if (score) *score = nullptr;
+    }
+    return status;
+}
+
 const char* dibella_last_error(void) { return error_slot().c_str(); }
 
 int dibella_get_tuning(dibella_tuning* out) {

@@ -146,6 +146,14 @@ int overlap_run(const dibella_csr* A, int nsets, const int32_t* min_shared, dibe
 int r_from_seeds_run(const dibella_overlap_out* C, int64_t row0, const int32_t* read_len, int32_t k,
                      int32_t min_overlap, int32_t max_drift, int32_t min_density, dibella_csr_out* R, Arena& ar,
                      Arena& out, bool out_as_work);
+// R's entries of C kept in tmp (tmp[e] >= 0 is the value, -1 dropped), rows
+// written from R's row pointers rrp (one wave per row, order kept).
+int write_marked_rows(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* tmp, const int64_t* rrp,
+                      int32_t* rcol, int32_t* rval, hipStream_t st);
+// R from the alignment of C's pairs (dibella_r_from_alignment).
+int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int64_t nbases, const int64_t* offsets,
+                         int32_t k, int32_t mat, int32_t mis, int32_t gap, int32_t X, int32_t min_score,
+                         uint32_t flags, dibella_csr_out* R, int32_t** score_out, Arena& ar);
 // A from the reads (dibella_kmer_matrix).
 int kmer_matrix_run(const uint8_t* bases, const int64_t* offsets, int64_t n, int64_t nbases, int32_t k, int32_t lo,
                     int32_t hi, uint32_t flags, dibella_csr_out* A, uint64_t** codes, int64_t* m, Arena& ar);
@@ -176,7 +184,7 @@ int side_streams(SideStreams** out);
 enum Phase {
     kPhKeys = 0, kPhPartCount, kPhPartScatter, kPhBucketSort, kPhPart2Count, kPhPart2Scatter, kPhSegments,
     kPhSymBits, kPhSymHash, kPhNumeric, kPhEsc, kPhTrMark, kPhTrCompact, kPhNumericAll, kPhRFromSeeds,
-    kPhKmerWindows, kPhKmerSort, kPhKmerRuns, kPhKmerRows
+    kPhKmerWindows, kPhKmerSort, kPhKmerRuns, kPhKmerRows, kPhAlign
 };
 bool timing_on();
 // While one lives on this host thread, no timing events are created or

@@ -145,6 +145,15 @@ __global__ __launch_bounds__(WPB* kWave) void k_rs_write(int64_t n, const int64_
     }
 }
 
+int write_marked_rows(int64_t n, const int64_t* rp, const int32_t* col, const int32_t* tmp, const int64_t* rrp,
+                      int32_t* rcol, int32_t* rval, hipStream_t st) {
+    constexpr int WPB = 4;
+    hipLaunchKernelGGL(k_rs_write<WPB>, dim3(grid_for(n, WPB, 1 << 16)), dim3(WPB * kWave), 0, st, n, rp, col, tmp,
+                       rrp, rcol, rval);
+    DB_HIP(hipGetLastError());
+    return DIBELLA_OK;
+}
+
 static const char* describe_rs_bad(int32_t bad) {
     if (bad & kRsBadRowptr) return "row pointers of C are not a valid CSR row pointer array";
     if (bad & kRsBadCol) return "a column index of C is outside [0, ncols)";
@@ -218,9 +227,7 @@ int r_from_seeds_run(const dibella_overlap_out* C, int64_t row0, const int32_t* 
     DB_TRY(out_as_work ? out.work_n(rnnz, &rval) : out.output_n(rnnz, &rval));
     if (n > 0 && rnnz > 0) {
         DB_TRY(timing_begin(kPhRFromSeeds, st, &tok));
-        hipLaunchKernelGGL(k_rs_write<WPB>, dim3(grid_for(n, WPB, 1 << 16)), dim3(WPB * kWave), 0, st, n, C->rowptr,
-                           C->col, tmp, rrp, rcol, rval);
-        DB_HIP(hipGetLastError());
+        DB_TRY(write_marked_rows(n, C->rowptr, C->col, tmp, rrp, rcol, rval, st));
         DB_TRY(timing_end(tok, st));
     }
     DB_TRY(stage_done(st));

@@ -1,0 +1,203 @@
+"""GPU parity of R from the alignment (dibella_r_from_alignment: X-drop
+extension of both sides of every pair's first seed, pruning by score, R's
+values from the alignment ends) against the oracle, bit for bit, scores
+included: the tiny and batch workloads under several scoring schemes and
+all three group widths, hand-made read sets (bands that reach the 256-cell
+limit, seeds at read ends, reads of exactly k bases, pairs without
+overlap), rows sampled from the mid and large workloads, and argument
+errors."""
+import types
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_10055_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def db():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_10055_amd as pkg
+    return pkg
+
+
+def _c_np(C):
+    return types.SimpleNamespace(nrows=C.nrows, ncols=C.ncols, rowptr=C.rowptr.cpu().numpy(),
+                                 col=C.col.cpu().numpy(), count=C.count.cpu().numpy(),
+                                 seed=C.seed.cpu().numpy().reshape(-1, 4))
+
+
+def _dev(bases, offsets):
+    return (torch.as_tensor(np.ascontiguousarray(bases, dtype=np.uint8), device="cuda:0"),
+            torch.as_tensor(np.ascontiguousarray(offsets, dtype=np.int64), device="cuda:0"))
+
+
+def _c_of(db, reads, lo=2, hi=8, min_shared=1):
+    A, _ = synth.kmer_matrix(reads, 17, lo, hi, strand_bit=True)
+    return db.overlap(db.CSRTensors.from_numpy(A, "cuda:0"), min_shared)
+
+
+def _check(db, C, bases, offsets, k, sc, group, min_score):
+    mat, mis, gap, X = sc
+    b, o = _dev(bases, offsets)
+    R, score = db.r_from_alignment(C, b, o, k, mat, mis, gap, X, min_score, group=group, with_score=True)
+    ref, ref_score = oracle.r_from_alignment(_c_np(C), bases, offsets, k, mat, mis, gap, X, min_score)
+    torch.cuda.synchronize()
+    assert np.array_equal(score.cpu().numpy(), ref_score)
+    assert R.nnz == ref.nnz
+    assert np.array_equal(R.rowptr.cpu().numpy(), ref.rowptr)
+    assert np.array_equal(R.col.cpu().numpy(), ref.col)
+    assert np.array_equal(R.val.cpu().numpy(), ref.val)
+    return R, ref_score
+
+
+@pytest.fixture(scope="module")
+def tiny(db):
+    w = synth.make_workload("tiny", strand_bit=True)
+    return w, db.overlap(db.CSRTensors.from_numpy(w.A, "cuda:0"), w.min_shared)
+
+
+@pytest.mark.parametrize("sc,group,min_score", [
+    ((1, -1, -2, 25), None, 100), ((1, -1, -2, 25), 16, 0), ((1, -1, -2, 25), 32, 100), ((1, -1, -2, 25), 64, 500),
+    ((2, -3, -3, 25), 16, 200), ((1, -1, -2, 50), 32, 100), ((1, -1, -1, 25), 64, 0), ((1, -1, -1, 25), 16, 0),
+    ((1, -1, -2, 0), 16, 0), ((3, -2, -5, 40), 32, 300), ((1, 0, -1, 10), 16, 0),
+])
+def test_alignment_tiny_matches_oracle(db, tiny, sc, group, min_score):
+    w, C = tiny
+    print(f"tiny: scores {sc} group {group} min_score {min_score} nnz(C) {C.nnz}", flush=True)
+    R, score = _check(db, C, w.reads.bases, w.reads.offsets, w.k, sc, group, min_score)
+    assert R.nnz > 0
+
+
+def test_alignment_batchset_matches_oracle(db):
+    w = synth.make_workload("batchset", seed=4007, strand_bit=True)
+    C = db.overlap(db.CSRTensors.from_numpy(w.A, "cuda:0"), w.min_shared)
+    print(f"batchset: reads {w.reads.n} nnz(C) {C.nnz}", flush=True)
+    _check(db, C, w.reads.bases, w.reads.offsets, w.k, (1, -1, -2, 25), None, 100)
+
+
+def _reads(seqs):
+    lens = np.array([s.size for s in seqs], np.int64)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    z = np.zeros(len(seqs), np.int64)
+    return synth.Reads(np.concatenate(seqs).astype(np.uint8) if seqs else np.zeros(0, np.uint8), offs, z, z,
+                       z.astype(np.int8))
+
+
+def test_alignment_hand_made_reads(db):
+    """Identical and nearly identical long reads with X unbounded (every
+    anti-diagonal widens until the 256-cell limit ends the extension),
+    seeds at the very ends of reads, reads of exactly k bases, both strands,
+    a read without any shared k-mer, and the four overlap categories."""
+    rng = np.random.default_rng(77)
+    g = synth.random_genome(rng, 12000)
+    rcv = synth.revcomp
+    noisy = g[2000:6000].copy()
+    noisy[::37] = (noisy[::37] + 1) % 4
+    seqs = [g[0:3000], g[1000:5000], rcv(g[2000:7000]), noisy, g[0:17], g[2983:3000], rcv(g[4000:4017]),
+            g[0:3000].copy(), rng.integers(0, 4, size=900, dtype=np.uint8), g[5000:9000], rcv(g[8000:12000])]
+    reads = _reads(seqs)
+    C = _c_of(db, reads, 1, 1000)
+    print(f"hand-made: reads {len(seqs)} nnz(C) {C.nnz}", flush=True)
+    for sc in ((1, -1, -2, 25), (1, -1, -2, 10 ** 6), (1, -1, -1, 10 ** 6), (2, -1, -1, 3)):
+        for group in (16, 32, 64):
+            _check(db, C, reads.bases, reads.offsets, 17, sc, group, 0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_alignment_short_noisy_reads(db, seed):
+    """Many short reads (40 to 400 bases, 10% errors) of a small genome,
+    small k: short extensions, empty sides, many pairs per row."""
+    rng = np.random.default_rng(800 + seed)
+    g = synth.random_genome(rng, 3000)
+    reads = synth.sample_reads(rng, g, n_reads=120, length_uniform=(40, 400), error_rate=0.1, min_len=40)
+    for k in (11, 17):
+        A, _ = synth.kmer_matrix(reads, k, 1, 50, strand_bit=True)
+        C = db.overlap(db.CSRTensors.from_numpy(A, "cuda:0"), 1)
+        print(f"short noisy: seed {seed} k {k} reads {reads.n} nnz(C) {C.nnz}", flush=True)
+        _check(db, C, reads.bases, reads.offsets, k, (1, -1, -2, 15), None, 20)
+        _check(db, C, reads.bases, reads.offsets, k, (2, -3, -3, 40), 64, 0)
+
+
+def test_alignment_empty_and_diagonal_only(db):
+    reads = _reads([np.zeros(0, np.uint8), np.array([0, 1, 2, 3, 0, 1], np.uint8)])
+    A = types.SimpleNamespace(nrows=2, ncols=1, rowptr=np.array([0, 0, 1], np.int64),
+                              col=np.array([0], np.int32), val=np.array([0], np.int32))
+    C = db.overlap(db.CSRTensors.from_numpy(A, "cuda:0"), 1)
+    assert C.nnz == 1                              # the diagonal of read 1
+    R, score = _check(db, C, reads.bases, reads.offsets, 3, (1, -1, -2, 25), None, 0)
+    assert R.nnz == 0 and score.tolist() == [0]
+    A0 = types.SimpleNamespace(nrows=0, ncols=0, rowptr=np.zeros(1, np.int64), col=np.zeros(0, np.int32),
+                               val=np.zeros(0, np.int32))
+    C0 = db.overlap(db.CSRTensors.from_numpy(A0, "cuda:0"), 1)
+    R0, s0 = db.r_from_alignment(C0, *_dev(np.zeros(0, np.uint8), np.zeros(1, np.int64)), 17, with_score=True)
+    assert R0.nrows == 0 and R0.nnz == 0 and s0.numel() == 0
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,rows", [("mid", 24), ("large", 12)])
+def test_alignment_sampled_rows_match_oracle(db, name, rows):
+    """At the mid and large sizes the oracle aligns a sample of rows of C
+    (the other rows left empty); the library aligns all of C, and its rows
+    and scores at the sampled rows must be the oracle's."""
+    w = synth.make_workload(name, device="cuda:0", strand_bit=True)
+    C = db.overlap(db.CSRTensors.from_numpy(w.A, "cuda:0"), w.min_shared)
+    b, o = _dev(w.reads.bases, w.reads.offsets)
+    print(f"{name}: reads {w.reads.n} nnz(C) {C.nnz}", flush=True)
+    R, score = db.r_from_alignment(C, b, o, w.k, 1, -1, -2, 25, 300, with_score=True)
+    torch.cuda.synchronize()
+    Cn = _c_np(C)
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(C.nrows, size=rows, replace=False))
+    lens = np.diff(Cn.rowptr)
+    sel_rp = np.zeros(C.nrows + 1, np.int64)
+    sel_rp[pick + 1] = lens[pick]
+    sel_rp = np.cumsum(sel_rp)
+    idx = np.concatenate([np.arange(Cn.rowptr[i], Cn.rowptr[i + 1]) for i in pick])
+    sub = types.SimpleNamespace(nrows=C.nrows, ncols=C.ncols, rowptr=sel_rp, col=Cn.col[idx],
+                                count=Cn.count[idx], seed=Cn.seed[idx])
+    print(f"{name}: oracle on {idx.size} entries of {rows} rows", flush=True)
+    ref, ref_score = oracle.r_from_alignment(sub, w.reads.bases, w.reads.offsets, w.k, 1, -1, -2, 25, 300)
+    assert np.array_equal(score.cpu().numpy()[idx], ref_score)
+    rp = R.rowptr.cpu().numpy()
+    rc, rv = R.col.cpu().numpy(), R.val.cpu().numpy()
+    for i in pick:
+        a, b2 = ref.rowptr[i], ref.rowptr[i + 1]
+        assert np.array_equal(rc[rp[i]:rp[i + 1]], ref.col[a:b2]), i
+        assert np.array_equal(rv[rp[i]:rp[i + 1]], ref.val[a:b2]), i
+
+
+def test_alignment_argument_errors(db, tiny):
+    w, C = tiny
+    b, o = _dev(w.reads.bases, w.reads.offsets)
+    for kw in (dict(match=0), dict(match=8), dict(mismatch=1), dict(gap=0), dict(gap=-1025), dict(xdrop=-1),
+               dict(xdrop=(1 << 20) + 1), dict(k=0), dict(k=33)):
+        args = dict(k=w.k, match=1, mismatch=-1, gap=-2, xdrop=25)
+        args.update(kw)
+        with pytest.raises(db.DibellaError):
+            db.r_from_alignment(C, b, o, **args)
+    bad = w.reads.bases.copy()
+    bad[12345] = 4
+    with pytest.raises(db.DibellaError):          # a base outside 0..3
+        db.r_from_alignment(C, *_dev(bad, w.reads.offsets), w.k)
+    off = w.reads.offsets.copy()
+    off[5], off[6] = off[6], off[5]
+    with pytest.raises(db.DibellaError):          # offsets that go back
+        db.r_from_alignment(C, *_dev(w.reads.bases, off), w.k)
+    with pytest.raises(db.DibellaError):          # offsets that do not end at the bases' end
+        db.r_from_alignment(C, *_dev(w.reads.bases[:-1], w.reads.offsets), w.k)
+    Cn = _c_np(C)
+    seed = Cn.seed.copy()
+    e = int(np.nonzero(Cn.col != np.repeat(np.arange(C.nrows), np.diff(Cn.rowptr)))[0][0])
+    seed[e, 1] = (1 << 30)                        # a seed outside its read
+    C2 = db.OverlapCSR(C.nrows, C.ncols, C.rowptr, C.col, C.count,
+                       torch.as_tensor(seed, device="cuda:0").contiguous())
+    with pytest.raises(db.DibellaError):
+        db.r_from_alignment(C2, b, o, w.k)
+    R = db.r_from_alignment(C, b, o, w.k, min_score=100)     # still works
+    assert R.nnz > 0
