@@ -213,10 +213,11 @@ def r_from_seeds(C, read_len, k: int, min_overlap: int, max_drift: int = -1, min
 def kmer_matrix(bases, offsets, k: int, lo: int, hi: int, strand_bit: bool = False):
     """A from the reads (k-mer counting, reliable k-mers in [lo, hi], the
     smallest position per read and k-mer; with strand_bit the values are
-    (position << 1) | strand).  Returns (A, codes): A with nrows, ncols,
-    rowptr, col, val; codes = the reliable canonical codes, ascending (A's
-    columns).  Raises ValueError on k outside [1, 31], bad bounds or a base
-    outside 0..3."""
+    (position << 1) | strand).  Columns are the reliable k-mers in the order
+    of their first occurrence (first read holding the k-mer, then its
+    smallest position there).  Returns (A, codes): A with nrows, ncols,
+    rowptr, col, val; codes[c] = the canonical code of column c.  Raises
+    ValueError on k outside [1, 31], bad bounds or a base outside 0..3."""
     lib = _load()
     b = np.ascontiguousarray(bases, dtype=np.uint8)
     off = np.ascontiguousarray(offsets, dtype=np.int64)

@@ -461,13 +461,17 @@ int oracle_r_from_seeds(int64_t n, const int64_t* c_rowptr, const int32_t* c_col
  * reverse complement is the smaller (the read holds the canonical k-mer
  * reverse complemented), else 0.  The frequency of a canonical k-mer is the
  * number of windows of all reads that have it (repeats inside a read
- * count); it is reliable when lo <= frequency <= hi.  The reliable k-mers,
- * in increasing code order, are A's columns.  A_ic = the smallest position
- * of k-mer c in read i, or (position << 1) | strand (the strand at that
+ * count); it is reliable when lo <= frequency <= hi.  The reliable k-mers
+ * are A's columns in the order of their first occurrence in the reads: by
+ * the first read holding the k-mer, then by the k-mer's smallest position
+ * in that read (the paper fixes no column order; this one makes the k-mers
+ * one read holds consecutive columns).  A_ic = the smallest position of
+ * k-mer c in read i, or (position << 1) | strand (the strand at that
  * position) when strand_bit is set.
  * Outputs: rowptr[n+1], *out_col, *out_val (nnz each), *out_codes (m
- * reliable codes, ascending), *out_m, *out_nnz.  Returns 0, -1 for k outside
- * [1, 31], lo < 1, hi < lo or a base outside 0..3. */
+ * reliable codes, codes[c] the k-mer of column c), *out_m, *out_nnz.
+ * Returns 0, -1 for k outside [1, 31], lo < 1, hi < lo or a base outside
+ * 0..3. */
 typedef struct {
     uint64_t code;
     int64_t read;
@@ -488,6 +492,20 @@ typedef struct {
     int64_t col;
     int32_t val;
 } oracle_entry;
+
+/* a reliable k-mer: its windows win[a, b) (sorted), first occurrence first */
+typedef struct {
+    int64_t a, b;
+} oracle_run;
+
+static const oracle_window* g_runs_win;   /* the windows the runs index (qsort has no context) */
+
+static int cmp_run_first(const void* x, const void* y) {
+    const oracle_window* p = &g_runs_win[((const oracle_run*)x)->a];
+    const oracle_window* q = &g_runs_win[((const oracle_run*)y)->a];
+    if (p->read != q->read) return p->read < q->read ? -1 : 1;
+    return (p->pos > q->pos) - (p->pos < q->pos);
+}
 
 static int cmp_entry(const void* a, const void* b) {
     const oracle_entry* x = (const oracle_entry*)a;
@@ -526,29 +544,40 @@ int oracle_kmer_matrix(int64_t n, const uint8_t* bases, const int64_t* offsets, 
         }
     }
     qsort(win, (size_t)W, sizeof(oracle_window), cmp_window);
-    /* frequencies (runs of equal codes), reliable k-mers and their columns;
-     * within a run the windows are in (read, position) order, so the first
-     * window of a read in a run has the read's smallest position */
-    oracle_entry* ent = (oracle_entry*)xmalloc(sizeof(oracle_entry) * (size_t)(W ? W : 1));
-    uint64_t* codes = (uint64_t*)xmalloc(sizeof(uint64_t) * (size_t)(W ? W : 1));
+    /* frequencies (runs of equal codes) and the reliable k-mers; within a run
+     * the windows are in (read, position) order, so a run's first window is
+     * the k-mer's first occurrence and the first window of a read in a run
+     * has the read's smallest position */
+    oracle_run* runs = (oracle_run*)xmalloc(sizeof(oracle_run) * (size_t)(W ? W : 1));
     int64_t m = 0, nnz = 0;
     for (int64_t a = 0; a < W;) {
         int64_t b = a;
         while (b < W && win[b].code == win[a].code) ++b;
         int64_t freq = b - a;
         if (freq >= lo && freq <= hi) {
-            codes[m] = win[a].code;
-            for (int64_t e = a; e < b; ++e) {
-                if (e > a && win[e].read == win[e - 1].read) continue;   /* not the read's first */
-                ent[nnz].read = win[e].read;
-                ent[nnz].col = m;
-                ent[nnz].val = strand_bit ? (int32_t)((win[e].pos << 1) | win[e].strand) : (int32_t)win[e].pos;
-                ++nnz;
-            }
+            runs[m].a = a;
+            runs[m].b = b;
             ++m;
         }
         a = b;
     }
+    /* columns: the reliable k-mers by first occurrence */
+    g_runs_win = win;
+    qsort(runs, (size_t)m, sizeof(oracle_run), cmp_run_first);
+    g_runs_win = NULL;
+    oracle_entry* ent = (oracle_entry*)xmalloc(sizeof(oracle_entry) * (size_t)(W ? W : 1));
+    uint64_t* codes = (uint64_t*)xmalloc(sizeof(uint64_t) * (size_t)(m ? m : 1));
+    for (int64_t c = 0; c < m; ++c) {
+        codes[c] = win[runs[c].a].code;
+        for (int64_t e = runs[c].a; e < runs[c].b; ++e) {
+            if (e > runs[c].a && win[e].read == win[e - 1].read) continue;   /* not the read's first */
+            ent[nnz].read = win[e].read;
+            ent[nnz].col = c;
+            ent[nnz].val = strand_bit ? (int32_t)((win[e].pos << 1) | win[e].strand) : (int32_t)win[e].pos;
+            ++nnz;
+        }
+    }
+    free(runs);
     free(win);
     qsort(ent, (size_t)nnz, sizeof(oracle_entry), cmp_entry);
     int32_t* oc = (int32_t*)xmalloc(sizeof(int32_t) * (size_t)(nnz ? nnz : 1));

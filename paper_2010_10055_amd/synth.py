@@ -225,11 +225,12 @@ class CSR:
 def kmer_matrix(reads: Reads, k: int = K_DEFAULT, lo: int = 2, hi: int = 8,
                 device: str = "cpu", strand_bit: bool = False) -> tuple:
     """Build A from reads.  Returns (A, kmer_codes) where kmer_codes[c] is the
-    canonical 2-bit code of column c (ascending).
+    canonical 2-bit code of column c.
 
     Frequency = occurrences of the canonical k-mer over all reads (repeats
     inside a read count); a k-mer is reliable if lo <= frequency <= hi.
-    Column order = ascending canonical code among reliable k-mers.
+    Column order = first occurrence among reliable k-mers: by the first read
+    holding the k-mer, then by its smallest position there.
     strand_bit: A's value is (position << 1) | strand instead of the
     position, strand = 1 where the read holds the reverse complement of the
     canonical k-mer (the orientation the overlap graph is derived from).
@@ -262,8 +263,15 @@ def kmer_matrix(reads: Reads, k: int = K_DEFAULT, lo: int = 2, hi: int = 8,
         pos = (pos << 1) | strand[valid].to(torch.int64)
     uniq, inv, cnt = torch.unique(canon, sorted=True, return_inverse=True, return_counts=True)
     reliable = (cnt >= lo) & (cnt <= hi)
-    colmap = torch.cumsum(reliable.to(torch.int64), 0) - 1
-    m = int(reliable.sum().item())
+    # the kept windows are in (read, position) order: a k-mer's first
+    # occurrence is its smallest window index
+    first = torch.full((uniq.numel(),), canon.numel(), dtype=torch.int64, device=dev)
+    first.scatter_reduce_(0, inv, torch.arange(canon.numel(), device=dev), reduce="amin")
+    rel_idx = torch.nonzero(reliable).flatten()
+    by_first = rel_idx[torch.argsort(first[rel_idx])]
+    m = int(by_first.numel())
+    colmap = torch.full((uniq.numel(),), -1, dtype=torch.int64, device=dev)
+    colmap[by_first] = torch.arange(m, device=dev)
     keep = reliable[inv]
     col = colmap[inv][keep]
     rid, pos = rid[keep], pos[keep]
@@ -279,7 +287,7 @@ def kmer_matrix(reads: Reads, k: int = K_DEFAULT, lo: int = 2, hi: int = 8,
     rowptr[1:] = torch.cumsum(rowcnt, 0)
     A = CSR(n, m, rowptr.cpu().numpy(), r_col.to(torch.int32).cpu().numpy(),
             r_pos.to(torch.int32).cpu().numpy())
-    return A, uniq[reliable].cpu().numpy()
+    return A, uniq[by_first].cpu().numpy()
 
 
 # ----------------------------------------------------------------------------

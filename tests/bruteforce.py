@@ -30,17 +30,19 @@ def canonical(kmer: str) -> str:
 def overlap_from_reads(reads, k: int, lo: int, hi: int, min_shared: int):
     """Dict {(i, j): (count, (p_i0, p_j0, p_i1, p_j1))} for every read pair
     (diagonal included) sharing >= min_shared reliable k-mers.  The kept
-    position pairs belong to the two lexicographically smallest shared
-    canonical k-mers; a position is the first start of that k-mer in the
-    read as sequenced."""
+    position pairs belong to the two shared canonical k-mers met first when
+    the reads are read one after the other (A's column order); a position
+    is the first start of that k-mer in the read as sequenced."""
     seqs = [bases_to_str(reads.read(i)) for i in range(reads.n)]
     freq = Counter()
+    met = {}                      # canonical k-mer -> when it was first met
     per_read = []
     for s in seqs:
         first = {}
         for p in range(len(s) - k + 1):
             c = canonical(s[p:p + k])
             freq[c] += 1
+            met.setdefault(c, len(met))
             if c not in first:
                 first[c] = p
         per_read.append(first)
@@ -54,7 +56,7 @@ def overlap_from_reads(reads, k: int, lo: int, hi: int, min_shared: int):
             shared = keys[i] & keys[j]
             if len(shared) < min_shared or not shared:
                 continue
-            srt = sorted(shared)
+            srt = sorted(shared, key=met.__getitem__)
             s0 = srt[0]
             seed = [sets[i][s0], sets[j][s0], -1, -1]
             if len(srt) > 1:

@@ -79,8 +79,11 @@ MUTANTS = [
     ("km-rc-not-complemented", "rc |= (uint64_t)(3 - s[p + q]) << (2 * q);", "rc |= (uint64_t)s[p + q] << (2 * q);"),
     ("km-bounds-strict", "if (freq >= lo && freq <= hi) {", "if (freq > lo && freq <= hi) {"),
     ("km-upper-bound-dropped", "if (freq >= lo && freq <= hi) {", "if (freq >= lo) {"),
-    ("km-last-position", "if (e > a && win[e].read == win[e - 1].read) continue;",
-     "if (e + 1 < b && win[e].read == win[e + 1].read) continue;"),
+    ("km-last-position", "if (e > runs[c].a && win[e].read == win[e - 1].read) continue;",
+     "if (e + 1 < runs[c].b && win[e].read == win[e + 1].read) continue;"),
+    ("km-columns-in-code-order", "qsort(runs, (size_t)m, sizeof(oracle_run), cmp_run_first);", ""),
+    ("km-first-occurrence-last-position", "return (p->pos > q->pos) - (p->pos < q->pos);",
+     "return (p->pos < q->pos) - (p->pos > q->pos);"),
     ("km-last-base-first", "fwd = (fwd << 2) | s[p + q];", "fwd |= (uint64_t)s[p + q] << (2 * q);"),
     ("km-window-past-end", "for (int64_t p = 0; p + k <= L; ++p) {", "for (int64_t p = 0; p + k < L; ++p) {"),
     # one-pass marks used for sampled checks
