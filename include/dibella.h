@@ -340,12 +340,15 @@ int dibella_transitive_reduce_noalloc(const dibella_csr* R, int32_t fuzz, uint32
  * significant) and its reverse complement's, its strand 1 when the reverse
  * complement is the smaller.  A k-mer's frequency is its number of windows
  * over all reads (repeats inside a read count); it is reliable when
- * lo <= frequency <= hi.  The reliable k-mers, in increasing code order,
- * are A's columns; A_ic = the smallest position of k-mer c in read i, or
- * (position << 1) | strand (the strand at that position) with
- * DIBELLA_KMER_STRAND.  A: n x m, rows sorted, allocated through alloc;
- * *codes: device uint64[m], the reliable canonical codes (column order),
- * allocated through alloc (NULL when m = 0).
+ * lo <= frequency <= hi.  The reliable k-mers are A's columns in the order
+ * of their first occurrence: by the first read holding the k-mer, then by
+ * its smallest position in that read (the paper fixes no column order;
+ * this one gives the k-mers of a read consecutive columns, so the rows of
+ * A^T that one read's products visit lie side by side in memory).  A_ic =
+ * the smallest position of k-mer c in read i, or (position << 1) | strand
+ * (the strand at that position) with DIBELLA_KMER_STRAND.  A: n x m, rows
+ * sorted, allocated through alloc; *codes: device uint64[m], codes[c] = the
+ * canonical code of column c, allocated through alloc (NULL when m = 0).
  * Errors: EINVAL for k outside [1, 31], lo < 1, hi < lo, malformed offsets
  * or a base outside 0..3; EOVERFLOW for n >= 2^31, 2^32 windows or more, or
  * 2^31 reliable k-mers or more.

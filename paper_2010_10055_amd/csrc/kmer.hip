@@ -2,21 +2,28 @@
 // every window of k bases of every read is a k-mer, counted under its
 // canonical form (the smaller 2-bit code of the k-mer and of its reverse
 // complement; bases A0 C1 G2 T3, the first base most significant); k-mers
-// whose count over all windows lies in [lo, hi] are reliable and, in
-// increasing code order, are A's columns; A_ic is the smallest position of
-// k-mer c in read i, or (position << 1) | strand (1: the read holds the
-// canonical k-mer reverse complemented).
+// whose count over all windows lies in [lo, hi] are reliable and are A's
+// columns in the order of their first occurrence (the first read holding
+// the k-mer, then its smallest position there: the k-mers of one read get
+// consecutive columns, so that the rows of A^T one read's walk visits lie
+// side by side); A_ic is the smallest position of k-mer c in read i, or
+// (position << 1) | strand (1: the read holds the canonical k-mer reverse
+// complemented).
 //
 // On the device, with no hashing: every window's canonical code is sorted
 // (stable LSD radix sort, 8-bit digits, keys and window numbers), so equal
 // k-mers form runs in window order; a run's length is its frequency (read
-// from its first element, at most hi + 1 steps), reliable runs are numbered
-// by a scan, and the first element of each read within a reliable run
+// from its first element, at most hi + 1 steps) and its first element is
+// the k-mer's first occurrence.  A reliable run marks its first window in a
+// bitmap over the windows; a column is the number of marked windows before
+// the run's first one (a popcount prefix), so columns follow first
+// occurrence.  The first element of each read within a reliable run
 // (stable order: the read's smallest position) becomes an entry
-// (read, column, value).  A second stable radix sort by read turns the
-// entries, which are in column order, into A's rows with their columns in
-// order.  Two host synchronisations: the window count (to size the sort)
-// and the reliable k-mers and entries (to size A).
+// (read, column, value), placed in column order by a scan of the columns'
+// entry counts.  A second stable radix sort by read turns the entries into
+// A's rows with their columns in order.  Two host synchronisations: the
+// window count (to size the sort) and the reliable k-mers and entries (to
+// size A).
 #include "common.hpp"
 
 #include <cstring>
@@ -321,9 +328,12 @@ __device__ __forceinline__ int64_t run_head(const uint64_t* keys, uint64_t mask,
 }
 
 // rel[e] = 1 where e starts a run (equal codes under `mask`) of length in
-// [lo, hi] (the length read at most hi + 1 elements far).
-__global__ void k_km_runs(const uint64_t* __restrict__ keys, int64_t W, uint64_t mask, int32_t lo, int32_t hi,
-                          int32_t* __restrict__ rel) {
+// [lo, hi] (the length read at most hi + 1 elements far); such a run's
+// first window (its k-mer's first occurrence) is marked in `first`, one bit
+// per window.
+__global__ void k_km_runs(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ wid, int64_t W,
+                          uint64_t mask, int32_t lo, int32_t hi, int32_t* __restrict__ rel,
+                          uint32_t* __restrict__ first) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < W; e += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t c = keys[e] & mask;
         int32_t r = 0;
@@ -331,8 +341,40 @@ __global__ void k_km_runs(const uint64_t* __restrict__ keys, int64_t W, uint64_t
             int64_t len = 1;
             while (len <= hi && e + len < W && (keys[e + len] & mask) == c) ++len;
             r = (len >= lo && len <= hi) ? 1 : 0;
+            if (r) {
+                const uint32_t w = wid[e];
+                atomicOr(&first[w >> 5], 1u << (w & 31));
+            }
         }
         rel[e] = r;
+    }
+}
+
+// Marked windows per 32-bit word of the bitmap.
+__global__ void k_km_popc(const uint32_t* __restrict__ first, int64_t nwords, int32_t* __restrict__ cnt) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nwords;
+         q += (int64_t)gridDim.x * blockDim.x)
+        cnt[q] = __popc(first[q]);
+}
+
+// For every reliable run (first element h): its column, the marked windows
+// before its first window (wbase: the words' exclusive scan), kept in
+// colof[h]; and its entry count (its kept elements, from the scan kpos of
+// the keep flags) in ccount[column].
+__global__ void k_km_columns(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ wid, int64_t W,
+                             uint64_t mask, int32_t hi, const int32_t* __restrict__ rel,
+                             const uint32_t* __restrict__ first, const int64_t* __restrict__ wbase,
+                             const int64_t* __restrict__ kpos, int64_t* __restrict__ colof,
+                             int32_t* __restrict__ ccount) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < W; e += (int64_t)gridDim.x * blockDim.x) {
+        if (!rel[e]) continue;
+        const uint64_t c = keys[e] & mask;
+        int64_t len = 1;
+        while (len <= hi && e + len < W && (keys[e + len] & mask) == c) ++len;
+        const uint32_t w = wid[e];
+        const int64_t col = wbase[w >> 5] + __popc(first[w >> 5] & ((1u << (w & 31)) - 1u));
+        colof[e] = col;
+        ccount[col] = (int32_t)(kpos[e + len] - kpos[e]);
     }
 }
 
@@ -357,13 +399,15 @@ __global__ void k_km_keep(const uint64_t* __restrict__ keys, const uint32_t* __r
 }
 
 // The kept elements as A entries in (column, read) order: key = read,
-// value = (column << 32) | (position, or (position << 1) | strand); a
-// reliable run's first element also writes the run's k-mer to codes.
+// value = (column << 32) | (position, or (position << 1) | strand), at the
+// column's first slot (cstart) plus the element's rank among its run's kept
+// elements; a reliable run's first element also writes the run's k-mer to
+// codes.
 __global__ void k_km_emit(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ wid, int64_t W,
                           uint64_t mask, const uint32_t* __restrict__ rd, const int64_t* __restrict__ woff,
-                          int32_t hi, const int64_t* __restrict__ colof, const int32_t* __restrict__ keep,
-                          const int64_t* __restrict__ kpos, int strand_bit, uint32_t* __restrict__ rkey,
-                          uint64_t* __restrict__ rval, uint64_t* __restrict__ codes) {
+                          int32_t hi, const int64_t* __restrict__ colof, const int64_t* __restrict__ cstart,
+                          const int32_t* __restrict__ keep, const int64_t* __restrict__ kpos, int strand_bit,
+                          uint32_t* __restrict__ rkey, uint64_t* __restrict__ rval, uint64_t* __restrict__ codes) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < W; e += (int64_t)gridDim.x * blockDim.x) {
         if (!keep[e]) continue;
         const int64_t h = run_head(keys, mask, e, hi);   // >= 0: kept elements lie in reliable runs
@@ -375,7 +419,7 @@ __global__ void k_km_emit(const uint64_t* __restrict__ keys, const uint32_t* __r
         const int64_t pos = w - woff[r];
         const uint32_t strand = (uint32_t)(key >> kStrandBit);
         const uint32_t v = strand_bit ? (uint32_t)((pos << 1) | strand) : (uint32_t)pos;
-        const int64_t o = kpos[e];
+        const int64_t o = cstart[col] + (kpos[e] - kpos[h]);
         rkey[o] = (uint32_t)r;
         rval[o] = ((uint64_t)(uint32_t)col << 32) | v;
     }
@@ -498,13 +542,18 @@ int kmer_matrix_run(const uint8_t* bases, const int64_t* offsets, int64_t n, int
         DB_TRY(wk.work_n(W + 1, &colof));
         DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &keep));
         DB_TRY(wk.work_n(W + 1, &kpos));
+        // one bit per window: the first windows of the reliable k-mers
+        const int64_t nwords = ceil_div(std::max<int64_t>(W, 1), int64_t(32));
+        uint32_t* first;
+        DB_TRY(wk.work_n(nwords, &first));
+        DB_TRY(fill_i32(reinterpret_cast<int32_t*>(first), 0, nwords, st));
         const int grid = grid_for(W, 256, 1 << 16);
         const uint64_t cmask = (1ull << (2 * k)) - 1;   // k <= 31: the code bits
         uint32_t* rd;
         DB_TRY(wk.work_n(std::max<int64_t>(W, 1), &rd));
         DB_TRY(timing_begin(kPhKmerRuns, st, &tok));
         if (W > 0) {
-            hipLaunchKernelGGL(k_km_runs, dim3(grid), dim3(256), 0, st, sk, W, cmask, lo, hi, rel);
+            hipLaunchKernelGGL(k_km_runs, dim3(grid), dim3(256), 0, st, sk, sw, W, cmask, lo, hi, rel, first);
             hipLaunchKernelGGL(k_km_keep, dim3(grid), dim3(256), 0, st, sk, sw, W, cmask, rtab, woff, hi, rel, keep,
                                rd);
             DB_HIP(hipGetLastError());
@@ -536,10 +585,29 @@ int kmer_matrix_run(const uint8_t* bases, const int64_t* offsets, int64_t n, int
         DB_TRY(ar.work_n(std::max<int64_t>(nnz, 1), &rkey[1]));
         DB_TRY(ar.work_n(std::max<int64_t>(nnz, 1), &rval[0]));
         DB_TRY(ar.work_n(std::max<int64_t>(nnz, 1), &rval[1]));
+        // columns by first occurrence, and each column's first entry slot
+        int32_t *wcnt, *ccount;
+        int64_t *wbase, *cstart;
+        DB_TRY(wk.work_n(nwords, &wcnt));
+        DB_TRY(wk.work_n(nwords + 1, &wbase));
+        DB_TRY(wk.work_n(std::max<int64_t>(m, 1), &ccount));
+        DB_TRY(wk.work_n(m + 1, &cstart));
         DB_TRY(timing_begin(kPhKmerRuns, st, &tok));
         if (W > 0) {
-            hipLaunchKernelGGL(k_km_emit, dim3(grid), dim3(256), 0, st, sk, sw, W, cmask, rd, woff, hi, colof, keep,
-                               kpos, strand_bit, rkey[0], rval[0], codes);
+            hipLaunchKernelGGL(k_km_popc, dim3(grid_for(nwords, 256, 1 << 16)), dim3(256), 0, st, first, nwords,
+                               wcnt);
+            DB_HIP(hipGetLastError());
+        }
+        DB_TRY(scan_exclusive(wcnt, wbase, nwords, nullptr, wk));
+        if (W > 0) {
+            hipLaunchKernelGGL(k_km_columns, dim3(grid), dim3(256), 0, st, sk, sw, W, cmask, hi, rel, first, wbase,
+                               kpos, colof, ccount);
+            DB_HIP(hipGetLastError());
+        }
+        DB_TRY(scan_exclusive(ccount, cstart, m, nullptr, wk));
+        if (W > 0) {
+            hipLaunchKernelGGL(k_km_emit, dim3(grid), dim3(256), 0, st, sk, sw, W, cmask, rd, woff, hi, colof, cstart,
+                               keep, kpos, strand_bit, rkey[0], rval[0], codes);
             DB_HIP(hipGetLastError());
         }
         DB_TRY(timing_end(tok, st));
