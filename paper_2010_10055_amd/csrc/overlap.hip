@@ -388,6 +388,25 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t key, int low, int nbucket
     return SEG ? (key >> low) & (uint32_t)(nbuckets - 1) : min(key >> low, (uint32_t)nbuckets - 1u);
 }
 
+// Adds `valid` lanes to hist[b] with one LDS atomic per run of consecutive
+// lanes of the wave that share b (neighbouring pairs often share a bucket:
+// a row's columns cluster when columns follow first occurrence, and one
+// atomic per lane on one address would serialise).  Invalid lanes are the
+// wave's last ones.
+__device__ __forceinline__ void wave_run_add(uint32_t* hist, uint32_t b, bool valid) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const uint32_t prev = __shfl_up(b, 1, kWave);
+    const bool head = lane == 0 || prev != b;
+    const uint64_t heads = __ballot(head);
+    const uint64_t valids = __ballot(valid);
+    if (head) {
+        const uint64_t above = lane == kWave - 1 ? 0ull : heads & ~((2ull << lane) - 1ull);
+        const uint64_t upto = above ? (above & (0ull - above)) - 1ull : ~0ull;   // lanes below the next head
+        const uint32_t cnt = (uint32_t)__popcll(valids & upto & ~((1ull << lane) - 1ull));
+        if (cnt) atomicAdd(&hist[b], cnt);
+    }
+}
+
 template <bool SEG>
 __global__ __launch_bounds__(kPartBlock) void k_ov_part_count(const uint32_t* __restrict__ keys, int64_t n,
                                                               int per_block, int low, int nbuckets,
@@ -413,7 +432,7 @@ __global__ __launch_bounds__(kPartBlock) void k_ov_part_count(const uint32_t* __
         for (int q = 0; q < kPartIlp; ++q) kk[q] = keys[min(c0 + q * kPartBlock + threadIdx.x, c1 - 1)];
 #pragma unroll
         for (int q = 0; q < kPartIlp; ++q)
-            atomicAdd(&hist[bucket_of<SEG>(kk[q], low, nbuckets)], c0 + q * kPartBlock + threadIdx.x < c1 ? 1u : 0u);
+            wave_run_add(hist, bucket_of<SEG>(kk[q], low, nbuckets), c0 + q * kPartBlock + threadIdx.x < c1);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbuckets; b += kPartBlock) counts[cp.tab0 + (int64_t)b * cp.tstride] = (int32_t)hist[b];
@@ -1035,40 +1054,43 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
             walk_fill<BLOCK>(tbuf, c_base, w0, w1, my_off, my_len);
             __syncthreads();
             for (int32_t q0 = w0 + (int32_t)threadIdx.x; q0 < w1; q0 += BLOCK * PER) {
-                if (stop && *(volatile const int32_t*)stop) break;
-                // the loads write only their own registers (an inline value
-                // written there instead would make every later load wait)
+                if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+                // The round's LDS reads are issued together (indices clamped,
+                // so that no branch separates them and one wait covers them),
+                // then the pairs of two-pair columns are decoded, then the
+                // gathers go out: a register that a load in flight targets is
+                // never written by an instruction after that load.
                 int tt[PER];
+                int64_t cb[PER];
                 int2 jp[PER];
 #pragma unroll
                 for (int u = 0; u < PER; ++u) {
                     const int32_t q = q0 + u * BLOCK;
-                    tt[u] = -1;
-                    if (q < w1) {
-                        const int tv = tbuf[q - w0];
-                        const int64_t cb = c_base[tv & 0x7FFF];
-                        tt[u] = tv;
-                        if (cb > kInlineBelow) jp[u] = at[cb + q];
-                    }
+                    const int tv = tbuf[min(q, w1 - 1) - w0];
+                    tt[u] = q < w1 ? tv : -1;
                 }
+#pragma unroll
+                for (int u = 0; u < PER; ++u) cb[u] = c_base[tt[u] < 0 ? 0 : (tt[u] & 0x7FFF)];
+#pragma unroll
+                for (int u = 0; u < PER; ++u)
+                    if (tt[u] >= 0 && cb[u] <= kInlineBelow)
+                        jp[u] = (tt[u] & 0x8000) ? inline_pair(cb[u])   // the column's other pair
+                                                 : make_int2(self, own ? own[cbase + (tt[u] & 0x7FFF)] : 0);
+#pragma unroll
+                for (int u = 0; u < PER; ++u)
+                    if (tt[u] >= 0 && cb[u] > kInlineBelow) jp[u] = at[cb[u] + q0 + u * BLOCK];
 #pragma unroll
                 for (int u = 0; u < PER; ++u) {
                     if (tt[u] < 0) continue;
-                    const int t = tt[u] & 0x7FFF;
-                    const int64_t cb = c_base[t];
-                    int2 v = jp[u];
-                    if (cb <= kInlineBelow)
-                        v = (tt[u] & 0x8000) ? inline_pair(cb)   // the column's other pair
-                                             : make_int2(self, own ? own[cbase + t] : 0);   // the entry itself
-                    f(cbase + t, v, (int64_t)(done + q0 + u * BLOCK));
+                    f(cbase + (tt[u] & 0x7FFF), jp[u], (int64_t)(done + q0 + u * BLOCK));
                 }
             }
             __syncthreads();
-            if (stop && *(volatile const int32_t*)stop) break;
+            if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
         }
         done += tot;
         if (tot == 0) __syncthreads();   // c_base is rewritten by the next chunk
-        if (stop && *(volatile const int32_t*)stop) break;
+        if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
     }
 }
 
@@ -1395,7 +1417,7 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
                              // m2 only decreases: a candidate above it now can never
                              // be one of the two smallest (all candidates of a column
                              // differ in t), so most products skip the cascade
-                             if (x > *(volatile const uint64_t*)&m2[r]) return;
+                             if (x > __hip_atomic_load(&m2[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
                              const uint64_t old = atomicMin(&m1[r], x);
                              const uint64_t rej = old > x ? old : x;
                              if (rej != kEmpty64) atomicMin(&m2[r], rej);
