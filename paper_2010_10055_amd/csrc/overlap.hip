@@ -1024,18 +1024,20 @@ __device__ __forceinline__ void walk_fill(uint16_t* tbuf, const int64_t* c_base,
     }
 }
 
-// f(t, (j, p_j), q).  self: the row's read.  rval: the row's positions,
-// loaded with the segments so that the other pair of a two-pair column
-// comes with its position (without it that position reads wrong: for
-// callers that use only j).  own: given, the row's own products come with
-// their positions too (else 0).  PER: gathers per thread and round (a kernel
-// short of registers takes fewer).
-template <int BLOCK, int PER = walk_per(BLOCK), class F>
-__device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
-                                              const int2* __restrict__ at, int64_t* c_base, uint16_t* tbuf,
-                                              int64_t* s_tmp, const int32_t* stop, int32_t self,
-                                              const int32_t* __restrict__ rval, const int32_t* __restrict__ own,
-                                              F&& f) {
+// rf(tt, jp, cbase, qb) once per round: product u of the round (u < PER)
+// is entry cbase + (tt[u] & 0x7FFF) of the row with pair jp[u] = (j, p_j)
+// and number qb + u * BLOCK, or absent (tt[u] < 0).  self: the row's read.
+// rval: the row's positions, loaded with the segments so that the other
+// pair of a two-pair column comes with its position (without it that
+// position reads wrong: for callers that use only j).  own: given, the
+// row's own products come with their positions too (else 0).  PER: gathers
+// per thread and round (a kernel short of registers takes fewer).
+template <int BLOCK, int PER, class RF>
+__device__ __forceinline__ void walk_rounds(const uint64_t* __restrict__ rseg, int L,
+                                            const int2* __restrict__ at, int64_t* c_base, uint16_t* tbuf,
+                                            int64_t* s_tmp, const int32_t* stop, int32_t self,
+                                            const int32_t* __restrict__ rval, const int32_t* __restrict__ own,
+                                            RF&& rf) {
     constexpr int CH = walk_chunk_of(BLOCK), WIN = walk_win_of(BLOCK);
     static_assert(CH % BLOCK == 0 && CH <= 65536, "chunk index kept in 16 bits");
     constexpr int E = walk_chunk_of(BLOCK) / BLOCK;
@@ -1079,11 +1081,7 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
 #pragma unroll
                 for (int u = 0; u < PER; ++u)
                     if (tt[u] >= 0 && cb[u] > kInlineBelow) jp[u] = at[cb[u] + q0 + u * BLOCK];
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    if (tt[u] < 0) continue;
-                    f(cbase + (tt[u] & 0x7FFF), jp[u], (int64_t)(done + q0 + u * BLOCK));
-                }
+                rf(tt, jp, cbase, done + q0);
             }
             __syncthreads();
             if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
@@ -1092,6 +1090,23 @@ __device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg,
         if (tot == 0) __syncthreads();   // c_base is rewritten by the next chunk
         if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
     }
+}
+
+// f(t, (j, p_j), q) for every product, in turn (see walk_rounds).
+template <int BLOCK, int PER = walk_per(BLOCK), class F>
+__device__ __forceinline__ void walk_products(const uint64_t* __restrict__ rseg, int L,
+                                              const int2* __restrict__ at, int64_t* c_base, uint16_t* tbuf,
+                                              int64_t* s_tmp, const int32_t* stop, int32_t self,
+                                              const int32_t* __restrict__ rval, const int32_t* __restrict__ own,
+                                              F&& f) {
+    walk_rounds<BLOCK, PER>(rseg, L, at, c_base, tbuf, s_tmp, stop, self, rval, own,
+                            [&](const int (&tt)[PER], const int2 (&jp)[PER], int cbase, int32_t qb) {
+#pragma unroll
+                                for (int u = 0; u < PER; ++u) {
+                                    if (tt[u] < 0) continue;
+                                    f(cbase + (tt[u] & 0x7FFF), jp[u], (int64_t)(qb + u * BLOCK));
+                                }
+                            });
 }
 
 // ---------------------------------------------------------------------------
@@ -1396,32 +1411,52 @@ __global__ __launch_bounds__(BLOCK) void k_ov_numeric(
     }
     __syncthreads();
     const int32_t self = (int32_t)(S.read_base + i);   // the diagonal is written from its closed form below
-    // four gathers per round: eight would take the registers of half the workgroups
-    walk_products<BLOCK, 4>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, S.a_val + lo,
-                            nullptr, [&](int t, int2 jp, int64_t) {
-                             const int32_t j = jp.x;
-                             if (j == self) return;
-                             int r;
-                             if (BITS) {
-                                 const uint32_t word = bm[j >> 5];
-                                 const uint32_t bit = 1u << (j & 31);
-                                 if (!(word & bit)) return;
-                                 r = (int)pre[j >> 5] + __popc(word & (bit - 1u));
-                             } else {
-                                 const int slot = table_find(keys, T, j);
-                                 if (slot < 0) return;
-                                 r = rank[slot];
-                             }
-                             atomicAdd(&cnt[r], 1);
-                             const uint64_t x = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)jp.y;
-                             // m2 only decreases: a candidate above it now can never
-                             // be one of the two smallest (all candidates of a column
-                             // differ in t), so most products skip the cascade
-                             if (x > __hip_atomic_load(&m2[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
-                             const uint64_t old = atomicMin(&m1[r], x);
-                             const uint64_t rej = old > x ? old : x;
-                             if (rej != kEmpty64) atomicMin(&m2[r], rej);
-                         });
+    // four gathers per round: eight would take the registers of half the
+    // workgroups.  A round's products first look up their output ranks and
+    // the current second seeds (LDS reads only, issued together), then count
+    // and update the seeds.
+    constexpr int NP = 4;
+    walk_rounds<BLOCK, NP>(seg + S.nnz_base + lo, L, at, c_base, tbuf, s_tmp, nullptr, self, S.a_val + lo,
+                           nullptr, [&](const int (&tt)[NP], const int2 (&jp)[NP], int cbase, int32_t) {
+        // (the reads are unconditional, at index 0 for an absent product, so
+        // that no branch keeps them apart)
+        int r[NP];
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const bool live = tt[u] >= 0 && jp[u].x != self;
+            const int32_t j = live ? jp[u].x : 0;
+            if (BITS) {
+                const uint32_t word = bm[j >> 5];
+                const uint32_t bit = 1u << (j & 31);
+                const int p = (int)pre[j >> 5];
+                r[u] = (live && (word & bit)) ? p + __popc(word & (bit - 1u)) : -1;
+            } else {
+                r[u] = -1;
+                if (live) {
+                    const int slot = table_find(keys, T, j);
+                    if (slot >= 0) r[u] = rank[slot];
+                }
+            }
+        }
+        uint64_t cur[NP];
+#pragma unroll
+        for (int u = 0; u < NP; ++u)
+            cur[u] = __hip_atomic_load(&m2[r[u] < 0 ? 0 : r[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            if (r[u] < 0) continue;
+            atomicAdd(&cnt[r[u]], 1);
+            const uint64_t x = ((uint64_t)(uint32_t)(cbase + (tt[u] & 0x7FFF)) << 32) | (uint64_t)(uint32_t)jp[u].y;
+            // m2 only decreases: a candidate above it (here, above a value it
+            // held earlier in the round) can never be one of the two smallest
+            // (all candidates of a column differ in t), so most products
+            // skip the cascade
+            if (x > cur[u]) continue;
+            const uint64_t old = atomicMin(&m1[r[u]], x);
+            const uint64_t rej = old > x ? old : x;
+            if (rej != kEmpty64) atomicMin(&m2[r[u]], rej);
+        }
+    });
     __syncthreads();
     const int64_t off = G[g] - G[S.row_base];
     int4* seed4 = reinterpret_cast<int4*>(S.c_seed);
