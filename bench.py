@@ -611,6 +611,72 @@ def kmer_compare(w, reps: int = 2):
     return out
 
 
+# Integer operations of one extension-table cell: compare the two bases,
+# pick match or mismatch, three additions (diagonal, and the gap from each
+# side), two maxima, one test against the X-drop floor.
+ALIGN_OPS_PER_CELL = 8
+# Plain vector ALU peak (32-bit integer lane operations): 256 CUs, 4 SIMDs of
+# 16 lanes each, 2.4 GHz.
+ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def align_compare(inp, reads, rows: int, reps: int = 2, scores=(1, -1, -2, 25), min_score: int = 300):
+    """R from the alignment (dibella_r_from_alignment) over the first `rows`
+    reads' rows of C (the other rows left empty): best kernel time of
+    `reps` calls, the cells of the extension tables considered, cells and
+    pairs per second, and the cells' integer operations against the vector
+    ALU peak."""
+    import torch
+    import paper_2010_10055_amd as db
+    from paper_2010_10055_amd import _lib
+    C = db.overlap(inp.A, inp.min_shared)
+    n = C.nrows
+    rows = min(rows, n)
+    rp = C.rowptr.clone()
+    rp[rows + 1:] = rp[rows]
+    e = int(rp[rows].item())
+    sub = db.OverlapCSR(n, n, rp, C.col[:e].clone(), C.count[:e].clone(), C.seed[:e].clone())
+    nnz_c = C.nnz
+    del C
+    pairs = e - rows                                   # off-diagonal entries (every row has its diagonal)
+    bases = torch.as_tensor(reads.bases, device="cuda:0")
+    offsets = torch.as_tensor(reads.offsets, device="cuda:0")
+    mat, mis, gap, X = scores
+    R = db.r_from_alignment(sub, bases, offsets, inp.k, mat, mis, gap, X, min_score)
+    torch.cuda.synchronize()
+    del R
+    best = wall = None
+    for _ in range(reps):
+        _lib.timing_enable(True)
+        t0 = time.perf_counter()
+        R = db.r_from_alignment(sub, bases, offsets, inp.k, mat, mis, gap, X, min_score)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ph = _lib.timing_collect()
+        _lib.timing_enable(False)
+        cells = db.last_stats()["cells"]
+        k_ms = ph["align"][0]
+        best = k_ms if best is None else min(best, k_ms)
+        wall = dt if wall is None else min(wall, dt)
+        kept = R.nnz
+        del R
+    ops = cells * ALIGN_OPS_PER_CELL / (best * 1e-3)
+    out = {"rows": rows, "reads": n, "pairs": pairs, "pairs_all_rows": nnz_c - n,
+           "scores": {"match": mat, "mismatch": mis, "gap": gap, "xdrop": X, "min_score": min_score},
+           "cells": int(cells), "kernel_ms": round(best, 2), "call_ms": round(wall * 1e3, 2),
+           "cells_per_s": round(cells / (best * 1e-3)), "pairs_per_s": round(pairs / (best * 1e-3)),
+           "kept_pairs": kept,
+           "roofline": {"bound": "alu", "achieved": round(ops / 1e12, 3), "peak": round(ALU_PEAK_OPS / 1e12, 2),
+                        "unit": "Tops/s (int32 lane operations, 8 per cell)",
+                        "frac": round(ops / ALU_PEAK_OPS, 4)}}
+    log(f"  {rows} rows, {pairs} pairs, {cells / 1e9:.1f} G cells in {best:.1f} ms "
+        f"({cells / (best * 1e-3) / 1e9:.0f} G cells/s, {ops / ALU_PEAK_OPS:.3f} of the ALU peak), "
+        f"{kept} pairs kept")
+    del bases, offsets, sub
+    torch.cuda.empty_cache()
+    return out
+
+
 def blocked_compare(inp, nblocks=(4, 16), reps: int = 2):
     """The overlap graph of one layout job built whole (dibella_overlap, then
     R from C's seeds) and blocked (dibella_overlap_graph_blocked: C formed a
@@ -753,6 +819,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=120, help="jobs of the serving comparison (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=3, help="slots of continuous batching")
     ap.add_argument("--no-kmer", action="store_true", help="skip the k-mer counting leg")
+    ap.add_argument("--align-rows", type=int, default=8192,
+                    help="rows of C aligned by the alignment leg (0 = skip)")
     ap.add_argument("--blocks", type=int, nargs="*", default=[4, 16],
                     help="block counts of the blocked overlap graph comparison (none = skip)")
     ap.add_argument("--calib-copy", action="store_true", help="only run the reference kernels used to scale counters")
@@ -917,12 +985,15 @@ def main():
     if not args.no_kmer:
         log("A from the reads on the device vs the generator ...")
         kmer = kmer_compare(w)
-    served = blocked = None
+    served = blocked = align = None
     entry = None
-    if args.serve_jobs > 0 or args.blocks:
+    if args.serve_jobs > 0 or args.blocks or args.align_rows > 0:
         del A, R
         torch.cuda.empty_cache()
         entry = main_pool_entry(w)
+    if args.align_rows > 0:
+        log(f"R from the alignment ({args.align_rows} rows of C) ...")
+        align = align_compare(entry[1], w.reads, args.align_rows)
     if args.blocks:
         log(f"blocked overlap graph ({args.blocks} blocks) vs whole ...")
         blocked = blocked_compare(entry[1], tuple(args.blocks))
@@ -958,6 +1029,7 @@ def main():
         "batch": batch,
         "kmer_matrix": kmer,
         "blocked": blocked,
+        "align": align,
         "serve": served,
         "cpu_baseline": cpu,
         "cpu_parallel": cpu_par,

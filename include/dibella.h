@@ -398,6 +398,8 @@ typedef struct {
     int32_t trace_len;        /* entries used in nnz_trace / triples_trace */
     int64_t nnz_trace[64];    /* reduction: total nnz after the contained drop, then after each pass */
     int64_t triples_trace[64];/* reduction: triples examined in each pass */
+    int64_t cells;            /* alignment: extension-table cells considered, both sides of
+                                 every pair (dibella_r_from_alignment) */
 } dibella_stats;
 
 int dibella_last_stats(dibella_stats* out);

@@ -72,7 +72,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("products", ctypes.c_int64), ("esc_rows", ctypes.c_int64),
                 ("host_syncs", ctypes.c_int64), ("triples", ctypes.c_int64),
                 ("passes", ctypes.c_int32), ("trace_len", ctypes.c_int32),
-                ("nnz_trace", ctypes.c_int64 * 64), ("triples_trace", ctypes.c_int64 * 64)]
+                ("nnz_trace", ctypes.c_int64 * 64), ("triples_trace", ctypes.c_int64 * 64),
+                ("cells", ctypes.c_int64)]
 
 
 class _Timing(ctypes.Structure):
@@ -397,10 +398,11 @@ KMER_STRAND = 0x1
 def kmer_matrix(bases: torch.Tensor, offsets: torch.Tensor, k: int, lo: int, hi: int, strand_bit: bool = False):
     """A from the reads on the device: bases uint8 (A0 C1 G2 T3, reads back
     to back), offsets int64[n + 1].  Reliable k-mers (frequency over all
-    windows in [lo, hi]) in code order are the columns; values are the
-    smallest position per read and k-mer (with strand_bit: (position << 1)
-    | strand).  Returns (A, codes): codes = the reliable canonical codes
-    (int64 tensor, column order)."""
+    windows in [lo, hi]) are the columns in the order of their first
+    occurrence (first read holding the k-mer, then its smallest position
+    there); values are the smallest position per read and k-mer (with
+    strand_bit: (position << 1) | strand).  Returns (A, codes): codes[c] =
+    the canonical code of column c (int64 tensor)."""
     if bases.dtype != torch.uint8 or not bases.is_cuda or not bases.is_contiguous():
         raise TypeError("bases must be a contiguous uint8 device tensor")
     if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous() or offsets.numel() < 1:
@@ -475,7 +477,8 @@ def last_stats() -> dict:
     return {"products": s.products, "esc_rows": s.esc_rows, "host_syncs": s.host_syncs,
             "triples": s.triples, "passes": s.passes,
             "nnz_trace": [s.nnz_trace[i] for i in range(n)],
-            "triples_trace": [s.triples_trace[i] for i in range(max(0, min(s.passes, 64)))]}
+            "triples_trace": [s.triples_trace[i] for i in range(max(0, min(s.passes, 64)))],
+            "cells": s.cells}
 
 
 def get_tuning() -> dict:

@@ -200,6 +200,7 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32
                                                      int32_t mis, int32_t gap, int32_t X,
                                                      unsigned long long* __restrict__ next,
                                                      int4* __restrict__ ext) {
+    // next[0]: the next task; next[1]: cells considered, over all extensions
     constexpr int NG = kWave / G;
     constexpr uint64_t kMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);   // a group's lanes, from bit 0
     __shared__ int32_t s_score[NG][3][kAlBand];
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32
     int32_t lo1 = 0, hi1 = -1, lo2 = 0, hi2 = -1;   // live ranges of d - 1 and d - 2
     int32_t best = 0, bx = 0, bd = 0;      // best score, its x and anti-diagonal
     int32_t vlA = 0, whA = 0, vlB = 0, whB = 0;   // staged positions [vl, wh) of each side
+    unsigned long long cells = 0;          // cells this group considered
 
     for (;;) {
         if (!busy && !done) {
@@ -261,7 +263,10 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32
             }
         }
         // leave once every group of the wave has run out of tasks
-        if (__ballot(!done) == 0) break;
+        if (__ballot(!done) == 0) {
+            if (gl == 0 && cells) atomicAdd(next + 1, cells);
+            break;
+        }
         if (!busy) continue;
 
         // one anti-diagonal
@@ -290,6 +295,7 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32
             if (to >= 1) staged |= al_cover<G>(wa, bases, A, max(from - 1, 0), to - 1, vlA, whA, gl);
             if (d - from >= 1) staged |= al_cover<G>(wb, bases, B, max(d - to - 1, 0), d - from - 1, vlB, whB, gl);
             if (staged) lds_sync();
+            cells += (unsigned long long)(to - from + 1);
             const int32_t floor_ = best - X;
             int32_t nlo = 0, nhi = -1, dbest = kAlDead, dx = 0;
             for (int32_t c0 = from; c0 <= to; c0 += G) {
@@ -463,11 +469,11 @@ int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int
     DB_TRY(ar.work_n(2 * nnz, &ext));
     DB_TRY(ar.work_n(n, &cnt));
     DB_TRY(ar.work_n(2, &d_flags));
-    DB_TRY(ar.work_n(1, &next));
+    DB_TRY(ar.work_n(2, &next));
     DB_TRY(ar.output_n(n + 1, &rrp));
     if (score_out) DB_TRY(ar.output_n(nnz, &score));
     DB_TRY(fill_i32(d_flags, 0, 2, st));
-    DB_TRY(fill_i64(reinterpret_cast<int64_t*>(next), 0, 1, st));
+    DB_TRY(fill_i64(reinterpret_cast<int64_t*>(next), 0, 2, st));
     constexpr int WPB = 4;
     int tok = -1;
     // checks of the reads and of C
@@ -523,8 +529,10 @@ int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int
     DB_TRY(scan_exclusive(cnt, rrp, n, nullptr, ar));
     int64_t* h64 = reinterpret_cast<int64_t*>(h + 2);
     DB_HIP(hipMemcpyAsync(h64, rrp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DB_HIP(hipMemcpyAsync(h64 + 1, next + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DB_TRY(sync_stream(st));
-    const int64_t rnnz = *h64;
+    const int64_t rnnz = h64[0];
+    stats().cells = h64[1];
     int32_t *rcol, *rval;
     DB_TRY(ar.output_n(rnnz, &rcol));
     DB_TRY(ar.output_n(rnnz, &rval));

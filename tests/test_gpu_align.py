@@ -124,6 +124,43 @@ def test_alignment_short_noisy_reads(db, seed):
         _check(db, C, reads.bases, reads.offsets, k, (2, -3, -3, 40), 64, 0)
 
 
+def test_alignment_counts_every_cell_without_pruning(db):
+    """With X unbounded and reads under 256 bases nothing dies and no
+    anti-diagonal reaches the band limit, so each extension considers every
+    cell of its table but the origin: (m + 1)(n + 1) - 1 for sides of m and
+    n bases.  The library's cell count must be that sum over both sides of
+    every off-diagonal entry."""
+    rng = np.random.default_rng(91)
+    g = synth.random_genome(rng, 1500)
+    seqs = []
+    for t in range(10):
+        s0 = int(rng.integers(0, 1200))
+        r = g[s0:s0 + int(rng.integers(120, 250))].copy()
+        flip = rng.random(r.size) < 0.03
+        r[flip] = (r[flip] + 1) % 4
+        seqs.append(synth.revcomp(r) if t % 3 == 0 else r)
+    reads = _reads(seqs)
+    C = _c_of(db, reads, 1, 1000)
+    Cn = _c_np(C)
+    lens = np.diff(reads.offsets)
+    want = 0
+    for i in range(C.nrows):
+        for e in range(Cn.rowptr[i], Cn.rowptr[i + 1]):
+            j = int(Cn.col[e])
+            if j == i:
+                continue
+            a, b = int(Cn.seed[e][0]), int(Cn.seed[e][1])
+            rc = (a ^ b) & 1
+            pi, pj = a >> 1, b >> 1
+            q = lens[j] - 17 - pj if rc else pj
+            for m, n in ((lens[i] - pi - 17, lens[j] - q - 17), (pi, q)):
+                want += (m + 1) * (n + 1) - 1
+    assert want > 0
+    for group in (16, 32, 64):
+        _check(db, C, reads.bases, reads.offsets, 17, (1, -1, -2, 10 ** 6), group, -10 ** 9)
+        assert db.last_stats()["cells"] == want, group
+
+
 def test_alignment_empty_and_diagonal_only(db):
     reads = _reads([np.zeros(0, np.uint8), np.array([0, 1, 2, 3, 0, 1], np.uint8)])
     A = types.SimpleNamespace(nrows=2, ncols=1, rowptr=np.array([0, 0, 1], np.int64),

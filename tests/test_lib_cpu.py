@@ -88,3 +88,25 @@ def test_timing_labels_match_the_header():
     labels = dict((int(n), name) for n, name in re.findall(r"^\s*\*\s+(\d+)\s+(\w+)", block, re.M))
     assert [labels[i] for i in range(len(labels))] == _lib.PHASES
     assert len(_lib.PHASES) <= int(re.search(r"#define DIBELLA_NUM_PHASES (\d+)", text).group(1))
+
+
+def test_stats_struct_matches_the_header(lib):
+    """The binding's mirror of dibella_stats has the header's fields in the
+    header's order, with the same widths, and the library fills a struct of
+    exactly that size (the last field is read back after a reset)."""
+    from paper_2010_10055_amd import _lib
+    text = open(HEADER).read()
+    body = text[text.index("/* Counters of the last call"):text.index("} dibella_stats;")]
+    body = body[body.index("typedef struct {") + len("typedef struct {"):]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(int64_t|int32_t)\s+(\w+)(?:\[(\d+)\])?;", body)
+    width = {"int64_t": ctypes.c_int64, "int32_t": ctypes.c_int32}
+    want = [(name, width[t] * int(n) if n else width[t]) for t, name, n in fields]
+    got = list(_lib._Stats._fields_)
+    assert [f for f, _ in got] == [f for f, _ in want]
+    for (_, a), (_, b) in zip(got, want):
+        assert ctypes.sizeof(a) == ctypes.sizeof(b)
+    s = _lib._Stats()
+    s.cells = 12345
+    assert lib.dibella_last_stats(ctypes.byref(s)) == 0
+    assert s.cells == 0          # the thread's counters start at zero
