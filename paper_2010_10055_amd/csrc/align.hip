@@ -154,45 +154,84 @@ __device__ __forceinline__ int32_t group_max(int32_t v) {
     return v;
 }
 
+// The maximum over a group of G lanes (G = 16, 32 or 64), in every lane of
+// the group, without shuffles through LDS: lane swaps inside quads and
+// mirrors inside rows of 16 (DPP), the two rows of 32 lanes by a swizzle,
+// the two halves of a wave by reading one lane of each.
+template <int G>
+__device__ __forceinline__ int32_t group_max_dpp(int32_t v) {
+    static_assert(G == 16 || G == 32 || G == 64, "groups of 16, 32 or 64 lanes");
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));    // quad_perm [1, 0, 3, 2]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));    // quad_perm [2, 3, 0, 1]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));   // mirror within half rows
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));   // mirror within rows
+    if (G >= 32) v = max(v, __builtin_amdgcn_ds_swizzle(v, 0x401F));          // lane ^ 16 within 32
+    if (G == 64) v = max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 32));
+    return v;
+}
+
 __device__ __forceinline__ void lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stage positions [from, min(from + kAlFill, side.len)) of a side into its ring.
-template <int G>
+// Stage positions [from, min(from + FILL, side.len)) of a side into its ring
+// of WIN positions.
+template <int G, int WIN = kAlWin, int FILL = kAlFill>
 __device__ __forceinline__ void al_stage(uint8_t* ring, const uint8_t* __restrict__ bases, const AlSide& s,
                                          int32_t from, int gl) {
-    const int32_t to = min(from + kAlFill, s.len);
+    const int32_t to = min(from + FILL, s.len);
 #pragma unroll 4
     for (int32_t p = from + gl; p < to; p += G) {
         uint8_t b = bases[s.s0 + (int64_t)s.dir * p];
-        ring[p & (kAlWin - 1)] = s.comp ? (uint8_t)(3 - b) : b;
+        ring[p & (WIN - 1)] = s.comp ? (uint8_t)(3 - b) : b;
     }
 }
 
 // Make positions [lo, hi] of a side readable from its ring, the staged range
-// being [vl, wh) (at most kAlWin positions): a band below the staged range
-// restarts it at lo; then blocks of kAlFill positions are staged until hi is
-// covered.  A band spans at most kAlBand positions, so the ring keeps all of
-// [lo, hi].  Returns whether anything was staged.
-template <int G>
+// being [vl, wh) (at most WIN positions): a band below the staged range
+// restarts it at lo; then blocks of FILL positions are staged until hi is
+// covered.  A band spans at most WIN - FILL positions, so the ring keeps all
+// of [lo, hi].  Returns whether anything was staged.
+template <int G, int WIN = kAlWin, int FILL = kAlFill>
 __device__ __forceinline__ bool al_cover(uint8_t* ring, const uint8_t* __restrict__ bases, const AlSide& s,
                                          int32_t lo, int32_t hi, int32_t& vl, int32_t& wh, int gl) {
     bool staged = false;
     if (lo < vl) vl = lo, wh = lo;
     while (hi >= wh && wh < s.len) {
-        al_stage<G>(ring, bases, s, wh, gl);
-        wh += kAlFill;
-        vl = max(vl, wh - kAlWin);
+        al_stage<G, WIN, FILL>(ring, bases, s, wh, gl);
+        wh += FILL;
+        vl = max(vl, wh - WIN);
         staged = true;
     }
     return staged;
 }
 
+// The two sides of extension `task` (entry task >> 1; right side for an even
+// task, left side for an odd one) of the off-diagonal entry C_ij with first
+// seed (a, b): read i against read j, or its reverse complement when the
+// seed's strands differ.
+__device__ __forceinline__ void al_sides(int64_t task, int32_t i, int32_t j, int32_t a, int32_t b,
+                                         const int64_t* __restrict__ off, int32_t k, AlSide& A, AlSide& B) {
+    const int64_t oi = off[i], oj = off[j];
+    const int32_t li = (int32_t)(off[i + 1] - oi), lj = (int32_t)(off[j + 1] - oj);
+    const bool rc = ((a ^ b) & 1) != 0;
+    const int32_t pi = a >> 1, pj = b >> 1;
+    const int32_t q = rc ? lj - k - pj : pj;
+    if ((task & 1) == 0) {
+        A = AlSide{oi + pi + k, 1, 0, li - pi - k};
+        B = rc ? AlSide{oj + (lj - 1 - q - k), -1, 1, lj - q - k} : AlSide{oj + q + k, 1, 0, lj - q - k};
+    } else {
+        A = AlSide{oi + pi - 1, -1, 0, pi};
+        B = rc ? AlSide{oj + (lj - q), 1, 1, q} : AlSide{oj + q - 1, -1, 0, q};
+    }
+}
+
 template <int G>
-__global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32_t* __restrict__ row_of,
+__global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int64_t* __restrict__ list,
+                                                     const unsigned long long* __restrict__ list_count,
+                                                     const int32_t* __restrict__ row_of,
                                                      const int32_t* __restrict__ col,
                                                      const int32_t* __restrict__ seed,
                                                      const uint8_t* __restrict__ bases,
@@ -200,7 +239,9 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32
                                                      int32_t mis, int32_t gap, int32_t X,
                                                      unsigned long long* __restrict__ next,
                                                      int4* __restrict__ ext) {
-    // next[0]: the next task; next[1]: cells considered, over all extensions
+    // next[0]: the next task; next[1]: cells considered, over all
+    // extensions.  With a list, the tasks are list[0, *list_count) and
+    // next[0] counts through the list.
     constexpr int NG = kWave / G;
     constexpr uint64_t kMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);   // a group's lanes, from bit 0
     __shared__ int32_t s_score[NG][3][kAlBand];
@@ -222,34 +263,22 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32
     int32_t vlA = 0, whA = 0, vlB = 0, whB = 0;   // staged positions [vl, wh) of each side
     unsigned long long cells = 0;          // cells this group considered
 
+    const int64_t nt = list ? (int64_t)*list_count : ntasks;
     for (;;) {
         if (!busy && !done) {
             unsigned long long t = 0;
             if (gl == 0) t = atomicAdd(next, 1ull);
             t = __shfl(t, leader, kWave);
-            if ((int64_t)t >= ntasks) {
+            if ((int64_t)t >= nt) {
                 done = true;
             } else {
-                task = (int64_t)t;
+                task = list ? list[t] : (int64_t)t;
                 const int64_t e = task >> 1;
-                const int side = (int)(task & 1);
                 const int32_t i = row_of[e], j = col[e];
                 if (i == j) {
                     if (gl == 0) ext[task] = make_int4(0, 0, 0, 0);
                 } else {
-                    const int32_t a = seed[4 * e], b = seed[4 * e + 1];
-                    const int64_t oi = off[i], oj = off[j];
-                    const int32_t li = (int32_t)(off[i + 1] - oi), lj = (int32_t)(off[j + 1] - oj);
-                    const bool rc = ((a ^ b) & 1) != 0;
-                    const int32_t pi = a >> 1, pj = b >> 1;
-                    const int32_t q = rc ? lj - k - pj : pj;
-                    if (side == 0) {
-                        A = AlSide{oi + pi + k, 1, 0, li - pi - k};
-                        B = rc ? AlSide{oj + (lj - 1 - q - k), -1, 1, lj - q - k} : AlSide{oj + q + k, 1, 0, lj - q - k};
-                    } else {
-                        A = AlSide{oi + pi - 1, -1, 0, pi};
-                        B = rc ? AlSide{oj + (lj - q), 1, 1, q} : AlSide{oj + q - 1, -1, 0, q};
-                    }
+                    al_sides(task, i, j, seed[4 * e], seed[4 * e + 1], off, k, A, B);
                     // anti-diagonal 0: the cell (0, 0)
                     if (gl == 0) ring[0][0] = 0;
                     d = 0;
@@ -344,6 +373,159 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int32
 }
 
 // ---------------------------------------------------------------------------
+// The extensions, fast path: an extension whose anti-diagonals never ask for
+// more than G cells (the common case: an extension keeps about
+// 2X / (match - gap) cells live).  Each lane of a group of G holds one cell
+// of the current anti-diagonal, x = from + lane; the two earlier
+// anti-diagonals stay in registers (a lane's cell there counted from that
+// anti-diagonal's first considered cell) and are read across lanes by
+// shuffles, so no score goes through LDS; only the bases are staged, in
+// rings of kBandWin positions.  The cells considered, the dead ones, the
+// ranges and the best cell are exactly the general kernel's.  An extension
+// that would consider more than G cells on one anti-diagonal is appended to
+// `fb` (fb_count[0] entries) and left to the general kernel, which redoes it
+// from the start; its cells are counted there only.
+// ---------------------------------------------------------------------------
+constexpr int kBandWin = 256;
+constexpr int kBandFill = 128;
+
+template <int G>
+__global__ __launch_bounds__(kWave) void k_al_band(int64_t ntasks, const int32_t* __restrict__ row_of,
+                                                   const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ seed,
+                                                   const uint8_t* __restrict__ bases,
+                                                   const int64_t* __restrict__ off, int32_t k, int32_t mat,
+                                                   int32_t mis, int32_t gap, int32_t X,
+                                                   unsigned long long* __restrict__ next, int4* __restrict__ ext,
+                                                   int64_t* __restrict__ fb,
+                                                   unsigned long long* __restrict__ fb_count) {
+    // next[0]: the next task; next[1]: cells considered by finished extensions
+    constexpr int NG = kWave / G;
+    constexpr uint64_t kMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
+    static_assert(G <= kBandWin - kBandFill, "a band fits the staged bases");
+    __shared__ uint8_t s_base[NG][2][kBandWin];
+    const int lane = threadIdx.x;
+    const int grp = lane / G, gl = lane % G;
+    const int leader = grp * G;
+    uint8_t* wa = s_base[grp][0];
+    uint8_t* wb = s_base[grp][1];
+
+    // group state (the same in every lane of the group)
+    bool busy = false, done = false;
+    int64_t task = 0;
+    AlSide A{}, B{};
+    int32_t d = 0;
+    int32_t lo1 = 0, hi1 = -1, lo2 = 0, hi2 = -1;   // live ranges of d - 1 and d - 2
+    int32_t f1 = 0, f2 = 0;                          // their first considered cells
+    int32_t best = 0, bx = 0, bd = 0;
+    int32_t vlA = 0, whA = 0, vlB = 0, whB = 0;
+    unsigned long long tcells = 0, cells = 0;
+    // this lane's cells of d - 1 and d - 2
+    int32_t v1 = kAlDead, v2 = kAlDead;
+
+    for (;;) {
+        if (!busy && !done) {
+            unsigned long long t = 0;
+            if (gl == 0) t = atomicAdd(next, 1ull);
+            t = __shfl(t, leader, kWave);
+            if ((int64_t)t >= ntasks) {
+                done = true;
+            } else {
+                task = (int64_t)t;
+                const int64_t e = task >> 1;
+                const int32_t i = row_of[e], j = col[e];
+                if (i == j) {
+                    if (gl == 0) ext[task] = make_int4(0, 0, 0, 0);
+                } else {
+                    al_sides(task, i, j, seed[4 * e], seed[4 * e + 1], off, k, A, B);
+                    // anti-diagonal 0: the cell (0, 0)
+                    d = 0;
+                    lo1 = 0, hi1 = 0, f1 = 0, v1 = gl == 0 ? 0 : kAlDead;
+                    lo2 = 0, hi2 = -1, f2 = 0, v2 = kAlDead;
+                    best = 0, bx = 0, bd = 0;
+                    vlA = 0, whA = 0, vlB = 0, whB = 0;
+                    tcells = 0;
+                    busy = true;
+                }
+            }
+        }
+        // leave once every group of the wave has run out of tasks
+        if (__ballot(!done) == 0) {
+            if (gl == 0 && cells) atomicAdd(next + 1, cells);
+            break;
+        }
+        if (!busy) continue;
+
+        ++d;
+        const int32_t m = A.len, n = B.len;
+        bool finish = d > m + n || (lo1 > hi1 && lo2 > hi2);
+        int32_t from = INT32_MAX, to = INT32_MIN;
+        if (!finish) {
+            if (lo1 <= hi1) from = lo1, to = hi1 + 1;
+            if (lo2 <= hi2) from = min(from, lo2 + 1), to = max(to, hi2 + 1);
+            from = max(from, max(d - n, 0));
+            to = min(to, min(m, d));
+            if (from <= to && to - from + 1 > kAlBand) finish = true;
+        }
+        if (!finish && from > to) {            // no cell to consider: an empty anti-diagonal
+            lo2 = lo1, hi2 = hi1, f2 = f1, v2 = v1;
+            lo1 = 0, hi1 = -1, v1 = kAlDead;
+            continue;
+        }
+        if (!finish && to - from + 1 > G) {    // wider than the group: the general kernel redoes it
+            if (gl == 0) fb[atomicAdd(fb_count, 1ull)] = task;
+            busy = false;
+            continue;
+        }
+        if (!finish) {
+            // stage the bases the cells read: positions x - 1 in [from - 1, to - 1]
+            // of side A and y - 1 in [d - to - 1, d - from - 1] of side B
+            bool staged = false;
+            if (to >= 1)
+                staged |= al_cover<G, kBandWin, kBandFill>(wa, bases, A, max(from - 1, 0), to - 1, vlA, whA, gl);
+            if (d - from >= 1)
+                staged |= al_cover<G, kBandWin, kBandFill>(wb, bases, B, max(d - to - 1, 0), d - from - 1, vlB, whB,
+                                                           gl);
+            if (staged) lds_sync();
+            tcells += (unsigned long long)(to - from + 1);
+            const int32_t x = from + gl, y = d - x;
+            // the predecessors: x - 1 on d - 2, x - 1 and x on d - 1 (a lane
+            // whose predecessor lies in a live range reads a lane of its group)
+            const int32_t pd = __shfl(v2, gl + from - f2 - 1, G);
+            const int32_t pl = __shfl(v1, gl + from - f1 - 1, G);
+            const int32_t pu = __shfl(v1, gl + from - f1, G);
+            const uint8_t ca = wa[(x - 1) & (kBandWin - 1)], cb = wb[(y - 1) & (kBandWin - 1)];
+            int32_t v = kAlDead;
+            if (x <= to) {
+                if (x >= 1 && y >= 1 && x - 1 >= lo2 && x - 1 <= hi2 && pd != kAlDead) v = pd + (ca == cb ? mat : mis);
+                if (x >= 1 && x - 1 >= lo1 && x - 1 <= hi1 && pl != kAlDead && pl + gap > v) v = pl + gap;
+                if (y >= 1 && x >= lo1 && x <= hi1 && pu != kAlDead && pu + gap > v) v = pu + gap;
+                if (v != kAlDead && v < best - X) v = kAlDead;
+            }
+            const uint64_t live = (__ballot(v != kAlDead) >> leader) & kMask;
+            lo2 = lo1, hi2 = hi1, f2 = f1, v2 = v1;
+            f1 = from, v1 = v;
+            if (live) {
+                lo1 = from + __builtin_ctzll(live);
+                hi1 = from + 63 - __builtin_clzll(live);
+                const int32_t dmax = group_max_dpp<G>(v);
+                if (dmax > best) {
+                    const uint64_t at = (__ballot(v == dmax) >> leader) & kMask;
+                    best = dmax, bx = from + __builtin_ctzll(at), bd = d;
+                }
+            } else {
+                lo1 = 0, hi1 = -1;
+            }
+            continue;
+        }
+        // the extension is over
+        if (gl == 0) ext[task] = make_int4(best, bx, bd - bx, 0);
+        cells += tcells;
+        busy = false;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Scores and R's values from the two extensions of every entry (one wave
 // per row); entries below min_score get -1.
 // ---------------------------------------------------------------------------
@@ -403,8 +585,15 @@ static const char* describe_al_bad(int32_t bad) {
     return "malformed input";
 }
 
-// Lanes per extension: about the band an extension keeps live, 2X / (match -
-// gap) cells.
+// Lanes of the fast path (0: none) from the band an extension keeps live,
+// about 2X / (match - gap) cells; a group holds the band with room to spare.
+static int al_band_group(int32_t mat, int32_t gap, int32_t X) {
+    const int64_t band = 2 * (int64_t)X / (mat - gap);
+    return band <= 10 ? 16 : band <= 24 ? 32 : band <= 48 ? 64 : 0;
+}
+
+// Lanes per extension of the general kernel: about the band an extension
+// keeps live, 2X / (match - gap) cells.
 static int al_group(int32_t mat, int32_t gap, int32_t X, uint32_t flags) {
     const uint32_t g = flags & DIBELLA_ALIGN_GROUP_MASK;
     if (g == DIBELLA_ALIGN_GROUP_16) return 16;
@@ -414,7 +603,7 @@ static int al_group(int32_t mat, int32_t gap, int32_t X, uint32_t flags) {
     return band <= 16 ? 16 : band <= 40 ? 32 : 64;
 }
 
-static int al_grid(int64_t ntasks, int G) {
+static int al_cus() {
     static std::atomic<int> cus_cached{0};
     int cus = cus_cached.load(std::memory_order_relaxed);
     if (!cus) {
@@ -425,6 +614,17 @@ static int al_grid(int64_t ntasks, int G) {
                   : 256;
         cus_cached.store(cus, std::memory_order_relaxed);
     }
+    return cus;
+}
+
+// One wave per workgroup; as many waves as the tasks need, up to 32 per CU.
+static int al_band_grid(int64_t ntasks, int G) {
+    const int64_t waves = ceil_div(ntasks, kWave / G);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(waves, (int64_t)al_cus() * 32));
+}
+
+static int al_grid(int64_t ntasks, int G) {
+    const int cus = al_cus();
     const int ng = kWave / G;
     const size_t lds = (size_t)ng * (3 * kAlBand * sizeof(int32_t) + 2 * kAlWin);
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(32, (160 * 1024) / lds));
@@ -469,11 +669,13 @@ int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int
     DB_TRY(ar.work_n(2 * nnz, &ext));
     DB_TRY(ar.work_n(n, &cnt));
     DB_TRY(ar.work_n(2, &d_flags));
-    DB_TRY(ar.work_n(2, &next));
+    // next: [0] fast-path task counter, [1] its cells, [2] extensions handed
+    // to the general kernel, [3] the general kernel's task counter, [4] its cells
+    DB_TRY(ar.work_n(6, &next));
     DB_TRY(ar.output_n(n + 1, &rrp));
     if (score_out) DB_TRY(ar.output_n(nnz, &score));
     DB_TRY(fill_i32(d_flags, 0, 2, st));
-    DB_TRY(fill_i64(reinterpret_cast<int64_t*>(next), 0, 2, st));
+    DB_TRY(fill_i64(reinterpret_cast<int64_t*>(next), 0, 6, st));
     constexpr int WPB = 4;
     int tok = -1;
     // checks of the reads and of C
@@ -503,21 +705,45 @@ int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int
         set_error(std::string("dibella_r_from_alignment: ") + describe_al_bad(h[0] ? h[0] : h[1]));
         return DIBELLA_EINVAL;
     }
-    // the extensions
+    // the extensions: the fast path over every task, then the general kernel
+    // over those it handed on (or, with a group width asked for, the general
+    // kernel over every task)
     const int64_t ntasks = 2 * nnz;
     if (ntasks > 0) {
-        const int G = al_group(mat, gap, X, flags);
-        const int grid = al_grid(ntasks, G);
+        const int FG = (flags & DIBELLA_ALIGN_GROUP_MASK) ? 0 : al_band_group(mat, gap, X);
+        const int G = FG ? 64 : al_group(mat, gap, X, flags);
+        int64_t* fb = nullptr;
+        const int64_t* list = nullptr;
+        const unsigned long long* list_count = nullptr;
         DB_TRY(timing_begin(kPhAlign, st, &tok));
+        if (FG) {
+            DB_TRY(ar.work_n(ntasks, &fb));
+            const int grid = al_band_grid(ntasks, FG);
+            if (FG == 16)
+                hipLaunchKernelGGL(k_al_band<16>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
+                                   bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
+            else if (FG == 32)
+                hipLaunchKernelGGL(k_al_band<32>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
+                                   bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
+            else
+                hipLaunchKernelGGL(k_al_band<64>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
+                                   bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
+            DB_HIP(hipGetLastError());
+            list = fb;
+            list_count = next + 2;
+        }
+        // with a list, its length is on the device: a grid of a few waves per
+        // CU drains it (waves with nothing to take leave at once)
+        const int grid = FG ? std::min(al_grid(ntasks, G), al_cus() * 4) : al_grid(ntasks, G);
         if (G == 16)
-            hipLaunchKernelGGL(k_al_extend<16>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
-                               bases, offsets, k, mat, mis, gap, X, next, ext);
+            hipLaunchKernelGGL(k_al_extend<16>, dim3(grid), dim3(kWave), 0, st, ntasks, list, list_count, row_of,
+                               C->col, C->seed, bases, offsets, k, mat, mis, gap, X, next + 3, ext);
         else if (G == 32)
-            hipLaunchKernelGGL(k_al_extend<32>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
-                               bases, offsets, k, mat, mis, gap, X, next, ext);
+            hipLaunchKernelGGL(k_al_extend<32>, dim3(grid), dim3(kWave), 0, st, ntasks, list, list_count, row_of,
+                               C->col, C->seed, bases, offsets, k, mat, mis, gap, X, next + 3, ext);
         else
-            hipLaunchKernelGGL(k_al_extend<64>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
-                               bases, offsets, k, mat, mis, gap, X, next, ext);
+            hipLaunchKernelGGL(k_al_extend<64>, dim3(grid), dim3(kWave), 0, st, ntasks, list, list_count, row_of,
+                               C->col, C->seed, bases, offsets, k, mat, mis, gap, X, next + 3, ext);
         DB_HIP(hipGetLastError());
         DB_TRY(timing_end(tok, st));
     }
@@ -529,10 +755,10 @@ int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int
     DB_TRY(scan_exclusive(cnt, rrp, n, nullptr, ar));
     int64_t* h64 = reinterpret_cast<int64_t*>(h + 2);
     DB_HIP(hipMemcpyAsync(h64, rrp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    DB_HIP(hipMemcpyAsync(h64 + 1, next + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DB_HIP(hipMemcpyAsync(h64 + 1, next, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DB_TRY(sync_stream(st));
     const int64_t rnnz = h64[0];
-    stats().cells = h64[1];
+    stats().cells = h64[2] + h64[5];
     int32_t *rcol, *rval;
     DB_TRY(ar.output_n(rnnz, &rcol));
     DB_TRY(ar.output_n(rnnz, &rval));

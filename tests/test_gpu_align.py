@@ -66,12 +66,31 @@ def tiny(db):
     ((1, -1, -2, 25), None, 100), ((1, -1, -2, 25), 16, 0), ((1, -1, -2, 25), 32, 100), ((1, -1, -2, 25), 64, 500),
     ((2, -3, -3, 25), 16, 200), ((1, -1, -2, 50), 32, 100), ((1, -1, -1, 25), 64, 0), ((1, -1, -1, 25), 16, 0),
     ((1, -1, -2, 0), 16, 0), ((3, -2, -5, 40), 32, 300), ((1, 0, -1, 10), 16, 0),
+    # the register-band fast path (groups of 16, 32, 64 lanes chosen from the
+    # scores), with the general kernel redoing extensions that outgrow it
+    ((2, -3, -3, 12), None, 0), ((1, -1, -1, 12), None, 0), ((1, -1, -2, 60), None, 0),
+    ((1, -1, -1, 30), None, 100),
 ])
 def test_alignment_tiny_matches_oracle(db, tiny, sc, group, min_score):
     w, C = tiny
     print(f"tiny: scores {sc} group {group} min_score {min_score} nnz(C) {C.nnz}", flush=True)
     R, score = _check(db, C, w.reads.bases, w.reads.offsets, w.k, sc, group, min_score)
     assert R.nnz > 0
+
+
+@pytest.mark.parametrize("sc", [(1, -1, -2, 25), (2, -3, -3, 12), (1, -1, -1, 30), (1, -1, -2, 60)])
+def test_alignment_fast_path_equals_general_kernel(db, tiny, sc):
+    """The fast path (and the general kernel over the extensions it hands
+    on) gives the general kernel's scores, R and cell count."""
+    w, C = tiny
+    b, o = _dev(w.reads.bases, w.reads.offsets)
+    R0, s0 = db.r_from_alignment(C, b, o, w.k, *sc, 0, group=64, with_score=True)
+    cells0 = db.last_stats()["cells"]
+    R1, s1 = db.r_from_alignment(C, b, o, w.k, *sc, 0, with_score=True)
+    cells1 = db.last_stats()["cells"]
+    assert torch.equal(s0, s1)
+    assert torch.equal(R0.rowptr, R1.rowptr) and torch.equal(R0.col, R1.col) and torch.equal(R0.val, R1.val)
+    assert cells0 == cells1 > 0
 
 
 def test_alignment_batchset_matches_oracle(db):
