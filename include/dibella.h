@@ -71,8 +71,10 @@ extern "C" {
 #define DIBELLA_TR_USE_GRAPH   0x8u  /* run the passes as captured HIP graphs */
 /* Flag of dibella_kmer_matrix. */
 #define DIBELLA_KMER_STRAND    0x1u  /* values (position << 1) | strand */
-/* Flags of dibella_r_from_alignment: lanes per extension (0 = chosen from
- * the scores and X). */
+/* Flags of dibella_r_from_alignment: lanes per extension of the general
+ * kernel, run over every extension (0 = a register-band fast path with
+ * lanes chosen from the scores and X, the general kernel redoing the
+ * extensions whose band outgrows it; the results are the same). */
 #define DIBELLA_ALIGN_GROUP_16   0x1u
 #define DIBELLA_ALIGN_GROUP_32   0x2u
 #define DIBELLA_ALIGN_GROUP_64   0x3u
@@ -256,7 +258,8 @@ int dibella_r_from_seeds(const dibella_overlap_out* C, const int32_t* read_len, 
  * R: n x n in dibella_transitive_reduce's layout, rows sorted, allocated
  * through alloc.  score (may be NULL): *score receives device int32[nnz(C)],
  * allocated through alloc, the score of every entry of C (0 on the
- * diagonal; NULL when C is empty).  flags: DIBELLA_ALIGN_GROUP_* or 0.
+ * diagonal; NULL when C is empty).  flags: DIBELLA_ALIGN_GROUP_* or 0
+ * (the lanes used never change the result).
  * Errors: EINVAL for a malformed C (row pointers, column range or order), a
  * non-square C, a missing seed or one outside its read, malformed offsets, a
  * base outside 0..3, k outside [1, 32], scores or xdrop outside their

@@ -435,9 +435,11 @@ def r_from_alignment(C: OverlapCSR, bases: torch.Tensor, offsets: torch.Tensor, 
     differ; pairs scoring below min_score dropped; the suffix and
     orientation code from the alignment ends, contained pairs kept with
     value 0.  bases uint8 (A0 C1 G2 T3, reads back to back), offsets
-    int64[n + 1].  group: lanes per extension (16, 32, 64; None = chosen
-    from the scores).  Returns R, or (R, score) with the int32 score of
-    every entry of C (0 on the diagonal)."""
+    int64[n + 1].  group: lanes per extension of the general kernel over
+    every extension (16, 32, 64; None = the register-band fast path with
+    lanes chosen from the scores, the general kernel redoing extensions
+    whose band outgrows it; the result is the same).  Returns R, or (R,
+    score) with the int32 score of every entry of C (0 on the diagonal)."""
     dev = C.rowptr.device
     if bases.dtype != torch.uint8 or not bases.is_cuda or not bases.is_contiguous():
         raise TypeError("bases must be a contiguous uint8 device tensor")
