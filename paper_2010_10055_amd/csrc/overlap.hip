@@ -175,8 +175,8 @@ __device__ __forceinline__ void planes_mark(uint32_t* B, int words, int planes, 
 // Column slices for the segment pass: the global columns are cut into
 // `count` ranges of about equal width, slice(c) = (c * mul) >> 32 with
 // mul = floor(2^32 * count / total columns), so slice(c) < count and is
-// monotone in c.  Each slice's share of the A^T column records is small
-// enough to stay in one XCD's L2 while that XCD works on the slice.
+// monotone in c.  Each XCD gathers from one slice's share of the A^T column
+// records at a time.
 struct SliceMap {
     int32_t count;   // 0: no slices
     uint32_t mul;
@@ -725,10 +725,11 @@ constexpr int kSegIlp = 8;
 // Sliced segment pass.  Workgroups are handed to the XCDs round-robin
 // (workgroup b runs on XCD b mod 8), so workgroup b takes slice
 // 8 * round + (b mod 8): at any time each XCD gathers column records from
-// one slice only (at most 4 MB), which its L2 then holds, instead of every
-// XCD gathering from all of them.  A workgroup covers the sub-ranges of
-// kSliceRows rows in its slice; those are short (a row spreads its entries
-// over all slices), so the workgroup numbers their entries consecutively
+// one slice only (at most 16 MB; with columns in first-occurrence order a
+// row's records cluster, so the lines one workgroup touches are far fewer),
+// instead of every XCD gathering from all of them.  A workgroup covers the
+// sub-ranges of kSliceRows rows in its slice; those are short (a row spreads
+// its entries over the slices), so the workgroup numbers their entries consecutively
 // (a scan of the 64 lengths) and every thread takes entries by number,
 // kSliceIlp at a time, finding the row with a search over the 64 starts:
 // consecutive threads read consecutive columns and write consecutive
@@ -739,7 +740,10 @@ constexpr int kSliceRows = 64;
 constexpr int kSliceBlock = 256;
 constexpr int kSliceIlp = 4;
 constexpr int kMaxSlices = 8192;                   // 2^32 columns at kSliceCols each
-constexpr int64_t kSliceCols = int64_t(1) << 19;   // 4 MB of column records: one L2
+// 2^21 columns (16 MB of records) per slice: with columns in first-occurrence
+// order, wider slices cut a row into fewer sub-ranges and write a smaller
+// boundary table (2^19 columns, one L2's worth, suited columns in code order)
+constexpr int64_t kSliceCols = int64_t(1) << 21;
 // a readable word for the loads of rows with no entries in a slice (their
 // values are never used)
 __device__ const int32_t kSliceNone[1] = {0};

@@ -93,7 +93,7 @@ def test_blocked_graph_mid_workload_sliced(db):
     """The mid-size workload: enough columns for the sliced segment pass, so
     every block reads its rows' part of the slice table, and A^T is built
     over as many column ranges of slices as there are blocks (5 ranges for
-    blocks of 7000 reads; 24, every slice, for blocks of 600).  Both against
+    blocks of 7000 reads; 8, every slice, for blocks of 600).  Both against
     the oracle's R from the whole C."""
     w = synth.make_workload("mid", device="cuda:0", strand_bit=True)
     print(f"mid: reads {w.A.nrows} nnz(A) {w.A.nnz} k-mers {w.A.ncols}", flush=True)

@@ -166,19 +166,20 @@ def _sliced_a(rng, n, m):
     return synth.coo_to_csr(n, m, rows, cols, rng.integers(0, 20000, rows.size).astype(np.int32))
 
 
-@pytest.mark.parametrize("m", [pytest.param((1 << 21) - 1, id="unsliced-narrow"), pytest.param(1 << 21, id="8-slices"),
-                               pytest.param(5 * (1 << 21) + 3, id="24-slices"), pytest.param(1 << 25, id="64-slices"),
-                               pytest.param((1 << 25) + 1, id="72-slices"), pytest.param((1 << 26) + 5, id="136-slices")])
+@pytest.mark.parametrize("m", [pytest.param((1 << 23) - 1, id="unsliced-narrow"), pytest.param(1 << 23, id="8-slices"),
+                               pytest.param(5 * (1 << 23) + 3, id="24-slices"), pytest.param(1 << 27, id="64-slices"),
+                               pytest.param((1 << 27) + 1, id="72-slices"), pytest.param((1 << 27) + (1 << 26) + 5,
+                                                                                      id="104-slices")])
 def test_overlap_sliced_segments(lib, m):
-    """From 2^21 columns the segment pass runs per column slice (rounds of 8
-    slices of at most 2^19 columns); one column fewer and it runs per row."""
+    """From 2^23 columns the segment pass runs per column slice (rounds of 8
+    slices of at most 2^21 columns); one column fewer and it runs per row."""
     A = _sliced_a(np.random.default_rng(31), 3001, m)
     assert_overlap_equal(_run_overlap(lib, A, 1), oracle.overlap(A, 1), f"sliced m={m}")
     assert_overlap_equal(_run_overlap(lib, A, 2), oracle.overlap(A, 2), f"sliced m={m} ms 2")
 
 
 def test_overlap_unsliced_when_slice_tables_outgrow_a(lib):
-    """3e5 rows of one entry over 2^27 columns: the slice tables (2 * 256 + 1
+    """3e5 rows of one entry over 2^27 columns: the slice tables (2 * 64 + 1
     int32 per row) would outgrow max(4 nnz, 2^24) entries, so the segment
     pass runs per row."""
     rng = np.random.default_rng(33)
@@ -189,10 +190,10 @@ def test_overlap_unsliced_when_slice_tables_outgrow_a(lib):
 
 
 def test_overlap_batched_sliced_segments(lib):
-    """Sets of 1.5e6, 2e3 and 1.5e6 columns: together they are wide enough
-    for the sliced segment pass, whose slices then cut across sets."""
+    """Sets of 6e6, 2e3 and 6e6 columns: together they are wide enough for
+    the sliced segment pass, whose slices then cut across sets."""
     rng = np.random.default_rng(32)
-    sets = [_sliced_a(rng, 700, 1500000), synth.random_a(rng, 60, 2000, 0.01), _sliced_a(rng, 900, 1500001)]
+    sets = [_sliced_a(rng, 700, 6000000), synth.random_a(rng, 60, 2000, 0.01), _sliced_a(rng, 900, 6000001)]
     Cs = lib.overlap_batched([lib.CSRTensors.from_numpy(a, _dev()) for a in sets], [1, 1, 2])
     for s, (a, ms) in enumerate(zip(sets, [1, 1, 2])):
         assert_overlap_equal(Cs[s], oracle.overlap(a, ms), f"set {s}")
