@@ -543,6 +543,7 @@ int oracle_kmer_matrix(int64_t n, const uint8_t* bases, const int64_t* offsets, 
             ++w;
         }
     }
+    W = w;   /* the windows filled (equal to the count above) */
     qsort(win, (size_t)W, sizeof(oracle_window), cmp_window);
     /* frequencies (runs of equal codes) and the reliable k-mers; within a run
      * the windows are in (read, position) order, so a run's first window is
