@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int64
 constexpr int kBandWin = 256;
 constexpr int kBandFill = 128;
 
-template <int G>
+template <int G, int C>
 __global__ __launch_bounds__(kWave) void k_al_band(int64_t ntasks, const int32_t* __restrict__ row_of,
                                                    const int32_t* __restrict__ col,
                                                    const int32_t* __restrict__ seed,
@@ -401,8 +401,12 @@ __global__ __launch_bounds__(kWave) void k_al_band(int64_t ntasks, const int32_t
                                                    unsigned long long* __restrict__ fb_count) {
     // next[0]: the next task; next[1]: cells considered by finished extensions
     constexpr int NG = kWave / G;
+    constexpr int BW = G * C;   // cells a group holds: lane l holds cells from + l + G * h, h < C
     constexpr uint64_t kMask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
-    static_assert(G <= kBandWin - kBandFill, "a band fits the staged bases");
+    static_assert(C == 1 || C == 2, "one or two cells per lane");
+    static_assert(BW <= 64, "a group's cells fit one 64-bit mask");
+    static_assert(BW <= kBandWin - kBandFill, "a band fits the staged bases");
+    constexpr int LG = G == 16 ? 4 : G == 32 ? 5 : 6;
     __shared__ uint8_t s_base[NG][2][kBandWin];
     const int lane = threadIdx.x;
     const int grp = lane / G, gl = lane % G;
@@ -421,7 +425,9 @@ __global__ __launch_bounds__(kWave) void k_al_band(int64_t ntasks, const int32_t
     int32_t vlA = 0, whA = 0, vlB = 0, whB = 0;
     unsigned long long tcells = 0, cells = 0;
     // this lane's cells of d - 1 and d - 2
-    int32_t v1 = kAlDead, v2 = kAlDead;
+    int32_t v1[C], v2[C];
+#pragma unroll
+    for (int h = 0; h < C; ++h) v1[h] = v2[h] = kAlDead;
 
     for (;;) {
         if (!busy && !done) {
@@ -440,8 +446,13 @@ __global__ __launch_bounds__(kWave) void k_al_band(int64_t ntasks, const int32_t
                     al_sides(task, i, j, seed[4 * e], seed[4 * e + 1], off, k, A, B);
                     // anti-diagonal 0: the cell (0, 0)
                     d = 0;
-                    lo1 = 0, hi1 = 0, f1 = 0, v1 = gl == 0 ? 0 : kAlDead;
-                    lo2 = 0, hi2 = -1, f2 = 0, v2 = kAlDead;
+                    lo1 = 0, hi1 = 0, f1 = 0;
+                    lo2 = 0, hi2 = -1, f2 = 0;
+#pragma unroll
+                    for (int h = 0; h < C; ++h) {
+                        v1[h] = (gl == 0 && h == 0) ? 0 : kAlDead;
+                        v2[h] = kAlDead;
+                    }
                     best = 0, bx = 0, bd = 0;
                     vlA = 0, whA = 0, vlB = 0, whB = 0;
                     tcells = 0;
@@ -468,11 +479,13 @@ __global__ __launch_bounds__(kWave) void k_al_band(int64_t ntasks, const int32_t
             if (from <= to && to - from + 1 > kAlBand) finish = true;
         }
         if (!finish && from > to) {            // no cell to consider: an empty anti-diagonal
-            lo2 = lo1, hi2 = hi1, f2 = f1, v2 = v1;
-            lo1 = 0, hi1 = -1, v1 = kAlDead;
+            lo2 = lo1, hi2 = hi1, f2 = f1;
+            lo1 = 0, hi1 = -1;
+#pragma unroll
+            for (int h = 0; h < C; ++h) v2[h] = v1[h], v1[h] = kAlDead;
             continue;
         }
-        if (!finish && to - from + 1 > G) {    // wider than the group: the general kernel redoes it
+        if (!finish && to - from + 1 > BW) {   // wider than the group holds: the general kernel redoes it
             if (gl == 0) fb[atomicAdd(fb_count, 1ull)] = task;
             busy = false;
             continue;
@@ -488,29 +501,59 @@ __global__ __launch_bounds__(kWave) void k_al_band(int64_t ntasks, const int32_t
                                                            gl);
             if (staged) lds_sync();
             tcells += (unsigned long long)(to - from + 1);
-            const int32_t x = from + gl, y = d - x;
-            // the predecessors: x - 1 on d - 2, x - 1 and x on d - 1 (a lane
-            // whose predecessor lies in a live range reads a lane of its group)
-            const int32_t pd = __shfl(v2, gl + from - f2 - 1, G);
-            const int32_t pl = __shfl(v1, gl + from - f1 - 1, G);
-            const int32_t pu = __shfl(v1, gl + from - f1, G);
-            const uint8_t ca = wa[(x - 1) & (kBandWin - 1)], cb = wb[(y - 1) & (kBandWin - 1)];
-            int32_t v = kAlDead;
-            if (x <= to) {
-                if (x >= 1 && y >= 1 && x - 1 >= lo2 && x - 1 <= hi2 && pd != kAlDead) v = pd + (ca == cb ? mat : mis);
-                if (x >= 1 && x - 1 >= lo1 && x - 1 <= hi1 && pl != kAlDead && pl + gap > v) v = pl + gap;
-                if (y >= 1 && x >= lo1 && x <= hi1 && pu != kAlDead && pu + gap > v) v = pu + gap;
-                if (v != kAlDead && v < best - X) v = kAlDead;
+            // the predecessors of cell c = gl + G * h: x - 1 on d - 2 (index
+            // c + from - f2 - 1 there), x - 1 and x on d - 1 (c + from - f1 - 1,
+            // c + from - f1).  Index t sits in lane t mod G, part t / G: the
+            // lane is the same for every h, so one shuffle per part serves all.
+            int32_t pd[C], pl[C], pu[C];
+#pragma unroll
+            for (int h = 0; h < C; ++h) pd[h] = pl[h] = pu[h] = kAlDead;
+            const int od = from - f2 - 1, ol = from - f1 - 1, ou = from - f1;
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                const int32_t sd = __shfl(v2[q], gl + od, G);
+                const int32_t sl = __shfl(v1[q], gl + ol, G);
+                const int32_t su = __shfl(v1[q], gl + ou, G);
+#pragma unroll
+                for (int h = 0; h < C; ++h) {
+                    if (C == 1 || ((gl + G * h + od) >> LG) == q) pd[h] = sd;
+                    if (C == 1 || ((gl + G * h + ol) >> LG) == q) pl[h] = sl;
+                    if (C == 1 || ((gl + G * h + ou) >> LG) == q) pu[h] = su;
+                }
             }
-            const uint64_t live = (__ballot(v != kAlDead) >> leader) & kMask;
-            lo2 = lo1, hi2 = hi1, f2 = f1, v2 = v1;
-            f1 = from, v1 = v;
+            int32_t v[C];
+#pragma unroll
+            for (int h = 0; h < C; ++h) {
+                const int32_t x = from + gl + G * h, y = d - x;
+                const uint8_t ca = wa[(x - 1) & (kBandWin - 1)], cb = wb[(y - 1) & (kBandWin - 1)];
+                int32_t w = kAlDead;
+                if (x <= to) {
+                    if (x >= 1 && y >= 1 && x - 1 >= lo2 && x - 1 <= hi2 && pd[h] != kAlDead)
+                        w = pd[h] + (ca == cb ? mat : mis);
+                    if (x >= 1 && x - 1 >= lo1 && x - 1 <= hi1 && pl[h] != kAlDead && pl[h] + gap > w) w = pl[h] + gap;
+                    if (y >= 1 && x >= lo1 && x <= hi1 && pu[h] != kAlDead && pu[h] + gap > w) w = pu[h] + gap;
+                    if (w != kAlDead && w < best - X) w = kAlDead;
+                }
+                v[h] = w;
+            }
+            uint64_t live = 0;
+#pragma unroll
+            for (int h = 0; h < C; ++h) live |= ((__ballot(v[h] != kAlDead) >> leader) & kMask) << (G * h);
+            lo2 = lo1, hi2 = hi1, f2 = f1;
+            f1 = from;
+#pragma unroll
+            for (int h = 0; h < C; ++h) v2[h] = v1[h], v1[h] = v[h];
             if (live) {
                 lo1 = from + __builtin_ctzll(live);
                 hi1 = from + 63 - __builtin_clzll(live);
-                const int32_t dmax = group_max_dpp<G>(v);
+                int32_t vm = v[0];
+#pragma unroll
+                for (int h = 1; h < C; ++h) vm = max(vm, v[h]);
+                const int32_t dmax = group_max_dpp<G>(vm);
                 if (dmax > best) {
-                    const uint64_t at = (__ballot(v == dmax) >> leader) & kMask;
+                    uint64_t at = 0;
+#pragma unroll
+                    for (int h = 0; h < C; ++h) at |= ((__ballot(v[h] == dmax) >> leader) & kMask) << (G * h);
                     best = dmax, bx = from + __builtin_ctzll(at), bd = d;
                 }
             } else {
@@ -718,16 +761,18 @@ int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int
         DB_TRY(timing_begin(kPhAlign, st, &tok));
         if (FG) {
             DB_TRY(ar.work_n(ntasks, &fb));
-            const int grid = al_band_grid(ntasks, FG);
+            const int grid = al_band_grid(ntasks, FG == 32 ? 16 : FG);
+            // a band of up to 32 cells: groups of 16 lanes, two cells a lane
+            // (four extensions a wave for the bookkeeping of one step)
             if (FG == 16)
-                hipLaunchKernelGGL(k_al_band<16>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
-                                   bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
+                hipLaunchKernelGGL((k_al_band<16, 1>), dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col,
+                                   C->seed, bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
             else if (FG == 32)
-                hipLaunchKernelGGL(k_al_band<32>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
-                                   bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
+                hipLaunchKernelGGL((k_al_band<16, 2>), dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col,
+                                   C->seed, bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
             else
-                hipLaunchKernelGGL(k_al_band<64>, dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col, C->seed,
-                                   bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
+                hipLaunchKernelGGL((k_al_band<64, 1>), dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col,
+                                   C->seed, bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
             DB_HIP(hipGetLastError());
             list = fb;
             list_count = next + 2;
