@@ -374,17 +374,20 @@ __global__ __launch_bounds__(kWave) void k_al_extend(int64_t ntasks, const int64
 
 // ---------------------------------------------------------------------------
 // The extensions, fast path: an extension whose anti-diagonals never ask for
-// more than G cells (the common case: an extension keeps about
-// 2X / (match - gap) cells live).  Each lane of a group of G holds one cell
-// of the current anti-diagonal, x = from + lane; the two earlier
-// anti-diagonals stay in registers (a lane's cell there counted from that
-// anti-diagonal's first considered cell) and are read across lanes by
-// shuffles, so no score goes through LDS; only the bases are staged, in
-// rings of kBandWin positions.  The cells considered, the dead ones, the
-// ranges and the best cell are exactly the general kernel's.  An extension
-// that would consider more than G cells on one anti-diagonal is appended to
-// `fb` (fb_count[0] entries) and left to the general kernel, which redoes it
-// from the start; its cells are counted there only.
+// more than G * C cells (the common case: an extension keeps about
+// 2X / (match - gap) cells live).  Each lane of a group of G holds C cells
+// of the current anti-diagonal, x = from + lane + G * h for h < C; the two
+// earlier anti-diagonals stay in registers (a lane's cells there counted
+// from that anti-diagonal's first considered cell) and are read across lanes
+// by shuffles, so no score goes through LDS; only the bases are staged, in
+// rings of kBandWin positions.  Two cells a lane halve the groups' share of
+// the per-step bookkeeping (range update, staging checks, ballots, group
+// maximum), which runs once per group and step whatever C is.  The cells
+// considered, the dead ones, the ranges and the best cell are exactly the
+// general kernel's.  An extension that would consider more than G * C cells
+// on one anti-diagonal is appended to `fb` (fb_count[0] entries) and left to
+// the general kernel, which redoes it from the start; its cells are counted
+// there only.
 // ---------------------------------------------------------------------------
 constexpr int kBandWin = 256;
 constexpr int kBandFill = 128;
@@ -628,8 +631,10 @@ static const char* describe_al_bad(int32_t bad) {
     return "malformed input";
 }
 
-// Lanes of the fast path (0: none) from the band an extension keeps live,
-// about 2X / (match - gap) cells; a group holds the band with room to spare.
+// Cells a group of the fast path holds (0: no fast path) from the band an
+// extension keeps live, about 2X / (match - gap) cells, with room to spare:
+// 16 is one cell a lane in groups of 16, 32 two cells a lane in groups of 16,
+// 64 one cell a lane in groups of 64.
 static int al_band_group(int32_t mat, int32_t gap, int32_t X) {
     const int64_t band = 2 * (int64_t)X / (mat - gap);
     return band <= 10 ? 16 : band <= 24 ? 32 : band <= 48 ? 64 : 0;
@@ -762,8 +767,6 @@ int r_from_alignment_run(const dibella_overlap_out* C, const uint8_t* bases, int
         if (FG) {
             DB_TRY(ar.work_n(ntasks, &fb));
             const int grid = al_band_grid(ntasks, FG == 32 ? 16 : FG);
-            // a band of up to 32 cells: groups of 16 lanes, two cells a lane
-            // (four extensions a wave for the bookkeeping of one step)
             if (FG == 16)
                 hipLaunchKernelGGL((k_al_band<16, 1>), dim3(grid), dim3(kWave), 0, st, ntasks, row_of, C->col,
                                    C->seed, bases, offsets, k, mat, mis, gap, X, next, ext, fb, next + 2);
