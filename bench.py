@@ -821,6 +821,8 @@ def main():
     ap.add_argument("--no-kmer", action="store_true", help="skip the k-mer counting leg")
     ap.add_argument("--align-rows", type=int, default=8192,
                     help="rows of C aligned by the alignment leg (0 = skip)")
+    ap.add_argument("--align-scores", type=int, nargs=4, default=[1, -1, -2, 25],
+                    metavar=("MATCH", "MISMATCH", "GAP", "XDROP"), help="scores of the alignment leg")
     ap.add_argument("--blocks", type=int, nargs="*", default=[4, 16],
                     help="block counts of the blocked overlap graph comparison (none = skip)")
     ap.add_argument("--calib-copy", action="store_true", help="only run the reference kernels used to scale counters")
@@ -993,7 +995,7 @@ def main():
         entry = main_pool_entry(w)
     if args.align_rows > 0:
         log(f"R from the alignment ({args.align_rows} rows of C) ...")
-        align = align_compare(entry[1], w.reads, args.align_rows)
+        align = align_compare(entry[1], w.reads, args.align_rows, scores=tuple(args.align_scores))
     if args.blocks:
         log(f"blocked overlap graph ({args.blocks} blocks) vs whole ...")
         blocked = blocked_compare(entry[1], tuple(args.blocks))
