@@ -6,6 +6,7 @@ and runs the oracle pin suite (tests/test_oracle.py) against it in a child
 process: the suite must fail.  The unedited source, built the same way, must
 pass.  Everything here runs on the CPU.
 """
+import json
 import os
 import subprocess
 import sys
@@ -138,14 +139,12 @@ def _run_pins(so):
     return r.returncode, r.stdout[-3000:] + r.stderr[-2000:]
 
 
-@pytest.fixture(scope="module")
-def outcomes(tmp_path_factory):
-    """Build the control and every planted copy, then run the pin suite
-    against each of them, several child processes at a time."""
+def _all_outcomes(d):
+    """Build the control and every planted copy in `d`, then run the pin
+    suite against each of them, several child processes at a time."""
     from concurrent.futures import ThreadPoolExecutor
     with open(SRC) as f:
         text = f.read()
-    d = str(tmp_path_factory.mktemp("oracle_mutants"))
     jobs = {"control": text}
     for mid, old, new in MUTANTS:
         jobs[mid] = text.replace(old, new, 1) if old in text else None
@@ -154,6 +153,25 @@ def outcomes(tmp_path_factory):
     with ThreadPoolExecutor(workers) as ex:
         futs = {mid: ex.submit(_run_pins, so) for mid, so in libs.items() if so}
         return {mid: f.result() for mid, f in futs.items()}
+
+
+@pytest.fixture(scope="module")
+def outcomes(tmp_path_factory):
+    """The pin suite's outcome on the control and on every planted copy.
+    Under pytest-xdist the first worker to get here computes them and the
+    others read its file (the temporary root's parent is shared by the
+    workers), so the suite runs once per session, not once per worker."""
+    if not os.environ.get("PYTEST_XDIST_WORKER"):
+        return _all_outcomes(str(tmp_path_factory.mktemp("oracle_mutants")))
+    from filelock import FileLock
+    shared = tmp_path_factory.getbasetemp().parent
+    path = shared / "oracle_mutants.json"
+    with FileLock(str(path) + ".lock"):
+        if path.is_file():
+            return json.loads(path.read_text())
+        res = _all_outcomes(str(tmp_path_factory.mktemp("oracle_mutants")))
+        path.write_text(json.dumps(res))
+        return res
 
 
 def test_unedited_oracle_passes_the_pins(outcomes):
